@@ -1,0 +1,299 @@
+"""CPU oracle for PST pose search against a TSDF (ROSEFusion, Sec. 3-4).
+
+TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the CPU
+baseline of the benchmark may import this package.  The product library
+never does; it shares no code with this package.
+
+The arithmetic lives in ``rose_oracle.c`` (plain single-threaded C, built
+with gcc, no FMA contraction); this module builds it and exposes numpy-level
+wrappers via ctypes.
+
+Parity status per function (what pins it, tests/test_oracle_*.py):
+
+* philox4x64_10      -- pinned: equals numpy's Philox bit generator (a
+                        published Philox4x64-10 implementation) on the same
+                        key and counter.
+* pst_sample         -- pinned: radial law P(|p| <= a) = a^6, E[p p^T] = I/8,
+                        sign symmetry, acceptance rate pi^3/384, exact
+                        2^-24 lattice, row 0 = origin.
+* chart_delta / pose_retract / particle_pose
+                     -- pinned: closed-form rotations (axis-angle),
+                        orthonormality, identity at u = 0, composition with
+                        an independent matrix product.
+* unproject          -- pinned: noise-free analytic render -> every point
+                        lies on the analytic surface.
+* overlap            -- pinned: identity motion keeps every point; pure
+                        forward translation keeps exactly the analytically
+                        predicted set.
+* fitness            -- pinned: analytic plane field F(d) = (d/mu)^2
+                        (trilinear exact on a linear field); 1-Lipschitz
+                        bound at the true pose (nearest); all-outside -> 1;
+                        Neumaier sum vs math.fsum; voxel index brute force.
+* pst_update         -- pinned: single-member APS reproduces that particle;
+                        symmetric APS -> zero step; empty APS and
+                        TSDF-not-built corner cases; permutation invariance.
+* track_frame        -- pinned: brute-force 6D grid search on a tiny scene;
+                        convergence to the true pose on the small frame.
+* integrate          -- pinned: fronto-parallel plane closed form; fused
+                        zero crossing vs analytic surface.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rose_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+F64 = 0
+F32 = 1
+NEAREST = 0
+TRILINEAR = 1
+NO_OVERLAP = 1
+NO_NORMALIZE = 2
+
+
+def build(force: bool = True) -> str:
+    """Compile rose_oracle.c into liboracle.so (gcc, -O2, no FMA contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+               "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _TrackParams(C.Structure):
+    _fields_ = [("max_iters", C.c_int32), ("early_stop", C.c_int32), ("stride", C.c_int32),
+                ("lookup", C.c_int32), ("flags", C.c_int32), ("prec", C.c_int32),
+                ("beta", C.c_double), ("eps", C.c_double), ("tau", C.c_double), ("stop_tol", C.c_double)]
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build()
+            lib = C.CDLL(_LIB)
+            P = C.c_void_p
+            lib.orc_philox4x64_10.argtypes = [P, P, P]
+            lib.orc_pst_sample.argtypes = [C.c_int32, C.c_uint64, P]
+            lib.orc_pst_sample.restype = C.c_int
+            lib.orc_chart_delta.argtypes = [P, P, P]
+            lib.orc_pose_retract.argtypes = [P, P, P, P, P]
+            lib.orc_particle_pose.argtypes = [P, P, P, P, P]
+            lib.orc_unproject.argtypes = [P, C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float,
+                                          C.c_int32, C.c_int, P]
+            lib.orc_unproject.restype = C.c_int
+            lib.orc_overlap.argtypes = [P, C.c_int32, P, P, C.c_float, C.c_float, C.c_float, C.c_float,
+                                        C.c_int32, C.c_int32, C.c_int, P]
+            lib.orc_overlap.restype = C.c_int
+            lib.orc_fitness.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_float, P, P, C.c_int32, P, P,
+                                        C.c_int32, C.c_int32, C.c_int, C.c_int, P]
+            lib.orc_voxel_indices.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_float, P, P, C.c_int32, P,
+                                              C.c_int32, P]
+            lib.orc_pst_update.argtypes = [P, P, C.c_int32, P, P, P, C.c_double, C.c_double, C.c_double,
+                                           C.c_int32, P, P, P, P, P]
+            lib.orc_pst_update.restype = C.c_int
+            lib.orc_track_frame.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_float, P, P, C.c_int32,
+                                            C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float, P, C.c_int32,
+                                            P, P, P, P, P, C.c_int32, C.POINTER(_TrackParams), P, P, P, P, P,
+                                            P, P, P, P]
+            lib.orc_track_frame.restype = C.c_int
+            lib.orc_integrate.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32, C.c_float, P, C.c_float,
+                                          C.c_float, P, C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float,
+                                          C.c_float, P, P, C.c_int]
+            lib.orc_integrate.restype = C.c_int64
+            _lib = lib
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ----------------------------------------------------------------- wrappers
+def philox4x64_10(ctr, key) -> np.ndarray:
+    lib = _load()
+    c = np.ascontiguousarray(ctr, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    lib.orc_philox4x64_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def pst_sample(n: int, seed: int):
+    """(n, 6) float32 template, and the number of rows that hit the cap."""
+    lib = _load()
+    out = np.zeros((n, 6), dtype=np.float32)
+    capped = lib.orc_pst_sample(int(n), C.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), _p(out))
+    return out, int(capped)
+
+
+def chart_delta(u):
+    lib = _load()
+    u = _f64(u)
+    q = np.zeros(4)
+    t = np.zeros(3)
+    lib.orc_chart_delta(_p(u), _p(q), _p(t))
+    return q, t
+
+
+def pose_retract(qc, tc, u):
+    lib = _load()
+    qc, tc, u = _f64(qc), _f64(tc), _f64(u)
+    q = np.zeros(4)
+    t = np.zeros(3)
+    lib.orc_pose_retract(_p(qc), _p(tc), _p(u), _p(q), _p(t))
+    return q, t
+
+
+def particle_poses(qc, tc, r, pst) -> np.ndarray:
+    """(n, 3, 4) float64 camera->world transforms of the PST particles."""
+    lib = _load()
+    qc, tc, r = _f64(qc), _f64(tc), _f64(r)
+    pst = _f32(pst)
+    n = pst.shape[0]
+    T = np.zeros((n, 3, 4))
+    for i in range(n):
+        lib.orc_particle_pose(_p(qc), _p(tc), _p(r), _p(pst[i]), _p(T[i]))
+    return T
+
+
+def unproject(depth, K, stride: int, prec: int = F32) -> np.ndarray:
+    lib = _load()
+    depth = _f32(depth)
+    H, W = depth.shape
+    mmax = ((H + stride - 1) // stride) * ((W + stride - 1) // stride)
+    out = np.zeros((max(mmax, 1), 3), dtype=np.float32)
+    m = lib.orc_unproject(_p(depth), W, H, K.fx, K.fy, K.cx, K.cy, stride, prec, _p(out))
+    return out[:m].copy()
+
+
+def overlap(pts, Tc, Tprev, K, prec: int = F32) -> np.ndarray:
+    lib = _load()
+    pts = _f32(pts)
+    Tc = _f64(np.asarray(Tc)[:3, :4])
+    Tprev = _f64(np.asarray(Tprev)[:3, :4])
+    mask = np.zeros(max(len(pts), 1), dtype=np.uint8)
+    lib.orc_overlap(_p(pts), len(pts), _p(Tc), _p(Tprev), K.fx, K.fy, K.cx, K.cy, K.width, K.height, prec,
+                    _p(mask))
+    return mask[:len(pts)].astype(bool)
+
+
+def fitness(psi, vox, origin, pts, T, lookup: int = NEAREST, prec: int = F32, mask=None,
+            normalize: bool = True) -> np.ndarray:
+    """F_i (float64) for transforms T (n, 3, 4) over points pts (m, 3).
+
+    psi: (nz, ny, nx) float32 normalised TSDF."""
+    lib = _load()
+    psi = _f32(psi)
+    nz, ny, nx = psi.shape
+    pts = _f32(pts).reshape(-1, 3)
+    T = _f64(np.asarray(T).reshape(-1, 3, 4))
+    org = _f32(origin)
+    F = np.zeros(max(len(T), 1))
+    mk = None
+    if mask is not None:
+        mk = np.ascontiguousarray(mask, dtype=np.uint8)
+    lib.orc_fitness(_p(psi), nx, ny, nz, float(vox), _p(org), _p(pts), len(pts),
+                    _p(mk) if mk is not None else None, _p(T), len(T), lookup, prec, int(normalize), _p(F))
+    return F[:len(T)].copy()
+
+
+def voxel_indices(dims, vox, origin, pts, T) -> np.ndarray:
+    lib = _load()
+    nx, ny, nz = dims
+    pts = _f32(pts).reshape(-1, 3)
+    T = _f64(np.asarray(T).reshape(-1, 3, 4))
+    org = _f32(origin)
+    idx = np.zeros((len(T), len(pts)), dtype=np.int64)
+    lib.orc_voxel_indices(nx, ny, nz, float(vox), _p(org), _p(pts), len(pts), _p(T), len(T), _p(idx))
+    return idx
+
+
+def pst_update(F, pst, r, qc, tc, tau=1.0, beta=0.1, eps=1e-3, tsdf_built=True):
+    lib = _load()
+    F = _f64(F)
+    pst = _f32(pst)
+    r, qc, tc = _f64(r), _f64(qc), _f64(tc)
+    r_out, q_out, t_out, us = np.zeros(6), np.zeros(4), np.zeros(3), np.zeros(6)
+    rt = np.zeros(1)
+    aps = lib.orc_pst_update(_p(F), _p(pst), len(F), _p(r), _p(qc), _p(tc), tau, beta, eps, int(tsdf_built),
+                             _p(r_out), _p(q_out), _p(t_out), _p(rt), _p(us))
+    return dict(aps=int(aps), r=r_out, q=q_out, t=t_out, rho_tilde=float(rt[0]), u_star=us)
+
+
+def track_frame(psi, vox, origin, depth, K, pst, q_prev, t_prev, r_init, q_init=None, t_init=None,
+                tsdf_built=True, max_iters=20, early_stop=False, stride=4, lookup=NEAREST, flags=0, prec=F32,
+                beta=0.1, eps=1e-3, tau=1.0, stop_tol=1e-6):
+    lib = _load()
+    psi = _f32(psi)
+    nz, ny, nx = psi.shape
+    depth = _f32(depth)
+    H, W = depth.shape
+    pst = _f32(pst)
+    q_prev, t_prev, r_init = _f64(q_prev), _f64(t_prev), _f64(r_init)
+    q_init = q_prev if q_init is None else _f64(q_init)
+    t_init = t_prev if t_init is None else _f64(t_init)
+    P = _TrackParams(max_iters, int(early_stop), stride, lookup, flags, prec, beta, eps, tau, stop_tol)
+    q_out, t_out, r1 = np.zeros(4), np.zeros(3), np.zeros(6)
+    rho, iters = np.zeros(1), np.zeros(1, dtype=np.int32)
+    aps = np.zeros(32, dtype=np.int32)
+    rho_it = np.zeros(32)
+    npts, nov = np.zeros(1, dtype=np.int32), np.zeros(1, dtype=np.int32)
+    org = _f32(origin)
+    rc = lib.orc_track_frame(_p(psi), nx, ny, nz, float(vox), _p(org), _p(depth), W, H, K.fx, K.fy, K.cx, K.cy,
+                             _p(pst), len(pst), _p(q_prev), _p(t_prev), _p(q_init), _p(t_init), _p(r_init),
+                             int(tsdf_built), C.byref(P), _p(q_out), _p(t_out), _p(r1), _p(rho), _p(iters),
+                             _p(aps), _p(rho_it), _p(npts), _p(nov))
+    it = int(iters[0])
+    return dict(status=int(rc), q=q_out, t=t_out, r1=r1, rho=float(rho[0]), iters=it,
+                aps=aps[:min(it, 32)].copy(), rho_iter=rho_it[:min(it, 32)].copy(), n_points=int(npts[0]),
+                n_overlap_last=int(nov[0]))
+
+
+def integrate(psi, wgt, vox, origin, mu, depth, K, q, t, w_max=128.0, prec: int = F32) -> int:
+    """In-place fusion of one depth frame into (psi, wgt), both (nz, ny, nx)
+    float32 C-contiguous arrays.  Returns the number of updated voxels."""
+    lib = _load()
+    assert psi.dtype == np.float32 and wgt.dtype == np.float32
+    assert psi.flags.c_contiguous and wgt.flags.c_contiguous
+    nz, ny, nx = psi.shape
+    depth = _f32(depth)
+    H, W = depth.shape
+    q, t = _f64(q), _f64(t)
+    org = _f32(origin)
+    return int(lib.orc_integrate(_p(psi), _p(wgt), nx, ny, nz, float(vox), _p(org), float(mu), float(w_max),
+                                 _p(depth), W, H, K.fx, K.fy, K.cx, K.cy, _p(q), _p(t), prec))
+
+
+def pose_mat(q, t) -> np.ndarray:
+    """4x4 camera->world matrix of (q, t), via the oracle's own quaternion
+    formula (binary64)."""
+    qd, td = _f64(q), _f64(t)
+    T = np.zeros((3, 4))
+    lib = _load()
+    zero_r = np.zeros(6)
+    zero_p = np.zeros(6, dtype=np.float32)
+    lib.orc_particle_pose(_p(qd), _p(td), _p(zero_r), _p(zero_p), _p(T))
+    M = np.eye(4)
+    M[:3, :] = T
+    return M

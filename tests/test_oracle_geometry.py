@@ -1,0 +1,243 @@
+"""Pins of the oracle's geometric steps: unprojection (Eq. unproj), overlap
+set (Eq. validness), fitness (Eqs. ourlh / normallh) and fusion."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+
+
+@pytest.fixture(scope="module")
+def room():
+    return synth.unit_box_room(2105)
+
+
+def _look(f, t):
+    return synth.Pose(synth.look_rotation(f), np.asarray(t, dtype=np.float64))
+
+
+# ----------------------------------------------------------- unprojection
+@pytest.mark.parametrize("prec", [0, 1])
+def test_unproject_lands_on_surface(orc, room, prec):
+    K = synth.Intrinsics.centred(160, 120, 140.0)
+    pose = _look([0.6, 0.5, 0.4], [0.01, -0.02, 0.0])
+    depth = synth.render_depth(room, K, pose)
+    pts = orc.unproject(depth, K, 3, prec)
+    assert len(pts) == ((depth[::3, ::3] > 0).sum())
+    X = pts.astype(np.float64) @ pose.R.T + pose.t
+    assert np.abs(room.sdf(X)).max() < 2e-6  # binary32 storage of metre-scale points
+
+
+def test_unproject_skips_invalid_and_keeps_row_major_order(orc):
+    K = synth.Intrinsics.centred(8, 6, 10.0)
+    d = np.arange(48, dtype=np.float32).reshape(6, 8) * 0.1
+    d[2, 4] = np.nan
+    d[0, 2] = -1.0
+    pts = orc.unproject(d, K, 2, 0)
+    expect = []
+    for v in range(0, 6, 2):
+        for u in range(0, 8, 2):
+            z = d[v, u]
+            if z > 0:
+                expect.append(((u - K.cx) * z / K.fx, (v - K.cy) * z / K.fy, z))
+    assert np.allclose(pts, np.array(expect, dtype=np.float32), rtol=1e-6, atol=1e-7)
+
+
+# ---------------------------------------------------------------- overlap
+def test_overlap_identity_keeps_interior(orc, room):
+    K = synth.Intrinsics.centred(160, 120, 140.0)
+    pose = _look([0.6, 0.5, 0.4], [0.0, 0.0, 0.0])
+    depth = synth.render_depth(room, K, pose)
+    for prec in (0, 1):
+        pts = orc.unproject(depth, K, 1, prec)
+        mask = orc.overlap(pts, pose.mat(), pose.mat(), K, prec)
+        px = pts[:, 0] / pts[:, 2] * K.fx + K.cx
+        py = pts[:, 1] / pts[:, 2] * K.fy + K.cy
+        interior = (px > 0.5) & (px < K.width - 1.5) & (py > 0.5) & (py < K.height - 1.5)
+        assert mask[interior].all()
+
+
+def test_overlap_backward_motion_closed_form(orc, room):
+    """Camera t moved back along its optical axis by delta relative to
+    frame t-1: a point x maps to x' = x - (0,0,delta)... kept iff its
+    projection in frame t-1 is inside the image."""
+    K = synth.Intrinsics.centred(160, 120, 140.0)
+    prev = _look([0.6, 0.5, 0.4], [0.05, 0.02, 0.0])
+    delta = 0.08
+    cur = synth.Pose(prev.R, prev.t - delta * prev.R[:, 2])  # moved backwards
+    depth = synth.render_depth(room, K, cur)
+    pts = orc.unproject(depth, K, 2, 0).astype(np.float64)
+    mask = orc.overlap(pts, cur.mat(), prev.mat(), K, 0)
+    zp = pts[:, 2] - delta
+    px = K.fx * pts[:, 0] / zp + K.cx
+    py = K.fy * pts[:, 1] / zp + K.cy
+    expect = (zp > 0) & (px >= 0) & (px <= K.width - 1) & (py >= 0) & (py <= K.height - 1)
+    margin = np.minimum.reduce([np.abs(px), np.abs(px - (K.width - 1)), np.abs(py), np.abs(py - (K.height - 1))])
+    clear = margin > 1e-6
+    assert 0 < expect.sum() < len(pts)  # the band is non-trivial
+    assert np.array_equal(mask[clear], expect[clear])
+    # moving forward instead keeps everything in view of frame t-1
+    fwd = synth.Pose(prev.R, prev.t + delta * prev.R[:, 2])
+    depth_f = synth.render_depth(room, K, fwd)
+    pts_f = orc.unproject(depth_f, K, 2, 0)
+    m_f = orc.overlap(pts_f, fwd.mat(), prev.mat(), K, 0)
+    assert m_f.all()
+
+
+# ---------------------------------------------------------------- fitness
+def test_fitness_plane_field_trilinear(orc):
+    """psi(X) = (c - X_z)/mu is linear, so trilinear lookup is exact and a
+    point set on the plane shifted by d scores F = (d/mu)^2 (Eq. normallh)."""
+    nx = ny = nz = 32
+    vox, mu = 0.02, 0.3
+    origin = np.array([-0.32, -0.32, -0.32])
+    c = 0.013
+    zc = origin[2] + (np.arange(nz) + 0.5) * vox
+    psi = np.broadcast_to(((c - zc) / mu)[:, None, None], (nz, ny, nx)).astype(np.float32).copy()
+    rng = np.random.default_rng(0)
+    xy = rng.uniform(-0.2, 0.2, size=(500, 2))
+    pts = np.column_stack([xy, np.full(500, c)]).astype(np.float32)  # world = camera (identity pose)
+    for d in (0.0, 0.01, -0.025, 0.07):
+        T = np.array([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, d]], dtype=np.float64)
+        for prec in (0, 1):
+            F = orc.fitness(psi, vox, origin, pts, T[None], lookup=1, prec=prec)[0]
+            assert abs(F - (d / mu) ** 2) <= 2e-6 * max((d / mu) ** 2, 1e-3)
+
+
+def test_fitness_lipschitz_bound_at_true_pose(orc, room):
+    """Analytic TSDF, exact surface points, nearest voxel: |psi| <= the
+    centre offset sqrt(3)/2 vox / mu (the SDF is 1-Lipschitz), so
+    F <= 3/4 (vox/mu)^2."""
+    dims, vox, mu = (64, 64, 64), 0.02, 0.06
+    origin = np.full(3, -0.64)
+    psi = synth.analytic_tsdf(room, dims, vox, origin, mu)
+    K = synth.Intrinsics.centred(160, 120, 140.0)
+    pose = _look([0.5, 0.6, -0.3], [0.02, 0.0, 0.01])
+    depth = synth.render_depth(room, K, pose)
+    pts = orc.unproject(depth, K, 3, 0)
+    F = orc.fitness(psi, vox, origin, pts, pose.as_3x4()[None], lookup=0, prec=1)[0]
+    assert F <= 0.75 * (vox / mu) ** 2 + 1e-4
+    Ft = orc.fitness(psi, vox, origin, pts, pose.as_3x4()[None], lookup=1, prec=1)[0]
+    assert Ft < 2e-3
+    # a 2-voxel shift along the view axis is clearly worse
+    T2 = pose.as_3x4().copy()
+    T2[:, 3] += 0.04 * pose.R[:, 2]
+    F2 = orc.fitness(psi, vox, origin, pts, T2[None], lookup=0, prec=1)[0]
+    assert F2 > 4 * F
+
+
+def test_fitness_outside_grid_is_one(orc):
+    psi = np.zeros((8, 8, 8), np.float32)
+    pts = np.random.default_rng(1).uniform(-1, 1, (100, 3)).astype(np.float32)
+    T = np.array([[1, 0, 0, 50.0], [0, 1, 0, 0], [0, 0, 1, 0]])
+    for lk in (0, 1):
+        for prec in (0, 1):
+            assert orc.fitness(psi, 0.1, np.zeros(3), pts, T[None], lookup=lk, prec=prec)[0] == 1.0
+    # no points at all: F = 1
+    assert orc.fitness(psi, 0.1, np.zeros(3), np.zeros((0, 3), np.float32), T[None])[0] == 1.0
+
+
+def test_fitness_sum_is_exact_sum_of_lookups(orc):
+    """Nearest-lookup F times |O| equals the exactly rounded sum (math.fsum)
+    of the squared values at the voxels the index routine reports."""
+    rng = np.random.default_rng(2)
+    nx, ny, nz = 24, 20, 16
+    psi = rng.uniform(-1, 1, (nz, ny, nx)).astype(np.float32)
+    vox = 0.05
+    origin = np.array([-0.6, -0.5, -0.4], np.float32)
+    pts = rng.uniform(-0.7, 0.7, (3000, 3)).astype(np.float32)
+    T = np.stack([np.hstack([synth.axis_angle(rng.standard_normal(3), 0.3), rng.uniform(-0.1, 0.1, (3, 1))])
+                  for _ in range(6)])
+    F = orc.fitness(psi, vox, origin, pts, T, lookup=0, prec=1)
+    idx = orc.voxel_indices((nx, ny, nz), vox, origin, pts, T)
+    flat = psi.ravel().astype(np.float64)
+    for i in range(len(T)):
+        v = np.where(idx[i] >= 0, flat[np.maximum(idx[i], 0)], 1.0)
+        exact = math.fsum(v * v) / len(pts)
+        assert abs(F[i] - exact) <= 1e-15 * exact
+
+
+def test_voxel_indices_are_floor_of_voxel_coordinate(orc):
+    """Indices (binary32 decision) agree with the binary64 definition
+    floor((R x + t - origin) / vox) wherever the coordinate is not within
+    1e-4 voxel of a cell boundary."""
+    rng = np.random.default_rng(3)
+    dims = (40, 30, 20)
+    vox = 0.025
+    origin = np.array([-0.5, -0.4, -0.25], np.float32)
+    pts = rng.uniform(-0.6, 0.6, (2000, 3)).astype(np.float32)
+    T = np.hstack([synth.axis_angle([1, 2, 3], 0.4), [[0.01], [-0.02], [0.03]]])
+    idx = orc.voxel_indices(dims, vox, origin, pts, T[None])[0]
+    g = ((pts.astype(np.float64) @ T[:, :3].T + T[:, 3]) - origin.astype(np.float64)) / vox
+    fl = np.floor(g).astype(np.int64)
+    inside = np.all((fl >= 0) & (fl < np.array(dims)), axis=1)
+    expect = np.where(inside, (fl[:, 2] * dims[1] + fl[:, 1]) * dims[0] + fl[:, 0], -1)
+    clear = np.all(np.abs(g - np.round(g)) > 1e-4, axis=1)
+    assert clear.mean() > 0.99
+    assert np.array_equal(idx[clear], expect[clear])
+
+
+# ---------------------------------------------------------------- fusion
+@pytest.mark.parametrize("prec", [0, 1])
+def test_integrate_fronto_parallel_plane(orc, prec):
+    """A camera at the origin looking along +z at the wall z = D: along a
+    voxel column near the optical axis, every voxel that projects into the
+    image with D - z >= -mu holds min(1, (D - z)/mu) after one frame,
+    W = 1; voxels out of view or further behind are untouched."""
+    scene = synth.Scene(np.array([-3.0, -3.0, -3.0]), np.array([3.0, 3.0, 0.553]))
+    K = synth.Intrinsics.centred(64, 48, 60.0)
+    pose = synth.Pose(np.eye(3), np.zeros(3))
+    depth = synth.render_depth(scene, K, pose)
+    assert np.allclose(depth, 0.553, atol=1e-6)
+    n, vox, mu = 32, 0.02, 0.06
+    origin = np.array([-0.32, -0.32, 0.0], np.float32)
+    psi = np.ones((n, n, n), np.float32)
+    w = np.zeros_like(psi)
+    orc.integrate(psi, w, vox, origin, mu, depth, K, [1, 0, 0, 0], [0, 0, 0], prec=prec)
+    i = j = 16  # voxel column whose centre is at x = y = 0.01
+    for k in range(n):
+        z = origin[2] + (k + 0.5) * vox
+        xc = origin[0] + (i + 0.5) * vox
+        u = math.floor(K.fx * xc / z + K.cx + 0.5)
+        sdf = 0.553 - z
+        if 0 <= u < K.width and sdf >= -mu:
+            assert w[k, j, i] == 1.0
+            assert abs(psi[k, j, i] - min(1.0, sdf / mu)) < 1e-5
+        else:
+            assert w[k, j, i] == 0.0 and psi[k, j, i] == 1.0
+
+
+def test_integrate_weight_cap_and_fixed_point(orc):
+    scene = synth.Scene(np.array([-3.0, -3.0, -3.0]), np.array([3.0, 3.0, 0.4]))
+    K = synth.Intrinsics.centred(32, 24, 30.0)
+    depth = synth.render_depth(scene, K, synth.Pose(np.eye(3), np.zeros(3)))
+    n = 16
+    psi = np.ones((n, n, n), np.float32)
+    w = np.zeros_like(psi)
+    once = None
+    for rep in range(6):
+        orc.integrate(psi, w, 0.04, np.array([-0.32, -0.32, 0.0]), 0.1, depth, K, [1, 0, 0, 0], [0, 0, 0],
+                      w_max=4.0, prec=1)
+        if rep == 0:
+            once = psi.copy()
+    seen = w > 0
+    assert seen.any() and np.all(w[seen] == 4.0)
+    assert np.allclose(psi[seen], once[seen], atol=2e-7)  # the same frame is a fixed point
+
+
+def test_integrate_zero_crossing_near_surface(orc, room):
+    """Single noise-free frame: trilinear reads of the fused TSDF at the
+    frame's own surface points are near zero (projective-distance and
+    nearest-pixel error only)."""
+    dims, vox, mu = (64, 64, 64), 0.02, 0.06
+    origin = np.full(3, -0.64)
+    K = synth.Intrinsics.centred(160, 120, 140.0)
+    pose = _look([0.6, 0.5, 0.4], [0.0, 0.01, 0.0])
+    depth = synth.render_depth(room, K, pose)
+    psi = np.ones((64, 64, 64), np.float32)
+    w = np.zeros_like(psi)
+    orc.integrate(psi, w, vox, origin, mu, depth, K, pose.q, pose.t, prec=0)
+    pts = orc.unproject(depth, K, 3, 0)
+    F = orc.fitness(psi, vox, origin, pts, pose.as_3x4()[None], lookup=1, prec=0)[0]
+    assert F < 0.02
