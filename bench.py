@@ -1,0 +1,169 @@
+"""Benchmark: PST pose search + TSDF fusion on a synthetic fast-motion
+sequence, one MI355X.
+
+Workload (one step = one frame): 512^3 TSDF at 1 cm (float psi + float
+weight), 640x480 depth (f = 525, noise sigma = 0.002 z^2) stride-4
+subsampled, 10240-particle PST, 20 iterations, then fusion of the frame at
+the tracked pose.  The camera moves at 3 m/s and 2 rad/s at 30 fps through a
+procedural room.  Depth frames are rendered on the host before timing and
+are resident in HBM when the timed region starts.
+
+Prints one JSON line: value = particle x point fitness evaluations per
+second over the whole timed job (all kernels, all frames); frames/s and ATE
+against the synthetic ground truth beside it; the roofline of the fitness
+kernel from HIP-event timings; the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+# fitness kernel, NEAREST lookup, binary32 TSDF: one 4-byte TSDF gather per
+# particle x point evaluation (the paper's per-evaluation data movement)
+BYTES_PER_EVAL = {0: 4.0, 1: 32.0}
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--lookup", choices=["nearest", "trilinear"], default="nearest")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--render-workers", type=int, default=16)
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(psi, seq, depth, prev_pose, n_particles, lookup):
+    """The oracle, single-threaded, on one iteration of one frame."""
+    import oracle
+    oracle.build(force=False)
+    pst, _ = oracle.pst_sample(n_particles, 5600)
+    t0 = time.perf_counter()
+    o = oracle.track_frame(psi, seq.vox, seq.origin, depth, seq.K, pst, prev_pose.q, prev_pose.t,
+                           np.full(6, 0.55), max_iters=1, stride=seq.stride, lookup=lookup, prec=oracle.F32)
+    dt = time.perf_counter() - t0
+    evals = n_particles * o["n_overlap_last"]
+    return dict(value=evals / dt, unit="particle*point fitness evals/s", cores=1, kind="oracle",
+                sample=f"1 iteration of frame 1: {n_particles} particles x {o['n_overlap_last']} points, "
+                       f"512^3 TSDF, {dt:.1f} s")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1",
+                          "n_gpus_requested": args.gpus}), flush=True)
+        sys.exit(2)
+    import torch
+
+    import synth
+    from paper_2105_05600_amd import rose
+
+    lookup = 0 if args.lookup == "nearest" else 1
+    n_frames = 1 + args.warmup + args.steps
+    if n_frames > 300:
+        raise SystemExit("warmup + steps must be < 300 (sequence length)")
+    seq = synth.room_sequence()
+    t0 = time.perf_counter()
+    depths = seq.depths(range(n_frames), workers=args.render_workers)
+    log(f"rendered {n_frames} frames in {time.perf_counter() - t0:.1f} s")
+    torch.cuda.set_device(0)
+    dev_depths = [torch.from_numpy(d).cuda() for d in depths]
+    vol = rose.Tsdf(seq.dims, seq.vox, seq.mu, seq.origin)
+    pst = rose.pst_sample(seq.n_particles, 5600)
+    params = rose.track_params(max_iters=seq.iters, stride=seq.stride, lookup=lookup)
+    p0 = seq.poses[0]
+    st = rose.track_state(p0.q, p0.t, [1.0] * 6, tsdf_built=False)
+    rose.track_frame(vol, dev_depths[0], seq.K, pst, params, st)  # first frame: r_1 = 0.55
+    vol.integrate(dev_depths[0], seq.K, p0.q, p0.t)
+    st.tsdf_built = 1
+    est = [np.array(p0.t)]
+    psi_after0 = None
+    if not args.no_cpu_baseline:
+        psi_t, _ = vol.export()
+        psi_after0 = psi_t.cpu().numpy()
+        del psi_t
+
+    def step(i):
+        res = rose.track_frame(vol, dev_depths[i], seq.K, pst, params, st)
+        vol.integrate(dev_depths[i], seq.K, st.pose.q, st.pose.t)
+        est.append(np.array(st.pose.t))
+        return res
+
+    for i in range(1, 1 + args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} frames done")
+    rose.profile_enable(True)
+    rose.profile_reset()
+    evals = 0.0
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(1 + args.warmup, n_frames):
+        res = step(i)
+        evals += seq.n_particles * float(sum(res["n_overlap"]))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    prof = rose.profile_read()
+    rose.profile_enable(False)
+    log(f"timed {args.steps} frames in {wall:.3f} s; profile {prof}")
+
+    gt = np.array([p.t for p in seq.poses[:n_frames]])
+    est_a = np.array(est)
+    ate_mean, ate_rmse = synth.ate(est_a, gt)
+    fit_ms = prof["fitness_ms"] / max(prof["fitness_launches"], 1)
+    fit_evals = prof["fitness_evals"] / max(prof["fitness_launches"], 1)
+    achieved = fit_evals * BYTES_PER_EVAL[lookup] / (fit_ms * 1e-3) / 1e9
+    out = {
+        "metric": "particle*point fitness evals/s (+ frames/s at 10k particles; ATE vs ground truth)",
+        "value": evals / wall,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "room sequence, 512^3 TSDF @1cm f32, 640x480 f=525 stride 4, PST 10240, "
+                               "20 iterations + fusion per frame, 3 m/s 2 rad/s",
+                   "tsdf": [512, 512, 512], "voxel_m": 0.01, "image": [640, 480], "stride": 4,
+                   "particles": seq.n_particles, "iters": seq.iters, "lookup": args.lookup},
+        "frames_per_s": args.steps / wall,
+        "fitness_kernel_evals_per_s": prof["fitness_evals"] / (prof["fitness_ms"] * 1e-3),
+        "ate_rmse_m": ate_rmse,
+        "ate_mean_m": ate_mean,
+        "time_split_ms_per_frame": {"fitness": prof["fitness_ms"] / args.steps,
+                                    "update": prof["update_ms"] / args.steps,
+                                    "integrate": prof["integrate_ms"] / args.steps},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_fitness", "avg_launch_ms": fit_ms, "evals_per_launch": fit_evals},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on one iteration of frame 1")
+        out["cpu_baseline"] = cpu_baseline(psi_after0, seq, depths[1], p0, seq.n_particles, lookup)
+    print(json.dumps(out), flush=True)
+    vol.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,258 @@
+/*
+ * rose.h -- C ABI of the MI355X (gfx950) PST pose-search library.
+ *
+ * The library implements the per-frame camera tracking of ROSEFusion
+ * (Zhang, Zhu, Ma, Xu -- "ROSEFusion: Random Optimization for Online Dense
+ * Reconstruction under Fast Camera Motion", ACM TOG 40(4), 2021): particle
+ * filter optimisation with a particle swarm template (PST) against a TSDF
+ * volume (Sec. 3.3, Alg. 1, Sec. 4), and the volumetric depth fusion it
+ * builds on (Sec. 3, "volumetric depth fusion framework").
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * - Every call returns a rose_status and never throws.  Arguments are
+ *   validated before anything is enqueued; on a non-OK status nothing was
+ *   enqueued and rose_last_error() holds a text for the calling thread.
+ * - "_dev" pointers are device pointers (HIP device memory, e.g. the storage
+ *   of a torch tensor on the GPU).  All other pointers are host pointers.
+ *   Buffers belong to the caller; the library never frees caller memory.
+ * - Work is enqueued on the given stream `s` (0 = the null stream) and is
+ *   asynchronous unless stated otherwise.
+ * - Poses map camera to world: X = R x + t (Eq. unproj).  Quaternions are
+ *   (w, x, y, z), Hamilton convention, unit length.  Lengths are metres.
+ * - Camera frame: x right, y down, z forward; depth is z-depth in metres,
+ *   0 (or any value that is not > 0) marks a missing measurement.
+ * - The TSDF stores psi = (signed distance / truncation), clamped to
+ *   [-1, 1]; unobserved voxels hold +1 with weight 0, and a query outside the
+ *   grid reads +1 (a penalty, never an exclusion).
+ */
+#ifndef ROSE_H
+#define ROSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ROSE_OK = 0,
+    ROSE_E_ARG = -1,         /* a NULL/negative/out-of-range argument */
+    ROSE_E_SHAPE = -2,       /* sizes inconsistent or above a documented limit */
+    ROSE_E_DEVICE = -3,      /* a HIP runtime call failed */
+    ROSE_E_STATE = -4,       /* the call cannot run in the current state (e.g. no valid depth) */
+    ROSE_E_UNSUPPORTED = -5  /* valid request that this build does not implement */
+} rose_status;
+
+typedef enum { ROSE_TSDF_F32 = 0, ROSE_TSDF_F16 = 1, ROSE_TSDF_SN16 = 2 } rose_tsdf_fmt;
+typedef enum { ROSE_LOOKUP_NEAREST = 0, ROSE_LOOKUP_TRILINEAR = 1 } rose_lookup;
+
+/* pso_track_frame flags: the ablation switches of Sec. 5.2 (Tab. ablt-tsdf) */
+#define ROSE_FLAG_NO_OVERLAP 1   /* O_k := every valid point (Eq. validness skipped) */
+#define ROSE_FLAG_NO_NORMALIZE 2 /* fitness = exp(-sum psi^2 / tau) (Eq. ourlh) instead of Eq. normallh */
+
+#define ROSE_MAX_ITERS 32
+#define ROSE_MAX_PARTICLES 65536
+#define ROSE_MAX_IMAGE_PIXELS (4096 * 4096)
+
+typedef struct {
+    float fx, fy, cx, cy;   /* pinhole intrinsics in pixels */
+    int32_t width, height;  /* image size; depth images are row-major height x width */
+} rose_camera;
+
+typedef struct {
+    double q[4]; /* unit quaternion (w, x, y, z) */
+    double t[3]; /* translation, metres */
+} rose_pose;
+
+typedef struct rose_tsdf rose_tsdf; /* opaque; host-side metadata plus small device scratch */
+
+/* Text of the last non-OK status of the calling thread ("" if none). */
+const char* rose_last_error(void);
+/* Library version string. */
+const char* rose_version(void);
+
+/* ------------------------------------------------------------------ TSDF */
+/* Bytes of device memory the caller provides for a TSDF of nx*ny*nz voxels
+ * in format `fmt`; which = 0 for the psi buffer, 1 for the weight buffer.
+ * F32: 4 + 4 bytes per voxel; F16 and SN16: 2 + 2 (u16 weight).  Returns 0
+ * for invalid sizes (each dimension a positive multiple of 8, <= 2048). */
+size_t tsdf_bytes(int32_t nx, int32_t ny, int32_t nz, rose_tsdf_fmt fmt, int32_t which);
+
+/* Create a TSDF handle over caller-owned device buffers psi_dev and
+ * weight_dev (sizes from tsdf_bytes) and enqueue their initialisation to
+ * psi = +1, weight = 0 on `s`.  Voxel (i,j,k) covers
+ * origin + [i, i+1) * voxel_m (and likewise in y, z); its centre is at
+ * origin + (i + 1/2) * voxel_m.  trunc_m is the truncation distance mu;
+ * w_max caps the running-average weight (the fusion framework of Sec. 3:
+ * Curless & Levoy 1996, KinectFusion 2011).  The buffer layout is internal
+ * (8x8x8 bricks, brick-major); use tsdf_export / tsdf_import for a linear
+ * view.  Errors: ROSE_E_ARG (NULL pointer, non-positive voxel/truncation,
+ * w_max < 1), ROSE_E_SHAPE (dimensions), ROSE_E_DEVICE. */
+rose_status tsdf_create(int32_t nx, int32_t ny, int32_t nz, float voxel_m, float trunc_m, const float origin_m[3],
+                        rose_tsdf_fmt fmt, float w_max, void* psi_dev, void* weight_dev, hipStream_t s,
+                        rose_tsdf** out);
+
+/* Release the handle and its device scratch.  NULL is a no-op.  Never frees
+ * the caller's psi/weight buffers.  Synchronises the handle's scratch. */
+rose_status tsdf_destroy(rose_tsdf* h);
+
+/* Fuse one depth frame (height x width float32, metres) taken at camera pose
+ * T_wc into the TSDF (projective running average, one weight per frame):
+ * for every voxel whose centre X maps to camera coordinates x_c = T^-1 X
+ * with z_c > 0 and a nearest pixel (u, v) = (floor(fx x_c/z_c + cx + 1/2),
+ * floor(fy y_c/z_c + cy + 1/2)) inside the image with depth D > 0:
+ * sdf = D - z_c; if sdf >= -mu: d = min(1, sdf/mu),
+ * psi <- (W psi + d)/(W + 1), W <- min(W + 1, w_max).
+ * The geometry is evaluated in binary32 in the operation order of the
+ * library's numerics notes (folded voxel->camera transform, fmaf chain,
+ * correctly rounded division).  Errors: ROSE_E_ARG, ROSE_E_SHAPE. */
+rose_status tsdf_integrate(rose_tsdf* h, const float* depth_dev, const rose_camera* cam, const rose_pose* T_wc,
+                           hipStream_t s);
+
+/* Copy the TSDF to / from linear float32 buffers laid out [k][j][i]
+ * (i fastest), nx*ny*nz elements each: psi decoded to float, weight as
+ * float.  tsdf_import encodes into the handle's format (round to nearest
+ * even for F16; round(psi * 32767) clamped for SN16; weights rounded and
+ * clamped to [0, 65535] for u16).  weight_lin_dev may be NULL in
+ * tsdf_import: weights then become 1 where psi < 1 and 0 elsewhere. */
+rose_status tsdf_export(const rose_tsdf* h, float* psi_lin_dev, float* weight_lin_dev, hipStream_t s);
+rose_status tsdf_import(rose_tsdf* h, const float* psi_lin_dev, const float* weight_lin_dev, hipStream_t s);
+
+/* -------------------------------------------------------------- PST (a1) */
+/* Pre-sample the particle swarm template (Sec. 3.3; Sec. 4 "PST
+ * pre-sampling"): n particles uniform in the closed unit 6-ball, written as
+ * n x 6 float32 (q_x, q_y, q_z, x, y, z) to out_dev.  Row 0 is the origin
+ * (the PST centre).  Row i > 0 takes the first accepted attempt a of:
+ * Philox4x64-10 (Salmon et al., SC 2011) block with counter (i, a, 0, 0),
+ * key (seed, 0); m_0..m_5 = bits 63..40 and 39..16 of words 0, 1, 2;
+ * a_d = 2 m_d + 1 - 2^24; accept iff sum a_d^2 <= 2^48 (exact integers);
+ * p_d = a_d * 2^-24 (exact).  1024 rejected attempts give the zero row.
+ * Errors: ROSE_E_ARG (n < 1 or > ROSE_MAX_PARTICLES, NULL). */
+rose_status pst_sample(int32_t n, uint64_t seed, float* out_dev, hipStream_t s);
+
+/* Particle poses (Alg. 1 MovePST + RescalePST applied on the fly to the
+ * stored unit template, Sec. 4 "GPU implementation"): for each row p_i,
+ * u = r (.) p_i and pose_i = c * Delta(u), Delta(u) = (quaternion
+ * (sqrt(1 - |u_123|^2), u_1, u_2, u_3), translation u_456).  Writes
+ * n x 12 binary64 [R|t] row-major to T_dev.  Diagnostic view of the pose
+ * build that pso_track_frame performs inside its fitness kernel. */
+rose_status pst_particle_poses(const rose_pose* centre, const double r[6], const float* pst_dev, int32_t n,
+                               double* T_dev, hipStream_t s);
+
+/* --------------------------------------------------------- fitness (a5) */
+/* Fitness of n arbitrary poses over m camera-frame points (Eq. ourlh with
+ * the normalisation of Eq. normallh over the given points):
+ * F_i = (1/m) sum_j psi(R_i x_j + t_i)^2 and rho_i = exp(-F_i) (tau = 1).
+ * pts_dev: m x 3 float32; T_dev: n x 12 float32 row-major [R|t]
+ * camera->world; F_dev: n float32; rho_dev: n float32 or NULL.  m = 0 gives
+ * F = 1.  The voxel is chosen in binary32 from a transform folded with the
+ * voxel scale in binary64 and rounded once; squares are summed in binary64.
+ * Limits: n <= ROSE_MAX_PARTICLES, m <= ROSE_MAX_IMAGE_PIXELS. */
+rose_status fitness_eval(const rose_tsdf* h, const float* pts_dev, int32_t m, const float* T_dev, int32_t n,
+                         rose_lookup lk, float* F_dev, float* rho_dev, hipStream_t s);
+
+/* Diagnostic: the NEAREST voxel of every (pose, point) pair of fitness_eval
+ * as a linear index (k*ny + j)*nx + i, or -1 outside the grid; idx_dev is
+ * n x m int64. */
+rose_status fitness_voxel_indices(const rose_tsdf* h, const float* pts_dev, int32_t m, const float* T_dev, int32_t n,
+                                  int64_t* idx_dev, hipStream_t s);
+
+/* ------------------------------------------------- points (a2) / overlap (a3) */
+/* Stride-s unprojection (Eq. unproj; Sec. 4 stride-based downsampling):
+ * pixels (u, v) = (0, s, 2s, ..) x (0, s, 2s, ..) with depth z > 0 give
+ * x = (((float)u - cx) z / fx, ((float)v - cy) z / fy, z) (binary32), in
+ * row-major pixel order, written as count x 3 float32 to pts_dev (capacity
+ * ceil(H/s) * ceil(W/s) points); the count goes to *count_dev (int32). */
+rose_status depth_unproject(const float* depth_dev, const rose_camera* cam, int32_t stride, float* pts_dev,
+                            int32_t* count_dev, hipStream_t s);
+
+/* Overlap mask (Eq. validness): mask_dev[j] = 1 iff point j, moved to the
+ * world by `centre` and into the previous camera by prev^-1, has z' > 0 and
+ * projects inside [0, W-1] x [0, H-1].  m points, m x 3 float32. */
+rose_status overlap_mask(const float* pts_dev, int32_t m, const rose_pose* centre, const rose_pose* prev,
+                         const rose_camera* cam, uint8_t* mask_dev, hipStream_t s);
+
+/* ---------------------------------------------------- per-frame tracking */
+typedef struct {
+    int32_t max_iters;  /* 1..ROSE_MAX_ITERS (paper: 20) */
+    int32_t early_stop; /* 1: stop on two consecutive empty APS or |u*_d| < stop_tol for all d */
+    int32_t stride;     /* depth subsampling stride, >= 1 */
+    int32_t lookup;     /* rose_lookup */
+    int32_t flags;      /* ROSE_FLAG_* */
+    int32_t reserved;
+    double beta;        /* momentum of Eq. momentum (paper: 0.1) */
+    double eps;         /* epsilon of Eq. rsinter (paper: 1e-3) */
+    double tau;         /* temperature of Eq. pfolh (paper: 1) */
+    double stop_tol;    /* stop tolerance (paper: 1e-6) */
+} rose_track_params;
+
+typedef struct {
+    rose_pose pose;      /* in: s^{t-1}_* (previous final pose); out: s^t_* */
+    double r[6];         /* in: r_0 = r_1^{t-1}; out: r_1^t (axis lengths after iteration 1) */
+    double rho;          /* out: approximated fitness (Eq. wafit) of the last non-empty iteration */
+    int32_t tsdf_built;  /* in: 0 for the first frame (Sec. 4 corner case 1) */
+    int32_t frame;       /* incremented by each successful call */
+} rose_track_state;
+
+typedef struct {
+    int32_t iters;          /* iterations run */
+    int32_t n_points;       /* valid subsampled points */
+    int32_t n_overlap_last; /* |O_k| of the last iteration */
+    int32_t reserved;
+    int32_t aps_size[ROSE_MAX_ITERS];
+    int32_t n_overlap[ROSE_MAX_ITERS]; /* |O_k| per iteration */
+    double rho_iter[ROSE_MAX_ITERS];   /* rho~ per iteration (rho of the centre when the APS is empty) */
+} rose_track_stats;
+
+/* One frame of Alg. 1 (PFO with PST) on the device.
+ * depth_dev: the current depth frame (cam->height x cam->width float32).
+ * pst_dev: n_particles x 6 template from pst_sample (row 0 = origin).
+ * init_centre: PST centre c_0 (NULL: state->pose, i.e. c_0 = s^{t-1}_*);
+ * init_r: r_0 (NULL: state->r).  The overlap set always reprojects into the
+ * previous frame's camera at state->pose.
+ * Every iteration k: O_k with the centre c_{k-1}; fitness of every particle
+ * pose c_{k-1} * Delta(r_{k-1} (.) p_i) (Eq. normallh); APS = particles with
+ * fitness above the centre's (particle 0); CompBestState (Eq. ebs),
+ * approximated best fitness (Eq. wafit), CompAxisLength (Eqs. rsdir,
+ * rsinter with |v_d|, momentum), MovePST (c_k = c_{k-1} * Delta(u*)) and the
+ * corner cases of Sec. 4.  The whole loop runs on the device; the call
+ * synchronises `s` once at the end and then fills state/stats.
+ * state->tsdf_built == 0: no fitness is evaluated; r_1 = beta r_0 +
+ * (1-beta) 0.5 and the pose is kept.  Returns ROSE_E_STATE (state
+ * unchanged) when the frame has no valid point.
+ * Limits: n_particles <= ROSE_MAX_PARTICLES; image <= ROSE_MAX_IMAGE_PIXELS.
+ * A handle must not be used by two streams at once. */
+rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_camera* cam, const float* pst_dev,
+                            int32_t n_particles, const rose_track_params* p, const rose_pose* init_centre,
+                            const double* init_r, rose_track_state* state, rose_track_stats* stats, hipStream_t s);
+
+/* ------------------------------------------------------- kernel timing */
+/* When enabled (process-wide), pso_track_frame and tsdf_integrate bracket
+ * each fitness, update and integration launch with HIP events recorded on
+ * the call's stream; rose_profile_read resolves the pending events
+ * (synchronising on them), adds their elapsed times to the totals and
+ * returns the totals; rose_profile_reset clears them.  Timing perturbs the
+ * launch stream slightly and is meant for measurement runs. */
+typedef struct {
+    double fitness_ms;      /* summed duration of fitness kernel launches */
+    int64_t fitness_launches;
+    double fitness_evals;   /* summed particle x point evaluations of those launches */
+    double update_ms;       /* per-iteration update kernels (APS, PST move/rescale, overlap) */
+    int64_t update_launches;
+    double integrate_ms;
+    int64_t integrate_launches;
+} rose_profile;
+
+rose_status rose_profile_enable(int32_t on);
+rose_status rose_profile_reset(void);
+rose_status rose_profile_read(rose_profile* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ROSE_H */

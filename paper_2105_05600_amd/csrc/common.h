@@ -1,0 +1,332 @@
+// Internal definitions shared by the HIP translation units of librose.
+//
+// gfx950 (CDNA4): wave64, 160 KB LDS per CU.  All floating-point code is built
+// with -ffp-contract=off: every fused multiply-add is an explicit fmaf / fma,
+// so that the binary32 geometry (voxel and pixel choice) follows a fixed
+// operation order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include <cstdint>
+#include <cstring>
+
+#include "rose.h"
+
+namespace rose {
+
+constexpr int kWave = 64;
+constexpr int kBrick = 8;          // bricks of 8x8x8 voxels, brick-major storage
+constexpr int kBrickVox = 512;
+
+// ------------------------------------------------------------------ errors
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define ROSE_CHECK_HIP(expr)                                                              \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess) {                                                           \
+            ::rose::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),      \
+                              __FILE__, __LINE__);                                        \
+            return ROSE_E_DEVICE;                                                         \
+        }                                                                                 \
+    } while (0)
+
+#define ROSE_REQUIRE(cond, code, ...)  \
+    do {                               \
+        if (!(cond)) {                 \
+            ::rose::set_error(__VA_ARGS__); \
+            return (code);             \
+        }                              \
+    } while (0)
+
+// -------------------------------------------------------------------- grid
+struct Grid {
+    int32_t nx, ny, nz;
+    int32_t nbx, nby, nbz;
+    float vox, mu, w_max;
+    float origin[3];
+    int32_t fmt;  // rose_tsdf_fmt
+    void* psi;
+    void* wgt;
+};
+
+// brick-major offset of voxel (i, j, k): brick index * 512 + in-brick offset
+__host__ __device__ inline uint32_t brick_offset(const Grid& g, uint32_t i, uint32_t j, uint32_t k) {
+    uint32_t b = ((k >> 3) * (uint32_t)g.nby + (j >> 3)) * (uint32_t)g.nbx + (i >> 3);
+    return (b << 9) | ((k & 7u) << 6) | ((j & 7u) << 3) | (i & 7u);
+}
+
+// ------------------------------------------------------- TSDF value codecs
+// F32: float psi, float weight.  F16: half psi (round to nearest even),
+// u16 weight.  SN16: int16 psi = round(psi * 32767), u16 weight.
+template <int FMT>
+__device__ inline float load_psi(const void* base, uint32_t off) {
+    if constexpr (FMT == ROSE_TSDF_F32) {
+        return ((const float*)base)[off];
+    } else if constexpr (FMT == ROSE_TSDF_F16) {
+        return __half2float(((const __half*)base)[off]);
+    } else {
+        return (float)((const int16_t*)base)[off] * (1.0f / 32767.0f);
+    }
+}
+
+template <int FMT>
+__device__ inline void store_psi(void* base, uint32_t off, float v) {
+    if constexpr (FMT == ROSE_TSDF_F32) {
+        ((float*)base)[off] = v;
+    } else if constexpr (FMT == ROSE_TSDF_F16) {
+        ((__half*)base)[off] = __float2half_rn(v);
+    } else {
+        float s = rintf(fminf(fmaxf(v, -1.0f), 1.0f) * 32767.0f);
+        ((int16_t*)base)[off] = (int16_t)s;
+    }
+}
+
+template <int FMT>
+__device__ inline float load_w(const void* base, uint32_t off) {
+    if constexpr (FMT == ROSE_TSDF_F32) {
+        return ((const float*)base)[off];
+    } else {
+        return (float)((const uint16_t*)base)[off];
+    }
+}
+
+template <int FMT>
+__device__ inline void store_w(void* base, uint32_t off, float v) {
+    if constexpr (FMT == ROSE_TSDF_F32) {
+        ((float*)base)[off] = v;
+    } else {
+        float c = rintf(fminf(fmaxf(v, 0.0f), 65535.0f));
+        ((uint16_t*)base)[off] = (uint16_t)c;
+    }
+}
+
+// ---------------------------------------------------------- pose algebra
+// Binary64.  Quaternion (w, x, y, z), Hamilton product; a pose maps camera
+// to world.
+__host__ __device__ inline void quat_rot(const double q[4], double R[9]) {
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1.0 - 2.0 * (y * y + z * z);
+    R[1] = 2.0 * (x * y - w * z);
+    R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z);
+    R[4] = 1.0 - 2.0 * (x * x + z * z);
+    R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y);
+    R[7] = 2.0 * (y * z + w * x);
+    R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+__host__ __device__ inline void quat_prod(const double a[4], const double b[4], double c[4]) {
+    c[0] = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+    c[1] = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
+    c[2] = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
+    c[3] = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
+}
+
+// chart of the 6D state (q_x, q_y, q_z, x, y, z): quaternion
+// (sqrt(1 - |u_123|^2), u_1, u_2, u_3) (imaginary part scaled to unit length
+// and w = 0 when |u_123| > 1) and translation u_456.
+__host__ __device__ inline void chart(const double u[6], double q[4], double t[3]) {
+    const double s = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    if (s <= 1.0) {
+        q[0] = sqrt(1.0 - s);
+        q[1] = u[0];
+        q[2] = u[1];
+        q[3] = u[2];
+    } else {
+        const double n = sqrt(s);
+        q[0] = 0.0;
+        q[1] = u[0] / n;
+        q[2] = u[1] / n;
+        q[3] = u[2] / n;
+    }
+    t[0] = u[3];
+    t[1] = u[4];
+    t[2] = u[5];
+}
+
+// pose of a template particle: c * Delta(r (.) p)  -> 3x4 [R|t]
+__host__ __device__ inline void particle_transform(const double qc[4], const double tc[3], const double r[6],
+                                                   const float p[6], double T[12]) {
+    double u[6], qd[4], td[3], q[4], R[9], Rc[9];
+    for (int d = 0; d < 6; ++d) u[d] = r[d] * (double)p[d];
+    chart(u, qd, td);
+    quat_prod(qc, qd, q);
+    quat_rot(q, R);
+    quat_rot(qc, Rc);
+    for (int i = 0; i < 3; ++i) {
+        T[4 * i + 0] = R[3 * i + 0];
+        T[4 * i + 1] = R[3 * i + 1];
+        T[4 * i + 2] = R[3 * i + 2];
+        const double rt = Rc[3 * i + 0] * td[0] + Rc[3 * i + 1] * td[1] + Rc[3 * i + 2] * td[2];
+        T[4 * i + 3] = rt + tc[i];
+    }
+}
+
+// MovePST of the centre: c <- c * Delta(u), quaternion renormalised, w >= 0
+__host__ __device__ inline void retract(double qc[4], double tc[3], const double u[6]) {
+    double qd[4], td[3], q[4], Rc[9], rt[3];
+    chart(u, qd, td);
+    quat_prod(qc, qd, q);
+    quat_rot(qc, Rc);
+    for (int i = 0; i < 3; ++i) rt[i] = Rc[3 * i + 0] * td[0] + Rc[3 * i + 1] * td[1] + Rc[3 * i + 2] * td[2];
+    const double n = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    const double sg = (q[0] < 0.0) ? -1.0 : 1.0;
+    for (int i = 0; i < 4; ++i) qc[i] = sg * q[i] / n;
+    for (int i = 0; i < 3; ++i) tc[i] = rt[i] + tc[i];
+}
+
+__host__ __device__ inline void pose_matrix(const double q[4], const double t[3], double T[12]) {
+    double R[9];
+    quat_rot(q, R);
+    for (int i = 0; i < 3; ++i) {
+        T[4 * i + 0] = R[3 * i + 0];
+        T[4 * i + 1] = R[3 * i + 1];
+        T[4 * i + 2] = R[3 * i + 2];
+        T[4 * i + 3] = t[i];
+    }
+}
+
+// A = P^-1 C for rigid 3x4 transforms (P^-1 = [P_R^T | -P_R^T P_t])
+__host__ __device__ inline void relative_transform(const double P[12], const double Cm[12], double A[12]) {
+    double Pi[12];
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) Pi[4 * i + j] = P[4 * j + i];
+        Pi[4 * i + 3] = -(P[0 * 4 + i] * P[3] + P[1 * 4 + i] * P[7] + P[2 * 4 + i] * P[11]);
+    }
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 4; ++j) {
+            double s = Pi[4 * i + 0] * Cm[0 * 4 + j] + Pi[4 * i + 1] * Cm[1 * 4 + j] + Pi[4 * i + 2] * Cm[2 * 4 + j];
+            if (j == 3) s += Pi[4 * i + 3];
+            A[4 * i + j] = s;
+        }
+    }
+}
+
+// camera->world transform folded with the voxel scaling, binary64, rounded
+// once: V = [R / vox | (t - origin) / vox]
+__host__ __device__ inline void fold_to_voxel(const double T[12], double vox, const float origin[3], float V[12]) {
+    const double inv = 1.0 / vox;
+    for (int c = 0; c < 3; ++c) {
+        for (int j = 0; j < 3; ++j) V[4 * c + j] = (float)(T[4 * c + j] * inv);
+        V[4 * c + 3] = (float)((T[4 * c + 3] - (double)origin[c]) * inv);
+    }
+}
+
+// the binary32 rigid transform used everywhere: fmaf chain, x then y then z
+__device__ inline float xf_row(float a0, float a1, float a2, float a3, float x, float y, float z) {
+    return fmaf(a2, z, fmaf(a1, y, fmaf(a0, x, a3)));
+}
+
+// ------------------------------------------------------- device tracking state
+struct DevState {
+    double qc[4];
+    double tc[3];
+    double r[6];
+    double r1[6];
+    double Tprev[12];
+    double rho_last;
+    int32_t k;
+    int32_t stopped;
+    int32_t empty_streak;
+    int32_t have_rho;
+    int32_t n_points;
+    int32_t n_overlap;
+    int32_t status;
+    int32_t pad;
+    int32_t aps[ROSE_MAX_ITERS];
+    int32_t n_overlap_iter[ROSE_MAX_ITERS];
+    double rho_iter[ROSE_MAX_ITERS];
+};
+
+// --------------------------------------------------------- wave primitives
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__device__ inline int wave_sum_i(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Order-preserving block compaction step: flag per thread -> exclusive
+// position among flagged threads of the block; *total receives the count.
+// lds must hold blockDim.x / 64 + 1 ints.  Uses two __syncthreads().
+__device__ inline int block_scan_flag(int flag, int* lds, int* total) {
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    const uint64_t m = __ballot(flag);
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int in_wave = __popcll(m & lt);
+    if (lane == 0) lds[wid] = __popcll(m);
+    __syncthreads();
+    int base = 0, tot = 0;
+    for (int w = 0; w < nw; ++w) {
+        const int c = lds[w];
+        base += (w < wid) ? c : 0;
+        tot += c;
+    }
+    __syncthreads();
+    *total = tot;
+    return base + in_wave;
+}
+
+// ------------------------------------------------------------ host helpers
+struct Scratch;  // defined in api.hip
+
+}  // namespace rose
+
+// Handle.  The TSDF buffers are the caller's; the tracking scratch below is
+// owned by the handle and released by tsdf_destroy.
+struct rose_tsdf {
+    rose::Grid g;
+    int device;
+    // tracking scratch (device)
+    float4* pts;        // all valid subsampled points of the current frame
+    float4* pts_o;      // overlap-compacted points
+    double* partial;    // n_particles x splits partial sums of psi^2
+    float* F;           // n_particles fitness values of the last iteration
+    rose::DevState* st; // device state of the current frame
+    rose::DevState* st_host;  // pinned host copy
+    int64_t cap_points;
+    int64_t cap_points_o;
+    int64_t cap_partial;
+    int64_t cap_particles;
+};
+
+namespace rose {
+
+// Fitness launch (fitness.hip).  Pose source: explicit binary32 transforms
+// (T32 != nullptr) or the PST of the device tracking state (st, pst).
+struct FitLaunch {
+    Grid g;
+    const float4* pts;
+    const int32_t* count_dev;  // device point count, or nullptr to use `count`
+    int32_t count;
+    const float* T32;
+    const DevState* st;
+    const float* pst;
+    int32_t n;
+    int32_t splits;
+    int32_t lookup;
+    double* partial;  // n x splits
+};
+rose_status launch_fitness(const FitLaunch& L, hipStream_t s);
+int choose_splits(int32_t n_particles, int64_t max_points);
+
+// kernel timing (profile.hip)
+enum { PROF_FITNESS = 0, PROF_UPDATE = 1, PROF_INTEGRATE = 2 };
+bool prof_on();
+int prof_begin(int kind, hipStream_t s);          // -1 when timing is off
+void prof_end(int tok, hipStream_t s, double evals);
+void prof_set_evals(int tok, double evals);
+
+}  // namespace rose

@@ -1,0 +1,260 @@
+// Particle fitness evaluation (Eq. ourlh with the normalisation of
+// Eq. normallh) -- the hot loop of the pose search.
+//
+// Mapping on gfx950: one wavefront evaluates P particles over one slice of
+// the point list.  The P transforms are built once per wave in binary64
+// (c * Delta(r (.) p), folded with the voxel scale, rounded once to binary32)
+// and held wave-uniform; the slice's points are striped across the 64 lanes,
+// so each point is loaded once (one 16-byte load) and reused for P
+// particles, and the P TSDF gathers per point are independent loads in
+// flight together.  Squares are accumulated in binary64 (the product of two
+// binary32 values is exact in binary64, so one fma per term), reduced over
+// the wave with butterfly shuffles, and written as one partial sum per
+// (particle, slice); a second pass adds the slices in a fixed order.
+#include "common.h"
+
+namespace rose {
+
+template <int FMT>
+__device__ inline float lookup_nearest(const Grid& g, float gx, float gy, float gz) {
+    const bool in = gx >= 0.0f && gx < (float)g.nx && gy >= 0.0f && gy < (float)g.ny && gz >= 0.0f &&
+                    gz < (float)g.nz;
+    const uint32_t off = in ? brick_offset(g, (uint32_t)gx, (uint32_t)gy, (uint32_t)gz) : 0u;
+    const float v = load_psi<FMT>(g.psi, off);
+    return in ? v : 1.0f;
+}
+
+template <int FMT>
+__device__ inline float lookup_trilinear(const Grid& g, float gx, float gy, float gz) {
+    const float hx = gx - 0.5f, hy = gy - 0.5f, hz = gz - 0.5f;
+    const bool in = hx >= 0.0f && hx < (float)(g.nx - 1) && hy >= 0.0f && hy < (float)(g.ny - 1) && hz >= 0.0f &&
+                    hz < (float)(g.nz - 1);
+    const uint32_t ix = in ? (uint32_t)hx : 0u, iy = in ? (uint32_t)hy : 0u, iz = in ? (uint32_t)hz : 0u;
+    const float fx = hx - (float)ix, fy = hy - (float)iy, fz = hz - (float)iz;
+    const float v000 = load_psi<FMT>(g.psi, brick_offset(g, ix, iy, iz));
+    const float v100 = load_psi<FMT>(g.psi, brick_offset(g, ix + 1, iy, iz));
+    const float v010 = load_psi<FMT>(g.psi, brick_offset(g, ix, iy + 1, iz));
+    const float v110 = load_psi<FMT>(g.psi, brick_offset(g, ix + 1, iy + 1, iz));
+    const float v001 = load_psi<FMT>(g.psi, brick_offset(g, ix, iy, iz + 1));
+    const float v101 = load_psi<FMT>(g.psi, brick_offset(g, ix + 1, iy, iz + 1));
+    const float v011 = load_psi<FMT>(g.psi, brick_offset(g, ix, iy + 1, iz + 1));
+    const float v111 = load_psi<FMT>(g.psi, brick_offset(g, ix + 1, iy + 1, iz + 1));
+    const float c00 = fmaf(fx, v100 - v000, v000);
+    const float c10 = fmaf(fx, v110 - v010, v010);
+    const float c01 = fmaf(fx, v101 - v001, v001);
+    const float c11 = fmaf(fx, v111 - v011, v011);
+    const float c0 = fmaf(fy, c10 - c00, c00);
+    const float c1 = fmaf(fy, c11 - c01, c01);
+    const float v = fmaf(fz, c1 - c0, c0);
+    return in ? v : 1.0f;
+}
+
+__device__ inline float bcast(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+template <int P, int FMT, int LK, bool FROM_STATE>
+__global__ __launch_bounds__(256) void k_fitness(FitLaunch a) {
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int group = wave / a.splits;
+    const int split = wave - group * a.splits;
+    const int p0 = group * P;
+    if (p0 >= a.n) return;
+    if (FROM_STATE && a.st->stopped) return;
+    const int m = a.count_dev ? *a.count_dev : a.count;
+
+    // particle transforms: lane l < P builds particle p0 + l
+    float V[12];
+    {
+        int pi = p0 + (lane < P ? lane : 0);
+        if (pi >= a.n) pi = a.n - 1;
+        double T[12];
+        if (FROM_STATE) {
+            float p[6];
+#pragma unroll
+            for (int d = 0; d < 6; ++d) p[d] = a.pst[6 * (int64_t)pi + d];
+            particle_transform(a.st->qc, a.st->tc, a.st->r, p, T);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 12; ++e) T[e] = (double)a.T32[12 * (int64_t)pi + e];
+        }
+        fold_to_voxel(T, (double)a.g.vox, a.g.origin, V);
+    }
+    float S[P][12];
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int e = 0; e < 12; ++e) S[p][e] = bcast(V[e], p);
+
+    const int chunk = (m + a.splits - 1) / a.splits;
+    const int j0 = split * chunk;
+    const int j1 = min(m, j0 + chunk);
+    double acc[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) acc[p] = 0.0;
+    for (int j = j0 + lane; j < j1; j += kWave) {
+        const float4 x = a.pts[j];
+        float v[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const float gx = xf_row(S[p][0], S[p][1], S[p][2], S[p][3], x.x, x.y, x.z);
+            const float gy = xf_row(S[p][4], S[p][5], S[p][6], S[p][7], x.x, x.y, x.z);
+            const float gz = xf_row(S[p][8], S[p][9], S[p][10], S[p][11], x.x, x.y, x.z);
+            v[p] = (LK == ROSE_LOOKUP_NEAREST) ? lookup_nearest<FMT>(a.g, gx, gy, gz)
+                                               : lookup_trilinear<FMT>(a.g, gx, gy, gz);
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p) acc[p] = fma((double)v[p], (double)v[p], acc[p]);
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) acc[p] = wave_sum(acc[p]);
+    if (lane == 0) {
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+            if (p0 + p < a.n) a.partial[(int64_t)(p0 + p) * a.splits + split] = acc[p];
+    }
+}
+
+// fitness_eval second pass: F_i = sum of slices / m (m = 0: F = 1)
+__global__ __launch_bounds__(256) void k_fitness_finish(const double* partial, int32_t n, int32_t splits, int32_t m,
+                                                        float* F, float* rho) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int k = 0; k < splits; ++k) s += partial[(int64_t)i * splits + k];
+    const float f = (m > 0) ? (float)(s / (double)m) : 1.0f;
+    F[i] = f;
+    if (rho) rho[i] = (float)exp(-(double)f);
+}
+
+__global__ __launch_bounds__(256) void k_voxel_indices(Grid g, const float* pts, int32_t m, const float* T32,
+                                                       int32_t n, int64_t* idx) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * m) return;
+    const int32_t i = (int32_t)(t / m), j = (int32_t)(t % m);
+    double T[12];
+    for (int e = 0; e < 12; ++e) T[e] = (double)T32[12 * (int64_t)i + e];
+    float V[12];
+    fold_to_voxel(T, (double)g.vox, g.origin, V);
+    const float x = pts[3 * (int64_t)j], y = pts[3 * (int64_t)j + 1], z = pts[3 * (int64_t)j + 2];
+    const float gx = xf_row(V[0], V[1], V[2], V[3], x, y, z);
+    const float gy = xf_row(V[4], V[5], V[6], V[7], x, y, z);
+    const float gz = xf_row(V[8], V[9], V[10], V[11], x, y, z);
+    const bool in = gx >= 0.0f && gx < (float)g.nx && gy >= 0.0f && gy < (float)g.ny && gz >= 0.0f &&
+                    gz < (float)g.nz;
+    idx[t] = in ? (((int64_t)(uint32_t)gz * g.ny + (uint32_t)gy) * g.nx + (uint32_t)gx) : -1;
+}
+
+__global__ __launch_bounds__(256) void k_pack_points(const float* pts3, int32_t m, float4* pts4) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    pts4[j] = make_float4(pts3[3 * (int64_t)j], pts3[3 * (int64_t)j + 1], pts3[3 * (int64_t)j + 2], 0.0f);
+}
+
+constexpr int kP = 4;  // particles per wave
+
+template <int FMT, int LK>
+static void launch_t(const FitLaunch& L, hipStream_t s) {
+    const int groups = (L.n + kP - 1) / kP;
+    const int64_t waves = (int64_t)groups * L.splits;
+    const unsigned blocks = (unsigned)((waves + 3) / 4);
+    if (L.T32)
+        hipLaunchKernelGGL((k_fitness<kP, FMT, LK, false>), dim3(blocks), dim3(256), 0, s, L);
+    else
+        hipLaunchKernelGGL((k_fitness<kP, FMT, LK, true>), dim3(blocks), dim3(256), 0, s, L);
+}
+
+template <int FMT>
+static void launch_f(const FitLaunch& L, hipStream_t s) {
+    if (L.lookup == ROSE_LOOKUP_TRILINEAR) launch_t<FMT, ROSE_LOOKUP_TRILINEAR>(L, s);
+    else launch_t<FMT, ROSE_LOOKUP_NEAREST>(L, s);
+}
+
+rose_status launch_fitness(const FitLaunch& L, hipStream_t s) {
+    if (L.g.fmt == ROSE_TSDF_F32) launch_f<ROSE_TSDF_F32>(L, s);
+    else if (L.g.fmt == ROSE_TSDF_F16) launch_f<ROSE_TSDF_F16>(L, s);
+    else launch_f<ROSE_TSDF_SN16>(L, s);
+    ROSE_CHECK_HIP(hipGetLastError());
+    return ROSE_OK;
+}
+
+// Slices per particle group: enough waves to fill 256 CUs several times
+// over, but at least ~4 lane-steps (256 points) per slice.
+int choose_splits(int32_t n_particles, int64_t max_points) {
+    const int64_t groups = (n_particles + kP - 1) / kP;
+    const int64_t target_waves = 256 * 4 * 8;  // CUs x SIMDs x waves per SIMD
+    int64_t s = (target_waves + groups - 1) / groups;
+    const int64_t max_s = (max_points + 255) / 256;
+    if (s > max_s) s = max_s;
+    if (s < 1) s = 1;
+    if (s > 64) s = 64;
+    return (int)s;
+}
+
+}  // namespace rose
+
+using namespace rose;
+
+extern "C" {
+
+rose_status fitness_eval(const rose_tsdf* h, const float* pts_dev, int32_t m, const float* T_dev, int32_t n,
+                         rose_lookup lk, float* F_dev, float* rho_dev, hipStream_t s) {
+    clear_error();
+    ROSE_REQUIRE(h && T_dev && F_dev && (pts_dev || m == 0), ROSE_E_ARG, "fitness_eval: NULL argument");
+    ROSE_REQUIRE(n >= 1 && n <= ROSE_MAX_PARTICLES, ROSE_E_ARG, "fitness_eval: n = %d out of [1, %d]", n,
+                 ROSE_MAX_PARTICLES);
+    ROSE_REQUIRE(m >= 0 && m <= ROSE_MAX_IMAGE_PIXELS, ROSE_E_ARG, "fitness_eval: m = %d out of range", m);
+    ROSE_REQUIRE(lk == ROSE_LOOKUP_NEAREST || lk == ROSE_LOOKUP_TRILINEAR, ROSE_E_ARG, "fitness_eval: bad lookup");
+    rose_tsdf* hm = const_cast<rose_tsdf*>(h);
+    const int splits = choose_splits(n, m);
+    // scratch: packed points and partial sums, owned by the handle
+    if (hm->cap_points < m) {
+        if (hm->pts) ROSE_CHECK_HIP(hipFree(hm->pts));
+        hm->pts = nullptr;
+        ROSE_CHECK_HIP(hipMalloc(&hm->pts, sizeof(float4) * (size_t)(m > 0 ? m : 1)));
+        hm->cap_points = m;
+    }
+    const int64_t need = (int64_t)n * splits;
+    if (hm->cap_partial < need) {
+        if (hm->partial) ROSE_CHECK_HIP(hipFree(hm->partial));
+        hm->partial = nullptr;
+        ROSE_CHECK_HIP(hipMalloc(&hm->partial, sizeof(double) * (size_t)need));
+        hm->cap_partial = need;
+    }
+    if (m > 0) {
+        hipLaunchKernelGGL(k_pack_points, dim3((m + 255) / 256), dim3(256), 0, s, pts_dev, m, hm->pts);
+        ROSE_CHECK_HIP(hipGetLastError());
+    }
+    FitLaunch L{};
+    L.g = h->g;
+    L.pts = hm->pts;
+    L.count_dev = nullptr;
+    L.count = m;
+    L.T32 = T_dev;
+    L.n = n;
+    L.splits = splits;
+    L.lookup = lk;
+    L.partial = hm->partial;
+    rose_status st = launch_fitness(L, s);
+    if (st != ROSE_OK) return st;
+    hipLaunchKernelGGL(k_fitness_finish, dim3((n + 255) / 256), dim3(256), 0, s, hm->partial, n, splits, m, F_dev,
+                       rho_dev);
+    ROSE_CHECK_HIP(hipGetLastError());
+    return ROSE_OK;
+}
+
+rose_status fitness_voxel_indices(const rose_tsdf* h, const float* pts_dev, int32_t m, const float* T_dev, int32_t n,
+                                  int64_t* idx_dev, hipStream_t s) {
+    clear_error();
+    ROSE_REQUIRE(h && pts_dev && T_dev && idx_dev, ROSE_E_ARG, "fitness_voxel_indices: NULL argument");
+    ROSE_REQUIRE(n >= 1 && m >= 1 && (int64_t)n * m <= (int64_t(1) << 31), ROSE_E_ARG,
+                 "fitness_voxel_indices: n*m out of range");
+    const int64_t total = (int64_t)n * m;
+    hipLaunchKernelGGL(k_voxel_indices, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, h->g, pts_dev, m,
+                       T_dev, n, idx_dev);
+    ROSE_CHECK_HIP(hipGetLastError());
+    return ROSE_OK;
+}
+
+}  // extern "C"

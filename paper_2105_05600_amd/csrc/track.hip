@@ -1,0 +1,471 @@
+// Per-frame PST pose search (Alg. 1 with the implementation choices of
+// Sec. 4), run entirely on the device: one small setup kernel, then per
+// iteration the fitness kernel (fitness.hip) and a single-workgroup update
+// kernel that folds the fitness into the APS sums, applies CompBestState /
+// CompAxisLength / MovePST and the corner cases, and compacts the overlap
+// set for the next iteration.  The host enqueues the whole loop and
+// synchronises once.
+#include "common.h"
+
+namespace rose {
+
+struct Cam {
+    float fx, fy, cx, cy;
+    int32_t W, H;
+};
+
+// Eq. unproj in binary32: x = (((float)u - cx) z) / fx, y likewise.
+__device__ inline float4 unproject_px(const Cam& c, int u, int v, float z) {
+    return make_float4((((float)u - c.cx) * z) / c.fx, (((float)v - c.cy) * z) / c.fy, z, 0.0f);
+}
+
+// Eq. validness with A = T_prev^-1 T_c rounded to binary32:
+// x' = A x (fmaf chain); kept iff z' > 0 and the projection
+// (fmaf(fx, x'/z', cx), fmaf(fy, y'/z', cy)) lies in [0, W-1] x [0, H-1].
+__device__ inline bool overlap_keep(const Cam& c, const float* A, float4 x) {
+    const float xp = xf_row(A[0], A[1], A[2], A[3], x.x, x.y, x.z);
+    const float yp = xf_row(A[4], A[5], A[6], A[7], x.x, x.y, x.z);
+    const float zp = xf_row(A[8], A[9], A[10], A[11], x.x, x.y, x.z);
+    if (!(zp > 0.0f)) return false;
+    const float px = fmaf(c.fx, xp / zp, c.cx);
+    const float py = fmaf(c.fy, yp / zp, c.cy);
+    return px >= 0.0f && px <= (float)(c.W - 1) && py >= 0.0f && py <= (float)(c.H - 1);
+}
+
+// Whole-block order-preserving overlap compaction of m points.
+__device__ inline int overlap_compact(const Cam& c, const float* A, bool all, const float4* pts, int m, float4* out,
+                                      int* lds) {
+    int base = 0;
+    for (int j0 = 0; j0 < m; j0 += blockDim.x) {
+        const int j = j0 + threadIdx.x;
+        float4 x = make_float4(0, 0, 0, 0);
+        int keep = 0;
+        if (j < m) {
+            x = pts[j];
+            keep = all ? 1 : (overlap_keep(c, A, x) ? 1 : 0);
+        }
+        int tot;
+        const int pos = block_scan_flag(keep, lds, &tot);
+        if (keep) out[base + pos] = x;
+        base += tot;
+    }
+    return base;
+}
+
+struct InitArgs {
+    DevState* st;
+    Cam cam;
+    const float* depth;
+    int32_t stride;
+    int32_t flags;
+    double qc[4], tc[3], r[6];
+    double Tprev[12];
+    float4* pts;
+    float4* pts_o;
+};
+
+__global__ __launch_bounds__(1024) void k_track_init(InitArgs a) {
+    __shared__ int lds[17];
+    __shared__ float A[12];
+    const int su = (a.cam.W + a.stride - 1) / a.stride;
+    const int sv = (a.cam.H + a.stride - 1) / a.stride;
+    const int total = su * sv;
+    // stride-s unprojection with order-preserving compaction
+    int m = 0;
+    for (int q0 = 0; q0 < total; q0 += blockDim.x) {
+        const int q = q0 + threadIdx.x;
+        int keep = 0;
+        float4 x = make_float4(0, 0, 0, 0);
+        if (q < total) {
+            const int u = (q % su) * a.stride, v = (q / su) * a.stride;
+            const float z = a.depth[(int64_t)v * a.cam.W + u];
+            if (z > 0.0f) {
+                keep = 1;
+                x = unproject_px(a.cam, u, v, z);
+            }
+        }
+        int tot;
+        const int pos = block_scan_flag(keep, lds, &tot);
+        if (keep) a.pts[m + pos] = x;
+        m += tot;
+    }
+    if (threadIdx.x == 0) {
+        DevState* s = a.st;
+        for (int i = 0; i < 4; ++i) s->qc[i] = a.qc[i];
+        for (int i = 0; i < 3; ++i) s->tc[i] = a.tc[i];
+        for (int i = 0; i < 6; ++i) s->r[i] = a.r[i];
+        for (int i = 0; i < 6; ++i) s->r1[i] = a.r[i];
+        for (int i = 0; i < 12; ++i) s->Tprev[i] = a.Tprev[i];
+        s->rho_last = 0.5;
+        s->k = 0;
+        s->stopped = (m == 0) ? 1 : 0;
+        s->empty_streak = 0;
+        s->have_rho = 0;
+        s->n_points = m;
+        s->n_overlap = 0;
+        s->status = 0;
+        double Tc[12], Ad[12];
+        pose_matrix(a.qc, a.tc, Tc);
+        relative_transform(a.Tprev, Tc, Ad);
+        for (int i = 0; i < 12; ++i) A[i] = (float)Ad[i];
+    }
+    __syncthreads();
+    const int nO = overlap_compact(a.cam, A, (a.flags & ROSE_FLAG_NO_OVERLAP) != 0, a.pts, m, a.pts_o, lds);
+    if (threadIdx.x == 0) a.st->n_overlap = nO;
+}
+
+struct UpdateArgs {
+    DevState* st;
+    Cam cam;
+    const float* pst;
+    const double* partial;
+    float* F;
+    const float4* pts;
+    float4* pts_o;
+    int32_t n;
+    int32_t splits;
+    int32_t max_iters;
+    int32_t early_stop;
+    int32_t flags;
+    double beta, eps, tau, stop_tol;
+};
+
+__device__ inline float final_fitness(const UpdateArgs& a, int i, int nO) {
+    double s = 0.0;
+    for (int k = 0; k < a.splits; ++k) s += a.partial[(int64_t)i * a.splits + k];
+    double f;
+    if (a.flags & ROSE_FLAG_NO_NORMALIZE) f = s;
+    else f = (nO > 0) ? s / (double)nO : 1.0;
+    return (float)f;
+}
+
+__global__ __launch_bounds__(1024) void k_track_update(UpdateArgs a) {
+    __shared__ int lds[17];
+    __shared__ double red[16][9];
+    __shared__ float F0s;
+    __shared__ float A[12];
+    __shared__ int go_on;
+    DevState* st = a.st;
+    if (st->stopped) return;
+    const int nO = st->n_overlap;
+    if (threadIdx.x == 0) F0s = final_fitness(a, 0, nO);
+    __syncthreads();
+    const float F0 = F0s;
+    const double rho0 = exp(-(double)F0 / a.tau);
+    double r[6];
+    for (int d = 0; d < 6; ++d) r[d] = st->r[d];
+    // per-thread APS sums: count, sum w, sum w rho, sum w u_d
+    double cnt = 0.0, sw = 0.0, swr = 0.0, su[6] = {0, 0, 0, 0, 0, 0};
+    for (int i = threadIdx.x; i < a.n; i += blockDim.x) {
+        const float f = final_fitness(a, i, nO);
+        a.F[i] = f;
+        if (f < F0) {
+            const double rho = exp(-(double)f / a.tau);
+            const double w = rho - rho0;
+            cnt += 1.0;
+            sw += w;
+            swr += w * rho;
+#pragma unroll
+            for (int d = 0; d < 6; ++d) su[d] += w * (r[d] * (double)a.pst[6 * (int64_t)i + d]);
+        }
+    }
+    double v9[9] = {cnt, sw, swr, su[0], su[1], su[2], su[3], su[4], su[5]};
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) v9[e] = wave_sum(v9[e]);
+    if (lane == 0)
+        for (int e = 0; e < 9; ++e) red[wid][e] = v9[e];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int w = 0; w < nw; ++w)
+            for (int e = 0; e < 9; ++e) tot[e] += red[w][e];
+        const int aps = (int)tot[0];
+        const double inv_sqrt6 = 1.0 / sqrt(6.0);
+        double rhat[6], rt;
+        if (aps > 0) {
+            const double W = tot[1];
+            double us[6], nv = 0.0;
+            for (int d = 0; d < 6; ++d) {
+                us[d] = tot[3 + d] / W;
+                nv += us[d] * us[d];
+            }
+            nv = sqrt(nv);
+            rt = tot[2] / W;
+            for (int d = 0; d < 6; ++d) rhat[d] = (1.0 - rt) * (nv > 0.0 ? fabs(us[d]) / nv : inv_sqrt6) + a.eps;
+            retract(st->qc, st->tc, us);
+            st->rho_last = rt;
+            st->have_rho = 1;
+            st->empty_streak = 0;
+            if (a.early_stop) {
+                bool small = true;
+                for (int d = 0; d < 6; ++d) small = small && (fabs(us[d]) < a.stop_tol);
+                if (small) st->stopped = 1;
+            }
+        } else {
+            rt = rho0;
+            for (int d = 0; d < 6; ++d) rhat[d] = 2.0 * (1.0 - rho0) * inv_sqrt6;
+            if (!st->have_rho) st->rho_last = rho0;
+            st->empty_streak += 1;
+            if (a.early_stop && st->empty_streak >= 2) st->stopped = 1;
+        }
+        for (int d = 0; d < 6; ++d) st->r[d] = a.beta * r[d] + (1.0 - a.beta) * rhat[d];
+        const int k = st->k;
+        st->aps[k] = aps;
+        st->n_overlap_iter[k] = nO;
+        st->rho_iter[k] = rt;
+        st->k = k + 1;
+        if (k == 0)
+            for (int d = 0; d < 6; ++d) st->r1[d] = st->r[d];
+        if (k + 1 >= a.max_iters) st->stopped = 1;
+        go_on = !st->stopped;
+        if (go_on) {
+            double Tc[12], Ad[12];
+            pose_matrix(st->qc, st->tc, Tc);
+            relative_transform(st->Tprev, Tc, Ad);
+            for (int i = 0; i < 12; ++i) A[i] = (float)Ad[i];
+        }
+    }
+    __syncthreads();
+    if (!go_on) return;
+    const int nO2 = overlap_compact(a.cam, A, (a.flags & ROSE_FLAG_NO_OVERLAP) != 0, a.pts, st->n_points, a.pts_o, lds);
+    if (threadIdx.x == 0) st->n_overlap = nO2;
+}
+
+// ------------------------------------------------- diagnostic entry kernels
+__global__ __launch_bounds__(1024) void k_unproject_only(Cam cam, const float* depth, int32_t stride, float* pts3,
+                                                         int32_t* count) {
+    __shared__ int lds[17];
+    const int su = (cam.W + stride - 1) / stride;
+    const int sv = (cam.H + stride - 1) / stride;
+    const int total = su * sv;
+    int m = 0;
+    for (int q0 = 0; q0 < total; q0 += blockDim.x) {
+        const int q = q0 + threadIdx.x;
+        int keep = 0;
+        float4 x = make_float4(0, 0, 0, 0);
+        if (q < total) {
+            const int u = (q % su) * stride, v = (q / su) * stride;
+            const float z = depth[(int64_t)v * cam.W + u];
+            if (z > 0.0f) {
+                keep = 1;
+                x = unproject_px(cam, u, v, z);
+            }
+        }
+        int tot;
+        const int pos = block_scan_flag(keep, lds, &tot);
+        if (keep) {
+            pts3[3 * (int64_t)(m + pos)] = x.x;
+            pts3[3 * (int64_t)(m + pos) + 1] = x.y;
+            pts3[3 * (int64_t)(m + pos) + 2] = x.z;
+        }
+        m += tot;
+    }
+    if (threadIdx.x == 0) *count = m;
+}
+
+struct OverlapArgs {
+    Cam cam;
+    float A[12];
+    const float* pts3;
+    int32_t m;
+    uint8_t* mask;
+};
+
+__global__ __launch_bounds__(256) void k_overlap_only(OverlapArgs a) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= a.m) return;
+    const float4 x = make_float4(a.pts3[3 * (int64_t)j], a.pts3[3 * (int64_t)j + 1], a.pts3[3 * (int64_t)j + 2], 0.f);
+    a.mask[j] = overlap_keep(a.cam, a.A, x) ? 1 : 0;
+}
+
+static Cam to_cam(const rose_camera* c) { return Cam{c->fx, c->fy, c->cx, c->cy, c->width, c->height}; }
+
+static rose_status check_cam(const rose_camera* c, const char* who) {
+    ROSE_REQUIRE(c != nullptr, ROSE_E_ARG, "%s: NULL camera", who);
+    ROSE_REQUIRE(c->width > 0 && c->height > 0 && (int64_t)c->width * c->height <= (int64_t)ROSE_MAX_IMAGE_PIXELS,
+                 ROSE_E_SHAPE, "%s: image %dx%d out of range", who, c->width, c->height);
+    ROSE_REQUIRE(c->fx > 0 && c->fy > 0, ROSE_E_ARG, "%s: focal lengths must be > 0", who);
+    return ROSE_OK;
+}
+
+template <typename T>
+static rose_status grow(T** p, int64_t* cap, int64_t need) {
+    if (*cap >= need && *p) return ROSE_OK;
+    if (*p) ROSE_CHECK_HIP(hipFree(*p));
+    *p = nullptr;
+    ROSE_CHECK_HIP(hipMalloc((void**)p, sizeof(T) * (size_t)(need > 0 ? need : 1)));
+    *cap = need;
+    return ROSE_OK;
+}
+
+}  // namespace rose
+
+using namespace rose;
+
+extern "C" {
+
+rose_status depth_unproject(const float* depth_dev, const rose_camera* cam, int32_t stride, float* pts_dev,
+                            int32_t* count_dev, hipStream_t s) {
+    clear_error();
+    ROSE_REQUIRE(depth_dev && pts_dev && count_dev, ROSE_E_ARG, "depth_unproject: NULL argument");
+    rose_status c = check_cam(cam, "depth_unproject");
+    if (c != ROSE_OK) return c;
+    ROSE_REQUIRE(stride >= 1, ROSE_E_ARG, "depth_unproject: stride must be >= 1");
+    hipLaunchKernelGGL(k_unproject_only, dim3(1), dim3(1024), 0, s, to_cam(cam), depth_dev, stride, pts_dev, count_dev);
+    ROSE_CHECK_HIP(hipGetLastError());
+    return ROSE_OK;
+}
+
+rose_status overlap_mask(const float* pts_dev, int32_t m, const rose_pose* centre, const rose_pose* prev,
+                         const rose_camera* cam, uint8_t* mask_dev, hipStream_t s) {
+    clear_error();
+    ROSE_REQUIRE(pts_dev && centre && prev && mask_dev, ROSE_E_ARG, "overlap_mask: NULL argument");
+    rose_status c = check_cam(cam, "overlap_mask");
+    if (c != ROSE_OK) return c;
+    ROSE_REQUIRE(m >= 0 && m <= ROSE_MAX_IMAGE_PIXELS, ROSE_E_ARG, "overlap_mask: m out of range");
+    if (m == 0) return ROSE_OK;
+    OverlapArgs a;
+    a.cam = to_cam(cam);
+    double Tc[12], Tp[12], Ad[12];
+    pose_matrix(centre->q, centre->t, Tc);
+    pose_matrix(prev->q, prev->t, Tp);
+    relative_transform(Tp, Tc, Ad);
+    for (int i = 0; i < 12; ++i) a.A[i] = (float)Ad[i];
+    a.pts3 = pts_dev;
+    a.m = m;
+    a.mask = mask_dev;
+    hipLaunchKernelGGL(k_overlap_only, dim3((m + 255) / 256), dim3(256), 0, s, a);
+    ROSE_CHECK_HIP(hipGetLastError());
+    return ROSE_OK;
+}
+
+rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_camera* cam, const float* pst_dev,
+                            int32_t n_particles, const rose_track_params* p, const rose_pose* init_centre,
+                            const double* init_r, rose_track_state* state, rose_track_stats* stats,
+                            hipStream_t s) {
+    clear_error();
+    ROSE_REQUIRE(h && depth_dev && pst_dev && p && state, ROSE_E_ARG, "pso_track_frame: NULL argument");
+    rose_status c = check_cam(cam, "pso_track_frame");
+    if (c != ROSE_OK) return c;
+    ROSE_REQUIRE(n_particles >= 1 && n_particles <= ROSE_MAX_PARTICLES, ROSE_E_ARG,
+                 "pso_track_frame: n_particles = %d out of [1, %d]", n_particles, ROSE_MAX_PARTICLES);
+    ROSE_REQUIRE(p->max_iters >= 1 && p->max_iters <= ROSE_MAX_ITERS, ROSE_E_ARG,
+                 "pso_track_frame: max_iters = %d out of [1, %d]", p->max_iters, ROSE_MAX_ITERS);
+    ROSE_REQUIRE(p->stride >= 1, ROSE_E_ARG, "pso_track_frame: stride must be >= 1");
+    ROSE_REQUIRE(p->lookup == ROSE_LOOKUP_NEAREST || p->lookup == ROSE_LOOKUP_TRILINEAR, ROSE_E_ARG,
+                 "pso_track_frame: bad lookup");
+    ROSE_REQUIRE(p->tau > 0.0 && p->beta >= 0.0 && p->beta <= 1.0, ROSE_E_ARG,
+                 "pso_track_frame: tau must be > 0 and beta in [0, 1]");
+    const double* r0 = init_r ? init_r : state->r;
+    const rose_pose* c0 = init_centre ? init_centre : &state->pose;
+
+    if (!state->tsdf_built) {
+        // Sec. 4, first corner case: no fitness; rhat = 0.5 * 1, pose kept
+        for (int d = 0; d < 6; ++d) state->r[d] = p->beta * r0[d] + (1.0 - p->beta) * 0.5;
+        state->pose = *c0;
+        state->rho = 0.5;
+        state->frame += 1;
+        if (stats) {
+            memset(stats, 0, sizeof(*stats));
+            stats->iters = 1;
+            stats->rho_iter[0] = 0.5;
+        }
+        return ROSE_OK;
+    }
+
+    const int su = (cam->width + p->stride - 1) / p->stride;
+    const int sv = (cam->height + p->stride - 1) / p->stride;
+    const int64_t mmax = (int64_t)su * sv;
+    const int splits = choose_splits(n_particles, mmax);
+    rose_status g;
+    if ((g = grow(&h->pts, &h->cap_points, mmax)) != ROSE_OK) return g;
+    if ((g = grow(&h->pts_o, &h->cap_points_o, mmax)) != ROSE_OK) return g;
+    if ((g = grow(&h->partial, &h->cap_partial, (int64_t)n_particles * splits)) != ROSE_OK) return g;
+    if ((g = grow(&h->F, &h->cap_particles, (int64_t)n_particles)) != ROSE_OK) return g;
+    if (!h->st) ROSE_CHECK_HIP(hipMalloc(&h->st, sizeof(DevState)));
+    if (!h->st_host) ROSE_CHECK_HIP(hipHostMalloc(&h->st_host, sizeof(DevState), hipHostMallocDefault));
+
+    InitArgs ia;
+    ia.st = h->st;
+    ia.cam = to_cam(cam);
+    ia.depth = depth_dev;
+    ia.stride = p->stride;
+    ia.flags = p->flags;
+    for (int i = 0; i < 4; ++i) ia.qc[i] = c0->q[i];
+    for (int i = 0; i < 3; ++i) ia.tc[i] = c0->t[i];
+    for (int i = 0; i < 6; ++i) ia.r[i] = r0[i];
+    pose_matrix(state->pose.q, state->pose.t, ia.Tprev);
+    ia.pts = h->pts;
+    ia.pts_o = h->pts_o;
+    hipLaunchKernelGGL(k_track_init, dim3(1), dim3(1024), 0, s, ia);
+    ROSE_CHECK_HIP(hipGetLastError());
+
+    FitLaunch L{};
+    L.g = h->g;
+    L.pts = h->pts_o;
+    L.count_dev = &h->st->n_overlap;
+    L.T32 = nullptr;
+    L.st = h->st;
+    L.pst = pst_dev;
+    L.n = n_particles;
+    L.splits = splits;
+    L.lookup = p->lookup;
+    L.partial = h->partial;
+
+    UpdateArgs ua;
+    ua.st = h->st;
+    ua.cam = ia.cam;
+    ua.pst = pst_dev;
+    ua.partial = h->partial;
+    ua.F = h->F;
+    ua.pts = h->pts;
+    ua.pts_o = h->pts_o;
+    ua.n = n_particles;
+    ua.splits = splits;
+    ua.max_iters = p->max_iters;
+    ua.early_stop = p->early_stop;
+    ua.flags = p->flags;
+    ua.beta = p->beta;
+    ua.eps = p->eps;
+    ua.tau = p->tau;
+    ua.stop_tol = p->stop_tol;
+    int tok_fit[ROSE_MAX_ITERS];
+    for (int k = 0; k < p->max_iters; ++k) {
+        tok_fit[k] = prof_begin(PROF_FITNESS, s);
+        if ((g = launch_fitness(L, s)) != ROSE_OK) return g;
+        prof_end(tok_fit[k], s, 0.0);
+        const int tu = prof_begin(PROF_UPDATE, s);
+        hipLaunchKernelGGL(k_track_update, dim3(1), dim3(1024), 0, s, ua);
+        prof_end(tu, s, 0.0);
+        ROSE_CHECK_HIP(hipGetLastError());
+    }
+    ROSE_CHECK_HIP(hipMemcpyAsync(h->st_host, h->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    ROSE_CHECK_HIP(hipStreamSynchronize(s));
+    const DevState& r = *h->st_host;
+    for (int k = 0; k < p->max_iters; ++k)
+        prof_set_evals(tok_fit[k], k < r.k ? (double)n_particles * (double)r.n_overlap_iter[k] : 0.0);
+    if (r.n_points == 0) {
+        set_error("pso_track_frame: the frame has no valid depth sample");
+        return ROSE_E_STATE;
+    }
+    for (int i = 0; i < 4; ++i) state->pose.q[i] = r.qc[i];
+    for (int i = 0; i < 3; ++i) state->pose.t[i] = r.tc[i];
+    for (int d = 0; d < 6; ++d) state->r[d] = r.r1[d];
+    state->rho = r.rho_last;
+    state->frame += 1;
+    if (stats) {
+        memset(stats, 0, sizeof(*stats));
+        stats->iters = r.k;
+        stats->n_points = r.n_points;
+        stats->n_overlap_last = r.n_overlap;
+        for (int k = 0; k < r.k && k < ROSE_MAX_ITERS; ++k) {
+            stats->aps_size[k] = r.aps[k];
+            stats->n_overlap[k] = r.n_overlap_iter[k];
+            stats->rho_iter[k] = r.rho_iter[k];
+        }
+    }
+    return ROSE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,327 @@
+"""Python binding of librose (include/rose.h): argument marshalling only.
+
+Every step of the pose search and the fusion runs in the HIP kernels of
+librose.so; this module converts torch tensors (device memory, streams) and
+small host structs to the C ABI and raises on a non-OK status.  There is no
+CPU fallback: importing this module fails loudly when the library has not
+been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librose.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "rose.h")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"librose.so is not built ({LIB_PATH}); run __graft_entry__.build() "
+                      "or python -m paper_2105_05600_amd.build")
+
+_lib = C.CDLL(LIB_PATH)
+
+OK = 0
+E_ARG, E_SHAPE, E_DEVICE, E_STATE, E_UNSUPPORTED = -1, -2, -3, -4, -5
+F32, F16, SN16 = 0, 1, 2
+NEAREST, TRILINEAR = 0, 1
+FLAG_NO_OVERLAP, FLAG_NO_NORMALIZE = 1, 2
+MAX_ITERS = 32
+
+
+class Camera(C.Structure):
+    _fields_ = [("fx", C.c_float), ("fy", C.c_float), ("cx", C.c_float), ("cy", C.c_float),
+                ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class Pose(C.Structure):
+    _fields_ = [("q", C.c_double * 4), ("t", C.c_double * 3)]
+
+
+class TrackParams(C.Structure):
+    _fields_ = [("max_iters", C.c_int32), ("early_stop", C.c_int32), ("stride", C.c_int32),
+                ("lookup", C.c_int32), ("flags", C.c_int32), ("reserved", C.c_int32),
+                ("beta", C.c_double), ("eps", C.c_double), ("tau", C.c_double), ("stop_tol", C.c_double)]
+
+
+class TrackState(C.Structure):
+    _fields_ = [("pose", Pose), ("r", C.c_double * 6), ("rho", C.c_double), ("tsdf_built", C.c_int32),
+                ("frame", C.c_int32)]
+
+
+class TrackStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("n_points", C.c_int32), ("n_overlap_last", C.c_int32),
+                ("reserved", C.c_int32), ("aps_size", C.c_int32 * MAX_ITERS),
+                ("n_overlap", C.c_int32 * MAX_ITERS), ("rho_iter", C.c_double * MAX_ITERS)]
+
+
+class Profile(C.Structure):
+    _fields_ = [("fitness_ms", C.c_double), ("fitness_launches", C.c_int64), ("fitness_evals", C.c_double),
+                ("update_ms", C.c_double), ("update_launches", C.c_int64), ("integrate_ms", C.c_double),
+                ("integrate_launches", C.c_int64)]
+
+
+_P = C.c_void_p
+_S = C.c_void_p  # hipStream_t
+_sigs = {
+    "rose_last_error": ([], C.c_char_p),
+    "rose_version": ([], C.c_char_p),
+    "tsdf_bytes": ([C.c_int32, C.c_int32, C.c_int32, C.c_int, C.c_int32], C.c_size_t),
+    "tsdf_create": ([C.c_int32, C.c_int32, C.c_int32, C.c_float, C.c_float, _P, C.c_int, C.c_float, _P, _P, _S,
+                     C.POINTER(C.c_void_p)], C.c_int),
+    "tsdf_destroy": ([_P], C.c_int),
+    "tsdf_integrate": ([_P, _P, C.POINTER(Camera), C.POINTER(Pose), _S], C.c_int),
+    "tsdf_export": ([_P, _P, _P, _S], C.c_int),
+    "tsdf_import": ([_P, _P, _P, _S], C.c_int),
+    "pst_sample": ([C.c_int32, C.c_uint64, _P, _S], C.c_int),
+    "pst_particle_poses": ([C.POINTER(Pose), _P, _P, C.c_int32, _P, _S], C.c_int),
+    "fitness_eval": ([_P, _P, C.c_int32, _P, C.c_int32, C.c_int, _P, _P, _S], C.c_int),
+    "fitness_voxel_indices": ([_P, _P, C.c_int32, _P, C.c_int32, _P, _S], C.c_int),
+    "depth_unproject": ([_P, C.POINTER(Camera), C.c_int32, _P, _P, _S], C.c_int),
+    "overlap_mask": ([_P, C.c_int32, C.POINTER(Pose), C.POINTER(Pose), C.POINTER(Camera), _P, _S], C.c_int),
+    "pso_track_frame": ([_P, _P, C.POINTER(Camera), _P, C.c_int32, C.POINTER(TrackParams), C.POINTER(Pose), _P,
+                         C.POINTER(TrackState), C.POINTER(TrackStats), _S], C.c_int),
+    "rose_profile_enable": ([C.c_int32], C.c_int),
+    "rose_profile_reset": ([], C.c_int),
+    "rose_profile_read": ([C.POINTER(Profile)], C.c_int),
+}
+for _name, (_args, _res) in _sigs.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+
+class RoseError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        msg = _lib.rose_last_error().decode(errors="replace")
+        super().__init__(f"{fn} returned {status}: {msg}")
+        self.status = status
+
+
+def _check(fn: str, st: int):
+    if st != OK:
+        raise RoseError(fn, st)
+
+
+def header_functions() -> list:
+    """Names of the functions include/rose.h declares."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_]+\s*\*?\s*([a-z_]+)\s*\(", txt, flags=re.M)))
+
+
+def version() -> str:
+    return _lib.rose_version().decode()
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dev(t: torch.Tensor, dtype, name: str) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def camera(K) -> Camera:
+    """Camera struct from any object with fx, fy, cx, cy, width, height."""
+    return Camera(float(K.fx), float(K.fy), float(K.cx), float(K.cy), int(K.width), int(K.height))
+
+
+def pose(q: Sequence[float], t: Sequence[float]) -> Pose:
+    p = Pose()
+    for i in range(4):
+        p.q[i] = float(q[i])
+    for i in range(3):
+        p.t[i] = float(t[i])
+    return p
+
+
+class Tsdf:
+    """A TSDF volume in caller-owned device memory (torch tensors)."""
+
+    _dtypes = {F32: (torch.float32, torch.float32), F16: (torch.float16, torch.int16),
+               SN16: (torch.int16, torch.int16)}
+
+    def __init__(self, dims, voxel: float, trunc: float, origin, fmt: int = F32, w_max: float = 128.0,
+                 device: str = "cuda", stream=None):
+        nx, ny, nz = (int(d) for d in dims)
+        nb = _lib.tsdf_bytes(nx, ny, nz, fmt, 0)
+        if nb == 0:
+            raise RoseError("tsdf_bytes", E_SHAPE)
+        pd, wd = self._dtypes[fmt]
+        n = nx * ny * nz
+        self.psi = torch.empty(n, dtype=pd, device=device)
+        self.weight = torch.empty(n, dtype=wd, device=device)
+        self.dims = (nx, ny, nz)
+        self.voxel = float(voxel)
+        self.trunc = float(trunc)
+        self.origin = tuple(float(o) for o in origin)
+        self.fmt = fmt
+        org = (C.c_float * 3)(*self.origin)
+        h = C.c_void_p()
+        _check("tsdf_create", _lib.tsdf_create(nx, ny, nz, self.voxel, self.trunc, org, fmt, float(w_max),
+                                               _ptr(self.psi), _ptr(self.weight), _stream(stream), C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _lib.tsdf_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def integrate(self, depth: torch.Tensor, K, q, t, stream=None):
+        _dev(depth, torch.float32, "depth")
+        cam = camera(K)
+        if depth.numel() != cam.width * cam.height:
+            raise ValueError("depth size does not match the camera")
+        p = pose(q, t)
+        _check("tsdf_integrate", _lib.tsdf_integrate(self.handle, _ptr(depth), C.byref(cam), C.byref(p),
+                                                     _stream(stream)))
+
+    def export(self, stream=None):
+        nx, ny, nz = self.dims
+        psi = torch.empty((nz, ny, nx), dtype=torch.float32, device=self.psi.device)
+        w = torch.empty((nz, ny, nx), dtype=torch.float32, device=self.psi.device)
+        _check("tsdf_export", _lib.tsdf_export(self.handle, _ptr(psi), _ptr(w), _stream(stream)))
+        return psi, w
+
+    def load(self, psi_lin: torch.Tensor, w_lin: Optional[torch.Tensor] = None, stream=None):
+        _dev(psi_lin, torch.float32, "psi")
+        if w_lin is not None:
+            _dev(w_lin, torch.float32, "weight")
+        if psi_lin.numel() != self.psi.numel():
+            raise ValueError("psi size does not match the volume")
+        _check("tsdf_import", _lib.tsdf_import(self.handle, _ptr(psi_lin), _ptr(w_lin), _stream(stream)))
+
+
+def pst_sample(n: int, seed: int, device: str = "cuda", stream=None) -> torch.Tensor:
+    out = torch.empty((n, 6), dtype=torch.float32, device=device)
+    _check("pst_sample", _lib.pst_sample(int(n), C.c_uint64(int(seed) & (2**64 - 1)), _ptr(out), _stream(stream)))
+    return out
+
+
+def particle_poses(qc, tc, r, pst: torch.Tensor, stream=None) -> torch.Tensor:
+    _dev(pst, torch.float32, "pst")
+    n = pst.shape[0]
+    T = torch.empty((n, 3, 4), dtype=torch.float64, device=pst.device)
+    c = pose(qc, tc)
+    rr = (C.c_double * 6)(*[float(v) for v in r])
+    _check("pst_particle_poses", _lib.pst_particle_poses(C.byref(c), rr, _ptr(pst), n, _ptr(T), _stream(stream)))
+    return T
+
+
+def fitness_eval(vol: Tsdf, pts: torch.Tensor, T: torch.Tensor, lookup: int = NEAREST, stream=None):
+    _dev(pts, torch.float32, "pts")
+    _dev(T, torch.float32, "T")
+    m = pts.shape[0]
+    n = T.shape[0]
+    F = torch.empty(n, dtype=torch.float32, device=T.device)
+    rho = torch.empty(n, dtype=torch.float32, device=T.device)
+    _check("fitness_eval", _lib.fitness_eval(vol.handle, _ptr(pts) if m else None, m, _ptr(T), n, lookup, _ptr(F),
+                                             _ptr(rho), _stream(stream)))
+    return F, rho
+
+
+def voxel_indices(vol: Tsdf, pts: torch.Tensor, T: torch.Tensor, stream=None) -> torch.Tensor:
+    _dev(pts, torch.float32, "pts")
+    _dev(T, torch.float32, "T")
+    idx = torch.empty((T.shape[0], pts.shape[0]), dtype=torch.int64, device=T.device)
+    _check("fitness_voxel_indices", _lib.fitness_voxel_indices(vol.handle, _ptr(pts), pts.shape[0], _ptr(T),
+                                                               T.shape[0], _ptr(idx), _stream(stream)))
+    return idx
+
+
+def depth_unproject(depth: torch.Tensor, K, stride: int, stream=None) -> torch.Tensor:
+    _dev(depth, torch.float32, "depth")
+    cam = camera(K)
+    su = (cam.width + stride - 1) // stride
+    sv = (cam.height + stride - 1) // stride
+    pts = torch.empty((max(su * sv, 1), 3), dtype=torch.float32, device=depth.device)
+    cnt = torch.zeros(1, dtype=torch.int32, device=depth.device)
+    _check("depth_unproject", _lib.depth_unproject(_ptr(depth), C.byref(cam), int(stride), _ptr(pts), _ptr(cnt),
+                                                   _stream(stream)))
+    return pts[: int(cnt.item())]
+
+
+def overlap_mask(pts: torch.Tensor, centre, prev, K, stream=None) -> torch.Tensor:
+    _dev(pts, torch.float32, "pts")
+    cam = camera(K)
+    m = pts.shape[0]
+    mask = torch.zeros(max(m, 1), dtype=torch.uint8, device=pts.device)
+    c = pose(*centre)
+    p = pose(*prev)
+    _check("overlap_mask", _lib.overlap_mask(_ptr(pts), m, C.byref(c), C.byref(p), C.byref(cam), _ptr(mask),
+                                             _stream(stream)))
+    return mask[:m].bool()
+
+
+def track_params(max_iters=20, early_stop=False, stride=4, lookup=NEAREST, flags=0, beta=0.1, eps=1e-3, tau=1.0,
+                 stop_tol=1e-6) -> TrackParams:
+    return TrackParams(int(max_iters), int(bool(early_stop)), int(stride), int(lookup), int(flags), 0,
+                       float(beta), float(eps), float(tau), float(stop_tol))
+
+
+def track_state(q, t, r, tsdf_built=True, frame=0) -> TrackState:
+    st = TrackState()
+    st.pose = pose(q, t)
+    for i in range(6):
+        st.r[i] = float(r[i])
+    st.rho = 0.0
+    st.tsdf_built = int(bool(tsdf_built))
+    st.frame = int(frame)
+    return st
+
+
+def track_frame(vol: Tsdf, depth: torch.Tensor, K, pst: torch.Tensor, params: TrackParams, state: TrackState,
+                init_centre=None, init_r=None, stream=None) -> dict:
+    """Run pso_track_frame; updates `state` in place and returns the stats."""
+    _dev(depth, torch.float32, "depth")
+    _dev(pst, torch.float32, "pst")
+    cam = camera(K)
+    if depth.numel() != cam.width * cam.height:
+        raise ValueError("depth size does not match the camera")
+    stats = TrackStats()
+    c0 = C.byref(pose(*init_centre)) if init_centre is not None else None
+    r0 = (C.c_double * 6)(*[float(v) for v in init_r]) if init_r is not None else None
+    st = _lib.pso_track_frame(vol.handle, _ptr(depth), C.byref(cam), _ptr(pst), pst.shape[0], C.byref(params), c0,
+                              r0, C.byref(state), C.byref(stats), _stream(stream))
+    _check("pso_track_frame", st)
+    it = stats.iters
+    return dict(iters=it, n_points=stats.n_points, n_overlap_last=stats.n_overlap_last,
+                aps=list(stats.aps_size[:it]), n_overlap=list(stats.n_overlap[:it]),
+                rho_iter=list(stats.rho_iter[:it]),
+                q=list(state.pose.q), t=list(state.pose.t), r1=list(state.r), rho=state.rho)
+
+
+def profile_enable(on: bool = True):
+    _check("rose_profile_enable", _lib.rose_profile_enable(int(bool(on))))
+
+
+def profile_reset():
+    _check("rose_profile_reset", _lib.rose_profile_reset())
+
+
+def profile_read() -> dict:
+    p = Profile()
+    _check("rose_profile_read", _lib.rose_profile_read(C.byref(p)))
+    return {f: getattr(p, f) for f, _ in Profile._fields_}

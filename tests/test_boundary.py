@@ -1,0 +1,67 @@
+"""The C-ABI library loads, exports every declared symbol, and validates
+arguments on the host before touching the device (no GPU needed)."""
+import ctypes as C
+
+import pytest
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_2105_05600_amd import rose
+    return rose
+
+
+def test_every_declared_symbol_is_exported(R):
+    names = R.header_functions()
+    expected = {"tsdf_create", "tsdf_integrate", "pst_sample", "pso_track_frame", "fitness_eval", "tsdf_destroy",
+                "tsdf_bytes", "tsdf_export", "tsdf_import", "rose_last_error"}
+    assert expected <= set(names)
+    missing = [n for n in names if not hasattr(R._lib, n)]
+    assert missing == []
+
+
+def test_version(R):
+    assert "gfx950" in R.version()
+
+
+def test_tsdf_bytes(R):
+    lib = R._lib
+    assert lib.tsdf_bytes(64, 64, 64, R.F32, 0) == 64**3 * 4
+    assert lib.tsdf_bytes(64, 64, 64, R.F32, 1) == 64**3 * 4
+    assert lib.tsdf_bytes(512, 512, 512, R.F16, 0) == 512**3 * 2
+    assert lib.tsdf_bytes(512, 512, 512, R.SN16, 1) == 512**3 * 2
+    for bad in [(0, 8, 8), (12, 8, 8), (8, 8, 4096), (-8, 8, 8)]:
+        assert lib.tsdf_bytes(*bad, R.F32, 0) == 0
+    assert lib.tsdf_bytes(8, 8, 8, 7, 0) == 0
+    assert lib.tsdf_bytes(8, 8, 8, R.F32, 2) == 0
+    assert lib.tsdf_bytes(2048, 2048, 1024, R.F32, 0) == 0  # above 2^31 voxels
+
+
+def test_host_side_argument_errors(R):
+    lib = R._lib
+    assert lib.pst_sample(0, 1, C.c_void_p(16), None) == R.E_ARG
+    assert b"out of" in lib.rose_last_error()
+    assert lib.pst_sample(R_MAX := 65537, 1, C.c_void_p(16), None) == R.E_ARG
+    assert lib.pst_sample(8, 1, None, None) == R.E_ARG
+    h = C.c_void_p()
+    org = (C.c_float * 3)(0, 0, 0)
+    assert lib.tsdf_create(12, 8, 8, 0.01, 0.03, org, R.F32, 128.0, C.c_void_p(16), C.c_void_p(16), None,
+                           C.byref(h)) == R.E_SHAPE
+    assert lib.tsdf_create(8, 8, 8, -0.01, 0.03, org, R.F32, 128.0, C.c_void_p(16), C.c_void_p(16), None,
+                           C.byref(h)) == R.E_ARG
+    assert lib.tsdf_create(8, 8, 8, 0.01, 0.03, org, R.F32, 128.0, None, C.c_void_p(16), None,
+                           C.byref(h)) == R.E_ARG
+    assert lib.tsdf_destroy(None) == R.OK
+    cam = R.Camera(100, 100, 10, 10, 0, 20)
+    assert lib.depth_unproject(C.c_void_p(16), C.byref(cam), 2, C.c_void_p(16), C.c_void_p(16), None) == R.E_SHAPE
+    cam = R.Camera(100, 100, 10, 10, 20, 20)
+    assert lib.depth_unproject(C.c_void_p(16), C.byref(cam), 0, C.c_void_p(16), C.c_void_p(16), None) == R.E_ARG
+    assert lib.fitness_eval(None, None, 0, None, 1, 0, None, None, None) == R.E_ARG
+    params = R.track_params(max_iters=0)
+    st = R.track_state([1, 0, 0, 0], [0, 0, 0], [0.1] * 6)
+    assert lib.pso_track_frame(C.c_void_p(16), C.c_void_p(16), C.byref(cam), C.c_void_p(16), 16, C.byref(params),
+                               None, None, C.byref(st), None, None) == R.E_ARG
+    params = R.track_params(max_iters=10)
+    assert lib.pso_track_frame(C.c_void_p(16), C.c_void_p(16), C.byref(cam), C.c_void_p(16), 0, C.byref(params),
+                               None, None, C.byref(st), None, None) == R.E_ARG
+    assert lib.rose_profile_read(None) == R.E_ARG

@@ -1,0 +1,301 @@
+"""GPU path (librose through its C ABI) against the CPU oracle, element by
+element on the same seeded inputs.
+
+Bars: bit-exact for the PST template, binary64 particle poses, unprojected
+points, overlap masks and voxel indices (integer or exactly specified
+results); relative 1e-5 on fitness; 1e-4 m / 1e-4 rad on tracked poses.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2105_05600_amd import rose
+    return rose
+
+
+def dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-30))
+
+
+def _rot_err(qa, qb):
+    Ra, Rb = synth.quat_to_mat(qa), synth.quat_to_mat(qb)
+    c = np.clip((np.trace(Ra.T @ Rb) - 1) / 2, -1, 1)
+    return math.acos(c)
+
+
+# ------------------------------------------------------------------- a1 PST
+@pytest.mark.parametrize("n,seed", [(1, 1), (5, 3), (1023, 5600), (10240, 5600), (16384, 77)])
+def test_pst_sample_bit_exact(R, orc, n, seed):
+    g = host(R.pst_sample(n, seed))
+    o, _ = orc.pst_sample(n, seed)
+    assert g.dtype == np.float32 and g.shape == (n, 6)
+    assert np.array_equal(g.view(np.uint32), o.view(np.uint32))
+
+
+# --------------------------------------------------------- a4 particle poses
+def test_particle_poses_bit_exact(R, orc):
+    rng = np.random.default_rng(11)
+    pst, _ = orc.pst_sample(1000, 9)
+    for _ in range(3):
+        q = synth.mat_to_quat(synth.axis_angle(rng.standard_normal(3), rng.uniform(0, 3)))
+        t = rng.uniform(-3, 3, 3)
+        r = rng.uniform(0.001, 1.0, 6)
+        g = host(R.particle_poses(q, t, r, dev(pst)))
+        o = orc.particle_poses(q, t, r, pst)
+        assert np.array_equal(g.view(np.uint64), o.view(np.uint64))
+
+
+# ------------------------------------------------------ a2 unprojection
+@pytest.mark.parametrize("W,H,f,stride", [(160, 120, 140.0, 3), (640, 480, 525.0, 4), (97, 61, 80.0, 7),
+                                          (64, 48, 60.0, 1)])
+def test_unproject_bit_exact(R, orc, W, H, f, stride):
+    room = synth.unit_box_room(2105)
+    K = synth.Intrinsics.centred(W, H, f)
+    pose = synth.Pose(synth.look_rotation([0.6, 0.5, 0.4]), np.array([0.01, -0.02, 0.0]))
+    depth = synth.render_depth(room, K, pose, noise_seed=4, noise_k=0.002)
+    depth[::5, ::3] = 0.0  # holes
+    g = host(R.depth_unproject(dev(depth), K, stride))
+    o = orc.unproject(depth, K, stride, orc.F32)
+    assert g.shape == o.shape
+    assert np.array_equal(g.view(np.uint32), o.view(np.uint32))
+
+
+# --------------------------------------------------------- a3 overlap mask
+def test_overlap_mask_bit_exact(R, orc):
+    room = synth.unit_box_room(2105)
+    K = synth.Intrinsics.centred(160, 120, 140.0)
+    rng = np.random.default_rng(5)
+    prev = synth.Pose(synth.look_rotation([0.6, 0.5, 0.4]), np.array([0.01, -0.02, 0.0]))
+    for _ in range(4):
+        cur = synth.Pose(synth.axis_angle(rng.standard_normal(3), 0.15) @ prev.R, prev.t + rng.uniform(-0.1, 0.1, 3))
+        depth = synth.render_depth(room, K, cur)
+        pts = orc.unproject(depth, K, 1, orc.F32)
+        g = host(R.overlap_mask(dev(pts), (cur.q, cur.t), (prev.q, prev.t), K))
+        o = orc.overlap(pts, orc.pose_mat(cur.q, cur.t), orc.pose_mat(prev.q, prev.t), K, orc.F32)
+        assert 0 < o.sum() < len(o)
+        assert np.array_equal(g, o)
+
+
+# ------------------------------------------------- a5 voxel indices, fitness
+def _random_volume(R, rng, dims, vox, origin, fmt=0):
+    nx, ny, nz = dims
+    psi = rng.uniform(-1, 1, (nz, ny, nx)).astype(np.float32)
+    psi[rng.random((nz, ny, nx)) < 0.2] = 1.0
+    vol = R.Tsdf(dims, vox, 3 * vox, origin, fmt=fmt)
+    vol.load(dev(psi.ravel()))
+    gpsi, _ = vol.export()
+    return vol, host(gpsi)
+
+
+def _random_poses(rng, n, spread=0.3):
+    T = np.zeros((n, 3, 4), np.float32)
+    for i in range(n):
+        T[i, :, :3] = synth.axis_angle(rng.standard_normal(3), rng.uniform(0, spread))
+        T[i, :, 3] = rng.uniform(-0.1, 0.1, 3)
+    return T
+
+
+def test_voxel_indices_bit_exact(R, orc):
+    rng = np.random.default_rng(6)
+    dims, vox, origin = (24, 16, 32), 0.05, (-0.6, -0.4, -0.8)
+    vol, _ = _random_volume(R, rng, dims, vox, origin)
+    pts = rng.uniform(-0.9, 0.9, (777, 3)).astype(np.float32)
+    T = _random_poses(rng, 9)
+    g = host(R.voxel_indices(vol, dev(pts), dev(T)))
+    o = orc.voxel_indices(dims, vox, np.array(origin, np.float32), pts, T.astype(np.float64))
+    assert (o >= 0).mean() > 0.3 and (o < 0).any()
+    assert np.array_equal(g, o)
+
+
+@pytest.mark.parametrize("fmt", [0, 1, 2])
+@pytest.mark.parametrize("lookup", [0, 1])
+@pytest.mark.parametrize("n,m", [(1, 1), (5, 63), (67, 65), (130, 3001), (9, 0)])
+def test_fitness_parity(R, orc, fmt, lookup, n, m):
+    rng = np.random.default_rng(100 + n + m)
+    dims, vox, origin = (32, 24, 16), 0.04, (-0.64, -0.48, -0.32)
+    vol, psi = _random_volume(R, rng, dims, vox, origin, fmt)
+    pts = rng.uniform(-0.7, 0.7, (m, 3)).astype(np.float32)
+    T = _random_poses(rng, n)
+    F, rho = R.fitness_eval(vol, dev(pts), dev(T), lookup)
+    F, rho = host(F), host(rho)
+    Fo = orc.fitness(psi, vox, np.array(origin, np.float32), pts, T.astype(np.float64), lookup=lookup, prec=orc.F32)
+    assert _rel(F, Fo) <= 1e-5
+    assert _rel(rho, np.exp(-Fo)) <= 1e-5
+    if m == 0:
+        assert np.all(F == 1.0)
+
+
+@pytest.fixture(scope="module")
+def room_frame(R):
+    """A 512^3 volume at 1 cm fused (on the GPU) from frame 0 of the
+    640x480 room sequence; frame 1 is tracked against it."""
+    seq = synth.room_sequence(n_frames=3)
+    d0, d1 = seq.depths([0, 1])
+    vol = R.Tsdf(seq.dims, seq.vox, seq.mu, seq.origin)
+    p0 = seq.poses[0]
+    vol.integrate(dev(d0), seq.K, p0.q, p0.t)
+    psi, w = vol.export()
+    return seq, vol, host(psi), host(w), d0, d1
+
+
+def test_fitness_full_size_sampled(R, orc, room_frame):
+    """10240 poses x all points of a 640x480 frame (stride 4) on the
+    512^3 volume, in the launch shape the tracker uses; 24 sampled
+    particles are recomputed by the oracle one by one."""
+    seq, vol, psi, _, _, d1 = room_frame
+    rng = np.random.default_rng(8)
+    pts = orc.unproject(d1, seq.K, seq.stride, orc.F32)
+    assert len(pts) > 10000
+    p0 = seq.poses[0]
+    T = np.repeat(p0.as_3x4()[None], 10240, 0)
+    T[:, :, :3] = np.einsum("nij,jk->nik", np.stack([synth.axis_angle(rng.standard_normal(3), rng.uniform(0, 0.1))
+                                                     for _ in range(10240)]), p0.R)
+    T[:, :, 3] += rng.uniform(-0.1, 0.1, (10240, 3))
+    T = T.astype(np.float32)
+    for lookup in (0, 1):
+        F, _ = R.fitness_eval(vol, dev(pts), dev(T), lookup)
+        F = host(F)
+        pick = np.concatenate([[0, 10239], rng.choice(10240, 22, replace=False)])
+        Fo = orc.fitness(psi, seq.vox, seq.origin.astype(np.float32), pts, T[pick].astype(np.float64), lookup=lookup,
+                         prec=orc.F32)
+        assert _rel(F[pick], Fo) <= 1e-5
+        assert np.all((F >= 0) & (F <= 1))
+
+
+# ------------------------------------------------------------ a8 fusion
+@pytest.mark.parametrize("fmt", [0])
+def test_integrate_parity_small(R, orc, fmt):
+    w = synth.small_frame()
+    nx, ny, nz = w.dims
+    vol = R.Tsdf(w.dims, w.vox, w.mu, w.origin, fmt=fmt)
+    psi = np.ones((nz, ny, nx), np.float32)
+    wt = np.zeros_like(psi)
+    for p, d in zip(w.fuse_poses, w.fuse_depths):
+        vol.integrate(dev(d), w.K, p.q, p.t)
+        orc.integrate(psi, wt, w.vox, w.origin, w.mu, d, w.K, p.q, p.t, prec=orc.F32)
+    gp, gw = vol.export()
+    gp, gw = host(gp), host(gw)
+    assert np.array_equal(gw, wt)
+    assert np.array_equal(gp.view(np.uint32), psi.view(np.uint32))
+
+
+def test_integrate_parity_full_size(R, orc, room_frame):
+    """Frame 0 of the 640x480 room sequence fused into the 512^3 volume:
+    weights equal and psi bit-identical to the oracle's binary32 fusion."""
+    seq, vol, psi, w, d0, _ = room_frame
+    nx, ny, nz = seq.dims
+    p0 = seq.poses[0]
+    full_psi = np.ones((nz, ny, nx), np.float32)
+    full_w = np.zeros_like(full_psi)
+    orc.integrate(full_psi, full_w, seq.vox, seq.origin, seq.mu, d0, seq.K, p0.q, p0.t, prec=orc.F32)
+    assert (full_w > 0).sum() > 1_000_000
+    assert np.array_equal(w, full_w)
+    assert np.array_equal(psi.view(np.uint32), full_psi.view(np.uint32))
+
+
+# --------------------------------------------------------- whole frame
+@pytest.fixture(scope="module")
+def small_gpu(R, orc):
+    w = synth.small_frame()
+    vol = R.Tsdf(w.dims, w.vox, w.mu, w.origin)
+    for p, d in zip(w.fuse_poses, w.fuse_depths):
+        vol.integrate(dev(d), w.K, p.q, p.t)
+    psi, _ = vol.export()
+    pst, _ = orc.pst_sample(w.n_particles, w.pst_seed)
+    return w, vol, host(psi), pst
+
+
+@pytest.mark.parametrize("lookup", [0, 1])
+@pytest.mark.parametrize("r0", [0.1, 0.55])
+def test_track_frame_parity(R, orc, small_gpu, lookup, r0):
+    w, vol, psi, pst = small_gpu
+    prev = w.fuse_poses[-1]
+    params = R.track_params(max_iters=w.iters, stride=w.stride, lookup=lookup)
+    st = R.track_state(prev.q, prev.t, [r0] * 6)
+    g = R.track_frame(vol, dev(w.depth), w.K, dev(pst), params, st)
+    o = orc.track_frame(psi, w.vox, w.origin, w.depth, w.K, pst, prev.q, prev.t, np.full(6, r0),
+                        max_iters=w.iters, stride=w.stride, lookup=lookup, prec=orc.F32)
+    assert g["iters"] == o["iters"] == w.iters
+    assert g["n_points"] == o["n_points"]
+    assert g["aps"][0] == o["aps"][0]
+    assert np.linalg.norm(np.array(g["t"]) - o["t"]) <= 1e-4
+    assert _rot_err(g["q"], o["q"]) <= 1e-4
+    assert np.allclose(g["r1"], o["r1"], rtol=1e-6, atol=1e-9)
+    assert abs(g["rho"] - o["rho"]) <= 1e-5
+
+
+@pytest.mark.parametrize("flags,early", [(1, False), (2, False), (0, True)])
+def test_track_frame_flags_parity(R, orc, small_gpu, flags, early):
+    w, vol, psi, pst = small_gpu
+    prev = w.fuse_poses[-1]
+    params = R.track_params(max_iters=12, stride=w.stride, flags=flags, early_stop=early)
+    st = R.track_state(prev.q, prev.t, [0.1] * 6)
+    g = R.track_frame(vol, dev(w.depth), w.K, dev(pst), params, st)
+    o = orc.track_frame(psi, w.vox, w.origin, w.depth, w.K, pst, prev.q, prev.t, np.full(6, 0.1), max_iters=12,
+                        stride=w.stride, flags=flags, early_stop=early, prec=orc.F32)
+    assert g["iters"] == o["iters"]
+    assert list(g["aps"]) == list(o["aps"])
+    assert np.linalg.norm(np.array(g["t"]) - o["t"]) <= 1e-4
+    assert _rot_err(g["q"], o["q"]) <= 1e-4
+
+
+def test_track_frame_corner_cases(R, orc, small_gpu):
+    w, vol, psi, pst = small_gpu
+    prev = w.fuse_poses[-1]
+    params = R.track_params(max_iters=10, stride=w.stride)
+    # no valid depth: status E_STATE, state untouched
+    st = R.track_state(prev.q, prev.t, [0.1] * 6)
+    with pytest.raises(R.RoseError) as ei:
+        R.track_frame(vol, dev(np.zeros_like(w.depth)), w.K, dev(pst), params, st)
+    assert ei.value.status == R.E_STATE
+    assert list(st.pose.t) == list(prev.t) and st.frame == 0
+    # first frame (TSDF not built): r_1 = 0.1 * 1 + 0.9 * 0.5
+    st = R.track_state(prev.q, prev.t, [1.0] * 6, tsdf_built=False)
+    g = R.track_frame(vol, dev(w.depth), w.K, dev(pst), params, st)
+    assert np.allclose(g["r1"], 0.55) and list(st.pose.t) == list(prev.t)
+    # a single particle (the centre only): every APS is empty
+    st = R.track_state(prev.q, prev.t, [0.1] * 6)
+    g = R.track_frame(vol, dev(w.depth), w.K, dev(pst[:1]), params, st)
+    assert g["aps"] == [0] * 10 and list(st.pose.t) == list(prev.t)
+
+
+def test_track_full_size_first_iteration(R, orc, room_frame):
+    """Real size (512^3, 640x480, stride 4, 10240 particles): one iteration
+    on the GPU equals the oracle's one iteration (APS size, centre, r_1)."""
+    seq, vol, psi, _, _, d1 = room_frame
+    pst, _ = orc.pst_sample(10240, 5600)
+    prev = seq.poses[0]
+    params = R.track_params(max_iters=1, stride=seq.stride)
+    st = R.track_state(prev.q, prev.t, [0.55] * 6)
+    g = R.track_frame(vol, dev(d1), seq.K, dev(pst), params, st)
+    o = orc.track_frame(psi, seq.vox, seq.origin, d1, seq.K, pst, prev.q, prev.t, np.full(6, 0.55), max_iters=1,
+                        stride=seq.stride, prec=orc.F32)
+    assert g["n_points"] == o["n_points"] and g["n_overlap"][0] == o["n_overlap_last"]
+    assert g["aps"][0] == o["aps"][0]
+    assert np.linalg.norm(np.array(g["t"]) - o["t"]) <= 1e-4
+    assert _rot_err(g["q"], o["q"]) <= 1e-4
+    assert np.allclose(g["r1"], o["r1"], rtol=1e-6)
