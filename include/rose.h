@@ -53,6 +53,11 @@ typedef enum { ROSE_LOOKUP_NEAREST = 0, ROSE_LOOKUP_TRILINEAR = 1 } rose_lookup;
 /* pso_track_frame flags: the ablation switches of Sec. 5.2 (Tab. ablt-tsdf) */
 #define ROSE_FLAG_NO_OVERLAP 1   /* O_k := every valid point (Eq. validness skipped) */
 #define ROSE_FLAG_NO_NORMALIZE 2 /* fitness = exp(-sum psi^2 / tau) (Eq. ourlh) instead of Eq. normallh */
+/* APS threshold rho(s*_{k-1}): by default the exact fitness of the centre
+ * (template row 0 sits at c_{k-1} = s*_{k-1}); with this flag, from k = 2 on,
+ * the approximated fitness of Eq. wafit carried from the last non-empty
+ * iteration (the substitute Sec. 4 uses for the fitness of s*_k). */
+#define ROSE_FLAG_WAFIT_THRESHOLD 4
 
 #define ROSE_MAX_ITERS 32
 #define ROSE_MAX_PARTICLES 65536
@@ -216,7 +221,7 @@ typedef struct {
  * previous frame's camera at state->pose.
  * Every iteration k: O_k with the centre c_{k-1}; fitness of every particle
  * pose c_{k-1} * Delta(r_{k-1} (.) p_i) (Eq. normallh); APS = particles with
- * fitness above the centre's (particle 0); CompBestState (Eq. ebs),
+ * fitness above rho(s*_{k-1}) (see ROSE_FLAG_WAFIT_THRESHOLD); CompBestState (Eq. ebs),
  * approximated best fitness (Eq. wafit), CompAxisLength (Eqs. rsdir,
  * rsinter with |v_d|, momentum), MovePST (c_k = c_{k-1} * Delta(u*)) and the
  * corner cases of Sec. 4.  The whole loop runs on the device; the call

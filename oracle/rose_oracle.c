@@ -37,6 +37,7 @@
 /* flag bits of the tracker (ablation switches of Sec. 5.2, Tab. ablt-tsdf) */
 #define ORC_NO_OVERLAP 1
 #define ORC_NO_NORMALIZE 2
+#define ORC_WAFIT_THRESHOLD 4
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x64-10 counter-based generator (Salmon, Moraes, Dror, Shaw, SC'11, */
@@ -491,9 +492,9 @@ void orc_voxel_indices(int32_t nx, int32_t ny, int32_t nz, float vox, const floa
 }
 
 /* ------------------------------------------------------------------------ */
-/* PST update of one iteration (Alg. 1 lines after the APS loop):           */
-/*  rho_prev = rho of the PST centre (template row 0 sits at c_{k-1}).      */
-/*  APS = { i : rho_i > rho_prev }, decided as F_i < F_0 (same set).        */
+/* PST update of one iteration (the steps of Alg. 1 after the APS loop):  */
+/*  rho_prev = rho(s*_{k-1}), the APS threshold, given by the caller.       */
+/*  APS = { i : rho_i > rho_prev }, rho_i = exp(-F_i / tau) in binary64.    */
 /*  Non-empty APS (Eqs. ebs, wafit, rsdir, rsinter):                        */
 /*     w_i = rho_i - rho_prev, W = sum w_i;                                 */
 /*     u* = sum w_i u_i / W  (u_i = r (.) p_i, chart of c_{k-1});            */
@@ -509,8 +510,8 @@ void orc_voxel_indices(int32_t nx, int32_t ny, int32_t nz, float vox, const floa
 /* (rho_prev when the APS is empty) and u* (zeros when empty).              */
 /* ------------------------------------------------------------------------ */
 int orc_pst_update(const double* F, const float* pst, int32_t n, const double r_in[6], const double qc[4],
-                   const double tc[3], double tau, double beta, double eps, int32_t tsdf_built, double r_out[6],
-                   double q_out[4], double t_out[3], double* rho_tilde, double u_star[6]) {
+                   const double tc[3], double tau, double beta, double eps, int32_t tsdf_built, double rho_thr,
+                   double r_out[6], double q_out[4], double t_out[3], double* rho_tilde, double u_star[6]) {
     const double inv_sqrt6 = 1.0 / sqrt(6.0);
     double rhat[6];
     int aps = 0;
@@ -521,12 +522,12 @@ int orc_pst_update(const double* F, const float* pst, int32_t n, const double r_
         for (int d = 0; d < 6; ++d) rhat[d] = 0.5;
         *rho_tilde = 0.5;
     } else {
-        double rho_prev = exp(-F[0] / tau);
+        double rho_prev = rho_thr;
         double sw = 0, cw = 0, sr = 0, cr = 0, su[6] = {0}, cu[6] = {0};
         for (int32_t i = 0; i < n; ++i) {
-            if (!(F[i] < F[0])) continue;
-            ++aps;
             double rho = exp(-F[i] / tau);
+            if (!(rho > rho_prev)) continue;
+            ++aps;
             double w = rho - rho_prev;
             neumaier_add(&sw, &cw, w);
             neumaier_add(&sr, &cr, w * rho);
@@ -600,6 +601,7 @@ int orc_track_frame(const float* psi, int32_t nx, int32_t ny, int32_t nz, float 
     orc_pose_to_mat(q_prev, t_prev, Tprev);
     int rc = 0;
     int32_t k = 0, empty_streak = 0, nO = 0;
+    double thr = 0.0;
     double rho_last = 0.5;
     int have_rho = 0;
     if (m == 0 && tsdf_built) {
@@ -623,8 +625,16 @@ int orc_track_frame(const float* psi, int32_t nx, int32_t ny, int32_t nz, float 
             if (P->prec == ORC_F32)
                 for (int32_t i = 0; i < n; ++i) F[i] = (double)(float)F[i];
         }
-        int aps = orc_pst_update(F, pst, n, r, qc, tc, P->tau, P->beta, P->eps, tsdf_built, r_new, q_new, t_new,
-                                 &rt, us);
+        /* APS threshold rho(s*_{k-1}): the centre's own fitness -- template    */
+        /* row 0 sits at c_{k-1} = s*_{k-1}, so its exact value comes with the  */
+        /* particle evaluation.  ORC_WAFIT_THRESHOLD: from k = 2 on, use the    */
+        /* approximation of Eq. wafit carried from the last non-empty          */
+        /* iteration instead (the substitute Sec. 4 uses for rho(s*_k)).       */
+        double centre = tsdf_built ? exp(-F[0] / P->tau) : 0.5;
+        double thr_k = (k == 1 || !(P->flags & ORC_WAFIT_THRESHOLD)) ? centre : thr;
+        int aps = orc_pst_update(F, pst, n, r, qc, tc, P->tau, P->beta, P->eps, tsdf_built, thr_k, r_new, q_new,
+                                 t_new, &rt, us);
+        thr = (aps > 0) ? rt : thr_k;
         if (k - 1 < 32) {
             aps_sizes[k - 1] = aps;
             rho_iter[k - 1] = rt;

@@ -230,6 +230,7 @@ struct DevState {
     double r1[6];
     double Tprev[12];
     double rho_last;
+    double thr;  // APS threshold carried between iterations (Eq. wafit)
     int32_t k;
     int32_t stopped;
     int32_t empty_streak;

@@ -97,6 +97,7 @@ __global__ __launch_bounds__(1024) void k_track_init(InitArgs a) {
         for (int i = 0; i < 6; ++i) s->r1[i] = a.r[i];
         for (int i = 0; i < 12; ++i) s->Tprev[i] = a.Tprev[i];
         s->rho_last = 0.5;
+        s->thr = 0.0;
         s->k = 0;
         s->stopped = (m == 0) ? 1 : 0;
         s->empty_streak = 0;
@@ -151,7 +152,10 @@ __global__ __launch_bounds__(1024) void k_track_update(UpdateArgs a) {
     if (threadIdx.x == 0) F0s = final_fitness(a, 0, nO);
     __syncthreads();
     const float F0 = F0s;
-    const double rho0 = exp(-(double)F0 / a.tau);
+    // APS threshold rho(s*_{k-1}): the centre's exact fitness (particle 0),
+    // or with ROSE_FLAG_WAFIT_THRESHOLD the carried Eq. wafit value from k = 2
+    const double centre = exp(-(double)F0 / a.tau);
+    const double rho0 = (st->k == 0 || !(a.flags & ROSE_FLAG_WAFIT_THRESHOLD)) ? centre : st->thr;
     double r[6];
     for (int d = 0; d < 6; ++d) r[d] = st->r[d];
     // per-thread APS sums: count, sum w, sum w rho, sum w u_d
@@ -159,8 +163,8 @@ __global__ __launch_bounds__(1024) void k_track_update(UpdateArgs a) {
     for (int i = threadIdx.x; i < a.n; i += blockDim.x) {
         const float f = final_fitness(a, i, nO);
         a.F[i] = f;
-        if (f < F0) {
-            const double rho = exp(-(double)f / a.tau);
+        const double rho = exp(-(double)f / a.tau);
+        if (rho > rho0) {
             const double w = rho - rho0;
             cnt += 1.0;
             sw += w;
@@ -210,6 +214,7 @@ __global__ __launch_bounds__(1024) void k_track_update(UpdateArgs a) {
             if (a.early_stop && st->empty_streak >= 2) st->stopped = 1;
         }
         for (int d = 0; d < 6; ++d) st->r[d] = a.beta * r[d] + (1.0 - a.beta) * rhat[d];
+        st->thr = (aps > 0) ? rt : rho0;
         const int k = st->k;
         st->aps[k] = aps;
         st->n_overlap_iter[k] = nO;

@@ -29,7 +29,7 @@ OK = 0
 E_ARG, E_SHAPE, E_DEVICE, E_STATE, E_UNSUPPORTED = -1, -2, -3, -4, -5
 F32, F16, SN16 = 0, 1, 2
 NEAREST, TRILINEAR = 0, 1
-FLAG_NO_OVERLAP, FLAG_NO_NORMALIZE = 1, 2
+FLAG_NO_OVERLAP, FLAG_NO_NORMALIZE, FLAG_WAFIT_THRESHOLD = 1, 2, 4
 MAX_ITERS = 32
 
 
