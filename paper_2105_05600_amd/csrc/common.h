@@ -54,8 +54,13 @@ struct Grid {
 };
 
 // brick-major offset of voxel (i, j, k): brick index * 512 + in-brick offset
+// (brick counts per axis are <= 256, so the products fit 24-bit multiplies)
 __host__ __device__ inline uint32_t brick_offset(const Grid& g, uint32_t i, uint32_t j, uint32_t k) {
-    uint32_t b = ((k >> 3) * (uint32_t)g.nby + (j >> 3)) * (uint32_t)g.nbx + (i >> 3);
+#if defined(__HIP_DEVICE_COMPILE__)
+    const uint32_t b = __umul24(__umul24(k >> 3, (uint32_t)g.nby) + (j >> 3), (uint32_t)g.nbx) + (i >> 3);
+#else
+    const uint32_t b = ((k >> 3) * (uint32_t)g.nby + (j >> 3)) * (uint32_t)g.nbx + (i >> 3);
+#endif
     return (b << 9) | ((k & 7u) << 6) | ((j & 7u) << 3) | (i & 7u);
 }
 

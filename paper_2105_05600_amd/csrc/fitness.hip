@@ -15,30 +15,54 @@
 
 namespace rose {
 
+// Byte offset of an element; volumes below 4 GB use 32-bit offsets so the
+// gather is a global load with a scalar base and a 32-bit vector offset.
 template <int FMT>
-__device__ inline float lookup_nearest(const Grid& g, float gx, float gy, float gz) {
-    const bool in = gx >= 0.0f && gx < (float)g.nx && gy >= 0.0f && gy < (float)g.ny && gz >= 0.0f &&
-                    gz < (float)g.nz;
-    const uint32_t off = in ? brick_offset(g, (uint32_t)gx, (uint32_t)gy, (uint32_t)gz) : 0u;
-    const float v = load_psi<FMT>(g.psi, off);
-    return in ? v : 1.0f;
+__device__ inline uint32_t elem_bytes() {
+    return FMT == ROSE_TSDF_F32 ? 4u : 2u;
 }
 
-template <int FMT>
+template <int FMT, bool WIDE>
+__device__ inline float gather(const void* base, uint32_t off) {
+    if constexpr (WIDE) {
+        return load_psi<FMT>(base, off);
+    } else {
+        const char* p = (const char*)base + (off * elem_bytes<FMT>());
+        if constexpr (FMT == ROSE_TSDF_F32) return *(const float*)p;
+        else if constexpr (FMT == ROSE_TSDF_F16) return __half2float(*(const __half*)p);
+        else return (float)(*(const int16_t*)p) * (1.0f / 32767.0f);
+    }
+}
+
+struct VoxelTest {
+    float fx, fy, fz;  // grid extent as float
+};
+
+// NEAREST voxel of voxel-space coordinate g: inside iff 0 <= g < n on every
+// axis (NaN is outside); then floor(g) == (uint32)g.
+__device__ inline bool nearest_offset(const Grid& g, const VoxelTest& e, float gx, float gy, float gz, uint32_t* off) {
+    const bool in = (gx >= 0.0f) & (gx < e.fx) & (gy >= 0.0f) & (gy < e.fy) & (gz >= 0.0f) & (gz < e.fz);
+    // out-of-range conversions saturate; their offset is replaced below
+    const uint32_t o = brick_offset(g, (uint32_t)gx, (uint32_t)gy, (uint32_t)gz);
+    *off = in ? o : 0u;
+    return in;
+}
+
+template <int FMT, bool WIDE>
 __device__ inline float lookup_trilinear(const Grid& g, float gx, float gy, float gz) {
     const float hx = gx - 0.5f, hy = gy - 0.5f, hz = gz - 0.5f;
-    const bool in = hx >= 0.0f && hx < (float)(g.nx - 1) && hy >= 0.0f && hy < (float)(g.ny - 1) && hz >= 0.0f &&
-                    hz < (float)(g.nz - 1);
+    const bool in = (hx >= 0.0f) & (hx < (float)(g.nx - 1)) & (hy >= 0.0f) & (hy < (float)(g.ny - 1)) &
+                    (hz >= 0.0f) & (hz < (float)(g.nz - 1));
     const uint32_t ix = in ? (uint32_t)hx : 0u, iy = in ? (uint32_t)hy : 0u, iz = in ? (uint32_t)hz : 0u;
     const float fx = hx - (float)ix, fy = hy - (float)iy, fz = hz - (float)iz;
-    const float v000 = load_psi<FMT>(g.psi, brick_offset(g, ix, iy, iz));
-    const float v100 = load_psi<FMT>(g.psi, brick_offset(g, ix + 1, iy, iz));
-    const float v010 = load_psi<FMT>(g.psi, brick_offset(g, ix, iy + 1, iz));
-    const float v110 = load_psi<FMT>(g.psi, brick_offset(g, ix + 1, iy + 1, iz));
-    const float v001 = load_psi<FMT>(g.psi, brick_offset(g, ix, iy, iz + 1));
-    const float v101 = load_psi<FMT>(g.psi, brick_offset(g, ix + 1, iy, iz + 1));
-    const float v011 = load_psi<FMT>(g.psi, brick_offset(g, ix, iy + 1, iz + 1));
-    const float v111 = load_psi<FMT>(g.psi, brick_offset(g, ix + 1, iy + 1, iz + 1));
+    const float v000 = gather<FMT, WIDE>(g.psi, brick_offset(g, ix, iy, iz));
+    const float v100 = gather<FMT, WIDE>(g.psi, brick_offset(g, ix + 1, iy, iz));
+    const float v010 = gather<FMT, WIDE>(g.psi, brick_offset(g, ix, iy + 1, iz));
+    const float v110 = gather<FMT, WIDE>(g.psi, brick_offset(g, ix + 1, iy + 1, iz));
+    const float v001 = gather<FMT, WIDE>(g.psi, brick_offset(g, ix, iy, iz + 1));
+    const float v101 = gather<FMT, WIDE>(g.psi, brick_offset(g, ix + 1, iy, iz + 1));
+    const float v011 = gather<FMT, WIDE>(g.psi, brick_offset(g, ix, iy + 1, iz + 1));
+    const float v111 = gather<FMT, WIDE>(g.psi, brick_offset(g, ix + 1, iy + 1, iz + 1));
     const float c00 = fmaf(fx, v100 - v000, v000);
     const float c10 = fmaf(fx, v110 - v010, v010);
     const float c01 = fmaf(fx, v101 - v001, v001);
@@ -53,7 +77,11 @@ __device__ inline float bcast(float v, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
-template <int P, int FMT, int LK, bool FROM_STATE>
+// U points per lane per loop step; all P*U gathers of a step are issued
+// before any is consumed.
+constexpr int kU = 2;
+
+template <int P, int FMT, int LK, bool FROM_STATE, bool WIDE>
 __global__ __launch_bounds__(256) void k_fitness(FitLaunch a) {
     const int lane = threadIdx.x & 63;
     const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -81,31 +109,71 @@ __global__ __launch_bounds__(256) void k_fitness(FitLaunch a) {
         }
         fold_to_voxel(T, (double)a.g.vox, a.g.origin, V);
     }
+    // rotation entries wave-uniform (scalar registers); the translation column
+    // is broadcast with a cross-lane shuffle so that each fma reads at most
+    // one scalar operand
     float S[P][12];
 #pragma unroll
     for (int p = 0; p < P; ++p)
 #pragma unroll
-        for (int e = 0; e < 12; ++e) S[p][e] = bcast(V[e], p);
+        for (int e = 0; e < 12; ++e) S[p][e] = (e % 4 == 3) ? __shfl(V[e], p, kWave) : bcast(V[e], p);
 
+    const Grid g = a.g;
+    const VoxelTest ext{(float)g.nx, (float)g.ny, (float)g.nz};
     const int chunk = (m + a.splits - 1) / a.splits;
     const int j0 = split * chunk;
     const int j1 = min(m, j0 + chunk);
     double acc[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) acc[p] = 0.0;
-    for (int j = j0 + lane; j < j1; j += kWave) {
-        const float4 x = a.pts[j];
-        float v[P];
+    for (int jb = j0; jb < j1; jb += kWave * kU) {
+        float4 x[kU];
+        bool ok[kU];
 #pragma unroll
-        for (int p = 0; p < P; ++p) {
-            const float gx = xf_row(S[p][0], S[p][1], S[p][2], S[p][3], x.x, x.y, x.z);
-            const float gy = xf_row(S[p][4], S[p][5], S[p][6], S[p][7], x.x, x.y, x.z);
-            const float gz = xf_row(S[p][8], S[p][9], S[p][10], S[p][11], x.x, x.y, x.z);
-            v[p] = (LK == ROSE_LOOKUP_NEAREST) ? lookup_nearest<FMT>(a.g, gx, gy, gz)
-                                               : lookup_trilinear<FMT>(a.g, gx, gy, gz);
+        for (int u = 0; u < kU; ++u) {
+            const int j = jb + u * kWave + lane;
+            ok[u] = j < j1;
+            x[u] = a.pts[ok[u] ? j : j0];
+        }
+        float v[kU][P];
+        if constexpr (LK == ROSE_LOOKUP_NEAREST) {
+            uint32_t off[kU][P];
+            bool in[kU][P];
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    const float gx = xf_row(S[p][0], S[p][1], S[p][2], S[p][3], x[u].x, x[u].y, x[u].z);
+                    const float gy = xf_row(S[p][4], S[p][5], S[p][6], S[p][7], x[u].x, x[u].y, x[u].z);
+                    const float gz = xf_row(S[p][8], S[p][9], S[p][10], S[p][11], x[u].x, x[u].y, x[u].z);
+                    in[u][p] = nearest_offset(g, ext, gx, gy, gz, &off[u][p]);
+                }
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+#pragma unroll
+                for (int p = 0; p < P; ++p) v[u][p] = gather<FMT, WIDE>(g.psi, off[u][p]);
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+#pragma unroll
+                for (int p = 0; p < P; ++p) v[u][p] = in[u][p] ? v[u][p] : 1.0f;
+        } else {
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    const float gx = xf_row(S[p][0], S[p][1], S[p][2], S[p][3], x[u].x, x[u].y, x[u].z);
+                    const float gy = xf_row(S[p][4], S[p][5], S[p][6], S[p][7], x[u].x, x[u].y, x[u].z);
+                    const float gz = xf_row(S[p][8], S[p][9], S[p][10], S[p][11], x[u].x, x[u].y, x[u].z);
+                    v[u][p] = lookup_trilinear<FMT, WIDE>(g, gx, gy, gz);
+                }
         }
 #pragma unroll
-        for (int p = 0; p < P; ++p) acc[p] = fma((double)v[p], (double)v[p], acc[p]);
+        for (int u = 0; u < kU; ++u)
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const double d = (double)(ok[u] ? v[u][p] : 0.0f);
+                acc[p] = fma(d, d, acc[p]);
+            }
     }
 #pragma unroll
     for (int p = 0; p < P; ++p) acc[p] = wave_sum(acc[p]);
@@ -154,21 +222,28 @@ __global__ __launch_bounds__(256) void k_pack_points(const float* pts3, int32_t 
 
 constexpr int kP = 4;  // particles per wave
 
-template <int FMT, int LK>
+template <int FMT, int LK, bool WIDE>
 static void launch_t(const FitLaunch& L, hipStream_t s) {
     const int groups = (L.n + kP - 1) / kP;
     const int64_t waves = (int64_t)groups * L.splits;
     const unsigned blocks = (unsigned)((waves + 3) / 4);
     if (L.T32)
-        hipLaunchKernelGGL((k_fitness<kP, FMT, LK, false>), dim3(blocks), dim3(256), 0, s, L);
+        hipLaunchKernelGGL((k_fitness<kP, FMT, LK, false, WIDE>), dim3(blocks), dim3(256), 0, s, L);
     else
-        hipLaunchKernelGGL((k_fitness<kP, FMT, LK, true>), dim3(blocks), dim3(256), 0, s, L);
+        hipLaunchKernelGGL((k_fitness<kP, FMT, LK, true, WIDE>), dim3(blocks), dim3(256), 0, s, L);
+}
+
+template <int FMT, int LK>
+static void launch_w(const FitLaunch& L, hipStream_t s) {
+    const uint64_t bytes = (uint64_t)L.g.nx * L.g.ny * L.g.nz * (FMT == ROSE_TSDF_F32 ? 4u : 2u);
+    if (bytes < (uint64_t(1) << 32)) launch_t<FMT, LK, false>(L, s);
+    else launch_t<FMT, LK, true>(L, s);
 }
 
 template <int FMT>
 static void launch_f(const FitLaunch& L, hipStream_t s) {
-    if (L.lookup == ROSE_LOOKUP_TRILINEAR) launch_t<FMT, ROSE_LOOKUP_TRILINEAR>(L, s);
-    else launch_t<FMT, ROSE_LOOKUP_NEAREST>(L, s);
+    if (L.lookup == ROSE_LOOKUP_TRILINEAR) launch_w<FMT, ROSE_LOOKUP_TRILINEAR>(L, s);
+    else launch_w<FMT, ROSE_LOOKUP_NEAREST>(L, s);
 }
 
 rose_status launch_fitness(const FitLaunch& L, hipStream_t s) {
