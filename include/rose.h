@@ -235,6 +235,38 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_cam
                             int32_t n_particles, const rose_track_params* p, const rose_pose* init_centre,
                             const double* init_r, rose_track_state* state, rose_track_stats* stats, hipStream_t s);
 
+/* ------------------------------------------- learned proposal network */
+/* A 3-layer perceptron in -> hid (GELU) -> hid (GELU) -> 12, output
+ * (mu in R^6, log-scale l in R^6) of the PST centre increment and axis
+ * lengths.  Parameters: one caller-owned float32 device buffer of
+ * rose_mlp_param_count() elements laid out [W1 (in x hid), b1, W2
+ * (hid x hid), b2, W3 (hid x 12), b3], y = x W + b.  The GEMMs run on the
+ * matrix cores with BF16 operands (round to nearest even) and FP32
+ * accumulation; GELU is the exact erf form.  The handle owns activation
+ * scratch for up to max_batch rows.  out_dim must be 12. */
+typedef struct rose_mlp rose_mlp;
+int64_t rose_mlp_param_count(int32_t in_dim, int32_t hidden, int32_t out_dim);
+rose_status rose_mlp_create(int32_t in_dim, int32_t hidden, int32_t out_dim, int32_t max_batch, rose_mlp** out);
+rose_status rose_mlp_destroy(rose_mlp* m);
+/* out_dev: B x 12 float32; X_dev: B x in float32 (row-major). */
+rose_status rose_mlp_forward(rose_mlp* m, const float* params_dev, const float* X_dev, int32_t B, float* out_dev,
+                             hipStream_t s);
+/* Heteroscedastic Gaussian NLL, mean over the batch of
+ * sum_d [(y_d - mu_d)^2 / (2 exp(2 l_d)) + l_d]; targets Y_dev B x 6.  Writes
+ * the gradient w.r.t. every parameter to grads_dev (same layout) and the
+ * loss to loss_dev[0] (device float). */
+rose_status rose_mlp_loss_grad(rose_mlp* m, const float* params_dev, const float* X_dev, const float* Y_dev,
+                               int32_t B, float* grads_dev, float* loss_dev, hipStream_t s);
+/* Adam (Kingma & Ba 2015), elementwise on FP32 master weights; step is the
+ * 1-based step count used for the bias corrections. */
+rose_status rose_mlp_adam(int64_t n, float* params_dev, const float* grads_dev, float* m_dev, float* v_dev,
+                          int32_t step, float lr, float beta1, float beta2, float eps, hipStream_t s);
+/* The BF16 matrix-core GEMM on its own: C(m, n) = sum_k A(m, k) B(k, n) with
+ * A(m, k) = A_dev[m sam + k sak], B(k, n) = B_dev[k sbk + n sbn],
+ * C(m, n) = C_dev[m ldc + n]. */
+rose_status rose_gemm_bf16(int32_t M, int32_t N, int32_t K, const float* A_dev, int64_t sam, int64_t sak,
+                           const float* B_dev, int64_t sbk, int64_t sbn, float* C_dev, int64_t ldc, hipStream_t s);
+
 /* ------------------------------------------------------- kernel timing */
 /* When enabled (process-wide), pso_track_frame and tsdf_integrate bracket
  * each fitness, update and integration launch with HIP events recorded on

@@ -127,6 +127,9 @@ def _load():
                                           C.c_float, P, C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float,
                                           C.c_float, P, P, C.c_int]
             lib.orc_integrate.restype = C.c_int64
+            lib.orc_raycast.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_float, P, P, P, C.c_int32,
+                                        C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
+                                        C.c_double, C.c_double, P]
             _lib = lib
     return _lib
 
@@ -313,3 +316,40 @@ def pose_mat(q, t) -> np.ndarray:
     M = np.eye(4)
     M[:3, :] = T
     return M
+
+
+def raycast(psi, vox, origin, q, t, K, near=0.2, far=8.0, step=None) -> np.ndarray:
+    """Depth (H, W) float32 of the TSDF rendered at pose (q, t) through the
+    intrinsics K (binary32 intrinsics widened to binary64)."""
+    lib = _load()
+    psi = _f32(psi)
+    nz, ny, nx = psi.shape
+    q, t = _f64(q), _f64(t)
+    org = _f32(origin)
+    out = np.zeros((K.height, K.width), np.float32)
+    st = float(np.float32(vox)) / 2 if step is None else step
+    f32 = lambda v: float(np.float32(v))  # noqa: E731
+    lib.orc_raycast(_p(psi), nx, ny, nz, float(vox), _p(org), _p(q), _p(t), K.width, K.height, f32(K.fx), f32(K.fy),
+                    f32(K.cx), f32(K.cy), float(near), float(far), float(st), _p(out))
+    return out
+
+
+def proposal_features(depth, render, scale: int, velocity, dim: int) -> np.ndarray:
+    """Input vector of the learned proposal: depth residual on the low-res
+    grid (the full-res sample at (scale u + scale/2, scale v + scale/2)
+    minus the rendered model depth, clamped to +-0.5 m, 0 where either is
+    missing), then the 6D previous velocity, then zeros up to dim."""
+    depth = np.asarray(depth, np.float32)
+    render = np.asarray(render, np.float32)
+    h, w = render.shape
+    H, W = depth.shape
+    out = np.zeros(dim, np.float32)
+    for v in range(h):
+        for u in range(w):
+            U, V = scale * u + scale // 2, scale * v + scale // 2
+            d = depth[V, U] if (U < W and V < H) else np.float32(0)
+            m = render[v, u]
+            if d > 0 and m > 0:
+                out[v * w + u] = min(np.float32(0.5), max(np.float32(-0.5), np.float32(d - m)))
+    out[h * w:h * w + 6] = np.asarray(velocity, np.float64).astype(np.float32)
+    return out

@@ -751,3 +751,44 @@ int64_t orc_integrate(float* psi, float* wgt, int32_t nx, int32_t ny, int32_t nz
             }
     return updated;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Low-resolution raycast of the TSDF (the model rendered at a pose; input  */
+/* of the learned proposal).  For pixel (u, v) of the given intrinsics the  */
+/* ray is x(z) = T (z (u - cx)/fx, z (v - cy)/fy, z), z = z-depth.  It is   */
+/* sampled at z_k = near + k * step (k = 0, 1, ..) while z_k <= far, with   */
+/* trilinear psi (any corner outside the grid: +1).  The first pair of      */
+/* consecutive samples with psi_k > 0 >= psi_{k+1}, both inside the          */
+/* truncation band (|psi| < 1), gives the depth by linear interpolation     */
+/* z* = z_k + step psi_k / (psi_k - psi_{k+1}); no such pair: 0.            */
+/* Binary64 throughout.                                                     */
+/* ------------------------------------------------------------------------ */
+void orc_raycast(const float* psi, int32_t nx, int32_t ny, int32_t nz, float vox, const float origin[3],
+                 const double q[4], const double t[3], int32_t W, int32_t H, double fx, double fy, double cx,
+                 double cy, double near_z, double far_z, double step, float* depth_out) {
+    orc_grid g = {psi, nx, ny, nz, (double)vox, {origin[0], origin[1], origin[2]}};
+    double R[9];
+    orc_quat_to_rot(q, R);
+    for (int32_t v = 0; v < H; ++v)
+        for (int32_t u = 0; u < W; ++u) {
+            double dc[3] = {((double)u - cx) / fx, ((double)v - cy) / fy, 1.0}, dw[3];
+            rot_apply(R, dc, dw);
+            double prev = 0.0, zprev = 0.0, out = 0.0;
+            int have = 0;
+            for (int64_t k = 0;; ++k) {
+                double z = near_z + (double)k * step;
+                if (z > far_z) break;
+                double gv[3];
+                for (int c = 0; c < 3; ++c) gv[c] = (t[c] + z * dw[c] - g.origin[c]) / g.vox - 0.5;
+                double s = lookup(&g, gv, ORC_LOOKUP_TRILINEAR);
+                if (have && prev > 0.0 && s <= 0.0 && prev < 1.0 && s > -1.0) {
+                    out = zprev + step * prev / (prev - s);
+                    break;
+                }
+                prev = s;
+                zprev = z;
+                have = 1;
+            }
+            depth_out[(size_t)v * W + u] = (float)out;
+        }
+}

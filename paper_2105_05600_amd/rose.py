@@ -13,6 +13,7 @@ import os
 import re
 from typing import Optional, Sequence
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -85,6 +86,19 @@ _sigs = {
     "overlap_mask": ([_P, C.c_int32, C.POINTER(Pose), C.POINTER(Pose), C.POINTER(Camera), _P, _S], C.c_int),
     "pso_track_frame": ([_P, _P, C.POINTER(Camera), _P, C.c_int32, C.POINTER(TrackParams), C.POINTER(Pose), _P,
                          C.POINTER(TrackState), C.POINTER(TrackStats), _S], C.c_int),
+    "tsdf_raycast": ([_P, C.POINTER(Pose), C.POINTER(Camera), C.c_double, C.c_double, C.c_double, _P, _S],
+                     C.c_int),
+    "proposal_features": ([_P, C.POINTER(Camera), _P, C.POINTER(Camera), C.c_int32, _P, C.c_int32, _P, _S],
+                          C.c_int),
+    "rose_mlp_param_count": ([C.c_int32, C.c_int32, C.c_int32], C.c_int64),
+    "rose_mlp_create": ([C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_void_p)], C.c_int),
+    "rose_mlp_destroy": ([_P], C.c_int),
+    "rose_mlp_forward": ([_P, _P, _P, C.c_int32, _P, _S], C.c_int),
+    "rose_mlp_loss_grad": ([_P, _P, _P, _P, C.c_int32, _P, _P, _S], C.c_int),
+    "rose_mlp_adam": ([C.c_int64, _P, _P, _P, _P, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float, _S],
+                      C.c_int),
+    "rose_gemm_bf16": ([C.c_int32, C.c_int32, C.c_int32, _P, C.c_int64, C.c_int64, _P, C.c_int64, C.c_int64, _P,
+                        C.c_int64, _S], C.c_int),
     "rose_profile_enable": ([C.c_int32], C.c_int),
     "rose_profile_reset": ([], C.c_int),
     "rose_profile_read": ([C.POINTER(Profile)], C.c_int),
@@ -275,6 +289,29 @@ def overlap_mask(pts: torch.Tensor, centre, prev, K, stream=None) -> torch.Tenso
     return mask[:m].bool()
 
 
+def raycast(vol: Tsdf, q, t, K, near: float = 0.2, far: float = 8.0, step: Optional[float] = None,
+            stream=None) -> torch.Tensor:
+    cam = camera(K)
+    out = torch.empty((cam.height, cam.width), dtype=torch.float32, device=vol.psi.device)
+    p = pose(q, t)
+    st = vol.voxel / 2 if step is None else step
+    _check("tsdf_raycast", _lib.tsdf_raycast(vol.handle, C.byref(p), C.byref(cam), float(near), float(far), float(st),
+                                             _ptr(out), _stream(stream)))
+    return out
+
+
+def proposal_features(depth: torch.Tensor, K, render: torch.Tensor, K_low, scale: int, velocity, dim: int,
+                      stream=None) -> torch.Tensor:
+    _dev(depth, torch.float32, "depth")
+    _dev(render, torch.float32, "render")
+    cam, cl = camera(K), camera(K_low)
+    out = torch.empty(dim, dtype=torch.float32, device=depth.device)
+    vel = (C.c_double * 6)(*[float(v) for v in velocity])
+    _check("proposal_features", _lib.proposal_features(_ptr(depth), C.byref(cam), _ptr(render), C.byref(cl),
+                                                       int(scale), vel, int(dim), _ptr(out), _stream(stream)))
+    return out
+
+
 def track_params(max_iters=20, early_stop=False, stride=4, lookup=NEAREST, flags=0, beta=0.1, eps=1e-3, tau=1.0,
                  stop_tol=1e-6) -> TrackParams:
     return TrackParams(int(max_iters), int(bool(early_stop)), int(stride), int(lookup), int(flags), 0,
@@ -325,3 +362,88 @@ def profile_read() -> dict:
     p = Profile()
     _check("rose_profile_read", _lib.rose_profile_read(C.byref(p)))
     return {f: getattr(p, f) for f, _ in Profile._fields_}
+
+
+def gemm_bf16(A: torch.Tensor, B: torch.Tensor, stream=None) -> torch.Tensor:
+    """C = A @ B on the matrix cores (BF16 operands, FP32 accumulation).
+    A, B: 2-D float32 device tensors with any strides."""
+    _dev_any(A, "A")
+    _dev_any(B, "B")
+    M, K = A.shape
+    K2, N = B.shape
+    if K != K2:
+        raise ValueError("inner dimensions differ")
+    Cm = torch.empty((M, N), dtype=torch.float32, device=A.device)
+    _check("rose_gemm_bf16", _lib.rose_gemm_bf16(M, N, K, _ptr(A), A.stride(0), A.stride(1), _ptr(B), B.stride(0),
+                                                 B.stride(1), _ptr(Cm), N, _stream(stream)))
+    return Cm
+
+
+def _dev_any(t: torch.Tensor, name: str):
+    if not t.is_cuda or t.dtype != torch.float32:
+        raise ValueError(f"{name} must be a float32 device tensor")
+
+
+class Mlp:
+    """Activation scratch for the proposal network; parameters, gradients and
+    Adam moments are caller-owned flat float32 tensors."""
+
+    def __init__(self, in_dim: int = 1216, hidden: int = 256, out_dim: int = 12, max_batch: int = 1024):
+        self.in_dim, self.hidden, self.out_dim, self.max_batch = in_dim, hidden, out_dim, max_batch
+        self.n_params = int(_lib.rose_mlp_param_count(in_dim, hidden, out_dim))
+        if self.n_params <= 0:
+            raise RoseError("rose_mlp_param_count", E_SHAPE)
+        h = C.c_void_p()
+        _check("rose_mlp_create", _lib.rose_mlp_create(in_dim, hidden, out_dim, max_batch, C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _lib.rose_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def pack(self, params: dict, device="cuda") -> torch.Tensor:
+        """Flatten {W1, b1, W2, b2, W3, b3} (numpy or torch) into the layout."""
+        parts = [torch.as_tensor(params[k], dtype=torch.float32).reshape(-1) for k in ("W1", "b1", "W2", "b2", "W3", "b3")]
+        flat = torch.cat(parts).to(device)
+        if flat.numel() != self.n_params:
+            raise ValueError("parameter sizes do not match the network")
+        return flat.contiguous()
+
+    def unpack(self, flat: torch.Tensor) -> dict:
+        i, h, o = self.in_dim, self.hidden, self.out_dim
+        shapes = {"W1": (i, h), "b1": (h,), "W2": (h, h), "b2": (h,), "W3": (h, o), "b3": (o,)}
+        out, k = {}, 0
+        for name in ("W1", "b1", "W2", "b2", "W3", "b3"):
+            n = int(np.prod(shapes[name]))
+            out[name] = flat[k:k + n].reshape(shapes[name])
+            k += n
+        return out
+
+    def forward(self, params: torch.Tensor, X: torch.Tensor, stream=None) -> torch.Tensor:
+        _dev(params, torch.float32, "params")
+        _dev(X, torch.float32, "X")
+        B = X.shape[0]
+        out = torch.empty((B, self.out_dim), dtype=torch.float32, device=X.device)
+        _check("rose_mlp_forward", _lib.rose_mlp_forward(self.handle, _ptr(params), _ptr(X), B, _ptr(out),
+                                                         _stream(stream)))
+        return out
+
+    def loss_grad(self, params: torch.Tensor, X: torch.Tensor, Y: torch.Tensor, grads: torch.Tensor,
+                  loss: torch.Tensor, stream=None):
+        for t, n in ((params, "params"), (X, "X"), (Y, "Y"), (grads, "grads"), (loss, "loss")):
+            _dev(t, torch.float32, n)
+        _check("rose_mlp_loss_grad", _lib.rose_mlp_loss_grad(self.handle, _ptr(params), _ptr(X), _ptr(Y), X.shape[0],
+                                                             _ptr(grads), _ptr(loss), _stream(stream)))
+
+    @staticmethod
+    def adam(params, grads, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        _check("rose_mlp_adam", _lib.rose_mlp_adam(params.numel(), _ptr(params), _ptr(grads), _ptr(m), _ptr(v),
+                                                   int(step), float(lr), float(beta1), float(beta2), float(eps),
+                                                   _stream(stream)))
