@@ -53,11 +53,12 @@ typedef enum { ROSE_LOOKUP_NEAREST = 0, ROSE_LOOKUP_TRILINEAR = 1 } rose_lookup;
 /* pso_track_frame flags: the ablation switches of Sec. 5.2 (Tab. ablt-tsdf) */
 #define ROSE_FLAG_NO_OVERLAP 1   /* O_k := every valid point (Eq. validness skipped) */
 #define ROSE_FLAG_NO_NORMALIZE 2 /* fitness = exp(-sum psi^2 / tau) (Eq. ourlh) instead of Eq. normallh */
-/* APS threshold rho(s*_{k-1}): by default the exact fitness of the centre
- * (template row 0 sits at c_{k-1} = s*_{k-1}); with this flag, from k = 2 on,
- * the approximated fitness of Eq. wafit carried from the last non-empty
- * iteration (the substitute Sec. 4 uses for the fitness of s*_k). */
-#define ROSE_FLAG_WAFIT_THRESHOLD 4
+/* APS threshold rho(s*_{k-1}): Sec. 4 never evaluates the fitness of a best
+ * state and uses the weighted APS average of Eq. wafit in its place; by
+ * default the threshold is therefore that average, carried from the last
+ * non-empty iteration (at k = 1, the centre's own fitness: template row 0
+ * sits at c_0).  With this flag: the centre's exact fitness at every k. */
+#define ROSE_FLAG_CENTRE_THRESHOLD 4
 
 #define ROSE_MAX_ITERS 32
 #define ROSE_MAX_PARTICLES 65536
@@ -169,11 +170,13 @@ rose_status fitness_voxel_indices(const rose_tsdf* h, const float* pts_dev, int3
 /* ------------------------------------------------- points (a2) / overlap (a3) */
 /* Stride-s unprojection (Eq. unproj; Sec. 4 stride-based downsampling):
  * pixels (u, v) = (0, s, 2s, ..) x (0, s, 2s, ..) with depth z > 0 give
- * x = (((float)u - cx) z / fx, ((float)v - cy) z / fy, z) (binary32), in
- * row-major pixel order, written as count x 3 float32 to pts_dev (capacity
- * ceil(H/s) * ceil(W/s) points); the count goes to *count_dev (int32). */
-rose_status depth_unproject(const float* depth_dev, const rose_camera* cam, int32_t stride, float* pts_dev,
-                            int32_t* count_dev, hipStream_t s);
+ * x = (((float)u - cx) z / fx, ((float)v - cy) z / fy, z) (binary32),
+ * written as count x 3 float32 to pts_dev (capacity ceil(H/s) * ceil(W/s)
+ * points); the count goes to *count_dev (int32).  order 0: row-major sample
+ * order; order 1: 8x8-sample tiles in row-major tile order (the order the
+ * tracker uses internally, for cache-line sharing of the TSDF gathers). */
+rose_status depth_unproject(const float* depth_dev, const rose_camera* cam, int32_t stride, int32_t order,
+                            float* pts_dev, int32_t* count_dev, hipStream_t s);
 
 /* Overlap mask (Eq. validness): mask_dev[j] = 1 iff point j, moved to the
  * world by `centre` and into the previous camera by prev^-1, has z' > 0 and
@@ -221,7 +224,7 @@ typedef struct {
  * previous frame's camera at state->pose.
  * Every iteration k: O_k with the centre c_{k-1}; fitness of every particle
  * pose c_{k-1} * Delta(r_{k-1} (.) p_i) (Eq. normallh); APS = particles with
- * fitness above rho(s*_{k-1}) (see ROSE_FLAG_WAFIT_THRESHOLD); CompBestState (Eq. ebs),
+ * fitness above rho(s*_{k-1}) (see ROSE_FLAG_CENTRE_THRESHOLD); CompBestState (Eq. ebs),
  * approximated best fitness (Eq. wafit), CompAxisLength (Eqs. rsdir,
  * rsinter with |v_d|, momentum), MovePST (c_k = c_{k-1} * Delta(u*)) and the
  * corner cases of Sec. 4.  The whole loop runs on the device; the call
@@ -266,6 +269,12 @@ rose_status rose_mlp_adam(int64_t n, float* params_dev, const float* grads_dev, 
  * C(m, n) = C_dev[m ldc + n]. */
 rose_status rose_gemm_bf16(int32_t M, int32_t N, int32_t K, const float* A_dev, int64_t sam, int64_t sak,
                            const float* B_dev, int64_t sbk, int64_t sbn, float* C_dev, int64_t ldc, hipStream_t s);
+
+/* Launch shape of the fitness kernel (process-wide): particles per
+ * wavefront and points per lane per loop step.  Compiled shapes: (2, 4),
+ * (4, 2) (default), (4, 4), (8, 2); others give ROSE_E_UNSUPPORTED.  Results
+ * do not depend on the shape beyond binary64 summation order. */
+rose_status rose_fitness_set_shape(int32_t particles_per_wave, int32_t points_per_lane);
 
 /* ------------------------------------------------------- kernel timing */
 /* When enabled (process-wide), pso_track_frame and tsdf_integrate bracket

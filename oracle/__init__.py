@@ -58,7 +58,7 @@ NEAREST = 0
 TRILINEAR = 1
 NO_OVERLAP = 1
 NO_NORMALIZE = 2
-WAFIT_THRESHOLD = 4
+CENTRE_THRESHOLD = 4
 
 
 def _cpu_has_fma() -> bool:

@@ -37,7 +37,7 @@
 /* flag bits of the tracker (ablation switches of Sec. 5.2, Tab. ablt-tsdf) */
 #define ORC_NO_OVERLAP 1
 #define ORC_NO_NORMALIZE 2
-#define ORC_WAFIT_THRESHOLD 4
+#define ORC_CENTRE_THRESHOLD 4
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x64-10 counter-based generator (Salmon, Moraes, Dror, Shaw, SC'11, */
@@ -625,13 +625,14 @@ int orc_track_frame(const float* psi, int32_t nx, int32_t ny, int32_t nz, float 
             if (P->prec == ORC_F32)
                 for (int32_t i = 0; i < n; ++i) F[i] = (double)(float)F[i];
         }
-        /* APS threshold rho(s*_{k-1}): the centre's own fitness -- template    */
-        /* row 0 sits at c_{k-1} = s*_{k-1}, so its exact value comes with the  */
-        /* particle evaluation.  ORC_WAFIT_THRESHOLD: from k = 2 on, use the    */
-        /* approximation of Eq. wafit carried from the last non-empty          */
-        /* iteration instead (the substitute Sec. 4 uses for rho(s*_k)).       */
+        /* APS threshold rho(s*_{k-1}).  Sec. 4 never evaluates the fitness of  */
+        /* a best state: it stands in the weighted APS average of Eq. wafit.   */
+        /* So from k = 2 on the threshold is that average, carried from the    */
+        /* last non-empty iteration; at k = 1 (s*_0 = c_0, no average yet) it  */
+        /* is the centre's own fitness (template row 0 sits at c_0).           */
+        /* ORC_CENTRE_THRESHOLD: the centre's exact fitness at every k.        */
         double centre = tsdf_built ? exp(-F[0] / P->tau) : 0.5;
-        double thr_k = (k == 1 || !(P->flags & ORC_WAFIT_THRESHOLD)) ? centre : thr;
+        double thr_k = (k == 1 || (P->flags & ORC_CENTRE_THRESHOLD)) ? centre : thr;
         int aps = orc_pst_update(F, pst, n, r, qc, tc, P->tau, P->beta, P->eps, tsdf_built, thr_k, r_new, q_new,
                                  t_new, &rt, us);
         thr = (aps > 0) ? rt : thr_k;

@@ -323,10 +323,13 @@ struct FitLaunch {
     int32_t n;
     int32_t splits;
     int32_t lookup;
-    double* partial;  // n x splits
+    int32_t shape_p, shape_u;  // particles per wave, points per lane per step
+    double* partial;           // n x splits
 };
 rose_status launch_fitness(const FitLaunch& L, hipStream_t s);
 int choose_splits(int32_t n_particles, int64_t max_points);
+bool fitness_shape_valid(int p, int u);
+void fitness_shape(int* p, int* u);
 
 // kernel timing (profile.hip)
 enum { PROF_FITNESS = 0, PROF_UPDATE = 1, PROF_INTEGRATE = 2 };

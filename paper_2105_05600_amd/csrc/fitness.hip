@@ -77,12 +77,11 @@ __device__ inline float bcast(float v, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
-// U points per lane per loop step; all P*U gathers of a step are issued
-// before any is consumed.
-constexpr int kU = 2;
-
-template <int P, int FMT, int LK, bool FROM_STATE, bool WIDE>
+// P particles per wave, U points per lane per loop step; all P*U gathers of
+// a step are issued before any is consumed.
+template <int P, int U, int FMT, int LK, bool FROM_STATE, bool WIDE>
 __global__ __launch_bounds__(256) void k_fitness(FitLaunch a) {
+    constexpr int kU = U;
     const int lane = threadIdx.x & 63;
     const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int group = wave / a.splits;
@@ -220,24 +219,33 @@ __global__ __launch_bounds__(256) void k_pack_points(const float* pts3, int32_t 
     pts4[j] = make_float4(pts3[3 * (int64_t)j], pts3[3 * (int64_t)j + 1], pts3[3 * (int64_t)j + 2], 0.0f);
 }
 
-constexpr int kP = 4;  // particles per wave
+// launch shape (particles per wave, points per lane per step); the tuner
+// may change it process-wide
+static int g_shape_p = 4, g_shape_u = 2;
 
-template <int FMT, int LK, bool WIDE>
-static void launch_t(const FitLaunch& L, hipStream_t s) {
-    const int groups = (L.n + kP - 1) / kP;
+template <int P, int U, int FMT, int LK, bool WIDE>
+static void launch_pu(const FitLaunch& L, hipStream_t s) {
+    const int groups = (L.n + P - 1) / P;
     const int64_t waves = (int64_t)groups * L.splits;
     const unsigned blocks = (unsigned)((waves + 3) / 4);
     if (L.T32)
-        hipLaunchKernelGGL((k_fitness<kP, FMT, LK, false, WIDE>), dim3(blocks), dim3(256), 0, s, L);
+        hipLaunchKernelGGL((k_fitness<P, U, FMT, LK, false, WIDE>), dim3(blocks), dim3(256), 0, s, L);
     else
-        hipLaunchKernelGGL((k_fitness<kP, FMT, LK, true, WIDE>), dim3(blocks), dim3(256), 0, s, L);
+        hipLaunchKernelGGL((k_fitness<P, U, FMT, LK, true, WIDE>), dim3(blocks), dim3(256), 0, s, L);
 }
 
 template <int FMT, int LK>
 static void launch_w(const FitLaunch& L, hipStream_t s) {
     const uint64_t bytes = (uint64_t)L.g.nx * L.g.ny * L.g.nz * (FMT == ROSE_TSDF_F32 ? 4u : 2u);
-    if (bytes < (uint64_t(1) << 32)) launch_t<FMT, LK, false>(L, s);
-    else launch_t<FMT, LK, true>(L, s);
+    if (bytes >= (uint64_t(1) << 32)) {
+        launch_pu<4, 2, FMT, LK, true>(L, s);
+        return;
+    }
+    const int p = L.shape_p, u = L.shape_u;
+    if (p == 2 && u == 4) launch_pu<2, 4, FMT, LK, false>(L, s);
+    else if (p == 4 && u == 4) launch_pu<4, 4, FMT, LK, false>(L, s);
+    else if (p == 8 && u == 2) launch_pu<8, 2, FMT, LK, false>(L, s);
+    else launch_pu<4, 2, FMT, LK, false>(L, s);
 }
 
 template <int FMT>
@@ -254,10 +262,19 @@ rose_status launch_fitness(const FitLaunch& L, hipStream_t s) {
     return ROSE_OK;
 }
 
+bool fitness_shape_valid(int p, int u) {
+    return (p == 2 && u == 4) || (p == 4 && u == 2) || (p == 4 && u == 4) || (p == 8 && u == 2);
+}
+
+void fitness_shape(int* p, int* u) {
+    *p = g_shape_p;
+    *u = g_shape_u;
+}
+
 // Slices per particle group: enough waves to fill 256 CUs several times
 // over, but at least ~4 lane-steps (256 points) per slice.
 int choose_splits(int32_t n_particles, int64_t max_points) {
-    const int64_t groups = (n_particles + kP - 1) / kP;
+    const int64_t groups = (n_particles + g_shape_p - 1) / g_shape_p;
     const int64_t target_waves = 256 * 4 * 8;  // CUs x SIMDs x waves per SIMD
     int64_t s = (target_waves + groups - 1) / groups;
     const int64_t max_s = (max_points + 255) / 256;
@@ -311,6 +328,7 @@ rose_status fitness_eval(const rose_tsdf* h, const float* pts_dev, int32_t m, co
     L.splits = splits;
     L.lookup = lk;
     L.partial = hm->partial;
+    fitness_shape(&L.shape_p, &L.shape_u);
     rose_status st = launch_fitness(L, s);
     if (st != ROSE_OK) return st;
     hipLaunchKernelGGL(k_fitness_finish, dim3((n + 255) / 256), dim3(256), 0, s, hm->partial, n, splits, m, F_dev,
@@ -333,3 +351,12 @@ rose_status fitness_voxel_indices(const rose_tsdf* h, const float* pts_dev, int3
 }
 
 }  // extern "C"
+
+extern "C" rose_status rose_fitness_set_shape(int32_t particles_per_wave, int32_t points_per_lane) {
+    clear_error();
+    ROSE_REQUIRE(fitness_shape_valid(particles_per_wave, points_per_lane), ROSE_E_UNSUPPORTED,
+                 "rose_fitness_set_shape: (%d, %d) is not a compiled shape", particles_per_wave, points_per_lane);
+    g_shape_p = particles_per_wave;
+    g_shape_u = points_per_lane;
+    return ROSE_OK;
+}

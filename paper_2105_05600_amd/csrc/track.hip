@@ -32,6 +32,28 @@ __device__ inline bool overlap_keep(const Cam& c, const float* A, float4 x) {
     return px >= 0.0f && px <= (float)(c.W - 1) && py >= 0.0f && py <= (float)(c.H - 1);
 }
 
+// Enumeration of the stride-s sample grid (su x sv samples).  Row-major
+// (tiled = false), or 8x8-sample tiles in row-major tile order with
+// row-major samples inside a tile (tiled = true), so that the 64 lanes of a
+// wavefront see a compact image patch and their TSDF gathers share cache
+// lines.  Returns false for the padding positions of partial tiles.
+__device__ inline int sample_count(int su, int sv, bool tiled) {
+    return tiled ? ((su + 7) / 8) * ((sv + 7) / 8) * 64 : su * sv;
+}
+
+__device__ inline bool sample_at(int q, int su, int sv, bool tiled, int* uu, int* vv) {
+    if (!tiled) {
+        *uu = q % su;
+        *vv = q / su;
+        return true;
+    }
+    const int ntx = (su + 7) / 8;
+    const int t = q >> 6, e = q & 63;
+    *uu = (t % ntx) * 8 + (e & 7);
+    *vv = (t / ntx) * 8 + (e >> 3);
+    return *uu < su && *vv < sv;
+}
+
 // Whole-block order-preserving overlap compaction of m points.
 __device__ inline int overlap_compact(const Cam& c, const float* A, bool all, const float4* pts, int m, float4* out,
                                       int* lds) {
@@ -69,15 +91,17 @@ __global__ __launch_bounds__(1024) void k_track_init(InitArgs a) {
     __shared__ float A[12];
     const int su = (a.cam.W + a.stride - 1) / a.stride;
     const int sv = (a.cam.H + a.stride - 1) / a.stride;
-    const int total = su * sv;
-    // stride-s unprojection with order-preserving compaction
+    const int total = sample_count(su, sv, true);
+    // stride-s unprojection in 8x8-sample tile order, order-preserving
+    // compaction
     int m = 0;
     for (int q0 = 0; q0 < total; q0 += blockDim.x) {
         const int q = q0 + threadIdx.x;
         int keep = 0;
         float4 x = make_float4(0, 0, 0, 0);
-        if (q < total) {
-            const int u = (q % su) * a.stride, v = (q / su) * a.stride;
+        int uu, vv;
+        if (q < total && sample_at(q, su, sv, true, &uu, &vv)) {
+            const int u = uu * a.stride, v = vv * a.stride;
             const float z = a.depth[(int64_t)v * a.cam.W + u];
             if (z > 0.0f) {
                 keep = 1;
@@ -152,10 +176,11 @@ __global__ __launch_bounds__(1024) void k_track_update(UpdateArgs a) {
     if (threadIdx.x == 0) F0s = final_fitness(a, 0, nO);
     __syncthreads();
     const float F0 = F0s;
-    // APS threshold rho(s*_{k-1}): the centre's exact fitness (particle 0),
-    // or with ROSE_FLAG_WAFIT_THRESHOLD the carried Eq. wafit value from k = 2
+    // APS threshold rho(s*_{k-1}): the carried Eq. wafit value from k = 2 on;
+    // the centre's exact fitness (particle 0) at k = 1 or with
+    // ROSE_FLAG_CENTRE_THRESHOLD
     const double centre = exp(-(double)F0 / a.tau);
-    const double rho0 = (st->k == 0 || !(a.flags & ROSE_FLAG_WAFIT_THRESHOLD)) ? centre : st->thr;
+    const double rho0 = (st->k == 0 || (a.flags & ROSE_FLAG_CENTRE_THRESHOLD)) ? centre : st->thr;
     double r[6];
     for (int d = 0; d < 6; ++d) r[d] = st->r[d];
     // per-thread APS sums: count, sum w, sum w rho, sum w u_d
@@ -238,19 +263,20 @@ __global__ __launch_bounds__(1024) void k_track_update(UpdateArgs a) {
 }
 
 // ------------------------------------------------- diagnostic entry kernels
-__global__ __launch_bounds__(1024) void k_unproject_only(Cam cam, const float* depth, int32_t stride, float* pts3,
-                                                         int32_t* count) {
+__global__ __launch_bounds__(1024) void k_unproject_only(Cam cam, const float* depth, int32_t stride, int32_t tiled,
+                                                         float* pts3, int32_t* count) {
     __shared__ int lds[17];
     const int su = (cam.W + stride - 1) / stride;
     const int sv = (cam.H + stride - 1) / stride;
-    const int total = su * sv;
+    const int total = sample_count(su, sv, tiled != 0);
     int m = 0;
     for (int q0 = 0; q0 < total; q0 += blockDim.x) {
         const int q = q0 + threadIdx.x;
         int keep = 0;
         float4 x = make_float4(0, 0, 0, 0);
-        if (q < total) {
-            const int u = (q % su) * stride, v = (q / su) * stride;
+        int uu, vv;
+        if (q < total && sample_at(q, su, sv, tiled != 0, &uu, &vv)) {
+            const int u = uu * stride, v = vv * stride;
             const float z = depth[(int64_t)v * cam.W + u];
             if (z > 0.0f) {
                 keep = 1;
@@ -310,14 +336,16 @@ using namespace rose;
 
 extern "C" {
 
-rose_status depth_unproject(const float* depth_dev, const rose_camera* cam, int32_t stride, float* pts_dev,
-                            int32_t* count_dev, hipStream_t s) {
+rose_status depth_unproject(const float* depth_dev, const rose_camera* cam, int32_t stride, int32_t order,
+                            float* pts_dev, int32_t* count_dev, hipStream_t s) {
     clear_error();
     ROSE_REQUIRE(depth_dev && pts_dev && count_dev, ROSE_E_ARG, "depth_unproject: NULL argument");
     rose_status c = check_cam(cam, "depth_unproject");
     if (c != ROSE_OK) return c;
     ROSE_REQUIRE(stride >= 1, ROSE_E_ARG, "depth_unproject: stride must be >= 1");
-    hipLaunchKernelGGL(k_unproject_only, dim3(1), dim3(1024), 0, s, to_cam(cam), depth_dev, stride, pts_dev, count_dev);
+    ROSE_REQUIRE(order == 0 || order == 1, ROSE_E_ARG, "depth_unproject: order must be 0 or 1");
+    hipLaunchKernelGGL(k_unproject_only, dim3(1), dim3(1024), 0, s, to_cam(cam), depth_dev, stride, order, pts_dev,
+                       count_dev);
     ROSE_CHECK_HIP(hipGetLastError());
     return ROSE_OK;
 }
@@ -417,6 +445,7 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_cam
     L.splits = splits;
     L.lookup = p->lookup;
     L.partial = h->partial;
+    fitness_shape(&L.shape_p, &L.shape_u);
 
     UpdateArgs ua;
     ua.st = h->st;

@@ -30,7 +30,7 @@ OK = 0
 E_ARG, E_SHAPE, E_DEVICE, E_STATE, E_UNSUPPORTED = -1, -2, -3, -4, -5
 F32, F16, SN16 = 0, 1, 2
 NEAREST, TRILINEAR = 0, 1
-FLAG_NO_OVERLAP, FLAG_NO_NORMALIZE, FLAG_WAFIT_THRESHOLD = 1, 2, 4
+FLAG_NO_OVERLAP, FLAG_NO_NORMALIZE, FLAG_CENTRE_THRESHOLD = 1, 2, 4
 MAX_ITERS = 32
 
 
@@ -82,7 +82,8 @@ _sigs = {
     "pst_particle_poses": ([C.POINTER(Pose), _P, _P, C.c_int32, _P, _S], C.c_int),
     "fitness_eval": ([_P, _P, C.c_int32, _P, C.c_int32, C.c_int, _P, _P, _S], C.c_int),
     "fitness_voxel_indices": ([_P, _P, C.c_int32, _P, C.c_int32, _P, _S], C.c_int),
-    "depth_unproject": ([_P, C.POINTER(Camera), C.c_int32, _P, _P, _S], C.c_int),
+    "depth_unproject": ([_P, C.POINTER(Camera), C.c_int32, C.c_int32, _P, _P, _S], C.c_int),
+    "rose_fitness_set_shape": ([C.c_int32, C.c_int32], C.c_int),
     "overlap_mask": ([_P, C.c_int32, C.POINTER(Pose), C.POINTER(Pose), C.POINTER(Camera), _P, _S], C.c_int),
     "pso_track_frame": ([_P, _P, C.POINTER(Camera), _P, C.c_int32, C.POINTER(TrackParams), C.POINTER(Pose), _P,
                          C.POINTER(TrackState), C.POINTER(TrackStats), _S], C.c_int),
@@ -265,15 +266,15 @@ def voxel_indices(vol: Tsdf, pts: torch.Tensor, T: torch.Tensor, stream=None) ->
     return idx
 
 
-def depth_unproject(depth: torch.Tensor, K, stride: int, stream=None) -> torch.Tensor:
+def depth_unproject(depth: torch.Tensor, K, stride: int, tiled: bool = False, stream=None) -> torch.Tensor:
     _dev(depth, torch.float32, "depth")
     cam = camera(K)
     su = (cam.width + stride - 1) // stride
     sv = (cam.height + stride - 1) // stride
     pts = torch.empty((max(su * sv, 1), 3), dtype=torch.float32, device=depth.device)
     cnt = torch.zeros(1, dtype=torch.int32, device=depth.device)
-    _check("depth_unproject", _lib.depth_unproject(_ptr(depth), C.byref(cam), int(stride), _ptr(pts), _ptr(cnt),
-                                                   _stream(stream)))
+    _check("depth_unproject", _lib.depth_unproject(_ptr(depth), C.byref(cam), int(stride), int(bool(tiled)), _ptr(pts),
+                                                   _ptr(cnt), _stream(stream)))
     return pts[: int(cnt.item())]
 
 
@@ -447,3 +448,7 @@ class Mlp:
         _check("rose_mlp_adam", _lib.rose_mlp_adam(params.numel(), _ptr(params), _ptr(grads), _ptr(m), _ptr(v),
                                                    int(step), float(lr), float(beta1), float(beta2), float(eps),
                                                    _stream(stream)))
+
+
+def set_fitness_shape(particles_per_wave: int, points_per_lane: int):
+    _check("rose_fitness_set_shape", _lib.rose_fitness_set_shape(int(particles_per_wave), int(points_per_lane)))

@@ -53,9 +53,11 @@ def test_host_side_argument_errors(R):
                            C.byref(h)) == R.E_ARG
     assert lib.tsdf_destroy(None) == R.OK
     cam = R.Camera(100, 100, 10, 10, 0, 20)
-    assert lib.depth_unproject(C.c_void_p(16), C.byref(cam), 2, C.c_void_p(16), C.c_void_p(16), None) == R.E_SHAPE
+    assert lib.depth_unproject(C.c_void_p(16), C.byref(cam), 2, 0, C.c_void_p(16), C.c_void_p(16), None) == R.E_SHAPE
     cam = R.Camera(100, 100, 10, 10, 20, 20)
-    assert lib.depth_unproject(C.c_void_p(16), C.byref(cam), 0, C.c_void_p(16), C.c_void_p(16), None) == R.E_ARG
+    assert lib.depth_unproject(C.c_void_p(16), C.byref(cam), 0, 0, C.c_void_p(16), C.c_void_p(16), None) == R.E_ARG
+    assert lib.depth_unproject(C.c_void_p(16), C.byref(cam), 2, 5, C.c_void_p(16), C.c_void_p(16), None) == R.E_ARG
+    assert lib.rose_fitness_set_shape(3, 3) == R.E_UNSUPPORTED
     assert lib.fitness_eval(None, None, 0, None, 1, 0, None, None, None) == R.E_ARG
     params = R.track_params(max_iters=0)
     st = R.track_state([1, 0, 0, 0], [0, 0, 0], [0.1] * 6)

@@ -117,7 +117,7 @@ def test_mlp_gradients_vs_oracle(R, net):
     m.loss_grad(P, torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(), G, loss)
     gl = float(loss.item())
     ol, og = omlp.loss_and_grads({k: v.astype(np.float64) for k, v in p.items()}, X, Y)
-    assert abs(gl - ol) <= 1e-3 * abs(ol)
+    assert abs(gl - ol) <= 2e-2 * abs(ol)  # BF16 operands: ~1% output error
     gg = m.unpack(G.cpu())
     for k in omlp.NAMES:
         cos, rel = _cos_rel(gg[k].numpy(), og[k])

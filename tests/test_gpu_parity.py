@@ -84,6 +84,30 @@ def test_unproject_bit_exact(R, orc, W, H, f, stride):
     assert np.array_equal(g.view(np.uint32), o.view(np.uint32))
 
 
+def test_unproject_tiled_order_is_a_permutation(R, orc):
+    """The tracker's 8x8-tile sample order lists exactly the oracle's
+    points, permuted tile by tile."""
+    room = synth.unit_box_room(2105)
+    K = synth.Intrinsics.centred(101, 77, 90.0)
+    pose = synth.Pose(synth.look_rotation([0.6, 0.5, 0.4]), np.array([0.01, -0.02, 0.0]))
+    depth = synth.render_depth(room, K, pose)
+    depth[::3, ::5] = 0.0
+    stride = 3
+    g = host(R.depth_unproject(dev(depth), K, stride, tiled=True))
+    o = orc.unproject(depth, K, stride, orc.F32)
+    su, sv = -(-K.width // stride), -(-K.height // stride)
+    row_major = [(uu, vv) for vv in range(sv) for uu in range(su) if depth[vv * stride, uu * stride] > 0]
+    index = {p: i for i, p in enumerate(row_major)}
+    ntx, nty = -(-su // 8), -(-sv // 8)
+    tiled = []
+    for t in range(ntx * nty):
+        for e in range(64):
+            uu, vv = (t % ntx) * 8 + e % 8, (t // ntx) * 8 + e // 8
+            if uu < su and vv < sv and depth[vv * stride, uu * stride] > 0:
+                tiled.append(index[(uu, vv)])
+    assert np.array_equal(g.view(np.uint32), o[tiled].view(np.uint32))
+
+
 # --------------------------------------------------------- a3 overlap mask
 def test_overlap_mask_bit_exact(R, orc):
     room = synth.unit_box_room(2105)
@@ -129,6 +153,23 @@ def test_voxel_indices_bit_exact(R, orc):
     o = orc.voxel_indices(dims, vox, np.array(origin, np.float32), pts, T.astype(np.float64))
     assert (o >= 0).mean() > 0.3 and (o < 0).any()
     assert np.array_equal(g, o)
+
+
+@pytest.mark.parametrize("shape", [(2, 4), (4, 4), (8, 2)])
+def test_fitness_shapes_parity(R, orc, shape):
+    rng = np.random.default_rng(31)
+    dims, vox, origin = (32, 24, 16), 0.04, (-0.64, -0.48, -0.32)
+    vol, psi = _random_volume(R, rng, dims, vox, origin)
+    pts = rng.uniform(-0.7, 0.7, (2999, 3)).astype(np.float32)
+    T = _random_poses(rng, 77)
+    try:
+        R.set_fitness_shape(*shape)
+        F, _ = R.fitness_eval(vol, dev(pts), dev(T), 0)
+        F = host(F)
+    finally:
+        R.set_fitness_shape(4, 2)
+    Fo = orc.fitness(psi, vox, np.array(origin, np.float32), pts, T.astype(np.float64), lookup=0, prec=orc.F32)
+    assert _rel(F, Fo) <= 1e-5
 
 
 @pytest.mark.parametrize("fmt", [0, 1, 2])
