@@ -83,9 +83,14 @@ template <int P, int U, int FMT, int LK, bool FROM_STATE, bool WIDE>
 __global__ __launch_bounds__(256) void k_fitness(FitLaunch a) {
     constexpr int kU = U;
     const int lane = threadIdx.x & 63;
-    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int group = wave / a.splits;
-    const int split = wave - group * a.splits;
+    // XCD-aware mapping: consecutive workgroups go to the 8 XCDs in turn, so
+    // with the slice index = workgroup index mod splits (splits a multiple of
+    // 8) every XCD works on a fixed 1/8 of the point list and its L2 only
+    // holds the voxels around those points.  The 4 waves of a workgroup take
+    // 4 consecutive particle groups of the same slice (shared point loads
+    // and nearby gathers in the CU's L1).
+    const int split = blockIdx.x % a.splits;
+    const int group = (blockIdx.x / a.splits) * 4 + (threadIdx.x >> 6);
     const int p0 = group * P;
     if (p0 >= a.n) return;
     if (FROM_STATE && a.st->stopped) return;
@@ -125,14 +130,26 @@ __global__ __launch_bounds__(256) void k_fitness(FitLaunch a) {
     double acc[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) acc[p] = 0.0;
+    // the next step's points are loaded one step ahead, so their latency
+    // overlaps the current step's gathers
+    float4 xn[kU];
+    bool okn[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        const int j = j0 + u * kWave + lane;
+        okn[u] = j < j1;
+        xn[u] = a.pts[okn[u] ? j : (j1 > j0 ? j0 : 0)];
+    }
     for (int jb = j0; jb < j1; jb += kWave * kU) {
         float4 x[kU];
         bool ok[kU];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
-            const int j = jb + u * kWave + lane;
-            ok[u] = j < j1;
-            x[u] = a.pts[ok[u] ? j : j0];
+            x[u] = xn[u];
+            ok[u] = okn[u];
+            const int j = jb + kWave * kU + u * kWave + lane;
+            okn[u] = j < j1;
+            xn[u] = a.pts[okn[u] ? j : j0];
         }
         float v[kU][P];
         if constexpr (LK == ROSE_LOOKUP_NEAREST) {
@@ -226,8 +243,7 @@ static int g_shape_p = 4, g_shape_u = 2;
 template <int P, int U, int FMT, int LK, bool WIDE>
 static void launch_pu(const FitLaunch& L, hipStream_t s) {
     const int groups = (L.n + P - 1) / P;
-    const int64_t waves = (int64_t)groups * L.splits;
-    const unsigned blocks = (unsigned)((waves + 3) / 4);
+    const unsigned blocks = (unsigned)(((groups + 3) / 4) * L.splits);
     if (L.T32)
         hipLaunchKernelGGL((k_fitness<P, U, FMT, LK, false, WIDE>), dim3(blocks), dim3(256), 0, s, L);
     else
@@ -245,6 +261,7 @@ static void launch_w(const FitLaunch& L, hipStream_t s) {
     if (p == 2 && u == 4) launch_pu<2, 4, FMT, LK, false>(L, s);
     else if (p == 4 && u == 4) launch_pu<4, 4, FMT, LK, false>(L, s);
     else if (p == 8 && u == 2) launch_pu<8, 2, FMT, LK, false>(L, s);
+    else if (p == 8 && u == 4) launch_pu<8, 4, FMT, LK, false>(L, s);
     else launch_pu<4, 2, FMT, LK, false>(L, s);
 }
 
@@ -263,7 +280,7 @@ rose_status launch_fitness(const FitLaunch& L, hipStream_t s) {
 }
 
 bool fitness_shape_valid(int p, int u) {
-    return (p == 2 && u == 4) || (p == 4 && u == 2) || (p == 4 && u == 4) || (p == 8 && u == 2);
+    return (p == 2 && u == 4) || (p == 4 && u == 2) || (p == 4 && u == 4) || (p == 8 && u == 2) || (p == 8 && u == 4);
 }
 
 void fitness_shape(int* p, int* u) {
@@ -271,16 +288,14 @@ void fitness_shape(int* p, int* u) {
     *u = g_shape_u;
 }
 
-// Slices per particle group: enough waves to fill 256 CUs several times
-// over, but at least ~4 lane-steps (256 points) per slice.
+// Point slices: a multiple of the 8 XCDs (see k_fitness), raised while the
+// grid holds fewer waves than the chip runs at once and each slice still
+// has at least ~4 lane-steps (256 points).
 int choose_splits(int32_t n_particles, int64_t max_points) {
     const int64_t groups = (n_particles + g_shape_p - 1) / g_shape_p;
     const int64_t target_waves = 256 * 4 * 8;  // CUs x SIMDs x waves per SIMD
-    int64_t s = (target_waves + groups - 1) / groups;
-    const int64_t max_s = (max_points + 255) / 256;
-    if (s > max_s) s = max_s;
-    if (s < 1) s = 1;
-    if (s > 64) s = 64;
+    int64_t s = 8;
+    while (s < 64 && groups * s < target_waves && max_points / (2 * s) >= 256) s *= 2;
     return (int)s;
 }
 

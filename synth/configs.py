@@ -11,7 +11,8 @@ follow the speed ranges the paper reports for its synthetic fast-motion set
   frame is offset from the last fused view by 5 cm and 3 degrees.
 * room_sequence(): a 300-frame 640x480 (f = 525) sequence at 30 fps,
   3 m/s and 2 rad/s, through a procedural room of boxes, cylinders and
-  spheres, depth noise sigma = 0.002 z^2, for a 512^3 TSDF at 1 cm.
+  spheres, depth noise sigma = 0.002 z^2, for a 512^3 TSDF at 1 cm with a
+  15 cm truncation band.
 """
 from __future__ import annotations
 
@@ -190,9 +191,9 @@ def fast_trajectory(scene: Scene, seed: int, n_frames: int, fps: float, speed: f
 def room_sequence(scene_seed: int = 7, traj_seed: int = 11, noise_seed: int = 13, n_frames: int = 300,
                   fps: float = 30.0, speed: float = 3.0, ang_speed: float = 2.0, width: int = 640,
                   height: int = 480, f: float = 525.0, dim: int = 512, vox: float = 0.01, stride: int = 4,
-                  n_particles: int = 10240, iters: int = 20) -> Sequence:
+                  n_particles: int = 10240, iters: int = 20, mu: float = 0.15) -> Sequence:
     scene = procedural_room(scene_seed)
     K = Intrinsics.centred(width, height, f * width / 640.0)
     poses = fast_trajectory(scene, traj_seed, n_frames, fps, speed, ang_speed)
-    return Sequence(scene, K, (dim, dim, dim), vox, np.zeros(3), 0.06, poses, noise_seed, 0.002, 0.2, 6.0,
+    return Sequence(scene, K, (dim, dim, dim), vox, np.zeros(3), mu, poses, noise_seed, 0.002, 0.2, 6.0,
                     stride, n_particles, iters)
