@@ -184,6 +184,28 @@ rose_status depth_unproject(const float* depth_dev, const rose_camera* cam, int3
 rose_status overlap_mask(const float* pts_dev, int32_t m, const rose_pose* centre, const rose_pose* prev,
                          const rose_camera* cam, uint8_t* mask_dev, hipStream_t s);
 
+/* --------------------------------------- learned-proposal inputs (a10) */
+/* Render the TSDF at camera pose T_wc through the given (low-resolution)
+ * intrinsics: for each pixel the ray is sampled at z = near + k step
+ * (z-depth) with trilinear psi; the first pair of consecutive samples with
+ * psi_k > 0 >= psi_{k+1}, both within the truncation band (|psi| < 1),
+ * gives z* = z_k + step psi_k / (psi_k - psi_{k+1}); none: 0.  Binary64
+ * geometry.  depth_out_dev: height x width float32.  At most 2^20 pixels
+ * and 1e6 steps per ray. */
+rose_status tsdf_raycast(const rose_tsdf* h, const rose_pose* T_wc, const rose_camera* cam, double near_m,
+                         double far_m, double step_m, float* depth_out_dev, hipStream_t s);
+
+/* Feature vector of the learned proposal (dim >= w*h + 6 floats):
+ * element i < w*h (low-res pixel (u, v), row-major) is the depth residual
+ * clamp(D(scale u + scale/2, scale v + scale/2) - render(u, v), -0.5, 0.5)
+ * where both depths are > 0, else 0; the next 6 are `velocity` (the previous
+ * inter-frame motion in the chart of Sec. 3.3); the rest are 0.
+ * depth_dev: full-resolution frame (cam); render_dev: tsdf_raycast output
+ * (cam_low). */
+rose_status proposal_features(const float* depth_dev, const rose_camera* cam, const float* render_dev,
+                              const rose_camera* cam_low, int32_t scale, const double velocity[6], int32_t dim,
+                              float* features_dev, hipStream_t s);
+
 /* ---------------------------------------------------- per-frame tracking */
 typedef struct {
     int32_t max_iters;  /* 1..ROSE_MAX_ITERS (paper: 20) */
@@ -210,7 +232,7 @@ typedef struct {
     int32_t iters;          /* iterations run */
     int32_t n_points;       /* valid subsampled points */
     int32_t n_overlap_last; /* |O_k| of the last iteration */
-    int32_t reserved;
+    int32_t status;         /* pso_batch_track: per-sequence status (ROSE_E_STATE: no valid depth) */
     int32_t aps_size[ROSE_MAX_ITERS];
     int32_t n_overlap[ROSE_MAX_ITERS]; /* |O_k| per iteration */
     double rho_iter[ROSE_MAX_ITERS];   /* rho~ per iteration (rho of the centre when the APS is empty) */
@@ -237,6 +259,33 @@ typedef struct {
 rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_camera* cam, const float* pst_dev,
                             int32_t n_particles, const rose_track_params* p, const rose_pose* init_centre,
                             const double* init_r, rose_track_state* state, rose_track_stats* stats, hipStream_t s);
+
+/* ------------------------------------------------- batched tracking (a14) */
+/* Many independent sequences (each its own TSDF handle, camera, template,
+ * particle count and parameters) tracked in lockstep, one frame step per
+ * pso_batch_track call, with the same per-sequence semantics as
+ * pso_track_frame.  Per frame step the device work is: one unprojection /
+ * overlap launch (one workgroup per sequence), then per iteration one
+ * persistent fitness launch over all sequences and one update launch, then
+ * one launch copying the states to pinned host memory; with use_graph != 0
+ * and a non-null stream it is captured into a HIP graph on the first call
+ * and replayed afterwards (new inputs are read from pinned host memory).
+ * The fitness launch shape is the one set by rose_fitness_set_shape when the
+ * batch is created ((4,2), (8,2) or (4,4); otherwise (4,2)).  Volumes must be
+ * below 4 GB.  The handles must stay alive and must not be tracked through
+ * another path while the batch exists. */
+typedef struct rose_batch rose_batch;
+rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_camera* cams,
+                             const float* const* pst_devs, const int32_t* n_particles,
+                             const rose_track_params* params, int32_t use_graph, rose_batch** out);
+/* depth_devs[count]; init_centres (count poses) and init_rs (count x 6) may be
+ * NULL (each sequence then starts from its state, as in pso_track_frame);
+ * states[count] in/out; stats[count] (nullable) receive per-sequence status.
+ * Synchronises `s` once. */
+rose_status pso_batch_track(rose_batch* b, const float* const* depth_devs, const rose_pose* init_centres,
+                            const double* init_rs, rose_track_state* states, rose_track_stats* stats,
+                            hipStream_t s);
+rose_status pso_batch_destroy(rose_batch* b);
 
 /* ------------------------------------------- learned proposal network */
 /* A 3-layer perceptron in -> hid (GELU) -> hid (GELU) -> 12, output

@@ -249,6 +249,15 @@ struct DevState {
     double rho_iter[ROSE_MAX_ITERS];
 };
 
+// per-frame inputs of one tracked sequence
+struct FrameIn {
+    double qc[4], tc[3], r[6];  // PST centre c_0 and axis lengths r_0
+    double Tprev[12];           // previous frame's final pose (overlap reference)
+    const float* depth;         // current depth frame
+    int32_t active;             // 0: nothing to do for this sequence
+    int32_t pad;
+};
+
 // --------------------------------------------------------- wave primitives
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -330,6 +339,9 @@ rose_status launch_fitness(const FitLaunch& L, hipStream_t s);
 int choose_splits(int32_t n_particles, int64_t max_points);
 bool fitness_shape_valid(int p, int u);
 void fitness_shape(int* p, int* u);
+int fitness_blocks(const FitLaunch& L, int P);
+rose_status launch_fitness_batch(const FitLaunch* seqs_dev, const int* begin_dev, int count, int total, int grid,
+                                 int P, int U, hipStream_t s);
 
 // kernel timing (profile.hip)
 enum { PROF_FITNESS = 0, PROF_UPDATE = 1, PROF_INTEGRATE = 2 };

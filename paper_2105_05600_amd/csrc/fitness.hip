@@ -80,7 +80,7 @@ __device__ inline float bcast(float v, int lane) {
 // P particles per wave, U points per lane per loop step; all P*U gathers of
 // a step are issued before any is consumed.
 template <int P, int U, int FMT, int LK, bool FROM_STATE, bool WIDE>
-__global__ __launch_bounds__(256) void k_fitness(FitLaunch a) {
+__device__ void fitness_body(const FitLaunch& a, const int blk) {
     constexpr int kU = U;
     const int lane = threadIdx.x & 63;
     // XCD-aware mapping: consecutive workgroups go to the 8 XCDs in turn, so
@@ -89,8 +89,8 @@ __global__ __launch_bounds__(256) void k_fitness(FitLaunch a) {
     // holds the voxels around those points.  The 4 waves of a workgroup take
     // 4 consecutive particle groups of the same slice (shared point loads
     // and nearby gathers in the CU's L1).
-    const int split = blockIdx.x % a.splits;
-    const int group = (blockIdx.x / a.splits) * 4 + (threadIdx.x >> 6);
+    const int split = blk % a.splits;
+    const int group = (blk / a.splits) * 4 + (threadIdx.x >> 6);
     const int p0 = group * P;
     if (p0 >= a.n) return;
     if (FROM_STATE && a.st->stopped) return;
@@ -198,6 +198,60 @@ __global__ __launch_bounds__(256) void k_fitness(FitLaunch a) {
         for (int p = 0; p < P; ++p)
             if (p0 + p < a.n) a.partial[(int64_t)(p0 + p) * a.splits + split] = acc[p];
     }
+}
+
+template <int P, int U, int FMT, int LK, bool FROM_STATE, bool WIDE>
+__global__ __launch_bounds__(256) void k_fitness(FitLaunch a) {
+    fitness_body<P, U, FMT, LK, FROM_STATE, WIDE>(a, blockIdx.x);
+}
+
+int fitness_blocks(const FitLaunch& L, int P) { return ((L.n + P - 1) / P + 3) / 4 * L.splits; }
+
+__device__ inline int fitness_blocks_dev(const FitLaunch& L, int P) { return ((L.n + P - 1) / P + 3) / 4 * L.splits; }
+
+// Persistent fitness over many tracked sequences: a grid of at most a few
+// workgroups per CU walks the concatenated work lists (sequence i owns items
+// [begin[i], begin[i+1]), each begin a multiple of 8 and the grid a multiple
+// of 8, so an item's XCD is its index mod 8 and the slice <-> XCD pairing of
+// k_fitness holds for every sequence).
+template <int P, int U>
+__global__ __launch_bounds__(256) void k_fitness_batch(const FitLaunch* seqs, const int* begin, int count, int total) {
+    for (int w = blockIdx.x; w < total; w += gridDim.x) {
+        int lo = 0, hi = count;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (begin[mid] <= w) lo = mid;
+            else hi = mid;
+        }
+        const FitLaunch& L = seqs[lo];
+        const int blk = w - begin[lo];
+        if (blk >= fitness_blocks_dev(L, P)) continue;
+        if (L.g.fmt == ROSE_TSDF_F32) {
+            if (L.lookup == ROSE_LOOKUP_TRILINEAR)
+                fitness_body<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_TRILINEAR, true, false>(L, blk);
+            else
+                fitness_body<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_NEAREST, true, false>(L, blk);
+        } else if (L.g.fmt == ROSE_TSDF_F16) {
+            if (L.lookup == ROSE_LOOKUP_TRILINEAR)
+                fitness_body<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_TRILINEAR, true, false>(L, blk);
+            else
+                fitness_body<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_NEAREST, true, false>(L, blk);
+        } else {
+            if (L.lookup == ROSE_LOOKUP_TRILINEAR)
+                fitness_body<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_TRILINEAR, true, false>(L, blk);
+            else
+                fitness_body<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_NEAREST, true, false>(L, blk);
+        }
+    }
+}
+
+rose_status launch_fitness_batch(const FitLaunch* seqs_dev, const int* begin_dev, int count, int total, int grid,
+                                 int P, int U, hipStream_t s) {
+    if (P == 8 && U == 2) hipLaunchKernelGGL((k_fitness_batch<8, 2>), dim3(grid), dim3(256), 0, s, seqs_dev, begin_dev, count, total);
+    else if (P == 4 && U == 4) hipLaunchKernelGGL((k_fitness_batch<4, 4>), dim3(grid), dim3(256), 0, s, seqs_dev, begin_dev, count, total);
+    else hipLaunchKernelGGL((k_fitness_batch<4, 2>), dim3(grid), dim3(256), 0, s, seqs_dev, begin_dev, count, total);
+    ROSE_CHECK_HIP(hipGetLastError());
+    return ROSE_OK;
 }
 
 // fitness_eval second pass: F_i = sum of slices / m (m = 0: F = 1)

@@ -74,26 +74,31 @@ __device__ inline int overlap_compact(const Cam& c, const float* A, bool all, co
     return base;
 }
 
-struct InitArgs {
+struct InitStatic {
     DevState* st;
     Cam cam;
-    const float* depth;
     int32_t stride;
     int32_t flags;
-    double qc[4], tc[3], r[6];
-    double Tprev[12];
     float4* pts;
     float4* pts_o;
 };
 
-__global__ __launch_bounds__(1024) void k_track_init(InitArgs a) {
+// Unprojection of the frame (8x8-sample tile order, order-preserving
+// compaction), device-state initialisation and the first overlap set.
+__device__ void track_init_body(const InitStatic& a, const FrameIn& in) {
     __shared__ int lds[17];
     __shared__ float A[12];
+    if (!in.active) {
+        if (threadIdx.x == 0) {
+            a.st->stopped = 1;
+            a.st->k = 0;
+            a.st->n_points = -1;
+        }
+        return;
+    }
     const int su = (a.cam.W + a.stride - 1) / a.stride;
     const int sv = (a.cam.H + a.stride - 1) / a.stride;
     const int total = sample_count(su, sv, true);
-    // stride-s unprojection in 8x8-sample tile order, order-preserving
-    // compaction
     int m = 0;
     for (int q0 = 0; q0 < total; q0 += blockDim.x) {
         const int q = q0 + threadIdx.x;
@@ -102,7 +107,7 @@ __global__ __launch_bounds__(1024) void k_track_init(InitArgs a) {
         int uu, vv;
         if (q < total && sample_at(q, su, sv, true, &uu, &vv)) {
             const int u = uu * a.stride, v = vv * a.stride;
-            const float z = a.depth[(int64_t)v * a.cam.W + u];
+            const float z = in.depth[(int64_t)v * a.cam.W + u];
             if (z > 0.0f) {
                 keep = 1;
                 x = unproject_px(a.cam, u, v, z);
@@ -115,11 +120,11 @@ __global__ __launch_bounds__(1024) void k_track_init(InitArgs a) {
     }
     if (threadIdx.x == 0) {
         DevState* s = a.st;
-        for (int i = 0; i < 4; ++i) s->qc[i] = a.qc[i];
-        for (int i = 0; i < 3; ++i) s->tc[i] = a.tc[i];
-        for (int i = 0; i < 6; ++i) s->r[i] = a.r[i];
-        for (int i = 0; i < 6; ++i) s->r1[i] = a.r[i];
-        for (int i = 0; i < 12; ++i) s->Tprev[i] = a.Tprev[i];
+        for (int i = 0; i < 4; ++i) s->qc[i] = in.qc[i];
+        for (int i = 0; i < 3; ++i) s->tc[i] = in.tc[i];
+        for (int i = 0; i < 6; ++i) s->r[i] = in.r[i];
+        for (int i = 0; i < 6; ++i) s->r1[i] = in.r[i];
+        for (int i = 0; i < 12; ++i) s->Tprev[i] = in.Tprev[i];
         s->rho_last = 0.5;
         s->thr = 0.0;
         s->k = 0;
@@ -130,13 +135,26 @@ __global__ __launch_bounds__(1024) void k_track_init(InitArgs a) {
         s->n_overlap = 0;
         s->status = 0;
         double Tc[12], Ad[12];
-        pose_matrix(a.qc, a.tc, Tc);
-        relative_transform(a.Tprev, Tc, Ad);
+        pose_matrix(in.qc, in.tc, Tc);
+        relative_transform(in.Tprev, Tc, Ad);
         for (int i = 0; i < 12; ++i) A[i] = (float)Ad[i];
     }
     __syncthreads();
     const int nO = overlap_compact(a.cam, A, (a.flags & ROSE_FLAG_NO_OVERLAP) != 0, a.pts, m, a.pts_o, lds);
     if (threadIdx.x == 0) a.st->n_overlap = nO;
+}
+
+__global__ __launch_bounds__(1024) void k_track_init(InitStatic a, FrameIn in) { track_init_body(a, in); }
+
+// one workgroup per sequence; the per-frame inputs are read from pinned host
+// memory (so that a captured graph replays with new inputs)
+__global__ __launch_bounds__(1024) void k_track_init_batch(const InitStatic* a, const FrameIn* in_host) {
+    __shared__ FrameIn fin;
+    constexpr int kWords = sizeof(FrameIn) / sizeof(uint64_t);
+    if (threadIdx.x < kWords)
+        ((uint64_t*)&fin)[threadIdx.x] = ((const volatile uint64_t*)&in_host[blockIdx.x])[threadIdx.x];
+    __syncthreads();
+    track_init_body(a[blockIdx.x], fin);
 }
 
 struct UpdateArgs {
@@ -164,7 +182,7 @@ __device__ inline float final_fitness(const UpdateArgs& a, int i, int nO) {
     return (float)f;
 }
 
-__global__ __launch_bounds__(1024) void k_track_update(UpdateArgs a) {
+__device__ void track_update_body(const UpdateArgs& a) {
     __shared__ int lds[17];
     __shared__ double red[16][9];
     __shared__ float F0s;
@@ -260,6 +278,17 @@ __global__ __launch_bounds__(1024) void k_track_update(UpdateArgs a) {
     if (!go_on) return;
     const int nO2 = overlap_compact(a.cam, A, (a.flags & ROSE_FLAG_NO_OVERLAP) != 0, a.pts, st->n_points, a.pts_o, lds);
     if (threadIdx.x == 0) st->n_overlap = nO2;
+}
+
+__global__ __launch_bounds__(1024) void k_track_update(UpdateArgs a) { track_update_body(a); }
+
+__global__ __launch_bounds__(1024) void k_track_update_batch(const UpdateArgs* a) { track_update_body(a[blockIdx.x]); }
+
+// copy every sequence's device state to pinned host memory
+__global__ __launch_bounds__(64) void k_track_finish_batch(DevState* const* st, DevState* out_host) {
+    const uint32_t* src = (const uint32_t*)st[blockIdx.x];
+    uint32_t* dst = (uint32_t*)&out_host[blockIdx.x];
+    for (int i = threadIdx.x; i < (int)(sizeof(DevState) / 4); i += blockDim.x) dst[i] = src[i];
 }
 
 // ------------------------------------------------- diagnostic entry kernels
@@ -419,19 +448,22 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_cam
     if (!h->st) ROSE_CHECK_HIP(hipMalloc(&h->st, sizeof(DevState)));
     if (!h->st_host) ROSE_CHECK_HIP(hipHostMalloc(&h->st_host, sizeof(DevState), hipHostMallocDefault));
 
-    InitArgs ia;
+    InitStatic ia;
     ia.st = h->st;
     ia.cam = to_cam(cam);
-    ia.depth = depth_dev;
     ia.stride = p->stride;
     ia.flags = p->flags;
-    for (int i = 0; i < 4; ++i) ia.qc[i] = c0->q[i];
-    for (int i = 0; i < 3; ++i) ia.tc[i] = c0->t[i];
-    for (int i = 0; i < 6; ++i) ia.r[i] = r0[i];
-    pose_matrix(state->pose.q, state->pose.t, ia.Tprev);
     ia.pts = h->pts;
     ia.pts_o = h->pts_o;
-    hipLaunchKernelGGL(k_track_init, dim3(1), dim3(1024), 0, s, ia);
+    FrameIn fin;
+    for (int i = 0; i < 4; ++i) fin.qc[i] = c0->q[i];
+    for (int i = 0; i < 3; ++i) fin.tc[i] = c0->t[i];
+    for (int i = 0; i < 6; ++i) fin.r[i] = r0[i];
+    pose_matrix(state->pose.q, state->pose.t, fin.Tprev);
+    fin.depth = depth_dev;
+    fin.active = 1;
+    fin.pad = 0;
+    hipLaunchKernelGGL(k_track_init, dim3(1), dim3(1024), 0, s, ia, fin);
     ROSE_CHECK_HIP(hipGetLastError());
 
     FitLaunch L{};
@@ -497,6 +529,288 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_cam
             stats->aps_size[k] = r.aps[k];
             stats->n_overlap[k] = r.n_overlap_iter[k];
             stats->rho_iter[k] = r.rho_iter[k];
+        }
+    }
+    return ROSE_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batching
+// Many sequences tracked in lockstep: per frame step one init launch (one
+// workgroup per sequence), then per iteration one persistent fitness launch
+// over every sequence's work and one update launch (one workgroup per
+// sequence), then one launch copying the states to pinned host memory.  The
+// sequence of launches is captured once into a HIP graph and replayed every
+// frame step; per-frame inputs are read by the init kernel from pinned host
+// memory, so the graph itself never changes.
+#include <vector>
+
+struct rose_batch {
+    int32_t count = 0, K = 0, P = 4, U = 2, grid = 8, total = 0;
+    bool use_graph = true;
+    std::vector<rose_tsdf*> h;
+    std::vector<rose_track_params> params;
+    std::vector<int32_t> n;
+    FitLaunch* fit_dev = nullptr;
+    int* begin_dev = nullptr;
+    InitStatic* init_dev = nullptr;
+    UpdateArgs* upd_dev = nullptr;
+    DevState** stp_dev = nullptr;
+    FrameIn* in_host = nullptr;
+    DevState* out_host = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t graph_stream = nullptr;
+};
+
+static void batch_free(rose_batch* b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->fit_dev) (void)hipFree(b->fit_dev);
+    if (b->begin_dev) (void)hipFree(b->begin_dev);
+    if (b->init_dev) (void)hipFree(b->init_dev);
+    if (b->upd_dev) (void)hipFree(b->upd_dev);
+    if (b->stp_dev) (void)hipFree(b->stp_dev);
+    if (b->in_host) (void)hipHostFree(b->in_host);
+    if (b->out_host) (void)hipHostFree(b->out_host);
+    delete b;
+}
+
+static rose_status batch_enqueue(rose_batch* b, hipStream_t s) {
+    hipLaunchKernelGGL(k_track_init_batch, dim3(b->count), dim3(1024), 0, s, b->init_dev, b->in_host);
+    ROSE_CHECK_HIP(hipGetLastError());
+    for (int k = 0; k < b->K; ++k) {
+        rose_status st = launch_fitness_batch(b->fit_dev, b->begin_dev, b->count, b->total, b->grid, b->P, b->U, s);
+        if (st != ROSE_OK) return st;
+        hipLaunchKernelGGL(k_track_update_batch, dim3(b->count), dim3(1024), 0, s, b->upd_dev);
+        ROSE_CHECK_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_track_finish_batch, dim3(b->count), dim3(64), 0, s, b->stp_dev, b->out_host);
+    ROSE_CHECK_HIP(hipGetLastError());
+    return ROSE_OK;
+}
+
+extern "C" {
+
+rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_camera* cams,
+                             const float* const* pst_devs, const int32_t* n_particles,
+                             const rose_track_params* params, int32_t use_graph, rose_batch** out) {
+    clear_error();
+    ROSE_REQUIRE(out && tsdfs && cams && pst_devs && n_particles && params, ROSE_E_ARG,
+                 "pso_batch_create: NULL argument");
+    *out = nullptr;
+    ROSE_REQUIRE(count >= 1 && count <= 4096, ROSE_E_ARG, "pso_batch_create: count = %d out of [1, 4096]", count);
+    for (int i = 0; i < count; ++i) {
+        ROSE_REQUIRE(tsdfs[i] && pst_devs[i], ROSE_E_ARG, "pso_batch_create: NULL handle or template %d", i);
+        rose_status c = check_cam(&cams[i], "pso_batch_create");
+        if (c != ROSE_OK) return c;
+        ROSE_REQUIRE(n_particles[i] >= 1 && n_particles[i] <= ROSE_MAX_PARTICLES, ROSE_E_ARG,
+                     "pso_batch_create: n_particles[%d] = %d out of range", i, n_particles[i]);
+        const rose_track_params& p = params[i];
+        ROSE_REQUIRE(p.max_iters >= 1 && p.max_iters <= ROSE_MAX_ITERS && p.stride >= 1 &&
+                         (p.lookup == ROSE_LOOKUP_NEAREST || p.lookup == ROSE_LOOKUP_TRILINEAR) && p.tau > 0.0 &&
+                         p.beta >= 0.0 && p.beta <= 1.0,
+                     ROSE_E_ARG, "pso_batch_create: bad parameters for sequence %d", i);
+        const uint64_t bytes =
+            (uint64_t)tsdfs[i]->g.nx * tsdfs[i]->g.ny * tsdfs[i]->g.nz * (tsdfs[i]->g.fmt == ROSE_TSDF_F32 ? 4u : 2u);
+        ROSE_REQUIRE(bytes < (uint64_t(1) << 32), ROSE_E_UNSUPPORTED,
+                     "pso_batch_create: volume %d is 4 GB or larger (use pso_track_frame)", i);
+        for (int j = 0; j < i; ++j)
+            ROSE_REQUIRE(tsdfs[j] != tsdfs[i], ROSE_E_ARG, "pso_batch_create: handle %d repeated", i);
+    }
+    rose_batch* b = new rose_batch();
+    b->count = count;
+    b->use_graph = use_graph != 0;
+    int P, U;
+    fitness_shape(&P, &U);
+    if (!((P == 4 && U == 2) || (P == 8 && U == 2) || (P == 4 && U == 4))) {
+        P = 4;
+        U = 2;
+    }
+    b->P = P;
+    b->U = U;
+    std::vector<FitLaunch> fit(count);
+    std::vector<int> begin(count + 1, 0);
+    std::vector<InitStatic> init(count);
+    std::vector<UpdateArgs> upd(count);
+    std::vector<DevState*> stp(count);
+    rose_status g = ROSE_OK;
+    for (int i = 0; i < count && g == ROSE_OK; ++i) {
+        rose_tsdf* h = tsdfs[i];
+        const rose_track_params& p = params[i];
+        const int su = (cams[i].width + p.stride - 1) / p.stride;
+        const int sv = (cams[i].height + p.stride - 1) / p.stride;
+        const int64_t mmax = (int64_t)su * sv;
+        const int splits = choose_splits(n_particles[i], mmax);
+        if ((g = grow(&h->pts, &h->cap_points, mmax)) != ROSE_OK) break;
+        if ((g = grow(&h->pts_o, &h->cap_points_o, mmax)) != ROSE_OK) break;
+        if ((g = grow(&h->partial, &h->cap_partial, (int64_t)n_particles[i] * splits)) != ROSE_OK) break;
+        if ((g = grow(&h->F, &h->cap_particles, (int64_t)n_particles[i])) != ROSE_OK) break;
+        if (!h->st && hipMalloc(&h->st, sizeof(DevState)) != hipSuccess) {
+            set_error("pso_batch_create: hipMalloc failed");
+            g = ROSE_E_DEVICE;
+            break;
+        }
+        FitLaunch& L = fit[i];
+        L = FitLaunch{};
+        L.g = h->g;
+        L.pts = h->pts_o;
+        L.count_dev = &h->st->n_overlap;
+        L.T32 = nullptr;
+        L.st = h->st;
+        L.pst = pst_devs[i];
+        L.n = n_particles[i];
+        L.splits = splits;
+        L.lookup = p.lookup;
+        L.shape_p = P;
+        L.shape_u = U;
+        L.partial = h->partial;
+        const int nb = fitness_blocks(L, P);
+        begin[i + 1] = begin[i] + (nb + 7) / 8 * 8;
+        init[i] = InitStatic{h->st, to_cam(&cams[i]), p.stride, p.flags, h->pts, h->pts_o};
+        UpdateArgs& ua = upd[i];
+        ua.st = h->st;
+        ua.cam = to_cam(&cams[i]);
+        ua.pst = pst_devs[i];
+        ua.partial = h->partial;
+        ua.F = h->F;
+        ua.pts = h->pts;
+        ua.pts_o = h->pts_o;
+        ua.n = n_particles[i];
+        ua.splits = splits;
+        ua.max_iters = p.max_iters;
+        ua.early_stop = p.early_stop;
+        ua.flags = p.flags;
+        ua.beta = p.beta;
+        ua.eps = p.eps;
+        ua.tau = p.tau;
+        ua.stop_tol = p.stop_tol;
+        stp[i] = h->st;
+        b->h.push_back(h);
+        b->params.push_back(p);
+        b->n.push_back(n_particles[i]);
+        b->K = std::max(b->K, (int32_t)p.max_iters);
+    }
+    if (g != ROSE_OK) {
+        batch_free(b);
+        return g;
+    }
+    b->total = begin[count];
+    b->grid = std::max(8, std::min(b->total, 256 * 8) / 8 * 8);
+    bool ok = hipMalloc(&b->fit_dev, sizeof(FitLaunch) * count) == hipSuccess &&
+              hipMalloc(&b->begin_dev, sizeof(int) * (count + 1)) == hipSuccess &&
+              hipMalloc(&b->init_dev, sizeof(InitStatic) * count) == hipSuccess &&
+              hipMalloc(&b->upd_dev, sizeof(UpdateArgs) * count) == hipSuccess &&
+              hipMalloc(&b->stp_dev, sizeof(DevState*) * count) == hipSuccess &&
+              hipHostMalloc(&b->in_host, sizeof(FrameIn) * count, hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&b->out_host, sizeof(DevState) * count, hipHostMallocDefault) == hipSuccess;
+    ok = ok && hipMemcpy(b->fit_dev, fit.data(), sizeof(FitLaunch) * count, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(b->begin_dev, begin.data(), sizeof(int) * (count + 1), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(b->init_dev, init.data(), sizeof(InitStatic) * count, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(b->upd_dev, upd.data(), sizeof(UpdateArgs) * count, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(b->stp_dev, stp.data(), sizeof(DevState*) * count, hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) {
+        batch_free(b);
+        set_error("pso_batch_create: device allocation or copy failed");
+        return ROSE_E_DEVICE;
+    }
+    memset(b->in_host, 0, sizeof(FrameIn) * count);
+    *out = b;
+    return ROSE_OK;
+}
+
+rose_status pso_batch_destroy(rose_batch* b) {
+    clear_error();
+    if (!b) return ROSE_OK;
+    (void)hipDeviceSynchronize();
+    batch_free(b);
+    return ROSE_OK;
+}
+
+rose_status pso_batch_track(rose_batch* b, const float* const* depth_devs, const rose_pose* init_centres,
+                            const double* init_rs, rose_track_state* states, rose_track_stats* stats,
+                            hipStream_t s) {
+    clear_error();
+    ROSE_REQUIRE(b && depth_devs && states, ROSE_E_ARG, "pso_batch_track: NULL argument");
+    for (int i = 0; i < b->count; ++i) ROSE_REQUIRE(depth_devs[i], ROSE_E_ARG, "pso_batch_track: NULL depth %d", i);
+    // per-frame inputs (pinned host memory, read by the init kernel)
+    for (int i = 0; i < b->count; ++i) {
+        FrameIn& in = b->in_host[i];
+        rose_track_state& st = states[i];
+        const rose_track_params& p = b->params[i];
+        const rose_pose* c0 = init_centres ? &init_centres[i] : &st.pose;
+        const double* r0 = init_rs ? &init_rs[6 * i] : st.r;
+        for (int k = 0; k < 4; ++k) in.qc[k] = c0->q[k];
+        for (int k = 0; k < 3; ++k) in.tc[k] = c0->t[k];
+        for (int k = 0; k < 6; ++k) in.r[k] = r0[k];
+        pose_matrix(st.pose.q, st.pose.t, in.Tprev);
+        in.depth = depth_devs[i];
+        in.active = st.tsdf_built ? 1 : 0;
+        in.pad = 0;
+        if (!st.tsdf_built) {
+            // Sec. 4, first corner case (no fitness): rhat = 0.5 * 1, pose kept
+            for (int d = 0; d < 6; ++d) st.r[d] = p.beta * r0[d] + (1.0 - p.beta) * 0.5;
+            st.pose = *c0;
+            st.rho = 0.5;
+            st.frame += 1;
+            if (stats) {
+                memset(&stats[i], 0, sizeof(rose_track_stats));
+                stats[i].iters = 1;
+                stats[i].rho_iter[0] = 0.5;
+            }
+        }
+    }
+    const bool graph = b->use_graph && s != nullptr;
+    if (graph) {
+        if (!b->exec || b->graph_stream != s) {
+            if (b->exec) (void)hipGraphExecDestroy(b->exec);
+            if (b->graph) (void)hipGraphDestroy(b->graph);
+            b->exec = nullptr;
+            b->graph = nullptr;
+            ROSE_CHECK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+            rose_status st = batch_enqueue(b, s);
+            hipGraph_t gr = nullptr;
+            hipError_t e = hipStreamEndCapture(s, &gr);
+            if (st != ROSE_OK) return st;
+            if (e != hipSuccess) {
+                set_error("pso_batch_track: graph capture failed: %s", hipGetErrorString(e));
+                return ROSE_E_DEVICE;
+            }
+            b->graph = gr;
+            ROSE_CHECK_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+            b->graph_stream = s;
+        }
+        ROSE_CHECK_HIP(hipGraphLaunch(b->exec, s));
+    } else {
+        rose_status st = batch_enqueue(b, s);
+        if (st != ROSE_OK) return st;
+    }
+    ROSE_CHECK_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < b->count; ++i) {
+        if (!b->in_host[i].active) continue;
+        const DevState& r = b->out_host[i];
+        rose_track_state& st = states[i];
+        if (stats) {
+            memset(&stats[i], 0, sizeof(rose_track_stats));
+            stats[i].status = (r.n_points == 0) ? ROSE_E_STATE : ROSE_OK;
+        }
+        if (r.n_points == 0) continue;  // no valid depth: state unchanged
+        for (int k = 0; k < 4; ++k) st.pose.q[k] = r.qc[k];
+        for (int k = 0; k < 3; ++k) st.pose.t[k] = r.tc[k];
+        for (int d = 0; d < 6; ++d) st.r[d] = r.r1[d];
+        st.rho = r.rho_last;
+        st.frame += 1;
+        if (stats) {
+            stats[i].iters = r.k;
+            stats[i].n_points = r.n_points;
+            stats[i].n_overlap_last = r.n_overlap;
+            for (int k = 0; k < r.k && k < ROSE_MAX_ITERS; ++k) {
+                stats[i].aps_size[k] = r.aps[k];
+                stats[i].n_overlap[k] = r.n_overlap_iter[k];
+                stats[i].rho_iter[k] = r.rho_iter[k];
+            }
         }
     }
     return ROSE_OK;

@@ -56,7 +56,7 @@ class TrackState(C.Structure):
 
 class TrackStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("n_points", C.c_int32), ("n_overlap_last", C.c_int32),
-                ("reserved", C.c_int32), ("aps_size", C.c_int32 * MAX_ITERS),
+                ("status", C.c_int32), ("aps_size", C.c_int32 * MAX_ITERS),
                 ("n_overlap", C.c_int32 * MAX_ITERS), ("rho_iter", C.c_double * MAX_ITERS)]
 
 
@@ -100,6 +100,9 @@ _sigs = {
                       C.c_int),
     "rose_gemm_bf16": ([C.c_int32, C.c_int32, C.c_int32, _P, C.c_int64, C.c_int64, _P, C.c_int64, C.c_int64, _P,
                         C.c_int64, _S], C.c_int),
+    "pso_batch_create": ([C.c_int32, _P, _P, _P, _P, _P, C.c_int32, C.POINTER(C.c_void_p)], C.c_int),
+    "pso_batch_track": ([_P, _P, _P, _P, _P, _P, _S], C.c_int),
+    "pso_batch_destroy": ([_P], C.c_int),
     "rose_profile_enable": ([C.c_int32], C.c_int),
     "rose_profile_reset": ([], C.c_int),
     "rose_profile_read": ([C.POINTER(Profile)], C.c_int),
@@ -126,7 +129,7 @@ def header_functions() -> list:
     """Names of the functions include/rose.h declares."""
     txt = open(HEADER).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_]+\s*\*?\s*([a-z_]+)\s*\(", txt, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z0-9_]+\s*\*?\s*([a-z0-9_]+)\s*\(", txt, flags=re.M)))
 
 
 def version() -> str:
@@ -452,3 +455,57 @@ class Mlp:
 
 def set_fitness_shape(particles_per_wave: int, points_per_lane: int):
     _check("rose_fitness_set_shape", _lib.rose_fitness_set_shape(int(particles_per_wave), int(points_per_lane)))
+
+
+class Batch:
+    """Many sequences tracked in lockstep (pso_batch_*)."""
+
+    def __init__(self, vols, cams, psts, params, use_graph: bool = True):
+        self.count = len(vols)
+        if not (len(cams) == len(psts) == len(params) == self.count):
+            raise ValueError("one camera, template and parameter set per volume")
+        self._vols = list(vols)
+        self._psts = list(psts)
+        H = (C.c_void_p * self.count)(*[v.handle.value for v in vols])
+        CA = (Camera * self.count)(*[camera(k) for k in cams])
+        PS = (C.c_void_p * self.count)(*[p.data_ptr() for p in psts])
+        N = (C.c_int32 * self.count)(*[p.shape[0] for p in psts])
+        PR = (TrackParams * self.count)(*params)
+        h = C.c_void_p()
+        _check("pso_batch_create", _lib.pso_batch_create(self.count, H, CA, PS, N, PR, int(bool(use_graph)),
+                                                         C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _lib.pso_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def track(self, depths, states, init_centres=None, init_rs=None, stream=None):
+        """states: a ctypes array of TrackState (updated in place); returns
+        per-sequence stats dicts."""
+        if len(depths) != self.count:
+            raise ValueError("one depth frame per sequence")
+        D = (C.c_void_p * self.count)(*[d.data_ptr() for d in depths])
+        ST = (TrackStats * self.count)()
+        IC = None
+        if init_centres is not None:
+            IC = (Pose * self.count)(*[pose(*c) for c in init_centres])
+        IR = None
+        if init_rs is not None:
+            IR = (C.c_double * (6 * self.count))(*[float(v) for r in init_rs for v in r])
+        _check("pso_batch_track", _lib.pso_batch_track(self.handle, D, IC, IR, states, ST, _stream(stream)))
+        out = []
+        for i in range(self.count):
+            s = ST[i]
+            it = s.iters
+            out.append(dict(status=s.status, iters=it, n_points=s.n_points, aps=list(s.aps_size[:it]),
+                            n_overlap=list(s.n_overlap[:it]), q=list(states[i].pose.q), t=list(states[i].pose.t),
+                            r1=list(states[i].r), rho=states[i].rho))
+        return out
