@@ -75,6 +75,7 @@ typedef struct {
 } rose_pose;
 
 typedef struct rose_tsdf rose_tsdf; /* opaque; host-side metadata plus small device scratch */
+typedef struct rose_mlp rose_mlp;   /* opaque; learned-proposal network scratch (see below) */
 
 /* Text of the last non-OK status of the calling thread ("" if none). */
 const char* rose_last_error(void);
@@ -260,6 +261,39 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_cam
                             int32_t n_particles, const rose_track_params* p, const rose_pose* init_centre,
                             const double* init_r, rose_track_state* state, rose_track_stats* stats, hipStream_t s);
 
+/* Chart of Sec. 3.3 between two poses: u = (imaginary part of the
+ * quaternion of a^-1 b with w >= 0, translation of a^-1 b), so that
+ * b = a * Delta(u) (rose_chart_exp).  Host functions. */
+rose_status rose_chart_log(const rose_pose* a, const rose_pose* b, double u[6]);
+rose_status rose_chart_exp(const rose_pose* a, const double u[6], rose_pose* out);
+
+/* ----------------------------------------- learned proposal frame (a11, a13) */
+typedef struct {
+    int32_t low_w, low_h, scale; /* residual grid (40 x 30) and its subsampling of the frame (16 at 640x480) */
+    int32_t feature_dim;         /* network input size (>= low_w * low_h + 6; 1216) */
+    double kappa;                /* r_0 = kappa * exp(l), clamped to [r_min, r_max] */
+    double r_min, r_max;
+    double delta;                /* fall back when rho < previous rho - delta */
+    double near_m, far_m, step_m;/* raycast range and step */
+} rose_learned_params;
+
+/* One frame with the learned PST proposal: render the model at the previous
+ * pose (tsdf_raycast), build the residual features (proposal_features with
+ * `velocity`), run the network (rose_mlp_forward, B = 1) for (mu, l); centre
+ * the small template at c_0 = s^{t-1} * Delta(mu) with axis lengths
+ * r_0 = kappa exp(l) and run pso_track_frame.  The result is kept unless the
+ * network output is not finite or the final fitness falls below the previous
+ * frame's state->rho - delta; then plain pso_track_frame with the plain
+ * template runs from the unchanged state (fallback, *fallback_out = 1).
+ * work_dev: >= low_w*low_h + feature_dim + 12 floats of device scratch.
+ * Synchronises `s`. */
+rose_status pso_track_frame_learned(rose_tsdf* h, const float* depth_dev, const rose_camera* cam,
+                                    const float* pst_small_dev, int32_t n_small, const float* pst_plain_dev,
+                                    int32_t n_plain, rose_mlp* mlp, const float* mlp_params_dev, float* work_dev,
+                                    const double velocity[6], const rose_track_params* p,
+                                    const rose_learned_params* lp, rose_track_state* state, rose_track_stats* stats,
+                                    int32_t* fallback_out, hipStream_t s);
+
 /* ------------------------------------------------- batched tracking (a14) */
 /* Many independent sequences (each its own TSDF handle, camera, template,
  * particle count and parameters) tracked in lockstep, one frame step per
@@ -296,7 +330,6 @@ rose_status pso_batch_destroy(rose_batch* b);
  * matrix cores with BF16 operands (round to nearest even) and FP32
  * accumulation; GELU is the exact erf form.  The handle owns activation
  * scratch for up to max_batch rows.  out_dim must be 12. */
-typedef struct rose_mlp rose_mlp;
 int64_t rose_mlp_param_count(int32_t in_dim, int32_t hidden, int32_t out_dim);
 rose_status rose_mlp_create(int32_t in_dim, int32_t hidden, int32_t out_dim, int32_t max_batch, rose_mlp** out);
 rose_status rose_mlp_destroy(rose_mlp* m);

@@ -817,3 +817,100 @@ rose_status pso_batch_track(rose_batch* b, const float* const* depth_devs, const
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------- learned proposal
+extern "C" {
+
+rose_status rose_chart_log(const rose_pose* a, const rose_pose* b, double u[6]) {
+    clear_error();
+    ROSE_REQUIRE(a && b && u, ROSE_E_ARG, "rose_chart_log: NULL argument");
+    // a^-1 b: q = conj(q_a) q_b, t = R_a^T (t_b - t_a); chart = (imag(q) with w >= 0, t)
+    const double qa_c[4] = {a->q[0], -a->q[1], -a->q[2], -a->q[3]};
+    double q[4], Ra[9];
+    quat_prod(qa_c, b->q, q);
+    const double n = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    const double sg = (q[0] < 0.0) ? -1.0 : 1.0;
+    quat_rot(a->q, Ra);
+    const double d[3] = {b->t[0] - a->t[0], b->t[1] - a->t[1], b->t[2] - a->t[2]};
+    for (int i = 0; i < 3; ++i) u[i] = sg * q[i + 1] / n;
+    for (int i = 0; i < 3; ++i) u[3 + i] = Ra[0 * 3 + i] * d[0] + Ra[1 * 3 + i] * d[1] + Ra[2 * 3 + i] * d[2];
+    return ROSE_OK;
+}
+
+rose_status rose_chart_exp(const rose_pose* a, const double u[6], rose_pose* out) {
+    clear_error();
+    ROSE_REQUIRE(a && u && out, ROSE_E_ARG, "rose_chart_exp: NULL argument");
+    double q[4] = {a->q[0], a->q[1], a->q[2], a->q[3]}, t[3] = {a->t[0], a->t[1], a->t[2]};
+    retract(q, t, u);
+    for (int i = 0; i < 4; ++i) out->q[i] = q[i];
+    for (int i = 0; i < 3; ++i) out->t[i] = t[i];
+    return ROSE_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+rose_status pso_track_frame_learned(rose_tsdf* h, const float* depth_dev, const rose_camera* cam,
+                                    const float* pst_small_dev, int32_t n_small, const float* pst_plain_dev,
+                                    int32_t n_plain, rose_mlp* mlp, const float* mlp_params_dev, float* work_dev,
+                                    const double velocity[6], const rose_track_params* p,
+                                    const rose_learned_params* lp, rose_track_state* state, rose_track_stats* stats,
+                                    int32_t* fallback_out, hipStream_t s) {
+    clear_error();
+    ROSE_REQUIRE(h && depth_dev && cam && pst_small_dev && pst_plain_dev && mlp && mlp_params_dev && work_dev &&
+                     velocity && p && lp && state,
+                 ROSE_E_ARG, "pso_track_frame_learned: NULL argument");
+    ROSE_REQUIRE(lp->scale >= 1 && lp->low_w >= 1 && lp->low_h >= 1 && lp->feature_dim >= lp->low_w * lp->low_h + 6 &&
+                     lp->kappa > 0 && lp->r_min > 0 && lp->r_max >= lp->r_min,
+                 ROSE_E_ARG, "pso_track_frame_learned: bad learned parameters");
+    if (fallback_out) *fallback_out = 0;
+    if (!state->tsdf_built)
+        return pso_track_frame(h, depth_dev, cam, pst_plain_dev, n_plain, p, nullptr, nullptr, state, stats, s);
+    rose_camera low;
+    low.fx = cam->fx / (float)lp->scale;
+    low.fy = cam->fy / (float)lp->scale;
+    low.cx = (cam->cx + 0.5f) / (float)lp->scale - 0.5f;
+    low.cy = (cam->cy + 0.5f) / (float)lp->scale - 0.5f;
+    low.width = lp->low_w;
+    low.height = lp->low_h;
+    float* render = work_dev;
+    float* X = render + lp->low_w * lp->low_h;
+    float* out = X + lp->feature_dim;
+    rose_status st;
+    if ((st = tsdf_raycast(h, &state->pose, &low, lp->near_m, lp->far_m, lp->step_m, render, s)) != ROSE_OK) return st;
+    if ((st = proposal_features(depth_dev, cam, render, &low, lp->scale, velocity, lp->feature_dim, X, s)) != ROSE_OK)
+        return st;
+    if ((st = rose_mlp_forward(mlp, mlp_params_dev, X, 1, out, s)) != ROSE_OK) return st;
+    float o[12];
+    ROSE_CHECK_HIP(hipMemcpyAsync(o, out, sizeof o, hipMemcpyDeviceToHost, s));
+    ROSE_CHECK_HIP(hipStreamSynchronize(s));
+    bool finite = true;
+    for (int i = 0; i < 12; ++i) finite = finite && std::isfinite(o[i]);
+    bool fallback = !finite;
+    if (finite) {
+        double mu[6], r0[6];
+        for (int d = 0; d < 6; ++d) {
+            mu[d] = o[d];
+            r0[d] = std::min(lp->r_max, std::max(lp->r_min, lp->kappa * std::exp((double)o[6 + d])));
+        }
+        rose_pose c0;
+        if ((st = rose_chart_exp(&state->pose, mu, &c0)) != ROSE_OK) return st;
+        rose_track_state trial = *state;
+        st = pso_track_frame(h, depth_dev, cam, pst_small_dev, n_small, p, &c0, r0, &trial, stats, s);
+        if (st == ROSE_OK && trial.rho >= state->rho - lp->delta) {
+            *state = trial;
+        } else if (st == ROSE_OK || st == ROSE_E_STATE) {
+            fallback = true;
+        } else {
+            return st;
+        }
+    }
+    if (fallback) {
+        if (fallback_out) *fallback_out = 1;
+        return pso_track_frame(h, depth_dev, cam, pst_plain_dev, n_plain, p, nullptr, nullptr, state, stats, s);
+    }
+    return ROSE_OK;
+}
+
+}  // extern "C"

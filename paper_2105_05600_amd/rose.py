@@ -60,6 +60,17 @@ class TrackStats(C.Structure):
                 ("n_overlap", C.c_int32 * MAX_ITERS), ("rho_iter", C.c_double * MAX_ITERS)]
 
 
+class LearnedParams(C.Structure):
+    _fields_ = [("low_w", C.c_int32), ("low_h", C.c_int32), ("scale", C.c_int32), ("feature_dim", C.c_int32),
+                ("kappa", C.c_double), ("r_min", C.c_double), ("r_max", C.c_double), ("delta", C.c_double),
+                ("near_m", C.c_double), ("far_m", C.c_double), ("step_m", C.c_double)]
+
+
+def learned_params(scale=16, low_w=40, low_h=30, feature_dim=1216, kappa=2.0, r_min=1e-3, r_max=1.0, delta=0.01,
+                   near=0.2, far=8.0, step=0.005) -> "LearnedParams":
+    return LearnedParams(low_w, low_h, scale, feature_dim, kappa, r_min, r_max, delta, near, far, step)
+
+
 class Profile(C.Structure):
     _fields_ = [("fitness_ms", C.c_double), ("fitness_launches", C.c_int64), ("fitness_evals", C.c_double),
                 ("update_ms", C.c_double), ("update_launches", C.c_int64), ("integrate_ms", C.c_double),
@@ -103,6 +114,11 @@ _sigs = {
     "pso_batch_create": ([C.c_int32, _P, _P, _P, _P, _P, C.c_int32, C.POINTER(C.c_void_p)], C.c_int),
     "pso_batch_track": ([_P, _P, _P, _P, _P, _P, _S], C.c_int),
     "pso_batch_destroy": ([_P], C.c_int),
+    "rose_chart_log": ([C.POINTER(Pose), C.POINTER(Pose), _P], C.c_int),
+    "rose_chart_exp": ([C.POINTER(Pose), _P, C.POINTER(Pose)], C.c_int),
+    "pso_track_frame_learned": ([_P, _P, C.POINTER(Camera), _P, C.c_int32, _P, C.c_int32, _P, _P, _P, _P,
+                                 C.POINTER(TrackParams), C.POINTER(LearnedParams), C.POINTER(TrackState),
+                                 C.POINTER(TrackStats), _P, _S], C.c_int),
     "rose_profile_enable": ([C.c_int32], C.c_int),
     "rose_profile_reset": ([], C.c_int),
     "rose_profile_read": ([C.POINTER(Profile)], C.c_int),
@@ -509,3 +525,35 @@ class Batch:
                             n_overlap=list(s.n_overlap[:it]), q=list(states[i].pose.q), t=list(states[i].pose.t),
                             r1=list(states[i].r), rho=states[i].rho))
         return out
+
+
+def chart_log(qa, ta, qb, tb):
+    """u with pose_b = pose_a * Delta(u) (the chart of Sec. 3.3)."""
+    u = (C.c_double * 6)()
+    _check("rose_chart_log", _lib.rose_chart_log(C.byref(pose(qa, ta)), C.byref(pose(qb, tb)), u))
+    return list(u)
+
+
+def chart_exp(qa, ta, u):
+    out = Pose()
+    uu = (C.c_double * 6)(*[float(v) for v in u])
+    _check("rose_chart_exp", _lib.rose_chart_exp(C.byref(pose(qa, ta)), uu, C.byref(out)))
+    return list(out.q), list(out.t)
+
+
+def track_frame_learned(vol: Tsdf, depth: torch.Tensor, K, pst_small: torch.Tensor, pst_plain: torch.Tensor,
+                        mlp: "Mlp", mlp_params: torch.Tensor, work: torch.Tensor, velocity, params: TrackParams,
+                        lparams: "LearnedParams", state: TrackState, stream=None) -> dict:
+    _dev(depth, torch.float32, "depth")
+    cam = camera(K)
+    stats = TrackStats()
+    fb = C.c_int32(0)
+    vel = (C.c_double * 6)(*[float(v) for v in velocity])
+    _check("pso_track_frame_learned", _lib.pso_track_frame_learned(
+        vol.handle, _ptr(depth), C.byref(cam), _ptr(pst_small), pst_small.shape[0], _ptr(pst_plain),
+        pst_plain.shape[0], mlp.handle, _ptr(mlp_params), _ptr(work), vel, C.byref(params), C.byref(lparams),
+        C.byref(state), C.byref(stats), C.byref(fb), _stream(stream)))
+    it = stats.iters
+    return dict(iters=it, n_points=stats.n_points, aps=list(stats.aps_size[:it]),
+                n_overlap=list(stats.n_overlap[:it]), q=list(state.pose.q), t=list(state.pose.t),
+                r1=list(state.r), rho=state.rho, fallback=bool(fb.value))
