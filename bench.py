@@ -110,6 +110,14 @@ def main():
         step(i)
     torch.cuda.synchronize()
     log(f"warmup {args.warmup} frames done")
+    # launch-shape tuning on the current frame: the tracker's points (8x8
+    # tiles) under the 10240 particle poses of its first iteration
+    from paper_2105_05600_amd import autotune
+    nxt = 1 + args.warmup
+    pts = rose.depth_unproject(dev_depths[nxt], seq.K, seq.stride, tiled=True)
+    Tp = rose.particle_poses(list(st.pose.q), list(st.pose.t), list(st.r), pst).float().contiguous()
+    tuned = autotune.tune(vol, pts, Tp, lookup)
+    log(f"fitness shape {tuned['shape']} ({'cached' if tuned['cached'] else 'timed'}: {tuned['ms']})")
     rose.profile_enable(True)
     rose.profile_reset()
     evals = 0.0
@@ -156,7 +164,8 @@ def main():
                                     "integrate": prof["integrate_ms"] / args.steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_fitness", "avg_launch_ms": fit_ms, "evals_per_launch": fit_evals},
+                     "kernel": "k_fitness", "avg_launch_ms": fit_ms, "evals_per_launch": fit_evals,
+                     "bytes_per_eval": BYTES_PER_EVAL[lookup], "shape": list(tuned["shape"])},
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on one iteration of frame 1")

@@ -1,0 +1,75 @@
+"""Launch-shape autotuner for the fitness kernel.
+
+The fitness kernel is compiled for a few shapes (particles per wavefront x
+points per lane per step).  For a workload (volume, point set, particle
+count) the tuner times every compiled shape on the GPU with HIP events,
+keeps the fastest, sets it process-wide (rose_fitness_set_shape) and caches
+the choice in a JSON file keyed by device, volume size/format, lookup,
+point count and particle count, so later runs skip the timing.
+"""
+from __future__ import annotations
+
+import json
+import os
+from typing import Optional
+
+import torch
+
+from paper_2105_05600_amd import rose
+
+SHAPES = [(4, 2), (8, 2), (4, 4), (2, 4), (8, 4)]
+BATCH_SHAPES = [(4, 2), (8, 2), (4, 4)]  # shapes the batched tracker supports
+DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
+
+
+def _key(vol, m: int, n: int, lookup: int) -> str:
+    dev = torch.cuda.get_device_properties(0)
+    arch = getattr(dev, "gcnArchName", dev.name).split(":")[0]
+    nx, ny, nz = vol.dims
+    # bucket the point count so nearby frames share an entry
+    mb = 1 << max(0, int(m).bit_length() - 1)
+    return f"{arch}|{nx}x{ny}x{nz}|fmt{vol.fmt}|lk{lookup}|m{mb}|n{n}"
+
+
+def _load(path: str) -> dict:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def time_shape(vol, pts, T, lookup: int, shape, reps: int = 5) -> float:
+    rose.set_fitness_shape(*shape)
+    rose.fitness_eval(vol, pts, T, lookup)  # warm
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        rose.fitness_eval(vol, pts, T, lookup)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune(vol, pts: torch.Tensor, T: torch.Tensor, lookup: int = 0, shapes=None, cache: Optional[str] = DEFAULT_CACHE,
+         force: bool = False) -> dict:
+    """Pick the fastest shape for (vol, pts, T) and make it current.
+    Returns {"shape": (P, U), "ms": {...}, "cached": bool}."""
+    shapes = shapes or SHAPES
+    key = _key(vol, pts.shape[0], T.shape[0], lookup)
+    db = _load(cache) if cache else {}
+    if not force and key in db and tuple(db[key]["shape"]) in shapes:
+        best = tuple(db[key]["shape"])
+        rose.set_fitness_shape(*best)
+        return {"shape": best, "ms": db[key].get("ms", {}), "cached": True, "key": key}
+    ms = {f"{p}x{u}": time_shape(vol, pts, T, lookup, (p, u)) for p, u in shapes}
+    best = min(shapes, key=lambda s: ms[f"{s[0]}x{s[1]}"])
+    rose.set_fitness_shape(*best)
+    if cache:
+        db[key] = {"shape": list(best), "ms": ms}
+        tmp = cache + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(db, f, indent=1, sort_keys=True)
+        os.replace(tmp, cache)
+    return {"shape": best, "ms": ms, "cached": False, "key": key}

@@ -1,0 +1,244 @@
+"""Train the learned PST proposal on pairs produced by plain PST on the GPU,
+then compare learned + fallback against plain PST on held-out sequences.
+
+Data: seeded synthetic fast-motion sequences (procedural rooms, 320x240
+depth with sigma = 0.002 z^2 noise, 1-4 m/s, angular speed 0.67 x linear
+speed in rad/s).  Plain PST (10240 particles, 20 iterations) tracks every
+sequence frame by frame -- many sequences at once through the batched
+tracker -- and each frame t >= 2 yields one training pair:
+  input  x_t: 40x30 depth residual of frame t against the model rendered at
+              the plain result for t-1, plus the previous increment u_{t-1}
+              (chart of Sec. 3.3), zero-padded to 1216;
+  target y_t: the plain result's increment u_t = chart(s_{t-1}^-1 s_t).
+The network (1216 -> 256 GELU -> 256 GELU -> 12 = mean and log-scale) is
+trained with the Gaussian negative log-likelihood and Adam, all on the GPU
+with the library's BF16 matrix-core kernels.
+
+Usage: python -m paper_2105_05600_amd.train_proposal --sequences 64 \
+           --frames 160 --out paper_2105_05600_amd/weights/proposal.npz
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+import synth.mlp_init as mlp_init  # noqa: E402
+from paper_2105_05600_amd import rose  # noqa: E402
+
+FEATURE_DIM = 1216
+LOW_W, LOW_H = 40, 30
+
+
+def log(msg):
+    print(f"[train] {msg}", flush=True)
+
+
+def make_sequence(seed: int, n_frames: int, width: int, height: int, speed=None):
+    rng = np.random.default_rng(seed)
+    v = float(rng.uniform(1.0, 4.0)) if speed is None else speed
+    return synth.room_sequence(scene_seed=seed, traj_seed=seed + 1, noise_seed=seed + 2, n_frames=n_frames,
+                               speed=v, ang_speed=0.67 * v, width=width, height=height)
+
+
+def low_camera(K, scale):
+    return synth.Intrinsics(LOW_W, LOW_H, K.fx / scale, K.fy / scale, (K.cx + 0.5) / scale - 0.5,
+                            (K.cy + 0.5) / scale - 0.5)
+
+
+def features(vol, depth, K, scale, q, t, vel):
+    render = rose.raycast(vol, q, t, low_camera(K, scale), near=0.2, far=8.0, step=0.005)
+    return rose.proposal_features(depth, K, render, low_camera(K, scale), scale, vel, FEATURE_DIM)
+
+
+def generate(seeds, n_frames, width, height, chunk, workers):
+    """Plain-PST pairs (X, Y) from the sequences `seeds` (GPU)."""
+    scale = width // LOW_W
+    Xs, Ys = [], []
+    pst = rose.pst_sample(10240, 5600)
+    for c0 in range(0, len(seeds), chunk):
+        group = seeds[c0:c0 + chunk]
+        seqs = [make_sequence(s, n_frames, width, height) for s in group]
+        t0 = time.perf_counter()
+        depths = [[torch.from_numpy(d).cuda() for d in sq.depths(range(n_frames), workers=workers)] for sq in seqs]
+        log(f"sequences {c0}..{c0 + len(group) - 1}: rendered in {time.perf_counter() - t0:.1f} s")
+        vols = [rose.Tsdf(sq.dims, sq.vox, sq.mu, sq.origin) for sq in seqs]
+        params = [rose.track_params(max_iters=20, stride=4) for _ in seqs]
+        batch = rose.Batch(vols, [sq.K for sq in seqs], [pst] * len(seqs), params)
+        states = (rose.TrackState * len(seqs))(*[rose.track_state(sq.poses[0].q, sq.poses[0].t, [1.0] * 6,
+                                                                  tsdf_built=False) for sq in seqs])
+        batch.track([d[0] for d in depths], states)
+        for i, sq in enumerate(seqs):
+            vols[i].integrate(depths[i][0], sq.K, sq.poses[0].q, sq.poses[0].t)
+            states[i].tsdf_built = 1
+        prev = [(list(sq.poses[0].q), list(sq.poses[0].t)) for sq in seqs]
+        vel = [[0.0] * 6 for _ in seqs]
+        t1 = time.perf_counter()
+        for f in range(1, n_frames):
+            feats = [features(vols[i], depths[i][f], seqs[i].K, scale, prev[i][0], prev[i][1], vel[i])
+                     for i in range(len(seqs))]
+            res = batch.track([d[f] for d in depths], states)
+            for i, sq in enumerate(seqs):
+                q, t = res[i]["q"], res[i]["t"]
+                u = rose.chart_log(prev[i][0], prev[i][1], q, t)
+                if f >= 2 and res[i]["status"] == 0:
+                    Xs.append(feats[i])
+                    Ys.append(torch.tensor(u, dtype=torch.float32))
+                vel[i] = u
+                prev[i] = (q, t)
+                vols[i].integrate(depths[i][f], sq.K, q, t)
+        torch.cuda.synchronize()
+        log(f"  tracked {len(seqs)} x {n_frames - 1} frames in {time.perf_counter() - t1:.1f} s; pairs {len(Xs)}")
+        batch.close()
+        for v in vols:
+            v.close()
+        del vols, depths
+        torch.cuda.empty_cache()
+    X = torch.stack(Xs).cuda().contiguous()
+    Y = torch.stack(Ys).cuda().contiguous()
+    return X, Y
+
+
+def train(X, Y, epochs, batch, lr, seed):
+    net = rose.Mlp(FEATURE_DIM, 256, 12, max_batch=batch)
+    P = net.pack(mlp_init.init_params(seed))
+    G = torch.zeros_like(P)
+    M = torch.zeros_like(P)
+    V = torch.zeros_like(P)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    n = X.shape[0]
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    step = 0
+    hist = []
+    for ep in range(epochs):
+        perm = torch.randperm(n, generator=g).cuda()
+        tot, cnt = 0.0, 0
+        for b0 in range(0, n - batch + 1, batch):
+            idx = perm[b0:b0 + batch]
+            xb = X[idx].contiguous()
+            yb = Y[idx].contiguous()
+            net.loss_grad(P, xb, yb, G, loss)
+            step += 1
+            rose.Mlp.adam(P, G, M, V, step, lr)
+            tot += float(loss.item())
+            cnt += 1
+        hist.append(tot / max(cnt, 1))
+        if ep % 5 == 0 or ep == epochs - 1:
+            log(f"epoch {ep}: mean NLL {hist[-1]:.4f}")
+    return net, P, hist
+
+
+def evaluate(net, P, seeds, n_frames, width, height, n_small=4096, workers=16):
+    """Plain 10240-particle PST vs learned proposal + 4096 particles with the
+    plain fallback, on identical held-out sequences: ATE (RMSE, Horn
+    alignment) and frames/s of the tracking calls."""
+    scale = width // LOW_W
+    pst_plain = rose.pst_sample(10240, 5600)
+    pst_small = rose.pst_sample(n_small, 5600)
+    work = torch.zeros(LOW_W * LOW_H + FEATURE_DIM + 12, dtype=torch.float32, device="cuda")
+    lp = rose.learned_params(scale=scale)
+    out = []
+    for seed in seeds:
+        sq = make_sequence(seed, n_frames, width, height)
+        depths = [torch.from_numpy(d).cuda() for d in sq.depths(range(n_frames), workers=workers)]
+        gt = np.array([p.t for p in sq.poses[:n_frames]])
+        row = {"seed": seed}
+        for mode in ("plain", "learned"):
+            vol = rose.Tsdf(sq.dims, sq.vox, sq.mu, sq.origin)
+            params = rose.track_params(max_iters=20, stride=4)
+            st = rose.track_state(sq.poses[0].q, sq.poses[0].t, [1.0] * 6, tsdf_built=False)
+            rose.track_frame(vol, depths[0], sq.K, pst_plain, params, st)
+            vol.integrate(depths[0], sq.K, sq.poses[0].q, sq.poses[0].t)
+            st.tsdf_built = 1
+            est = [np.array(sq.poses[0].t)]
+            prev = (list(sq.poses[0].q), list(sq.poses[0].t))
+            vel = [0.0] * 6
+            fallbacks = 0
+            evals = 0.0
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for f in range(1, n_frames):
+                if mode == "plain":
+                    r = rose.track_frame(vol, depths[f], sq.K, pst_plain, params, st)
+                    evals += 10240 * sum(r["n_overlap"])
+                else:
+                    r = rose.track_frame_learned(vol, depths[f], sq.K, pst_small, pst_plain, net, P, work, vel,
+                                                 params, lp, st)
+                    fallbacks += int(r["fallback"])
+                    evals += (10240 if r["fallback"] else n_small) * sum(r["n_overlap"])
+                q, t = list(st.pose.q), list(st.pose.t)
+                vel = rose.chart_log(prev[0], prev[1], q, t)
+                prev = (q, t)
+                est.append(np.array(t))
+                vol.integrate(depths[f], sq.K, q, t)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            _, rmse = synth.ate(np.array(est), gt)
+            row[mode] = {"ate_rmse_m": rmse, "frames_per_s": (n_frames - 1) / dt, "fallbacks": fallbacks,
+                         "evals": evals}
+            vol.close()
+        log(f"eval seed {seed}: {json.dumps(row)}")
+        out.append(row)
+    return out
+
+
+def save(path, net, P, meta):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    parts = net.unpack(P.detach().cpu())
+    np.savez(path, **{k: v.numpy() for k, v in parts.items()})
+    with open(os.path.splitext(path)[0] + ".json", "w") as f:
+        json.dump(meta, f, indent=1)
+
+
+def load(path):
+    with np.load(path, allow_pickle=False) as z:
+        return {k: z[k] for k in ("W1", "b1", "W2", "b2", "W3", "b3")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--sequences", type=int, default=64)
+    ap.add_argument("--frames", type=int, default=160)
+    ap.add_argument("--width", type=int, default=320)
+    ap.add_argument("--height", type=int, default=240)
+    ap.add_argument("--chunk", type=int, default=16)
+    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--batch", type=int, default=512)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--eval-sequences", type=int, default=4)
+    ap.add_argument("--eval-frames", type=int, default=90)
+    ap.add_argument("--workers", type=int, default=16)
+    ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights",
+                                                  "proposal.npz"))
+    args = ap.parse_args()
+    torch.cuda.set_device(0)
+    seeds = [10000 + 10 * i for i in range(args.sequences)]
+    t0 = time.perf_counter()
+    X, Y = generate(seeds, args.frames, args.width, args.height, args.chunk, args.workers)
+    t_gen = time.perf_counter() - t0
+    log(f"{X.shape[0]} pairs in {t_gen:.1f} s; |y| mean {Y.abs().mean(0).tolist()}")
+    t0 = time.perf_counter()
+    net, P, hist = train(X, Y, args.epochs, args.batch, args.lr, seed=1)
+    t_train = time.perf_counter() - t0
+    ev = evaluate(net, P, [20000 + 10 * i for i in range(args.eval_sequences)], args.eval_frames, args.width,
+                  args.height, workers=args.workers)
+    meta = {"pairs": int(X.shape[0]), "sequences": args.sequences, "frames": args.frames,
+            "image": [args.width, args.height], "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
+            "generation_s": t_gen, "training_s": t_train, "nll_history": hist, "eval": ev}
+    save(args.out, net, P, meta)
+    log(f"saved {args.out}")
+
+
+if __name__ == "__main__":
+    main()
