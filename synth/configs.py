@@ -192,7 +192,8 @@ def room_sequence(scene_seed: int = 7, traj_seed: int = 11, noise_seed: int = 13
                   fps: float = 30.0, speed: float = 3.0, ang_speed: float = 2.0, width: int = 640,
                   height: int = 480, f: float = 525.0, dim: int = 512, vox: float = 0.01, stride: int = 4,
                   n_particles: int = 10240, iters: int = 20, mu: float = 0.15) -> Sequence:
-    scene = procedural_room(scene_seed)
+    # the room fills the volume, leaving a 10 cm margin (5.02 m at 512^3 x 1 cm)
+    scene = procedural_room(scene_seed, 0.1, dim * vox - 0.1)
     K = Intrinsics.centred(width, height, f * width / 640.0)
     poses = fast_trajectory(scene, traj_seed, n_frames, fps, speed, ang_speed)
     return Sequence(scene, K, (dim, dim, dim), vox, np.zeros(3), mu, poses, noise_seed, 0.002, 0.2, 6.0,
