@@ -32,6 +32,11 @@ import numpy as np  # noqa: E402
 # particle x point evaluation (the paper's per-evaluation data movement)
 BYTES_PER_EVAL = {0: 4.0, 1: 32.0}
 HBM_PEAK_GBS = 8000.0
+# measured HBM traffic of the fitness kernel (rocprofv3 FETCH_SIZE + WRITE_SIZE
+# on this workload, scaled by the same counters on a copy of known size); it
+# is reported only while the kernel sources hash to the value it was taken on
+COUNTERS = os.path.join(ROOT, "profiles", "k_fitness_room512_counters.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2105_05600_amd", "csrc", f) for f in ("fitness.hip", "common.h")]
 
 
 def parse():
@@ -42,11 +47,50 @@ def parse():
     ap.add_argument("--lookup", choices=["nearest", "trilinear"], default="nearest")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--render-workers", type=int, default=16)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="before warmup, run a float32 copy of MIB MiB three times (counter calibration)")
     return ap.parse_args()
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(lookup: int):
+    """HBM bytes per fitness launch from the committed counter summary, or
+    None when it is missing, for another lookup, or the kernel has changed."""
+    try:
+        with open(COUNTERS) as f:
+            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith(" "))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("kernel_source_sha256_16") != kernel_source_hash() or kv.get("lookup") != str(lookup):
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_probe(torch, mib: int):
+    n = mib * (1 << 20) // 4
+    src = torch.rand(n, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    log(f"copy probe: 3 x {mib} MiB read + {mib} MiB written")
+    del src, dst
 
 
 def cpu_baseline(psi, seq, depth, prev_pose, n_particles, lookup, iters=3):
@@ -85,6 +129,8 @@ def main():
     depths = seq.depths(range(n_frames), workers=args.render_workers)
     log(f"rendered {n_frames} frames in {time.perf_counter() - t0:.1f} s")
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        copy_probe(torch, args.copy_probe)
     dev_depths = [torch.from_numpy(d).cuda() for d in depths]
     vol = rose.Tsdf(seq.dims, seq.vox, seq.mu, seq.origin)
     pst = rose.pst_sample(seq.n_particles, 5600)
@@ -164,9 +210,10 @@ def main():
                                     "update": prof["update_ms"] / args.steps,
                                     "integrate": prof["integrate_ms"] / args.steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(lookup),
                      "kernel": "k_fitness", "avg_launch_ms": fit_ms, "evals_per_launch": fit_evals,
-                     "bytes_per_eval": BYTES_PER_EVAL[lookup], "shape": list(tuned["shape"])},
+                     "bytes_per_eval": BYTES_PER_EVAL[lookup], "shape": list(tuned["shape"]),
+                     "kernel_source_sha256_16": kernel_source_hash()},
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on one iteration of frame 1")

@@ -88,6 +88,7 @@ def build(force: bool = True) -> str:
 class _TrackParams(C.Structure):
     _fields_ = [("max_iters", C.c_int32), ("early_stop", C.c_int32), ("stride", C.c_int32),
                 ("lookup", C.c_int32), ("flags", C.c_int32), ("prec", C.c_int32),
+                ("levels", C.c_int32), ("level_n", C.c_int32 * 4), ("level_stride", C.c_int32 * 4),
                 ("beta", C.c_double), ("eps", C.c_double), ("tau", C.c_double), ("stop_tol", C.c_double)]
 
 
@@ -262,7 +263,10 @@ def pst_update(F, pst, r, qc, tc, tau=1.0, beta=0.1, eps=1e-3, tsdf_built=True, 
 
 def track_frame(psi, vox, origin, depth, K, pst, q_prev, t_prev, r_init, q_init=None, t_init=None,
                 tsdf_built=True, max_iters=20, early_stop=False, stride=4, lookup=NEAREST, flags=0, prec=F32,
-                beta=0.1, eps=1e-3, tau=1.0, stop_tol=1e-6):
+                beta=0.1, eps=1e-3, tau=1.0, stop_tol=1e-6, levels=None):
+    """One frame of Alg. 1.  levels: optional multi-resolution schedule
+    [(n_particles, stride), ...] used in turn across the iterations (the
+    particles of a level are the first n rows of `pst`)."""
     lib = _load()
     psi = _f32(psi)
     nz, ny, nx = psi.shape
@@ -272,7 +276,13 @@ def track_frame(psi, vox, origin, depth, K, pst, q_prev, t_prev, r_init, q_init=
     q_prev, t_prev, r_init = _f64(q_prev), _f64(t_prev), _f64(r_init)
     q_init = q_prev if q_init is None else _f64(q_init)
     t_init = t_prev if t_init is None else _f64(t_init)
-    P = _TrackParams(max_iters, int(early_stop), stride, lookup, flags, prec, beta, eps, tau, stop_tol)
+    lv = list(levels or [])
+    if len(lv) > 4:
+        raise ValueError("at most 4 levels")
+    ln = (C.c_int32 * 4)(*([int(a) for a, _ in lv] + [0] * (4 - len(lv))))
+    ls = (C.c_int32 * 4)(*([int(b) for _, b in lv] + [0] * (4 - len(lv))))
+    P = _TrackParams(max_iters, int(early_stop), stride, lookup, flags, prec, len(lv), ln, ls, beta, eps, tau,
+                     stop_tol)
     q_out, t_out, r1 = np.zeros(4), np.zeros(3), np.zeros(6)
     rho, iters = np.zeros(1), np.zeros(1, dtype=np.int32)
     aps = np.zeros(32, dtype=np.int32)

@@ -573,9 +573,21 @@ int orc_pst_update(const double* F, const float* pst, int32_t n, const double r_
 /* iteration (rho_prev if none), iteration count, per-iteration APS sizes   */
 /* and rho~, point count, last overlap count.                               */
 /* Returns 0, or -4 when the frame has no valid point.                      */
+/*                                                                          */
+/* Multi-resolution PST (Sec. 4 "Multi-resolution PST"; levels >= 2): the  */
+/* paper alternates a few (PST size, depth subsampling) pairs across the   */
+/* iterations.  Iteration k uses level (k - 1) mod levels: the particles    */
+/* are the first level_n[l] rows of the template (an i.i.d. template's     */
+/* prefix is itself a uniform template) and the points are the frame       */
+/* subsampled with stride level_stride[l].  Everything else (centre, axis  */
+/* lengths, APS threshold, stop rules) carries across levels unchanged.    */
+/* A level with no valid sample has F = 1 for every particle; -4 only when */
+/* no level has a valid sample.  levels <= 1: one level (n, stride).       */
 /* ------------------------------------------------------------------------ */
+#define ORC_MAX_LEVELS 4
 typedef struct {
     int32_t max_iters, early_stop, stride, lookup, flags, prec;
+    int32_t levels, level_n[ORC_MAX_LEVELS], level_stride[ORC_MAX_LEVELS];
     double beta, eps, tau, stop_tol;
 } orc_track_params;
 
@@ -586,12 +598,28 @@ int orc_track_frame(const float* psi, int32_t nx, int32_t ny, int32_t nz, float 
                     const orc_track_params* P, double q_out[4], double t_out[3], double r1_out[6],
                     double* rho_out, int32_t* iters_out, int32_t* aps_sizes, double* rho_iter,
                     int32_t* n_points_out, int32_t* n_overlap_last) {
-    int32_t maxm = ((H + P->stride - 1) / P->stride) * ((W + P->stride - 1) / P->stride);
-    float* pts = (float*)malloc(sizeof(float) * 3 * (size_t)(maxm > 0 ? maxm : 1));
-    uint8_t* mask = (uint8_t*)malloc((size_t)(maxm > 0 ? maxm : 1));
+    const int32_t L = (P->levels > 1) ? P->levels : 1;
+    if (L > ORC_MAX_LEVELS) return -1;
+    int32_t lv_n[ORC_MAX_LEVELS], lv_m[ORC_MAX_LEVELS];
+    float* lv_pts[ORC_MAX_LEVELS];
+    int32_t m_all = 0;
+    for (int32_t l = 0; l < L; ++l) {
+        const int32_t st = (L > 1) ? P->level_stride[l] : P->stride;
+        lv_n[l] = (L > 1) ? P->level_n[l] : n;
+        if (st < 1 || lv_n[l] < 1 || lv_n[l] > n) {
+            for (int32_t e = 0; e < l; ++e) free(lv_pts[e]);
+            return -1;
+        }
+        const int32_t cap = ((H + st - 1) / st) * ((W + st - 1) / st);
+        lv_pts[l] = (float*)malloc(sizeof(float) * 3 * (size_t)(cap > 0 ? cap : 1));
+        lv_m[l] = orc_unproject(depth, W, H, fx, fy, cx, cy, st, P->prec, lv_pts[l]);
+        if (lv_m[l] > m_all) m_all = lv_m[l];
+    }
+    uint8_t* mask = (uint8_t*)malloc((size_t)(m_all > 0 ? m_all : 1));
     double* T = (double*)malloc(sizeof(double) * 12 * (size_t)n);
     double* F = (double*)malloc(sizeof(double) * (size_t)n);
-    int32_t m = orc_unproject(depth, W, H, fx, fy, cx, cy, P->stride, P->prec, pts);
+    const float* pts = lv_pts[0];
+    int32_t m = lv_m[0];
     *n_points_out = m;
     memcpy(r1_out, r_init, 6 * sizeof(double));
     double qc[4], tc[3], r[6], Tprev[12];
@@ -604,12 +632,15 @@ int orc_track_frame(const float* psi, int32_t nx, int32_t ny, int32_t nz, float 
     double thr = 0.0;
     double rho_last = 0.5;
     int have_rho = 0;
-    if (m == 0 && tsdf_built) {
+    if (m_all == 0 && tsdf_built) {
         rc = -4;
         goto done;
     }
     for (k = 1; k <= P->max_iters; ++k) {
         double r_new[6], q_new[4], t_new[3], rt, us[6];
+        pts = lv_pts[(k - 1) % L];
+        m = lv_m[(k - 1) % L];
+        n = lv_n[(k - 1) % L];
         if (tsdf_built) {
             double Tc[12];
             orc_pose_to_mat(qc, tc, Tc);
@@ -666,7 +697,8 @@ done:
     *rho_out = rho_last;
     *iters_out = (rc == 0) ? k : 0;
     *n_overlap_last = nO;
-    free(pts); free(mask); free(T); free(F);
+    for (int32_t l = 0; l < L; ++l) free(lv_pts[l]);
+    free(mask); free(T); free(F);
     return rc;
 }
 
