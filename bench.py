@@ -32,6 +32,8 @@ import numpy as np  # noqa: E402
 # particle x point evaluation (the paper's per-evaluation data movement)
 BYTES_PER_EVAL = {0: 4.0, 1: 32.0}
 HBM_PEAK_GBS = 8000.0
+# Sec. 4 multi-resolution PST: (particles, per-axis stride) used in turn
+MULTIRES_LEVELS = [(1024, 3), (3072, 4), (10240, 6)]
 # measured HBM traffic of the fitness kernel (rocprofv3 FETCH_SIZE + WRITE_SIZE
 # on this workload, scaled by the same counters on a copy of known size); it
 # is reported only while the kernel sources hash to the value it was taken on
@@ -45,6 +47,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=60)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--lookup", choices=["nearest", "trilinear"], default="nearest")
+    ap.add_argument("--schedule", choices=["single", "multires"], default="single",
+                    help="multires: the paper's alternation (1024, 1/8), (3072, 1/16), (10240, 1/32) as strides "
+                         "3, 4, 6")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--render-workers", type=int, default=16)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -93,11 +98,16 @@ def copy_probe(torch, mib: int):
     del src, dst
 
 
-def cpu_baseline(psi, seq, depth, prev_pose, n_particles, lookup, iters=3):
-    """The oracle, single-threaded, on the first `iters` iterations of one
-    frame (about 10-15 s of CPU work)."""
+def cpu_baseline(seq, depth0, depth, prev_pose, n_particles, lookup, iters=3):
+    """The oracle, single-threaded, on the first `iters` iterations of frame
+    1 (about 10-15 s of CPU work) against its own fusion of frame 0."""
     import oracle
     oracle.build(force=False)
+    nx, ny, nz = seq.dims
+    psi = np.ones((nz, ny, nx), np.float32)
+    wt = np.zeros_like(psi)
+    oracle.integrate(psi, wt, seq.vox, seq.origin, seq.mu, depth0, seq.K, prev_pose.q, prev_pose.t, prec=oracle.F32)
+    del wt
     pst, _ = oracle.pst_sample(n_particles, 5600)
     t0 = time.perf_counter()
     o = oracle.track_frame(psi, seq.vox, seq.origin, depth, seq.K, pst, prev_pose.q, prev_pose.t,
@@ -134,18 +144,14 @@ def main():
     dev_depths = [torch.from_numpy(d).cuda() for d in depths]
     vol = rose.Tsdf(seq.dims, seq.vox, seq.mu, seq.origin)
     pst = rose.pst_sample(seq.n_particles, 5600)
-    params = rose.track_params(max_iters=seq.iters, stride=seq.stride, lookup=lookup)
+    levels = MULTIRES_LEVELS if args.schedule == "multires" else None
+    params = rose.track_params(max_iters=seq.iters, stride=seq.stride, lookup=lookup, levels=levels)
     p0 = seq.poses[0]
     st = rose.track_state(p0.q, p0.t, [1.0] * 6, tsdf_built=False)
     rose.track_frame(vol, dev_depths[0], seq.K, pst, params, st)  # first frame: r_1 = 0.55
     vol.integrate(dev_depths[0], seq.K, p0.q, p0.t)
     st.tsdf_built = 1
     est = [np.array(p0.t)]
-    psi_after0 = None
-    if not args.no_cpu_baseline:
-        psi_t, _ = vol.export()
-        psi_after0 = psi_t.cpu().numpy()
-        del psi_t
 
     def step(i):
         res = rose.track_frame(vol, dev_depths[i], seq.K, pst, params, st)
@@ -172,7 +178,7 @@ def main():
     t_start = time.perf_counter()
     for i in range(1 + args.warmup, n_frames):
         res = step(i)
-        evals += seq.n_particles * float(sum(res["n_overlap"]))
+        evals += float(sum(n * o for n, o in zip(res["n_particles"], res["n_overlap"])))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     prof = rose.profile_read()
@@ -201,7 +207,7 @@ def main():
         "config": {"workload": "room sequence, 512^3 TSDF @1cm f32, 640x480 f=525 stride 4, PST 10240, "
                                "20 iterations + fusion per frame, 3 m/s 2 rad/s",
                    "tsdf": [512, 512, 512], "voxel_m": 0.01, "image": [640, 480], "stride": 4,
-                   "particles": seq.n_particles, "iters": seq.iters, "lookup": args.lookup},
+                   "particles": seq.n_particles, "iters": seq.iters, "lookup": args.lookup, "schedule": args.schedule},
         "frames_per_s": args.steps / wall,
         "fitness_kernel_evals_per_s": prof["fitness_evals"] / (prof["fitness_ms"] * 1e-3),
         "ate_rmse_m": ate_rmse,
@@ -217,7 +223,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on one iteration of frame 1")
-        out["cpu_baseline"] = cpu_baseline(psi_after0, seq, depths[1], p0, seq.n_particles, lookup)
+        out["cpu_baseline"] = cpu_baseline(seq, depths[0], depths[1], p0, seq.n_particles, lookup)
     print(json.dumps(out), flush=True)
     vol.close()
 

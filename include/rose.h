@@ -61,6 +61,7 @@ typedef enum { ROSE_LOOKUP_NEAREST = 0, ROSE_LOOKUP_TRILINEAR = 1 } rose_lookup;
 #define ROSE_FLAG_CENTRE_THRESHOLD 4
 
 #define ROSE_MAX_ITERS 32
+#define ROSE_MAX_LEVELS 4
 #define ROSE_MAX_PARTICLES 65536
 #define ROSE_MAX_IMAGE_PIXELS (4096 * 4096)
 
@@ -214,11 +215,21 @@ typedef struct {
     int32_t stride;     /* depth subsampling stride, >= 1 */
     int32_t lookup;     /* rose_lookup */
     int32_t flags;      /* ROSE_FLAG_* */
-    int32_t reserved;
+    int32_t levels;     /* 0 or 1: one resolution (n_particles, stride); 2..ROSE_MAX_LEVELS: the schedule below */
     double beta;        /* momentum of Eq. momentum (paper: 0.1) */
     double eps;         /* epsilon of Eq. rsinter (paper: 1e-3) */
     double tau;         /* temperature of Eq. pfolh (paper: 1) */
     double stop_tol;    /* stop tolerance (paper: 1e-6) */
+    /* Multi-resolution PST (Sec. 4 "Multi-resolution PST"): iteration k uses
+     * level (k - 1) mod levels, i.e. the first level_n[l] template rows
+     * (1 <= level_n[l] <= n_particles) and the frame subsampled with stride
+     * level_stride[l] (>= 1); centre, axis lengths, APS threshold and stop
+     * rules carry across levels.  A level without valid samples evaluates
+     * F = 1 for every particle.  The paper's (1024, 1/8), (3072, 1/16),
+     * (10240, 1/32) read as pixel fractions are strides 3, 4, 6.  Ignored when
+     * levels <= 1; not supported by pso_batch_* or the learned frame. */
+    int32_t level_n[ROSE_MAX_LEVELS];
+    int32_t level_stride[ROSE_MAX_LEVELS];
 } rose_track_params;
 
 typedef struct {
@@ -231,12 +242,13 @@ typedef struct {
 
 typedef struct {
     int32_t iters;          /* iterations run */
-    int32_t n_points;       /* valid subsampled points */
+    int32_t n_points;       /* valid subsampled points (of level 0 under a multi-resolution schedule) */
     int32_t n_overlap_last; /* |O_k| of the last iteration */
     int32_t status;         /* pso_batch_track: per-sequence status (ROSE_E_STATE: no valid depth) */
     int32_t aps_size[ROSE_MAX_ITERS];
     int32_t n_overlap[ROSE_MAX_ITERS]; /* |O_k| per iteration */
     double rho_iter[ROSE_MAX_ITERS];   /* rho~ per iteration (rho of the centre when the APS is empty) */
+    int32_t n_particles[ROSE_MAX_ITERS]; /* particles evaluated per iteration */
 } rose_track_stats;
 
 /* One frame of Alg. 1 (PFO with PST) on the device.

@@ -244,6 +244,7 @@ struct DevState {
     int32_t n_overlap;
     int32_t status;
     int32_t pad;
+    int32_t lvl_points[ROSE_MAX_LEVELS];  // valid samples per resolution level
     int32_t aps[ROSE_MAX_ITERS];
     int32_t n_overlap_iter[ROSE_MAX_ITERS];
     double rho_iter[ROSE_MAX_ITERS];

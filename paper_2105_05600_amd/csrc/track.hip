@@ -5,6 +5,8 @@
 // CompAxisLength / MovePST and the corner cases, and compacts the overlap
 // set for the next iteration.  The host enqueues the whole loop and
 // synchronises once.
+#include <algorithm>
+
 #include "common.h"
 
 namespace rose {
@@ -77,14 +79,44 @@ __device__ inline int overlap_compact(const Cam& c, const float* A, bool all, co
 struct InitStatic {
     DevState* st;
     Cam cam;
-    int32_t stride;
+    int32_t levels;                        // 1, or the multi-resolution level count
     int32_t flags;
+    int32_t stride[ROSE_MAX_LEVELS];       // subsampling stride per level
+    int32_t offset[ROSE_MAX_LEVELS];       // first point of each level in pts
     float4* pts;
     float4* pts_o;
 };
 
-// Unprojection of the frame (8x8-sample tile order, order-preserving
-// compaction), device-state initialisation and the first overlap set.
+// Stride-s unprojection of a frame into pts (8x8-sample tile order,
+// order-preserving compaction); returns the number of valid samples.
+__device__ int unproject_level(const Cam& cam, const float* depth, int stride, float4* pts, int* lds) {
+    const int su = (cam.W + stride - 1) / stride;
+    const int sv = (cam.H + stride - 1) / stride;
+    const int total = sample_count(su, sv, true);
+    int m = 0;
+    for (int q0 = 0; q0 < total; q0 += blockDim.x) {
+        const int q = q0 + threadIdx.x;
+        int keep = 0;
+        float4 x = make_float4(0, 0, 0, 0);
+        int uu, vv;
+        if (q < total && sample_at(q, su, sv, true, &uu, &vv)) {
+            const int u = uu * stride, v = vv * stride;
+            const float z = depth[(int64_t)v * cam.W + u];
+            if (z > 0.0f) {
+                keep = 1;
+                x = unproject_px(cam, u, v, z);
+            }
+        }
+        int tot;
+        const int pos = block_scan_flag(keep, lds, &tot);
+        if (keep) pts[m + pos] = x;
+        m += tot;
+    }
+    return m;
+}
+
+// Unprojection of the frame at every resolution level, device-state
+// initialisation and the first overlap set (level 0).
 __device__ void track_init_body(const InitStatic& a, const FrameIn& in) {
     __shared__ int lds[17];
     __shared__ float A[12];
@@ -96,27 +128,14 @@ __device__ void track_init_body(const InitStatic& a, const FrameIn& in) {
         }
         return;
     }
-    const int su = (a.cam.W + a.stride - 1) / a.stride;
-    const int sv = (a.cam.H + a.stride - 1) / a.stride;
-    const int total = sample_count(su, sv, true);
-    int m = 0;
-    for (int q0 = 0; q0 < total; q0 += blockDim.x) {
-        const int q = q0 + threadIdx.x;
-        int keep = 0;
-        float4 x = make_float4(0, 0, 0, 0);
-        int uu, vv;
-        if (q < total && sample_at(q, su, sv, true, &uu, &vv)) {
-            const int u = uu * a.stride, v = vv * a.stride;
-            const float z = in.depth[(int64_t)v * a.cam.W + u];
-            if (z > 0.0f) {
-                keep = 1;
-                x = unproject_px(a.cam, u, v, z);
-            }
-        }
-        int tot;
-        const int pos = block_scan_flag(keep, lds, &tot);
-        if (keep) a.pts[m + pos] = x;
-        m += tot;
+    __shared__ int lvl_m[ROSE_MAX_LEVELS];
+    if (threadIdx.x < ROSE_MAX_LEVELS) lvl_m[threadIdx.x] = 0;
+    int m = 0, m_any = 0;
+    for (int l = 0; l < a.levels; ++l) {
+        const int ml = unproject_level(a.cam, in.depth, a.stride[l], a.pts + a.offset[l], lds);
+        if (threadIdx.x == 0) lvl_m[l] = ml;  // read back by thread 0 only
+        if (l == 0) m = ml;
+        m_any += ml;
     }
     if (threadIdx.x == 0) {
         DevState* s = a.st;
@@ -128,10 +147,11 @@ __device__ void track_init_body(const InitStatic& a, const FrameIn& in) {
         s->rho_last = 0.5;
         s->thr = 0.0;
         s->k = 0;
-        s->stopped = (m == 0) ? 1 : 0;
+        s->stopped = (m_any == 0) ? 1 : 0;
         s->empty_streak = 0;
         s->have_rho = 0;
         s->n_points = m;
+        for (int l = 0; l < ROSE_MAX_LEVELS; ++l) s->lvl_points[l] = lvl_m[l];
         s->n_overlap = 0;
         s->status = 0;
         double Tc[12], Ad[12];
@@ -163,8 +183,9 @@ struct UpdateArgs {
     const float* pst;
     const double* partial;
     float* F;
-    const float4* pts;
+    const float4* pts;  // points of the next iteration's level
     float4* pts_o;
+    int32_t next_level; // level of the next iteration (its count is st->lvl_points[next_level])
     int32_t n;
     int32_t splits;
     int32_t max_iters;
@@ -276,7 +297,8 @@ __device__ void track_update_body(const UpdateArgs& a) {
     }
     __syncthreads();
     if (!go_on) return;
-    const int nO2 = overlap_compact(a.cam, A, (a.flags & ROSE_FLAG_NO_OVERLAP) != 0, a.pts, st->n_points, a.pts_o, lds);
+    const int nO2 = overlap_compact(a.cam, A, (a.flags & ROSE_FLAG_NO_OVERLAP) != 0, a.pts,
+                                    st->lvl_points[a.next_level], a.pts_o, lds);
     if (threadIdx.x == 0) st->n_overlap = nO2;
 }
 
@@ -414,7 +436,18 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_cam
                  "pso_track_frame: n_particles = %d out of [1, %d]", n_particles, ROSE_MAX_PARTICLES);
     ROSE_REQUIRE(p->max_iters >= 1 && p->max_iters <= ROSE_MAX_ITERS, ROSE_E_ARG,
                  "pso_track_frame: max_iters = %d out of [1, %d]", p->max_iters, ROSE_MAX_ITERS);
-    ROSE_REQUIRE(p->stride >= 1, ROSE_E_ARG, "pso_track_frame: stride must be >= 1");
+    ROSE_REQUIRE(p->levels >= 0 && p->levels <= ROSE_MAX_LEVELS, ROSE_E_ARG,
+                 "pso_track_frame: levels = %d out of [0, %d]", p->levels, ROSE_MAX_LEVELS);
+    if (p->levels > 1) {
+        for (int l = 0; l < p->levels; ++l) {
+            ROSE_REQUIRE(p->level_n[l] >= 1 && p->level_n[l] <= n_particles, ROSE_E_ARG,
+                         "pso_track_frame: level %d has %d particles (template has %d)", l, p->level_n[l],
+                         n_particles);
+            ROSE_REQUIRE(p->level_stride[l] >= 1, ROSE_E_ARG, "pso_track_frame: level %d stride must be >= 1", l);
+        }
+    } else {
+        ROSE_REQUIRE(p->stride >= 1, ROSE_E_ARG, "pso_track_frame: stride must be >= 1");
+    }
     ROSE_REQUIRE(p->lookup == ROSE_LOOKUP_NEAREST || p->lookup == ROSE_LOOKUP_TRILINEAR, ROSE_E_ARG,
                  "pso_track_frame: bad lookup");
     ROSE_REQUIRE(p->tau > 0.0 && p->beta >= 0.0 && p->beta <= 1.0, ROSE_E_ARG,
@@ -436,22 +469,41 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_cam
         return ROSE_OK;
     }
 
-    const int su = (cam->width + p->stride - 1) / p->stride;
-    const int sv = (cam->height + p->stride - 1) / p->stride;
-    const int64_t mmax = (int64_t)su * sv;
-    const int splits = choose_splits(n_particles, mmax);
+    // resolution levels: one (n_particles, stride), or the schedule
+    const int L = p->levels > 1 ? p->levels : 1;
+    int lv_n[ROSE_MAX_LEVELS], lv_splits[ROSE_MAX_LEVELS];
+    int64_t lv_off[ROSE_MAX_LEVELS + 1];
+    InitStatic ia;
+    ia.levels = L;
+    lv_off[0] = 0;
+    int64_t mmax_all = 0, partial_need = 0;
+    for (int l = 0; l < ROSE_MAX_LEVELS; ++l) {
+        ia.stride[l] = 1;
+        ia.offset[l] = 0;
+    }
+    for (int l = 0; l < L; ++l) {
+        const int st_l = L > 1 ? p->level_stride[l] : p->stride;
+        lv_n[l] = L > 1 ? p->level_n[l] : n_particles;
+        const int su = (cam->width + st_l - 1) / st_l;
+        const int sv = (cam->height + st_l - 1) / st_l;
+        const int64_t mmax = (int64_t)su * sv;
+        lv_splits[l] = choose_splits(lv_n[l], mmax);
+        lv_off[l + 1] = lv_off[l] + mmax;
+        mmax_all = std::max(mmax_all, mmax);
+        partial_need = std::max(partial_need, (int64_t)lv_n[l] * lv_splits[l]);
+        ia.stride[l] = st_l;
+        ia.offset[l] = (int32_t)lv_off[l];
+    }
     rose_status g;
-    if ((g = grow(&h->pts, &h->cap_points, mmax)) != ROSE_OK) return g;
-    if ((g = grow(&h->pts_o, &h->cap_points_o, mmax)) != ROSE_OK) return g;
-    if ((g = grow(&h->partial, &h->cap_partial, (int64_t)n_particles * splits)) != ROSE_OK) return g;
+    if ((g = grow(&h->pts, &h->cap_points, lv_off[L])) != ROSE_OK) return g;
+    if ((g = grow(&h->pts_o, &h->cap_points_o, mmax_all)) != ROSE_OK) return g;
+    if ((g = grow(&h->partial, &h->cap_partial, partial_need)) != ROSE_OK) return g;
     if ((g = grow(&h->F, &h->cap_particles, (int64_t)n_particles)) != ROSE_OK) return g;
     if (!h->st) ROSE_CHECK_HIP(hipMalloc(&h->st, sizeof(DevState)));
     if (!h->st_host) ROSE_CHECK_HIP(hipHostMalloc(&h->st_host, sizeof(DevState), hipHostMallocDefault));
 
-    InitStatic ia;
     ia.st = h->st;
     ia.cam = to_cam(cam);
-    ia.stride = p->stride;
     ia.flags = p->flags;
     ia.pts = h->pts;
     ia.pts_o = h->pts_o;
@@ -466,18 +518,16 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_cam
     hipLaunchKernelGGL(k_track_init, dim3(1), dim3(1024), 0, s, ia, fin);
     ROSE_CHECK_HIP(hipGetLastError());
 
-    FitLaunch L{};
-    L.g = h->g;
-    L.pts = h->pts_o;
-    L.count_dev = &h->st->n_overlap;
-    L.T32 = nullptr;
-    L.st = h->st;
-    L.pst = pst_dev;
-    L.n = n_particles;
-    L.splits = splits;
-    L.lookup = p->lookup;
-    L.partial = h->partial;
-    fitness_shape(&L.shape_p, &L.shape_u);
+    FitLaunch fl{};
+    fl.g = h->g;
+    fl.pts = h->pts_o;
+    fl.count_dev = &h->st->n_overlap;
+    fl.T32 = nullptr;
+    fl.st = h->st;
+    fl.pst = pst_dev;
+    fl.lookup = p->lookup;
+    fl.partial = h->partial;
+    fitness_shape(&fl.shape_p, &fl.shape_u);
 
     UpdateArgs ua;
     ua.st = h->st;
@@ -485,10 +535,7 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_cam
     ua.pst = pst_dev;
     ua.partial = h->partial;
     ua.F = h->F;
-    ua.pts = h->pts;
     ua.pts_o = h->pts_o;
-    ua.n = n_particles;
-    ua.splits = splits;
     ua.max_iters = p->max_iters;
     ua.early_stop = p->early_stop;
     ua.flags = p->flags;
@@ -498,8 +545,16 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_cam
     ua.stop_tol = p->stop_tol;
     int tok_fit[ROSE_MAX_ITERS];
     for (int k = 0; k < p->max_iters; ++k) {
+        // iteration k + 1 runs level k mod L and prepares level (k + 1) mod L
+        const int l = k % L, ln = (k + 1) % L;
+        fl.n = lv_n[l];
+        fl.splits = lv_splits[l];
+        ua.n = lv_n[l];
+        ua.splits = lv_splits[l];
+        ua.pts = h->pts + lv_off[ln];
+        ua.next_level = ln;
         tok_fit[k] = prof_begin(PROF_FITNESS, s);
-        if ((g = launch_fitness(L, s)) != ROSE_OK) return g;
+        if ((g = launch_fitness(fl, s)) != ROSE_OK) return g;
         prof_end(tok_fit[k], s, 0.0);
         const int tu = prof_begin(PROF_UPDATE, s);
         hipLaunchKernelGGL(k_track_update, dim3(1), dim3(1024), 0, s, ua);
@@ -510,8 +565,10 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_cam
     ROSE_CHECK_HIP(hipStreamSynchronize(s));
     const DevState& r = *h->st_host;
     for (int k = 0; k < p->max_iters; ++k)
-        prof_set_evals(tok_fit[k], k < r.k ? (double)n_particles * (double)r.n_overlap_iter[k] : 0.0);
-    if (r.n_points == 0) {
+        prof_set_evals(tok_fit[k], k < r.k ? (double)lv_n[k % L] * (double)r.n_overlap_iter[k] : 0.0);
+    int64_t any = 0;
+    for (int l = 0; l < L; ++l) any += r.lvl_points[l];
+    if (any == 0) {
         set_error("pso_track_frame: the frame has no valid depth sample");
         return ROSE_E_STATE;
     }
@@ -529,6 +586,7 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_cam
             stats->aps_size[k] = r.aps[k];
             stats->n_overlap[k] = r.n_overlap_iter[k];
             stats->rho_iter[k] = r.rho_iter[k];
+            stats->n_particles[k] = lv_n[k % L];
         }
     }
     return ROSE_OK;
@@ -613,6 +671,8 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
                          (p.lookup == ROSE_LOOKUP_NEAREST || p.lookup == ROSE_LOOKUP_TRILINEAR) && p.tau > 0.0 &&
                          p.beta >= 0.0 && p.beta <= 1.0,
                      ROSE_E_ARG, "pso_batch_create: bad parameters for sequence %d", i);
+        ROSE_REQUIRE(p.levels <= 1, ROSE_E_UNSUPPORTED,
+                     "pso_batch_create: multi-resolution schedules are not batched (sequence %d)", i);
         const uint64_t bytes =
             (uint64_t)tsdfs[i]->g.nx * tsdfs[i]->g.ny * tsdfs[i]->g.nz * (tsdfs[i]->g.fmt == ROSE_TSDF_F32 ? 4u : 2u);
         ROSE_REQUIRE(bytes < (uint64_t(1) << 32), ROSE_E_UNSUPPORTED,
@@ -669,7 +729,15 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
         L.partial = h->partial;
         const int nb = fitness_blocks(L, P);
         begin[i + 1] = begin[i] + (nb + 7) / 8 * 8;
-        init[i] = InitStatic{h->st, to_cam(&cams[i]), p.stride, p.flags, h->pts, h->pts_o};
+        InitStatic& ia = init[i];
+        ia = InitStatic{};
+        ia.st = h->st;
+        ia.cam = to_cam(&cams[i]);
+        ia.levels = 1;
+        ia.flags = p.flags;
+        for (int l = 0; l < ROSE_MAX_LEVELS; ++l) ia.stride[l] = p.stride;
+        ia.pts = h->pts;
+        ia.pts_o = h->pts_o;
         UpdateArgs& ua = upd[i];
         ua.st = h->st;
         ua.cam = to_cam(&cams[i]);
@@ -678,6 +746,7 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
         ua.F = h->F;
         ua.pts = h->pts;
         ua.pts_o = h->pts_o;
+        ua.next_level = 0;
         ua.n = n_particles[i];
         ua.splits = splits;
         ua.max_iters = p.max_iters;
@@ -810,6 +879,7 @@ rose_status pso_batch_track(rose_batch* b, const float* const* depth_devs, const
                 stats[i].aps_size[k] = r.aps[k];
                 stats[i].n_overlap[k] = r.n_overlap_iter[k];
                 stats[i].rho_iter[k] = r.rho_iter[k];
+                stats[i].n_particles[k] = b->n[i];
             }
         }
     }
@@ -864,6 +934,8 @@ rose_status pso_track_frame_learned(rose_tsdf* h, const float* depth_dev, const 
     ROSE_REQUIRE(lp->scale >= 1 && lp->low_w >= 1 && lp->low_h >= 1 && lp->feature_dim >= lp->low_w * lp->low_h + 6 &&
                      lp->kappa > 0 && lp->r_min > 0 && lp->r_max >= lp->r_min,
                  ROSE_E_ARG, "pso_track_frame_learned: bad learned parameters");
+    ROSE_REQUIRE(p->levels <= 1, ROSE_E_UNSUPPORTED,
+                 "pso_track_frame_learned: multi-resolution schedules are not supported here");
     if (fallback_out) *fallback_out = 0;
     if (!state->tsdf_built)
         return pso_track_frame(h, depth_dev, cam, pst_plain_dev, n_plain, p, nullptr, nullptr, state, stats, s);

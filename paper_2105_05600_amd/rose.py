@@ -32,6 +32,7 @@ F32, F16, SN16 = 0, 1, 2
 NEAREST, TRILINEAR = 0, 1
 FLAG_NO_OVERLAP, FLAG_NO_NORMALIZE, FLAG_CENTRE_THRESHOLD = 1, 2, 4
 MAX_ITERS = 32
+MAX_LEVELS = 4
 
 
 class Camera(C.Structure):
@@ -45,8 +46,9 @@ class Pose(C.Structure):
 
 class TrackParams(C.Structure):
     _fields_ = [("max_iters", C.c_int32), ("early_stop", C.c_int32), ("stride", C.c_int32),
-                ("lookup", C.c_int32), ("flags", C.c_int32), ("reserved", C.c_int32),
-                ("beta", C.c_double), ("eps", C.c_double), ("tau", C.c_double), ("stop_tol", C.c_double)]
+                ("lookup", C.c_int32), ("flags", C.c_int32), ("levels", C.c_int32),
+                ("beta", C.c_double), ("eps", C.c_double), ("tau", C.c_double), ("stop_tol", C.c_double),
+                ("level_n", C.c_int32 * MAX_LEVELS), ("level_stride", C.c_int32 * MAX_LEVELS)]
 
 
 class TrackState(C.Structure):
@@ -57,7 +59,8 @@ class TrackState(C.Structure):
 class TrackStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("n_points", C.c_int32), ("n_overlap_last", C.c_int32),
                 ("status", C.c_int32), ("aps_size", C.c_int32 * MAX_ITERS),
-                ("n_overlap", C.c_int32 * MAX_ITERS), ("rho_iter", C.c_double * MAX_ITERS)]
+                ("n_overlap", C.c_int32 * MAX_ITERS), ("rho_iter", C.c_double * MAX_ITERS),
+                ("n_particles", C.c_int32 * MAX_ITERS)]
 
 
 class LearnedParams(C.Structure):
@@ -333,9 +336,16 @@ def proposal_features(depth: torch.Tensor, K, render: torch.Tensor, K_low, scale
 
 
 def track_params(max_iters=20, early_stop=False, stride=4, lookup=NEAREST, flags=0, beta=0.1, eps=1e-3, tau=1.0,
-                 stop_tol=1e-6) -> TrackParams:
-    return TrackParams(int(max_iters), int(bool(early_stop)), int(stride), int(lookup), int(flags), 0,
-                       float(beta), float(eps), float(tau), float(stop_tol))
+                 stop_tol=1e-6, levels=None) -> TrackParams:
+    """levels: optional multi-resolution schedule [(n_particles, stride), ...]
+    (2..MAX_LEVELS entries) used in turn across the iterations."""
+    lv = list(levels or [])
+    if len(lv) > MAX_LEVELS:
+        raise ValueError(f"at most {MAX_LEVELS} levels")
+    ln = (C.c_int32 * MAX_LEVELS)(*([int(a) for a, _ in lv] + [0] * (MAX_LEVELS - len(lv))))
+    ls = (C.c_int32 * MAX_LEVELS)(*([int(b) for _, b in lv] + [0] * (MAX_LEVELS - len(lv))))
+    return TrackParams(int(max_iters), int(bool(early_stop)), int(stride), int(lookup), int(flags), len(lv),
+                       float(beta), float(eps), float(tau), float(stop_tol), ln, ls)
 
 
 def track_state(q, t, r, tsdf_built=True, frame=0) -> TrackState:
@@ -366,7 +376,7 @@ def track_frame(vol: Tsdf, depth: torch.Tensor, K, pst: torch.Tensor, params: Tr
     it = stats.iters
     return dict(iters=it, n_points=stats.n_points, n_overlap_last=stats.n_overlap_last,
                 aps=list(stats.aps_size[:it]), n_overlap=list(stats.n_overlap[:it]),
-                rho_iter=list(stats.rho_iter[:it]),
+                rho_iter=list(stats.rho_iter[:it]), n_particles=list(stats.n_particles[:it]),
                 q=list(state.pose.q), t=list(state.pose.t), r1=list(state.r), rho=state.rho)
 
 

@@ -66,4 +66,11 @@ def test_host_side_argument_errors(R):
     params = R.track_params(max_iters=10)
     assert lib.pso_track_frame(C.c_void_p(16), C.c_void_p(16), C.byref(cam), C.c_void_p(16), 0, C.byref(params),
                                None, None, C.byref(st), None, None) == R.E_ARG
+    params = R.track_params(levels=[(8, 2), (16, 3)])
+    assert lib.pso_track_frame(C.c_void_p(16), C.c_void_p(16), C.byref(cam), C.c_void_p(16), 12, C.byref(params),
+                               None, None, C.byref(st), None, None) == R.E_ARG  # level larger than the template
+    assert b"level 1" in lib.rose_last_error()
+    params.levels = R.MAX_LEVELS + 1
+    assert lib.pso_track_frame(C.c_void_p(16), C.c_void_p(16), C.byref(cam), C.c_void_p(16), 16, C.byref(params),
+                               None, None, C.byref(st), None, None) == R.E_ARG
     assert lib.rose_profile_read(None) == R.E_ARG

@@ -47,13 +47,18 @@ def test_gemm_bf16_matches_exact_products(R, M, N, K, ta, tb):
 
 
 @pytest.fixture(scope="module")
-def small_vol(R):
+def small_vol(R, orc):
+    """The small frame's volume fused on the GPU (vol) and by the oracle
+    (psi, the oracle's input)."""
     w = synth.small_frame()
     vol = R.Tsdf(w.dims, w.vox, w.mu, w.origin)
+    nx, ny, nz = w.dims
+    psi = np.ones((nz, ny, nx), np.float32)
+    wt = np.zeros_like(psi)
     for p, d in zip(w.fuse_poses, w.fuse_depths):
         vol.integrate(torch.from_numpy(d).cuda(), w.K, p.q, p.t)
-    psi, _ = vol.export()
-    return w, vol, psi.cpu().numpy()
+        orc.integrate(psi, wt, w.vox, w.origin, w.mu, d, w.K, p.q, p.t, prec=orc.F32)
+    return w, vol, psi
 
 
 def test_raycast_parity(R, orc, small_vol):

@@ -1,0 +1,119 @@
+"""Multi-resolution PST on the GPU (Sec. 4 "Multi-resolution PST") against
+the oracle's schedule: per-iteration APS sizes and particle counts equal,
+poses within 1e-4; identical levels reproduce the single-resolution kernel
+path bit for bit; the paper's schedule at full size (640x480, 512^3,
+1024/3072/10240 particles at strides 3/4/6) matches the oracle over one
+round of the three levels; bad schedules are rejected before any work."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+PAPER_LEVELS = [(1024, 3), (3072, 4), (10240, 6)]
+
+
+@pytest.fixture(scope="module")
+def R():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2105_05600_amd import rose
+    return rose
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _rot_err(qa, qb):
+    Ra, Rb = synth.quat_to_mat(qa), synth.quat_to_mat(qb)
+    return math.acos(np.clip((np.trace(Ra.T @ Rb) - 1) / 2, -1, 1))
+
+
+def _fuse_oracle(orc, dims, vox, origin, mu, frames, K):
+    nx, ny, nz = dims
+    psi = np.ones((nz, ny, nx), np.float32)
+    wt = np.zeros_like(psi)
+    for p, d in frames:
+        orc.integrate(psi, wt, vox, origin, mu, d, K, p.q, p.t, prec=orc.F32)
+    return psi
+
+
+@pytest.fixture(scope="module")
+def small(R, orc):
+    w = synth.small_frame()
+    vol = R.Tsdf(w.dims, w.vox, w.mu, w.origin)
+    for p, d in zip(w.fuse_poses, w.fuse_depths):
+        vol.integrate(dev(d), w.K, p.q, p.t)
+    psi = _fuse_oracle(orc, w.dims, w.vox, w.origin, w.mu, list(zip(w.fuse_poses, w.fuse_depths)), w.K)
+    pst, _ = orc.pst_sample(2048, w.pst_seed)
+    return w, vol, psi, pst
+
+
+@pytest.mark.parametrize("levels", [[(300, 4), (700, 3), (2048, 5)], [(2048, 2), (512, 6)],
+                                    [(64, 3), (1000, 3), (1500, 4), (2048, 7)]])
+@pytest.mark.parametrize("flags", [0, 4])
+def test_multires_parity(R, orc, small, levels, flags):
+    w, vol, psi, pst = small
+    prev = w.fuse_poses[-1]
+    params = R.track_params(max_iters=11, flags=flags, levels=levels)
+    st = R.track_state(prev.q, prev.t, [0.1] * 6)
+    g = R.track_frame(vol, dev(w.depth), w.K, dev(pst), params, st)
+    o = orc.track_frame(psi, w.vox, w.origin, w.depth, w.K, pst, prev.q, prev.t, np.full(6, 0.1), max_iters=11,
+                        flags=flags, levels=levels, prec=orc.F32)
+    assert g["iters"] == o["iters"] == 11
+    assert g["n_particles"] == [levels[k % len(levels)][0] for k in range(11)]
+    assert g["n_points"] == o["n_points"]
+    assert list(g["aps"]) == list(o["aps"])
+    assert np.linalg.norm(np.array(g["t"]) - o["t"]) <= 1e-4
+    assert _rot_err(g["q"], o["q"]) <= 1e-4
+    assert np.allclose(g["r1"], o["r1"], rtol=1e-6, atol=1e-9)
+
+
+def test_identical_levels_equal_single_resolution(R, small):
+    w, vol, _, pst = small
+    prev = w.fuse_poses[-1]
+    out = []
+    for levels in (None, [(2048, w.stride)] * 3):
+        params = R.track_params(max_iters=9, stride=w.stride, levels=levels)
+        st = R.track_state(prev.q, prev.t, [0.1] * 6)
+        out.append(R.track_frame(vol, dev(w.depth), w.K, dev(pst), params, st))
+    a, b = out
+    for key in ("q", "t", "r1", "aps", "n_overlap", "rho_iter"):
+        assert a[key] == b[key], key
+
+
+def test_multires_rejects_bad_schedules(R, small):
+    w, vol, _, pst = small
+    prev = w.fuse_poses[-1]
+    st = R.track_state(prev.q, prev.t, [0.1] * 6)
+    for levels in ([(4096, 3), (512, 4)], [(512, 3), (512, 0)], [(1, 1)] * 5):
+        with pytest.raises((R.RoseError, ValueError)):
+            R.track_frame(vol, dev(w.depth), w.K, dev(pst), R.track_params(levels=levels), st)
+    assert list(st.pose.t) == list(prev.t) and st.frame == 0
+
+
+def test_multires_full_size_one_round(R, orc):
+    """The paper's schedule at full size: three iterations (one per level)
+    on the GPU equal the oracle's three iterations."""
+    seq = synth.room_sequence(n_frames=3)
+    d0, d1 = seq.depths([0, 1])
+    p0 = seq.poses[0]
+    vol = R.Tsdf(seq.dims, seq.vox, seq.mu, seq.origin)
+    vol.integrate(dev(d0), seq.K, p0.q, p0.t)
+    psi = _fuse_oracle(orc, seq.dims, seq.vox, seq.origin, seq.mu, [(p0, d0)], seq.K)
+    pst, _ = orc.pst_sample(10240, 5600)
+    params = R.track_params(max_iters=3, levels=PAPER_LEVELS)
+    st = R.track_state(p0.q, p0.t, [0.55] * 6)
+    g = R.track_frame(vol, dev(d1), seq.K, dev(pst), params, st)
+    o = orc.track_frame(psi, seq.vox, seq.origin, d1, seq.K, pst, p0.q, p0.t, np.full(6, 0.55), max_iters=3,
+                        levels=PAPER_LEVELS, prec=orc.F32)
+    assert g["n_points"] == o["n_points"] > 30000
+    assert list(g["aps"]) == list(o["aps"])
+    assert g["n_overlap"][-1] == o["n_overlap_last"]
+    assert np.linalg.norm(np.array(g["t"]) - o["t"]) <= 1e-4
+    assert _rot_err(g["q"], o["q"]) <= 1e-4
+    vol.close()

@@ -35,6 +35,16 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
+def oracle_volume(orc, w):
+    """The oracle's binary32 fusion of a small frame's fusion depths."""
+    nx, ny, nz = w.dims
+    psi = np.ones((nz, ny, nx), np.float32)
+    wt = np.zeros_like(psi)
+    for p, d in zip(w.fuse_poses, w.fuse_depths):
+        orc.integrate(psi, wt, w.vox, w.origin, w.mu, d, w.K, p.q, p.t, prec=orc.F32)
+    return psi
+
+
 def _rel(a, b):
     a = np.asarray(a, np.float64)
     b = np.asarray(b, np.float64)
@@ -125,14 +135,31 @@ def test_overlap_mask_bit_exact(R, orc):
 
 
 # ------------------------------------------------- a5 voxel indices, fitness
+def stored_values(psi, fmt):
+    """psi (binary32) as the storage format holds it, from the formats'
+    definitions: binary16 round-to-nearest-even; SNORM16 code
+    round(clamp(psi) * 32767) read back as code * (1/32767) in binary32."""
+    psi = np.asarray(psi, np.float32)
+    if fmt == 0:
+        return psi.copy()
+    if fmt == 1:
+        return psi.astype(np.float16).astype(np.float32)
+    code = np.rint(np.clip(psi, -1, 1) * np.float32(32767)).astype(np.int16)
+    return code.astype(np.float32) * np.float32(1.0 / 32767.0)
+
+
 def _random_volume(R, rng, dims, vox, origin, fmt=0):
+    """A random volume loaded on the GPU, and the oracle's copy of it made
+    on the host (the export is checked against that copy, never used)."""
     nx, ny, nz = dims
     psi = rng.uniform(-1, 1, (nz, ny, nx)).astype(np.float32)
     psi[rng.random((nz, ny, nx)) < 0.2] = 1.0
     vol = R.Tsdf(dims, vox, 3 * vox, origin, fmt=fmt)
     vol.load(dev(psi.ravel()))
+    ref = stored_values(psi, fmt)
     gpsi, _ = vol.export()
-    return vol, host(gpsi)
+    assert np.array_equal(host(gpsi).view(np.uint32), ref.view(np.uint32))
+    return vol, ref
 
 
 def _random_poses(rng, n, spread=0.3):
@@ -191,16 +218,20 @@ def test_fitness_parity(R, orc, fmt, lookup, n, m):
 
 
 @pytest.fixture(scope="module")
-def room_frame(R):
-    """A 512^3 volume at 1 cm fused (on the GPU) from frame 0 of the
-    640x480 room sequence; frame 1 is tracked against it."""
+def room_frame(R, orc):
+    """Frame 0 of the 640x480 room sequence fused into a 512^3 volume at
+    1 cm twice: on the GPU (vol) and by the oracle (psi, w, the oracle's
+    inputs); frame 1 is tracked against it."""
     seq = synth.room_sequence(n_frames=3)
     d0, d1 = seq.depths([0, 1])
     vol = R.Tsdf(seq.dims, seq.vox, seq.mu, seq.origin)
     p0 = seq.poses[0]
     vol.integrate(dev(d0), seq.K, p0.q, p0.t)
-    psi, w = vol.export()
-    return seq, vol, host(psi), host(w), d0, d1
+    nx, ny, nz = seq.dims
+    psi = np.ones((nz, ny, nx), np.float32)
+    w = np.zeros_like(psi)
+    orc.integrate(psi, w, seq.vox, seq.origin, seq.mu, d0, seq.K, p0.q, p0.t, prec=orc.F32)
+    return seq, vol, psi, w, d0, d1
 
 
 def test_fitness_full_size_sampled(R, orc, room_frame):
@@ -247,27 +278,26 @@ def test_integrate_parity_small(R, orc, fmt):
 def test_integrate_parity_full_size(R, orc, room_frame):
     """Frame 0 of the 640x480 room sequence fused into the 512^3 volume:
     weights equal and psi bit-identical to the oracle's binary32 fusion."""
-    seq, vol, psi, w, d0, _ = room_frame
-    nx, ny, nz = seq.dims
-    p0 = seq.poses[0]
-    full_psi = np.ones((nz, ny, nx), np.float32)
-    full_w = np.zeros_like(full_psi)
-    orc.integrate(full_psi, full_w, seq.vox, seq.origin, seq.mu, d0, seq.K, p0.q, p0.t, prec=orc.F32)
+    seq, vol, full_psi, full_w, d0, _ = room_frame
+    gp, gw = vol.export()
+    gp, gw = host(gp), host(gw)
     assert (full_w > 0).sum() > 1_000_000
-    assert np.array_equal(w, full_w)
-    assert np.array_equal(psi.view(np.uint32), full_psi.view(np.uint32))
+    assert np.array_equal(gw, full_w)
+    assert np.array_equal(gp.view(np.uint32), full_psi.view(np.uint32))
 
 
 # --------------------------------------------------------- whole frame
 @pytest.fixture(scope="module")
 def small_gpu(R, orc):
+    """The small frame's volume fused on the GPU (vol) and by the oracle
+    (psi, the oracle's input)."""
     w = synth.small_frame()
     vol = R.Tsdf(w.dims, w.vox, w.mu, w.origin)
     for p, d in zip(w.fuse_poses, w.fuse_depths):
         vol.integrate(dev(d), w.K, p.q, p.t)
-    psi, _ = vol.export()
+    psi = oracle_volume(orc, w)
     pst, _ = orc.pst_sample(w.n_particles, w.pst_seed)
-    return w, vol, host(psi), pst
+    return w, vol, psi, pst
 
 
 @pytest.mark.parametrize("lookup", [0, 1])
