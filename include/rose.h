@@ -59,6 +59,12 @@ typedef enum { ROSE_LOOKUP_NEAREST = 0, ROSE_LOOKUP_TRILINEAR = 1 } rose_lookup;
  * non-empty iteration (at k = 1, the centre's own fitness: template row 0
  * sits at c_0).  With this flag: the centre's exact fitness at every k. */
 #define ROSE_FLAG_CENTRE_THRESHOLD 4
+/* Rescaling ablation (Sec. 5 ablation of Eq. rsinter; at most one of the
+ * two): ISO_ONLY replaces the attractor direction |v|/||v|| by the isotropic
+ * unit vector 1/sqrt6, rhat = (1 - rho~)/sqrt6 + eps; ANISO_ONLY drops the
+ * isotropic factor, rhat = |v|/||v|| + eps.  Non-empty APS only. */
+#define ROSE_FLAG_ISO_ONLY 8
+#define ROSE_FLAG_ANISO_ONLY 16
 
 #define ROSE_MAX_ITERS 32
 #define ROSE_MAX_LEVELS 4

@@ -59,6 +59,8 @@ TRILINEAR = 1
 NO_OVERLAP = 1
 NO_NORMALIZE = 2
 CENTRE_THRESHOLD = 4
+ISO_ONLY = 8
+ANISO_ONLY = 16
 
 
 def _cpu_has_fma() -> bool:
@@ -117,7 +119,7 @@ def _load():
             lib.orc_voxel_indices.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_float, P, P, C.c_int32, P,
                                               C.c_int32, P]
             lib.orc_pst_update.argtypes = [P, P, C.c_int32, P, P, P, C.c_double, C.c_double, C.c_double,
-                                           C.c_int32, C.c_double, P, P, P, P, P]
+                                           C.c_int32, C.c_double, P, P, P, P, P, C.c_int32]
             lib.orc_pst_update.restype = C.c_int
             lib.orc_track_frame.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_float, P, P, C.c_int32,
                                             C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float, P, C.c_int32,
@@ -247,7 +249,7 @@ def voxel_indices(dims, vox, origin, pts, T) -> np.ndarray:
     return idx
 
 
-def pst_update(F, pst, r, qc, tc, tau=1.0, beta=0.1, eps=1e-3, tsdf_built=True, rho_thr=None):
+def pst_update(F, pst, r, qc, tc, tau=1.0, beta=0.1, eps=1e-3, tsdf_built=True, rho_thr=None, flags=0):
     lib = _load()
     F = _f64(F)
     pst = _f32(pst)
@@ -257,7 +259,7 @@ def pst_update(F, pst, r, qc, tc, tau=1.0, beta=0.1, eps=1e-3, tsdf_built=True, 
     if rho_thr is None:
         rho_thr = float(np.exp(-F[0] / tau))
     aps = lib.orc_pst_update(_p(F), _p(pst), len(F), _p(r), _p(qc), _p(tc), tau, beta, eps, int(tsdf_built),
-                             float(rho_thr), _p(r_out), _p(q_out), _p(t_out), _p(rt), _p(us))
+                             float(rho_thr), _p(r_out), _p(q_out), _p(t_out), _p(rt), _p(us), int(flags))
     return dict(aps=int(aps), r=r_out, q=q_out, t=t_out, rho_tilde=float(rt[0]), u_star=us)
 
 

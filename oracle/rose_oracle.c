@@ -38,6 +38,8 @@
 #define ORC_NO_OVERLAP 1
 #define ORC_NO_NORMALIZE 2
 #define ORC_CENTRE_THRESHOLD 4
+#define ORC_ISO_ONLY 8   /* rescaling ablation: isotropic part of Eq. rsinter only */
+#define ORC_ANISO_ONLY 16 /* rescaling ablation: anisotropic part of Eq. rsinter only */
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x64-10 counter-based generator (Salmon, Moraes, Dror, Shaw, SC'11, */
@@ -505,13 +507,21 @@ void orc_voxel_indices(int32_t nx, int32_t ny, int32_t nz, float vox, const floa
 /*     rhat = 2 (1 - rho_prev) 1/||1||; c unchanged.                         */
 /*  TSDF not built (first corner case): rhat = 0.5 * 1, c unchanged.        */
 /*  Momentum (Eq. momentum): r_k = beta r_{k-1} + (1 - beta) rhat.          */
+/*  Rescaling ablation (Sec. 5 ablation of Eq. rsinter, flags):             */
+/*     ORC_ISO_ONLY:   the attractor direction |v|/||v|| is replaced by the */
+/*                     isotropic unit vector 1/sqrt6: rhat = (1-rho~)/sqrt6 */
+/*                     + eps;                                               */
+/*     ORC_ANISO_ONLY: the isotropic factor (1 - rho~) is dropped:          */
+/*                     rhat = |v|/||v|| + eps.                              */
+/*  Both concern the non-empty branch only.                                 */
 /* Sums in binary64 with Neumaier compensation.                              */
 /* Returns the APS size; outputs r_out, q_out/t_out (new centre), rho~      */
 /* (rho_prev when the APS is empty) and u* (zeros when empty).              */
 /* ------------------------------------------------------------------------ */
 int orc_pst_update(const double* F, const float* pst, int32_t n, const double r_in[6], const double qc[4],
                    const double tc[3], double tau, double beta, double eps, int32_t tsdf_built, double rho_thr,
-                   double r_out[6], double q_out[4], double t_out[3], double* rho_tilde, double u_star[6]) {
+                   double r_out[6], double q_out[4], double t_out[3], double* rho_tilde, double u_star[6],
+                   int32_t flags) {
     const double inv_sqrt6 = 1.0 / sqrt(6.0);
     double rhat[6];
     int aps = 0;
@@ -543,8 +553,11 @@ int orc_pst_update(const double* F, const float* pst, int32_t n, const double r_
             nv = sqrt(nv);
             double rt = (sr + cr) / W;
             *rho_tilde = rt;
-            for (int d = 0; d < 6; ++d)
-                rhat[d] = (1.0 - rt) * (nv > 0.0 ? fabs(u_star[d]) / nv : inv_sqrt6) + eps;
+            const double iso = (flags & ORC_ANISO_ONLY) ? 1.0 : (1.0 - rt);
+            for (int d = 0; d < 6; ++d) {
+                const double dir = (nv > 0.0 && !(flags & ORC_ISO_ONLY)) ? fabs(u_star[d]) / nv : inv_sqrt6;
+                rhat[d] = iso * dir + eps;
+            }
             orc_pose_retract(qc, tc, u_star, q_out, t_out);
         } else {
             *rho_tilde = rho_prev;
@@ -665,7 +678,7 @@ int orc_track_frame(const float* psi, int32_t nx, int32_t ny, int32_t nz, float 
         double centre = tsdf_built ? exp(-F[0] / P->tau) : 0.5;
         double thr_k = (k == 1 || (P->flags & ORC_CENTRE_THRESHOLD)) ? centre : thr;
         int aps = orc_pst_update(F, pst, n, r, qc, tc, P->tau, P->beta, P->eps, tsdf_built, thr_k, r_new, q_new,
-                                 t_new, &rt, us);
+                                 t_new, &rt, us, P->flags);
         thr = (aps > 0) ? rt : thr_k;
         if (k - 1 < 32) {
             aps_sizes[k - 1] = aps;

@@ -260,7 +260,10 @@ __device__ void track_update_body(const UpdateArgs& a) {
             }
             nv = sqrt(nv);
             rt = tot[2] / W;
-            for (int d = 0; d < 6; ++d) rhat[d] = (1.0 - rt) * (nv > 0.0 ? fabs(us[d]) / nv : inv_sqrt6) + a.eps;
+            // Eq. rsinter; the rescaling ablation keeps one of its two parts
+            const double iso = (a.flags & ROSE_FLAG_ANISO_ONLY) ? 1.0 : (1.0 - rt);
+            const bool aniso = nv > 0.0 && !(a.flags & ROSE_FLAG_ISO_ONLY);
+            for (int d = 0; d < 6; ++d) rhat[d] = iso * (aniso ? fabs(us[d]) / nv : inv_sqrt6) + a.eps;
             retract(st->qc, st->tc, us);
             st->rho_last = rt;
             st->have_rho = 1;
@@ -436,6 +439,9 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_cam
                  "pso_track_frame: n_particles = %d out of [1, %d]", n_particles, ROSE_MAX_PARTICLES);
     ROSE_REQUIRE(p->max_iters >= 1 && p->max_iters <= ROSE_MAX_ITERS, ROSE_E_ARG,
                  "pso_track_frame: max_iters = %d out of [1, %d]", p->max_iters, ROSE_MAX_ITERS);
+    ROSE_REQUIRE((p->flags & (ROSE_FLAG_ISO_ONLY | ROSE_FLAG_ANISO_ONLY)) !=
+                     (ROSE_FLAG_ISO_ONLY | ROSE_FLAG_ANISO_ONLY),
+                 ROSE_E_ARG, "pso_track_frame: ISO_ONLY and ANISO_ONLY exclude each other");
     ROSE_REQUIRE(p->levels >= 0 && p->levels <= ROSE_MAX_LEVELS, ROSE_E_ARG,
                  "pso_track_frame: levels = %d out of [0, %d]", p->levels, ROSE_MAX_LEVELS);
     if (p->levels > 1) {
@@ -671,6 +677,9 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
                          (p.lookup == ROSE_LOOKUP_NEAREST || p.lookup == ROSE_LOOKUP_TRILINEAR) && p.tau > 0.0 &&
                          p.beta >= 0.0 && p.beta <= 1.0,
                      ROSE_E_ARG, "pso_batch_create: bad parameters for sequence %d", i);
+        ROSE_REQUIRE((p.flags & (ROSE_FLAG_ISO_ONLY | ROSE_FLAG_ANISO_ONLY)) !=
+                         (ROSE_FLAG_ISO_ONLY | ROSE_FLAG_ANISO_ONLY),
+                     ROSE_E_ARG, "pso_batch_create: ISO_ONLY and ANISO_ONLY exclude each other (sequence %d)", i);
         ROSE_REQUIRE(p.levels <= 1, ROSE_E_UNSUPPORTED,
                      "pso_batch_create: multi-resolution schedules are not batched (sequence %d)", i);
         const uint64_t bytes =

@@ -70,6 +70,10 @@ def test_host_side_argument_errors(R):
     assert lib.pso_track_frame(C.c_void_p(16), C.c_void_p(16), C.byref(cam), C.c_void_p(16), 12, C.byref(params),
                                None, None, C.byref(st), None, None) == R.E_ARG  # level larger than the template
     assert b"level 1" in lib.rose_last_error()
+    params = R.track_params(flags=R.FLAG_ISO_ONLY | R.FLAG_ANISO_ONLY)
+    assert lib.pso_track_frame(C.c_void_p(16), C.c_void_p(16), C.byref(cam), C.c_void_p(16), 16, C.byref(params),
+                               None, None, C.byref(st), None, None) == R.E_ARG
+    params = R.track_params(levels=[(8, 2), (16, 3)])
     params.levels = R.MAX_LEVELS + 1
     assert lib.pso_track_frame(C.c_void_p(16), C.c_void_p(16), C.byref(cam), C.c_void_p(16), 16, C.byref(params),
                                None, None, C.byref(st), None, None) == R.E_ARG

@@ -319,7 +319,7 @@ def test_track_frame_parity(R, orc, small_gpu, lookup, r0):
     assert abs(g["rho"] - o["rho"]) <= 1e-5
 
 
-@pytest.mark.parametrize("flags,early", [(1, False), (2, False), (4, False), (0, True)])
+@pytest.mark.parametrize("flags,early", [(1, False), (2, False), (4, False), (0, True), (8, False), (16, False)])
 def test_track_frame_flags_parity(R, orc, small_gpu, flags, early):
     w, vol, psi, pst = small_gpu
     prev = w.fuse_poses[-1]

@@ -181,3 +181,26 @@ def test_brute_force_grid_agrees_with_search(orc):
         Tf = orc.pose_mat(res["q"], res["t"])[:3]
         Ff = orc.fitness(psi, vox, origin, pts, Tf[None], lookup=1, prec=0)[0]
         assert Ff <= second
+
+
+@pytest.mark.parametrize("flag", ["iso", "aniso"])
+def test_rescaling_ablation_worked_example(orc, flag):
+    """The worked example above with one part of Eq. rsinter switched off:
+    isotropic only -> rhat_d = (1 - 11/12) / sqrt6 + 1e-3 on every axis;
+    anisotropic only -> rhat = |v| / ||v|| + 1e-3.  The centre moves as in
+    the full scheme; the empty-APS branch is unaffected."""
+    pst = _pst([[0] * 6, [0, 0, 0, 0.375, 0, 0], [0, 0, 0, 0, 0.75, 0]])
+    F = [math.log(2.0), math.log(4.0 / 3.0), 0.0]
+    f = orc.ISO_ONLY if flag == "iso" else orc.ANISO_ONLY
+    out = orc.pst_update(F, pst, np.ones(6), [1, 0, 0, 0], [1.0, 2.0, 3.0], flags=f)
+    nv = math.sqrt(17 / 64)
+    if flag == "iso":
+        rhat = np.full(6, (1 / 12) / math.sqrt(6)) + 1e-3
+    else:
+        rhat = np.array([0, 0, 0, 0.125 / nv, 0.5 / nv, 0]) + 1e-3
+    assert out["aps"] == 2
+    assert out["r"] == pytest.approx(0.1 + 0.9 * rhat, abs=1e-14)
+    assert out["t"] == pytest.approx([1.125, 2.5, 3.0], abs=1e-15)
+    empty = orc.pst_update([0.3, 0.5, 0.9], pst, np.full(6, 0.2), [1, 0, 0, 0], [0, 0, 0], flags=f)
+    assert empty["aps"] == 0
+    assert empty["r"] == pytest.approx(0.02 + 0.9 * 2 * (1 - math.exp(-0.3)) / math.sqrt(6), rel=1e-13)
