@@ -222,7 +222,7 @@ def main():
                      "kernel_source_sha256_16": kernel_source_hash()},
     }
     if not args.no_cpu_baseline:
-        log("timing the CPU oracle on one iteration of frame 1")
+        log("timing the CPU oracle on 3 iterations of frame 1")
         out["cpu_baseline"] = cpu_baseline(seq, depths[0], depths[1], p0, seq.n_particles, lookup)
     print(json.dumps(out), flush=True)
     vol.close()
