@@ -118,6 +118,8 @@ def _load():
                                         C.c_int32, C.c_int32, C.c_int, C.c_int, P]
             lib.orc_voxel_indices.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_float, P, P, C.c_int32, P,
                                               C.c_int32, P]
+            lib.orc_pst_poisson.argtypes = [C.c_int32, C.c_uint64, C.c_double, C.c_int32, P, P]
+            lib.orc_pst_poisson.restype = C.c_int32
             lib.orc_pst_update.argtypes = [P, P, C.c_int32, P, P, P, C.c_double, C.c_double, C.c_double,
                                            C.c_int32, C.c_double, P, P, P, P, P, C.c_int32]
             lib.orc_pst_update.restype = C.c_int
@@ -247,6 +249,16 @@ def voxel_indices(dims, vox, origin, pts, T) -> np.ndarray:
     idx = np.zeros((len(T), len(pts)), dtype=np.int64)
     lib.orc_voxel_indices(nx, ny, nz, float(vox), _p(org), _p(pts), len(pts), _p(T), len(T), _p(idx))
     return idx
+
+
+def pst_poisson(n: int, seed: int, r_min: float, max_cand: int):
+    """6D Poisson-disk template by dart throwing over the i.i.d. sampler's
+    stream; returns (n x 6 float32, rows accepted, candidates drawn)."""
+    lib = _load()
+    out = np.zeros((n, 6), dtype=np.float32)
+    drawn = np.zeros(1, dtype=np.int32)
+    got = lib.orc_pst_poisson(int(n), int(seed), float(r_min), int(max_cand), _p(out), _p(drawn))
+    return out, int(got), int(drawn[0])
 
 
 def pst_update(F, pst, r, qc, tc, tau=1.0, beta=0.1, eps=1e-3, tsdf_built=True, rho_thr=None, flags=0):

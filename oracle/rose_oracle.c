@@ -115,6 +115,56 @@ int orc_pst_sample(int32_t n, uint64_t seed, float* out) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* 6D Poisson-disk PST (Sec. 4 "PST pre-sampling": the template is a 6D     */
+/* Poisson-disk sample of the unit ball).  Dart throwing: the candidates   */
+/* are rows 1, 2, ... of orc_pst_sample(seed) (uniform in the unit ball);  */
+/* the origin is accepted first; a candidate is accepted iff its squared   */
+/* distance to every point accepted before it is >= r_min^2.  Distances    */
+/* are taken on the sampler's integer lattice (p = a 2^-24, a odd integers */
+/* below 2^24), where sum (a - b)^2 < 6 * 2^50 is exact in int64; the      */
+/* threshold is d2 = ceil(r_min^2 2^48) evaluated in binary64.             */
+/* Stops when n points are accepted or max_cand candidates were drawn.     */
+/* Returns the number of accepted rows (n on success); rows past it are 0; */
+/* *drawn = the number of candidates drawn.                                */
+/* ------------------------------------------------------------------------ */
+int32_t orc_pst_poisson(int32_t n, uint64_t seed, double r_min, int32_t max_cand, float* out, int32_t* drawn) {
+    const int64_t d2 = (int64_t)ceil(r_min * r_min * 281474976710656.0);
+    float* cand = (float*)malloc(sizeof(float) * 6 * ((size_t)max_cand + 1));
+    int64_t* acc = (int64_t*)malloc(sizeof(int64_t) * 6 * (size_t)(n > 0 ? n : 1));
+    orc_pst_sample(max_cand + 1, seed, cand);
+    for (size_t e = 0; e < 6 * (size_t)n; ++e) out[e] = 0.0f;
+    int32_t count = 0;
+    if (n > 0) {
+        for (int d = 0; d < 6; ++d) acc[d] = 0;
+        count = 1;
+    }
+    int32_t c = 1;
+    for (; c <= max_cand && count < n; ++c) {
+        int64_t a[6];
+        for (int d = 0; d < 6; ++d) a[d] = (int64_t)ldexp((double)cand[6 * (size_t)c + d], 24);
+        int far = 1;
+        for (int32_t k = 0; k < count && far; ++k) {
+            int64_t s = 0;
+            for (int d = 0; d < 6; ++d) {
+                const int64_t df = a[d] - acc[6 * (size_t)k + d];
+                s += df * df;
+            }
+            far = (s >= d2);
+        }
+        if (!far) continue;
+        for (int d = 0; d < 6; ++d) {
+            acc[6 * (size_t)count + d] = a[d];
+            out[6 * (size_t)count + d] = cand[6 * (size_t)c + d];
+        }
+        ++count;
+    }
+    *drawn = c - 1;
+    free(cand);
+    free(acc);
+    return count;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Pose algebra, binary64.  A pose is (q, t): unit quaternion q = (w,x,y,z) */
 /* (Hamilton convention) and translation t; it maps camera to world,        */
 /* X = R(q) x + t (Eq. unproj).                                             */
