@@ -565,5 +565,6 @@ def track_frame_learned(vol: Tsdf, depth: torch.Tensor, K, pst_small: torch.Tens
         C.byref(state), C.byref(stats), C.byref(fb), _stream(stream)))
     it = stats.iters
     return dict(iters=it, n_points=stats.n_points, aps=list(stats.aps_size[:it]),
-                n_overlap=list(stats.n_overlap[:it]), q=list(state.pose.q), t=list(state.pose.t),
-                r1=list(state.r), rho=state.rho, fallback=bool(fb.value))
+                n_overlap=list(stats.n_overlap[:it]), n_particles=list(stats.n_particles[:it]),
+                q=list(state.pose.q), t=list(state.pose.t), r1=list(state.r), rho=state.rho,
+                fallback=bool(fb.value))

@@ -176,7 +176,8 @@ def evaluate(net, P, seeds, n_frames, width, height, n_small=4096, workers=16):
                     r = rose.track_frame_learned(vol, depths[f], sq.K, pst_small, pst_plain, net, P, work, vel,
                                                  params, lp, st)
                     fallbacks += int(r["fallback"])
-                    evals += (10240 if r["fallback"] else n_small) * sum(r["n_overlap"])
+                    # the stats are the final run's (the plain rerun after a fallback)
+                    evals += sum(n * o for n, o in zip(r["n_particles"], r["n_overlap"]))
                 q, t = list(st.pose.q), list(st.pose.t)
                 vel = rose.chart_log(prev[0], prev[1], q, t)
                 prev = (q, t)
