@@ -98,6 +98,27 @@ def copy_probe(torch, mib: int):
     del src, dst
 
 
+def gather_roofline(torch, rose, region_mib: int, reps: int = 5) -> float:
+    """4-byte loads per second of the gather-rate probe: every load from its
+    own pseudo-random 128-byte line of a region of `region_mib` MiB per XCD
+    (2 MiB: L2-resident; 1024 MiB: served by HBM), timed with HIP events on
+    the current stream."""
+    lines = region_mib * (1 << 20) // 128
+    buf = torch.rand(8 * lines * 32, device="cuda")
+    blocks, iters = 2048, 64
+    sink = torch.zeros(blocks, device="cuda")
+    rose.gather_peak(buf, lines, blocks, iters, sink)  # warm
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    loads = 0
+    for _ in range(reps):
+        loads += rose.gather_peak(buf, lines, blocks, iters, sink)
+    e1.record()
+    torch.cuda.synchronize()
+    del buf, sink
+    return loads / (e0.elapsed_time(e1) * 1e-3)
+
+
 def cpu_baseline(seq, depth0, depth, prev_pose, n_particles, lookup, iters=3):
     """The oracle, single-threaded, on the first `iters` iterations of frame
     1 (about 10-15 s of CPU work) against its own fusion of frame 0."""
@@ -221,6 +242,15 @@ def main():
                      "bytes_per_eval": BYTES_PER_EVAL[lookup], "shape": list(tuned["shape"]),
                      "kernel_source_sha256_16": kernel_source_hash()},
     }
+    g_l2 = gather_roofline(torch, rose, 2)
+    g_hbm = gather_roofline(torch, rose, 1024)
+    fit_rate = prof["fitness_evals"] / (prof["fitness_ms"] * 1e-3)
+    out["gather_roofline"] = {
+        "what": "one 4-byte gather per particle-point evaluation, each from its own 128-byte line; peak = "
+                "gather-rate probe with an L2-resident working set (2 MiB per XCD)",
+        "peak_per_s": g_l2, "hbm_resident_peak_per_s": g_hbm, "achieved_evals_per_s": fit_rate,
+        "frac": fit_rate / g_l2}
+    log(f"gather probe: L2-resident {g_l2:.3e}/s, HBM-resident {g_hbm:.3e}/s; fitness {fit_rate:.3e} evals/s")
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on 3 iterations of frame 1")
         out["cpu_baseline"] = cpu_baseline(seq, depths[0], depths[1], p0, seq.n_particles, lookup)

@@ -397,6 +397,21 @@ rose_status rose_profile_enable(int32_t on);
 rose_status rose_profile_reset(void);
 rose_status rose_profile_read(rose_profile* out);
 
+/* ------------------------------------------------------------ measurement */
+/* Gather-rate probe (the roofline of the fitness kernel's TSDF reads): a
+ * launch of `blocks` workgroups of 256 lanes (blocks a positive multiple of
+ * 8), each lane issuing iters * rose_gather_peak_loads_per_lane()
+ * independent 4-byte loads, every load from a pseudo-random 128-byte line of
+ * one of 8 regions of region_lines lines (a power of two <= 2^26), region
+ * b mod 8 for workgroup b (one region per XCD).  buf_dev must hold
+ * 8 * region_lines * 32 floats (E_SHAPE otherwise); sink_dev (blocks floats)
+ * is never written for finite buffer contents.  Asynchronous on s; the
+ * caller times it with events on s.  Not part of the method: bench.py uses
+ * it to state the kernel's gather roofline. */
+rose_status rose_gather_peak(const float* buf_dev, int64_t buf_elems, int32_t region_lines, int32_t blocks,
+                             int32_t iters, uint32_t seed, float* sink_dev, hipStream_t s);
+int32_t rose_gather_peak_loads_per_lane(void);
+
 #ifdef __cplusplus
 }
 #endif

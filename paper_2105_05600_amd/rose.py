@@ -125,6 +125,8 @@ _sigs = {
     "rose_profile_enable": ([C.c_int32], C.c_int),
     "rose_profile_reset": ([], C.c_int),
     "rose_profile_read": ([C.POINTER(Profile)], C.c_int),
+    "rose_gather_peak": ([_P, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_uint32, _P, _S], C.c_int),
+    "rose_gather_peak_loads_per_lane": ([], C.c_int32),
 }
 for _name, (_args, _res) in _sigs.items():
     _f = getattr(_lib, _name)
@@ -386,6 +388,20 @@ def profile_enable(on: bool = True):
 
 def profile_reset():
     _check("rose_profile_reset", _lib.rose_profile_reset())
+
+
+def gather_peak(buf: torch.Tensor, region_lines: int, blocks: int, iters: int, sink: torch.Tensor, seed: int = 1,
+                stream=None) -> int:
+    """Enqueue the gather-rate probe (rose_gather_peak) on `stream`; returns
+    the number of 4-byte loads it issues."""
+    _dev(buf, torch.float32, "buf")
+    _dev(sink, torch.float32, "sink")
+    if sink.numel() < blocks:
+        raise ValueError("sink needs one float per workgroup")
+    _check("rose_gather_peak", _lib.rose_gather_peak(_ptr(buf), buf.numel(), int(region_lines), int(blocks),
+                                                     int(iters), int(seed) & 0xFFFFFFFF, _ptr(sink),
+                                                     _stream(stream)))
+    return int(blocks) * 256 * int(iters) * int(_lib.rose_gather_peak_loads_per_lane())
 
 
 def profile_read() -> dict:
