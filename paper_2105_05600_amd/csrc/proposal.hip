@@ -39,34 +39,52 @@ struct RaycastArgs {
     float* out;
 };
 
-// one thread per pixel; fixed-step march, first + to - crossing inside the
-// truncation band, linear interpolation of the crossing
+// One wavefront per pixel: the fixed-step march of the ray is evaluated 64
+// samples at a time, lane j taking sample k = base + j (z = near + k step,
+// the same expression as a serial march, so the samples are identical).  A
+// crossing at k is a + to - change between samples k-1 and k inside the
+// truncation band; sample k-1 comes from the lane below (lane 0 keeps the
+// previous chunk's last sample).  The first crossing in step order -- the
+// lowest lane of the first chunk that has one -- gives the depth by linear
+// interpolation, exactly as a serial march stopping there would.
 template <int FMT>
 __global__ __launch_bounds__(256) void k_raycast(RaycastArgs a) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= a.W * a.H) return;
-    const int u = idx % a.W, v = idx / a.W;
+    const int lane = threadIdx.x & 63;
+    const int64_t idx = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (idx >= (int64_t)a.W * a.H) return;  // whole wavefronts leave together
+    const int u = (int)(idx % a.W), v = (int)(idx / a.W);
     const double dc[3] = {((double)u - a.cx) / a.fx, ((double)v - a.cy) / a.fy, 1.0};
     double dw[3];
     for (int i = 0; i < 3; ++i) dw[i] = a.R[3 * i + 0] * dc[0] + a.R[3 * i + 1] * dc[1] + a.R[3 * i + 2] * dc[2];
-    double prev = 0.0, zprev = 0.0, out = 0.0;
-    bool have = false;
     const double vox = (double)a.g.vox;
-    for (int64_t k = 0;; ++k) {
+    double carry = 0.0;  // sample base - 1 (from the previous chunk)
+    double out = 0.0;
+    for (int64_t base = 0;; base += kWave) {
+        const int64_t k = base + lane;
         const double z = a.near_z + (double)k * a.step;
-        if (z > a.far_z) break;
-        double h[3];
-        for (int c = 0; c < 3; ++c) h[c] = (a.t[c] + z * dw[c] - (double)a.g.origin[c]) / vox - 0.5;
-        const double s = trilinear64<FMT>(a.g, h[0], h[1], h[2]);
-        if (have && prev > 0.0 && s <= 0.0 && prev < 1.0 && s > -1.0) {
-            out = zprev + a.step * prev / (prev - s);
+        const bool valid = !(z > a.far_z);
+        double s = 0.0;
+        if (valid) {
+            double h[3];
+            for (int c = 0; c < 3; ++c) h[c] = (a.t[c] + z * dw[c] - (double)a.g.origin[c]) / vox - 0.5;
+            s = trilinear64<FMT>(a.g, h[0], h[1], h[2]);
+        }
+        double prev = __shfl_up(s, 1, kWave);
+        if (lane == 0) prev = carry;
+        const bool cross = valid && k >= 1 && prev > 0.0 && s <= 0.0 && prev < 1.0 && s > -1.0;
+        const uint64_t hits = __ballot(cross);
+        if (hits) {
+            const int first = __ffsll((unsigned long long)hits) - 1;
+            const double zp = a.near_z + (double)(k - 1) * a.step;
+            const double o = zp + a.step * prev / (prev - s);
+            out = __shfl(o, first, kWave);
             break;
         }
-        prev = s;
-        zprev = z;
-        have = true;
+        // any lane past `far` ends the march (later chunks are all past it)
+        if (__ballot(!valid)) break;
+        carry = __shfl(s, kWave - 1, kWave);
     }
-    a.out[idx] = (float)out;
+    if (lane == 0) a.out[idx] = (float)out;
 }
 
 struct FeatureArgs {
@@ -122,7 +140,7 @@ rose_status tsdf_raycast(const rose_tsdf* h, const rose_pose* T_wc, const rose_c
     a.fx = cam->fx; a.fy = cam->fy; a.cx = cam->cx; a.cy = cam->cy;
     a.near_z = near_m; a.far_z = far_m; a.step = step_m;
     a.out = depth_out_dev;
-    const unsigned blocks = (unsigned)((a.W * a.H + 255) / 256);
+    const unsigned blocks = (unsigned)((a.W * a.H + 3) / 4);  // 4 pixels (wavefronts) per workgroup
     if (h->g.fmt == ROSE_TSDF_F32) hipLaunchKernelGGL(k_raycast<ROSE_TSDF_F32>, dim3(blocks), dim3(256), 0, s, a);
     else if (h->g.fmt == ROSE_TSDF_F16) hipLaunchKernelGGL(k_raycast<ROSE_TSDF_F16>, dim3(blocks), dim3(256), 0, s, a);
     else hipLaunchKernelGGL(k_raycast<ROSE_TSDF_SN16>, dim3(blocks), dim3(256), 0, s, a);
