@@ -111,6 +111,7 @@ def generate(seeds, n_frames, width, height, chunk, workers):
 
 
 def train(X, Y, epochs, batch, lr, seed):
+    """Adam on the Gaussian NLL with a cosine learning-rate decay to lr/20."""
     net = rose.Mlp(FEATURE_DIM, 256, 12, max_batch=batch)
     P = net.pack(mlp_init.init_params(seed))
     G = torch.zeros_like(P)
@@ -121,6 +122,7 @@ def train(X, Y, epochs, batch, lr, seed):
     g = torch.Generator(device="cpu").manual_seed(seed)
     step = 0
     hist = []
+    steps_total = max(1, epochs * (n // batch))
     for ep in range(epochs):
         perm = torch.randperm(n, generator=g).cuda()
         tot, cnt = 0.0, 0
@@ -130,7 +132,8 @@ def train(X, Y, epochs, batch, lr, seed):
             yb = Y[idx].contiguous()
             net.loss_grad(P, xb, yb, G, loss)
             step += 1
-            rose.Mlp.adam(P, G, M, V, step, lr)
+            lr_t = lr * (0.05 + 0.95 * 0.5 * (1.0 + math.cos(math.pi * min(step, steps_total) / steps_total)))
+            rose.Mlp.adam(P, G, M, V, step, lr_t)
             tot += float(loss.item())
             cnt += 1
         hist.append(tot / max(cnt, 1))
@@ -139,22 +142,27 @@ def train(X, Y, epochs, batch, lr, seed):
     return net, P, hist
 
 
-def evaluate(net, P, seeds, n_frames, width, height, n_small=4096, workers=16):
+def evaluate(net, P, seeds, n_frames, width, height, n_small=4096, workers=16, kappa=2.0, delta=0.01,
+             modes=("plain", "learned"), nets=None):
     """Plain 10240-particle PST vs learned proposal + 4096 particles with the
     plain fallback, on identical held-out sequences: ATE (RMSE, Horn
-    alignment) and frames/s of the tracking calls."""
+    alignment) and frames/s of the tracking calls.  `nets` optionally maps
+    further mode names to other parameter vectors (e.g. an untrained
+    network) run like "learned"."""
     scale = width // LOW_W
     pst_plain = rose.pst_sample(10240, 5600)
     pst_small = rose.pst_sample(n_small, 5600)
     work = torch.zeros(LOW_W * LOW_H + FEATURE_DIM + 12, dtype=torch.float32, device="cuda")
-    lp = rose.learned_params(scale=scale)
+    lp = rose.learned_params(scale=scale, kappa=kappa, delta=delta)
+    nets = dict(nets or {})
+    nets.setdefault("learned", P)
     out = []
     for seed in seeds:
         sq = make_sequence(seed, n_frames, width, height)
         depths = [torch.from_numpy(d).cuda() for d in sq.depths(range(n_frames), workers=workers)]
         gt = np.array([p.t for p in sq.poses[:n_frames]])
         row = {"seed": seed}
-        for mode in ("plain", "learned"):
+        for mode in modes:
             vol = rose.Tsdf(sq.dims, sq.vox, sq.mu, sq.origin)
             params = rose.track_params(max_iters=20, stride=4)
             st = rose.track_state(sq.poses[0].q, sq.poses[0].t, [1.0] * 6, tsdf_built=False)
@@ -173,8 +181,8 @@ def evaluate(net, P, seeds, n_frames, width, height, n_small=4096, workers=16):
                     r = rose.track_frame(vol, depths[f], sq.K, pst_plain, params, st)
                     evals += 10240 * sum(r["n_overlap"])
                 else:
-                    r = rose.track_frame_learned(vol, depths[f], sq.K, pst_small, pst_plain, net, P, work, vel,
-                                                 params, lp, st)
+                    r = rose.track_frame_learned(vol, depths[f], sq.K, pst_small, pst_plain, net, nets[mode], work,
+                                                 vel, params, lp, st)
                     fallbacks += int(r["fallback"])
                     # the stats are the final run's (the plain rerun after a fallback)
                     evals += sum(n * o for n, o in zip(r["n_particles"], r["n_overlap"]))
@@ -192,6 +200,17 @@ def evaluate(net, P, seeds, n_frames, width, height, n_small=4096, workers=16):
         log(f"eval seed {seed}: {json.dumps(row)}")
         out.append(row)
     return out
+
+
+def summarize(rows, modes):
+    """Mean ATE and total frames/s per mode over evaluated sequences."""
+    res = {}
+    for m in modes:
+        ate = [r[m]["ate_rmse_m"] for r in rows]
+        fps = [r[m]["frames_per_s"] for r in rows]
+        res[m] = {"ate_rmse_mean_m": float(np.mean(ate)), "frames_per_s_mean": float(np.mean(fps)),
+                  "fallbacks": int(sum(r[m].get("fallbacks", 0) for r in rows))}
+    return res
 
 
 def save(path, net, P, meta):
@@ -217,6 +236,11 @@ def main():
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--batch", type=int, default=512)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--load", default=None, help="skip data generation and training; load these weights")
+    ap.add_argument("--kappas", default="2", help="comma-separated kappa values tried on the validation set")
+    ap.add_argument("--deltas", default="0.01", help="comma-separated fallback deltas tried on the validation set")
+    ap.add_argument("--val-sequences", type=int, default=4)
+    ap.add_argument("--val-frames", type=int, default=60)
     ap.add_argument("--eval-sequences", type=int, default=4)
     ap.add_argument("--eval-frames", type=int, default=90)
     ap.add_argument("--workers", type=int, default=16)
@@ -224,19 +248,46 @@ def main():
                                                   "proposal.npz"))
     args = ap.parse_args()
     torch.cuda.set_device(0)
-    seeds = [10000 + 10 * i for i in range(args.sequences)]
-    t0 = time.perf_counter()
-    X, Y = generate(seeds, args.frames, args.width, args.height, args.chunk, args.workers)
-    t_gen = time.perf_counter() - t0
-    log(f"{X.shape[0]} pairs in {t_gen:.1f} s; |y| mean {Y.abs().mean(0).tolist()}")
-    t0 = time.perf_counter()
-    net, P, hist = train(X, Y, args.epochs, args.batch, args.lr, seed=1)
-    t_train = time.perf_counter() - t0
+    meta = {}
+    if args.load:
+        net = rose.Mlp(FEATURE_DIM, 256, 12, max_batch=args.batch)
+        P = net.pack(load(args.load))
+        with open(os.path.splitext(args.load)[0] + ".json") as f:
+            meta = json.load(f)
+        meta.pop("eval", None)
+        meta.pop("validation", None)
+    else:
+        seeds = [10000 + 10 * i for i in range(args.sequences)]
+        t0 = time.perf_counter()
+        X, Y = generate(seeds, args.frames, args.width, args.height, args.chunk, args.workers)
+        t_gen = time.perf_counter() - t0
+        log(f"{X.shape[0]} pairs in {t_gen:.1f} s; |y| mean {Y.abs().mean(0).tolist()}")
+        t0 = time.perf_counter()
+        net, P, hist = train(X, Y, args.epochs, args.batch, args.lr, seed=1)
+        t_train = time.perf_counter() - t0
+        meta = {"pairs": int(X.shape[0]), "sequences": args.sequences, "frames": args.frames,
+                "image": [args.width, args.height], "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
+                "generation_s": t_gen, "training_s": t_train, "nll_history": hist}
+        del X, Y
+    # fallback parameters chosen on validation sequences (seeds 30000+), never on the test sequences
+    val_seeds = [30000 + 10 * i for i in range(args.val_sequences)]
+    grid = [(float(k), float(d)) for k in args.kappas.split(",") for d in args.deltas.split(",")]
+    val = []
+    for kappa, delta in grid:
+        rows = evaluate(net, P, val_seeds, args.val_frames, args.width, args.height, workers=args.workers,
+                        kappa=kappa, delta=delta, modes=("learned",))
+        sm = summarize(rows, ("learned",))["learned"]
+        val.append({"kappa": kappa, "delta": delta, **sm})
+        log(f"validation kappa {kappa} delta {delta}: {json.dumps(sm)}")
+    best = min(val, key=lambda v: v["ate_rmse_mean_m"])
+    log(f"chosen kappa {best['kappa']} delta {best['delta']}")
+    untrained = net.pack(mlp_init.init_params(1))
     ev = evaluate(net, P, [20000 + 10 * i for i in range(args.eval_sequences)], args.eval_frames, args.width,
-                  args.height, workers=args.workers)
-    meta = {"pairs": int(X.shape[0]), "sequences": args.sequences, "frames": args.frames,
-            "image": [args.width, args.height], "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
-            "generation_s": t_gen, "training_s": t_train, "nll_history": hist, "eval": ev}
+                  args.height, workers=args.workers, kappa=best["kappa"], delta=best["delta"],
+                  modes=("plain", "learned", "untrained"), nets={"untrained": untrained})
+    meta.update({"kappa": best["kappa"], "delta": best["delta"], "validation": val, "eval": ev,
+                 "eval_summary": summarize(ev, ("plain", "learned", "untrained"))})
+    log(f"test summary: {json.dumps(meta['eval_summary'])}")
     save(args.out, net, P, meta)
     log(f"saved {args.out}")
 
