@@ -14,8 +14,8 @@ The network (1216 -> 256 GELU -> 256 GELU -> 12 = mean and log-scale) is
 trained with the Gaussian negative log-likelihood and Adam, all on the GPU
 with the library's BF16 matrix-core kernels.
 
-Usage: python -m paper_2105_05600_amd.train_proposal --sequences 64 \
-           --frames 160 --out paper_2105_05600_amd/weights/proposal.npz
+Usage: python -m paper_2105_05600_amd.train_proposal --sequences 192 --epochs 150 \
+           --kappas 1.5,2,3,4 --deltas 0.005,0.01,0.02 --eval-sequences 6 --eval-frames 120
 """
 from __future__ import annotations
 
