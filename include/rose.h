@@ -148,6 +148,21 @@ rose_status tsdf_import(rose_tsdf* h, const float* psi_lin_dev, const float* wei
  * Errors: ROSE_E_ARG (n < 1 or > ROSE_MAX_PARTICLES, NULL). */
 rose_status pst_sample(int32_t n, uint64_t seed, float* out_dev, hipStream_t s);
 
+/* 6D Poisson-disk PST template (Sec. 4 "PST pre-sampling" samples the
+ * template as a 6D Poisson disk) by dart throwing over pst_sample's stream:
+ * the candidates are rows 1, 2, ... of pst_sample(max_candidates + 1, seed)
+ * (written to work_dev, (max_candidates + 1) x 6 floats); row 0 (origin) is
+ * accepted first; a candidate is accepted iff its squared distance to every
+ * point accepted before it is >= r_min^2, decided exactly on the sampler's
+ * lattice (threshold ceil(r_min^2 2^48) in units of 2^-48).  Stops at n rows
+ * or after max_candidates candidates.  out_dev: n x 6, accepted rows in
+ * acceptance order, the rest 0.  result_dev (2 int32): rows accepted (n on
+ * success), candidates drawn.  r_min in [0, 2]; r_min = 0 gives
+ * pst_sample's template.  1 <= n <= ROSE_MAX_PARTICLES; max_candidates in
+ * [0, 2^24].  Asynchronous on s. */
+rose_status pst_poisson(int32_t n, uint64_t seed, double r_min, int32_t max_candidates, float* work_dev,
+                        float* out_dev, int32_t* result_dev, hipStream_t s);
+
 /* Particle poses (Alg. 1 MovePST + RescalePST applied on the fly to the
  * stored unit template, Sec. 4 "GPU implementation"): for each row p_i,
  * u = r (.) p_i and pose_i = c * Delta(u), Delta(u) = (quaternion

@@ -344,6 +344,9 @@ int fitness_blocks(const FitLaunch& L, int P);
 rose_status launch_fitness_batch(const FitLaunch* seqs_dev, const int* begin_dev, int count, int total, int grid,
                                  int P, int U, hipStream_t s);
 
+// PST template rows 0..n-1 (tsdf.hip)
+rose_status launch_pst_sample(int64_t n, uint64_t seed, float* out_dev, hipStream_t s);
+
 // kernel timing (profile.hip)
 enum { PROF_FITNESS = 0, PROF_UPDATE = 1, PROF_INTEGRATE = 2 };
 bool prof_on();

@@ -307,6 +307,20 @@ rose_status tsdf_import(rose_tsdf* h, const float* psi_lin_dev, const float* wei
     return ROSE_OK;
 }
 
+}  // extern "C"
+
+namespace rose {
+// rows 0..n-1 of the template (any n >= 1; the Poisson-disk sampler draws
+// its candidates from the same stream)
+rose_status launch_pst_sample(int64_t n, uint64_t seed, float* out_dev, hipStream_t s) {
+    hipLaunchKernelGGL(k_pst_sample, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (int32_t)n, seed, out_dev);
+    ROSE_CHECK_HIP(hipGetLastError());
+    return ROSE_OK;
+}
+}  // namespace rose
+
+extern "C" {
+
 rose_status pst_sample(int32_t n, uint64_t seed, float* out_dev, hipStream_t s) {
     clear_error();
     ROSE_REQUIRE(out_dev != nullptr, ROSE_E_ARG, "pst_sample: NULL output");

@@ -125,6 +125,7 @@ _sigs = {
     "rose_profile_enable": ([C.c_int32], C.c_int),
     "rose_profile_reset": ([], C.c_int),
     "rose_profile_read": ([C.POINTER(Profile)], C.c_int),
+    "pst_poisson": ([C.c_int32, C.c_uint64, C.c_double, C.c_int32, _P, _P, _P, _S], C.c_int),
     "rose_gather_peak": ([_P, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_uint32, _P, _S], C.c_int),
     "rose_gather_peak_loads_per_lane": ([], C.c_int32),
 }
@@ -388,6 +389,26 @@ def profile_enable(on: bool = True):
 
 def profile_reset():
     _check("rose_profile_reset", _lib.rose_profile_reset())
+
+
+def pst_poisson(n: int, seed: int, r_min: float, max_candidates: int, stream=None):
+    """6D Poisson-disk template (pst_poisson): (n x 6 float32 tensor, rows
+    accepted, candidates drawn).  Synchronises the stream to read the
+    counts."""
+    work = torch.empty((max_candidates + 1) * 6, dtype=torch.float32, device="cuda")
+    out = torch.empty((n, 6), dtype=torch.float32, device="cuda")
+    res = torch.zeros(2, dtype=torch.int32, device="cuda")
+    _check("pst_poisson", _lib.pst_poisson(int(n), int(seed), float(r_min), int(max_candidates), _ptr(work),
+                                           _ptr(out), _ptr(res), _stream(stream)))
+    got, drawn = res.cpu().tolist()
+    return out, int(got), int(drawn)
+
+
+def poisson_radius(n: int, packing: float = 0.03) -> float:
+    """Minimum distance for an n-point template at a given packing fraction
+    n (r/2)^6 of the unit ball (0.03: dart throwing draws about 2.3 n to
+    2.7 n candidates for n = 1024 to 10240)."""
+    return 2.0 * (packing / n) ** (1.0 / 6.0)
 
 
 def gather_peak(buf: torch.Tensor, region_lines: int, blocks: int, iters: int, sink: torch.Tensor, seed: int = 1,
