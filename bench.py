@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--schedule", choices=["single", "multires"], default="single",
                     help="multires: the paper's alternation (1024, 1/8), (3072, 1/16), (10240, 1/32) as strides "
                          "3, 4, 6")
+    ap.add_argument("--template", choices=["iid", "poisson"], default="iid",
+                    help="poisson: 6D Poisson-disk template (dart throwing, packing fraction 0.03)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--render-workers", type=int, default=16)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -164,7 +166,13 @@ def main():
         copy_probe(torch, args.copy_probe)
     dev_depths = [torch.from_numpy(d).cuda() for d in depths]
     vol = rose.Tsdf(seq.dims, seq.vox, seq.mu, seq.origin)
-    pst = rose.pst_sample(seq.n_particles, 5600)
+    if args.template == "poisson":
+        pst, got, drawn = rose.pst_poisson(seq.n_particles, 5600, rose.poisson_radius(seq.n_particles), 1 << 22)
+        if got != seq.n_particles:
+            raise SystemExit(f"Poisson-disk template: only {got} rows after {drawn} candidates")
+        log(f"Poisson-disk template: {drawn} candidates for {got} rows")
+    else:
+        pst = rose.pst_sample(seq.n_particles, 5600)
     levels = MULTIRES_LEVELS if args.schedule == "multires" else None
     params = rose.track_params(max_iters=seq.iters, stride=seq.stride, lookup=lookup, levels=levels)
     p0 = seq.poses[0]
@@ -228,7 +236,8 @@ def main():
         "config": {"workload": "room sequence, 512^3 TSDF @1cm f32, 640x480 f=525 stride 4, PST 10240, "
                                "20 iterations + fusion per frame, 3 m/s 2 rad/s",
                    "tsdf": [512, 512, 512], "voxel_m": 0.01, "image": [640, 480], "stride": 4,
-                   "particles": seq.n_particles, "iters": seq.iters, "lookup": args.lookup, "schedule": args.schedule},
+                   "particles": seq.n_particles, "iters": seq.iters, "lookup": args.lookup, "schedule": args.schedule,
+                   "template": args.template},
         "frames_per_s": args.steps / wall,
         "fitness_kernel_evals_per_s": prof["fitness_evals"] / (prof["fitness_ms"] * 1e-3),
         "ate_rmse_m": ate_rmse,

@@ -1,0 +1,172 @@
+"""Ablation experiments of the paper's Sec. 5 on synthetic sequences, run
+through the library (one GPU).
+
+  rescale   Fig. "ablation of rescaling": PST rescaling with both parts of
+            Eq. rsinter, with the isotropic part only and with the
+            anisotropic part only, on three sets of sequences -- motion along
+            or about one camera axis (0.5-4 m/s, 0.2-5 rad/s), pure 3D
+            rotation (0.2-5 rad/s) and 6D motion (1-4 m/s).  Reported: the
+            average fitness (rho~ of Eq. wafit; the threshold when the APS is
+            empty) at every iteration over all frames, with its 10th and
+            90th percentiles.
+  tsdf      Tab. "TSDF normalisation": the fitness with and without the
+            overlap set O_k (Eq. validness) and with and without the
+            normalisation of Eq. normallh; ATE on the 6D set.
+  multires  Fig. "multi-resolution": the alternating (1024, 1/8),
+            (3072, 1/16), (10240, 1/32) schedule (strides 3, 4, 6) against
+            each single setting and the 10240-particle stride-4 default;
+            ATE and tracking time per frame on the 6D set.
+  template  i.i.d. uniform template vs the 6D Poisson-disk template (Sec. 4
+            "PST pre-sampling"); ATE and time per frame on the 6D set.
+
+Every sequence is tracked frame by frame (20 iterations, fusion at the
+tracked pose) from its first ground-truth pose.  ATE: translation RMSE after
+Horn alignment.  320x240 depth (f = 262.5), 512^3 TSDF at 1 cm, mu = 15 cm.
+
+Usage: python -m paper_2105_05600_amd.ablation --out results.json \\
+           [--experiments rescale,tsdf,multires,template] [--sequences 10]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+from paper_2105_05600_amd import rose  # noqa: E402
+
+ITERS = 20
+MULTIRES = [(1024, 3), (3072, 4), (10240, 6)]
+
+
+def log(msg):
+    print(f"[ablation] {msg}", flush=True)
+
+
+def track(sq, depths, pst, params):
+    """Track a sequence; returns (ATE RMSE, ms per frame of the tracking
+    calls, per-frame rho~ per iteration)."""
+    vol = rose.Tsdf(sq.dims, sq.vox, sq.mu, sq.origin)
+    p0 = sq.poses[0]
+    st = rose.track_state(p0.q, p0.t, [1.0] * 6, tsdf_built=False)
+    rose.track_frame(vol, depths[0], sq.K, pst, params, st)
+    vol.integrate(depths[0], sq.K, p0.q, p0.t)
+    st.tsdf_built = 1
+    est = [np.array(p0.t)]
+    rho = []
+    t_track = 0.0
+    for f in range(1, len(depths)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            r = rose.track_frame(vol, depths[f], sq.K, pst, params, st)
+        except rose.RoseError as e:  # a frame without valid depth: the pose is kept
+            if e.status != rose.E_STATE:
+                raise
+            r = None
+        t_track += time.perf_counter() - t0
+        if r is not None:
+            rho.append(r["rho_iter"] + [r["rho_iter"][-1]] * (ITERS - len(r["rho_iter"])))
+        est.append(np.array(st.pose.t))
+        vol.integrate(depths[f], sq.K, st.pose.q, st.pose.t)
+    vol.close()
+    gt = np.array([p.t for p in sq.poses[:len(depths)]])
+    _, rmse = synth.ate(np.array(est), gt)
+    return float(rmse), 1e3 * t_track / (len(depths) - 1), rho
+
+
+def sequences(kind, n, frames, base):
+    for i in range(n):
+        sq = synth.configs.ablation_sequence(kind, base + 10 * i, frames)
+        yield base + 10 * i, sq, [torch.from_numpy(d).cuda() for d in sq.depths(range(frames), workers=16)]
+
+
+def exp_rescale(n_seq, frames, pst):
+    out = {}
+    variants = {"both": 0, "iso_only": rose.FLAG_ISO_ONLY, "aniso_only": rose.FLAG_ANISO_ONLY}
+    for kind, base in (("1d", 61000), ("3d", 62000), ("6d", 63000)):
+        curves = {v: [] for v in variants}
+        ates = {v: [] for v in variants}
+        for seed, sq, depths in sequences(kind, n_seq, frames, base):
+            for v, flag in variants.items():
+                ate, ms, rho = track(sq, depths, pst, rose.track_params(max_iters=ITERS, stride=4, flags=flag))
+                curves[v].extend(rho)
+                ates[v].append(ate)
+        res = {}
+        for v in variants:
+            a = np.array(curves[v])  # frames x iterations
+            res[v] = {"mean": a.mean(0).tolist(), "p10": np.percentile(a, 10, axis=0).tolist(),
+                      "p90": np.percentile(a, 90, axis=0).tolist(), "ate_rmse_mean_m": float(np.mean(ates[v]))}
+            log(f"rescale {kind} {v}: rho~ at iterations 1/5/10/20 "
+                f"{res[v]['mean'][0]:.4f} {res[v]['mean'][4]:.4f} {res[v]['mean'][9]:.4f} {res[v]['mean'][19]:.4f}; "
+                f"ATE {res[v]['ate_rmse_mean_m']:.4f} m")
+        out[kind] = res
+    return out
+
+
+def exp_variants(n_seq, frames, variants, base):
+    """variants: name -> (pst, params); returns per-variant ATE and time."""
+    rows = {v: {"ate": [], "ms": []} for v in variants}
+    for seed, sq, depths in sequences("6d", n_seq, frames, base):
+        for v, (pst, params) in variants.items():
+            ate, ms, _ = track(sq, depths, pst, params)
+            rows[v]["ate"].append(ate)
+            rows[v]["ms"].append(ms)
+    res = {}
+    for v, r in rows.items():
+        res[v] = {"ate_rmse_mean_m": float(np.mean(r["ate"])), "ate_rmse_median_m": float(np.median(r["ate"])),
+                  "ms_per_frame": float(np.mean(r["ms"])), "ate_per_sequence": r["ate"]}
+        log(f"{v}: ATE mean {res[v]['ate_rmse_mean_m']:.4f} m median {res[v]['ate_rmse_median_m']:.4f} m, "
+            f"{res[v]['ms_per_frame']:.2f} ms/frame")
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--experiments", default="rescale,tsdf,multires,template")
+    ap.add_argument("--sequences", type=int, default=10)
+    ap.add_argument("--frames", type=int, default=60)
+    ap.add_argument("--out", required=True)
+    args = ap.parse_args()
+    torch.cuda.set_device(0)
+    pst = rose.pst_sample(10240, 5600)
+    exps = args.experiments.split(",")
+    res = {"sequences": args.sequences, "frames": args.frames}
+    if "rescale" in exps:
+        res["rescale"] = exp_rescale(args.sequences, args.frames, pst)
+    if "tsdf" in exps:
+        res["tsdf"] = exp_variants(args.sequences, args.frames, {
+            "full": (pst, rose.track_params(max_iters=ITERS, stride=4)),
+            "no_overlap": (pst, rose.track_params(max_iters=ITERS, stride=4, flags=rose.FLAG_NO_OVERLAP)),
+            "no_normalize": (pst, rose.track_params(max_iters=ITERS, stride=4, flags=rose.FLAG_NO_NORMALIZE)),
+        }, 64000)
+    if "multires" in exps:
+        var = {"single_10240_s4": (pst, rose.track_params(max_iters=ITERS, stride=4)),
+               "alternating": (pst, rose.track_params(max_iters=ITERS, levels=MULTIRES))}
+        for n, s in MULTIRES:
+            var[f"single_{n}_s{s}"] = (pst[:n].contiguous(), rose.track_params(max_iters=ITERS, stride=s))
+        res["multires"] = exp_variants(args.sequences, args.frames, var, 65000)
+    if "template" in exps:
+        ppd, got, drawn = rose.pst_poisson(10240, 5600, rose.poisson_radius(10240), 1 << 22)
+        assert got == 10240, (got, drawn)
+        res["template"] = exp_variants(args.sequences, args.frames, {
+            "iid": (pst, rose.track_params(max_iters=ITERS, stride=4)),
+            "poisson": (ppd, rose.track_params(max_iters=ITERS, stride=4)),
+        }, 66000)
+    os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+    with open(args.out, "w") as f:
+        json.dump(res, f, indent=1)
+    log(f"wrote {args.out}")
+
+
+if __name__ == "__main__":
+    main()

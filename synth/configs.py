@@ -198,3 +198,73 @@ def room_sequence(scene_seed: int = 7, traj_seed: int = 11, noise_seed: int = 13
     poses = fast_trajectory(scene, traj_seed, n_frames, fps, speed, ang_speed)
     return Sequence(scene, K, (dim, dim, dim), vox, np.zeros(3), mu, poses, noise_seed, 0.002, 0.2, 6.0,
                     stride, n_particles, iters)
+
+
+def _free_point(scene: Scene, rng, clearance: float) -> np.ndarray:
+    lo, hi = scene.room_lo, scene.room_hi
+    for _ in range(10000):
+        p = rng.uniform(lo + clearance, hi - clearance)
+        if scene.sdf(p[None])[0] >= clearance:
+            return p
+    raise RuntimeError("no free point")
+
+
+def axis_motion(scene: Scene, seed: int, n_frames: int, fps: float, kind: str) -> List[Pose]:
+    """Motions of the rescaling ablation's sequence sets.
+    kind "1d": translation along, or rotation about, one camera axis (chosen
+    by the seed), with the speed varying smoothly in [0.5, 4] m/s or
+    [0.2, 5] rad/s; a translating camera turns back when it would come
+    within 0.5 m of the room's boxes or walls.  kind "3d": rotation only,
+    about a smoothly varying body axis at [0.2, 5] rad/s, from a fixed
+    free-space point.  Every camera starts looking at the room centre."""
+    rng = np.random.default_rng(seed)
+    centre = 0.5 * (scene.room_lo + scene.room_hi)
+    t = _free_point(scene, rng, 0.8)
+    R = look_rotation(centre - t)
+    dt = 1.0 / fps
+    f1, p1 = rng.uniform(0.1, 0.5), rng.uniform(0, 2 * np.pi)
+    axis = int(rng.integers(3))
+    translate = kind == "1d" and bool(rng.integers(2))
+    freqs = rng.uniform(0.05, 0.4, size=(3, 3))
+    phases = rng.uniform(0, 2 * np.pi, size=(3, 3))
+    sign = 1.0
+    poses = []
+    for k in range(n_frames):
+        poses.append(Pose(R.copy(), t.copy()))
+        tk = k * dt
+        level = 0.5 + 0.5 * np.sin(2 * np.pi * f1 * tk + p1)
+        if translate:
+            v = 0.5 + 3.5 * level
+            d = R[:, axis] * sign
+            nxt = t + v * dt * d
+            if scene.sdf(nxt[None])[0] < 0.5 or np.any(nxt < scene.room_lo + 0.5) or np.any(nxt > scene.room_hi - 0.5):
+                sign = -sign
+                nxt = t - v * dt * d
+            t = nxt
+        else:
+            w = 0.2 + 4.8 * level
+            if kind == "1d":
+                a = np.zeros(3)
+                a[axis] = 1.0
+            else:
+                a = np.array([np.sum(np.sin(2 * np.pi * freqs[d] * tk + phases[d])) for d in range(3)])
+                a = a / max(np.linalg.norm(a), 1e-9)
+            R = R @ axis_angle(a, w * dt)
+            U, _, Vt = np.linalg.svd(R)
+            R = U @ Vt
+    return poses
+
+
+def ablation_sequence(kind: str, seed: int, n_frames: int = 60, width: int = 320, height: int = 240,
+                      dim: int = 512, vox: float = 0.01, mu: float = 0.15) -> Sequence:
+    """A sequence of the ablation sets: kind "1d", "3d" (axis_motion) or
+    "6d" (fast_trajectory at a seeded speed in [1, 4] m/s and 0.67 x that in
+    rad/s), in a procedural room filling the volume, 320x240 depth."""
+    scene = procedural_room(seed, 0.1, dim * vox - 0.1)
+    K = Intrinsics.centred(width, height, 525.0 * width / 640.0)
+    if kind == "6d":
+        v = float(np.random.default_rng(seed).uniform(1.0, 4.0))
+        poses = fast_trajectory(scene, seed + 1, n_frames, 30.0, v, 0.67 * v)
+    else:
+        poses = axis_motion(scene, seed + 1, n_frames, 30.0, kind)
+    return Sequence(scene, K, (dim, dim, dim), vox, np.zeros(3), mu, poses, seed + 2, 0.002, 0.2, 6.0, 4, 10240, 20)
