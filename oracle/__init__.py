@@ -36,6 +36,24 @@ Parity status per function (what pins it, tests/test_oracle_*.py):
                         convergence to the true pose on the small frame.
 * integrate          -- pinned: fronto-parallel plane closed form; fused
                         zero crossing vs analytic surface.
+* track_frame levels -- pinned: identical levels reproduce the single
+  (multi-resolution)    resolution tracker bit for bit; with the centre
+                        threshold a K-iteration schedule equals K chained
+                        one-iteration single-resolution runs; the paper's
+                        schedule converges on the small frame.
+* pst_update flags   -- pinned: the worked example with the isotropic or
+  (rescaling ablation)  the anisotropic part of Eq. rsinter switched off.
+* pst_poisson        -- pinned: r_min = 0 gives the i.i.d. template bit for
+                        bit; exact minimum spacing; every rejected candidate
+                        lies within r_min of an earlier accepted point;
+                        budget exhaustion; uniform-like moments.
+* raycast            -- pinned: analytic render of a scene at the same pose
+                        within half a voxel; plane exact; misses are 0.
+* proposal_features  -- pinned: closed forms on constant frames (clamped
+                        difference, missing samples, velocity, padding).
+* mlp (oracle/mlp.py) -- pinned: central differences of the loss; GELU
+                        closed forms; the NLL minimiser is the sample mean
+                        and log standard deviation; Adam's first step.
 """
 from __future__ import annotations
 

@@ -35,3 +35,24 @@ def test_raycast_plane_is_exact_and_misses_are_zero(orc):
     assert np.all(np.abs(d - c) < 1e-6)
     d_far = orc.raycast(psi, vox, origin, [1, 0, 0, 0], [0, 0, 0], K, near=0.05, far=0.3, step=0.013)
     assert np.all(d_far == 0)
+
+
+def test_proposal_features_closed_forms(orc):
+    """Constant frames: the residual is the clamped depth difference on every
+    low-res pixel, 0 where either depth is missing; the velocity follows the
+    residual block and the rest is zero padding."""
+    depth = np.full((240, 320), 2.0, np.float32)
+    render = np.full((30, 40), 1.75, np.float32)
+    render[3, 7] = 0.0          # no model surface there
+    depth[8 * 5 + 4, 8 * 9 + 4] = 0.0  # no measurement at low-res pixel (9, 5)
+    depth[8 * 1 + 4, 8 * 2 + 4] = 3.0  # residual 1.25 m -> clamped to 0.5
+    vel = [0.1, -0.2, 0.3, 1.0, 2.0, -3.0]
+    f = orc.proposal_features(depth, render, 8, vel, 1216)
+    res = f[:1200].reshape(30, 40)
+    expect = np.full((30, 40), np.float32(2.0) - np.float32(1.75))
+    expect[3, 7] = 0.0
+    expect[5, 9] = 0.0
+    expect[1, 2] = 0.5
+    assert np.array_equal(res, expect)
+    assert np.array_equal(f[1200:1206], np.array(vel, np.float32))
+    assert np.all(f[1206:] == 0)
