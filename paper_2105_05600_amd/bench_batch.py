@@ -1,0 +1,160 @@
+"""Batched tracking benchmark: many independent synthetic sequences of
+uneven sizes tracked in lockstep through one persistent fitness launch per
+iteration, captured in a HIP graph (pso_batch_*), against the same sequences
+tracked one after another through the single-sequence path.
+
+Sequences (seeds 1000 + i): TSDF 256^3 / 384^3 / 512^3 at 1 cm (the room
+scaled to the volume), depth 320x240 (f = 262.5) or 640x480 (f = 525),
+4096-16384 particles, 1-4 m/s with 0.67 x that in rad/s, stride 4, 20
+iterations, fusion at the tracked pose after every frame.  Depth frames are
+rendered on the host before timing and are resident in HBM.
+
+The batch's fitness launch shape is chosen by timing the supported shapes on
+the first frame steps (a small autotuner).  Both paths give bit-identical
+poses (tested); the JSON line reports frames/s and evaluations/s of both and
+the ATE of every sequence.
+
+Usage: python -m paper_2105_05600_amd.bench_batch [--sequences 32] [--frames 30]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+from paper_2105_05600_amd import autotune, rose  # noqa: E402
+
+DIMS = (256, 384, 512)
+FRAMES = ((320, 240), (640, 480))
+PARTICLES = (4096, 6144, 8192, 10240, 12288, 16384)
+
+
+def log(msg):
+    print(f"[bench_batch] {msg}", file=sys.stderr, flush=True)
+
+
+def make_sequences(n, frames):
+    seqs = []
+    for i in range(n):
+        rng = np.random.default_rng(1000 + i)
+        dim = int(rng.choice(DIMS))
+        w, h = FRAMES[int(rng.integers(2))]
+        npart = int(rng.choice(PARTICLES))
+        v = float(rng.uniform(1.0, 4.0))
+        seqs.append(synth.room_sequence(scene_seed=1000 + i, traj_seed=2000 + i, noise_seed=3000 + i,
+                                        n_frames=frames, speed=v, ang_speed=0.67 * v, width=w, height=h,
+                                        dim=dim, n_particles=npart))
+    return seqs
+
+
+def fresh(seqs, depths):
+    """Volumes fused from frame 0 and states at frame 0's pose (r_1 = 0.55)."""
+    vols, states = [], (rose.TrackState * len(seqs))()
+    for i, sq in enumerate(seqs):
+        vol = rose.Tsdf(sq.dims, sq.vox, sq.mu, sq.origin)
+        p0 = sq.poses[0]
+        vol.integrate(depths[i][0], sq.K, p0.q, p0.t)
+        vols.append(vol)
+        states[i] = rose.track_state(p0.q, p0.t, [0.55] * 6)
+    return vols, states
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--sequences", type=int, default=32)
+    ap.add_argument("--frames", type=int, default=30)
+    ap.add_argument("--tune-steps", type=int, default=3)
+    args = ap.parse_args()
+    torch.cuda.set_device(0)
+    seqs = make_sequences(args.sequences, args.frames)
+    t0 = time.perf_counter()
+    depths = [[torch.from_numpy(d).cuda() for d in sq.depths(range(args.frames), workers=16)] for sq in seqs]
+    log(f"rendered {args.sequences} x {args.frames} frames in {time.perf_counter() - t0:.1f} s")
+    psts = {n: rose.pst_sample(n, 5600) for n in sorted({sq.n_particles for sq in seqs})}
+    params = [rose.track_params(max_iters=sq.iters, stride=sq.stride) for sq in seqs]
+    stream = torch.cuda.Stream()
+
+    # launch-shape tuning: time a few frame steps of the batch per shape
+    tune_ms = {}
+    for shape in autotune.BATCH_SHAPES:
+        rose.set_fitness_shape(*shape)
+        vols, states = fresh(seqs, depths)
+        with torch.cuda.stream(stream):
+            b = rose.Batch(vols, [sq.K for sq in seqs], [psts[sq.n_particles] for sq in seqs], params)
+            b.track([d[1] for d in depths], states, stream=stream)  # capture
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for f in range(2, 2 + args.tune_steps):
+                b.track([d[f] for d in depths], states, stream=stream)
+            torch.cuda.synchronize()
+        tune_ms[f"{shape[0]}x{shape[1]}"] = 1e3 * (time.perf_counter() - t1) / args.tune_steps
+        b.close()
+        for v in vols:
+            v.close()
+    best = min(autotune.BATCH_SHAPES, key=lambda s: tune_ms[f"{s[0]}x{s[1]}"])
+    rose.set_fitness_shape(*best)
+    log(f"batch shape {best} (ms per frame step: {tune_ms})")
+
+    # batched run (graph-captured)
+    vols, states = fresh(seqs, depths)
+    est_b = [[np.array(sq.poses[0].t)] for sq in seqs]
+    evals = 0.0
+    with torch.cuda.stream(stream):
+        b = rose.Batch(vols, [sq.K for sq in seqs], [psts[sq.n_particles] for sq in seqs], params)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for f in range(1, args.frames):
+            res = b.track([d[f] for d in depths], states, stream=stream)
+            for i, sq in enumerate(seqs):
+                evals += sq.n_particles * float(sum(res[i]["n_overlap"]))
+                est_b[i].append(np.array(res[i]["t"]))
+                vols[i].integrate(depths[i][f], sq.K, res[i]["q"], res[i]["t"], stream=stream)
+        torch.cuda.synchronize()
+        wall_b = time.perf_counter() - t1
+    b.close()
+    for v in vols:
+        v.close()
+
+    # the same sequences through the single-sequence path, one after another
+    rose.set_fitness_shape(*best)
+    vols, states = fresh(seqs, depths)
+    est_s = [[np.array(sq.poses[0].t)] for sq in seqs]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for f in range(1, args.frames):
+        for i, sq in enumerate(seqs):
+            r = rose.track_frame(vols[i], depths[i][f], sq.K, psts[sq.n_particles], params[i], states[i])
+            est_s[i].append(np.array(r["t"]))
+            vols[i].integrate(depths[i][f], sq.K, r["q"], r["t"])
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - t1
+    for v in vols:
+        v.close()
+
+    same = all(np.array_equal(np.array(a), np.array(c)) for a, c in zip(est_b, est_s))
+    ates = [synth.ate(np.array(e), np.array([p.t for p in sq.poses[:args.frames]]))[1] for e, sq in zip(est_b, seqs)]
+    steps = args.sequences * (args.frames - 1)
+    out = {"metric": "batched tracking: frames/s and particle*point evals/s over all sequences",
+           "sequences": args.sequences, "frames": args.frames,
+           "config": [{"tsdf": sq.dims[0], "image": [sq.K.width, sq.K.height], "particles": sq.n_particles}
+                      for sq in seqs],
+           "shape": list(best), "tune_ms_per_step": tune_ms,
+           "batch": {"wall_s": wall_b, "frames_per_s": steps / wall_b, "evals_per_s": evals / wall_b},
+           "single": {"wall_s": wall_s, "frames_per_s": steps / wall_s, "evals_per_s": evals / wall_s},
+           "speedup": wall_s / wall_b, "poses_identical": bool(same),
+           "ate_rmse_m": {"mean": float(np.mean(ates)), "max": float(np.max(ates)), "per_sequence": ates}}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
