@@ -338,8 +338,9 @@ rose_status pso_track_frame_learned(rose_tsdf* h, const float* depth_dev, const 
  * and a non-null stream it is captured into a HIP graph on the first call
  * and replayed afterwards (new inputs are read from pinned host memory).
  * The fitness launch shape is the one set by rose_fitness_set_shape when the
- * batch is created ((4,2), (8,2) or (4,4); otherwise (4,2)).  Volumes must be
- * below 4 GB.  The handles must stay alive and must not be tracked through
+ * batch is created ((4,2), (8,2), (4,4) or (8,4); otherwise (4,2)); one
+ * persistent fitness launch per iteration and per group of sequences that
+ * share a storage format and lookup.  Volumes must be below 4 GB.  The handles must stay alive and must not be tracked through
  * another path while the batch exists. */
 typedef struct rose_batch rose_batch;
 rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_camera* cams,

@@ -341,8 +341,9 @@ int choose_splits(int32_t n_particles, int64_t max_points);
 bool fitness_shape_valid(int p, int u);
 void fitness_shape(int* p, int* u);
 int fitness_blocks(const FitLaunch& L, int P);
-rose_status launch_fitness_batch(const FitLaunch* seqs_dev, const int* begin_dev, int count, int total, int grid,
-                                 int P, int U, hipStream_t s);
+bool batch_shape_valid(int p, int u);
+rose_status launch_fitness_batch(const FitLaunch* seqs_dev, const int* begin_dev, int count, int base, int end,
+                                 int grid, int P, int U, int fmt, int lk, hipStream_t s);
 
 // PST template rows 0..n-1 (tsdf.hip)
 rose_status launch_pst_sample(int64_t n, uint64_t seed, float* out_dev, hipStream_t s);

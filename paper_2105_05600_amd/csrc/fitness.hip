@@ -209,47 +209,67 @@ int fitness_blocks(const FitLaunch& L, int P) { return ((L.n + P - 1) / P + 3) /
 
 __device__ inline int fitness_blocks_dev(const FitLaunch& L, int P) { return ((L.n + P - 1) / P + 3) / 4 * L.splits; }
 
-// Persistent fitness over many tracked sequences: a grid of at most a few
-// workgroups per CU walks the concatenated work lists (sequence i owns items
-// [begin[i], begin[i+1]), each begin a multiple of 8 and the grid a multiple
-// of 8, so an item's XCD is its index mod 8 and the slice <-> XCD pairing of
-// k_fitness holds for every sequence).
-template <int P, int U>
-__global__ __launch_bounds__(256) void k_fitness_batch(const FitLaunch* seqs, const int* begin, int count, int total) {
-    for (int w = blockIdx.x; w < total; w += gridDim.x) {
+// Persistent fitness over many tracked sequences of one storage format and
+// lookup (a batch launches one kernel per such group, so each kernel holds a
+// single fitness body and keeps its registers): a grid of a few workgroups
+// per CU walks the group's concatenated work lists [base, end) (sequence i
+// owns items [begin[i], begin[i+1]), every begin a multiple of 8 and the grid
+// a multiple of 8, so an item's XCD is its index mod 8 and the slice <-> XCD
+// pairing of k_fitness holds for every sequence).
+template <int P, int U, int FMT, int LK>
+__global__ __launch_bounds__(256) void k_fitness_batch(const FitLaunch* __restrict__ seqs,
+                                                       const int* __restrict__ begin, int count, int base, int end) {
+    for (int w = base + (int)blockIdx.x; w < end; w += gridDim.x) {
         int lo = 0, hi = count;
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
             if (begin[mid] <= w) lo = mid;
             else hi = mid;
         }
-        const FitLaunch& L = seqs[lo];
+        const FitLaunch L = seqs[lo];  // wave-uniform: scalar loads of read-only memory
         const int blk = w - begin[lo];
         if (blk >= fitness_blocks_dev(L, P)) continue;
-        if (L.g.fmt == ROSE_TSDF_F32) {
-            if (L.lookup == ROSE_LOOKUP_TRILINEAR)
-                fitness_body<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_TRILINEAR, true, false>(L, blk);
-            else
-                fitness_body<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_NEAREST, true, false>(L, blk);
-        } else if (L.g.fmt == ROSE_TSDF_F16) {
-            if (L.lookup == ROSE_LOOKUP_TRILINEAR)
-                fitness_body<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_TRILINEAR, true, false>(L, blk);
-            else
-                fitness_body<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_NEAREST, true, false>(L, blk);
-        } else {
-            if (L.lookup == ROSE_LOOKUP_TRILINEAR)
-                fitness_body<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_TRILINEAR, true, false>(L, blk);
-            else
-                fitness_body<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_NEAREST, true, false>(L, blk);
-        }
+        fitness_body<P, U, FMT, LK, true, false>(L, blk);
     }
 }
 
-rose_status launch_fitness_batch(const FitLaunch* seqs_dev, const int* begin_dev, int count, int total, int grid,
-                                 int P, int U, hipStream_t s) {
-    if (P == 8 && U == 2) hipLaunchKernelGGL((k_fitness_batch<8, 2>), dim3(grid), dim3(256), 0, s, seqs_dev, begin_dev, count, total);
-    else if (P == 4 && U == 4) hipLaunchKernelGGL((k_fitness_batch<4, 4>), dim3(grid), dim3(256), 0, s, seqs_dev, begin_dev, count, total);
-    else hipLaunchKernelGGL((k_fitness_batch<4, 2>), dim3(grid), dim3(256), 0, s, seqs_dev, begin_dev, count, total);
+template <int P, int U>
+static void launch_batch_shape(const FitLaunch* seqs, const int* begin, int count, int base, int end, int grid,
+                               int fmt, int lk, hipStream_t s) {
+    if (fmt == ROSE_TSDF_F32) {
+        if (lk == ROSE_LOOKUP_TRILINEAR)
+            hipLaunchKernelGGL((k_fitness_batch<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_TRILINEAR>), dim3(grid), dim3(256), 0,
+                               s, seqs, begin, count, base, end);
+        else
+            hipLaunchKernelGGL((k_fitness_batch<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_NEAREST>), dim3(grid), dim3(256), 0,
+                               s, seqs, begin, count, base, end);
+    } else if (fmt == ROSE_TSDF_F16) {
+        if (lk == ROSE_LOOKUP_TRILINEAR)
+            hipLaunchKernelGGL((k_fitness_batch<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_TRILINEAR>), dim3(grid), dim3(256), 0,
+                               s, seqs, begin, count, base, end);
+        else
+            hipLaunchKernelGGL((k_fitness_batch<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_NEAREST>), dim3(grid), dim3(256), 0,
+                               s, seqs, begin, count, base, end);
+    } else {
+        if (lk == ROSE_LOOKUP_TRILINEAR)
+            hipLaunchKernelGGL((k_fitness_batch<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_TRILINEAR>), dim3(grid), dim3(256), 0,
+                               s, seqs, begin, count, base, end);
+        else
+            hipLaunchKernelGGL((k_fitness_batch<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_NEAREST>), dim3(grid), dim3(256), 0,
+                               s, seqs, begin, count, base, end);
+    }
+}
+
+bool batch_shape_valid(int P, int U) {
+    return (P == 4 && U == 2) || (P == 8 && U == 2) || (P == 4 && U == 4) || (P == 8 && U == 4);
+}
+
+rose_status launch_fitness_batch(const FitLaunch* seqs_dev, const int* begin_dev, int count, int base, int end,
+                                 int grid, int P, int U, int fmt, int lk, hipStream_t s) {
+    if (P == 8 && U == 4) launch_batch_shape<8, 4>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, s);
+    else if (P == 8 && U == 2) launch_batch_shape<8, 2>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, s);
+    else if (P == 4 && U == 4) launch_batch_shape<4, 4>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, s);
+    else launch_batch_shape<4, 2>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, s);
     ROSE_CHECK_HIP(hipGetLastError());
     return ROSE_OK;
 }

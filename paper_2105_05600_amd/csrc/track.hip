@@ -610,8 +610,17 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_cam
 // memory, so the graph itself never changes.
 #include <vector>
 
+// sequences of one storage format and lookup: one fitness launch each
+struct BatchGroup {
+    int fmt, lk;
+    int first, count;  // positions in the group-ordered work arrays
+    int base, end;     // work items [base, end)
+    int grid;
+};
+
 struct rose_batch {
-    int32_t count = 0, K = 0, P = 4, U = 2, grid = 8, total = 0;
+    int32_t count = 0, K = 0, P = 4, U = 2, total = 0;
+    std::vector<BatchGroup> groups;
     bool use_graph = true;
     std::vector<rose_tsdf*> h;
     std::vector<rose_track_params> params;
@@ -646,8 +655,11 @@ static rose_status batch_enqueue(rose_batch* b, hipStream_t s) {
     hipLaunchKernelGGL(k_track_init_batch, dim3(b->count), dim3(1024), 0, s, b->init_dev, b->in_host);
     ROSE_CHECK_HIP(hipGetLastError());
     for (int k = 0; k < b->K; ++k) {
-        rose_status st = launch_fitness_batch(b->fit_dev, b->begin_dev, b->count, b->total, b->grid, b->P, b->U, s);
-        if (st != ROSE_OK) return st;
+        for (const BatchGroup& gr : b->groups) {
+            rose_status st = launch_fitness_batch(b->fit_dev + gr.first, b->begin_dev + gr.first, gr.count, gr.base,
+                                                  gr.end, gr.grid, b->P, b->U, gr.fmt, gr.lk, s);
+            if (st != ROSE_OK) return st;
+        }
         hipLaunchKernelGGL(k_track_update_batch, dim3(b->count), dim3(1024), 0, s, b->upd_dev);
         ROSE_CHECK_HIP(hipGetLastError());
     }
@@ -694,14 +706,23 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
     b->use_graph = use_graph != 0;
     int P, U;
     fitness_shape(&P, &U);
-    if (!((P == 4 && U == 2) || (P == 8 && U == 2) || (P == 4 && U == 4))) {
+    if (!batch_shape_valid(P, U)) {
         P = 4;
         U = 2;
     }
     b->P = P;
     b->U = U;
+    // the fitness work arrays list the sequences grouped by (format, lookup)
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        const int kx = tsdfs[x]->g.fmt * 2 + params[x].lookup, ky = tsdfs[y]->g.fmt * 2 + params[y].lookup;
+        return kx < ky;
+    });
+    std::vector<int> pos(count);
+    for (int k = 0; k < count; ++k) pos[order[k]] = k;
     std::vector<FitLaunch> fit(count);
-    std::vector<int> begin(count + 1, 0);
+    std::vector<int> nblk(count, 0);
     std::vector<InitStatic> init(count);
     std::vector<UpdateArgs> upd(count);
     std::vector<DevState*> stp(count);
@@ -722,7 +743,7 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
             g = ROSE_E_DEVICE;
             break;
         }
-        FitLaunch& L = fit[i];
+        FitLaunch& L = fit[pos[i]];
         L = FitLaunch{};
         L.g = h->g;
         L.pts = h->pts_o;
@@ -736,8 +757,7 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
         L.shape_p = P;
         L.shape_u = U;
         L.partial = h->partial;
-        const int nb = fitness_blocks(L, P);
-        begin[i + 1] = begin[i] + (nb + 7) / 8 * 8;
+        nblk[pos[i]] = fitness_blocks(L, P);
         InitStatic& ia = init[i];
         ia = InitStatic{};
         ia.st = h->st;
@@ -775,8 +795,24 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
         batch_free(b);
         return g;
     }
+    std::vector<int> begin(count + 1, 0);
+    for (int k = 0; k < count; ++k) begin[k + 1] = begin[k] + (nblk[k] + 7) / 8 * 8;
     b->total = begin[count];
-    b->grid = std::max(8, std::min(b->total, 256 * 8) / 8 * 8);
+    for (int k = 0; k < count;) {
+        const int key = tsdfs[order[k]]->g.fmt * 2 + params[order[k]].lookup;
+        int e = k;
+        while (e < count && tsdfs[order[e]]->g.fmt * 2 + params[order[e]].lookup == key) ++e;
+        BatchGroup gr;
+        gr.fmt = tsdfs[order[k]]->g.fmt;
+        gr.lk = params[order[k]].lookup;
+        gr.first = k;
+        gr.count = e - k;
+        gr.base = begin[k];
+        gr.end = begin[e];
+        gr.grid = std::max(8, std::min(gr.end - gr.base, 256 * 8) / 8 * 8);
+        b->groups.push_back(gr);
+        k = e;
+    }
     bool ok = hipMalloc(&b->fit_dev, sizeof(FitLaunch) * count) == hipSuccess &&
               hipMalloc(&b->begin_dev, sizeof(int) * (count + 1)) == hipSuccess &&
               hipMalloc(&b->init_dev, sizeof(InitStatic) * count) == hipSuccess &&
