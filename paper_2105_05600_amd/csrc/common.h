@@ -342,6 +342,7 @@ bool fitness_shape_valid(int p, int u);
 void fitness_shape(int* p, int* u);
 int fitness_blocks(const FitLaunch& L, int P);
 bool batch_shape_valid(int p, int u);
+int batch_grid(int P, int U, int fmt, int lk, int requested);
 rose_status launch_fitness_batch(const FitLaunch* seqs_dev, const int* begin_dev, int count, int base, int end,
                                  int grid, int P, int U, int fmt, int lk, hipStream_t s);
 

@@ -11,6 +11,8 @@
 // binary32 values is exact in binary64, so one fma per term), reduced over
 // the wave with butterfly shuffles, and written as one partial sum per
 // (particle, slice); a second pass adds the slices in a fixed order.
+#include <algorithm>
+
 #include "common.h"
 
 namespace rose {
@@ -233,30 +235,69 @@ __global__ __launch_bounds__(256) void k_fitness_batch(const FitLaunch* __restri
     }
 }
 
+// A persistent grid must fit on the device at once: workgroups that only
+// start when others finish would take their full static share of items late.
+// grid = min(requested, resident workgroups of this kernel), a multiple of 8.
+template <typename K>
+static int resident_grid(K kernel, int requested) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kernel), 256, 0) !=
+            hipSuccess ||
+        per_cu < 1)
+        return std::max(8, requested / 8 * 8);
+    return std::max(8, std::min(requested, cus * per_cu) / 8 * 8);
+}
+
+template <int P, int U, int FMT, int LK>
+static void launch_batch_kernel(const FitLaunch* seqs, const int* begin, int count, int base, int end, int grid,
+                                hipStream_t s) {
+    hipLaunchKernelGGL((k_fitness_batch<P, U, FMT, LK>), dim3(grid), dim3(256), 0, s, seqs, begin, count, base, end);
+}
+
+template <int P, int U>
+static int batch_grid_shape(int fmt, int lk, int requested) {
+    if (fmt == ROSE_TSDF_F32)
+        return lk == ROSE_LOOKUP_TRILINEAR
+                   ? resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_TRILINEAR>, requested)
+                   : resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_NEAREST>, requested);
+    if (fmt == ROSE_TSDF_F16)
+        return lk == ROSE_LOOKUP_TRILINEAR
+                   ? resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_TRILINEAR>, requested)
+                   : resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_NEAREST>, requested);
+    return lk == ROSE_LOOKUP_TRILINEAR
+               ? resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_TRILINEAR>, requested)
+               : resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_NEAREST>, requested);
+}
+
+// grid of the persistent batch launch for a group (host query; call outside
+// stream capture)
+int batch_grid(int P, int U, int fmt, int lk, int requested) {
+    if (P == 8 && U == 4) return batch_grid_shape<8, 4>(fmt, lk, requested);
+    if (P == 8 && U == 2) return batch_grid_shape<8, 2>(fmt, lk, requested);
+    if (P == 4 && U == 4) return batch_grid_shape<4, 4>(fmt, lk, requested);
+    return batch_grid_shape<4, 2>(fmt, lk, requested);
+}
+
 template <int P, int U>
 static void launch_batch_shape(const FitLaunch* seqs, const int* begin, int count, int base, int end, int grid,
                                int fmt, int lk, hipStream_t s) {
     if (fmt == ROSE_TSDF_F32) {
         if (lk == ROSE_LOOKUP_TRILINEAR)
-            hipLaunchKernelGGL((k_fitness_batch<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_TRILINEAR>), dim3(grid), dim3(256), 0,
-                               s, seqs, begin, count, base, end);
+            launch_batch_kernel<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_TRILINEAR>(seqs, begin, count, base, end, grid, s);
         else
-            hipLaunchKernelGGL((k_fitness_batch<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_NEAREST>), dim3(grid), dim3(256), 0,
-                               s, seqs, begin, count, base, end);
+            launch_batch_kernel<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_NEAREST>(seqs, begin, count, base, end, grid, s);
     } else if (fmt == ROSE_TSDF_F16) {
         if (lk == ROSE_LOOKUP_TRILINEAR)
-            hipLaunchKernelGGL((k_fitness_batch<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_TRILINEAR>), dim3(grid), dim3(256), 0,
-                               s, seqs, begin, count, base, end);
+            launch_batch_kernel<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_TRILINEAR>(seqs, begin, count, base, end, grid, s);
         else
-            hipLaunchKernelGGL((k_fitness_batch<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_NEAREST>), dim3(grid), dim3(256), 0,
-                               s, seqs, begin, count, base, end);
+            launch_batch_kernel<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_NEAREST>(seqs, begin, count, base, end, grid, s);
     } else {
         if (lk == ROSE_LOOKUP_TRILINEAR)
-            hipLaunchKernelGGL((k_fitness_batch<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_TRILINEAR>), dim3(grid), dim3(256), 0,
-                               s, seqs, begin, count, base, end);
+            launch_batch_kernel<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_TRILINEAR>(seqs, begin, count, base, end, grid, s);
         else
-            hipLaunchKernelGGL((k_fitness_batch<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_NEAREST>), dim3(grid), dim3(256), 0,
-                               s, seqs, begin, count, base, end);
+            launch_batch_kernel<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_NEAREST>(seqs, begin, count, base, end, grid, s);
     }
 }
 

@@ -809,7 +809,7 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
         gr.count = e - k;
         gr.base = begin[k];
         gr.end = begin[e];
-        gr.grid = std::max(8, std::min(gr.end - gr.base, 256 * 8) / 8 * 8);
+        gr.grid = batch_grid(P, U, gr.fmt, gr.lk, gr.end - gr.base);
         b->groups.push_back(gr);
         k = e;
     }
