@@ -43,14 +43,21 @@ def log(msg):
     print(f"[bench_batch] {msg}", file=sys.stderr, flush=True)
 
 
-def make_sequences(n, frames):
+def make_sequences(n, frames, small=False):
+    """small: 128^3 volumes at 4 cm, 160x120 depth, 1024 particles, stride 3
+    (work a single launch cannot spread over the whole GPU)."""
     seqs = []
     for i in range(n):
         rng = np.random.default_rng(1000 + i)
+        v = float(rng.uniform(1.0, 4.0))
+        if small:
+            seqs.append(synth.room_sequence(scene_seed=1000 + i, traj_seed=2000 + i, noise_seed=3000 + i,
+                                            n_frames=frames, speed=v, ang_speed=0.67 * v, width=160, height=120,
+                                            dim=128, vox=0.04, stride=3, n_particles=1024))
+            continue
         dim = int(rng.choice(DIMS))
         w, h = FRAMES[int(rng.integers(2))]
         npart = int(rng.choice(PARTICLES))
-        v = float(rng.uniform(1.0, 4.0))
         seqs.append(synth.room_sequence(scene_seed=1000 + i, traj_seed=2000 + i, noise_seed=3000 + i,
                                         n_frames=frames, speed=v, ang_speed=0.67 * v, width=w, height=h,
                                         dim=dim, n_particles=npart))
@@ -74,9 +81,10 @@ def main():
     ap.add_argument("--sequences", type=int, default=32)
     ap.add_argument("--frames", type=int, default=30)
     ap.add_argument("--tune-steps", type=int, default=3)
+    ap.add_argument("--small", action="store_true", help="small sequences (128^3 at 4 cm, 160x120, 1024 particles)")
     args = ap.parse_args()
     torch.cuda.set_device(0)
-    seqs = make_sequences(args.sequences, args.frames)
+    seqs = make_sequences(args.sequences, args.frames, args.small)
     t0 = time.perf_counter()
     depths = [[torch.from_numpy(d).cuda() for d in sq.depths(range(args.frames), workers=16)] for sq in seqs]
     log(f"rendered {args.sequences} x {args.frames} frames in {time.perf_counter() - t0:.1f} s")
@@ -145,7 +153,7 @@ def main():
     ates = [synth.ate(np.array(e), np.array([p.t for p in sq.poses[:args.frames]]))[1] for e, sq in zip(est_b, seqs)]
     steps = args.sequences * (args.frames - 1)
     out = {"metric": "batched tracking: frames/s and particle*point evals/s over all sequences",
-           "sequences": args.sequences, "frames": args.frames,
+           "sequences": args.sequences, "frames": args.frames, "small": args.small,
            "config": [{"tsdf": sq.dims[0], "image": [sq.K.width, sq.K.height], "particles": sq.n_particles}
                       for sq in seqs],
            "shape": list(best), "tune_ms_per_step": tune_ms,
