@@ -308,6 +308,8 @@ typedef struct {
     double r_min, r_max;
     double delta;                /* fall back when rho < previous rho - delta */
     double near_m, far_m, step_m;/* raycast range and step */
+    int32_t iters;               /* iterations of the learned run (0: p->max_iters; the fallback uses p) */
+    int32_t reserved;
 } rose_learned_params;
 
 /* One frame with the learned PST proposal: render the model at the previous

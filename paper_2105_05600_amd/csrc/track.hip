@@ -979,6 +979,8 @@ rose_status pso_track_frame_learned(rose_tsdf* h, const float* depth_dev, const 
     ROSE_REQUIRE(lp->scale >= 1 && lp->low_w >= 1 && lp->low_h >= 1 && lp->feature_dim >= lp->low_w * lp->low_h + 6 &&
                      lp->kappa > 0 && lp->r_min > 0 && lp->r_max >= lp->r_min,
                  ROSE_E_ARG, "pso_track_frame_learned: bad learned parameters");
+    ROSE_REQUIRE(lp->iters >= 0 && lp->iters <= ROSE_MAX_ITERS, ROSE_E_ARG,
+                 "pso_track_frame_learned: iters = %d out of [0, %d]", lp->iters, ROSE_MAX_ITERS);
     ROSE_REQUIRE(p->levels <= 1, ROSE_E_UNSUPPORTED,
                  "pso_track_frame_learned: multi-resolution schedules are not supported here");
     if (fallback_out) *fallback_out = 0;
@@ -1014,7 +1016,9 @@ rose_status pso_track_frame_learned(rose_tsdf* h, const float* depth_dev, const 
         rose_pose c0;
         if ((st = rose_chart_exp(&state->pose, mu, &c0)) != ROSE_OK) return st;
         rose_track_state trial = *state;
-        st = pso_track_frame(h, depth_dev, cam, pst_small_dev, n_small, p, &c0, r0, &trial, stats, s);
+        rose_track_params pl = *p;
+        if (lp->iters > 0) pl.max_iters = lp->iters;
+        st = pso_track_frame(h, depth_dev, cam, pst_small_dev, n_small, &pl, &c0, r0, &trial, stats, s);
         if (st == ROSE_OK && trial.rho >= state->rho - lp->delta) {
             *state = trial;
         } else if (st == ROSE_OK || st == ROSE_E_STATE) {

@@ -66,12 +66,15 @@ class TrackStats(C.Structure):
 class LearnedParams(C.Structure):
     _fields_ = [("low_w", C.c_int32), ("low_h", C.c_int32), ("scale", C.c_int32), ("feature_dim", C.c_int32),
                 ("kappa", C.c_double), ("r_min", C.c_double), ("r_max", C.c_double), ("delta", C.c_double),
-                ("near_m", C.c_double), ("far_m", C.c_double), ("step_m", C.c_double)]
+                ("near_m", C.c_double), ("far_m", C.c_double), ("step_m", C.c_double), ("iters", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 def learned_params(scale=16, low_w=40, low_h=30, feature_dim=1216, kappa=2.0, r_min=1e-3, r_max=1.0, delta=0.01,
-                   near=0.2, far=8.0, step=0.005) -> "LearnedParams":
-    return LearnedParams(low_w, low_h, scale, feature_dim, kappa, r_min, r_max, delta, near, far, step)
+                   near=0.2, far=8.0, step=0.005, iters=0) -> "LearnedParams":
+    """iters: iterations of the learned run (0: those of the track
+    parameters; the plain fallback always uses the track parameters)."""
+    return LearnedParams(low_w, low_h, scale, feature_dim, kappa, r_min, r_max, delta, near, far, step, int(iters), 0)
 
 
 class Profile(C.Structure):

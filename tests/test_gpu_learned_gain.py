@@ -35,8 +35,9 @@ def test_trained_proposal_gain():
     P = net.pack(tp.load(WEIGHTS))
     untrained = net.pack(mlp_init.init_params(1))
     seeds = [50000, 50010, 50020]
-    rows = tp.evaluate(net, P, seeds, 90, 320, 240, workers=16, kappa=meta["kappa"], delta=meta["delta"],
-                       modes=("plain", "learned", "untrained"), nets={"untrained": untrained})
+    rows = tp.evaluate(net, P, seeds, 90, 320, 240, n_small=meta.get("particles", 4096), workers=16,
+                       kappa=meta["kappa"], delta=meta["delta"], modes=("plain", "learned", "untrained"),
+                       nets={"untrained": untrained}, learned_iters=meta.get("iters", 0))
     s = tp.summarize(rows, ("plain", "learned", "untrained"))
     print(json.dumps(s, indent=1))
     assert s["learned"]["frames_per_s_mean"] >= 1.3 * s["plain"]["frames_per_s_mean"]
