@@ -203,18 +203,32 @@ __device__ inline float final_fitness(const UpdateArgs& a, int i, int nO) {
     return (float)f;
 }
 
+// F_i of every particle from its slice partials (fixed slice order), before
+// the update: many workgroups, so the update kernel's single workgroup reads
+// n floats instead of n x splits doubles.
+__device__ inline void reduce_fitness_body(const UpdateArgs& a, int i) {
+    if (i >= a.n || a.st->stopped) return;
+    a.F[i] = final_fitness(a, i, a.st->n_overlap);
+}
+
+__global__ __launch_bounds__(256) void k_fitness_reduce(UpdateArgs a) {
+    reduce_fitness_body(a, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// one column of workgroups per sequence
+__global__ __launch_bounds__(256) void k_fitness_reduce_batch(const UpdateArgs* a) {
+    reduce_fitness_body(a[blockIdx.y], blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 __device__ void track_update_body(const UpdateArgs& a) {
     __shared__ int lds[17];
     __shared__ double red[16][9];
-    __shared__ float F0s;
     __shared__ float A[12];
     __shared__ int go_on;
     DevState* st = a.st;
     if (st->stopped) return;
     const int nO = st->n_overlap;
-    if (threadIdx.x == 0) F0s = final_fitness(a, 0, nO);
-    __syncthreads();
-    const float F0 = F0s;
+    const float F0 = a.F[0];
     // APS threshold rho(s*_{k-1}): the carried Eq. wafit value from k = 2 on;
     // the centre's exact fitness (particle 0) at k = 1 or with
     // ROSE_FLAG_CENTRE_THRESHOLD
@@ -225,8 +239,7 @@ __device__ void track_update_body(const UpdateArgs& a) {
     // per-thread APS sums: count, sum w, sum w rho, sum w u_d
     double cnt = 0.0, sw = 0.0, swr = 0.0, su[6] = {0, 0, 0, 0, 0, 0};
     for (int i = threadIdx.x; i < a.n; i += blockDim.x) {
-        const float f = final_fitness(a, i, nO);
-        a.F[i] = f;
+        const float f = a.F[i];
         const double rho = exp(-(double)f / a.tau);
         if (rho > rho0) {
             const double w = rho - rho0;
@@ -563,6 +576,7 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_cam
         if ((g = launch_fitness(fl, s)) != ROSE_OK) return g;
         prof_end(tok_fit[k], s, 0.0);
         const int tu = prof_begin(PROF_UPDATE, s);
+        hipLaunchKernelGGL(k_fitness_reduce, dim3((ua.n + 255) / 256), dim3(256), 0, s, ua);
         hipLaunchKernelGGL(k_track_update, dim3(1), dim3(1024), 0, s, ua);
         prof_end(tu, s, 0.0);
         ROSE_CHECK_HIP(hipGetLastError());
@@ -619,7 +633,7 @@ struct BatchGroup {
 };
 
 struct rose_batch {
-    int32_t count = 0, K = 0, P = 4, U = 2, total = 0;
+    int32_t count = 0, K = 0, P = 4, U = 2, total = 0, max_n = 1;
     std::vector<BatchGroup> groups;
     bool use_graph = true;
     std::vector<rose_tsdf*> h;
@@ -660,6 +674,8 @@ static rose_status batch_enqueue(rose_batch* b, hipStream_t s) {
                                                   gr.end, gr.grid, b->P, b->U, gr.fmt, gr.lk, s);
             if (st != ROSE_OK) return st;
         }
+        hipLaunchKernelGGL(k_fitness_reduce_batch, dim3((b->max_n + 255) / 256, b->count), dim3(256), 0, s,
+                           b->upd_dev);
         hipLaunchKernelGGL(k_track_update_batch, dim3(b->count), dim3(1024), 0, s, b->upd_dev);
         ROSE_CHECK_HIP(hipGetLastError());
     }
@@ -789,6 +805,7 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
         b->h.push_back(h);
         b->params.push_back(p);
         b->n.push_back(n_particles[i]);
+        b->max_n = std::max(b->max_n, n_particles[i]);
         b->K = std::max(b->K, (int32_t)p.max_iters);
     }
     if (g != ROSE_OK) {
