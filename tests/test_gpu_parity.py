@@ -58,7 +58,7 @@ def _rot_err(qa, qb):
 
 
 # ------------------------------------------------------------------- a1 PST
-@pytest.mark.parametrize("n,seed", [(1, 1), (5, 3), (1023, 5600), (10240, 5600), (16384, 77)])
+@pytest.mark.parametrize("n,seed", [(1, 1), (5, 3), (1023, 5600), (10240, 5600), (16384, 77), (65536, 9)])
 def test_pst_sample_bit_exact(R, orc, n, seed):
     g = host(R.pst_sample(n, seed))
     o, _ = orc.pst_sample(n, seed)
@@ -375,3 +375,19 @@ def test_track_full_size_first_iteration(R, orc, room_frame):
     assert np.linalg.norm(np.array(g["t"]) - o["t"]) <= 1e-4
     assert _rot_err(g["q"], o["q"]) <= 1e-4
     assert np.allclose(g["r1"], o["r1"], rtol=1e-6)
+
+
+def test_track_frame_max_particles(R, orc, small_gpu):
+    """The largest template the ABI accepts (ROSE_MAX_PARTICLES = 65536): one
+    iteration on the small frame equals the oracle's."""
+    w, vol, psi, _ = small_gpu
+    pst, _ = orc.pst_sample(65536, 31)
+    prev = w.fuse_poses[-1]
+    params = R.track_params(max_iters=1, stride=w.stride)
+    st = R.track_state(prev.q, prev.t, [0.1] * 6)
+    g = R.track_frame(vol, dev(w.depth), w.K, dev(pst), params, st)
+    o = orc.track_frame(psi, w.vox, w.origin, w.depth, w.K, pst, prev.q, prev.t, np.full(6, 0.1), max_iters=1,
+                        stride=w.stride, prec=orc.F32)
+    assert g["aps"][0] == o["aps"][0] > 0
+    assert np.linalg.norm(np.array(g["t"]) - o["t"]) <= 1e-4
+    assert _rot_err(g["q"], o["q"]) <= 1e-4
