@@ -342,8 +342,9 @@ rose_status pso_track_frame_learned(rose_tsdf* h, const float* depth_dev, const 
  * The fitness launch shape is the one set by rose_fitness_set_shape when the
  * batch is created ((4,2), (8,2), (4,4) or (8,4); otherwise (4,2)); one
  * persistent fitness launch per iteration and per group of sequences that
- * share a storage format and lookup.  Volumes must be below 4 GB.  The handles must stay alive and must not be tracked through
- * another path while the batch exists. */
+ * share a storage format and lookup.  Volumes must be below 4 GB.  The handles must stay alive while the batch
+ * exists; tracking one through another path between batch steps is allowed
+ * (the batch re-reads the handles' scratch pointers before each step). */
 typedef struct rose_batch rose_batch;
 rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_camera* cams,
                              const float* const* pst_devs, const int32_t* n_particles,
@@ -356,6 +357,28 @@ rose_status pso_batch_track(rose_batch* b, const float* const* depth_devs, const
                             const double* init_rs, rose_track_state* states, rose_track_stats* stats,
                             hipStream_t s);
 rose_status pso_batch_destroy(rose_batch* b);
+
+/* Batched learned frame step: for every sequence of batch b whose model
+ * exists, the learned proposal of pso_track_frame_learned (raycast at the
+ * previous pose, features with velocities[6 i .. 6 i + 5], one forward of the
+ * network over all sequences, B = count <= the network's max_batch), then
+ * one pso_batch_track step of b (its templates and parameters drive the
+ * learned runs: create b with the small templates and the learned-run
+ * iteration count) from the proposed centres and axis lengths.  A sequence
+ * whose proposal is not finite, whose frame has no valid depth, or whose
+ * final fitness falls below its previous state->rho - delta is tracked again
+ * by plain pso_track_frame from its unchanged state with pst_plain_devs[i],
+ * n_plain[i], plain_params[i] (fallback_out[i] = 1; stats[i].status carries
+ * that call's status).  Sequences without a model (tsdf_built = 0) take the
+ * batch's first-frame step.  work_dev: count x (low_w low_h + feature_dim +
+ * 12) floats.  The results equal pso_track_frame_learned per sequence.
+ * Synchronises s. */
+rose_status pso_batch_track_learned(rose_batch* b, const float* const* depth_devs, rose_mlp* mlp,
+                                    const float* mlp_params_dev, float* work_dev, const double* velocities,
+                                    const rose_learned_params* lp, const float* const* pst_plain_devs,
+                                    const int32_t* n_plain, const rose_track_params* plain_params,
+                                    rose_track_state* states, rose_track_stats* stats, int32_t* fallback_out,
+                                    hipStream_t s);
 
 /* ------------------------------------------- learned proposal network */
 /* A 3-layer perceptron in -> hid (GELU) -> hid (GELU) -> 12, output

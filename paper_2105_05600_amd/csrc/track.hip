@@ -637,6 +637,7 @@ struct rose_batch {
     std::vector<BatchGroup> groups;
     bool use_graph = true;
     std::vector<rose_tsdf*> h;
+    std::vector<rose_camera> cams;
     std::vector<rose_track_params> params;
     std::vector<int32_t> n;
     FitLaunch* fit_dev = nullptr;
@@ -649,7 +650,53 @@ struct rose_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t graph_stream = nullptr;
+    // host copies of the per-sequence launch records (fit in group order: pos)
+    std::vector<FitLaunch> fit_host;
+    std::vector<InitStatic> init_host;
+    std::vector<UpdateArgs> upd_host;
+    std::vector<int> pos;
 };
+
+// The launch records hold each handle's scratch pointers.  A handle tracked
+// through another path (the learned step's plain fallback) may have grown,
+// i.e. reallocated, its scratch since; rewrite the records from the handles
+// and upload them (the captured graph reads them at execution).  Call outside
+// stream capture.
+static rose_status batch_refresh(rose_batch* b, bool force) {
+    bool stale = force;
+    for (int i = 0; i < b->count && !stale; ++i) {
+        const rose_tsdf* h = b->h[i];
+        const UpdateArgs& u = b->upd_host[i];
+        stale = u.partial != h->partial || u.F != h->F || u.pts != h->pts || u.pts_o != h->pts_o || u.st != h->st;
+    }
+    if (!stale) return ROSE_OK;
+    for (int i = 0; i < b->count; ++i) {
+        rose_tsdf* h = b->h[i];
+        FitLaunch& L = b->fit_host[b->pos[i]];
+        L.pts = h->pts_o;
+        L.count_dev = &h->st->n_overlap;
+        L.st = h->st;
+        L.partial = h->partial;
+        InitStatic& ia = b->init_host[i];
+        ia.st = h->st;
+        ia.pts = h->pts;
+        ia.pts_o = h->pts_o;
+        UpdateArgs& ua = b->upd_host[i];
+        ua.st = h->st;
+        ua.partial = h->partial;
+        ua.F = h->F;
+        ua.pts = h->pts;
+        ua.pts_o = h->pts_o;
+    }
+    const size_t n = (size_t)b->count;
+    ROSE_CHECK_HIP(hipMemcpy(b->fit_dev, b->fit_host.data(), sizeof(FitLaunch) * n, hipMemcpyHostToDevice));
+    ROSE_CHECK_HIP(hipMemcpy(b->init_dev, b->init_host.data(), sizeof(InitStatic) * n, hipMemcpyHostToDevice));
+    ROSE_CHECK_HIP(hipMemcpy(b->upd_dev, b->upd_host.data(), sizeof(UpdateArgs) * n, hipMemcpyHostToDevice));
+    std::vector<DevState*> stp(n);
+    for (size_t i = 0; i < n; ++i) stp[i] = b->h[i]->st;
+    ROSE_CHECK_HIP(hipMemcpy(b->stp_dev, stp.data(), sizeof(DevState*) * n, hipMemcpyHostToDevice));
+    return ROSE_OK;
+}
 
 static void batch_free(rose_batch* b) {
     if (!b) return;
@@ -803,6 +850,7 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
         ua.stop_tol = p.stop_tol;
         stp[i] = h->st;
         b->h.push_back(h);
+        b->cams.push_back(cams[i]);
         b->params.push_back(p);
         b->n.push_back(n_particles[i]);
         b->max_n = std::max(b->max_n, n_particles[i]);
@@ -848,6 +896,10 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
         return ROSE_E_DEVICE;
     }
     memset(b->in_host, 0, sizeof(FrameIn) * count);
+    b->fit_host = fit;
+    b->init_host = init;
+    b->upd_host = upd;
+    b->pos = pos;
     *out = b;
     return ROSE_OK;
 }
@@ -866,6 +918,10 @@ rose_status pso_batch_track(rose_batch* b, const float* const* depth_devs, const
     clear_error();
     ROSE_REQUIRE(b && depth_devs && states, ROSE_E_ARG, "pso_batch_track: NULL argument");
     for (int i = 0; i < b->count; ++i) ROSE_REQUIRE(depth_devs[i], ROSE_E_ARG, "pso_batch_track: NULL depth %d", i);
+    {
+        rose_status rs = batch_refresh(b, false);
+        if (rs != ROSE_OK) return rs;
+    }
     // per-frame inputs (pinned host memory, read by the init kernel)
     for (int i = 0; i < b->count; ++i) {
         FrameIn& in = b->in_host[i];
@@ -1048,6 +1104,121 @@ rose_status pso_track_frame_learned(rose_tsdf* h, const float* depth_dev, const 
         if (fallback_out) *fallback_out = 1;
         return pso_track_frame(h, depth_dev, cam, pst_plain_dev, n_plain, p, nullptr, nullptr, state, stats, s);
     }
+    return ROSE_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ batched learned frame step
+extern "C" {
+
+rose_status pso_batch_track_learned(rose_batch* b, const float* const* depth_devs, rose_mlp* mlp,
+                                    const float* mlp_params_dev, float* work_dev, const double* velocities,
+                                    const rose_learned_params* lp, const float* const* pst_plain_devs,
+                                    const int32_t* n_plain, const rose_track_params* plain_params,
+                                    rose_track_state* states, rose_track_stats* stats, int32_t* fallback_out,
+                                    hipStream_t s) {
+    clear_error();
+    ROSE_REQUIRE(b && depth_devs && mlp && mlp_params_dev && work_dev && velocities && lp && pst_plain_devs &&
+                     n_plain && plain_params && states,
+                 ROSE_E_ARG, "pso_batch_track_learned: NULL argument");
+    ROSE_REQUIRE(lp->scale >= 1 && lp->low_w >= 1 && lp->low_h >= 1 && lp->feature_dim >= lp->low_w * lp->low_h + 6 &&
+                     lp->kappa > 0 && lp->r_min > 0 && lp->r_max >= lp->r_min,
+                 ROSE_E_ARG, "pso_batch_track_learned: bad learned parameters");
+    const int n = b->count;
+    for (int i = 0; i < n; ++i)
+        ROSE_REQUIRE(depth_devs[i] && pst_plain_devs[i] && n_plain[i] >= 1 && n_plain[i] <= ROSE_MAX_PARTICLES,
+                     ROSE_E_ARG, "pso_batch_track_learned: bad depth or plain template for sequence %d", i);
+    // size every handle's scratch for a plain fallback now, so that no
+    // fallback reallocates it under the batch's launch records
+    for (int i = 0; i < n; ++i) {
+        rose_tsdf* h = b->h[i];
+        const rose_track_params& pp = plain_params[i];
+        ROSE_REQUIRE(pp.stride >= 1 && pp.levels <= 1, ROSE_E_ARG,
+                     "pso_batch_track_learned: plain parameters of sequence %d need stride >= 1 and one level", i);
+        const int64_t mmax = (int64_t)((b->cams[i].width + pp.stride - 1) / pp.stride) *
+                             ((b->cams[i].height + pp.stride - 1) / pp.stride);
+        const int splits = choose_splits(n_plain[i], mmax);
+        rose_status g;
+        if ((g = grow(&h->pts, &h->cap_points, mmax)) != ROSE_OK) return g;
+        if ((g = grow(&h->pts_o, &h->cap_points_o, mmax)) != ROSE_OK) return g;
+        if ((g = grow(&h->partial, &h->cap_partial, (int64_t)n_plain[i] * splits)) != ROSE_OK) return g;
+        if ((g = grow(&h->F, &h->cap_particles, (int64_t)n_plain[i])) != ROSE_OK) return g;
+    }
+    const int64_t npx = (int64_t)lp->low_w * lp->low_h, fd = lp->feature_dim;
+    float* renders = work_dev;
+    float* X = renders + n * npx;
+    float* out = X + n * fd;
+    if (fallback_out)
+        for (int i = 0; i < n; ++i) fallback_out[i] = 0;
+    // inputs of the network for every sequence whose model exists, one batched forward
+    rose_status st;
+    for (int i = 0; i < n; ++i) {
+        float* Xi = X + i * fd;
+        if (!states[i].tsdf_built) {
+            ROSE_CHECK_HIP(hipMemsetAsync(Xi, 0, sizeof(float) * (size_t)fd, s));
+            continue;
+        }
+        const rose_camera& cam = b->cams[i];
+        rose_camera low;
+        low.fx = cam.fx / (float)lp->scale;
+        low.fy = cam.fy / (float)lp->scale;
+        low.cx = (cam.cx + 0.5f) / (float)lp->scale - 0.5f;
+        low.cy = (cam.cy + 0.5f) / (float)lp->scale - 0.5f;
+        low.width = lp->low_w;
+        low.height = lp->low_h;
+        float* Ri = renders + i * npx;
+        if ((st = tsdf_raycast(b->h[i], &states[i].pose, &low, lp->near_m, lp->far_m, lp->step_m, Ri, s)) != ROSE_OK)
+            return st;
+        if ((st = proposal_features(depth_devs[i], &cam, Ri, &low, lp->scale, velocities + 6 * i, (int32_t)fd, Xi,
+                                    s)) != ROSE_OK)
+            return st;
+    }
+    if ((st = rose_mlp_forward(mlp, mlp_params_dev, X, n, out, s)) != ROSE_OK) return st;
+    std::vector<float> o((size_t)n * 12);
+    ROSE_CHECK_HIP(hipMemcpyAsync(o.data(), out, sizeof(float) * o.size(), hipMemcpyDeviceToHost, s));
+    ROSE_CHECK_HIP(hipStreamSynchronize(s));
+    // proposals: c_0 = s^{t-1} * Delta(mu), r_0 = kappa exp(l) clamped; sequences
+    // without a finite proposal run from their own state and fall back below
+    std::vector<rose_pose> c0(n);
+    std::vector<double> r0((size_t)n * 6);
+    std::vector<char> finite(n, 1);
+    for (int i = 0; i < n; ++i) {
+        c0[i] = states[i].pose;
+        for (int d = 0; d < 6; ++d) r0[6 * i + d] = states[i].r[d];
+        if (!states[i].tsdf_built) continue;
+        const float* oi = &o[(size_t)i * 12];
+        for (int e = 0; e < 12; ++e) finite[i] = finite[i] && std::isfinite(oi[e]);
+        if (!finite[i]) continue;
+        double mu[6];
+        for (int d = 0; d < 6; ++d) {
+            mu[d] = oi[d];
+            r0[6 * i + d] = std::min(lp->r_max, std::max(lp->r_min, lp->kappa * std::exp((double)oi[6 + d])));
+        }
+        if ((st = rose_chart_exp(&states[i].pose, mu, &c0[i])) != ROSE_OK) return st;
+    }
+    std::vector<rose_track_state> trial(states, states + n);
+    std::vector<rose_track_stats> tstats(n);
+    if ((st = pso_batch_track(b, depth_devs, c0.data(), r0.data(), trial.data(), tstats.data(), s)) != ROSE_OK)
+        return st;
+    for (int i = 0; i < n; ++i) {
+        const bool keep = !states[i].tsdf_built ||
+                          (finite[i] && tstats[i].status == ROSE_OK && trial[i].rho >= states[i].rho - lp->delta);
+        if (keep) {
+            states[i] = trial[i];
+            if (stats) stats[i] = tstats[i];
+            continue;
+        }
+        // fallback: plain PST from the unchanged state
+        if (fallback_out) fallback_out[i] = 1;
+        rose_track_stats fs;
+        st = pso_track_frame(b->h[i], depth_devs[i], &b->cams[i], pst_plain_devs[i], n_plain[i], &plain_params[i],
+                             nullptr, nullptr, &states[i], &fs, s);
+        if (st != ROSE_OK && st != ROSE_E_STATE) return st;
+        fs.status = st;
+        if (stats) stats[i] = fs;
+    }
+    clear_error();
     return ROSE_OK;
 }
 

@@ -120,6 +120,8 @@ _sigs = {
     "pso_batch_create": ([C.c_int32, _P, _P, _P, _P, _P, C.c_int32, C.POINTER(C.c_void_p)], C.c_int),
     "pso_batch_track": ([_P, _P, _P, _P, _P, _P, _S], C.c_int),
     "pso_batch_destroy": ([_P], C.c_int),
+    "pso_batch_track_learned": ([_P, _P, _P, _P, _P, _P, C.POINTER(LearnedParams), _P, _P, C.POINTER(TrackParams),
+                                 _P, _P, _P, _S], C.c_int),
     "rose_chart_log": ([C.POINTER(Pose), C.POINTER(Pose), _P], C.c_int),
     "rose_chart_exp": ([C.POINTER(Pose), _P, C.POINTER(Pose)], C.c_int),
     "pso_track_frame_learned": ([_P, _P, C.POINTER(Camera), _P, C.c_int32, _P, C.c_int32, _P, _P, _P, _P,
@@ -575,6 +577,40 @@ class Batch:
                             n_overlap=list(s.n_overlap[:it]), q=list(states[i].pose.q), t=list(states[i].pose.t),
                             r1=list(states[i].r), rho=states[i].rho))
         return out
+
+
+def batch_track_learned(batch: "Batch", depths, mlp: "Mlp", mlp_params: torch.Tensor, work: torch.Tensor,
+                        velocities, lparams: "LearnedParams", plain_psts, plain_params, states, stream=None):
+    """One batched learned frame step (pso_batch_track_learned): the batch's
+    own templates and parameters drive the learned runs, plain_psts /
+    plain_params the fallbacks.  work: count x (low_w*low_h + feature_dim +
+    12) floats.  Returns per-sequence stats dicts with a `fallback` flag."""
+    n = batch.count
+    if not (len(depths) == len(velocities) == len(plain_psts) == len(plain_params) == n):
+        raise ValueError("one depth, velocity, plain template and parameter set per sequence")
+    _dev(work, torch.float32, "work")
+    need = n * (lparams.low_w * lparams.low_h + lparams.feature_dim + 12)
+    if work.numel() < need:
+        raise ValueError(f"work needs {need} floats")
+    D = (C.c_void_p * n)(*[d.data_ptr() for d in depths])
+    V = (C.c_double * (6 * n))(*[float(x) for v in velocities for x in v])
+    PP = (C.c_void_p * n)(*[p.data_ptr() for p in plain_psts])
+    NP = (C.c_int32 * n)(*[p.shape[0] for p in plain_psts])
+    PR = (TrackParams * n)(*plain_params)
+    ST = (TrackStats * n)()
+    FB = (C.c_int32 * n)()
+    _check("pso_batch_track_learned", _lib.pso_batch_track_learned(
+        batch.handle, D, mlp.handle, _ptr(mlp_params), _ptr(work), V, C.byref(lparams), PP, NP, PR, states, ST, FB,
+        _stream(stream)))
+    out = []
+    for i in range(n):
+        s_ = ST[i]
+        it = s_.iters
+        out.append(dict(status=s_.status, iters=it, n_points=s_.n_points, aps=list(s_.aps_size[:it]),
+                        n_overlap=list(s_.n_overlap[:it]), n_particles=list(s_.n_particles[:it]),
+                        q=list(states[i].pose.q), t=list(states[i].pose.t), r1=list(states[i].r),
+                        rho=states[i].rho, fallback=bool(FB[i])))
+    return out
 
 
 def chart_log(qa, ta, qb, tb):
