@@ -76,14 +76,105 @@ def fresh(seqs, depths):
     return vols, states
 
 
+def learned_main(args):
+    """Plain PST (10240 particles, 20 iterations) one sequence after another
+    vs the learned proposal batched over all sequences (settings and weights
+    of paper_2105_05600_amd/weights), on 320x240 sequences at 1-4 m/s."""
+    from paper_2105_05600_amd import train_proposal as tp
+    weights = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "proposal.npz")
+    with open(os.path.splitext(weights)[0] + ".json") as f:
+        meta = json.load(f)
+    n = args.sequences
+    seqs = [tp.make_sequence(52000 + 10 * i, args.frames, 320, 240) for i in range(n)]
+    t0 = time.perf_counter()
+    depths = [[torch.from_numpy(d).cuda() for d in sq.depths(range(args.frames), workers=16)] for sq in seqs]
+    log(f"rendered {n} x {args.frames} frames in {time.perf_counter() - t0:.1f} s")
+    net = rose.Mlp(tp.FEATURE_DIM, 256, 12, max_batch=max(64, n))
+    P = net.pack(tp.load(weights))
+    iters = meta.get("iters", 0) or 20
+    pst_small = rose.pst_sample(meta.get("particles", 4096), 5600)
+    pst_plain = rose.pst_sample(10240, 5600)
+    plain = rose.track_params(max_iters=20, stride=4)
+    small = rose.track_params(max_iters=iters, stride=4)
+    lp = rose.learned_params(scale=8, kappa=meta["kappa"], delta=meta["delta"], iters=iters)
+    rose.set_fitness_shape(8, 2)
+
+    def start():
+        vols, states = [], (rose.TrackState * n)()
+        for i, sq in enumerate(seqs):
+            vol = rose.Tsdf(sq.dims, sq.vox, sq.mu, sq.origin)
+            p0 = sq.poses[0]
+            vol.integrate(depths[i][0], sq.K, p0.q, p0.t)
+            vols.append(vol)
+            states[i] = rose.track_state(p0.q, p0.t, [0.55] * 6)
+        return vols, states
+
+    def ate(est):
+        return [synth.ate(np.array(e), np.array([p.t for p in sq.poses[:args.frames]]))[1]
+                for e, sq in zip(est, seqs)]
+
+    # plain, one sequence after another
+    vols, states = start()
+    est = [[np.array(sq.poses[0].t)] for sq in seqs]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for f in range(1, args.frames):
+        for i, sq in enumerate(seqs):
+            r = rose.track_frame(vols[i], depths[i][f], sq.K, pst_plain, plain, states[i])
+            est[i].append(np.array(r["t"]))
+            vols[i].integrate(depths[i][f], sq.K, r["q"], r["t"])
+    torch.cuda.synchronize()
+    wall_p = time.perf_counter() - t1
+    ate_p = ate(est)
+    for v in vols:
+        v.close()
+    # learned, batched
+    vols, states = start()
+    est = [[np.array(sq.poses[0].t)] for sq in seqs]
+    b = rose.Batch(vols, [sq.K for sq in seqs], [pst_small] * n, [small] * n, use_graph=False)
+    work = torch.zeros(n * (tp.LOW_W * tp.LOW_H + tp.FEATURE_DIM + 12), device="cuda")
+    vel = [[0.0] * 6 for _ in range(n)]
+    fallbacks = 0
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for f in range(1, args.frames):
+        prev = [(list(states[i].pose.q), list(states[i].pose.t)) for i in range(n)]
+        res = rose.batch_track_learned(b, [d[f] for d in depths], net, P, work, vel, lp, [pst_plain] * n,
+                                       [plain] * n, states)
+        for i, sq in enumerate(seqs):
+            fallbacks += int(res[i]["fallback"])
+            q, t = list(states[i].pose.q), list(states[i].pose.t)
+            vel[i] = rose.chart_log(prev[i][0], prev[i][1], q, t)
+            est[i].append(np.array(t))
+            vols[i].integrate(depths[i][f], sq.K, q, t)
+    torch.cuda.synchronize()
+    wall_l = time.perf_counter() - t1
+    ate_l = ate(est)
+    b.close()
+    steps = n * (args.frames - 1)
+    out = {"metric": "learned proposal batched vs plain PST: frames/s over all sequences and ATE",
+           "sequences": n, "frames": args.frames, "image": [320, 240],
+           "learned": {"particles": pst_small.shape[0], "iters": iters, "kappa": meta["kappa"], "delta": meta["delta"]},
+           "plain_single": {"frames_per_s": steps / wall_p, "ate_rmse_mean_m": float(np.mean(ate_p)),
+                            "ate_rmse_median_m": float(np.median(ate_p))},
+           "learned_batched": {"frames_per_s": steps / wall_l, "ate_rmse_mean_m": float(np.mean(ate_l)),
+                               "ate_rmse_median_m": float(np.median(ate_l)), "fallbacks": fallbacks},
+           "speedup": wall_p / wall_l, "ate_plain": ate_p, "ate_learned": ate_l}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--sequences", type=int, default=32)
     ap.add_argument("--frames", type=int, default=30)
     ap.add_argument("--tune-steps", type=int, default=3)
     ap.add_argument("--small", action="store_true", help="small sequences (128^3 at 4 cm, 160x120, 1024 particles)")
+    ap.add_argument("--learned", action="store_true",
+                    help="learned proposal, batched, against plain PST one sequence after another (320x240)")
     args = ap.parse_args()
     torch.cuda.set_device(0)
+    if args.learned:
+        return learned_main(args)
     seqs = make_sequences(args.sequences, args.frames, args.small)
     t0 = time.perf_counter()
     depths = [[torch.from_numpy(d).cuda() for d in sq.depths(range(args.frames), workers=16)] for sq in seqs]

@@ -16,7 +16,8 @@ WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
                        "weights", "proposal.npz")
 
 
-def test_batch_learned_equals_single():
+@pytest.mark.parametrize("always_fall_back", [False, True])
+def test_batch_learned_equals_single(always_fall_back):
     from paper_2105_05600_amd import rose, train_proposal as tp
     with open(os.path.splitext(WEIGHTS)[0] + ".json") as f:
         meta = json.load(f)
@@ -28,7 +29,10 @@ def test_batch_learned_equals_single():
     n_small, iters = meta.get("particles", 4096), meta.get("iters", 0) or 20
     pst_small = rose.pst_sample(n_small, 5600)
     pst_plain = rose.pst_sample(10240, 5600)
-    lp = rose.learned_params(scale=8, kappa=meta["kappa"], delta=meta["delta"], iters=iters)
+    # delta = -1: every learned run "regresses", so every frame takes the
+    # plain fallback (which reallocates the handles' scratch under the batch)
+    delta = -1.0 if always_fall_back else meta["delta"]
+    lp = rose.learned_params(scale=8, kappa=meta["kappa"], delta=delta, iters=iters)
     plain = rose.track_params(max_iters=20, stride=4)
     small = rose.track_params(max_iters=iters, stride=4)
 
@@ -77,6 +81,8 @@ def test_batch_learned_equals_single():
             vel[i] = rose.chart_log(prev[i][0], prev[i][1], list(states[i].pose.q), list(states[i].pose.t))
             vols[i].integrate(depths[i][f], sq.K, states[i].pose.q, states[i].pose.t)
     print(f"{n_seq} sequences x {n_frames - 1} frames, {fallbacks} fallbacks")
+    if always_fall_back:
+        assert fallbacks == n_seq * (n_frames - 1)
     b.close()
     for v in vols:
         v.close()
