@@ -82,3 +82,15 @@ def test_host_side_argument_errors(R):
     assert lib.rose_gather_peak(C.c_void_p(16), 1 << 10, 4096, 8, 1, 1, C.c_void_p(16), None) == R.E_SHAPE
     assert lib.rose_gather_peak(C.c_void_p(16), 1 << 20, 64, 12, 1, 1, C.c_void_p(16), None) == R.E_ARG
     assert lib.rose_gather_peak_loads_per_lane() == 8
+    v = C.c_void_p(16)
+    assert lib.pst_poisson(0, 1, 0.3, 100, v, v, v, None) == R.E_ARG
+    assert lib.pst_poisson(8, 1, 2.5, 100, v, v, v, None) == R.E_ARG
+    assert lib.pst_poisson(8, 1, 0.3, -1, v, v, v, None) == R.E_ARG
+    assert lib.pst_poisson(8, 1, 0.3, 100, None, v, v, None) == R.E_ARG
+    lp = R.learned_params()
+    assert lib.pso_batch_track_learned(None, None, None, None, None, None, C.byref(lp), None, None, None, None, None,
+                                       None, None) == R.E_ARG
+    lp.iters = 99
+    assert lib.pso_track_frame_learned(v, v, C.byref(cam), v, 16, v, 16, v, v, v, (C.c_double * 6)(),
+                                       C.byref(R.track_params()), C.byref(lp), C.byref(st), None, None,
+                                       None) == R.E_ARG
