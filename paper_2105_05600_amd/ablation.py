@@ -151,7 +151,11 @@ def main():
         }, 64000)
     if "multires" in exps:
         var = {"single_10240_s4": (pst, rose.track_params(max_iters=ITERS, stride=4)),
-               "alternating": (pst, rose.track_params(max_iters=ITERS, levels=MULTIRES))}
+               "alternating": (pst, rose.track_params(max_iters=ITERS, levels=MULTIRES)),
+               "alternating_centre_threshold": (pst, rose.track_params(max_iters=ITERS, levels=MULTIRES,
+                                                                       flags=rose.FLAG_CENTRE_THRESHOLD)),
+               "single_10240_s4_centre_threshold": (pst, rose.track_params(max_iters=ITERS, stride=4,
+                                                                           flags=rose.FLAG_CENTRE_THRESHOLD))}
         for n, s in MULTIRES:
             var[f"single_{n}_s{s}"] = (pst[:n].contiguous(), rose.track_params(max_iters=ITERS, stride=s))
         res["multires"] = exp_variants(args.sequences, args.frames, var, 65000)
