@@ -154,6 +154,8 @@ def main():
                "alternating": (pst, rose.track_params(max_iters=ITERS, levels=MULTIRES)),
                "alternating_centre_threshold": (pst, rose.track_params(max_iters=ITERS, levels=MULTIRES,
                                                                        flags=rose.FLAG_CENTRE_THRESHOLD)),
+               "alternating_dense_first": (pst, rose.track_params(max_iters=ITERS, levels=MULTIRES[::-1])),
+               "alternating_21_dense_last": (pst, rose.track_params(max_iters=ITERS + 1, levels=MULTIRES)),
                "single_10240_s4_centre_threshold": (pst, rose.track_params(max_iters=ITERS, stride=4,
                                                                            flags=rose.FLAG_CENTRE_THRESHOLD))}
         for n, s in MULTIRES:
