@@ -30,7 +30,8 @@ import numpy as np  # noqa: E402
 
 # fitness kernel, NEAREST lookup, binary32 TSDF: one 4-byte TSDF gather per
 # particle x point evaluation (the paper's per-evaluation data movement)
-BYTES_PER_EVAL = {0: 4.0, 1: 32.0}
+BYTES_PER_EVAL = {0: 4.0, 1: 32.0}  # binary32 storage; the 16-bit formats move half
+FORMATS = {"f32": 0, "f16": 1, "sn16": 2}
 HBM_PEAK_GBS = 8000.0
 # Sec. 4 multi-resolution PST: (particles, per-axis stride) used in turn; the
 # paper does not fix which combination starts a cycle: the densest template
@@ -52,6 +53,8 @@ def parse():
     ap.add_argument("--schedule", choices=["single", "multires"], default="single",
                     help="multires: the paper's alternation of (10240, 1/32), (3072, 1/16), (1024, 1/8) as strides "
                          "6, 4, 3")
+    ap.add_argument("--fmt", choices=list(FORMATS), default="f32",
+                    help="TSDF storage: binary32, binary16 or normalised int16 (arithmetic stays binary32)")
     ap.add_argument("--template", choices=["iid", "poisson"], default="iid",
                     help="poisson: 6D Poisson-disk template (dart throwing, packing fraction 0.03)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -167,7 +170,8 @@ def main():
     if args.copy_probe:
         copy_probe(torch, args.copy_probe)
     dev_depths = [torch.from_numpy(d).cuda() for d in depths]
-    vol = rose.Tsdf(seq.dims, seq.vox, seq.mu, seq.origin)
+    fmt = FORMATS[args.fmt]
+    vol = rose.Tsdf(seq.dims, seq.vox, seq.mu, seq.origin, fmt=fmt)
     if args.template == "poisson":
         pst, got, drawn = rose.pst_poisson(seq.n_particles, 5600, rose.poisson_radius(seq.n_particles), 1 << 22)
         if got != seq.n_particles:
@@ -221,7 +225,8 @@ def main():
     ate_mean, ate_rmse = synth.ate(est_a, gt)
     fit_ms = prof["fitness_ms"] / max(prof["fitness_launches"], 1)
     fit_evals = prof["fitness_evals"] / max(prof["fitness_launches"], 1)
-    achieved = fit_evals * BYTES_PER_EVAL[lookup] / (fit_ms * 1e-3) / 1e9
+    bytes_per_eval = BYTES_PER_EVAL[lookup] * (1.0 if fmt == 0 else 0.5)
+    achieved = fit_evals * bytes_per_eval / (fit_ms * 1e-3) / 1e9
     out = {
         "metric": "particle*point fitness evals/s (+ frames/s at 10k particles; ATE vs ground truth)",
         "value": evals / wall,
@@ -235,11 +240,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "room sequence, 512^3 TSDF @1cm f32, 640x480 f=525 stride 4, PST 10240, "
+        "config": {"workload": f"room sequence, 512^3 TSDF @1cm {args.fmt}, 640x480 f=525 stride 4, PST 10240, "
                                "20 iterations + fusion per frame, 3 m/s 2 rad/s",
                    "tsdf": [512, 512, 512], "voxel_m": 0.01, "image": [640, 480], "stride": 4,
                    "particles": seq.n_particles, "iters": seq.iters, "lookup": args.lookup, "schedule": args.schedule,
-                   "template": args.template},
+                   "template": args.template, "tsdf_format": args.fmt},
         "frames_per_s": args.steps / wall,
         "fitness_kernel_evals_per_s": prof["fitness_evals"] / (prof["fitness_ms"] * 1e-3),
         "ate_rmse_m": ate_rmse,
@@ -248,9 +253,9 @@ def main():
                                     "update": prof["update_ms"] / args.steps,
                                     "integrate": prof["integrate_ms"] / args.steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(lookup),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(lookup) if fmt == 0 else None,
                      "kernel": "k_fitness", "avg_launch_ms": fit_ms, "evals_per_launch": fit_evals,
-                     "bytes_per_eval": BYTES_PER_EVAL[lookup], "shape": list(tuned["shape"]),
+                     "bytes_per_eval": bytes_per_eval, "shape": list(tuned["shape"]),
                      "kernel_source_sha256_16": kernel_source_hash()},
     }
     g_l2 = gather_roofline(torch, rose, 2)
