@@ -248,14 +248,20 @@ def test_fitness_full_size_sampled(R, orc, room_frame):
                                                      for _ in range(10240)]), p0.R)
     T[:, :, 3] += rng.uniform(-0.1, 0.1, (10240, 3))
     T = T.astype(np.float32)
+    pick = np.concatenate([[0, 10239], rng.choice(10240, 22, replace=False)])
     for lookup in (0, 1):
-        F, _ = R.fitness_eval(vol, dev(pts), dev(T), lookup)
-        F = host(F)
-        pick = np.concatenate([[0, 10239], rng.choice(10240, 22, replace=False)])
         Fo = orc.fitness(psi, seq.vox, seq.origin.astype(np.float32), pts, T[pick].astype(np.float64), lookup=lookup,
                          prec=orc.F32)
-        assert _rel(F[pick], Fo) <= 1e-5
-        assert np.all((F >= 0) & (F <= 1))
+        # every launch shape the autotuner may pick for the bench
+        for shape in ((2, 4), (4, 2), (4, 4), (8, 2), (8, 4)):
+            try:
+                R.set_fitness_shape(*shape)
+                F, _ = R.fitness_eval(vol, dev(pts), dev(T), lookup)
+                F = host(F)
+            finally:
+                R.set_fitness_shape(4, 2)
+            assert _rel(F[pick], Fo) <= 1e-5, (lookup, shape)
+            assert np.all((F >= 0) & (F <= 1))
 
 
 # ------------------------------------------------------------ a8 fusion
@@ -359,15 +365,21 @@ def test_track_frame_corner_cases(R, orc, small_gpu):
     assert g["aps"] == [0] * 10 and list(st.pose.t) == list(prev.t)
 
 
-def test_track_full_size_first_iteration(R, orc, room_frame):
+@pytest.mark.parametrize("shape", [(4, 2), (8, 4)])
+def test_track_full_size_first_iteration(R, orc, room_frame, shape):
     """Real size (512^3, 640x480, stride 4, 10240 particles): one iteration
-    on the GPU equals the oracle's one iteration (APS size, centre, r_1)."""
+    on the GPU equals the oracle's one iteration (APS size, centre, r_1), in
+    the default launch shape and the one the bench's autotuner picks."""
     seq, vol, psi, _, _, d1 = room_frame
     pst, _ = orc.pst_sample(10240, 5600)
     prev = seq.poses[0]
     params = R.track_params(max_iters=1, stride=seq.stride)
     st = R.track_state(prev.q, prev.t, [0.55] * 6)
-    g = R.track_frame(vol, dev(d1), seq.K, dev(pst), params, st)
+    try:
+        R.set_fitness_shape(*shape)
+        g = R.track_frame(vol, dev(d1), seq.K, dev(pst), params, st)
+    finally:
+        R.set_fitness_shape(4, 2)
     o = orc.track_frame(psi, seq.vox, seq.origin, d1, seq.K, pst, prev.q, prev.t, np.full(6, 0.55), max_iters=1,
                         stride=seq.stride, prec=orc.F32)
     assert g["n_points"] == o["n_points"] and g["n_overlap"][0] == o["n_overlap_last"]
