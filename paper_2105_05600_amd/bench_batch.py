@@ -85,7 +85,7 @@ def learned_main(args):
     with open(os.path.splitext(weights)[0] + ".json") as f:
         meta = json.load(f)
     n = args.sequences
-    seqs = [tp.make_sequence(52000 + 10 * i, args.frames, 320, 240) for i in range(n)]
+    seqs = [tp.make_sequence(args.seed_base + 10 * i, args.frames, 320, 240) for i in range(n)]
     t0 = time.perf_counter()
     depths = [[torch.from_numpy(d).cuda() for d in sq.depths(range(args.frames), workers=16)] for sq in seqs]
     log(f"rendered {n} x {args.frames} frames in {time.perf_counter() - t0:.1f} s")
@@ -153,7 +153,7 @@ def learned_main(args):
     b.close()
     steps = n * (args.frames - 1)
     out = {"metric": "learned proposal batched vs plain PST: frames/s over all sequences and ATE",
-           "sequences": n, "frames": args.frames, "image": [320, 240],
+           "sequences": n, "frames": args.frames, "image": [320, 240], "seed_base": args.seed_base,
            "learned": {"particles": pst_small.shape[0], "iters": iters, "kappa": meta["kappa"], "delta": meta["delta"]},
            "plain_single": {"frames_per_s": steps / wall_p, "ate_rmse_mean_m": float(np.mean(ate_p)),
                             "ate_rmse_median_m": float(np.median(ate_p))},
@@ -169,6 +169,7 @@ def main():
     ap.add_argument("--frames", type=int, default=30)
     ap.add_argument("--tune-steps", type=int, default=3)
     ap.add_argument("--small", action="store_true", help="small sequences (128^3 at 4 cm, 160x120, 1024 particles)")
+    ap.add_argument("--seed-base", type=int, default=52000, help="--learned: first sequence seed")
     ap.add_argument("--learned", action="store_true",
                     help="learned proposal, batched, against plain PST one sequence after another (320x240)")
     args = ap.parse_args()
