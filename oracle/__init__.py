@@ -51,6 +51,15 @@ Parity status per function (what pins it, tests/test_oracle_*.py):
                         within half a voxel; plane exact; misses are 0.
 * proposal_features  -- pinned: closed forms on constant frames (clamped
                         difference, missing samples, velocity, padding).
+* pfo_resample / pso_move / swarm_frame (comparison optimisers of the
+  Sec. 5 ablation)   -- pinned: a hand-worked resampling example; equal
+                        weights give the identity; one dominant weight takes
+                        every slot; copy counts within one of n w_i / W; a
+                        hand-worked PSO step with the velocity clamp; with no
+                        motion (sigma = 0, or c1 = c2 = 0 from rest) the
+                        result is the brute-force best of the initial set;
+                        the best fitness never decreases; both converge on
+                        the small frame.
 * mlp (oracle/mlp.py) -- pinned: central differences of the loss; GELU
                         closed forms; the NLL minimiser is the sample mean
                         and log standard deviation; Adam's first step.
@@ -79,6 +88,8 @@ NO_NORMALIZE = 2
 CENTRE_THRESHOLD = 4
 ISO_ONLY = 8
 ANISO_ONLY = 16
+SWARM_PFO = 0
+SWARM_PSO = 1
 
 
 def _cpu_has_fma() -> bool:
@@ -110,6 +121,13 @@ class _TrackParams(C.Structure):
                 ("lookup", C.c_int32), ("flags", C.c_int32), ("prec", C.c_int32),
                 ("levels", C.c_int32), ("level_n", C.c_int32 * 4), ("level_stride", C.c_int32 * 4),
                 ("beta", C.c_double), ("eps", C.c_double), ("tau", C.c_double), ("stop_tol", C.c_double)]
+
+
+class _SwarmParams(C.Structure):
+    _fields_ = [("method", C.c_int32), ("iters", C.c_int32), ("stride", C.c_int32), ("lookup", C.c_int32),
+                ("flags", C.c_int32), ("prec", C.c_int32), ("tau", C.c_double), ("r_init", C.c_double * 6),
+                ("sigma", C.c_double * 6), ("w_start", C.c_double), ("w_end", C.c_double), ("c1", C.c_double),
+                ("c2", C.c_double), ("vmax", C.c_double * 6)]
 
 
 def _load():
@@ -150,6 +168,12 @@ def _load():
                                           C.c_float, P, C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float,
                                           C.c_float, P, P, C.c_int]
             lib.orc_integrate.restype = C.c_int64
+            lib.orc_pfo_resample.argtypes = [P, C.c_int32, C.c_double, C.c_double, C.c_double, P]
+            lib.orc_pso_move.argtypes = [P, P, P, P, P, C.c_int32, C.c_float, C.c_float, C.c_float, P]
+            lib.orc_swarm_frame.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_float, P, P, C.c_int32,
+                                            C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float, P, C.c_int32,
+                                            P, P, C.POINTER(_SwarmParams), P, P, P, P, P, P, P, P, P, P]
+            lib.orc_swarm_frame.restype = C.c_int
             lib.orc_raycast.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_float, P, P, P, C.c_int32,
                                         C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
                                         C.c_double, C.c_double, P]
@@ -395,3 +419,62 @@ def proposal_features(depth, render, scale: int, velocity, dim: int) -> np.ndarr
                 out[v * w + u] = min(np.float32(0.5), max(np.float32(-0.5), np.float32(d - m)))
     out[h * w:h * w + 6] = np.asarray(velocity, np.float64).astype(np.float32)
     return out
+
+
+# ------------------------------------------- comparison optimisers (Sec. 5)
+def pfo_resample(F, F_best: float, u: float, tau: float = 1.0) -> np.ndarray:
+    """Ancestors (int32, n) of systematic resampling with the weights
+    exp(-(F_i - F_best)/tau) and offset u in [0, 1)."""
+    lib = _load()
+    F = _f64(F)
+    anc = np.zeros(max(len(F), 1), dtype=np.int32)
+    lib.orc_pfo_resample(_p(F), len(F), float(F_best), float(tau), float(u), _p(anc))
+    return anc[:len(F)].copy()
+
+
+def pso_move(x, v, p, g, R, w: float, c1: float, c2: float, vmax):
+    """One PSO velocity/position step; returns the new (x, v) (float32)."""
+    lib = _load()
+    x, v, p = _f32(x).copy(), _f32(v).copy(), _f32(p)
+    g, R, vm = _f32(g), _f32(R), _f32(vmax)
+    n = x.shape[0]
+    lib.orc_pso_move(_p(x), _p(v), _p(p), _p(g), _p(R), n, float(w), float(c1), float(c2), _p(vm))
+    return x, v
+
+
+def swarm_frame(method: int, psi, vox, origin, depth, K, pst, q_prev, t_prev, draws, offsets=None, iters=20,
+                stride=4, lookup=NEAREST, flags=0, prec=F32, tau=1.0, r_init=(0.1,) * 6, sigma=None,
+                w_start=0.9, w_end=0.4, c1=2.0, c2=2.0, vmax=None):
+    """One frame of vanilla PFO (method SWARM_PFO) or PSO (SWARM_PSO) from
+    c_0 = (q_prev, t_prev).  draws: PFO (iters, n, 6) standard normals, PSO
+    (iters, n, 12) uniforms; offsets: PFO (iters,) uniforms.  sigma defaults
+    to r_init / sqrt(8) (the per-axis spread of the initial set), vmax to
+    r_init."""
+    lib = _load()
+    psi = _f32(psi)
+    nz, ny, nx = psi.shape
+    depth = _f32(depth)
+    H, W = depth.shape
+    pst = _f32(pst)
+    n = len(pst)
+    r_init = np.asarray(r_init, np.float64)
+    sigma = r_init / np.sqrt(8.0) if sigma is None else np.asarray(sigma, np.float64)
+    vmax = r_init if vmax is None else np.asarray(vmax, np.float64)
+    d6 = lambda a: (C.c_double * 6)(*[float(e) for e in a])  # noqa: E731
+    P = _SwarmParams(method, iters, stride, lookup, flags, prec, tau, d6(r_init), d6(sigma), w_start, w_end, c1,
+                     c2, d6(vmax))
+    cols = 6 if method == SWARM_PFO else 12
+    dr = _f32(draws).reshape(-1)
+    assert dr.size >= iters * n * cols, "draws too small"
+    off = _f32(np.zeros(iters) if offsets is None else offsets)
+    q_out, t_out, rho = np.zeros(4), np.zeros(3), np.zeros(1)
+    rb, rm = np.zeros(32), np.zeros(32)
+    bi, nov, npts = np.zeros(32, np.int32), np.zeros(32, np.int32), np.zeros(1, np.int32)
+    org = _f32(origin)
+    q_prev, t_prev = _f64(q_prev), _f64(t_prev)
+    rc = lib.orc_swarm_frame(_p(psi), nx, ny, nz, float(vox), _p(org), _p(depth), W, H, K.fx, K.fy, K.cx, K.cy,
+                             _p(pst), n, _p(q_prev), _p(t_prev), C.byref(P), _p(dr), _p(off), _p(q_out), _p(t_out),
+                             _p(rho), _p(rb), _p(rm), _p(bi), _p(nov), _p(npts))
+    k = iters if rc == 0 else 0
+    return dict(status=int(rc), q=q_out, t=t_out, rho=float(rho[0]), rho_best=rb[:k].copy(), rho_mean=rm[:k].copy(),
+                best_index=bi[:k].copy(), n_overlap=nov[:k].copy(), n_points=int(npts[0]))

@@ -888,3 +888,202 @@ void orc_raycast(const float* psi, int32_t nx, int32_t ny, int32_t nz, float vox
             depth_out[(size_t)v * W + u] = (float)out;
         }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Comparison optimisers of the Sec. 5 ablation of the optimisation         */
+/* strategy: vanilla PFO (particle filter optimisation as in Sec. 3.1,      */
+/* without particle swarm guidance) and PSO (particle swarm optimisation,   */
+/* no template), on the same fitness (Eq. normallh) and particle count as   */
+/* PFO with PST.  The paper names both without parameters; the readings:   */
+/*  * State space: the chart at the frame's initial pose c_0 = s^{t-1}_*;   */
+/*    particle x in R^6 (binary32) denotes the pose c_0 * Delta(x).          */
+/*  * Start: x_i = (float)(r_init_d * p_i,d) from the PST template, i.e.    */
+/*    the initial particle set of PFO with PST at axis lengths r_init.       */
+/*  * Iteration k = 1..K: O_k is the overlap set (Eq. validness) of the     */
+/*    best state so far s*_{k-1} (s*_0 = c_0); F_i is the fitness of         */
+/*    c_0 * Delta(x_i) over O_k (rounded to binary32 in F32 mode); the best  */
+/*    state is replaced when min_i F_i (lowest index on ties) is strictly    */
+/*    below F*.  Then, for k < K, one step of the method.                    */
+/*  * Vanilla PFO step (Eqs. proposal, weight, pfolh): after resampling the */
+/*    weights are uniform, so the new weight is the likelihood of Eq. pfolh */
+/*    with g(s*) the best objective found so far, w_i = exp(-(F_i - F*)/tau);*/
+/*    systematic resampling with one offset u_k in [0, 1); Gaussian proposal */
+/*    around each resampled particle, Sigma = diag(sigma^2) fixed.           */
+/*  * PSO step (inertia-weight PSO with a global best, the empirical study  */
+/*    the paper cites for PSO): personal bests, inertia weight linear from   */
+/*    w_start (k = 1) to w_end (k = K), acceleration coefficients c1, c2,    */
+/*    velocity clamp vmax, velocities starting at 0.                         */
+/*  * Output: s^t = c_0 * Delta(x*) (orc_pose_retract), rho = exp(-F* / tau). */
+/* Random numbers are inputs: PFO takes K x n x 6 standard normals and K    */
+/* offsets, PSO K x n x 12 uniforms (r1 in columns 0-5, r2 in 6-11); the    */
+/* draws of step k (after iteration k) are row k - 1.                       */
+/* ------------------------------------------------------------------------ */
+#define ORC_SWARM_PFO 0
+#define ORC_SWARM_PSO 1
+
+/* Systematic resampling of n particles with weights                        */
+/* w_i = exp(-(F_i - F_best)/tau): C_i = w_0 + ... + w_i (binary64, in      */
+/* index order); the ancestor of slot m is the first i with                 */
+/* C_i > ((m + u)/n) C_{n-1} (n - 1 if none).                               */
+void orc_pfo_resample(const double* F, int32_t n, double F_best, double tau, double u, int32_t* anc) {
+    double* Cs = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double acc = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        acc += exp(-(F[i] - F_best) / tau);
+        Cs[i] = acc;
+    }
+    int32_t i = 0;
+    for (int32_t m = 0; m < n; ++m) {
+        const double t = (((double)m + u) / (double)n) * Cs[n - 1];
+        while (i < n - 1 && !(Cs[i] > t)) ++i;
+        anc[m] = i;
+    }
+    free(Cs);
+}
+
+/* PSO velocity and position step for n particles (x, v, p: n x 6; g: 6;   */
+/* R: n x 12 uniforms), binary32 in this order per coordinate d:           */
+/*   a = (c1 * r1) * (p - x);  b = (c2 * r2) * (g - x);                    */
+/*   v = ((w * v) + a) + b;  v = min(max(v, -vmax), vmax);  x = x + v.      */
+void orc_pso_move(float* x, float* v, const float* p, const float* g, const float* R, int32_t n, float w, float c1,
+                  float c2, const float vmax[6]) {
+    for (int32_t i = 0; i < n; ++i) {
+        for (int d = 0; d < 6; ++d) {
+            const size_t e = 6 * (size_t)i + d;
+            const float r1 = R[12 * (size_t)i + d], r2 = R[12 * (size_t)i + 6 + d];
+            const float t1 = c1 * r1, t2 = c2 * r2;
+            const float d1 = p[e] - x[e], d2 = g[d] - x[e];
+            const float a = t1 * d1, b = t2 * d2;
+            float vv = w * v[e];
+            vv = vv + a;
+            vv = vv + b;
+            vv = fminf(fmaxf(vv, -vmax[d]), vmax[d]);
+            v[e] = vv;
+            x[e] = x[e] + vv;
+        }
+    }
+}
+
+typedef struct {
+    int32_t method, iters, stride, lookup, flags, prec;
+    double tau;
+    double r_init[6], sigma[6];
+    double w_start, w_end, c1, c2;
+    double vmax[6];
+} orc_swarm_params;
+
+/* One frame of either comparison optimiser.  Returns 0, -1 for bad         */
+/* parameters, -4 when the frame has no valid point (pose unchanged).       */
+/* Per iteration k (index k - 1): rho_best = exp(-F* / tau) after the         */
+/* iteration, rho_mean = mean_i exp(-F_i/tau), best_index = the particle    */
+/* that improved F* (-1 if none), n_overlap = |O_k|.                         */
+int orc_swarm_frame(const float* psi, int32_t nx, int32_t ny, int32_t nz, float vox, const float origin[3],
+                    const float* depth, int32_t W, int32_t H, float fx, float fy, float cx, float cy,
+                    const float* pst, int32_t n, const double q_prev[4], const double t_prev[3],
+                    const orc_swarm_params* P, const float* draws, const float* offsets, double q_out[4],
+                    double t_out[3], double* rho_out, double* rho_best, double* rho_mean, int32_t* best_index,
+                    int32_t* n_overlap, int32_t* n_points_out) {
+    memcpy(q_out, q_prev, 4 * sizeof(double));
+    memcpy(t_out, t_prev, 3 * sizeof(double));
+    *n_points_out = 0;
+    if (n < 1 || P->iters < 1 || P->iters > 32 || P->stride < 1 ||
+        (P->method != ORC_SWARM_PFO && P->method != ORC_SWARM_PSO))
+        return -1;
+    const int32_t K = P->iters;
+    const int32_t cap = ((H + P->stride - 1) / P->stride) * ((W + P->stride - 1) / P->stride);
+    float* pts = (float*)malloc(sizeof(float) * 3 * (size_t)(cap > 0 ? cap : 1));
+    const int32_t m = orc_unproject(depth, W, H, fx, fy, cx, cy, P->stride, P->prec, pts);
+    *n_points_out = m;
+    if (m == 0) {
+        free(pts);
+        return -4;
+    }
+    uint8_t* mask = (uint8_t*)malloc((size_t)m);
+    double* T = (double*)malloc(sizeof(double) * 12 * (size_t)n);
+    double* F = (double*)malloc(sizeof(double) * (size_t)n);
+    float* x = (float*)malloc(sizeof(float) * 6 * (size_t)n);
+    float* xn = (float*)malloc(sizeof(float) * 6 * (size_t)n);
+    float* v = (float*)calloc(6 * (size_t)n, sizeof(float));
+    float* pb = (float*)malloc(sizeof(float) * 6 * (size_t)n);
+    double* pF = (double*)malloc(sizeof(double) * (size_t)n);
+    int32_t* anc = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    const double ones[6] = {1, 1, 1, 1, 1, 1};
+    for (int32_t i = 0; i < n; ++i) {
+        for (int d = 0; d < 6; ++d) x[6 * (size_t)i + d] = (float)(P->r_init[d] * (double)pst[6 * (size_t)i + d]);
+        pF[i] = INFINITY;
+    }
+    double Tprev[12];
+    orc_pose_to_mat(q_prev, t_prev, Tprev);
+    double qb[4], tb[3], Fb = INFINITY;
+    float xb[6] = {0, 0, 0, 0, 0, 0};
+    memcpy(qb, q_prev, sizeof qb);
+    memcpy(tb, t_prev, sizeof tb);
+    float sig[6], vmx[6];
+    for (int d = 0; d < 6; ++d) {
+        sig[d] = (float)P->sigma[d];
+        vmx[d] = (float)P->vmax[d];
+    }
+    for (int32_t k = 1; k <= K; ++k) {
+        double Tb[12];
+        orc_pose_to_mat(qb, tb, Tb);
+        int32_t nO;
+        if (P->flags & ORC_NO_OVERLAP) {
+            for (int32_t j = 0; j < m; ++j) mask[j] = 1;
+            nO = m;
+        } else {
+            nO = orc_overlap(pts, m, Tb, Tprev, fx, fy, cx, cy, W, H, P->prec, mask);
+        }
+        for (int32_t i = 0; i < n; ++i) orc_particle_pose(q_prev, t_prev, ones, x + 6 * (size_t)i, T + 12 * (size_t)i);
+        orc_fitness(psi, nx, ny, nz, vox, origin, pts, m, mask, T, n, P->lookup, P->prec,
+                    !(P->flags & ORC_NO_NORMALIZE), F);
+        if (P->prec == ORC_F32)
+            for (int32_t i = 0; i < n; ++i) F[i] = (double)(float)F[i];
+        int32_t imin = 0;
+        double srho = 0.0;
+        for (int32_t i = 0; i < n; ++i) {
+            if (F[i] < F[imin]) imin = i;
+            srho += exp(-F[i] / P->tau);
+        }
+        best_index[k - 1] = -1;
+        if (F[imin] < Fb) {
+            double u[6];
+            Fb = F[imin];
+            for (int d = 0; d < 6; ++d) {
+                xb[d] = x[6 * (size_t)imin + d];
+                u[d] = (double)xb[d];
+            }
+            orc_pose_retract(q_prev, t_prev, u, qb, tb);
+            best_index[k - 1] = imin;
+        }
+        rho_best[k - 1] = exp(-Fb / P->tau);
+        rho_mean[k - 1] = srho / (double)n;
+        n_overlap[k - 1] = nO;
+        if (k == K) break;
+        if (P->method == ORC_SWARM_PFO) {
+            orc_pfo_resample(F, n, Fb, P->tau, (double)offsets[k - 1], anc);
+            const float* N = draws + (size_t)(k - 1) * n * 6;
+            for (int32_t i = 0; i < n; ++i)
+                for (int d = 0; d < 6; ++d) {
+                    const float step = sig[d] * N[6 * (size_t)i + d];
+                    xn[6 * (size_t)i + d] = x[6 * (size_t)anc[i] + d] + step;
+                }
+            float* tmp = x;
+            x = xn;
+            xn = tmp;
+        } else {
+            for (int32_t i = 0; i < n; ++i)
+                if (F[i] < pF[i]) {
+                    pF[i] = F[i];
+                    memcpy(pb + 6 * (size_t)i, x + 6 * (size_t)i, 6 * sizeof(float));
+                }
+            const double w = P->w_start + (P->w_end - P->w_start) * (double)(k - 1) / (double)(K - 1);
+            orc_pso_move(x, v, pb, xb, draws + (size_t)(k - 1) * n * 12, n, (float)w, (float)P->c1, (float)P->c2,
+                         vmx);
+        }
+    }
+    memcpy(q_out, qb, sizeof qb);
+    memcpy(t_out, tb, sizeof tb);
+    *rho_out = exp(-Fb / P->tau);
+    free(pts); free(mask); free(T); free(F); free(x); free(xn); free(v); free(pb); free(pF); free(anc);
+    return 0;
+}
