@@ -270,6 +270,7 @@ typedef struct {
     int32_t n_overlap[ROSE_MAX_ITERS]; /* |O_k| per iteration */
     double rho_iter[ROSE_MAX_ITERS];   /* rho~ per iteration (rho of the centre when the APS is empty) */
     int32_t n_particles[ROSE_MAX_ITERS]; /* particles evaluated per iteration */
+    double rho_centre[ROSE_MAX_ITERS];   /* exact rho of the centre c_{k-1} (particle 0) in iteration k */
 } rose_track_stats;
 
 /* One frame of Alg. 1 (PFO with PST) on the device.
@@ -293,6 +294,71 @@ typedef struct {
 rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_camera* cam, const float* pst_dev,
                             int32_t n_particles, const rose_track_params* p, const rose_pose* init_centre,
                             const double* init_r, rose_track_state* state, rose_track_stats* stats, hipStream_t s);
+
+/* ------------------------------------------- comparison optimisers */
+/* The two optimisers that Sec. 5 (ablation of the optimisation strategy)
+ * compares PFO with PST against: vanilla PFO (Sec. 3.1: Gaussian proposal,
+ * Eq. proposal; weights by the likelihood of Eq. pfolh, Eq. weight;
+ * resampling) and PSO (inertia-weight particle swarm optimisation with a
+ * global best).  Both use the fitness of Eq. normallh and the same particle
+ * count.  The paper gives neither method's parameters; the definitions:
+ *  - state: x in R^6 (binary32) in the chart at c_0 = state->pose, i.e. the
+ *    pose c_0 * Delta(x); start x_i = (float)(r_init_d * p_i,d) from the PST
+ *    template rows p_i (the initial particle set of PFO with PST);
+ *  - iteration k = 1..iters: O_k = overlap set (Eq. validness) of the best
+ *    state so far s*_{k-1} (s*_0 = c_0); F_i = fitness of c_0 * Delta(x_i)
+ *    over O_k, kept in binary32; the best state becomes the particle with
+ *    the smallest F_i (lowest index on ties) if that is below F*; then, for
+ *    k < iters, one step of the method;
+ *  - vanilla PFO step: w_i = exp(-(F_i - F*) / tau) (uniform weights after
+ *    the previous resampling, so Eq. weight is Eq. pfolh with g(s*) = F*);
+ *    systematic resampling, C_i = w_0 + .. + w_i, the ancestor of slot m is
+ *    the first i with C_i > ((m + u_k) / n) C_{n-1}; proposal
+ *    x'_m = x_{a_m} + sigma (.) z_{k,m} (product and sum rounded to binary32);
+ *  - PSO step: personal best p_i (F_i below the particle's best so far);
+ *    w_k = w_start + (w_end - w_start)(k - 1)/(iters - 1);
+ *    v = ((w_k v + (c1 r1)(p_i - x)) + (c2 r2)(x* - x)) clamped to
+ *    [-vmax, vmax], x = x + v, binary32 in this order, v starting at 0;
+ *  - result: state->pose = c_0 * Delta(x*) (quaternion renormalised),
+ *    state->rho = exp(-F* / tau), state->frame + 1; state->r is untouched.
+ * Random numbers are inputs (device buffers, float32): PFO normals_dev
+ * iters x n x 6 standard normals z and offsets_dev iters uniforms u_k in
+ * [0, 1); PSO uniforms_dev iters x n x 12 (r1 in columns 0-5, r2 in 6-11).
+ * Row k - 1 serves the step after iteration k (the last row is not read).
+ * flags: ROSE_FLAG_NO_OVERLAP and ROSE_FLAG_NO_NORMALIZE (others: E_ARG).
+ * state->tsdf_built == 0: nothing to search, the pose is kept (OK).  No
+ * valid depth sample: ROSE_E_STATE, state unchanged.  The search runs on
+ * the device and the call synchronises `s` once at the end.  Scratch
+ * (108 bytes per particle) is owned by the handle. */
+typedef struct {
+    int32_t iters;      /* 1..ROSE_MAX_ITERS */
+    int32_t stride;     /* depth subsampling stride (>= 1) */
+    int32_t lookup;     /* rose_lookup */
+    int32_t flags;      /* ROSE_FLAG_NO_OVERLAP | ROSE_FLAG_NO_NORMALIZE */
+    double tau;         /* temperature (> 0; paper: 1) */
+    double r_init[6];   /* axis lengths of the initial set (>= 0) */
+    double sigma[6];    /* vanilla PFO: standard deviation of the proposal per axis (>= 0) */
+    double w_start, w_end; /* PSO: inertia weight at the first and last iteration */
+    double c1, c2;      /* PSO: acceleration towards the personal and the global best */
+    double vmax[6];     /* PSO: velocity clamp per axis (>= 0) */
+} rose_swarm_params;
+
+typedef struct {
+    int32_t iters;                       /* iterations run */
+    int32_t n_points;                    /* valid subsampled points */
+    int32_t n_overlap[ROSE_MAX_ITERS];   /* |O_k| */
+    int32_t best_index[ROSE_MAX_ITERS];  /* particle that improved F* in iteration k, -1 if none */
+    double rho_best[ROSE_MAX_ITERS];     /* exp(-F* / tau) after iteration k */
+    double rho_mean[ROSE_MAX_ITERS];     /* mean over the particles of exp(-F_i / tau) in iteration k */
+} rose_swarm_stats;
+
+rose_status vanilla_pfo_track_frame(rose_tsdf* h, const float* depth_dev, const rose_camera* cam,
+                                    const float* pst_dev, int32_t n_particles, const rose_swarm_params* p,
+                                    const float* normals_dev, const float* offsets_dev, rose_track_state* state,
+                                    rose_swarm_stats* stats, hipStream_t s);
+rose_status plain_pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_camera* cam, const float* pst_dev,
+                                  int32_t n_particles, const rose_swarm_params* p, const float* uniforms_dev,
+                                  rose_track_state* state, rose_swarm_stats* stats, hipStream_t s);
 
 /* Chart of Sec. 3.3 between two poses: u = (imaginary part of the
  * quaternion of a^-1 b with w >= 0, translation of a^-1 b), so that

@@ -248,6 +248,7 @@ struct DevState {
     int32_t aps[ROSE_MAX_ITERS];
     int32_t n_overlap_iter[ROSE_MAX_ITERS];
     double rho_iter[ROSE_MAX_ITERS];
+    double rho_centre[ROSE_MAX_ITERS];  // exact rho of c_{k-1} (particle 0) in iteration k
 };
 
 // per-frame inputs of one tracked sequence
@@ -316,6 +317,15 @@ struct rose_tsdf {
     int64_t cap_points_o;
     int64_t cap_partial;
     int64_t cap_particles;
+    // comparison optimisers' scratch (swarm.hip), n particles
+    float* sw_x;        // 2 x n x 6 states (current, next)
+    float* sw_v;        // n x 6 velocities
+    float* sw_p;        // n x 6 personal bests
+    float* sw_pF;       // n personal best fitness values
+    double* sw_C;       // n cumulative resampling weights
+    void* sw_st;        // device search state
+    void* sw_host;      // pinned host copy
+    int64_t cap_swarm;
 };
 
 namespace rose {

@@ -7,85 +7,9 @@
 // synchronises once.
 #include <algorithm>
 
-#include "common.h"
+#include "track_dev.h"
 
 namespace rose {
-
-struct Cam {
-    float fx, fy, cx, cy;
-    int32_t W, H;
-};
-
-// Eq. unproj in binary32: x = (((float)u - cx) z) / fx, y likewise.
-__device__ inline float4 unproject_px(const Cam& c, int u, int v, float z) {
-    return make_float4((((float)u - c.cx) * z) / c.fx, (((float)v - c.cy) * z) / c.fy, z, 0.0f);
-}
-
-// Eq. validness with A = T_prev^-1 T_c rounded to binary32:
-// x' = A x (fmaf chain); kept iff z' > 0 and the projection
-// (fmaf(fx, x'/z', cx), fmaf(fy, y'/z', cy)) lies in [0, W-1] x [0, H-1].
-__device__ inline bool overlap_keep(const Cam& c, const float* A, float4 x) {
-    const float xp = xf_row(A[0], A[1], A[2], A[3], x.x, x.y, x.z);
-    const float yp = xf_row(A[4], A[5], A[6], A[7], x.x, x.y, x.z);
-    const float zp = xf_row(A[8], A[9], A[10], A[11], x.x, x.y, x.z);
-    if (!(zp > 0.0f)) return false;
-    const float px = fmaf(c.fx, xp / zp, c.cx);
-    const float py = fmaf(c.fy, yp / zp, c.cy);
-    return px >= 0.0f && px <= (float)(c.W - 1) && py >= 0.0f && py <= (float)(c.H - 1);
-}
-
-// Enumeration of the stride-s sample grid (su x sv samples).  Row-major
-// (tiled = false), or 8x8-sample tiles in row-major tile order with
-// row-major samples inside a tile (tiled = true), so that the 64 lanes of a
-// wavefront see a compact image patch and their TSDF gathers share cache
-// lines.  Returns false for the padding positions of partial tiles.
-__device__ inline int sample_count(int su, int sv, bool tiled) {
-    return tiled ? ((su + 7) / 8) * ((sv + 7) / 8) * 64 : su * sv;
-}
-
-__device__ inline bool sample_at(int q, int su, int sv, bool tiled, int* uu, int* vv) {
-    if (!tiled) {
-        *uu = q % su;
-        *vv = q / su;
-        return true;
-    }
-    const int ntx = (su + 7) / 8;
-    const int t = q >> 6, e = q & 63;
-    *uu = (t % ntx) * 8 + (e & 7);
-    *vv = (t / ntx) * 8 + (e >> 3);
-    return *uu < su && *vv < sv;
-}
-
-// Whole-block order-preserving overlap compaction of m points.
-__device__ inline int overlap_compact(const Cam& c, const float* A, bool all, const float4* pts, int m, float4* out,
-                                      int* lds) {
-    int base = 0;
-    for (int j0 = 0; j0 < m; j0 += blockDim.x) {
-        const int j = j0 + threadIdx.x;
-        float4 x = make_float4(0, 0, 0, 0);
-        int keep = 0;
-        if (j < m) {
-            x = pts[j];
-            keep = all ? 1 : (overlap_keep(c, A, x) ? 1 : 0);
-        }
-        int tot;
-        const int pos = block_scan_flag(keep, lds, &tot);
-        if (keep) out[base + pos] = x;
-        base += tot;
-    }
-    return base;
-}
-
-struct InitStatic {
-    DevState* st;
-    Cam cam;
-    int32_t levels;                        // 1, or the multi-resolution level count
-    int32_t flags;
-    int32_t stride[ROSE_MAX_LEVELS];       // subsampling stride per level
-    int32_t offset[ROSE_MAX_LEVELS];       // first point of each level in pts
-    float4* pts;
-    float4* pts_o;
-};
 
 // Stride-s unprojection of a frame into pts (8x8-sample tile order,
 // order-preserving compaction); returns the number of valid samples.
@@ -166,6 +90,12 @@ __device__ void track_init_body(const InitStatic& a, const FrameIn& in) {
 
 __global__ __launch_bounds__(1024) void k_track_init(InitStatic a, FrameIn in) { track_init_body(a, in); }
 
+rose_status launch_track_init(const InitStatic& a, const FrameIn& in, hipStream_t s) {
+    hipLaunchKernelGGL(k_track_init, dim3(1), dim3(1024), 0, s, a, in);
+    ROSE_CHECK_HIP(hipGetLastError());
+    return ROSE_OK;
+}
+
 // one workgroup per sequence; the per-frame inputs are read from pinned host
 // memory (so that a captured graph replays with new inputs)
 __global__ __launch_bounds__(1024) void k_track_init_batch(const InitStatic* a, const FrameIn* in_host) {
@@ -175,32 +105,6 @@ __global__ __launch_bounds__(1024) void k_track_init_batch(const InitStatic* a, 
         ((uint64_t*)&fin)[threadIdx.x] = ((const volatile uint64_t*)&in_host[blockIdx.x])[threadIdx.x];
     __syncthreads();
     track_init_body(a[blockIdx.x], fin);
-}
-
-struct UpdateArgs {
-    DevState* st;
-    Cam cam;
-    const float* pst;
-    const double* partial;
-    float* F;
-    const float4* pts;  // points of the next iteration's level
-    float4* pts_o;
-    int32_t next_level; // level of the next iteration (its count is st->lvl_points[next_level])
-    int32_t n;
-    int32_t splits;
-    int32_t max_iters;
-    int32_t early_stop;
-    int32_t flags;
-    double beta, eps, tau, stop_tol;
-};
-
-__device__ inline float final_fitness(const UpdateArgs& a, int i, int nO) {
-    double s = 0.0;
-    for (int k = 0; k < a.splits; ++k) s += a.partial[(int64_t)i * a.splits + k];
-    double f;
-    if (a.flags & ROSE_FLAG_NO_NORMALIZE) f = s;
-    else f = (nO > 0) ? s / (double)nO : 1.0;
-    return (float)f;
 }
 
 // F_i of every particle from its slice partials (fixed slice order), before
@@ -213,6 +117,12 @@ __device__ inline void reduce_fitness_body(const UpdateArgs& a, int i) {
 
 __global__ __launch_bounds__(256) void k_fitness_reduce(UpdateArgs a) {
     reduce_fitness_body(a, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+rose_status launch_fitness_reduce(const UpdateArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_fitness_reduce, dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+    ROSE_CHECK_HIP(hipGetLastError());
+    return ROSE_OK;
 }
 
 // one column of workgroups per sequence
@@ -299,6 +209,7 @@ __device__ void track_update_body(const UpdateArgs& a) {
         st->aps[k] = aps;
         st->n_overlap_iter[k] = nO;
         st->rho_iter[k] = rt;
+        st->rho_centre[k] = centre;
         st->k = k + 1;
         if (k == 0)
             for (int d = 0; d < 6; ++d) st->r1[d] = st->r[d];
@@ -375,26 +286,6 @@ __global__ __launch_bounds__(256) void k_overlap_only(OverlapArgs a) {
     if (j >= a.m) return;
     const float4 x = make_float4(a.pts3[3 * (int64_t)j], a.pts3[3 * (int64_t)j + 1], a.pts3[3 * (int64_t)j + 2], 0.f);
     a.mask[j] = overlap_keep(a.cam, a.A, x) ? 1 : 0;
-}
-
-static Cam to_cam(const rose_camera* c) { return Cam{c->fx, c->fy, c->cx, c->cy, c->width, c->height}; }
-
-static rose_status check_cam(const rose_camera* c, const char* who) {
-    ROSE_REQUIRE(c != nullptr, ROSE_E_ARG, "%s: NULL camera", who);
-    ROSE_REQUIRE(c->width > 0 && c->height > 0 && (int64_t)c->width * c->height <= (int64_t)ROSE_MAX_IMAGE_PIXELS,
-                 ROSE_E_SHAPE, "%s: image %dx%d out of range", who, c->width, c->height);
-    ROSE_REQUIRE(c->fx > 0 && c->fy > 0, ROSE_E_ARG, "%s: focal lengths must be > 0", who);
-    return ROSE_OK;
-}
-
-template <typename T>
-static rose_status grow(T** p, int64_t* cap, int64_t need) {
-    if (*cap >= need && *p) return ROSE_OK;
-    if (*p) ROSE_CHECK_HIP(hipFree(*p));
-    *p = nullptr;
-    ROSE_CHECK_HIP(hipMalloc((void**)p, sizeof(T) * (size_t)(need > 0 ? need : 1)));
-    *cap = need;
-    return ROSE_OK;
 }
 
 }  // namespace rose
@@ -606,6 +497,7 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_cam
             stats->aps_size[k] = r.aps[k];
             stats->n_overlap[k] = r.n_overlap_iter[k];
             stats->rho_iter[k] = r.rho_iter[k];
+            stats->rho_centre[k] = r.rho_centre[k];
             stats->n_particles[k] = lv_n[k % L];
         }
     }
@@ -997,6 +889,7 @@ rose_status pso_batch_track(rose_batch* b, const float* const* depth_devs, const
                 stats[i].aps_size[k] = r.aps[k];
                 stats[i].n_overlap[k] = r.n_overlap_iter[k];
                 stats[i].rho_iter[k] = r.rho_iter[k];
+                stats[i].rho_centre[k] = r.rho_centre[k];
                 stats[i].n_particles[k] = b->n[i];
             }
         }

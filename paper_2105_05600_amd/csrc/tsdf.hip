@@ -229,13 +229,20 @@ rose_status tsdf_create(int32_t nx, int32_t ny, int32_t nz, float voxel_m, float
 rose_status tsdf_destroy(rose_tsdf* h) {
     clear_error();
     if (h == nullptr) return ROSE_OK;
-    if (h->pts || h->partial || h->st) (void)hipDeviceSynchronize();
+    if (h->pts || h->partial || h->st || h->sw_x) (void)hipDeviceSynchronize();
     if (h->pts) (void)hipFree(h->pts);
     if (h->pts_o) (void)hipFree(h->pts_o);
     if (h->partial) (void)hipFree(h->partial);
     if (h->F) (void)hipFree(h->F);
     if (h->st) (void)hipFree(h->st);
     if (h->st_host) (void)hipHostFree(h->st_host);
+    if (h->sw_x) (void)hipFree(h->sw_x);
+    if (h->sw_v) (void)hipFree(h->sw_v);
+    if (h->sw_p) (void)hipFree(h->sw_p);
+    if (h->sw_pF) (void)hipFree(h->sw_pF);
+    if (h->sw_C) (void)hipFree(h->sw_C);
+    if (h->sw_st) (void)hipFree(h->sw_st);
+    if (h->sw_host) (void)hipHostFree(h->sw_host);
     free(h);
     return ROSE_OK;
 }

@@ -9,6 +9,7 @@ been built.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import re
 from typing import Optional, Sequence
@@ -60,7 +61,7 @@ class TrackStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("n_points", C.c_int32), ("n_overlap_last", C.c_int32),
                 ("status", C.c_int32), ("aps_size", C.c_int32 * MAX_ITERS),
                 ("n_overlap", C.c_int32 * MAX_ITERS), ("rho_iter", C.c_double * MAX_ITERS),
-                ("n_particles", C.c_int32 * MAX_ITERS)]
+                ("n_particles", C.c_int32 * MAX_ITERS), ("rho_centre", C.c_double * MAX_ITERS)]
 
 
 class LearnedParams(C.Structure):
@@ -75,6 +76,32 @@ def learned_params(scale=16, low_w=40, low_h=30, feature_dim=1216, kappa=2.0, r_
     """iters: iterations of the learned run (0: those of the track
     parameters; the plain fallback always uses the track parameters)."""
     return LearnedParams(low_w, low_h, scale, feature_dim, kappa, r_min, r_max, delta, near, far, step, int(iters), 0)
+
+
+class SwarmParams(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("stride", C.c_int32), ("lookup", C.c_int32), ("flags", C.c_int32),
+                ("tau", C.c_double), ("r_init", C.c_double * 6), ("sigma", C.c_double * 6),
+                ("w_start", C.c_double), ("w_end", C.c_double), ("c1", C.c_double), ("c2", C.c_double),
+                ("vmax", C.c_double * 6)]
+
+
+class SwarmStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("n_points", C.c_int32), ("n_overlap", C.c_int32 * MAX_ITERS),
+                ("best_index", C.c_int32 * MAX_ITERS), ("rho_best", C.c_double * MAX_ITERS),
+                ("rho_mean", C.c_double * MAX_ITERS)]
+
+
+def swarm_params(iters=20, stride=4, lookup=NEAREST, flags=0, tau=1.0, r_init=(0.1,) * 6, sigma=None, w_start=0.9,
+                 w_end=0.4, c1=2.0, c2=2.0, vmax=None) -> "SwarmParams":
+    """Parameters of the comparison optimisers (vanilla PFO, PSO).  sigma
+    defaults to r_init / sqrt(8) (the per-axis spread of the initial set),
+    vmax to r_init."""
+    r = [float(v) for v in r_init]
+    sg = [v / math.sqrt(8.0) for v in r] if sigma is None else [float(v) for v in sigma]
+    vm = r if vmax is None else [float(v) for v in vmax]
+    d6 = lambda v: (C.c_double * 6)(*v)  # noqa: E731
+    return SwarmParams(int(iters), int(stride), int(lookup), int(flags), float(tau), d6(r), d6(sg), float(w_start),
+                       float(w_end), float(c1), float(c2), d6(vm))
 
 
 class Profile(C.Structure):
@@ -127,6 +154,10 @@ _sigs = {
     "pso_track_frame_learned": ([_P, _P, C.POINTER(Camera), _P, C.c_int32, _P, C.c_int32, _P, _P, _P, _P,
                                  C.POINTER(TrackParams), C.POINTER(LearnedParams), C.POINTER(TrackState),
                                  C.POINTER(TrackStats), _P, _S], C.c_int),
+    "vanilla_pfo_track_frame": ([_P, _P, C.POINTER(Camera), _P, C.c_int32, C.POINTER(SwarmParams), _P, _P,
+                                 C.POINTER(TrackState), C.POINTER(SwarmStats), _S], C.c_int),
+    "plain_pso_track_frame": ([_P, _P, C.POINTER(Camera), _P, C.c_int32, C.POINTER(SwarmParams), _P,
+                               C.POINTER(TrackState), C.POINTER(SwarmStats), _S], C.c_int),
     "rose_profile_enable": ([C.c_int32], C.c_int),
     "rose_profile_reset": ([], C.c_int),
     "rose_profile_read": ([C.POINTER(Profile)], C.c_int),
@@ -385,7 +416,52 @@ def track_frame(vol: Tsdf, depth: torch.Tensor, K, pst: torch.Tensor, params: Tr
     return dict(iters=it, n_points=stats.n_points, n_overlap_last=stats.n_overlap_last,
                 aps=list(stats.aps_size[:it]), n_overlap=list(stats.n_overlap[:it]),
                 rho_iter=list(stats.rho_iter[:it]), n_particles=list(stats.n_particles[:it]),
+                rho_centre=list(stats.rho_centre[:it]),
                 q=list(state.pose.q), t=list(state.pose.t), r1=list(state.r), rho=state.rho)
+
+
+PFO = 0
+PSO = 1
+
+
+def swarm_track_frame(method: int, vol: Tsdf, depth: torch.Tensor, K, pst: torch.Tensor, params: SwarmParams,
+                      state: TrackState, draws: Optional[torch.Tensor], offsets: Optional[torch.Tensor] = None,
+                      stream=None) -> dict:
+    """One frame of vanilla PFO (method PFO: draws = iters x n x 6 standard
+    normals, offsets = iters uniforms) or PSO (method PSO: draws = iters x n
+    x 12 uniforms), float32 device tensors; updates `state` in place."""
+    _dev(depth, torch.float32, "depth")
+    _dev(pst, torch.float32, "pst")
+    n = pst.shape[0]
+    cols = 6 if method == PFO else 12
+    if draws is not None:
+        _dev(draws, torch.float32, "draws")
+        if draws.numel() < params.iters * n * cols:
+            raise ValueError(f"draws must hold iters x n x {cols} values")
+    if method == PFO and offsets is not None:
+        _dev(offsets, torch.float32, "offsets")
+        if offsets.numel() < params.iters:
+            raise ValueError("offsets must hold iters values")
+    cam = camera(K)
+    if depth.numel() != cam.width * cam.height:
+        raise ValueError("depth size does not match the camera")
+    stats = SwarmStats()
+    if method == PFO:
+        name = "vanilla_pfo_track_frame"
+        st = _lib.vanilla_pfo_track_frame(vol.handle, _ptr(depth), C.byref(cam), _ptr(pst), n, C.byref(params),
+                                          _ptr(draws), _ptr(offsets), C.byref(state), C.byref(stats),
+                                          _stream(stream))
+    elif method == PSO:
+        name = "plain_pso_track_frame"
+        st = _lib.plain_pso_track_frame(vol.handle, _ptr(depth), C.byref(cam), _ptr(pst), n, C.byref(params),
+                                        _ptr(draws), C.byref(state), C.byref(stats), _stream(stream))
+    else:
+        raise ValueError(f"unknown method {method}")
+    _check(name, st)
+    it = stats.iters
+    return dict(iters=it, n_points=stats.n_points, n_overlap=list(stats.n_overlap[:it]),
+                best_index=list(stats.best_index[:it]), rho_best=list(stats.rho_best[:it]),
+                rho_mean=list(stats.rho_mean[:it]), q=list(state.pose.q), t=list(state.pose.t), rho=state.rho)
 
 
 def profile_enable(on: bool = True):

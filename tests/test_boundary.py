@@ -94,3 +94,42 @@ def test_host_side_argument_errors(R):
     assert lib.pso_track_frame_learned(v, v, C.byref(cam), v, 16, v, 16, v, v, v, (C.c_double * 6)(),
                                        C.byref(R.track_params()), C.byref(lp), C.byref(st), None, None,
                                        None) == R.E_ARG
+
+
+def test_swarm_argument_errors(R):
+    """vanilla_pfo_track_frame / plain_pso_track_frame validate everything on
+    the host; with tsdf_built = 0 they keep the pose without touching the
+    device or the handle."""
+    lib = R._lib
+    fake = C.c_void_p(16)  # never dereferenced on these paths
+    cam = R.Camera(100, 100, 10, 10, 20, 20)
+    st = R.track_state([1, 0, 0, 0], [0.1, 0.2, 0.3], [1.0] * 6)
+    stats = R.SwarmStats()
+
+    def pfo(params, n=8, normals=fake, offsets=fake, h=fake, state=st):
+        return lib.vanilla_pfo_track_frame(h, fake, C.byref(cam), fake, n, C.byref(params), normals, offsets,
+                                           C.byref(state), C.byref(stats), None)
+
+    def pso(params, n=8, uniforms=fake):
+        return lib.plain_pso_track_frame(fake, fake, C.byref(cam), fake, n, C.byref(params), uniforms, C.byref(st),
+                                         C.byref(stats), None)
+
+    ok = R.swarm_params(iters=5)
+    assert pfo(ok, h=None) == R.E_ARG
+    assert pfo(ok, n=0) == R.E_ARG and pfo(ok, n=65537) == R.E_ARG
+    assert pfo(R.swarm_params(iters=0)) == R.E_ARG and pfo(R.swarm_params(iters=33)) == R.E_ARG
+    assert pfo(R.swarm_params(stride=0)) == R.E_ARG
+    assert pfo(R.swarm_params(lookup=2)) == R.E_ARG
+    assert pfo(R.swarm_params(flags=R.FLAG_CENTRE_THRESHOLD)) == R.E_ARG
+    assert b"only ROSE_FLAG_NO_OVERLAP" in lib.rose_last_error()
+    assert pfo(R.swarm_params(tau=0.0)) == R.E_ARG
+    assert pfo(R.swarm_params(r_init=[0.1] * 5 + [-0.1])) == R.E_ARG
+    assert pfo(R.swarm_params(sigma=[float("nan")] * 6)) == R.E_ARG
+    assert pso(R.swarm_params(vmax=[-1.0] * 6)) == R.E_ARG
+    assert pso(R.swarm_params(c1=float("inf"))) == R.E_ARG
+    assert pfo(ok, normals=None) == R.E_ARG and pfo(ok, offsets=None) == R.E_ARG
+    assert pso(ok, uniforms=None) == R.E_ARG
+    # one iteration needs no draws
+    cold = R.track_state([1, 0, 0, 0], [0.1, 0.2, 0.3], [1.0] * 6, tsdf_built=False)
+    assert pfo(R.swarm_params(iters=1), normals=None, offsets=None, state=cold) == R.OK
+    assert list(cold.pose.t) == [0.1, 0.2, 0.3] and cold.frame == 1 and stats.iters == 0
