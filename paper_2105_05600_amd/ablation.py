@@ -21,7 +21,8 @@ through the library (one GPU).
   optimizer Fig. "optimisation strategy": PFO with PST against vanilla PFO
             (Gaussian proposal + resampling, Eq. pfolh) and PSO (inertia
             weight 0.9 -> 0.4, c1 = c2 = 2), all with 10240 particles, 20
-            iterations and the fitness of Eq. normallh, on the 6D set.
+            iterations and the fitness of Eq. normallh, on the 6D set and on
+            a faster 6D set (4-8 m/s, 2.7-5.4 rad/s).
             Reported per iteration: the exact fitness of each method's
             current estimate (PST: the centre c_k; the others: the best state
             so far) averaged over all frames, with its percentiles; ATE and
@@ -164,13 +165,13 @@ def track_swarm(sq, depths, pst, method, params, seed):
     return float(rmse), 1e3 * t_track / (len(depths) - 1), curves
 
 
-def exp_optimizer(n_seq, frames, pst, base, spreads=(0.05, 0.1, 0.2)):
+def exp_optimizer(n_seq, frames, pst, base, kind="6d", spreads=(0.05, 0.1, 0.2)):
     runs = {"pfo_pst": None}
     for r0 in spreads:
         runs[f"vanilla_pfo_r{r0}"] = (rose.PFO, r0)
         runs[f"pso_r{r0}"] = (rose.PSO, r0)
     rows = {v: {"ate": [], "ms": [], "curves": []} for v in runs}
-    for seed, sq, depths in sequences("6d", n_seq, frames, base):
+    for seed, sq, depths in sequences(kind, n_seq, frames, base):
         for v, spec in runs.items():
             if spec is None:
                 ate, ms, cv = track_pst_curve(sq, depths, pst)
@@ -191,7 +192,7 @@ def exp_optimizer(n_seq, frames, pst, base, spreads=(0.05, 0.1, 0.2)):
                   "rho_p90": np.percentile(a, 90, axis=0).tolist(), "rho_min": a.min(0).tolist(),
                   "rho_max": a.max(0).tolist()}
         m = res[v]["rho_mean"]
-        log(f"optimizer {v}: rho at iterations 1/2/5/10/20 {m[0]:.4f} {m[1]:.4f} {m[4]:.4f} {m[9]:.4f} {m[19]:.4f}; "
+        log(f"optimizer {kind} {v}: rho at iterations 1/2/5/10/20 {m[0]:.4f} {m[1]:.4f} {m[4]:.4f} {m[9]:.4f} {m[19]:.4f}; "
             f"ATE mean {res[v]['ate_rmse_mean_m']:.4f} m median {res[v]['ate_rmse_median_m']:.4f} m, "
             f"{res[v]['ms_per_frame']:.2f} ms/frame")
     return res
@@ -283,6 +284,7 @@ def main():
         }, 66000)
     if "optimizer" in exps:
         res["optimizer"] = exp_optimizer(args.sequences, args.frames, pst, 67000)
+        res["optimizer_fast"] = exp_optimizer(args.sequences, args.frames, pst, 68000, kind="6dfast")
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     with open(args.out, "w") as f:
         json.dump(res, f, indent=1)

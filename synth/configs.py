@@ -257,13 +257,15 @@ def axis_motion(scene: Scene, seed: int, n_frames: int, fps: float, kind: str) -
 
 def ablation_sequence(kind: str, seed: int, n_frames: int = 60, width: int = 320, height: int = 240,
                       dim: int = 512, vox: float = 0.01, mu: float = 0.15) -> Sequence:
-    """A sequence of the ablation sets: kind "1d", "3d" (axis_motion) or
+    """A sequence of the ablation sets: kind "1d", "3d" (axis_motion),
     "6d" (fast_trajectory at a seeded speed in [1, 4] m/s and 0.67 x that in
-    rad/s), in a procedural room filling the volume, 320x240 depth."""
+    rad/s) or "6dfast" (the same at [4, 8] m/s), in a procedural room filling
+    the volume, 320x240 depth."""
     scene = procedural_room(seed, 0.1, dim * vox - 0.1)
     K = Intrinsics.centred(width, height, 525.0 * width / 640.0)
-    if kind == "6d":
-        v = float(np.random.default_rng(seed).uniform(1.0, 4.0))
+    if kind in ("6d", "6dfast"):
+        lo, hi = (1.0, 4.0) if kind == "6d" else (4.0, 8.0)
+        v = float(np.random.default_rng(seed).uniform(lo, hi))
         poses = fast_trajectory(scene, seed + 1, n_frames, 30.0, v, 0.67 * v)
     else:
         poses = axis_motion(scene, seed + 1, n_frames, 30.0, kind)
