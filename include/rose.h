@@ -285,7 +285,11 @@ typedef struct {
  * approximated best fitness (Eq. wafit), CompAxisLength (Eqs. rsdir,
  * rsinter with |v_d|, momentum), MovePST (c_k = c_{k-1} * Delta(u*)) and the
  * corner cases of Sec. 4.  The whole loop runs on the device; the call
- * synchronises `s` once at the end and then fills state/stats.
+ * synchronises `s` once at the end and then fills state/stats.  The first
+ * call with a template (pointer and particle count) on a handle also reads
+ * the template back once to derive the order in which wavefronts take the
+ * particles (similar rotations together, for cache reuse); results do not
+ * depend on that order.
  * state->tsdf_built == 0: no fitness is evaluated; r_1 = beta r_0 +
  * (1-beta) 0.5 and the pose is kept.  Returns ROSE_E_STATE (state
  * unchanged) when the frame has no valid point.

@@ -326,6 +326,13 @@ struct rose_tsdf {
     void* sw_st;        // device search state
     void* sw_host;      // pinned host copy
     int64_t cap_swarm;
+    // schedule orders of the PST templates tracked with this handle (fitness.hip)
+    struct Order {
+        const float* pst;
+        int32_t n;
+        int32_t* order;
+    } orders[8];
+    int32_t n_orders;
 };
 
 namespace rose {
@@ -340,6 +347,7 @@ struct FitLaunch {
     const float* T32;
     const DevState* st;
     const float* pst;
+    const int32_t* order;      // schedule order of the template rows (n), or nullptr (index order)
     int32_t n;
     int32_t splits;
     int32_t lookup;
@@ -347,6 +355,10 @@ struct FitLaunch {
     double* partial;           // n x splits
 };
 rose_status launch_fitness(const FitLaunch& L, hipStream_t s);
+// Schedule order of the first n rows of a PST template (cached per handle;
+// the first request reads the template back, synchronising s).  nullptr
+// (index order) when the handle's cache is full.
+rose_status particle_order(rose_tsdf* h, const float* pst_dev, int32_t n, hipStream_t s, const int32_t** out);
 int choose_splits(int32_t n_particles, int64_t max_points);
 bool fitness_shape_valid(int p, int u);
 void fitness_shape(int* p, int* u);

@@ -12,6 +12,7 @@
 // the wave with butterfly shuffles, and written as one partial sum per
 // (particle, slice); a second pass adds the slices in a fixed order.
 #include <algorithm>
+#include <vector>
 
 #include "common.h"
 
@@ -103,6 +104,7 @@ __device__ void fitness_body(const FitLaunch& a, const int blk) {
     {
         int pi = p0 + (lane < P ? lane : 0);
         if (pi >= a.n) pi = a.n - 1;
+        if (FROM_STATE && a.order) pi = a.order[pi];
         double T[12];
         if (FROM_STATE) {
             float p[6];
@@ -198,7 +200,10 @@ __device__ void fitness_body(const FitLaunch& a, const int blk) {
     if (lane == 0) {
 #pragma unroll
         for (int p = 0; p < P; ++p)
-            if (p0 + p < a.n) a.partial[(int64_t)(p0 + p) * a.splits + split] = acc[p];
+            if (p0 + p < a.n) {
+                const int pi = (FROM_STATE && a.order) ? a.order[p0 + p] : p0 + p;
+                a.partial[(int64_t)pi * a.splits + split] = acc[p];
+            }
     }
 }
 
@@ -412,6 +417,65 @@ int choose_splits(int32_t n_particles, int64_t max_points) {
     int64_t s = 8;
     while (s < 64 && groups * s < target_waves && max_points / (2 * s) >= 256) s *= 2;
     return (int)s;
+}
+
+// Schedule order of template rows.  Waves take particles in this order, so
+// that the particles evaluated together -- a wave's P, and the waves in
+// flight on an XCD -- have similar poses and their gathers share cache lines
+// in L1 and L2.  A particle's footprint moves with its rotation about
+// (depth x angle) and with its translation, and at a few metres depth the
+// rotation weighs most: the key interleaves, from the top bit down, 9 bits
+// of each rotation coordinate with 7 bits of each translation coordinate (a
+// Morton order in which rotation leads by two levels).  Any permutation
+// gives the same fitness values (each particle's sums are written at its own
+// index), so the order affects speed only.
+static uint64_t order_key(const float* p) {
+    uint32_t q[6];
+    for (int d = 0; d < 6; ++d) {
+        float v = p[d];
+        if (!(v >= -1.0f)) v = -1.0f;  // also NaN
+        if (v > 1.0f) v = 1.0f;
+        const int bits = d < 3 ? 9 : 7;
+        const uint32_t top = (1u << bits) - 1u;
+        q[d] = std::min(top, (uint32_t)((v + 1.0f) * 0.5f * (float)(1u << bits)));
+    }
+    uint64_t key = 0;
+    for (int lvl = 8; lvl >= 0; --lvl) {
+        for (int d = 0; d < 3; ++d) key = (key << 1) | ((q[d] >> lvl) & 1u);
+        if (lvl < 7)
+            for (int d = 3; d < 6; ++d) key = (key << 1) | ((q[d] >> lvl) & 1u);
+    }
+    return key;
+}
+
+rose_status particle_order(rose_tsdf* h, const float* pst_dev, int32_t n, hipStream_t s, const int32_t** out) {
+    *out = nullptr;
+    for (int i = 0; i < h->n_orders; ++i)
+        if (h->orders[i].pst == pst_dev && h->orders[i].n == n) {
+            *out = h->orders[i].order;
+            return ROSE_OK;
+        }
+    constexpr int kSlots = (int)(sizeof(h->orders) / sizeof(h->orders[0]));
+    if (h->n_orders >= kSlots || n < 1) return ROSE_OK;  // index order
+    std::vector<float> rows((size_t)n * 6);
+    ROSE_CHECK_HIP(hipMemcpyAsync(rows.data(), pst_dev, sizeof(float) * rows.size(), hipMemcpyDeviceToHost, s));
+    ROSE_CHECK_HIP(hipStreamSynchronize(s));
+    std::vector<uint64_t> key((size_t)n);
+    std::vector<int32_t> idx((size_t)n);
+    for (int32_t i = 0; i < n; ++i) {
+        key[i] = order_key(&rows[6 * (size_t)i]);
+        idx[i] = i;
+    }
+    std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+    int32_t* dev = nullptr;
+    ROSE_CHECK_HIP(hipMalloc(&dev, sizeof(int32_t) * (size_t)n));
+    ROSE_CHECK_HIP(hipMemcpy(dev, idx.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice));
+    h->orders[h->n_orders].pst = pst_dev;
+    h->orders[h->n_orders].n = n;
+    h->orders[h->n_orders].order = dev;
+    h->n_orders += 1;
+    *out = dev;
+    return ROSE_OK;
 }
 
 }  // namespace rose

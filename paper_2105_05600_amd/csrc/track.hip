@@ -425,6 +425,10 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_cam
     fin.depth = depth_dev;
     fin.active = 1;
     fin.pad = 0;
+    // schedule order of each level's particles (first use: reads the template)
+    const int32_t* lv_order[ROSE_MAX_LEVELS] = {nullptr, nullptr, nullptr, nullptr};
+    for (int l = 0; l < L; ++l)
+        if ((g = particle_order(h, pst_dev, lv_n[l], s, &lv_order[l])) != ROSE_OK) return g;
     hipLaunchKernelGGL(k_track_init, dim3(1), dim3(1024), 0, s, ia, fin);
     ROSE_CHECK_HIP(hipGetLastError());
 
@@ -458,6 +462,7 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_cam
         // iteration k + 1 runs level k mod L and prepares level (k + 1) mod L
         const int l = k % L, ln = (k + 1) % L;
         fl.n = lv_n[l];
+        fl.order = lv_order[l];
         fl.splits = lv_splits[l];
         ua.n = lv_n[l];
         ua.splits = lv_splits[l];
@@ -707,6 +712,7 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
         L.st = h->st;
         L.pst = pst_devs[i];
         L.n = n_particles[i];
+        if ((g = particle_order(h, pst_devs[i], n_particles[i], nullptr, &L.order)) != ROSE_OK) break;
         L.splits = splits;
         L.lookup = p.lookup;
         L.shape_p = P;

@@ -229,7 +229,7 @@ rose_status tsdf_create(int32_t nx, int32_t ny, int32_t nz, float voxel_m, float
 rose_status tsdf_destroy(rose_tsdf* h) {
     clear_error();
     if (h == nullptr) return ROSE_OK;
-    if (h->pts || h->partial || h->st || h->sw_x) (void)hipDeviceSynchronize();
+    if (h->pts || h->partial || h->st || h->sw_x || h->n_orders) (void)hipDeviceSynchronize();
     if (h->pts) (void)hipFree(h->pts);
     if (h->pts_o) (void)hipFree(h->pts_o);
     if (h->partial) (void)hipFree(h->partial);
@@ -243,6 +243,7 @@ rose_status tsdf_destroy(rose_tsdf* h) {
     if (h->sw_C) (void)hipFree(h->sw_C);
     if (h->sw_st) (void)hipFree(h->sw_st);
     if (h->sw_host) (void)hipHostFree(h->sw_host);
+    for (int i = 0; i < h->n_orders; ++i) (void)hipFree(h->orders[i].order);
     free(h);
     return ROSE_OK;
 }
