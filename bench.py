@@ -198,13 +198,11 @@ def main():
         step(i)
     torch.cuda.synchronize()
     log(f"warmup {args.warmup} frames done")
-    # launch-shape tuning on the current frame: the tracker's points (8x8
-    # tiles) under the 10240 particle poses of its first iteration
+    # launch-shape tuning on the next frame: one tracked frame per compiled
+    # shape (from a copy of the state), fitness launches timed
     from paper_2105_05600_amd import autotune
     nxt = 1 + args.warmup
-    pts = rose.depth_unproject(dev_depths[nxt], seq.K, seq.stride, tiled=True)
-    Tp = rose.particle_poses(list(st.pose.q), list(st.pose.t), list(st.r), pst).float().contiguous()
-    tuned = autotune.tune(vol, pts, Tp, lookup)
+    tuned = autotune.tune_track(vol, dev_depths[nxt], seq.K, pst, params, st)
     log(f"fitness shape {tuned['shape']} ({'cached' if tuned['cached'] else 'timed'}: {tuned['ms']})")
     rose.profile_enable(True)
     rose.profile_reset()

@@ -73,3 +73,29 @@ def tune(vol, pts: torch.Tensor, T: torch.Tensor, lookup: int = 0, shapes=None, 
             json.dump(db, f, indent=1, sort_keys=True)
         os.replace(tmp, cache)
     return {"shape": best, "ms": ms, "cached": False, "key": key}
+
+
+def tune_track(vol, depth: torch.Tensor, K, pst: torch.Tensor, params, state, shapes=None) -> dict:
+    """Pick the fastest shape for the tracker itself: for every shape, one
+    frame of pso_track_frame from a copy of `state` (the first run of each
+    shape warms up), timed by the library's fitness-launch timers.  Unlike
+    tune(), this measures the particles in the order the tracker schedules
+    them.  `state` is not changed.  Returns {"shape", "ms", "cached"}."""
+    shapes = shapes or SHAPES
+    ms = {}
+    rose.profile_enable(True)
+    try:
+        for shape in shapes:
+            rose.set_fitness_shape(*shape)
+            for _ in range(2):
+                probe = rose.track_state(list(state.pose.q), list(state.pose.t), list(state.r))
+                rose.profile_reset()
+                rose.track_frame(vol, depth, K, pst, params, probe)
+                prof = rose.profile_read()
+            ms[f"{shape[0]}x{shape[1]}"] = prof["fitness_ms"] / max(prof["fitness_launches"], 1)
+    finally:
+        rose.profile_reset()
+        rose.profile_enable(False)
+    best = min(shapes, key=lambda sh: ms[f"{sh[0]}x{sh[1]}"])
+    rose.set_fitness_shape(*best)
+    return {"shape": tuple(best), "ms": ms, "cached": False}
