@@ -365,8 +365,9 @@ void fitness_shape(int* p, int* u);
 int fitness_blocks(const FitLaunch& L, int P);
 bool batch_shape_valid(int p, int u);
 int batch_grid(int P, int U, int fmt, int lk, int requested);
+// ctr_dev: the group's 8 per-XCD work counters, zero at launch
 rose_status launch_fitness_batch(const FitLaunch* seqs_dev, const int* begin_dev, int count, int base, int end,
-                                 int grid, int P, int U, int fmt, int lk, hipStream_t s);
+                                 int grid, int P, int U, int fmt, int lk, int* ctr_dev, hipStream_t s);
 
 // PST template rows 0..n-1 (tsdf.hip)
 rose_status launch_pst_sample(int64_t n, uint64_t seed, float* out_dev, hipStream_t s);

@@ -220,13 +220,28 @@ __device__ inline int fitness_blocks_dev(const FitLaunch& L, int P) { return ((L
 // lookup (a batch launches one kernel per such group, so each kernel holds a
 // single fitness body and keeps its registers): a grid of a few workgroups
 // per CU walks the group's concatenated work lists [base, end) (sequence i
-// owns items [begin[i], begin[i+1]), every begin a multiple of 8 and the grid
-// a multiple of 8, so an item's XCD is its index mod 8 and the slice <-> XCD
-// pairing of k_fitness holds for every sequence).
+// owns items [begin[i], begin[i+1]), every begin a multiple of 8).  Items
+// are handed out by one counter per XCD: workgroup b (on XCD b mod 8 -- the
+// grid is a multiple of 8 and workgroups are dealt to the XCDs in turn)
+// takes the next item w = base + (b mod 8) + 8 k of its XCD's queue, so the
+// slice <-> XCD pairing of k_fitness holds for every sequence and the items
+// in flight stay a contiguous window of the list (static striding lets slow
+// and fast workgroups drift apart across sequences and volumes).  The
+// counters (ctr[0..7]) are zero at launch: the kernel that runs before each
+// launch on the stream clears them, and every workgroup leaves once its
+// queue passes `end`.
 template <int P, int U, int FMT, int LK>
 __global__ __launch_bounds__(256) void k_fitness_batch(const FitLaunch* __restrict__ seqs,
-                                                       const int* __restrict__ begin, int count, int base, int end) {
-    for (int w = base + (int)blockIdx.x; w < end; w += gridDim.x) {
+                                                       const int* __restrict__ begin, int count, int base, int end,
+                                                       int* __restrict__ ctr) {
+    __shared__ int s_k;
+    const int xcd = (int)(blockIdx.x & 7u);
+    for (;;) {
+        if (threadIdx.x == 0) s_k = atomicAdd(&ctr[xcd], 1);
+        __syncthreads();
+        const int w = base + xcd + 8 * s_k;
+        __syncthreads();
+        if (w >= end) break;
         int lo = 0, hi = count;
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
@@ -257,8 +272,9 @@ static int resident_grid(K kernel, int requested) {
 
 template <int P, int U, int FMT, int LK>
 static void launch_batch_kernel(const FitLaunch* seqs, const int* begin, int count, int base, int end, int grid,
-                                hipStream_t s) {
-    hipLaunchKernelGGL((k_fitness_batch<P, U, FMT, LK>), dim3(grid), dim3(256), 0, s, seqs, begin, count, base, end);
+                                int* ctr, hipStream_t s) {
+    hipLaunchKernelGGL((k_fitness_batch<P, U, FMT, LK>), dim3(grid), dim3(256), 0, s, seqs, begin, count, base, end,
+                       ctr);
 }
 
 template <int P, int U>
@@ -287,22 +303,22 @@ int batch_grid(int P, int U, int fmt, int lk, int requested) {
 
 template <int P, int U>
 static void launch_batch_shape(const FitLaunch* seqs, const int* begin, int count, int base, int end, int grid,
-                               int fmt, int lk, hipStream_t s) {
+                               int fmt, int lk, int* ctr, hipStream_t s) {
     if (fmt == ROSE_TSDF_F32) {
         if (lk == ROSE_LOOKUP_TRILINEAR)
-            launch_batch_kernel<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_TRILINEAR>(seqs, begin, count, base, end, grid, s);
+            launch_batch_kernel<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_TRILINEAR>(seqs, begin, count, base, end, grid, ctr, s);
         else
-            launch_batch_kernel<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_NEAREST>(seqs, begin, count, base, end, grid, s);
+            launch_batch_kernel<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_NEAREST>(seqs, begin, count, base, end, grid, ctr, s);
     } else if (fmt == ROSE_TSDF_F16) {
         if (lk == ROSE_LOOKUP_TRILINEAR)
-            launch_batch_kernel<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_TRILINEAR>(seqs, begin, count, base, end, grid, s);
+            launch_batch_kernel<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_TRILINEAR>(seqs, begin, count, base, end, grid, ctr, s);
         else
-            launch_batch_kernel<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_NEAREST>(seqs, begin, count, base, end, grid, s);
+            launch_batch_kernel<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_NEAREST>(seqs, begin, count, base, end, grid, ctr, s);
     } else {
         if (lk == ROSE_LOOKUP_TRILINEAR)
-            launch_batch_kernel<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_TRILINEAR>(seqs, begin, count, base, end, grid, s);
+            launch_batch_kernel<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_TRILINEAR>(seqs, begin, count, base, end, grid, ctr, s);
         else
-            launch_batch_kernel<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_NEAREST>(seqs, begin, count, base, end, grid, s);
+            launch_batch_kernel<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_NEAREST>(seqs, begin, count, base, end, grid, ctr, s);
     }
 }
 
@@ -311,11 +327,11 @@ bool batch_shape_valid(int P, int U) {
 }
 
 rose_status launch_fitness_batch(const FitLaunch* seqs_dev, const int* begin_dev, int count, int base, int end,
-                                 int grid, int P, int U, int fmt, int lk, hipStream_t s) {
-    if (P == 8 && U == 4) launch_batch_shape<8, 4>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, s);
-    else if (P == 8 && U == 2) launch_batch_shape<8, 2>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, s);
-    else if (P == 4 && U == 4) launch_batch_shape<4, 4>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, s);
-    else launch_batch_shape<4, 2>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, s);
+                                 int grid, int P, int U, int fmt, int lk, int* ctr_dev, hipStream_t s) {
+    if (P == 8 && U == 4) launch_batch_shape<8, 4>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
+    else if (P == 8 && U == 2) launch_batch_shape<8, 2>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
+    else if (P == 4 && U == 4) launch_batch_shape<4, 4>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
+    else launch_batch_shape<4, 2>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
     ROSE_CHECK_HIP(hipGetLastError());
     return ROSE_OK;
 }

@@ -96,9 +96,17 @@ rose_status launch_track_init(const InitStatic& a, const FrameIn& in, hipStream_
     return ROSE_OK;
 }
 
+// the batched fitness launches' per-XCD work counters (n_ctr <= 1024) are
+// cleared by the kernel that precedes each launch on the stream
+__device__ inline void clear_counters(int* ctr, int n_ctr) {
+    if (blockIdx.x == 0 && (int)threadIdx.x < n_ctr) ctr[threadIdx.x] = 0;
+}
+
 // one workgroup per sequence; the per-frame inputs are read from pinned host
 // memory (so that a captured graph replays with new inputs)
-__global__ __launch_bounds__(1024) void k_track_init_batch(const InitStatic* a, const FrameIn* in_host) {
+__global__ __launch_bounds__(1024) void k_track_init_batch(const InitStatic* a, const FrameIn* in_host, int* ctr,
+                                                           int n_ctr) {
+    clear_counters(ctr, n_ctr);
     __shared__ FrameIn fin;
     constexpr int kWords = sizeof(FrameIn) / sizeof(uint64_t);
     if (threadIdx.x < kWords)
@@ -231,7 +239,10 @@ __device__ void track_update_body(const UpdateArgs& a) {
 
 __global__ __launch_bounds__(1024) void k_track_update(UpdateArgs a) { track_update_body(a); }
 
-__global__ __launch_bounds__(1024) void k_track_update_batch(const UpdateArgs* a) { track_update_body(a[blockIdx.x]); }
+__global__ __launch_bounds__(1024) void k_track_update_batch(const UpdateArgs* a, int* ctr, int n_ctr) {
+    clear_counters(ctr, n_ctr);
+    track_update_body(a[blockIdx.x]);
+}
 
 // copy every sequence's device state to pinned host memory
 __global__ __launch_bounds__(64) void k_track_finish_batch(DevState* const* st, DevState* out_host) {
@@ -539,6 +550,7 @@ struct rose_batch {
     std::vector<int32_t> n;
     FitLaunch* fit_dev = nullptr;
     int* begin_dev = nullptr;
+    int* ctr_dev = nullptr;  // 8 work counters per group
     InitStatic* init_dev = nullptr;
     UpdateArgs* upd_dev = nullptr;
     DevState** stp_dev = nullptr;
@@ -601,6 +613,7 @@ static void batch_free(rose_batch* b) {
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->fit_dev) (void)hipFree(b->fit_dev);
     if (b->begin_dev) (void)hipFree(b->begin_dev);
+    if (b->ctr_dev) (void)hipFree(b->ctr_dev);
     if (b->init_dev) (void)hipFree(b->init_dev);
     if (b->upd_dev) (void)hipFree(b->upd_dev);
     if (b->stp_dev) (void)hipFree(b->stp_dev);
@@ -610,17 +623,23 @@ static void batch_free(rose_batch* b) {
 }
 
 static rose_status batch_enqueue(rose_batch* b, hipStream_t s) {
-    hipLaunchKernelGGL(k_track_init_batch, dim3(b->count), dim3(1024), 0, s, b->init_dev, b->in_host);
+    // every group's counters are cleared before each round of fitness launches
+    // (by the init kernel, then by each update kernel); each group has its own
+    // 8 counters, so the launches of one round do not disturb each other
+    const int n_ctr = 8 * (int)b->groups.size();
+    hipLaunchKernelGGL(k_track_init_batch, dim3(b->count), dim3(1024), 0, s, b->init_dev, b->in_host, b->ctr_dev,
+                       n_ctr);
     ROSE_CHECK_HIP(hipGetLastError());
     for (int k = 0; k < b->K; ++k) {
-        for (const BatchGroup& gr : b->groups) {
+        for (size_t q = 0; q < b->groups.size(); ++q) {
+            const BatchGroup& gr = b->groups[q];
             rose_status st = launch_fitness_batch(b->fit_dev + gr.first, b->begin_dev + gr.first, gr.count, gr.base,
-                                                  gr.end, gr.grid, b->P, b->U, gr.fmt, gr.lk, s);
+                                                  gr.end, gr.grid, b->P, b->U, gr.fmt, gr.lk, b->ctr_dev + 8 * q, s);
             if (st != ROSE_OK) return st;
         }
         hipLaunchKernelGGL(k_fitness_reduce_batch, dim3((b->max_n + 255) / 256, b->count), dim3(256), 0, s,
                            b->upd_dev);
-        hipLaunchKernelGGL(k_track_update_batch, dim3(b->count), dim3(1024), 0, s, b->upd_dev);
+        hipLaunchKernelGGL(k_track_update_batch, dim3(b->count), dim3(1024), 0, s, b->upd_dev, b->ctr_dev, n_ctr);
         ROSE_CHECK_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_track_finish_batch, dim3(b->count), dim3(64), 0, s, b->stp_dev, b->out_host);
@@ -778,6 +797,8 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
     }
     bool ok = hipMalloc(&b->fit_dev, sizeof(FitLaunch) * count) == hipSuccess &&
               hipMalloc(&b->begin_dev, sizeof(int) * (count + 1)) == hipSuccess &&
+              hipMalloc(&b->ctr_dev, sizeof(int) * 8 * b->groups.size()) == hipSuccess &&
+              hipMemset(b->ctr_dev, 0, sizeof(int) * 8 * b->groups.size()) == hipSuccess &&
               hipMalloc(&b->init_dev, sizeof(InitStatic) * count) == hipSuccess &&
               hipMalloc(&b->upd_dev, sizeof(UpdateArgs) * count) == hipSuccess &&
               hipMalloc(&b->stp_dev, sizeof(DevState*) * count) == hipSuccess &&
