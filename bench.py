@@ -59,6 +59,8 @@ def parse():
                     help="poisson: 6D Poisson-disk template (dart throwing, packing fraction 0.03)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--render-workers", type=int, default=16)
+    ap.add_argument("--shape", default=None, metavar="P,U",
+                    help="fitness launch shape (particles per wave, points per lane); default: timed per run")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="before warmup, run a float32 copy of MIB MiB three times (counter calibration)")
     return ap.parse_args()
@@ -77,9 +79,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(lookup: int):
+def measured_traffic(lookup: int, shape):
     """HBM bytes per fitness launch from the committed counter summary, or
-    None when it is missing, for another lookup, or the kernel has changed."""
+    None when it is missing, for another lookup or launch shape, or the
+    kernel has changed."""
     try:
         with open(COUNTERS) as f:
             kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith(" "))
@@ -87,6 +90,8 @@ def measured_traffic(lookup: int):
         return None
     kv = {k.strip(): v.strip() for k, v in kv.items()}
     if kv.get("kernel_source_sha256_16") != kernel_source_hash() or kv.get("lookup") != str(lookup):
+        return None
+    if kv.get("shape") != f"{shape[0]}x{shape[1]}":
         return None
     try:
         return float(kv["traffic_bytes_per_launch"])
@@ -202,8 +207,13 @@ def main():
     # shape (from a copy of the state), fitness launches timed
     from paper_2105_05600_amd import autotune
     nxt = 1 + args.warmup
-    tuned = autotune.tune_track(vol, dev_depths[nxt], seq.K, pst, params, st)
-    log(f"fitness shape {tuned['shape']} ({'cached' if tuned['cached'] else 'timed'}: {tuned['ms']})")
+    if args.shape:
+        shp = tuple(int(v) for v in args.shape.split(","))
+        rose.set_fitness_shape(*shp)
+        tuned = {"shape": shp, "ms": {}, "cached": False}
+    else:
+        tuned = autotune.tune_track(vol, dev_depths[nxt], seq.K, pst, params, st)
+    log(f"fitness shape {tuned['shape']} ({'given' if args.shape else 'timed'}: {tuned['ms']})")
     rose.profile_enable(True)
     rose.profile_reset()
     evals = 0.0
@@ -251,7 +261,7 @@ def main():
                                     "update": prof["update_ms"] / args.steps,
                                     "integrate": prof["integrate_ms"] / args.steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(lookup) if fmt == 0 else None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(lookup, tuned["shape"]) if fmt == 0 else None,
                      "kernel": "k_fitness", "avg_launch_ms": fit_ms, "evals_per_launch": fit_evals,
                      "bytes_per_eval": bytes_per_eval, "shape": list(tuned["shape"]),
                      "kernel_source_sha256_16": kernel_source_hash()},

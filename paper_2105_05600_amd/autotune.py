@@ -75,12 +75,18 @@ def tune(vol, pts: torch.Tensor, T: torch.Tensor, lookup: int = 0, shapes=None, 
     return {"shape": best, "ms": ms, "cached": False, "key": key}
 
 
-def tune_track(vol, depth: torch.Tensor, K, pst: torch.Tensor, params, state, shapes=None) -> dict:
+PREFERRED = (8, 4)
+
+
+def tune_track(vol, depth: torch.Tensor, K, pst: torch.Tensor, params, state, shapes=None, margin: float = 0.03) -> dict:
     """Pick the fastest shape for the tracker itself: for every shape, one
     frame of pso_track_frame from a copy of `state` (the first run of each
     shape warms up), timed by the library's fitness-launch timers.  Unlike
     tune(), this measures the particles in the order the tracker schedules
-    them.  `state` is not changed.  Returns {"shape", "ms", "cached"}."""
+    them.  A shape must beat PREFERRED by more than `margin` to replace it,
+    so that near-ties (8x2 and 8x4 differ by ~2 % on one frame) resolve the
+    same way in every run.  `state` is not changed.  Returns {"shape", "ms",
+    "cached"}."""
     shapes = shapes or SHAPES
     ms = {}
     rose.profile_enable(True)
@@ -97,5 +103,8 @@ def tune_track(vol, depth: torch.Tensor, K, pst: torch.Tensor, params, state, sh
         rose.profile_reset()
         rose.profile_enable(False)
     best = min(shapes, key=lambda sh: ms[f"{sh[0]}x{sh[1]}"])
+    pk = f"{PREFERRED[0]}x{PREFERRED[1]}"
+    if pk in ms and ms[f"{best[0]}x{best[1]}"] > (1.0 - margin) * ms[pk]:
+        best = PREFERRED
     rose.set_fitness_shape(*best)
     return {"shape": tuple(best), "ms": ms, "cached": False}

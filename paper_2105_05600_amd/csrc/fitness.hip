@@ -86,13 +86,18 @@ template <int P, int U, int FMT, int LK, bool FROM_STATE, bool WIDE>
 __device__ void fitness_body(const FitLaunch& a, const int blk) {
     constexpr int kU = U;
     const int lane = threadIdx.x & 63;
-    // XCD-aware mapping: consecutive workgroups go to the 8 XCDs in turn, so
-    // with the slice index = workgroup index mod splits (splits a multiple of
-    // 8) every XCD works on a fixed 1/8 of the point list and its L2 only
-    // holds the voxels around those points.  The 4 waves of a workgroup take
-    // 4 consecutive particle groups of the same slice (shared point loads
-    // and nearby gathers in the CU's L1).
-    const int split = blk % a.splits;
+    // XCD-aware mapping: consecutive workgroups go to the 8 XCDs in turn
+    // (XCD = workgroup index mod 8).  With splits a multiple of 8, XCD x owns
+    // the contiguous slices x*splits/8 .. (x+1)*splits/8 - 1, i.e. a fixed 1/8
+    // of the point list, so its L2 only holds the voxels around those
+    // points; its workgroups cycle through those slices before moving to the
+    // next particles, so the particles in flight on an XCD are few (and, in
+    // the schedule order, similar).  The 4 waves of a workgroup take 4
+    // consecutive particle groups of the same slice (shared point loads and
+    // nearby gathers in the CU's L1).
+    const int s8 = a.splits >> 3;
+    const int r = blk % a.splits;
+    const int split = (r & 7) * s8 + (r >> 3);
     const int group = (blk / a.splits) * 4 + (threadIdx.x >> 6);
     const int p0 = group * P;
     if (p0 >= a.n) return;
@@ -424,13 +429,17 @@ void fitness_shape(int* p, int* u) {
     *u = g_shape_u;
 }
 
-// Point slices: a multiple of the 8 XCDs (see k_fitness), raised while the
-// grid holds fewer waves than the chip runs at once and each slice still
-// has at least ~4 lane-steps (256 points).
+// Point slices: a multiple of the 8 XCDs (see k_fitness).  16 (two slices
+// per XCD, halving the particles in flight per XCD) once a slice keeps at
+// least 512 points -- measured on the 640x480 room workload: 8 slices 0.737
+// ms per launch, 16: 0.692, 32: 0.701, 64: 0.710 (per-wave setup and partial
+// sums grow) -- and raised further while the grid holds fewer waves than the
+// chip runs at once and each slice still has at least ~4 lane-steps (256
+// points).
 int choose_splits(int32_t n_particles, int64_t max_points) {
     const int64_t groups = (n_particles + g_shape_p - 1) / g_shape_p;
     const int64_t target_waves = 256 * 4 * 8;  // CUs x SIMDs x waves per SIMD
-    int64_t s = 8;
+    int64_t s = (max_points / 16 >= 512) ? 16 : 8;
     while (s < 64 && groups * s < target_waves && max_points / (2 * s) >= 256) s *= 2;
     return (int)s;
 }

@@ -52,22 +52,62 @@ __device__ inline bool sample_at(int q, int su, int sv, bool tiled, int* uu, int
     return *uu < su && *vv < sv;
 }
 
-// Whole-block order-preserving overlap compaction of m points.
+// Whole-block order-preserving overlap compaction of m points, kRounds
+// coalesced rounds of blockDim points at a time: every thread loads and
+// tests its point of each round (all loads in flight together), the waves'
+// ballots give per-round, per-wave counts, one table in LDS turns them into
+// output offsets, and each thread writes its kept points.  The output is the
+// kept points in index order.  (lds is unused; kept for the callers' shape.)
 __device__ inline int overlap_compact(const Cam& c, const float* A, bool all, const float4* pts, int m, float4* out,
                                       int* lds) {
+    (void)lds;
+    constexpr int kRounds = 8, kMaxWaves = 16;
+    __shared__ int cnt[kMaxWaves * kRounds];   // wave w, round q: kept count, then exclusive wave offset
+    __shared__ int start[kRounds + 1];         // round offsets; start[kRounds] = batch total
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int bd = (int)blockDim.x;
     int base = 0;
-    for (int j0 = 0; j0 < m; j0 += blockDim.x) {
-        const int j = j0 + threadIdx.x;
-        float4 x = make_float4(0, 0, 0, 0);
-        int keep = 0;
-        if (j < m) {
-            x = pts[j];
-            keep = all ? 1 : (overlap_keep(c, A, x) ? 1 : 0);
+    for (int j0 = 0; j0 < m; j0 += kRounds * bd) {
+        float4 x[kRounds];
+        uint64_t ball[kRounds];
+#pragma unroll
+        for (int q = 0; q < kRounds; ++q) x[q] = pts[min(j0 + q * bd + (int)threadIdx.x, m - 1)];
+#pragma unroll
+        for (int q = 0; q < kRounds; ++q) {
+            const int j = j0 + q * bd + (int)threadIdx.x;
+            const bool keep = (j < m) && (all || overlap_keep(c, A, x[q]));
+            ball[q] = __ballot(keep);
+            if (lane == 0) cnt[wid * kRounds + q] = __popcll(ball[q]);
         }
-        int tot;
-        const int pos = block_scan_flag(keep, lds, &tot);
-        if (keep) out[base + pos] = x;
-        base += tot;
+        __syncthreads();
+        if ((int)threadIdx.x < kRounds) {  // one thread per round: offsets of the waves
+            const int q = threadIdx.x;
+            int acc = 0;
+            for (int w = 0; w < nw; ++w) {
+                const int cw = cnt[w * kRounds + q];
+                cnt[w * kRounds + q] = acc;
+                acc += cw;
+            }
+            start[q] = acc;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int acc = 0;
+            for (int q = 0; q < kRounds; ++q) {
+                const int t = start[q];
+                start[q] = acc;
+                acc += t;
+            }
+            start[kRounds] = acc;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kRounds; ++q)
+            if ((ball[q] >> lane) & 1ull)
+                out[base + start[q] + cnt[wid * kRounds + q] + __popcll(ball[q] & lt)] = x[q];
+        base += start[kRounds];
+        __syncthreads();  // the tables are rewritten by the next batch
     }
     return base;
 }
