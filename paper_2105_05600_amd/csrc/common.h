@@ -359,7 +359,7 @@ rose_status launch_fitness(const FitLaunch& L, hipStream_t s);
 // the first request reads the template back, synchronising s).  nullptr
 // (index order) when the handle's cache is full.
 rose_status particle_order(rose_tsdf* h, const float* pst_dev, int32_t n, hipStream_t s, const int32_t** out);
-int choose_splits(int32_t n_particles, int64_t max_points);
+int choose_splits(int32_t n_particles, int64_t max_points, int32_t fmt);
 bool fitness_shape_valid(int p, int u);
 void fitness_shape(int* p, int* u);
 int fitness_blocks(const FitLaunch& L, int P);

@@ -429,17 +429,18 @@ void fitness_shape(int* p, int* u) {
     *u = g_shape_u;
 }
 
-// Point slices: a multiple of the 8 XCDs (see k_fitness).  16 (two slices
-// per XCD, halving the particles in flight per XCD) once a slice keeps at
-// least 512 points -- measured on the 640x480 room workload: 8 slices 0.737
-// ms per launch, 16: 0.692, 32: 0.701, 64: 0.710 (per-wave setup and partial
-// sums grow) -- and raised further while the grid holds fewer waves than the
-// chip runs at once and each slice still has at least ~4 lane-steps (256
-// points).
-int choose_splits(int32_t n_particles, int64_t max_points) {
+// Point slices: a multiple of the 8 XCDs (see k_fitness).  For binary32
+// volumes 16 (two slices per XCD, halving the particles in flight per XCD)
+// once a slice keeps at least 512 points -- measured on the 640x480 room
+// workload: 8 slices 0.737 ms per launch, 16: 0.692, 32: 0.701, 64: 0.710;
+// the 16-bit volumes, half the bytes and resident in the Infinity Cache,
+// lose with 16 (0.508 -> 0.577 ms) -- and raised further while the grid
+// holds fewer waves than the chip runs at once and each slice still has at
+// least ~4 lane-steps (256 points).
+int choose_splits(int32_t n_particles, int64_t max_points, int32_t fmt) {
     const int64_t groups = (n_particles + g_shape_p - 1) / g_shape_p;
     const int64_t target_waves = 256 * 4 * 8;  // CUs x SIMDs x waves per SIMD
-    int64_t s = (max_points / 16 >= 512) ? 16 : 8;
+    int64_t s = (fmt == ROSE_TSDF_F32 && max_points / 16 >= 512) ? 16 : 8;
     while (s < 64 && groups * s < target_waves && max_points / (2 * s) >= 256) s *= 2;
     return (int)s;
 }
@@ -518,7 +519,7 @@ rose_status fitness_eval(const rose_tsdf* h, const float* pts_dev, int32_t m, co
     ROSE_REQUIRE(m >= 0 && m <= ROSE_MAX_IMAGE_PIXELS, ROSE_E_ARG, "fitness_eval: m = %d out of range", m);
     ROSE_REQUIRE(lk == ROSE_LOOKUP_NEAREST || lk == ROSE_LOOKUP_TRILINEAR, ROSE_E_ARG, "fitness_eval: bad lookup");
     rose_tsdf* hm = const_cast<rose_tsdf*>(h);
-    const int splits = choose_splits(n, m);
+    const int splits = choose_splits(n, m, h->g.fmt);
     // scratch: packed points and partial sums, owned by the handle
     if (hm->cap_points < m) {
         if (hm->pts) ROSE_CHECK_HIP(hipFree(hm->pts));
