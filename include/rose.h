@@ -412,9 +412,13 @@ rose_status pso_track_frame_learned(rose_tsdf* h, const float* depth_dev, const 
  * The fitness launch shape is the one set by rose_fitness_set_shape when the
  * batch is created ((4,2), (8,2), (4,4) or (8,4); otherwise (4,2)); one
  * persistent fitness launch per iteration and per group of sequences that
- * share a storage format and lookup.  Volumes must be below 4 GB.  The handles must stay alive while the batch
- * exists; tracking one through another path between batch steps is allowed
- * (the batch re-reads the handles' scratch pointers before each step). */
+ * share a storage format and lookup; its workgroups take work items from one
+ * counter per XCD, cleared by the kernel before each fitness round.
+ * Creation reads each template back once to derive the particle schedule
+ * order (as pso_track_frame does).  Volumes must be below 4 GB.  The handles
+ * must stay alive while the batch exists; tracking one through another path
+ * between batch steps is allowed (the batch re-reads the handles' scratch
+ * pointers before each step). */
 typedef struct rose_batch rose_batch;
 rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_camera* cams,
                              const float* const* pst_devs, const int32_t* n_particles,
