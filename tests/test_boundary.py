@@ -54,6 +54,8 @@ def test_host_side_argument_errors(R):
     assert lib.tsdf_destroy(None) == R.OK
     cam = R.Camera(100, 100, 10, 10, 0, 20)
     assert lib.depth_unproject(C.c_void_p(16), C.byref(cam), 2, 0, C.c_void_p(16), C.c_void_p(16), None) == R.E_SHAPE
+    cam = R.Camera(100, 100, 10, 10, 4096, 4097)  # one row above ROSE_MAX_IMAGE_PIXELS
+    assert lib.depth_unproject(C.c_void_p(16), C.byref(cam), 2, 0, C.c_void_p(16), C.c_void_p(16), None) == R.E_SHAPE
     cam = R.Camera(100, 100, 10, 10, 20, 20)
     assert lib.depth_unproject(C.c_void_p(16), C.byref(cam), 0, 0, C.c_void_p(16), C.c_void_p(16), None) == R.E_ARG
     assert lib.depth_unproject(C.c_void_p(16), C.byref(cam), 2, 5, C.c_void_p(16), C.c_void_p(16), None) == R.E_ARG
