@@ -403,3 +403,22 @@ def test_track_frame_max_particles(R, orc, small_gpu):
     assert g["aps"][0] == o["aps"][0] > 0
     assert np.linalg.norm(np.array(g["t"]) - o["t"]) <= 1e-4
     assert _rot_err(g["q"], o["q"]) <= 1e-4
+
+
+def test_track_frame_all_points_outside(R, orc, small_gpu):
+    """Degenerate frame: the camera 10 m away from the volume, so every
+    point of every particle reads +1 (F = 1 for all): every APS is empty, the
+    pose is kept and the axis lengths follow the empty-APS rule of Sec. 4,
+    as in the oracle."""
+    w, vol, psi, pst = small_gpu
+    prev = w.fuse_poses[-1]
+    far = np.asarray(prev.t) + np.array([10.0, 0.0, 0.0])
+    params = R.track_params(max_iters=6, stride=w.stride)
+    st = R.track_state(prev.q, far, [0.1] * 6)
+    g = R.track_frame(vol, dev(w.depth), w.K, dev(pst), params, st)
+    o = orc.track_frame(psi, w.vox, w.origin, w.depth, w.K, pst, prev.q, far, np.full(6, 0.1), max_iters=6,
+                        stride=w.stride, prec=orc.F32)
+    assert g["aps"] == [0] * 6 and list(o["aps"]) == [0] * 6
+    assert list(st.pose.t) == list(far) and list(st.pose.q) == list(prev.q)
+    assert np.allclose(g["r1"], o["r1"], rtol=1e-12, atol=0)
+    assert np.allclose(g["rho_centre"], np.exp(-1.0), rtol=1e-12)
