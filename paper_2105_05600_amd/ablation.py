@@ -23,7 +23,8 @@ through the library (one GPU).
             weight 0.9 -> 0.4, c1 = c2 = 2), all with 10240 particles, 20
             iterations and the fitness of Eq. normallh, on the 6D set and on
             a faster 6D set (4-8 m/s, 2.7-5.4 rad/s).
-            Reported per iteration: the exact fitness of each method's
+            PFO with PST also runs with the centre's exact fitness as the
+            APS threshold.  Reported per iteration: the exact fitness of each method's
             current estimate (PST: the centre c_k; the others: the best state
             so far) averaged over all frames, with its percentiles; ATE and
             time per frame.  The comparison methods have no adaptive scale:
@@ -95,13 +96,13 @@ def track(sq, depths, pst, params):
     return float(rmse), 1e3 * t_track / (len(depths) - 1), rho
 
 
-def track_pst_curve(sq, depths, pst):
+def track_pst_curve(sq, depths, pst, flags=0):
     """PFO with PST (20 iterations) with the exact fitness of the centre c_k
     after every iteration k: a 21-iteration run from a copy of the state
     reads rho(c_k) as particle 0's fitness of iteration k + 1 (the first 20
     iterations of both runs are the same computation)."""
-    params = rose.track_params(max_iters=ITERS, stride=4)
-    probe_params = rose.track_params(max_iters=ITERS + 1, stride=4)
+    params = rose.track_params(max_iters=ITERS, stride=4, flags=flags)
+    probe_params = rose.track_params(max_iters=ITERS + 1, stride=4, flags=flags)
     vol = rose.Tsdf(sq.dims, sq.vox, sq.mu, sq.origin)
     p0 = sq.poses[0]
     st = rose.track_state(p0.q, p0.t, [1.0] * 6, tsdf_built=False)
@@ -166,15 +167,15 @@ def track_swarm(sq, depths, pst, method, params, seed):
 
 
 def exp_optimizer(n_seq, frames, pst, base, kind="6d", spreads=(0.05, 0.1, 0.2)):
-    runs = {"pfo_pst": None}
+    runs = {"pfo_pst": None, "pfo_pst_centre_threshold": rose.FLAG_CENTRE_THRESHOLD}
     for r0 in spreads:
         runs[f"vanilla_pfo_r{r0}"] = (rose.PFO, r0)
         runs[f"pso_r{r0}"] = (rose.PSO, r0)
     rows = {v: {"ate": [], "ms": [], "curves": []} for v in runs}
     for seed, sq, depths in sequences(kind, n_seq, frames, base):
         for v, spec in runs.items():
-            if spec is None:
-                ate, ms, cv = track_pst_curve(sq, depths, pst)
+            if spec is None or isinstance(spec, int):
+                ate, ms, cv = track_pst_curve(sq, depths, pst, flags=spec or 0)
             else:
                 method, r0 = spec
                 params = rose.swarm_params(iters=ITERS, stride=4, r_init=(r0,) * 6)
