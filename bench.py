@@ -225,6 +225,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     prof = rose.profile_read()
+    launch_ms = rose.profile_fitness_launches()
     rose.profile_enable(False)
     log(f"timed {args.steps} frames in {wall:.3f} s; profile {prof}")
 
@@ -264,6 +265,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(lookup, tuned["shape"]) if fmt == 0 else None,
                      "kernel": "k_fitness", "avg_launch_ms": fit_ms, "evals_per_launch": fit_evals,
                      "bytes_per_eval": bytes_per_eval, "shape": list(tuned["shape"]),
+                     "launch_ms_p10_median_p90": ([float(v) for v in np.percentile(launch_ms, [10, 50, 90])]
+                                                  if len(launch_ms) else None),
                      "kernel_source_sha256_16": kernel_source_hash()},
     }
     g_l2 = gather_roofline(torch, rose, 2)

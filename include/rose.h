@@ -511,6 +511,11 @@ typedef struct {
 rose_status rose_profile_enable(int32_t on);
 rose_status rose_profile_reset(void);
 rose_status rose_profile_read(rose_profile* out);
+/* Durations (ms) of the fitness launches timed since the last reset, in
+ * launch order: copies min(cap, count) of them to ms_out (host memory) and
+ * sets *count_out to the count.  Resolves pending events like
+ * rose_profile_read. */
+rose_status rose_profile_fitness_launches(float* ms_out, int64_t cap, int64_t* count_out);
 
 /* ------------------------------------------------------------ measurement */
 /* Gather-rate probe (the roofline of the fitness kernel's TSDF reads): a

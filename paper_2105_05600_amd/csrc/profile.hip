@@ -17,6 +17,7 @@ bool g_on = false;
 std::vector<Pending> g_pending;
 std::vector<hipEvent_t> g_pool;
 rose_profile g_tot = {};
+std::vector<float> g_fit_ms;  // duration of every resolved fitness launch, in launch order
 
 hipEvent_t take_event() {
     if (!g_pool.empty()) {
@@ -64,6 +65,7 @@ static void resolve_locked() {
         (void)hipEventSynchronize(p.b);
         if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
             if (p.kind == PROF_FITNESS) {
+                g_fit_ms.push_back(ms);
                 g_tot.fitness_ms += ms;
                 g_tot.fitness_launches += 1;
                 g_tot.fitness_evals += p.evals;
@@ -99,6 +101,19 @@ rose_status rose_profile_reset(void) {
     std::lock_guard<std::mutex> l(g_mu);
     resolve_locked();
     g_tot = rose_profile{};
+    g_fit_ms.clear();
+    return ROSE_OK;
+}
+
+rose_status rose_profile_fitness_launches(float* ms_out, int64_t cap, int64_t* count_out) {
+    clear_error();
+    ROSE_REQUIRE(count_out != nullptr && (ms_out != nullptr || cap == 0) && cap >= 0, ROSE_E_ARG,
+                 "rose_profile_fitness_launches: bad arguments");
+    std::lock_guard<std::mutex> l(g_mu);
+    resolve_locked();
+    const int64_t n = (int64_t)g_fit_ms.size();
+    for (int64_t i = 0; i < n && i < cap; ++i) ms_out[i] = g_fit_ms[(size_t)i];
+    *count_out = n;
     return ROSE_OK;
 }
 

@@ -161,6 +161,7 @@ _sigs = {
     "rose_profile_enable": ([C.c_int32], C.c_int),
     "rose_profile_reset": ([], C.c_int),
     "rose_profile_read": ([C.POINTER(Profile)], C.c_int),
+    "rose_profile_fitness_launches": ([_P, C.c_int64, C.POINTER(C.c_int64)], C.c_int),
     "pst_poisson": ([C.c_int32, C.c_uint64, C.c_double, C.c_int32, _P, _P, _P, _S], C.c_int),
     "rose_gather_peak": ([_P, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_uint32, _P, _S], C.c_int),
     "rose_gather_peak_loads_per_lane": ([], C.c_int32),
@@ -504,6 +505,16 @@ def gather_peak(buf: torch.Tensor, region_lines: int, blocks: int, iters: int, s
                                                      int(iters), int(seed) & 0xFFFFFFFF, _ptr(sink),
                                                      _stream(stream)))
     return int(blocks) * 256 * int(iters) * int(_lib.rose_gather_peak_loads_per_lane())
+
+
+def profile_fitness_launches() -> np.ndarray:
+    """Durations (ms) of the fitness launches timed since the last reset."""
+    cnt = C.c_int64(0)
+    _check("rose_profile_fitness_launches", _lib.rose_profile_fitness_launches(None, 0, C.byref(cnt)))
+    out = np.zeros(max(cnt.value, 1), np.float32)
+    _check("rose_profile_fitness_launches",
+           _lib.rose_profile_fitness_launches(out.ctypes.data_as(C.c_void_p), cnt.value, C.byref(cnt)))
+    return out[: cnt.value].copy()
 
 
 def profile_read() -> dict:

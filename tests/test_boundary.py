@@ -135,3 +135,11 @@ def test_swarm_argument_errors(R):
     cold = R.track_state([1, 0, 0, 0], [0.1, 0.2, 0.3], [1.0] * 6, tsdf_built=False)
     assert pfo(R.swarm_params(iters=1), normals=None, offsets=None, state=cold) == R.OK
     assert list(cold.pose.t) == [0.1, 0.2, 0.3] and cold.frame == 1 and stats.iters == 0
+
+
+def test_profile_launch_log_host_side(R):
+    """With nothing timed, the per-launch fitness log is empty (no device
+    call needed); NULL count pointers are rejected."""
+    R.profile_reset()
+    assert len(R.profile_fitness_launches()) == 0
+    assert R._lib.rose_profile_fitness_launches(None, 0, None) == R.E_ARG
