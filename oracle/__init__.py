@@ -29,6 +29,10 @@ Parity status per function (what pins it, tests/test_oracle_*.py):
                         (trilinear exact on a linear field); 1-Lipschitz
                         bound at the true pose (nearest); all-outside -> 1;
                         Neumaier sum vs math.fsum; voxel index brute force.
+  (kahan=False)         the plain binary32 sum: within the recursive-
+                        summation bound (m-1) 2^-24 sum v^2 of math.fsum; a
+                        constructed case where it loses exactly the terms
+                        below half an ulp of the running sum.
 * pst_update         -- pinned: single-member APS reproduces that particle;
                         symmetric APS -> zero step; empty APS and
                         TSDF-not-built corner cases; permutation invariance.
@@ -88,6 +92,7 @@ NO_NORMALIZE = 2
 CENTRE_THRESHOLD = 4
 ISO_ONLY = 8
 ANISO_ONLY = 16
+NO_KAHAN = 32
 SWARM_PFO = 0
 SWARM_PSO = 1
 
@@ -152,6 +157,8 @@ def _load():
             lib.orc_overlap.restype = C.c_int
             lib.orc_fitness.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_float, P, P, C.c_int32, P, P,
                                         C.c_int32, C.c_int32, C.c_int, C.c_int, P]
+            lib.orc_fitness_ex.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_float, P, P, C.c_int32, P, P,
+                                           C.c_int32, C.c_int32, C.c_int, C.c_int, C.c_int, P]
             lib.orc_voxel_indices.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_float, P, P, C.c_int32, P,
                                               C.c_int32, P]
             lib.orc_pst_poisson.argtypes = [C.c_int32, C.c_uint64, C.c_double, C.c_int32, P, P]
@@ -263,10 +270,11 @@ def overlap(pts, Tc, Tprev, K, prec: int = F32) -> np.ndarray:
 
 
 def fitness(psi, vox, origin, pts, T, lookup: int = NEAREST, prec: int = F32, mask=None,
-            normalize: bool = True) -> np.ndarray:
+            normalize: bool = True, kahan: bool = True) -> np.ndarray:
     """F_i (float64) for transforms T (n, 3, 4) over points pts (m, 3).
 
-    psi: (nz, ny, nx) float32 normalised TSDF."""
+    psi: (nz, ny, nx) float32 normalised TSDF.  kahan=False: the plain
+    binary32 sum in point order ("No Kahan" of the Sec. 5 ablation)."""
     lib = _load()
     psi = _f32(psi)
     nz, ny, nx = psi.shape
@@ -277,8 +285,9 @@ def fitness(psi, vox, origin, pts, T, lookup: int = NEAREST, prec: int = F32, ma
     mk = None
     if mask is not None:
         mk = np.ascontiguousarray(mask, dtype=np.uint8)
-    lib.orc_fitness(_p(psi), nx, ny, nz, float(vox), _p(org), _p(pts), len(pts),
-                    _p(mk) if mk is not None else None, _p(T), len(T), lookup, prec, int(normalize), _p(F))
+    lib.orc_fitness_ex(_p(psi), nx, ny, nz, float(vox), _p(org), _p(pts), len(pts),
+                       _p(mk) if mk is not None else None, _p(T), len(T), lookup, prec, int(normalize),
+                       int(not kahan), _p(F))
     return F[:len(T)].copy()
 
 

@@ -40,6 +40,7 @@
 #define ORC_CENTRE_THRESHOLD 4
 #define ORC_ISO_ONLY 8   /* rescaling ablation: isotropic part of Eq. rsinter only */
 #define ORC_ANISO_ONLY 16 /* rescaling ablation: anisotropic part of Eq. rsinter only */
+#define ORC_NO_KAHAN 32   /* TSDF-normalisation ablation: plain binary32 summation of psi^2 */
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x64-10 counter-based generator (Salmon, Moraes, Dror, Shaw, SC'11, */
@@ -487,9 +488,13 @@ static void neumaier_add(double* s, double* c, double v) {
     *s = t;
 }
 
-void orc_fitness(const float* psi, int32_t nx, int32_t ny, int32_t nz, float vox, const float origin[3],
-                 const float* pts, int32_t m, const uint8_t* mask, const double* T, int32_t n, int32_t lk,
-                 int prec, int normalize, double* F) {
+/* plain32 != 0 ("No Kahan" of the Sec. 5 TSDF-normalisation ablation): the  */
+/* sum is taken directly in binary32 in point order, acc = fmaf(v, v, acc)  */
+/* with v rounded to binary32, i.e. one rounding per added term and no      */
+/* compensation; S = acc.                                                   */
+void orc_fitness_ex(const float* psi, int32_t nx, int32_t ny, int32_t nz, float vox, const float origin[3],
+                    const float* pts, int32_t m, const uint8_t* mask, const double* T, int32_t n, int32_t lk,
+                    int prec, int normalize, int plain32, double* F) {
     orc_grid g = {psi, nx, ny, nz, (double)vox, {origin[0], origin[1], origin[2]}};
     int32_t cnt = 0;
     for (int32_t j = 0; j < m; ++j) cnt += (mask == NULL || mask[j]);
@@ -498,6 +503,7 @@ void orc_fitness(const float* psi, int32_t nx, int32_t ny, int32_t nz, float vox
         float V32[12];
         fold_voxel(&g, Ti, V32);
         double s = 0.0, c = 0.0;
+        float acc = 0.0f;
         for (int32_t j = 0; j < m; ++j) {
             if (mask != NULL && !mask[j]) continue;
             double gv[3];
@@ -509,12 +515,23 @@ void orc_fitness(const float* psi, int32_t nx, int32_t ny, int32_t nz, float vox
             } else {
                 v = lookup(&g, gv, ORC_LOOKUP_NEAREST);
             }
-            neumaier_add(&s, &c, v * v);
+            if (plain32) {
+                const float vf = (float)v;
+                acc = fmaf(vf, vf, acc);
+            } else {
+                neumaier_add(&s, &c, v * v);
+            }
         }
-        double S = s + c;
+        double S = plain32 ? (double)acc : s + c;
         if (!normalize) F[i] = S;
         else F[i] = (cnt > 0) ? S / (double)cnt : 1.0;
     }
+}
+
+void orc_fitness(const float* psi, int32_t nx, int32_t ny, int32_t nz, float vox, const float origin[3],
+                 const float* pts, int32_t m, const uint8_t* mask, const double* T, int32_t n, int32_t lk,
+                 int prec, int normalize, double* F) {
+    orc_fitness_ex(psi, nx, ny, nz, vox, origin, pts, m, mask, T, n, lk, prec, normalize, 0, F);
 }
 
 /* Voxel indices of each (particle, point) pair under NEAREST lookup, for   */
@@ -714,8 +731,8 @@ int orc_track_frame(const float* psi, int32_t nx, int32_t ny, int32_t nz, float 
                 nO = orc_overlap(pts, m, Tc, Tprev, fx, fy, cx, cy, W, H, P->prec, mask);
             }
             for (int32_t i = 0; i < n; ++i) orc_particle_pose(qc, tc, r, pst + 6 * (size_t)i, T + 12 * (size_t)i);
-            orc_fitness(psi, nx, ny, nz, vox, origin, pts, m, mask, T, n, P->lookup, P->prec,
-                        !(P->flags & ORC_NO_NORMALIZE), F);
+            orc_fitness_ex(psi, nx, ny, nz, vox, origin, pts, m, mask, T, n, P->lookup, P->prec,
+                           !(P->flags & ORC_NO_NORMALIZE), (P->flags & ORC_NO_KAHAN) != 0, F);
             if (P->prec == ORC_F32)
                 for (int32_t i = 0; i < n; ++i) F[i] = (double)(float)F[i];
         }
