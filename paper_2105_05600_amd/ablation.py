@@ -10,8 +10,9 @@ through the library (one GPU).
             empty) at every iteration over all frames, with its 10th and
             90th percentiles.
   tsdf      Tab. "TSDF normalisation": the fitness with and without the
-            overlap set O_k (Eq. validness) and with and without the
-            normalisation of Eq. normallh; ATE on the 6D set.
+            overlap set O_k (Eq. validness), with and without the
+            normalisation of Eq. normallh, and with plain binary32 sums
+            instead of compensated ones ("No Kahan"); ATE on the 6D set.
   multires  Fig. "multi-resolution": the alternating (1024, 1/8),
             (3072, 1/16), (10240, 1/32) schedule (strides 3, 4, 6) against
             each single setting and the 10240-particle stride-4 default;
@@ -263,6 +264,7 @@ def main():
             "full": (pst, rose.track_params(max_iters=ITERS, stride=4)),
             "no_overlap": (pst, rose.track_params(max_iters=ITERS, stride=4, flags=rose.FLAG_NO_OVERLAP)),
             "no_normalize": (pst, rose.track_params(max_iters=ITERS, stride=4, flags=rose.FLAG_NO_NORMALIZE)),
+            "no_kahan": (pst, rose.track_params(max_iters=ITERS, stride=4, flags=rose.FLAG_NO_KAHAN)),
         }, 64000)
     if "multires" in exps:
         var = {"single_10240_s4": (pst, rose.track_params(max_iters=ITERS, stride=4)),

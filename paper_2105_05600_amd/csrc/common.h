@@ -352,6 +352,7 @@ struct FitLaunch {
     int32_t splits;
     int32_t lookup;
     int32_t shape_p, shape_u;  // particles per wave, points per lane per step
+    int32_t acc32;             // 1: plain binary32 sums (ROSE_FLAG_NO_KAHAN), FROM_STATE binary32 volumes only
     double* partial;           // n x splits
 };
 rose_status launch_fitness(const FitLaunch& L, hipStream_t s);

@@ -82,7 +82,13 @@ __device__ inline float bcast(float v, int lane) {
 
 // P particles per wave, U points per lane per loop step; all P*U gathers of
 // a step are issued before any is consumed.
-template <int P, int U, int FMT, int LK, bool FROM_STATE, bool WIDE>
+__device__ inline float wave_sum_f(float v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+template <int P, int U, int FMT, int LK, bool FROM_STATE, bool WIDE, bool ACC32 = false>
 __device__ void fitness_body(const FitLaunch& a, const int blk) {
     constexpr int kU = U;
     const int lane = threadIdx.x & 63;
@@ -137,8 +143,12 @@ __device__ void fitness_body(const FitLaunch& a, const int blk) {
     const int j0 = split * chunk;
     const int j1 = min(m, j0 + chunk);
     double acc[P];
+    float accf[P];  // ACC32: plain binary32 running sums
 #pragma unroll
-    for (int p = 0; p < P; ++p) acc[p] = 0.0;
+    for (int p = 0; p < P; ++p) {
+        acc[p] = 0.0;
+        accf[p] = 0.0f;
+    }
     // the next step's points are loaded one step ahead, so their latency
     // overlaps the current step's gathers
     float4 xn[kU];
@@ -196,12 +206,20 @@ __device__ void fitness_body(const FitLaunch& a, const int blk) {
         for (int u = 0; u < kU; ++u)
 #pragma unroll
             for (int p = 0; p < P; ++p) {
-                const double d = (double)(ok[u] ? v[u][p] : 0.0f);
-                acc[p] = fma(d, d, acc[p]);
+                if constexpr (ACC32) {
+                    const float d = ok[u] ? v[u][p] : 0.0f;
+                    accf[p] = fmaf(d, d, accf[p]);
+                } else {
+                    const double d = (double)(ok[u] ? v[u][p] : 0.0f);
+                    acc[p] = fma(d, d, acc[p]);
+                }
             }
     }
 #pragma unroll
-    for (int p = 0; p < P; ++p) acc[p] = wave_sum(acc[p]);
+    for (int p = 0; p < P; ++p) {
+        if constexpr (ACC32) acc[p] = (double)wave_sum_f(accf[p]);
+        else acc[p] = wave_sum(acc[p]);
+    }
     if (lane == 0) {
 #pragma unroll
         for (int p = 0; p < P; ++p)
@@ -212,9 +230,9 @@ __device__ void fitness_body(const FitLaunch& a, const int blk) {
     }
 }
 
-template <int P, int U, int FMT, int LK, bool FROM_STATE, bool WIDE>
+template <int P, int U, int FMT, int LK, bool FROM_STATE, bool WIDE, bool ACC32 = false>
 __global__ __launch_bounds__(256) void k_fitness(FitLaunch a) {
-    fitness_body<P, U, FMT, LK, FROM_STATE, WIDE>(a, blockIdx.x);
+    fitness_body<P, U, FMT, LK, FROM_STATE, WIDE, ACC32>(a, blockIdx.x);
 }
 
 int fitness_blocks(const FitLaunch& L, int P) { return ((L.n + P - 1) / P + 3) / 4 * L.splits; }
@@ -387,7 +405,12 @@ static void launch_pu(const FitLaunch& L, hipStream_t s) {
     const unsigned blocks = (unsigned)(((groups + 3) / 4) * L.splits);
     if (L.T32)
         hipLaunchKernelGGL((k_fitness<P, U, FMT, LK, false, WIDE>), dim3(blocks), dim3(256), 0, s, L);
-    else
+    else if constexpr (FMT == ROSE_TSDF_F32 && !WIDE) {
+        if (L.acc32)
+            hipLaunchKernelGGL((k_fitness<P, U, FMT, LK, true, WIDE, true>), dim3(blocks), dim3(256), 0, s, L);
+        else
+            hipLaunchKernelGGL((k_fitness<P, U, FMT, LK, true, WIDE>), dim3(blocks), dim3(256), 0, s, L);
+    } else
         hipLaunchKernelGGL((k_fitness<P, U, FMT, LK, true, WIDE>), dim3(blocks), dim3(256), 0, s, L);
 }
 

@@ -371,6 +371,10 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_cam
     }
     ROSE_REQUIRE(p->lookup == ROSE_LOOKUP_NEAREST || p->lookup == ROSE_LOOKUP_TRILINEAR, ROSE_E_ARG,
                  "pso_track_frame: bad lookup");
+    ROSE_REQUIRE(!(p->flags & ROSE_FLAG_NO_KAHAN) ||
+                     (h->g.fmt == ROSE_TSDF_F32 &&
+                      (uint64_t)h->g.nx * h->g.ny * h->g.nz * 4u < (uint64_t(1) << 32)),
+                 ROSE_E_UNSUPPORTED, "pso_track_frame: ROSE_FLAG_NO_KAHAN needs a binary32 volume below 4 GB");
     ROSE_REQUIRE(p->tau > 0.0 && p->beta >= 0.0 && p->beta <= 1.0, ROSE_E_ARG,
                  "pso_track_frame: tau must be > 0 and beta in [0, 1]");
     const double* r0 = init_r ? init_r : state->r;
@@ -452,6 +456,7 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_cam
     fl.pst = pst_dev;
     fl.lookup = p->lookup;
     fl.partial = h->partial;
+    fl.acc32 = (p->flags & ROSE_FLAG_NO_KAHAN) ? 1 : 0;
     fitness_shape(&fl.shape_p, &fl.shape_u);
 
     UpdateArgs ua;
@@ -677,6 +682,8 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
             (uint64_t)tsdfs[i]->g.nx * tsdfs[i]->g.ny * tsdfs[i]->g.nz * (tsdfs[i]->g.fmt == ROSE_TSDF_F32 ? 4u : 2u);
         ROSE_REQUIRE(bytes < (uint64_t(1) << 32), ROSE_E_UNSUPPORTED,
                      "pso_batch_create: volume %d is 4 GB or larger (use pso_track_frame)", i);
+        ROSE_REQUIRE(!(params[i].flags & ROSE_FLAG_NO_KAHAN), ROSE_E_UNSUPPORTED,
+                     "pso_batch_create: ROSE_FLAG_NO_KAHAN is not batched (sequence %d)", i);
         for (int j = 0; j < i; ++j)
             ROSE_REQUIRE(tsdfs[j] != tsdfs[i], ROSE_E_ARG, "pso_batch_create: handle %d repeated", i);
     }

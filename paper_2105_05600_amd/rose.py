@@ -32,6 +32,7 @@ E_ARG, E_SHAPE, E_DEVICE, E_STATE, E_UNSUPPORTED = -1, -2, -3, -4, -5
 F32, F16, SN16 = 0, 1, 2
 NEAREST, TRILINEAR = 0, 1
 FLAG_NO_OVERLAP, FLAG_NO_NORMALIZE, FLAG_CENTRE_THRESHOLD, FLAG_ISO_ONLY, FLAG_ANISO_ONLY = 1, 2, 4, 8, 16
+FLAG_NO_KAHAN = 32
 MAX_ITERS = 32
 MAX_LEVELS = 4
 

@@ -1,0 +1,96 @@
+"""ROSE_FLAG_NO_KAHAN ("No Kahan" of the Sec. 5 TSDF-normalisation ablation):
+plain binary32 sums of psi^2 on the GPU against the oracle's plain binary32
+sum.  The two add in different orders (lanes and a wavefront tree vs point
+order), so each is within the recursive-summation bound (m - 1) 2^-24 of the
+exact sum and they are compared within twice that, at the centre's fitness
+in iteration 1; whole frames agree within 5 mm / 0.5 degrees (different
+rounding can flip APS members of weight ~0).  Unsupported combinations are
+refused."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2105_05600_amd import rose
+    return rose
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.fixture(scope="module")
+def small(R, orc):
+    w = synth.small_frame()
+    vol = R.Tsdf(w.dims, w.vox, w.mu, w.origin)
+    nx, ny, nz = w.dims
+    psi = np.ones((nz, ny, nx), np.float32)
+    wt = np.zeros_like(psi)
+    for p, d in zip(w.fuse_poses, w.fuse_depths):
+        vol.integrate(dev(d), w.K, p.q, p.t)
+        orc.integrate(psi, wt, w.vox, w.origin, w.mu, d, w.K, p.q, p.t, prec=orc.F32)
+    pst, _ = orc.pst_sample(w.n_particles, w.pst_seed)
+    return w, vol, psi, pst
+
+
+def _rot_err(qa, qb):
+    Ra, Rb = synth.quat_to_mat(qa), synth.quat_to_mat(qb)
+    return math.acos(np.clip((np.trace(Ra.T @ Rb) - 1) / 2, -1, 1))
+
+
+@pytest.mark.parametrize("lookup", [0, 1])
+def test_no_kahan_centre_fitness(R, orc, small, lookup):
+    w, vol, psi, pst = small
+    prev = w.fuse_poses[-1]
+    st = R.track_state(prev.q, prev.t, [0.1] * 6)
+    g = R.track_frame(vol, dev(w.depth), w.K, dev(pst), R.track_params(max_iters=1, stride=w.stride, lookup=lookup,
+                                                                        flags=R.FLAG_NO_KAHAN), st)
+    Fg = -math.log(g["rho_centre"][0])
+    pts = orc.unproject(w.depth, w.K, w.stride)
+    # O_1 at c_0 = the previous pose: the identity motion, yet border points
+    # whose reprojection rounds past W - 1 or H - 1 drop out (Eq. validness)
+    Tp = orc.pose_mat(prev.q, prev.t)
+    mask = orc.overlap(pts, Tp, Tp, w.K)
+    T0 = orc.particle_poses(prev.q, prev.t, np.zeros(6), pst[:1])
+    Fo = orc.fitness(psi, w.vox, w.origin, pts, T0, lookup=lookup, kahan=False, mask=mask)[0]
+    Fk = orc.fitness(psi, w.vox, w.origin, pts, T0, lookup=lookup, kahan=True, mask=mask)[0]
+    m = int(mask.sum())
+    assert g["n_overlap"][0] == m
+    bound = 2 * (m - 1) * 2.0 ** -24 * Fk + 2.0 ** -22 * Fk  # two summation bounds + the binary32 F
+    assert abs(Fg - Fo) <= bound and abs(Fg - Fk) <= bound
+
+
+def test_no_kahan_whole_frame(R, orc, small):
+    w, vol, psi, pst = small
+    prev = w.fuse_poses[-1]
+    params = R.track_params(max_iters=w.iters, stride=w.stride, flags=R.FLAG_NO_KAHAN)
+    st = R.track_state(prev.q, prev.t, [0.1] * 6)
+    g = R.track_frame(vol, dev(w.depth), w.K, dev(pst), params, st)
+    o = orc.track_frame(psi, w.vox, w.origin, w.depth, w.K, pst, prev.q, prev.t, np.full(6, 0.1),
+                        max_iters=w.iters, stride=w.stride, flags=orc.NO_KAHAN, prec=orc.F32)
+    assert g["iters"] == o["iters"]
+    assert np.linalg.norm(np.array(g["t"]) - o["t"]) <= 5e-3
+    assert _rot_err(g["q"], o["q"]) <= math.radians(0.5)
+
+
+def test_no_kahan_refused_where_unsupported(R, small):
+    w, vol, psi, pst = small
+    prev = w.fuse_poses[-1]
+    v16 = R.Tsdf(w.dims, w.vox, w.mu, w.origin, fmt=1)
+    st = R.track_state(prev.q, prev.t, [0.1] * 6)
+    with pytest.raises(R.RoseError) as ei:
+        R.track_frame(v16, dev(w.depth), w.K, dev(pst), R.track_params(flags=R.FLAG_NO_KAHAN), st)
+    assert ei.value.status == R.E_UNSUPPORTED
+    with pytest.raises(R.RoseError) as ei:
+        R.Batch([vol], [w.K], [dev(pst)], [R.track_params(flags=R.FLAG_NO_KAHAN)], use_graph=False)
+    assert ei.value.status == R.E_UNSUPPORTED
+    v16.close()
