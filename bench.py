@@ -79,10 +79,13 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(lookup: int, shape):
-    """HBM bytes per fitness launch from the committed counter summary, or
-    None when it is missing, for another lookup or launch shape, or the
-    kernel has changed."""
+L2_PEAK_GBS = 39300.0  # 16 channels x 128 B per clock per XCD, 8 XCDs, 2.4 GHz
+
+
+def measured_counter(key: str, lookup: int, shape):
+    """A per-launch figure of the committed counter summary (HBM traffic,
+    L2 read bytes), or None when it is missing, for another lookup or launch
+    shape, or the kernel has changed."""
     try:
         with open(COUNTERS) as f:
             kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith(" "))
@@ -94,7 +97,7 @@ def measured_traffic(lookup: int, shape):
     if kv.get("shape") != f"{shape[0]}x{shape[1]}":
         return None
     try:
-        return float(kv["traffic_bytes_per_launch"])
+        return float(kv[key])
     except (KeyError, ValueError):
         return None
 
@@ -262,7 +265,7 @@ def main():
                                     "update": prof["update_ms"] / args.steps,
                                     "integrate": prof["integrate_ms"] / args.steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(lookup, tuned["shape"]) if fmt == 0 else None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_counter("traffic_bytes_per_launch", lookup, tuned["shape"]) if fmt == 0 else None,
                      "kernel": "k_fitness", "avg_launch_ms": fit_ms, "evals_per_launch": fit_evals,
                      "bytes_per_eval": bytes_per_eval, "shape": list(tuned["shape"]),
                      "launch_ms_p10_median_p90": ([float(v) for v in np.percentile(launch_ms, [10, 50, 90])]
@@ -278,6 +281,17 @@ def main():
         "peak_per_s": g_l2, "hbm_resident_peak_per_s": g_hbm, "achieved_evals_per_s": fit_rate,
         "frac": fit_rate / g_l2}
     log(f"gather probe: L2-resident {g_l2:.3e}/s, HBM-resident {g_hbm:.3e}/s; fitness {fit_rate:.3e} evals/s")
+    # L1 -> L2 read bandwidth of the fitness kernel: the committed counter
+    # summary's bytes per launch (while the kernel is unchanged) over this
+    # run's average launch time
+    l2_bytes = measured_counter("l2_read_bytes_per_launch", lookup, tuned["shape"]) if fmt == 0 else None
+    l2_gbs = l2_bytes / (fit_ms * 1e-3) / 1e9 if l2_bytes is not None else None
+    out["l2_roofline"] = {
+        "what": "L1 -> L2 read requests x 128 B per fitness launch (rocprofv3 TCP_TCC_READ_REQ) over the average "
+                "launch time; peak = 16 channels x 128 B per clock per XCD, 8 XCDs, 2.4 GHz",
+        "achieved": l2_gbs, "peak": L2_PEAK_GBS, "unit": "GB/s",
+        "frac": l2_gbs / L2_PEAK_GBS if l2_gbs is not None else None,
+        "probe_lines_gbs": g_l2 * 128.0 / 1e9}
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on 3 iterations of frame 1")
         out["cpu_baseline"] = cpu_baseline(seq, depths[0], depths[1], p0, seq.n_particles, lookup)
