@@ -62,8 +62,10 @@ def features(vol, depth, K, scale, q, t, vel):
     return rose.proposal_features(depth, K, render, low_camera(K, scale), scale, vel, FEATURE_DIM)
 
 
-def generate(seeds, n_frames, width, height, chunk, workers):
-    """Plain-PST pairs (X, Y) from the sequences `seeds` (GPU)."""
+def generate(seeds, n_frames, width, height, chunk, workers, gpu_render=False):
+    """Plain-PST pairs (X, Y) from the sequences `seeds` (GPU).  gpu_render:
+    the depth frames are rendered on the GPU (synth.gpu_render, seeded torch
+    noise) instead of on the host."""
     scale = width // LOW_W
     Xs, Ys = [], []
     pst = rose.pst_sample(10240, 5600)
@@ -71,7 +73,14 @@ def generate(seeds, n_frames, width, height, chunk, workers):
         group = seeds[c0:c0 + chunk]
         seqs = [make_sequence(s, n_frames, width, height) for s in group]
         t0 = time.perf_counter()
-        depths = [[torch.from_numpy(d).cuda() for d in sq.depths(range(n_frames), workers=workers)] for sq in seqs]
+        if gpu_render:
+            from synth.gpu_render import render_depths
+            depths = [list(render_depths(sq.scene, sq.K, sq.poses[:n_frames], sq.zmin, sq.zmax,
+                                         noise_seed=sq.noise_seed, noise_k=sq.noise_k, device="cuda"))
+                      for sq in seqs]
+        else:
+            depths = [[torch.from_numpy(d).cuda() for d in sq.depths(range(n_frames), workers=workers)]
+                      for sq in seqs]
         log(f"sequences {c0}..{c0 + len(group) - 1}: rendered in {time.perf_counter() - t0:.1f} s")
         vols = [rose.Tsdf(sq.dims, sq.vox, sq.mu, sq.origin) for sq in seqs]
         params = [rose.track_params(max_iters=20, stride=4) for _ in seqs]
@@ -233,6 +242,7 @@ def main():
     ap.add_argument("--width", type=int, default=320)
     ap.add_argument("--height", type=int, default=240)
     ap.add_argument("--chunk", type=int, default=16)
+    ap.add_argument("--gpu-render", action="store_true", help="render the training frames on the GPU")
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--batch", type=int, default=512)
     ap.add_argument("--lr", type=float, default=1e-3)
@@ -261,7 +271,7 @@ def main():
     else:
         seeds = [10000 + 10 * i for i in range(args.sequences)]
         t0 = time.perf_counter()
-        X, Y = generate(seeds, args.frames, args.width, args.height, args.chunk, args.workers)
+        X, Y = generate(seeds, args.frames, args.width, args.height, args.chunk, args.workers, args.gpu_render)
         t_gen = time.perf_counter() - t0
         log(f"{X.shape[0]} pairs in {t_gen:.1f} s; |y| mean {Y.abs().mean(0).tolist()}")
         t0 = time.perf_counter()
