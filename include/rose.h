@@ -494,8 +494,12 @@ rose_status rose_gemm_bf16(int32_t M, int32_t N, int32_t K, const float* A_dev, 
 
 /* Launch shape of the fitness kernel (process-wide): particles per
  * wavefront and points per lane per loop step.  Compiled shapes: (2, 4),
- * (4, 2) (default), (4, 4), (8, 2), (8, 4); others give ROSE_E_UNSUPPORTED.
- * Results do not depend on the shape beyond binary64 summation order. */
+ * (4, 2) (default), (4, 4), (8, 2), (8, 4) -- points across the lanes, P
+ * particles per wave -- and (64, 4), (64, 8), (64, 16) -- one particle per
+ * lane, U points looked up per step; others give ROSE_E_UNSUPPORTED.  The
+ * batched tracker runs (4, 2) when the current shape is not one of the
+ * first five.  Results do not depend on the shape beyond binary64
+ * summation order. */
 rose_status rose_fitness_set_shape(int32_t particles_per_wave, int32_t points_per_lane);
 
 /* ------------------------------------------------------- kernel timing */

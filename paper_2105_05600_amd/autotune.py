@@ -17,7 +17,7 @@ import torch
 
 from paper_2105_05600_amd import rose
 
-SHAPES = [(4, 2), (8, 2), (4, 4), (2, 4), (8, 4)]
+SHAPES = [(4, 2), (8, 2), (4, 4), (2, 4), (8, 4), (64, 4), (64, 8), (64, 16)]  # (64, U): one particle per lane
 BATCH_SHAPES = [(4, 2), (8, 2), (4, 4), (8, 4)]  # shapes the batched tracker supports
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
 

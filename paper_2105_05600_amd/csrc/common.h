@@ -360,9 +360,16 @@ rose_status launch_fitness(const FitLaunch& L, hipStream_t s);
 // the first request reads the template back, synchronising s).  nullptr
 // (index order) when the handle's cache is full.
 rose_status particle_order(rose_tsdf* h, const float* pst_dev, int32_t n, hipStream_t s, const int32_t** out);
-int choose_splits(int32_t n_particles, int64_t max_points, int32_t fmt);
+// point slices for n particles in waves of P (the launch shape's first entry)
+int choose_splits(int32_t n_particles, int64_t max_points, int32_t fmt, int P);
 bool fitness_shape_valid(int p, int u);
 void fitness_shape(int* p, int* u);
+// particles per wave of the current launch shape
+inline int shape_particles() {
+    int p, u;
+    fitness_shape(&p, &u);
+    return p;
+}
 int fitness_blocks(const FitLaunch& L, int P);
 bool batch_shape_valid(int p, int u);
 int batch_grid(int P, int U, int fmt, int lk, int requested);

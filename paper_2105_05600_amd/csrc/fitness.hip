@@ -230,9 +230,108 @@ __device__ void fitness_body(const FitLaunch& a, const int blk) {
     }
 }
 
+// Transposed mapping (shape (64, U)): one particle per lane.  A wave takes 64
+// consecutive particles of the schedule order over one slice of the point
+// list; each lane builds and keeps its own transform, the wave loads 64
+// points at a time (one 16-byte load per lane) and hands them out one by one
+// from lane registers (readlane: the point is wave-uniform).  Every gather
+// instruction then looks up one point under 64 neighbouring poses of the
+// schedule order: once the search radius has shrunk to a few centimetres
+// these land in a handful of voxels, and the lanes share cache lines (a CPU
+// count on the room frames: ~4 lanes per 128-byte line at r = 0.03, ~13 at
+// 0.01, against ~1.1 when the lanes hold 64 neighbouring points).  U points
+// are looked up per step, their gathers in flight together.  Slices, XCD
+// mapping and the partial-sum layout are those of fitness_body; each lane
+// sums its particle's squares in point order.
+template <int U, int FMT, int LK, bool FROM_STATE, bool WIDE, bool ACC32 = false>
+__device__ void fitness_body_pl(const FitLaunch& a, const int blk) {
+    const int lane = threadIdx.x & 63;
+    const int s8 = a.splits >> 3;
+    const int r = blk % a.splits;
+    const int split = (r & 7) * s8 + (r >> 3);
+    const int group = (blk / a.splits) * 4 + (threadIdx.x >> 6);
+    const int p0 = group * kWave;
+    if (p0 >= a.n) return;
+    if (FROM_STATE && a.st->stopped) return;
+    const int m = a.count_dev ? *a.count_dev : a.count;
+
+    const bool live = p0 + lane < a.n;
+    int pi = live ? p0 + lane : a.n - 1;
+    if (FROM_STATE && a.order) pi = a.order[pi];
+    float V[12];
+    {
+        double T[12];
+        if (FROM_STATE) {
+            float p[6];
+#pragma unroll
+            for (int d = 0; d < 6; ++d) p[d] = a.pst[6 * (int64_t)pi + d];
+            particle_transform(a.st->qc, a.st->tc, a.st->r, p, T);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 12; ++e) T[e] = (double)a.T32[12 * (int64_t)pi + e];
+        }
+        fold_to_voxel(T, (double)a.g.vox, a.g.origin, V);
+    }
+
+    const Grid g = a.g;
+    const VoxelTest ext{(float)g.nx, (float)g.ny, (float)g.nz};
+    const int chunk = (m + a.splits - 1) / a.splits;
+    const int j0 = split * chunk;
+    const int j1 = min(m, j0 + chunk);
+    double acc = 0.0;
+    float accf = 0.0f;
+    for (int jb = j0; jb < j1; jb += kWave) {
+        const int cnt = min(kWave, j1 - jb);  // wave-uniform, >= 1
+        const float4 xl = a.pts[jb + (lane < cnt ? lane : 0)];
+        for (int u0 = 0; u0 < cnt; u0 += U) {
+            float v[U];
+            if constexpr (LK == ROSE_LOOKUP_NEAREST) {
+                uint32_t off[U];
+                bool in[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int src = min(u0 + u, cnt - 1);
+                    const float x = bcast(xl.x, src), y = bcast(xl.y, src), z = bcast(xl.z, src);
+                    const float gx = xf_row(V[0], V[1], V[2], V[3], x, y, z);
+                    const float gy = xf_row(V[4], V[5], V[6], V[7], x, y, z);
+                    const float gz = xf_row(V[8], V[9], V[10], V[11], x, y, z);
+                    in[u] = nearest_offset(g, ext, gx, gy, gz, &off[u]);
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) v[u] = gather<FMT, WIDE>(g.psi, off[u]);
+#pragma unroll
+                for (int u = 0; u < U; ++u) v[u] = in[u] ? v[u] : 1.0f;
+            } else {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int src = min(u0 + u, cnt - 1);
+                    const float x = bcast(xl.x, src), y = bcast(xl.y, src), z = bcast(xl.z, src);
+                    const float gx = xf_row(V[0], V[1], V[2], V[3], x, y, z);
+                    const float gy = xf_row(V[4], V[5], V[6], V[7], x, y, z);
+                    const float gz = xf_row(V[8], V[9], V[10], V[11], x, y, z);
+                    v[u] = lookup_trilinear<FMT, WIDE>(g, gx, gy, gz);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool ok = u0 + u < cnt;  // wave-uniform
+                if constexpr (ACC32) {
+                    const float d = ok ? v[u] : 0.0f;
+                    accf = fmaf(d, d, accf);
+                } else {
+                    const double d = (double)(ok ? v[u] : 0.0f);
+                    acc = fma(d, d, acc);
+                }
+            }
+        }
+    }
+    if (live) a.partial[(int64_t)pi * a.splits + split] = ACC32 ? (double)accf : acc;
+}
+
 template <int P, int U, int FMT, int LK, bool FROM_STATE, bool WIDE, bool ACC32 = false>
 __global__ __launch_bounds__(256) void k_fitness(FitLaunch a) {
-    fitness_body<P, U, FMT, LK, FROM_STATE, WIDE, ACC32>(a, blockIdx.x);
+    if constexpr (P == kWave) fitness_body_pl<U, FMT, LK, FROM_STATE, WIDE, ACC32>(a, blockIdx.x);
+    else fitness_body<P, U, FMT, LK, FROM_STATE, WIDE, ACC32>(a, blockIdx.x);
 }
 
 int fitness_blocks(const FitLaunch& L, int P) { return ((L.n + P - 1) / P + 3) / 4 * L.splits; }
@@ -426,6 +525,9 @@ static void launch_w(const FitLaunch& L, hipStream_t s) {
     else if (p == 4 && u == 4) launch_pu<4, 4, FMT, LK, false>(L, s);
     else if (p == 8 && u == 2) launch_pu<8, 2, FMT, LK, false>(L, s);
     else if (p == 8 && u == 4) launch_pu<8, 4, FMT, LK, false>(L, s);
+    else if (p == kWave && u == 4) launch_pu<kWave, 4, FMT, LK, false>(L, s);
+    else if (p == kWave && u == 8) launch_pu<kWave, 8, FMT, LK, false>(L, s);
+    else if (p == kWave && u == 16) launch_pu<kWave, 16, FMT, LK, false>(L, s);
     else launch_pu<4, 2, FMT, LK, false>(L, s);
 }
 
@@ -444,7 +546,8 @@ rose_status launch_fitness(const FitLaunch& L, hipStream_t s) {
 }
 
 bool fitness_shape_valid(int p, int u) {
-    return (p == 2 && u == 4) || (p == 4 && u == 2) || (p == 4 && u == 4) || (p == 8 && u == 2) || (p == 8 && u == 4);
+    return (p == 2 && u == 4) || (p == 4 && u == 2) || (p == 4 && u == 4) || (p == 8 && u == 2) ||
+           (p == 8 && u == 4) || (p == kWave && (u == 4 || u == 8 || u == 16));
 }
 
 void fitness_shape(int* p, int* u) {
@@ -460,8 +563,8 @@ void fitness_shape(int* p, int* u) {
 // lose with 16 (0.508 -> 0.577 ms) -- and raised further while the grid
 // holds fewer waves than the chip runs at once and each slice still has at
 // least ~4 lane-steps (256 points).
-int choose_splits(int32_t n_particles, int64_t max_points, int32_t fmt) {
-    const int64_t groups = (n_particles + g_shape_p - 1) / g_shape_p;
+int choose_splits(int32_t n_particles, int64_t max_points, int32_t fmt, int P) {
+    const int64_t groups = (n_particles + P - 1) / P;
     const int64_t target_waves = 256 * 4 * 8;  // CUs x SIMDs x waves per SIMD
     int64_t s = (fmt == ROSE_TSDF_F32 && max_points / 16 >= 512) ? 16 : 8;
     while (s < 64 && groups * s < target_waves && max_points / (2 * s) >= 256) s *= 2;
@@ -542,7 +645,7 @@ rose_status fitness_eval(const rose_tsdf* h, const float* pts_dev, int32_t m, co
     ROSE_REQUIRE(m >= 0 && m <= ROSE_MAX_IMAGE_PIXELS, ROSE_E_ARG, "fitness_eval: m = %d out of range", m);
     ROSE_REQUIRE(lk == ROSE_LOOKUP_NEAREST || lk == ROSE_LOOKUP_TRILINEAR, ROSE_E_ARG, "fitness_eval: bad lookup");
     rose_tsdf* hm = const_cast<rose_tsdf*>(h);
-    const int splits = choose_splits(n, m, h->g.fmt);
+    const int splits = choose_splits(n, m, h->g.fmt, g_shape_p);
     // scratch: packed points and partial sums, owned by the handle
     if (hm->cap_points < m) {
         if (hm->pts) ROSE_CHECK_HIP(hipFree(hm->pts));

@@ -280,7 +280,7 @@ static rose_status swarm_track(rose_tsdf* h, const float* depth_dev, const rose_
     const int su = (cam->width + p->stride - 1) / p->stride;
     const int sv = (cam->height + p->stride - 1) / p->stride;
     const int64_t mmax = (int64_t)su * sv;
-    const int splits = choose_splits(n, mmax, h->g.fmt);
+    const int splits = choose_splits(n, mmax, h->g.fmt, shape_particles());
     rose_status g;
     if ((g = grow(&h->pts, &h->cap_points, mmax)) != ROSE_OK) return g;
     if ((g = grow(&h->pts_o, &h->cap_points_o, mmax)) != ROSE_OK) return g;

@@ -412,7 +412,7 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_cam
         const int su = (cam->width + st_l - 1) / st_l;
         const int sv = (cam->height + st_l - 1) / st_l;
         const int64_t mmax = (int64_t)su * sv;
-        lv_splits[l] = choose_splits(lv_n[l], mmax, h->g.fmt);
+        lv_splits[l] = choose_splits(lv_n[l], mmax, h->g.fmt, shape_particles());
         lv_off[l + 1] = lv_off[l] + mmax;
         mmax_all = std::max(mmax_all, mmax);
         partial_need = std::max(partial_need, (int64_t)lv_n[l] * lv_splits[l]);
@@ -719,7 +719,7 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
         const int su = (cams[i].width + p.stride - 1) / p.stride;
         const int sv = (cams[i].height + p.stride - 1) / p.stride;
         const int64_t mmax = (int64_t)su * sv;
-        const int splits = choose_splits(n_particles[i], mmax, h->g.fmt);
+        const int splits = choose_splits(n_particles[i], mmax, h->g.fmt, P);
         if ((g = grow(&h->pts, &h->cap_points, mmax)) != ROSE_OK) break;
         if ((g = grow(&h->pts_o, &h->cap_points_o, mmax)) != ROSE_OK) break;
         if ((g = grow(&h->partial, &h->cap_partial, (int64_t)n_particles[i] * splits)) != ROSE_OK) break;
@@ -1065,7 +1065,7 @@ rose_status pso_batch_track_learned(rose_batch* b, const float* const* depth_dev
                      "pso_batch_track_learned: plain parameters of sequence %d need stride >= 1 and one level", i);
         const int64_t mmax = (int64_t)((b->cams[i].width + pp.stride - 1) / pp.stride) *
                              ((b->cams[i].height + pp.stride - 1) / pp.stride);
-        const int splits = choose_splits(n_plain[i], mmax, h->g.fmt);
+        const int splits = choose_splits(n_plain[i], mmax, h->g.fmt, shape_particles());
         rose_status g;
         if ((g = grow(&h->pts, &h->cap_points, mmax)) != ROSE_OK) return g;
         if ((g = grow(&h->pts_o, &h->cap_points_o, mmax)) != ROSE_OK) return g;

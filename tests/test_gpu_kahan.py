@@ -47,13 +47,18 @@ def _rot_err(qa, qb):
     return math.acos(np.clip((np.trace(Ra.T @ Rb) - 1) / 2, -1, 1))
 
 
+@pytest.mark.parametrize("shape", [(4, 2), (64, 8)])
 @pytest.mark.parametrize("lookup", [0, 1])
-def test_no_kahan_centre_fitness(R, orc, small, lookup):
+def test_no_kahan_centre_fitness(R, orc, small, lookup, shape):
     w, vol, psi, pst = small
     prev = w.fuse_poses[-1]
     st = R.track_state(prev.q, prev.t, [0.1] * 6)
-    g = R.track_frame(vol, dev(w.depth), w.K, dev(pst), R.track_params(max_iters=1, stride=w.stride, lookup=lookup,
-                                                                        flags=R.FLAG_NO_KAHAN), st)
+    try:
+        R.set_fitness_shape(*shape)
+        g = R.track_frame(vol, dev(w.depth), w.K, dev(pst),
+                          R.track_params(max_iters=1, stride=w.stride, lookup=lookup, flags=R.FLAG_NO_KAHAN), st)
+    finally:
+        R.set_fitness_shape(4, 2)
     Fg = -math.log(g["rho_centre"][0])
     pts = orc.unproject(w.depth, w.K, w.stride)
     # O_1 at c_0 = the previous pose: the identity motion, yet border points

@@ -30,8 +30,17 @@ def _volume(R, w):
     return vol
 
 
+@pytest.mark.parametrize("shape", [(4, 2), (64, 8)])
 @pytest.mark.parametrize("lookup", [0, 1])
-def test_schedule_order_does_not_change_results(R, orc, lookup):
+def test_schedule_order_does_not_change_results(R, orc, lookup, shape):
+    R.set_fitness_shape(*shape)
+    try:
+        _check_order(R, orc, lookup)
+    finally:
+        R.set_fitness_shape(4, 2)
+
+
+def _check_order(R, orc, lookup):
     w = synth.small_frame()
     pst, _ = orc.pst_sample(3000, 77)
     P = dev(pst)

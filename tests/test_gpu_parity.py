@@ -182,7 +182,7 @@ def test_voxel_indices_bit_exact(R, orc):
     assert np.array_equal(g, o)
 
 
-@pytest.mark.parametrize("shape", [(2, 4), (4, 4), (8, 2)])
+@pytest.mark.parametrize("shape", [(2, 4), (4, 4), (8, 2), (64, 4), (64, 8), (64, 16)])
 def test_fitness_shapes_parity(R, orc, shape):
     rng = np.random.default_rng(31)
     dims, vox, origin = (32, 24, 16), 0.04, (-0.64, -0.48, -0.32)
@@ -210,6 +210,31 @@ def test_fitness_parity(R, orc, fmt, lookup, n, m):
     T = _random_poses(rng, n)
     F, rho = R.fitness_eval(vol, dev(pts), dev(T), lookup)
     F, rho = host(F), host(rho)
+    Fo = orc.fitness(psi, vox, np.array(origin, np.float32), pts, T.astype(np.float64), lookup=lookup, prec=orc.F32)
+    assert _rel(F, Fo) <= 1e-5
+    assert _rel(rho, np.exp(-Fo)) <= 1e-5
+    if m == 0:
+        assert np.all(F == 1.0)
+
+
+@pytest.mark.parametrize("fmt", [0, 1, 2])
+@pytest.mark.parametrize("lookup", [0, 1])
+@pytest.mark.parametrize("n,m", [(1, 1), (63, 65), (64, 64), (65, 3001), (130, 63), (9, 0)])
+def test_fitness_parity_particle_per_lane(R, orc, fmt, lookup, n, m):
+    """The one-particle-per-lane shape (64, 8): particle counts around the
+    64-lane wave and point counts around the 64-point step and its 8-point
+    sub-steps, every storage format and lookup."""
+    rng = np.random.default_rng(300 + n + m)
+    dims, vox, origin = (32, 24, 16), 0.04, (-0.64, -0.48, -0.32)
+    vol, psi = _random_volume(R, rng, dims, vox, origin, fmt)
+    pts = rng.uniform(-0.7, 0.7, (m, 3)).astype(np.float32)
+    T = _random_poses(rng, n)
+    try:
+        R.set_fitness_shape(64, 8)
+        F, rho = R.fitness_eval(vol, dev(pts), dev(T), lookup)
+        F, rho = host(F), host(rho)
+    finally:
+        R.set_fitness_shape(4, 2)
     Fo = orc.fitness(psi, vox, np.array(origin, np.float32), pts, T.astype(np.float64), lookup=lookup, prec=orc.F32)
     assert _rel(F, Fo) <= 1e-5
     assert _rel(rho, np.exp(-Fo)) <= 1e-5
@@ -253,7 +278,7 @@ def test_fitness_full_size_sampled(R, orc, room_frame):
         Fo = orc.fitness(psi, seq.vox, seq.origin.astype(np.float32), pts, T[pick].astype(np.float64), lookup=lookup,
                          prec=orc.F32)
         # every launch shape the autotuner may pick for the bench
-        for shape in ((2, 4), (4, 2), (4, 4), (8, 2), (8, 4)):
+        for shape in ((2, 4), (4, 2), (4, 4), (8, 2), (8, 4), (64, 4), (64, 8), (64, 16)):
             try:
                 R.set_fitness_shape(*shape)
                 F, _ = R.fitness_eval(vol, dev(pts), dev(T), lookup)
@@ -365,7 +390,7 @@ def test_track_frame_corner_cases(R, orc, small_gpu):
     assert g["aps"] == [0] * 10 and list(st.pose.t) == list(prev.t)
 
 
-@pytest.mark.parametrize("shape", [(4, 2), (8, 4)])
+@pytest.mark.parametrize("shape", [(4, 2), (8, 4), (64, 8)])
 def test_track_full_size_first_iteration(R, orc, room_frame, shape):
     """Real size (512^3, 640x480, stride 4, 10240 particles): one iteration
     on the GPU equals the oracle's one iteration (APS size, centre, r_1), in
@@ -424,18 +449,19 @@ def test_track_frame_all_points_outside(R, orc, small_gpu):
     assert np.allclose(g["rho_centre"], np.exp(-1.0), rtol=1e-12)
 
 
-def test_track_full_size_three_iterations(R, orc, room_frame):
-    """Real size in the bench's launch configuration (shape 8x4, 16 point
-    slices, the particle schedule order): three iterations of frame 1 on the
-    GPU equal the oracle's three iterations (APS sizes, overlap counts,
-    centre, r_1)."""
+@pytest.mark.parametrize("shape", [(8, 4), (64, 8)])
+def test_track_full_size_three_iterations(R, orc, room_frame, shape):
+    """Real size in the bench's launch configurations (shape 8x4 with 16
+    point slices, 64x8 with 64; the particle schedule order): three
+    iterations of frame 1 on the GPU equal the oracle's three iterations
+    (APS sizes, overlap counts, centre, r_1)."""
     seq, vol, psi, _, _, d1 = room_frame
     pst, _ = orc.pst_sample(10240, 5600)
     prev = seq.poses[0]
     params = R.track_params(max_iters=3, stride=seq.stride)
     st = R.track_state(prev.q, prev.t, [0.55] * 6)
     try:
-        R.set_fitness_shape(8, 4)
+        R.set_fitness_shape(*shape)
         g = R.track_frame(vol, dev(d1), seq.K, dev(pst), params, st)
     finally:
         R.set_fitness_shape(4, 2)
