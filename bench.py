@@ -60,7 +60,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--render-workers", type=int, default=16)
     ap.add_argument("--shape", default=None, metavar="P,U",
-                    help="fitness launch shape (particles per wave, points per lane); default: timed per run")
+                    help="fitness launch shape (particles per wave, points per lane; 0,0: switching mode); "
+                         "default: timed per run")
+    ap.add_argument("--switch", default=None, metavar="VOX,DEPTH",
+                    help="switching-mode threshold: footprint in voxels, reference depth in metres")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="before warmup, run a float32 copy of MIB MiB three times (counter calibration)")
     return ap.parse_args()
@@ -210,6 +213,8 @@ def main():
     # shape (from a copy of the state), fitness launches timed
     from paper_2105_05600_amd import autotune
     nxt = 1 + args.warmup
+    if args.switch:
+        rose.set_fitness_switch(*(float(v) for v in args.switch.split(",")))
     if args.shape:
         shp = tuple(int(v) for v in args.shape.split(","))
         rose.set_fitness_shape(*shp)
@@ -266,7 +271,8 @@ def main():
                                     "integrate": prof["integrate_ms"] / args.steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_counter("traffic_bytes_per_launch", lookup, tuned["shape"]) if fmt == 0 else None,
-                     "kernel": "k_fitness", "avg_launch_ms": fit_ms, "evals_per_launch": fit_evals,
+                     "kernel": ("k_fitness, switched pair <8,4> / <64,8> (one does the work each iteration)"
+                                if tuple(tuned["shape"]) == (0, 0) else "k_fitness"), "avg_launch_ms": fit_ms, "evals_per_launch": fit_evals,
                      "bytes_per_eval": bytes_per_eval, "shape": list(tuned["shape"]),
                      "launch_ms_p10_median_p90": ([float(v) for v in np.percentile(launch_ms, [10, 50, 90])]
                                                   if len(launch_ms) else None),

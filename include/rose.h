@@ -496,11 +496,24 @@ rose_status rose_gemm_bf16(int32_t M, int32_t N, int32_t K, const float* A_dev, 
  * wavefront and points per lane per loop step.  Compiled shapes: (2, 4),
  * (4, 2) (default), (4, 4), (8, 2), (8, 4) -- points across the lanes, P
  * particles per wave -- and (64, 4), (64, 8), (64, 16) -- one particle per
- * lane, U points looked up per step; others give ROSE_E_UNSUPPORTED.  The
- * batched tracker runs (4, 2) when the current shape is not one of the
- * first five.  Results do not depend on the shape beyond binary64
- * summation order. */
+ * lane, U points looked up per step.  (0, 0) selects the switching mode:
+ * pso_track_frame and the learned tracker run (8, 4) while the search
+ * footprint (see rose_fitness_set_switch) is above the threshold and
+ * (64, 8) at or below it, decided on the device each iteration from the
+ * current axis lengths; every other caller runs (8, 4).  Other values give
+ * ROSE_E_UNSUPPORTED.  The batched tracker runs (4, 2) when the current
+ * shape is not one of (2, 4) ... (8, 4) or the switching mode's (8, 4).
+ * Results do not depend on the shape beyond binary64 summation order. */
 rose_status rose_fitness_set_shape(int32_t particles_per_wave, int32_t points_per_lane);
+
+/* Threshold of the switching mode (process-wide): the footprint of an
+ * iteration is max(r_4, r_5, r_6) + reference_depth_m * max(r_1, r_2, r_3)
+ * (translation axis lengths plus rotation axis lengths turned into a
+ * displacement at the reference depth), in units of the volume's voxel
+ * size; at or below footprint_voxels the particle-per-lane kernel runs.
+ * Defaults 48 voxels and 3 m.  ROSE_E_ARG unless 0 < footprint_voxels <= 1e6
+ * and 0 <= reference_depth_m <= 1e3.  Host-only. */
+rose_status rose_fitness_set_switch(float footprint_voxels, float reference_depth_m);
 
 /* ------------------------------------------------------- kernel timing */
 /* When enabled (process-wide), pso_track_frame and tsdf_integrate bracket

@@ -19,6 +19,14 @@ from paper_2105_05600_amd import rose
 
 SHAPES = [(4, 2), (8, 2), (4, 4), (2, 4), (8, 4), (64, 4), (64, 8), (64, 16)]  # (64, U): one particle per lane
 BATCH_SHAPES = [(4, 2), (8, 2), (4, 4), (8, 4)]  # shapes the batched tracker supports
+# the tracker's candidates: the points-across shapes and the switching mode
+# (0, 0).  The fixed particle-per-lane shapes are left out: they win only on
+# iterations with a small search footprint and lose on wide ones, and one
+# timed frame does not show a sequence's mix of the two (on the room
+# workload a frame of small axis lengths timed 64x8 at 0.24 ms against 0.32
+# for the switching mode, while over 60 frames 64x8 averaged 0.79 ms per
+# step against 0.62); the switching mode uses that kernel exactly where it wins.
+TRACK_SHAPES = [s for s in SHAPES if s[0] != 64] + [(0, 0)]
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
 
 
@@ -75,7 +83,7 @@ def tune(vol, pts: torch.Tensor, T: torch.Tensor, lookup: int = 0, shapes=None, 
     return {"shape": best, "ms": ms, "cached": False, "key": key}
 
 
-PREFERRED = (8, 4)
+PREFERRED = (0, 0)  # the switching mode
 
 
 def tune_track(vol, depth: torch.Tensor, K, pst: torch.Tensor, params, state, shapes=None, margin: float = 0.03) -> dict:
@@ -87,7 +95,7 @@ def tune_track(vol, depth: torch.Tensor, K, pst: torch.Tensor, params, state, sh
     so that near-ties (8x2 and 8x4 differ by ~2 % on one frame) resolve the
     same way in every run.  `state` is not changed.  Returns {"shape", "ms",
     "cached"}."""
-    shapes = shapes or SHAPES
+    shapes = shapes or TRACK_SHAPES
     ms = {}
     rose.profile_enable(True)
     try:

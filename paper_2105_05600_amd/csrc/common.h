@@ -353,6 +353,11 @@ struct FitLaunch {
     int32_t lookup;
     int32_t shape_p, shape_u;  // particles per wave, points per lane per step
     int32_t acc32;             // 1: plain binary32 sums (ROSE_FLAG_NO_KAHAN), FROM_STATE binary32 volumes only
+    // mapping switch (FROM_STATE launches): side 1 runs only while the
+    // search footprint is at most pl_thr voxels, side 2 only above it; 0: always
+    int32_t pl_side;
+    float pl_thr;   // voxels
+    float pl_zref;  // metres: depth at which a rotation axis length is turned into a displacement
     double* partial;           // n x splits
 };
 rose_status launch_fitness(const FitLaunch& L, hipStream_t s);
@@ -364,6 +369,9 @@ rose_status particle_order(rose_tsdf* h, const float* pst_dev, int32_t n, hipStr
 int choose_splits(int32_t n_particles, int64_t max_points, int32_t fmt, int P);
 bool fitness_shape_valid(int p, int u);
 void fitness_shape(int* p, int* u);
+// the switching mode (rose_fitness_set_shape(0, 0)): fitness_shape then
+// reports the points-across shape and the PST tracker sets pl_thr / pl_zref
+bool fitness_switching(float* thr_vox, float* zref_m);
 // particles per wave of the current launch shape
 inline int shape_particles() {
     int p, u;

@@ -88,6 +88,20 @@ __device__ inline float wave_sum_f(float v) {
     return v;
 }
 
+// Mapping switch: the footprint of the search -- how far one point moves
+// across the particles -- is taken as the largest translation axis length
+// plus the largest rotation axis length times a reference depth, in voxels.
+// Both kernels of a switched launch evaluate this same expression on the
+// same device state, so exactly one of them does the work.
+__device__ inline bool switch_skips(const FitLaunch& a) {
+    if (a.pl_side == 0) return false;
+    const double* r = a.st->r;
+    const double rr = fmax(fmax(r[0], r[1]), r[2]);
+    const double rt = fmax(fmax(r[3], r[4]), r[5]);
+    const bool small = (rt + (double)a.pl_zref * rr) <= (double)a.pl_thr * (double)a.g.vox;
+    return small != (a.pl_side == 1);
+}
+
 template <int P, int U, int FMT, int LK, bool FROM_STATE, bool WIDE, bool ACC32 = false>
 __device__ void fitness_body(const FitLaunch& a, const int blk) {
     constexpr int kU = U;
@@ -107,7 +121,7 @@ __device__ void fitness_body(const FitLaunch& a, const int blk) {
     const int group = (blk / a.splits) * 4 + (threadIdx.x >> 6);
     const int p0 = group * P;
     if (p0 >= a.n) return;
-    if (FROM_STATE && a.st->stopped) return;
+    if (FROM_STATE && (a.st->stopped || switch_skips(a))) return;
     const int m = a.count_dev ? *a.count_dev : a.count;
 
     // particle transforms: lane l < P builds particle p0 + l
@@ -252,7 +266,7 @@ __device__ void fitness_body_pl(const FitLaunch& a, const int blk) {
     const int group = (blk / a.splits) * 4 + (threadIdx.x >> 6);
     const int p0 = group * kWave;
     if (p0 >= a.n) return;
-    if (FROM_STATE && a.st->stopped) return;
+    if (FROM_STATE && (a.st->stopped || switch_skips(a))) return;
     const int m = a.count_dev ? *a.count_dev : a.count;
 
     const bool live = p0 + lane < a.n;
@@ -537,10 +551,30 @@ static void launch_f(const FitLaunch& L, hipStream_t s) {
     else launch_w<FMT, ROSE_LOOKUP_NEAREST>(L, s);
 }
 
-rose_status launch_fitness(const FitLaunch& L, hipStream_t s) {
+static void launch_fmt(const FitLaunch& L, hipStream_t s) {
     if (L.g.fmt == ROSE_TSDF_F32) launch_f<ROSE_TSDF_F32>(L, s);
     else if (L.g.fmt == ROSE_TSDF_F16) launch_f<ROSE_TSDF_F16>(L, s);
     else launch_f<ROSE_TSDF_SN16>(L, s);
+}
+
+rose_status launch_fitness(const FitLaunch& L, hipStream_t s) {
+    const uint64_t bytes = (uint64_t)L.g.nx * L.g.ny * L.g.nz * (L.g.fmt == ROSE_TSDF_F32 ? 4u : 2u);
+    if (L.pl_thr > 0.0f && L.st && !L.T32 && bytes < (uint64_t(1) << 32)) {
+        // switched: the points-across kernel (the given shape) above the
+        // threshold, the particle-per-lane kernel at or below it; both
+        // write the same partial-sum slices
+        FitLaunch a = L, b = L;
+        a.pl_side = 2;
+        b.pl_side = 1;
+        b.shape_p = kWave;
+        b.shape_u = 8;
+        launch_fmt(a, s);
+        launch_fmt(b, s);
+    } else {
+        FitLaunch a = L;
+        a.pl_side = 0;
+        launch_fmt(a, s);
+    }
     ROSE_CHECK_HIP(hipGetLastError());
     return ROSE_OK;
 }
@@ -553,6 +587,24 @@ bool fitness_shape_valid(int p, int u) {
 void fitness_shape(int* p, int* u) {
     *p = g_shape_p;
     *u = g_shape_u;
+}
+
+// switching mode: the points-across shape (8, 4) while the search footprint
+// exceeds the threshold, one particle per lane (64, 8) at or below it.
+// Default threshold 48 voxels at a 3 m reference depth, measured on the
+// 640x480 room workload (1 cm voxels, 10240 particles): 8, 16, 32, 48, 64,
+// 96 voxels -> 0.709, 0.703, 0.618, 0.595, 0.632, 0.638 ms per fitness step
+// (fixed (8, 4): 0.707 ms, fixed (64, 8): 0.651 ms).  With one shared
+// footprint for all six axes the crossover sits above the one measured with
+// equal axis lengths (about 25 voxels): the largest axis overstates the
+// spread of the others.
+static bool g_switch = false;
+static float g_switch_vox = 48.0f, g_switch_zref = 3.0f;
+
+bool fitness_switching(float* thr_vox, float* zref_m) {
+    *thr_vox = g_switch ? g_switch_vox : 0.0f;
+    *zref_m = g_switch_zref;
+    return g_switch;
 }
 
 // Point slices: a multiple of the 8 XCDs (see k_fitness).  For binary32
@@ -698,10 +750,28 @@ rose_status fitness_voxel_indices(const rose_tsdf* h, const float* pts_dev, int3
 
 }  // extern "C"
 
+extern "C" rose_status rose_fitness_set_switch(float footprint_voxels, float reference_depth_m) {
+    clear_error();
+    ROSE_REQUIRE(footprint_voxels > 0.0f && footprint_voxels <= 1.0e6f && reference_depth_m >= 0.0f &&
+                     reference_depth_m <= 1.0e3f,
+                 ROSE_E_ARG, "rose_fitness_set_switch: threshold %g voxels / depth %g m out of range",
+                 (double)footprint_voxels, (double)reference_depth_m);
+    g_switch_vox = footprint_voxels;
+    g_switch_zref = reference_depth_m;
+    return ROSE_OK;
+}
+
 extern "C" rose_status rose_fitness_set_shape(int32_t particles_per_wave, int32_t points_per_lane) {
     clear_error();
+    if (particles_per_wave == 0 && points_per_lane == 0) {
+        g_switch = true;
+        g_shape_p = 8;
+        g_shape_u = 4;
+        return ROSE_OK;
+    }
     ROSE_REQUIRE(fitness_shape_valid(particles_per_wave, points_per_lane), ROSE_E_UNSUPPORTED,
                  "rose_fitness_set_shape: (%d, %d) is not a compiled shape", particles_per_wave, points_per_lane);
+    g_switch = false;
     g_shape_p = particles_per_wave;
     g_shape_u = points_per_lane;
     return ROSE_OK;

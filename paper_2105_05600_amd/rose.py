@@ -129,6 +129,7 @@ _sigs = {
     "fitness_voxel_indices": ([_P, _P, C.c_int32, _P, C.c_int32, _P, _S], C.c_int),
     "depth_unproject": ([_P, C.POINTER(Camera), C.c_int32, C.c_int32, _P, _P, _S], C.c_int),
     "rose_fitness_set_shape": ([C.c_int32, C.c_int32], C.c_int),
+    "rose_fitness_set_switch": ([C.c_float, C.c_float], C.c_int),
     "overlap_mask": ([_P, C.c_int32, C.POINTER(Pose), C.POINTER(Pose), C.POINTER(Camera), _P, _S], C.c_int),
     "pso_track_frame": ([_P, _P, C.POINTER(Camera), _P, C.c_int32, C.POINTER(TrackParams), C.POINTER(Pose), _P,
                          C.POINTER(TrackState), C.POINTER(TrackStats), _S], C.c_int),
@@ -611,6 +612,11 @@ class Mlp:
 
 def set_fitness_shape(particles_per_wave: int, points_per_lane: int):
     _check("rose_fitness_set_shape", _lib.rose_fitness_set_shape(int(particles_per_wave), int(points_per_lane)))
+
+
+def set_fitness_switch(footprint_voxels: float, reference_depth_m: float = 3.0):
+    """Threshold of the switching launch mode (set_fitness_shape(0, 0))."""
+    _check("rose_fitness_set_switch", _lib.rose_fitness_set_switch(float(footprint_voxels), float(reference_depth_m)))
 
 
 class Batch:

@@ -449,12 +449,12 @@ def test_track_frame_all_points_outside(R, orc, small_gpu):
     assert np.allclose(g["rho_centre"], np.exp(-1.0), rtol=1e-12)
 
 
-@pytest.mark.parametrize("shape", [(8, 4), (64, 8)])
+@pytest.mark.parametrize("shape", [(8, 4), (64, 8), (0, 0)])
 def test_track_full_size_three_iterations(R, orc, room_frame, shape):
     """Real size in the bench's launch configurations (shape 8x4 with 16
-    point slices, 64x8 with 64; the particle schedule order): three
-    iterations of frame 1 on the GPU equal the oracle's three iterations
-    (APS sizes, overlap counts, centre, r_1)."""
+    point slices, 64x8 with 64, the switching mode (0, 0); the particle
+    schedule order): three iterations of frame 1 on the GPU equal the
+    oracle's three iterations (APS sizes, overlap counts, centre, r_1)."""
     seq, vol, psi, _, _, d1 = room_frame
     pst, _ = orc.pst_sample(10240, 5600)
     prev = seq.poses[0]
@@ -468,6 +468,32 @@ def test_track_full_size_three_iterations(R, orc, room_frame, shape):
     o = orc.track_frame(psi, seq.vox, seq.origin, d1, seq.K, pst, prev.q, prev.t, np.full(6, 0.55), max_iters=3,
                         stride=seq.stride, prec=orc.F32)
     assert g["iters"] == o["iters"] == 3
+    assert list(g["aps"]) == list(o["aps"])
+    assert g["n_overlap_last"] == o["n_overlap_last"]
+    assert np.linalg.norm(np.array(g["t"]) - o["t"]) <= 1e-4
+    assert _rot_err(g["q"], o["q"]) <= 1e-4
+    assert np.allclose(g["r1"], o["r1"], rtol=1e-6)
+
+
+@pytest.mark.parametrize("r0", [0.002, 0.02])
+def test_track_switching_small_footprint(R, orc, room_frame, r0):
+    """The switching mode with small axis lengths, where the particle-per-lane
+    kernel does the work (a footprint of a few voxels), at real size: two
+    iterations of frame 1 equal the oracle's (APS sizes, overlap counts,
+    centre, r_1)."""
+    seq, vol, psi, _, _, d1 = room_frame
+    pst, _ = orc.pst_sample(10240, 5600)
+    prev = seq.poses[0]
+    params = R.track_params(max_iters=2, stride=seq.stride)
+    st = R.track_state(prev.q, prev.t, [r0] * 6)
+    try:
+        R.set_fitness_shape(0, 0)
+        g = R.track_frame(vol, dev(d1), seq.K, dev(pst), params, st)
+    finally:
+        R.set_fitness_shape(4, 2)
+    o = orc.track_frame(psi, seq.vox, seq.origin, d1, seq.K, pst, prev.q, prev.t, np.full(6, r0), max_iters=2,
+                        stride=seq.stride, prec=orc.F32)
+    assert g["iters"] == o["iters"]
     assert list(g["aps"]) == list(o["aps"])
     assert g["n_overlap_last"] == o["n_overlap_last"]
     assert np.linalg.norm(np.array(g["t"]) - o["t"]) <= 1e-4
