@@ -255,15 +255,21 @@ __device__ void fitness_body(const FitLaunch& a, const int blk) {
 // count on the room frames: ~4 lanes per 128-byte line at r = 0.03, ~13 at
 // 0.01, against ~1.1 when the lanes hold 64 neighbouring points).  U points
 // are looked up per step, their gathers in flight together.  Slices, XCD
-// mapping and the partial-sum layout are those of fitness_body; each lane
-// sums its particle's squares in point order.
+// mapping and the partial-sum layout are those of fitness_body, but a
+// workgroup takes one group of 64 particles and its 4 waves take the 4
+// quarters of the slice (4x the waves of one wave per group and slice, which
+// the points-across slice counts would leave too few); each lane sums its
+// particle's squares in point order, and the quarters are added in order
+// through LDS.  Every exit before the barrier is uniform over the workgroup.
 template <int U, int FMT, int LK, bool FROM_STATE, bool WIDE, bool ACC32 = false>
 __device__ void fitness_body_pl(const FitLaunch& a, const int blk) {
+    __shared__ double s_part[4][kWave];
     const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
     const int s8 = a.splits >> 3;
     const int r = blk % a.splits;
     const int split = (r & 7) * s8 + (r >> 3);
-    const int group = (blk / a.splits) * 4 + (threadIdx.x >> 6);
+    const int group = blk / a.splits;
     const int p0 = group * kWave;
     if (p0 >= a.n) return;
     if (FROM_STATE && (a.st->stopped || switch_skips(a))) return;
@@ -290,8 +296,11 @@ __device__ void fitness_body_pl(const FitLaunch& a, const int blk) {
     const Grid g = a.g;
     const VoxelTest ext{(float)g.nx, (float)g.ny, (float)g.nz};
     const int chunk = (m + a.splits - 1) / a.splits;
-    const int j0 = split * chunk;
-    const int j1 = min(m, j0 + chunk);
+    const int s0 = split * chunk;
+    const int s1 = min(m, s0 + chunk);
+    const int quarter = (max(s1 - s0, 0) + 3) / 4;
+    const int j0 = s0 + wave * quarter;
+    const int j1 = min(s1, j0 + quarter);
     double acc = 0.0;
     float accf = 0.0f;
     for (int jb = j0; jb < j1; jb += kWave) {
@@ -339,7 +348,22 @@ __device__ void fitness_body_pl(const FitLaunch& a, const int blk) {
             }
         }
     }
-    if (live) a.partial[(int64_t)pi * a.splits + split] = ACC32 ? (double)accf : acc;
+    s_part[wave][lane] = ACC32 ? (double)accf : acc;
+    __syncthreads();
+    if (wave == 0 && live) {
+        double sum;
+        if constexpr (ACC32) {
+            float f = (float)s_part[0][lane];
+#pragma unroll
+            for (int w = 1; w < 4; ++w) f += (float)s_part[w][lane];
+            sum = (double)f;
+        } else {
+            sum = s_part[0][lane];
+#pragma unroll
+            for (int w = 1; w < 4; ++w) sum += s_part[w][lane];
+        }
+        a.partial[(int64_t)pi * a.splits + split] = sum;
+    }
 }
 
 template <int P, int U, int FMT, int LK, bool FROM_STATE, bool WIDE, bool ACC32 = false>
@@ -348,7 +372,12 @@ __global__ __launch_bounds__(256) void k_fitness(FitLaunch a) {
     else fitness_body<P, U, FMT, LK, FROM_STATE, WIDE, ACC32>(a, blockIdx.x);
 }
 
-int fitness_blocks(const FitLaunch& L, int P) { return ((L.n + P - 1) / P + 3) / 4 * L.splits; }
+// workgroups of a launch: 4 particle groups per workgroup (points across the
+// lanes) or one (one particle per lane, its 4 waves splitting the slice)
+int fitness_blocks(const FitLaunch& L, int P) {
+    const int groups = (L.n + P - 1) / P;
+    return (P == kWave ? groups : (groups + 3) / 4) * L.splits;
+}
 
 __device__ inline int fitness_blocks_dev(const FitLaunch& L, int P) { return ((L.n + P - 1) / P + 3) / 4 * L.splits; }
 
@@ -514,8 +543,7 @@ static int g_shape_p = 4, g_shape_u = 2;
 
 template <int P, int U, int FMT, int LK, bool WIDE>
 static void launch_pu(const FitLaunch& L, hipStream_t s) {
-    const int groups = (L.n + P - 1) / P;
-    const unsigned blocks = (unsigned)(((groups + 3) / 4) * L.splits);
+    const unsigned blocks = (unsigned)fitness_blocks(L, P);
     if (L.T32)
         hipLaunchKernelGGL((k_fitness<P, U, FMT, LK, false, WIDE>), dim3(blocks), dim3(256), 0, s, L);
     else if constexpr (FMT == ROSE_TSDF_F32 && !WIDE) {
