@@ -53,11 +53,17 @@ struct Grid {
     void* wgt;
 };
 
-// brick-major offset of voxel (i, j, k): brick index * 512 + in-brick offset
-// (brick counts per axis are <= 256, so the products fit 24-bit multiplies)
+// brick-major offset of voxel (i, j, k) inside the volume: brick index * 512
+// + in-brick offset.  Dimensions are at most 2048, so brick coordinates take
+// 8 bits and brick counts 9; extracting exactly those bits lets the compiler
+// see that every product fits a 24-bit multiply (v_mad_u32_u24; without the
+// bounds it emits 64-bit v_mad_u64_u32).  Callers pass in-volume indices or
+// discard the offset.
 __host__ __device__ inline uint32_t brick_offset(const Grid& g, uint32_t i, uint32_t j, uint32_t k) {
 #if defined(__HIP_DEVICE_COMPILE__)
-    const uint32_t b = __umul24(__umul24(k >> 3, (uint32_t)g.nby) + (j >> 3), (uint32_t)g.nbx) + (i >> 3);
+    const uint32_t nbx = (uint32_t)g.nbx & 0x1ffu, nby = (uint32_t)g.nby & 0x1ffu;
+    const uint32_t b = (__builtin_amdgcn_ubfe(k, 3, 8) * nby + __builtin_amdgcn_ubfe(j, 3, 8)) * nbx +
+                       __builtin_amdgcn_ubfe(i, 3, 8);
 #else
     const uint32_t b = ((k >> 3) * (uint32_t)g.nby + (j >> 3)) * (uint32_t)g.nbx + (i >> 3);
 #endif

@@ -304,7 +304,9 @@ __device__ void fitness_body_pl(const FitLaunch& a, const int blk) {
     double acc = 0.0;
     float accf = 0.0f;
     for (int jb = j0; jb < j1; jb += kWave) {
-        const int cnt = min(kWave, j1 - jb);  // wave-uniform, >= 1
+        // wave-uniform, >= 1; held in a scalar register so that the lane
+        // index of each broadcast below is scalar arithmetic
+        const int cnt = __builtin_amdgcn_readfirstlane(min(kWave, j1 - jb));
         const float4 xl = a.pts[jb + (lane < cnt ? lane : 0)];
         for (int u0 = 0; u0 < cnt; u0 += U) {
             float v[U];
