@@ -47,7 +47,7 @@ def _rot_err(qa, qb):
     return math.acos(np.clip((np.trace(Ra.T @ Rb) - 1) / 2, -1, 1))
 
 
-@pytest.mark.parametrize("shape", [(4, 2), (64, 8)])
+@pytest.mark.parametrize("shape", [(4, 2), (64, 8), (0, 0)])
 @pytest.mark.parametrize("lookup", [0, 1])
 def test_no_kahan_centre_fitness(R, orc, small, lookup, shape):
     w, vol, psi, pst = small

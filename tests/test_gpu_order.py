@@ -30,7 +30,7 @@ def _volume(R, w):
     return vol
 
 
-@pytest.mark.parametrize("shape", [(4, 2), (64, 8)])
+@pytest.mark.parametrize("shape", [(4, 2), (64, 8), (0, 0)])
 @pytest.mark.parametrize("lookup", [0, 1])
 def test_schedule_order_does_not_change_results(R, orc, lookup, shape):
     R.set_fitness_shape(*shape)
