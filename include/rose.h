@@ -501,8 +501,9 @@ rose_status rose_gemm_bf16(int32_t M, int32_t N, int32_t K, const float* A_dev, 
  * footprint (see rose_fitness_set_switch) is above the threshold and
  * (64, 8) at or below it, decided on the device each iteration from the
  * current axis lengths; every other caller runs (8, 4).  Other values give
- * ROSE_E_UNSUPPORTED.  The batched tracker runs (4, 2) when the current
- * shape is not one of (2, 4) ... (8, 4) or the switching mode's (8, 4).
+ * ROSE_E_UNSUPPORTED.  The batched tracker runs the current shape when it
+ * is (4, 2), (8, 2), (4, 4), (8, 4) or (64, 8) (the switching mode: its
+ * (8, 4)), else (4, 2).
  * Results do not depend on the shape beyond binary64 summation order. */
 rose_status rose_fitness_set_shape(int32_t particles_per_wave, int32_t points_per_lane);
 

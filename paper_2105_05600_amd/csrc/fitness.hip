@@ -381,7 +381,10 @@ int fitness_blocks(const FitLaunch& L, int P) {
     return (P == kWave ? groups : (groups + 3) / 4) * L.splits;
 }
 
-__device__ inline int fitness_blocks_dev(const FitLaunch& L, int P) { return ((L.n + P - 1) / P + 3) / 4 * L.splits; }
+__device__ inline int fitness_blocks_dev(const FitLaunch& L, int P) {
+    const int groups = (L.n + P - 1) / P;
+    return (P == kWave ? groups : (groups + 3) / 4) * L.splits;
+}
 
 // Persistent fitness over many tracked sequences of one storage format and
 // lookup (a batch launches one kernel per such group, so each kernel holds a
@@ -418,7 +421,10 @@ __global__ __launch_bounds__(256) void k_fitness_batch(const FitLaunch* __restri
         const FitLaunch L = seqs[lo];  // wave-uniform: scalar loads of read-only memory
         const int blk = w - begin[lo];
         if (blk >= fitness_blocks_dev(L, P)) continue;
-        fitness_body<P, U, FMT, LK, true, false>(L, blk);
+        // the particle-per-lane body synchronises its workgroup once; every
+        // branch above is uniform over the workgroup (one item per workgroup)
+        if constexpr (P == kWave) fitness_body_pl<U, FMT, LK, true, false>(L, blk);
+        else fitness_body<P, U, FMT, LK, true, false>(L, blk);
     }
 }
 
@@ -462,6 +468,7 @@ static int batch_grid_shape(int fmt, int lk, int requested) {
 // grid of the persistent batch launch for a group (host query; call outside
 // stream capture)
 int batch_grid(int P, int U, int fmt, int lk, int requested) {
+    if (P == kWave && U == 8) return batch_grid_shape<kWave, 8>(fmt, lk, requested);
     if (P == 8 && U == 4) return batch_grid_shape<8, 4>(fmt, lk, requested);
     if (P == 8 && U == 2) return batch_grid_shape<8, 2>(fmt, lk, requested);
     if (P == 4 && U == 4) return batch_grid_shape<4, 4>(fmt, lk, requested);
@@ -490,12 +497,15 @@ static void launch_batch_shape(const FitLaunch* seqs, const int* begin, int coun
 }
 
 bool batch_shape_valid(int P, int U) {
-    return (P == 4 && U == 2) || (P == 8 && U == 2) || (P == 4 && U == 4) || (P == 8 && U == 4);
+    return (P == 4 && U == 2) || (P == 8 && U == 2) || (P == 4 && U == 4) || (P == 8 && U == 4) ||
+           (P == kWave && U == 8);
 }
 
 rose_status launch_fitness_batch(const FitLaunch* seqs_dev, const int* begin_dev, int count, int base, int end,
                                  int grid, int P, int U, int fmt, int lk, int* ctr_dev, hipStream_t s) {
-    if (P == 8 && U == 4) launch_batch_shape<8, 4>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
+    if (P == kWave && U == 8)
+        launch_batch_shape<kWave, 8>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
+    else if (P == 8 && U == 4) launch_batch_shape<8, 4>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
     else if (P == 8 && U == 2) launch_batch_shape<8, 2>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
     else if (P == 4 && U == 4) launch_batch_shape<4, 4>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
     else launch_batch_shape<4, 2>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);

@@ -51,8 +51,17 @@ def _single(R, w, fmt, n, stride, steps, lookup=0):
     return out
 
 
+@pytest.mark.parametrize("shape", [(4, 2), (64, 8)])
 @pytest.mark.parametrize("use_graph", [False, True])
-def test_batch_equals_single_path(R, scenes, use_graph):
+def test_batch_equals_single_path(R, scenes, use_graph, shape):
+    R.set_fitness_shape(*shape)
+    try:
+        _batch_equals_single(R, scenes, use_graph)
+    finally:
+        R.set_fitness_shape(4, 2)
+
+
+def _batch_equals_single(R, scenes, use_graph):
     ws, fmts, ns, strides = scenes
     # frame steps: the tracked frame, then the same frame again (a second
     # graph replay with new inputs), then a frame with no valid depth
