@@ -600,11 +600,17 @@ static void launch_fmt(const FitLaunch& L, hipStream_t s) {
 rose_status launch_fitness(const FitLaunch& L, hipStream_t s) {
     const uint64_t bytes = (uint64_t)L.g.nx * L.g.ny * L.g.nz * (L.g.fmt == ROSE_TSDF_F32 ? 4u : 2u);
     if (L.pl_thr > 0.0f && L.st && !L.T32 && bytes < (uint64_t(1) << 32)) {
-        // switched: the points-across kernel (the given shape) above the
-        // threshold, the particle-per-lane kernel at or below it; both
-        // write the same partial-sum slices
+        // switched: the points-across kernel above the threshold (the given
+        // shape; 4x2 for trilinear lookups, whose 8 gathers per evaluation
+        // make deeper shapes register-bound: 1.80 ms for 4x2 against 2.80
+        // for 8x4 on a room frame), the particle-per-lane kernel at or below
+        // it; both write the same partial-sum slices
         FitLaunch a = L, b = L;
         a.pl_side = 2;
+        if (L.lookup == ROSE_LOOKUP_TRILINEAR) {
+            a.shape_p = 4;
+            a.shape_u = 2;
+        }
         b.pl_side = 1;
         b.shape_p = kWave;
         b.shape_u = 8;

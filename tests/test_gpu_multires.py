@@ -73,8 +73,9 @@ def test_multires_parity(R, orc, small, levels, flags):
     assert np.allclose(g["r1"], o["r1"], rtol=1e-6, atol=1e-9)
 
 
+@pytest.mark.parametrize("lookup", [0, 1])
 @pytest.mark.parametrize("thr", [1e-3, 48.0, 1e6])
-def test_multires_parity_switching(R, orc, small, thr):
+def test_multires_parity_switching(R, orc, small, thr, lookup):
     """The switching mode through a multi-resolution schedule (particle counts
     not multiples of 64): footprint thresholds that keep the points-across
     kernel working throughout (1e-3 voxels), the default, and one that keeps
@@ -83,7 +84,7 @@ def test_multires_parity_switching(R, orc, small, thr):
     w, vol, psi, pst = small
     levels = [(300, 4), (700, 3), (2048, 5)]
     prev = w.fuse_poses[-1]
-    params = R.track_params(max_iters=11, levels=levels)
+    params = R.track_params(max_iters=11, levels=levels, lookup=lookup)
     st = R.track_state(prev.q, prev.t, [0.1] * 6)
     try:
         R.set_fitness_shape(0, 0)
@@ -93,7 +94,7 @@ def test_multires_parity_switching(R, orc, small, thr):
         R.set_fitness_switch(48.0, 3.0)
         R.set_fitness_shape(4, 2)
     o = orc.track_frame(psi, w.vox, w.origin, w.depth, w.K, pst, prev.q, prev.t, np.full(6, 0.1), max_iters=11,
-                        levels=levels, prec=orc.F32)
+                        levels=levels, lookup=lookup, prec=orc.F32)
     assert g["iters"] == o["iters"] == 11
     assert list(g["aps"]) == list(o["aps"])
     assert np.linalg.norm(np.array(g["t"]) - o["t"]) <= 1e-4
