@@ -512,8 +512,11 @@ rose_status rose_fitness_set_shape(int32_t particles_per_wave, int32_t points_pe
  * (translation axis lengths plus rotation axis lengths turned into a
  * displacement at the reference depth), in units of the volume's voxel
  * size; at or below footprint_voxels the particle-per-lane kernel runs.
- * Defaults 48 voxels and 3 m.  ROSE_E_ARG unless 0 < footprint_voxels <= 1e6
- * and 0 <= reference_depth_m <= 1e3.  Host-only. */
+ * Defaults: 48 voxels for nearest lookups, 32 for trilinear ones, at 3 m;
+ * a call sets the threshold for both lookups; footprint_voxels = 0 restores
+ * the defaults (reference_depth_m ignored).  ROSE_E_ARG unless
+ * footprint_voxels is 0 or in (0, 1e6] with 0 <= reference_depth_m <= 1e3.
+ * Host-only. */
 rose_status rose_fitness_set_switch(float footprint_voxels, float reference_depth_m);
 
 /* ------------------------------------------------------- kernel timing */

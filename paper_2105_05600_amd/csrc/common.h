@@ -377,7 +377,7 @@ bool fitness_shape_valid(int p, int u);
 void fitness_shape(int* p, int* u);
 // the switching mode (rose_fitness_set_shape(0, 0)): fitness_shape then
 // reports the points-across shape and the PST tracker sets pl_thr / pl_zref
-bool fitness_switching(float* thr_vox, float* zref_m);
+bool fitness_switching(int lookup, float* thr_vox, float* zref_m);
 // particles per wave of the current launch shape
 inline int shape_particles() {
     int p, u;

@@ -458,7 +458,7 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_cam
     fl.partial = h->partial;
     fl.acc32 = (p->flags & ROSE_FLAG_NO_KAHAN) ? 1 : 0;
     fitness_shape(&fl.shape_p, &fl.shape_u);
-    fitness_switching(&fl.pl_thr, &fl.pl_zref);
+    fitness_switching(p->lookup, &fl.pl_thr, &fl.pl_zref);
 
     UpdateArgs ua;
     ua.st = h->st;

@@ -615,7 +615,8 @@ def set_fitness_shape(particles_per_wave: int, points_per_lane: int):
 
 
 def set_fitness_switch(footprint_voxels: float, reference_depth_m: float = 3.0):
-    """Threshold of the switching launch mode (set_fitness_shape(0, 0))."""
+    """Threshold of the switching launch mode (set_fitness_shape(0, 0));
+    footprint_voxels = 0 restores the defaults."""
     _check("rose_fitness_set_switch", _lib.rose_fitness_set_switch(float(footprint_voxels), float(reference_depth_m)))
 
 

@@ -147,16 +147,18 @@ def test_profile_launch_log_host_side(R):
 
 def test_fitness_shapes_host_side(R):
     """rose_fitness_set_shape accepts the compiled shapes and (0, 0) (the
-    switching mode) and refuses everything else with ROSE_E_UNSUPPORTED; no
-    device call is made."""
+    switching mode) and refuses everything else with ROSE_E_UNSUPPORTED;
+    rose_fitness_set_switch checks its range and restores its defaults with
+    a zero threshold; no device call is made."""
     lib = R._lib
     try:
         for p, u in [(2, 4), (4, 2), (4, 4), (8, 2), (8, 4), (64, 4), (64, 8), (64, 16), (0, 0)]:
             assert lib.rose_fitness_set_shape(p, u) == R.OK, (p, u)
         for p, u in [(64, 2), (64, 32), (16, 4), (1, 1), (0, 4), (-1, -1)]:
             assert lib.rose_fitness_set_shape(p, u) == R.E_UNSUPPORTED, (p, u)
-        for thr, z in [(0.0, 3.0), (-1.0, 3.0), (8.0, -0.5), (2e6, 3.0)]:
+        for thr, z in [(-1.0, 3.0), (8.0, -0.5), (2e6, 3.0)]:
             assert lib.rose_fitness_set_switch(thr, z) == R.E_ARG, (thr, z)
         R.set_fitness_switch(8.0, 3.0)
+        assert lib.rose_fitness_set_switch(0.0, 0.0) == R.OK  # the defaults
     finally:
         assert lib.rose_fitness_set_shape(4, 2) == R.OK

@@ -91,7 +91,7 @@ def test_multires_parity_switching(R, orc, small, thr, lookup):
         R.set_fitness_switch(thr, 3.0)
         g = R.track_frame(vol, dev(w.depth), w.K, dev(pst), params, st)
     finally:
-        R.set_fitness_switch(48.0, 3.0)
+        R.set_fitness_switch(0.0)
         R.set_fitness_shape(4, 2)
     o = orc.track_frame(psi, w.vox, w.origin, w.depth, w.K, pst, prev.q, prev.t, np.full(6, 0.1), max_iters=11,
                         levels=levels, lookup=lookup, prec=orc.F32)
