@@ -497,8 +497,9 @@ rose_status rose_gemm_bf16(int32_t M, int32_t N, int32_t K, const float* A_dev, 
  * (4, 2) (default), (4, 4), (8, 2), (8, 4) -- points across the lanes, P
  * particles per wave -- and (64, 4), (64, 8), (64, 16) -- one particle per
  * lane, U points looked up per step.  (0, 0) selects the switching mode:
- * pso_track_frame and the learned tracker run (8, 4) while the search
- * footprint (see rose_fitness_set_switch) is above the threshold and
+ * pso_track_frame and the learned tracker run (8, 4) ((4, 2) for trilinear
+ * lookups) while the search footprint (see rose_fitness_set_switch) is
+ * above the threshold and
  * (64, 8) at or below it, decided on the device each iteration from the
  * current axis lengths; every other caller runs (8, 4).  Other values give
  * ROSE_E_UNSUPPORTED.  The batched tracker runs the current shape when it
