@@ -66,8 +66,10 @@ typedef enum { ROSE_LOOKUP_NEAREST = 0, ROSE_LOOKUP_TRILINEAR = 1 } rose_lookup;
 #define ROSE_FLAG_ISO_ONLY 8
 #define ROSE_FLAG_ANISO_ONLY 16
 /* "No Kahan" of the TSDF-normalisation ablation (Sec. 5): each particle's
- * sum of psi^2 is taken directly in binary32 -- per lane a running fmaf sum
- * over its points, then a butterfly sum over the wavefront -- instead of in
+ * sum of psi^2 is taken directly in binary32 -- with points across the
+ * lanes, per lane a running fmaf sum over its points, then a butterfly sum
+ * over the wavefront; with one particle per lane, a running fmaf sum over
+ * each quarter of a slice, the four added in order -- instead of in
  * binary64 over exact squares; the 8-64 slice totals are still added in
  * binary64.  Binary32 volumes below 4 GB only (ROSE_E_UNSUPPORTED otherwise);
  * not supported by pso_batch_*. */
