@@ -1,8 +1,9 @@
 """ROSE_FLAG_NO_KAHAN ("No Kahan" of the Sec. 5 TSDF-normalisation ablation):
 plain binary32 sums of psi^2 on the GPU against the oracle's plain binary32
-sum.  The two add in different orders (lanes and a wavefront tree vs point
-order), so each is within the recursive-summation bound (m - 1) 2^-24 of the
-exact sum and they are compared within twice that, at the centre's fitness
+sum.  The two add in different orders (lanes and a wavefront tree, or with
+one particle per lane quarters of each slice, vs point order), so each is
+within the recursive-summation bound (m - 1) 2^-24 of the exact sum and they
+are compared within twice that, at the centre's fitness
 in iteration 1; whole frames agree within 5 mm / 0.5 degrees (different
 rounding can flip APS members of weight ~0).  Unsupported combinations are
 refused."""
