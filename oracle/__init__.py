@@ -36,8 +36,17 @@ Parity status per function (what pins it, tests/test_oracle_*.py):
 * pst_update         -- pinned: single-member APS reproduces that particle;
                         symmetric APS -> zero step; empty APS and
                         TSDF-not-built corner cases; permutation invariance.
-* track_frame        -- pinned: brute-force 6D grid search on a tiny scene;
-                        convergence to the true pose on the small frame.
+* track_frame        -- pinned: brute-force 6D grid search on a tiny scene
+                        within the paper's 20 iterations (both threshold
+                        readings); convergence to the true pose on the small
+                        frame; an independent replay of the loop through
+                        pst_update with the threshold carried as Eq. wafit
+                        reads (centre fitness at k = 1, then rho~ of the last
+                        non-empty iteration, unchanged across empty ones)
+                        equals it bit for bit.
+* set_threads        -- fitness over particle ranges and fusion over
+                        z-slices on host threads: equal bit for bit to one
+                        thread.
 * integrate          -- pinned: fronto-parallel plane closed form; fused
                         zero crossing vs analytic surface.
 * track_frame levels -- pinned: identical levels reproduce the single
@@ -112,10 +121,10 @@ def build(force: bool = True) -> str:
     """Compile rose_oracle.c into liboracle.so (gcc, -O2, no FMA contraction)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-pthread"]
         if _cpu_has_fma():
             cmd.append("-mfma")  # fmaf() inlines to the (correctly rounded) hardware instruction
-        cmd += ["-o", tmp, _SRC, "-lm"]
+        cmd += ["-o", tmp, _SRC, "-lm", "-lpthread"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -143,6 +152,8 @@ def _load():
                 build()
             lib = C.CDLL(_LIB)
             P = C.c_void_p
+            lib.orc_set_threads.argtypes = [C.c_int32]
+            lib.orc_get_threads.restype = C.c_int32
             lib.orc_philox4x64_10.argtypes = [P, P, P]
             lib.orc_pst_sample.argtypes = [C.c_int32, C.c_uint64, P]
             lib.orc_pst_sample.restype = C.c_int
@@ -169,7 +180,7 @@ def _load():
             lib.orc_track_frame.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_float, P, P, C.c_int32,
                                             C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float, P, C.c_int32,
                                             P, P, P, P, P, C.c_int32, C.POINTER(_TrackParams), P, P, P, P, P,
-                                            P, P, P, P]
+                                            P, P, P, P, P, P, P]
             lib.orc_track_frame.restype = C.c_int
             lib.orc_integrate.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32, C.c_float, P, C.c_float,
                                           C.c_float, P, C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float,
@@ -201,6 +212,40 @@ def _f64(a):
 
 
 # ----------------------------------------------------------------- wrappers
+def set_threads(n: int) -> None:
+    """Host threads of the oracle's fitness (contiguous particle ranges) and
+    fusion (z-slices); results do not depend on it.  Process-wide."""
+    _load().orc_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(_load().orc_get_threads())
+
+
+class threads:
+    """Context manager: run the enclosed oracle calls on n host threads."""
+
+    def __init__(self, n: int):
+        self.n = int(n)
+
+    def __enter__(self):
+        self.prev = get_threads()
+        set_threads(self.n)
+        return self
+
+    def __exit__(self, *exc):
+        set_threads(self.prev)
+        return False
+
+
+def host_threads() -> int:
+    """Threads this process may run on (its CPU affinity)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        return os.cpu_count() or 1
+
+
 def philox4x64_10(ctr, key) -> np.ndarray:
     lib = _load()
     c = np.ascontiguousarray(ctr, dtype=np.uint64)
@@ -353,15 +398,18 @@ def track_frame(psi, vox, origin, depth, K, pst, q_prev, t_prev, r_init, q_init=
     aps = np.zeros(32, dtype=np.int32)
     rho_it = np.zeros(32)
     npts, nov = np.zeros(1, dtype=np.int32), np.zeros(1, dtype=np.int32)
+    nov_it, rc_it, thr_it = np.zeros(32, dtype=np.int32), np.zeros(32), np.zeros(32)
     org = _f32(origin)
     rc = lib.orc_track_frame(_p(psi), nx, ny, nz, float(vox), _p(org), _p(depth), W, H, K.fx, K.fy, K.cx, K.cy,
                              _p(pst), len(pst), _p(q_prev), _p(t_prev), _p(q_init), _p(t_init), _p(r_init),
                              int(tsdf_built), C.byref(P), _p(q_out), _p(t_out), _p(r1), _p(rho), _p(iters),
-                             _p(aps), _p(rho_it), _p(npts), _p(nov))
+                             _p(aps), _p(rho_it), _p(npts), _p(nov), _p(nov_it), _p(rc_it), _p(thr_it))
     it = int(iters[0])
+    k = min(it, 32)
     return dict(status=int(rc), q=q_out, t=t_out, r1=r1, rho=float(rho[0]), iters=it,
-                aps=aps[:min(it, 32)].copy(), rho_iter=rho_it[:min(it, 32)].copy(), n_points=int(npts[0]),
-                n_overlap_last=int(nov[0]))
+                aps=aps[:k].copy(), rho_iter=rho_it[:k].copy(), n_points=int(npts[0]),
+                n_overlap_last=int(nov[0]), n_overlap=nov_it[:k].copy(), rho_centre=rc_it[:k].copy(),
+                thr=thr_it[:k].copy())
 
 
 def integrate(psi, wgt, vox, origin, mu, depth, K, q, t, w_max=128.0, prec: int = F32) -> int:

@@ -8,7 +8,11 @@
  * helper with the HIP library, and it includes nothing from it.
  *
  * Every function is a direct transcription of the definition it cites
- * (section / equation of the paper), in plain single-threaded loops.
+ * (section / equation of the paper), in plain loops.  Two of them may split
+ * their outer loop over host threads (orc_set_threads): the fitness over
+ * contiguous particle ranges and the fusion over z-slices of the volume.
+ * Each particle's (each voxel's) arithmetic and point order are unchanged,
+ * so the results do not depend on the thread count (pinned by the tests).
  *
  * Precision.  Two modes exist for the geometric steps whose floating-point
  * result decides an integer (which voxel, which pixel, inside or outside):
@@ -24,9 +28,60 @@
  * oracle/__init__.py and in the design notes.
  */
 #include <math.h>
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Host threads for the two loops that may be split (see the header).  One  */
+/* thread by default.                                                       */
+/* ------------------------------------------------------------------------ */
+#define ORC_MAX_THREADS 256
+static int g_threads = 1;
+
+void orc_set_threads(int32_t n) { g_threads = n < 1 ? 1 : (n > ORC_MAX_THREADS ? ORC_MAX_THREADS : n); }
+int32_t orc_get_threads(void) { return g_threads; }
+
+/* run fn(arg_t, t0, t1) for T contiguous ranges [t0, t1) of [0, n) */
+typedef void (*orc_range_fn)(void* arg, int64_t t0, int64_t t1);
+typedef struct {
+    orc_range_fn fn;
+    void* arg;
+    int64_t t0, t1;
+} orc_range_job;
+
+static void* orc_range_main(void* p) {
+    orc_range_job* j = (orc_range_job*)p;
+    j->fn(j->arg, j->t0, j->t1);
+    return NULL;
+}
+
+static void orc_parallel_ranges(orc_range_fn fn, void* arg, int64_t n) {
+    int64_t T = g_threads;
+    if (T > n) T = n;
+    if (T <= 1) {
+        fn(arg, 0, n);
+        return;
+    }
+    orc_range_job jobs[ORC_MAX_THREADS];
+    pthread_t tid[ORC_MAX_THREADS];
+    int started[ORC_MAX_THREADS];
+    for (int64_t t = 0; t < T; ++t) {
+        jobs[t].fn = fn;
+        jobs[t].arg = arg;
+        jobs[t].t0 = n * t / T;
+        jobs[t].t1 = n * (t + 1) / T;
+    }
+    /* threads 1..T-1 run beside the caller, which takes range 0; a thread  */
+    /* that cannot be started runs its range on the caller afterwards       */
+    for (int64_t t = 1; t < T; ++t) started[t] = pthread_create(&tid[t], NULL, orc_range_main, &jobs[t]) == 0;
+    fn(arg, jobs[0].t0, jobs[0].t1);
+    for (int64_t t = 1; t < T; ++t) {
+        if (started[t]) pthread_join(tid[t], NULL);
+        else fn(arg, jobs[t].t0, jobs[t].t1);
+    }
+}
 
 #define ORC_F64 0
 #define ORC_F32 1
@@ -492,40 +547,57 @@ static void neumaier_add(double* s, double* c, double v) {
 /* sum is taken directly in binary32 in point order, acc = fmaf(v, v, acc)  */
 /* with v rounded to binary32, i.e. one rounding per added term and no      */
 /* compensation; S = acc.                                                   */
-void orc_fitness_ex(const float* psi, int32_t nx, int32_t ny, int32_t nz, float vox, const float origin[3],
-                    const float* pts, int32_t m, const uint8_t* mask, const double* T, int32_t n, int32_t lk,
-                    int prec, int normalize, int plain32, double* F) {
-    orc_grid g = {psi, nx, ny, nz, (double)vox, {origin[0], origin[1], origin[2]}};
-    int32_t cnt = 0;
-    for (int32_t j = 0; j < m; ++j) cnt += (mask == NULL || mask[j]);
-    for (int32_t i = 0; i < n; ++i) {
-        const double* Ti = T + 12 * (size_t)i;
+typedef struct {
+    const orc_grid* g;
+    const float* pts;
+    int32_t m;
+    const uint8_t* mask;
+    const double* T;
+    int32_t lk, prec, normalize, plain32, cnt;
+    double* F;
+} orc_fitness_job;
+
+/* particles [i0, i1) of one orc_fitness_ex call */
+static void fitness_range(void* arg, int64_t i0, int64_t i1) {
+    const orc_fitness_job* a = (const orc_fitness_job*)arg;
+    for (int64_t i = i0; i < i1; ++i) {
+        const double* Ti = a->T + 12 * (size_t)i;
         float V32[12];
-        fold_voxel(&g, Ti, V32);
+        fold_voxel(a->g, Ti, V32);
         double s = 0.0, c = 0.0;
         float acc = 0.0f;
-        for (int32_t j = 0; j < m; ++j) {
-            if (mask != NULL && !mask[j]) continue;
+        for (int32_t j = 0; j < a->m; ++j) {
+            if (a->mask != NULL && !a->mask[j]) continue;
             double gv[3];
-            voxel_coord(&g, Ti, V32, pts + 3 * (size_t)j, prec, lk, gv);
+            voxel_coord(a->g, Ti, V32, a->pts + 3 * (size_t)j, a->prec, a->lk, gv);
             double v;
-            if (lk == ORC_LOOKUP_TRILINEAR) {
+            if (a->lk == ORC_LOOKUP_TRILINEAR) {
                 /* gv already holds h = g - 1/2; lookup() treats it as h */
-                v = lookup(&g, gv, ORC_LOOKUP_TRILINEAR);
+                v = lookup(a->g, gv, ORC_LOOKUP_TRILINEAR);
             } else {
-                v = lookup(&g, gv, ORC_LOOKUP_NEAREST);
+                v = lookup(a->g, gv, ORC_LOOKUP_NEAREST);
             }
-            if (plain32) {
+            if (a->plain32) {
                 const float vf = (float)v;
                 acc = fmaf(vf, vf, acc);
             } else {
                 neumaier_add(&s, &c, v * v);
             }
         }
-        double S = plain32 ? (double)acc : s + c;
-        if (!normalize) F[i] = S;
-        else F[i] = (cnt > 0) ? S / (double)cnt : 1.0;
+        double S = a->plain32 ? (double)acc : s + c;
+        if (!a->normalize) a->F[i] = S;
+        else a->F[i] = (a->cnt > 0) ? S / (double)a->cnt : 1.0;
     }
+}
+
+void orc_fitness_ex(const float* psi, int32_t nx, int32_t ny, int32_t nz, float vox, const float origin[3],
+                    const float* pts, int32_t m, const uint8_t* mask, const double* T, int32_t n, int32_t lk,
+                    int prec, int normalize, int plain32, double* F) {
+    orc_grid g = {psi, nx, ny, nz, (double)vox, {origin[0], origin[1], origin[2]}};
+    int32_t cnt = 0;
+    for (int32_t j = 0; j < m; ++j) cnt += (mask == NULL || mask[j]);
+    orc_fitness_job job = {&g, pts, m, mask, T, lk, prec, normalize, plain32, cnt, F};
+    orc_parallel_ranges(fitness_range, &job, (int64_t)(n > 0 ? n : 0));
 }
 
 void orc_fitness(const float* psi, int32_t nx, int32_t ny, int32_t nz, float vox, const float origin[3],
@@ -651,7 +723,9 @@ int orc_pst_update(const double* F, const float* pst, int32_t n, const double r_
 /* Outputs: final centre (pose of frame t), r_1 (axis lengths after the     */
 /* first iteration, carried to frame t+1), rho~ of the last non-empty       */
 /* iteration (rho_prev if none), iteration count, per-iteration APS sizes   */
-/* and rho~, point count, last overlap count.                               */
+/* and rho~, point count, last overlap count; optional (NULL: not written)  */
+/* per-iteration |O_k|, the centre's exact fitness exp(-F_0/tau) and the    */
+/* APS threshold used.                                                      */
 /* Returns 0, or -4 when the frame has no valid point.                      */
 /*                                                                          */
 /* Multi-resolution PST (Sec. 4 "Multi-resolution PST"; levels >= 2): the  */
@@ -677,7 +751,8 @@ int orc_track_frame(const float* psi, int32_t nx, int32_t ny, int32_t nz, float 
                     const double q_init[4], const double t_init[3], const double r_init[6], int32_t tsdf_built,
                     const orc_track_params* P, double q_out[4], double t_out[3], double r1_out[6],
                     double* rho_out, int32_t* iters_out, int32_t* aps_sizes, double* rho_iter,
-                    int32_t* n_points_out, int32_t* n_overlap_last) {
+                    int32_t* n_points_out, int32_t* n_overlap_last, int32_t* n_overlap_iter,
+                    double* rho_centre_iter, double* thr_iter) {
     const int32_t L = (P->levels > 1) ? P->levels : 1;
     if (L > ORC_MAX_LEVELS) return -1;
     int32_t lv_n[ORC_MAX_LEVELS], lv_m[ORC_MAX_LEVELS];
@@ -750,6 +825,9 @@ int orc_track_frame(const float* psi, int32_t nx, int32_t ny, int32_t nz, float 
         if (k - 1 < 32) {
             aps_sizes[k - 1] = aps;
             rho_iter[k - 1] = rt;
+            if (n_overlap_iter) n_overlap_iter[k - 1] = tsdf_built ? nO : 0;
+            if (rho_centre_iter) rho_centre_iter[k - 1] = centre;
+            if (thr_iter) thr_iter[k - 1] = thr_k;
         }
         memcpy(r, r_new, sizeof r);
         memcpy(qc, q_new, sizeof qc);
@@ -801,6 +879,77 @@ done:
 /*   F64: the same in binary64, stored rounded to binary32.                 */
 /* Returns the number of voxels updated.                                    */
 /* ------------------------------------------------------------------------ */
+typedef struct {
+    float *psi, *wgt;
+    int32_t nx, ny, nz;
+    float vox, mu, w_max;
+    const float* origin;
+    const float* depth;
+    int32_t W, H;
+    float fx, fy, cx, cy;
+    const double* R;
+    const double* t;
+    const float* A32;
+    int prec;
+    int64_t* updated; /* per z-slice */
+} orc_integrate_job;
+
+/* z-slices [k0, k1) of one orc_integrate call */
+static void integrate_range(void* arg, int64_t k0, int64_t k1) {
+    const orc_integrate_job* a = (const orc_integrate_job*)arg;
+    const int32_t nx = a->nx, ny = a->ny, W = a->W, H = a->H;
+    const float fx = a->fx, fy = a->fy, cx = a->cx, cy = a->cy, mu = a->mu;
+    const double vx = (double)a->vox;
+    for (int64_t k = k0; k < k1; ++k) {
+        int64_t updated = 0;
+        for (int32_t j = 0; j < ny; ++j)
+            for (int32_t i = 0; i < nx; ++i) {
+                size_t id = ((size_t)k * ny + j) * nx + i;
+                if (a->prec == ORC_F32) {
+                    float vi[3] = {(float)i, (float)j, (float)k};
+                    double o[3];
+                    xform_point(NULL, a->A32, vi, ORC_F32, o);
+                    float xc = (float)o[0], yc = (float)o[1], zc = (float)o[2];
+                    if (!(zc > 0.0f)) continue;
+                    float pu = floorf(fmaf(fx, xc / zc, cx) + 0.5f);
+                    float pv = floorf(fmaf(fy, yc / zc, cy) + 0.5f);
+                    if (!(pu >= 0.0f && pu < (float)W && pv >= 0.0f && pv < (float)H)) continue;
+                    float D = a->depth[(size_t)pv * W + (size_t)pu];
+                    if (!(D > 0.0f)) continue;
+                    float sdf = D - zc;
+                    if (sdf < -mu) continue;
+                    float d = fminf(1.0f, sdf / mu);
+                    float w0 = a->wgt[id];
+                    a->psi[id] = fmaf(w0, a->psi[id], d) / (w0 + 1.0f);
+                    a->wgt[id] = fminf(w0 + 1.0f, a->w_max);
+                } else {
+                    double X[3] = {a->origin[0] + (i + 0.5) * vx, a->origin[1] + (j + 0.5) * vx,
+                                   a->origin[2] + (k + 0.5) * vx};
+                    double xc[3];
+                    for (int r = 0; r < 3; ++r) {
+                        double s = 0.0;
+                        for (int c = 0; c < 3; ++c) s += a->R[3 * c + r] * (X[c] - a->t[c]);
+                        xc[r] = s;
+                    }
+                    if (!(xc[2] > 0.0)) continue;
+                    double pu = floor(fx * (xc[0] / xc[2]) + cx + 0.5);
+                    double pv = floor(fy * (xc[1] / xc[2]) + cy + 0.5);
+                    if (!(pu >= 0.0 && pu < (double)W && pv >= 0.0 && pv < (double)H)) continue;
+                    double D = a->depth[(size_t)pv * W + (size_t)pu];
+                    if (!(D > 0.0)) continue;
+                    double sdf = D - xc[2];
+                    if (sdf < -(double)mu) continue;
+                    double d = fmin(1.0, sdf / (double)mu);
+                    double w0 = a->wgt[id];
+                    a->psi[id] = (float)((w0 * (double)a->psi[id] + d) / (w0 + 1.0));
+                    a->wgt[id] = (float)fmin(w0 + 1.0, (double)a->w_max);
+                }
+                ++updated;
+            }
+        a->updated[k] = updated;
+    }
+}
+
 int64_t orc_integrate(float* psi, float* wgt, int32_t nx, int32_t ny, int32_t nz, float vox, const float origin[3],
                       float mu, float w_max, const float* depth, int32_t W, int32_t H, float fx, float fy, float cx,
                       float cy, const double q[4], const double t[3], int prec) {
@@ -817,51 +966,13 @@ int64_t orc_integrate(float* psi, float* wgt, int32_t nx, int32_t ny, int32_t nz
         A[4 * r + 3] = s;
     }
     round_xform(A, A32);
+    int64_t* per_slice = (int64_t*)calloc((size_t)(nz > 0 ? nz : 1), sizeof(int64_t));
+    orc_integrate_job job = {psi, wgt, nx, ny, nz, vox, mu, w_max, origin, depth, W, H,
+                             fx, fy, cx, cy, R, t, A32, prec, per_slice};
+    orc_parallel_ranges(integrate_range, &job, (int64_t)(nz > 0 ? nz : 0));
     int64_t updated = 0;
-    for (int32_t k = 0; k < nz; ++k)
-        for (int32_t j = 0; j < ny; ++j)
-            for (int32_t i = 0; i < nx; ++i) {
-                size_t id = ((size_t)k * ny + j) * nx + i;
-                if (prec == ORC_F32) {
-                    float vi[3] = {(float)i, (float)j, (float)k};
-                    double o[3];
-                    xform_point(A, A32, vi, ORC_F32, o);
-                    float xc = (float)o[0], yc = (float)o[1], zc = (float)o[2];
-                    if (!(zc > 0.0f)) continue;
-                    float pu = floorf(fmaf(fx, xc / zc, cx) + 0.5f);
-                    float pv = floorf(fmaf(fy, yc / zc, cy) + 0.5f);
-                    if (!(pu >= 0.0f && pu < (float)W && pv >= 0.0f && pv < (float)H)) continue;
-                    float D = depth[(size_t)pv * W + (size_t)pu];
-                    if (!(D > 0.0f)) continue;
-                    float sdf = D - zc;
-                    if (sdf < -mu) continue;
-                    float d = fminf(1.0f, sdf / mu);
-                    float w0 = wgt[id];
-                    psi[id] = fmaf(w0, psi[id], d) / (w0 + 1.0f);
-                    wgt[id] = fminf(w0 + 1.0f, w_max);
-                } else {
-                    double X[3] = {origin[0] + (i + 0.5) * vx, origin[1] + (j + 0.5) * vx, origin[2] + (k + 0.5) * vx};
-                    double xc[3];
-                    for (int r = 0; r < 3; ++r) {
-                        double s = 0.0;
-                        for (int c = 0; c < 3; ++c) s += R[3 * c + r] * (X[c] - t[c]);
-                        xc[r] = s;
-                    }
-                    if (!(xc[2] > 0.0)) continue;
-                    double pu = floor(fx * (xc[0] / xc[2]) + cx + 0.5);
-                    double pv = floor(fy * (xc[1] / xc[2]) + cy + 0.5);
-                    if (!(pu >= 0.0 && pu < (double)W && pv >= 0.0 && pv < (double)H)) continue;
-                    double D = depth[(size_t)pv * W + (size_t)pu];
-                    if (!(D > 0.0)) continue;
-                    double sdf = D - xc[2];
-                    if (sdf < -(double)mu) continue;
-                    double d = fmin(1.0, sdf / (double)mu);
-                    double w0 = wgt[id];
-                    psi[id] = (float)((w0 * (double)psi[id] + d) / (w0 + 1.0));
-                    wgt[id] = (float)fmin(w0 + 1.0, (double)w_max);
-                }
-                ++updated;
-            }
+    for (int32_t k = 0; k < nz; ++k) updated += per_slice[k];
+    free(per_slice);
     return updated;
 }
 

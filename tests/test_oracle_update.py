@@ -152,8 +152,8 @@ def test_brute_force_grid_agrees_with_search(orc):
     """Tiny scene: a 16^3 TSDF of a room corner and ~60 points.  A 7^6 grid
     (1 cm, 0.01 quaternion steps) around the true pose has its argmin at
     the true pose, and PST search from a 2 cm / 2 degree offset reaches an
-    objective no worse than the grid's second-best value (both APS
-    threshold readings)."""
+    objective no worse than the grid's second-best value within the paper's
+    20 iterations (both APS threshold readings)."""
     scene = synth.Scene(np.array([-0.2, -0.2, -0.2]), np.array([0.15, 0.17, 0.16]),
                         spheres=[synth.Sphere(np.array([0.05, -0.05, 0.1]), 0.06)])
     dims, vox, mu = (16, 16, 16), 0.025, 0.075
@@ -175,7 +175,9 @@ def test_brute_force_grid_agrees_with_search(orc):
     pst, _ = orc.pst_sample(1024, 5600)
     start = synth.Pose(synth.axis_angle([0, 1, 0], math.radians(2.0)) @ gt.R, gt.t + np.array([0.02, 0, 0]))
     second = np.partition(F, 1)[1]
-    for flags, iters in ((0, 30), (orc.CENTRE_THRESHOLD, 15)):
+    # both readings of the APS threshold within the paper's 20-iteration cap
+    # (Sec. 4 "Convergence criteria")
+    for flags, iters in ((0, 20), (orc.CENTRE_THRESHOLD, 20)):
         res = orc.track_frame(psi, vox, origin, depth, K, pst, start.q, start.t, np.full(6, 0.1), max_iters=iters,
                               stride=4, lookup=1, flags=flags)
         Tf = orc.pose_mat(res["q"], res["t"])[:3]
@@ -204,3 +206,78 @@ def test_rescaling_ablation_worked_example(orc, flag):
     empty = orc.pst_update([0.3, 0.5, 0.9], pst, np.full(6, 0.2), [1, 0, 0, 0], [0, 0, 0], flags=f)
     assert empty["aps"] == 0
     assert empty["r"] == pytest.approx(0.02 + 0.9 * 2 * (1 - math.exp(-0.3)) / math.sqrt(6), rel=1e-13)
+
+
+# ---------------------------------------------- the APS threshold, replayed
+def _replay(orc, psi, w, pst, r0, lookup, iters, rule):
+    """Alg. 1 for one frame, one iteration at a time, through the oracle's
+    single-iteration update (pst_update), with the APS threshold chosen here:
+      carry  -- Sec. 4: the fitness of s*_k is never evaluated and Eq. wafit
+                stands in for it, so the threshold of iteration k >= 2 is
+                rho~ of the last iteration whose APS was non-empty; at k = 1
+                (s*_0 = c_0) it is the centre's own fitness (template row 0);
+      centre -- the centre's exact fitness at every k;
+      reset  -- a slip: back to the centre's fitness after an empty APS."""
+    pts = orc.unproject(w.depth, w.K, w.stride, orc.F32)
+    prev = w.fuse_poses[-1]
+    Tprev = orc.pose_mat(prev.q, prev.t)
+    qc, tc, r = np.array(prev.q, float), np.array(prev.t, float), np.full(6, float(r0))
+    thr, r1, rho_last, empty_before = None, None, None, False
+    aps, rts = [], []
+    for k in range(1, iters + 1):
+        mask = orc.overlap(pts, orc.pose_mat(qc, tc), Tprev, w.K, orc.F32)
+        T = orc.particle_poses(qc, tc, r, pst)
+        F = orc.fitness(psi, w.vox, w.origin, pts, T, lookup=lookup, prec=orc.F32, mask=mask)
+        F = F.astype(np.float32).astype(np.float64)  # the tracker keeps F in binary32
+        centre = math.exp(-F[0])
+        if rule == "carry":
+            t_k = centre if k == 1 else thr
+        elif rule == "centre":
+            t_k = centre
+        else:
+            t_k = centre if (k == 1 or empty_before) else thr
+        out = orc.pst_update(F, pst, r, qc, tc, rho_thr=t_k)
+        thr = out["rho_tilde"] if out["aps"] > 0 else t_k
+        empty_before = out["aps"] == 0
+        aps.append(out["aps"])
+        rts.append(out["rho_tilde"])
+        if out["aps"] > 0 or rho_last is None:
+            rho_last = out["rho_tilde"]
+        qc, tc, r = out["q"], out["t"], out["r"]
+        if k == 1:
+            r1 = r.copy()
+    return dict(aps=aps, rho_iter=rts, q=qc, t=tc, r1=r1, rho=rho_last)
+
+
+@pytest.mark.parametrize("lookup,r0", [(0, 0.55), (1, 0.1)])
+def test_threshold_carry_replayed_exactly(orc, lookup, r0):
+    """orc_track_frame equals, bit for bit, an independent replay of its
+    loop whose APS threshold follows the Eq. wafit reading; the two inputs
+    exercise an empty APS before any non-empty one (r0 = 0.55: the
+    threshold stays the centre's fitness) and an empty APS after a
+    one-member APS followed by a non-empty one (r0 = 0.1, trilinear: the
+    carried rho~ survives the empty step).  The slips "reset to the centre
+    after an empty APS" and "centre every k" give different results on the
+    second input, so the replay tells them apart."""
+    w = synth.small_frame()
+    psi = synth.analytic_tsdf(w.scene, w.dims, w.vox, w.origin, w.mu)
+    pst, _ = orc.pst_sample(w.n_particles, w.pst_seed)
+    prev = w.fuse_poses[-1]
+    iters = 20
+    res = orc.track_frame(psi, w.vox, w.origin, w.depth, w.K, pst, prev.q, prev.t, np.full(6, r0),
+                          max_iters=iters, stride=w.stride, lookup=lookup)
+    rep = _replay(orc, psi, w, pst, r0, lookup, iters, "carry")
+    assert res["aps"].tolist() == rep["aps"]
+    assert res["rho_iter"].tolist() == rep["rho_iter"]
+    assert np.array_equal(res["q"], rep["q"]) and np.array_equal(res["t"], rep["t"])
+    assert np.array_equal(res["r1"], rep["r1"]) and res["rho"] == rep["rho"]
+    a = rep["aps"]
+    first_full = next(k for k, n in enumerate(a) if n > 0)
+    if r0 == 0.55:
+        assert a[0] == 0 and first_full == 1  # empty first, then a non-empty step
+    else:
+        # a one-member APS, then an empty one, then a non-empty one
+        assert any(a[k] == 1 and a[k + 1] == 0 and a[k + 2] > 0 for k in range(len(a) - 2))
+        for rule in ("reset", "centre"):
+            alt = _replay(orc, psi, w, pst, r0, lookup, iters, rule)
+            assert alt["aps"] != rep["aps"] or not np.array_equal(alt["t"], rep["t"])
