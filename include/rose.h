@@ -280,6 +280,7 @@ typedef struct {
     double rho_iter[ROSE_MAX_ITERS];   /* rho~ per iteration (rho of the centre when the APS is empty) */
     int32_t n_particles[ROSE_MAX_ITERS]; /* particles evaluated per iteration */
     double rho_centre[ROSE_MAX_ITERS];   /* exact rho of the centre c_{k-1} (particle 0) in iteration k */
+    double r_iter[ROSE_MAX_ITERS][6];    /* axis lengths r_{k-1} that scale the template in iteration k */
 } rose_track_stats;
 
 /* One frame of Alg. 1 (PFO with PST) on the device.
@@ -562,6 +563,20 @@ rose_status rose_profile_fitness_launches(float* ms_out, int64_t cap, int64_t* c
 rose_status rose_gather_peak(const float* buf_dev, int64_t buf_elems, int32_t region_lines, int32_t blocks,
                              int32_t iters, uint32_t seed, float* sink_dev, hipStream_t s);
 int32_t rose_gather_peak_loads_per_lane(void);
+
+/* L2 -> CU read bandwidth probe (the measured P_L2 of the fitness kernel's
+ * gather roofline, R_gather = P_L2 / bytes per TSDF element): `blocks`
+ * workgroups of 256 lanes (a positive multiple of 8) each sweep, `sweeps`
+ * times, one of 8 regions of region_f4 float4 values (a power of two in
+ * [1024, 2^24]; region b mod 8 for workgroup b, one per XCD) with coalesced
+ * 16-byte loads.  A region that fits the L2 (2 MiB) and exceeds a CU's L1
+ * makes every load after the first sweep an L2 hit.  Bytes read =
+ * blocks * sweeps * region_f4 * 16.  buf_dev: 8 * region_f4 * 4 floats,
+ * 16-byte aligned (E_SHAPE / E_ARG otherwise); sink_dev (blocks floats) is
+ * never written for finite contents.  Asynchronous on s.  Not part of the
+ * method. */
+rose_status rose_l2_read_peak(const float* buf_dev, int64_t buf_elems, int32_t region_f4, int32_t blocks,
+                              int32_t sweeps, float* sink_dev, hipStream_t s);
 
 #ifdef __cplusplus
 }

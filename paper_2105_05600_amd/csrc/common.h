@@ -255,6 +255,7 @@ struct DevState {
     int32_t n_overlap_iter[ROSE_MAX_ITERS];
     double rho_iter[ROSE_MAX_ITERS];
     double rho_centre[ROSE_MAX_ITERS];  // exact rho of c_{k-1} (particle 0) in iteration k
+    double r_iter[ROSE_MAX_ITERS][6];   // axis lengths r_{k-1} of iteration k
 };
 
 // per-frame inputs of one tracked sequence

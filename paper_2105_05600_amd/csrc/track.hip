@@ -218,6 +218,7 @@ __device__ void track_update_body(const UpdateArgs& a) {
         st->n_overlap_iter[k] = nO;
         st->rho_iter[k] = rt;
         st->rho_centre[k] = centre;
+        for (int d = 0; d < 6; ++d) st->r_iter[k][d] = r[d];
         st->k = k + 1;
         if (k == 0)
             for (int d = 0; d < 6; ++d) st->r1[d] = st->r[d];
@@ -520,6 +521,7 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_cam
             stats->n_overlap[k] = r.n_overlap_iter[k];
             stats->rho_iter[k] = r.rho_iter[k];
             stats->rho_centre[k] = r.rho_centre[k];
+            for (int d = 0; d < 6; ++d) stats->r_iter[k][d] = r.r_iter[k][d];
             stats->n_particles[k] = lv_n[k % L];
         }
     }
@@ -925,6 +927,7 @@ rose_status pso_batch_track(rose_batch* b, const float* const* depth_devs, const
                 stats[i].n_overlap[k] = r.n_overlap_iter[k];
                 stats[i].rho_iter[k] = r.rho_iter[k];
                 stats[i].rho_centre[k] = r.rho_centre[k];
+                for (int d = 0; d < 6; ++d) stats[i].r_iter[k][d] = r.r_iter[k][d];
                 stats[i].n_particles[k] = b->n[i];
             }
         }

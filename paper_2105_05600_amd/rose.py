@@ -62,7 +62,8 @@ class TrackStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("n_points", C.c_int32), ("n_overlap_last", C.c_int32),
                 ("status", C.c_int32), ("aps_size", C.c_int32 * MAX_ITERS),
                 ("n_overlap", C.c_int32 * MAX_ITERS), ("rho_iter", C.c_double * MAX_ITERS),
-                ("n_particles", C.c_int32 * MAX_ITERS), ("rho_centre", C.c_double * MAX_ITERS)]
+                ("n_particles", C.c_int32 * MAX_ITERS), ("rho_centre", C.c_double * MAX_ITERS),
+                ("r_iter", (C.c_double * 6) * MAX_ITERS)]
 
 
 class LearnedParams(C.Structure):
@@ -167,6 +168,7 @@ _sigs = {
     "pst_poisson": ([C.c_int32, C.c_uint64, C.c_double, C.c_int32, _P, _P, _P, _S], C.c_int),
     "rose_gather_peak": ([_P, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_uint32, _P, _S], C.c_int),
     "rose_gather_peak_loads_per_lane": ([], C.c_int32),
+    "rose_l2_read_peak": ([_P, C.c_int64, C.c_int32, C.c_int32, C.c_int32, _P, _S], C.c_int),
 }
 for _name, (_args, _res) in _sigs.items():
     _f = getattr(_lib, _name)
@@ -419,7 +421,7 @@ def track_frame(vol: Tsdf, depth: torch.Tensor, K, pst: torch.Tensor, params: Tr
     return dict(iters=it, n_points=stats.n_points, n_overlap_last=stats.n_overlap_last,
                 aps=list(stats.aps_size[:it]), n_overlap=list(stats.n_overlap[:it]),
                 rho_iter=list(stats.rho_iter[:it]), n_particles=list(stats.n_particles[:it]),
-                rho_centre=list(stats.rho_centre[:it]),
+                rho_centre=list(stats.rho_centre[:it]), r_iter=[list(stats.r_iter[k]) for k in range(it)],
                 q=list(state.pose.q), t=list(state.pose.t), r1=list(state.r), rho=state.rho)
 
 
@@ -507,6 +509,19 @@ def gather_peak(buf: torch.Tensor, region_lines: int, blocks: int, iters: int, s
                                                      int(iters), int(seed) & 0xFFFFFFFF, _ptr(sink),
                                                      _stream(stream)))
     return int(blocks) * 256 * int(iters) * int(_lib.rose_gather_peak_loads_per_lane())
+
+
+def l2_read_peak(buf: torch.Tensor, region_f4: int, blocks: int, sweeps: int, sink: torch.Tensor,
+                 stream=None) -> int:
+    """Enqueue the L2 -> CU read bandwidth probe (rose_l2_read_peak) on
+    `stream`; returns the number of bytes it reads."""
+    _dev(buf, torch.float32, "buf")
+    _dev(sink, torch.float32, "sink")
+    if sink.numel() < blocks:
+        raise ValueError("sink needs one float per workgroup")
+    _check("rose_l2_read_peak", _lib.rose_l2_read_peak(_ptr(buf), buf.numel(), int(region_f4), int(blocks),
+                                                       int(sweeps), _ptr(sink), _stream(stream)))
+    return int(blocks) * int(sweeps) * int(region_f4) * 16
 
 
 def profile_fitness_launches() -> np.ndarray:
