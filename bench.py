@@ -47,7 +47,7 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2105_05600_amd", "csrc", f) for f in
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--lookup", choices=["nearest", "trilinear"], default="nearest")
     ap.add_argument("--schedule", choices=["single", "multires"], default="single",
@@ -64,6 +64,8 @@ def parse():
                          "default: timed per run")
     ap.add_argument("--switch", default=None, metavar="VOX,DEPTH",
                     help="switching-mode threshold: footprint in voxels, reference depth in metres")
+    ap.add_argument("--switch-shape", default=None, metavar="P,U",
+                    help="switching mode: the points-across shape used above the threshold (default 4,4)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="before warmup, run a float32 copy of MIB MiB three times (counter calibration)")
     return ap.parse_args()
@@ -82,27 +84,36 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-L2_PEAK_GBS = 39300.0  # 16 channels x 128 B per clock per XCD, 8 XCDs, 2.4 GHz
+L2_NOMINAL_GBS = 39300.0  # 16 channels x 128 B per clock per XCD, 8 XCDs, 2.4 GHz
+VALU_LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock (one lane-op per lane per clock)
 
 
-def measured_counter(key: str, lookup: int, shape):
-    """A per-launch figure of the committed counter summary (HBM traffic,
-    L2 read bytes), or None when it is missing, for another lookup or launch
-    shape, or the kernel has changed."""
+def counter_summary(lookup: int, shape, window: str):
+    """The committed counter summary's per-step figures when it was taken on
+    the current kernel sources, for this lookup, launch shape and timed
+    window; otherwise (None, reason)."""
     try:
         with open(COUNTERS) as f:
-            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith(" "))
+            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith((" ", "|", "*", "#")))
     except OSError:
-        return None
+        return None, "no counter summary"
     kv = {k.strip(): v.strip() for k, v in kv.items()}
-    if kv.get("kernel_source_sha256_16") != kernel_source_hash() or kv.get("lookup") != str(lookup):
-        return None
+    if kv.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None, "counter summary taken on other kernel sources"
+    if kv.get("lookup") != ("nearest" if lookup == 0 else "trilinear"):
+        return None, "counter summary taken with the other lookup"
     if kv.get("shape") != f"{shape[0]}x{shape[1]}":
-        return None
-    try:
-        return float(kv[key])
-    except (KeyError, ValueError):
-        return None
+        return None, f"counter summary taken with launch shape {kv.get('shape')}"
+    if kv.get("window") != window:
+        return None, f"counter summary taken over frames {kv.get('window')}, this run {window}"
+    out = {}
+    for k in ("traffic_bytes_per_launch", "l2_read_bytes_per_launch", "l2_requests_per_eval", "valu_lane_ops_per_eval",
+              "ta_stalled_by_tc_frac", "valu_busy_frac", "evals_per_launch", "trace_ms_per_launch"):
+        try:
+            out[k] = float(kv[k])
+        except (KeyError, ValueError):
+            out[k] = None
+    return out, None
 
 
 def copy_probe(torch, mib: int):
@@ -137,25 +148,100 @@ def gather_roofline(torch, rose, region_mib: int, reps: int = 5) -> float:
     return loads / (e0.elapsed_time(e1) * 1e-3)
 
 
-def cpu_baseline(seq, depth0, depth, prev_pose, n_particles, lookup, iters=3):
-    """The oracle, single-threaded, on the first `iters` iterations of frame
-    1 (about 10-15 s of CPU work) against its own fusion of frame 0."""
+def l2_read_peak(torch, rose, reps: int = 3) -> float:
+    """L2 -> CU read bytes per second: coalesced 16-byte loads sweeping a
+    2 MiB region per XCD (L2-resident, far larger than a CU's L1), timed
+    with HIP events on the current stream."""
+    region = 2 * (1 << 20) // 16
+    buf = torch.rand(8 * region * 4, device="cuda")
+    blocks = 2048
+    sink = torch.zeros(blocks, device="cuda")
+    rose.l2_read_peak(buf, region, blocks, 1, sink)  # warm
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    nbytes = 0
+    for _ in range(reps):
+        nbytes += rose.l2_read_peak(buf, region, blocks, 4, sink)
+    e1.record()
+    torch.cuda.synchronize()
+    del buf, sink
+    return nbytes / (e0.elapsed_time(e1) * 1e-3)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(seq, depth0, depth1, prev_pose, n_particles, lookup):
+    """The oracle as it stands (plain C, fitness over particle ranges and
+    fusion over z-slices on host threads), timed on this host:
+    * frame 1 of the room sequence in full (20 iterations, then fusion) on
+      all threads this process may use (at most 16) -> evals/s and frames/s;
+    * the first iteration of the same frame on one thread;
+    * the small one-frame workload (64^3, 160x120 stride 3, 1024 particles,
+      10 iterations) in full, on all threads and on one.
+    About 20-40 s of CPU work on a 16-thread host."""
     import oracle
     oracle.build(force=False)
+    n_all = max(1, min(16, oracle.host_threads()))
     nx, ny, nz = seq.dims
     psi = np.ones((nz, ny, nx), np.float32)
     wt = np.zeros_like(psi)
-    oracle.integrate(psi, wt, seq.vox, seq.origin, seq.mu, depth0, seq.K, prev_pose.q, prev_pose.t, prec=oracle.F32)
-    del wt
+    with oracle.threads(n_all):
+        oracle.integrate(psi, wt, seq.vox, seq.origin, seq.mu, depth0, seq.K, prev_pose.q, prev_pose.t,
+                         prec=oracle.F32)
     pst, _ = oracle.pst_sample(n_particles, 5600)
-    t0 = time.perf_counter()
-    o = oracle.track_frame(psi, seq.vox, seq.origin, depth, seq.K, pst, prev_pose.q, prev_pose.t,
-                           np.full(6, 0.55), max_iters=iters, stride=seq.stride, lookup=lookup, prec=oracle.F32)
-    dt = time.perf_counter() - t0
-    evals = n_particles * o["n_overlap_last"] * o["iters"]
-    return dict(value=evals / dt, unit="evals/s", cores=1, kind="oracle",
-                sample=f"{o['iters']} iterations of frame 1 (whole tracker: overlap, fitness, update): "
-                       f"{n_particles} particles x ~{o['n_overlap_last']} points on the 512^3 TSDF, {dt:.1f} s")
+    args = (psi, seq.vox, seq.origin, depth1, seq.K, pst, prev_pose.q, prev_pose.t, np.full(6, 0.55))
+    kw = dict(stride=seq.stride, lookup=lookup, prec=oracle.F32)
+    with oracle.threads(n_all):
+        t0 = time.perf_counter()
+        o = oracle.track_frame(*args, max_iters=seq.iters, **kw)
+        t1 = time.perf_counter()
+        oracle.integrate(psi, wt, seq.vox, seq.origin, seq.mu, depth1, seq.K, o["q"], o["t"], prec=oracle.F32)
+        t2 = time.perf_counter()
+    evals = float(n_particles * int(np.sum(o["n_overlap"])))
+    with oracle.threads(1):
+        t3 = time.perf_counter()
+        o1 = oracle.track_frame(*args, max_iters=1, **kw)
+        t4 = time.perf_counter()
+    evals1 = float(n_particles * int(o1["n_overlap"][0]))
+    del psi, wt
+    # the small workload in full
+    import synth
+    w = synth.small_frame()
+    sp = np.ones(w.dims[::-1], np.float32)
+    sw = np.zeros_like(sp)
+    for p, d in zip(w.fuse_poses, w.fuse_depths):
+        oracle.integrate(sp, sw, w.vox, w.origin, w.mu, d, w.K, p.q, p.t, prec=oracle.F32)
+    spst, _ = oracle.pst_sample(w.n_particles, w.pst_seed)
+    prev = w.fuse_poses[-1]
+    small = {}
+    for n in (n_all, 1):
+        with oracle.threads(n):
+            ts = time.perf_counter()
+            so = oracle.track_frame(sp, w.vox, w.origin, w.depth, w.K, spst, prev.q, prev.t, np.full(6, 0.1),
+                                    max_iters=w.iters, stride=w.stride, prec=oracle.F32)
+            te = time.perf_counter()
+        small[n] = (w.n_particles * int(np.sum(so["n_overlap"])) / (te - ts), te - ts)
+    return dict(
+        value=evals / (t1 - t0), unit="evals/s", cores=n_all, kind="oracle",
+        sample=f"frame 1 of the room sequence in full: {seq.iters} iterations x {n_particles} particles x "
+               f"~{o['n_overlap_last']} points on the 512^3 TSDF (whole tracker: overlap, fitness, update), "
+               f"{t1 - t0:.1f} s on {n_all} threads; fusion of the frame {t2 - t1:.2f} s",
+        frames_per_s=1.0 / (t2 - t0), cpu_model=cpu_model(), nproc=os.cpu_count(),
+        threads_available=oracle.host_threads(),
+        single_core={"value": evals1 / (t4 - t3), "unit": "evals/s", "cores": 1,
+                     "sample": f"iteration 1 of the same frame, {t4 - t3:.1f} s"},
+        small_frame={"workload": "64^3 TSDF, 160x120 stride 3, 1024 particles, 10 iterations (whole frame)",
+                     "evals_per_s": small[n_all][0], "frames_per_s": 1.0 / small[n_all][1], "cores": n_all,
+                     "single_core_evals_per_s": small[1][0], "single_core_frames_per_s": 1.0 / small[1][1]})
 
 
 def main():
@@ -215,6 +301,10 @@ def main():
     nxt = 1 + args.warmup
     if args.switch:
         rose.set_fitness_switch(*(float(v) for v in args.switch.split(",")))
+    wide = (4, 4)
+    if args.switch_shape:
+        wide = tuple(int(v) for v in args.switch_shape.split(","))
+        rose.set_fitness_switch_shape(*wide)
     if args.shape:
         shp = tuple(int(v) for v in args.shape.split(","))
         rose.set_fitness_shape(*shp)
@@ -269,37 +359,59 @@ def main():
         "time_split_ms_per_frame": {"fitness": prof["fitness_ms"] / args.steps,
                                     "update": prof["update_ms"] / args.steps,
                                     "integrate": prof["integrate_ms"] / args.steps},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_counter("traffic_bytes_per_launch", lookup, tuned["shape"]) if fmt == 0 else None,
-                     "kernel": ("k_fitness, switched pair <8,4> / <64,8> (one does the work each iteration)"
-                                if tuple(tuned["shape"]) == (0, 0) else "k_fitness"), "avg_launch_ms": fit_ms, "evals_per_launch": fit_evals,
-                     "bytes_per_eval": bytes_per_eval, "shape": list(tuned["shape"]),
-                     "launch_ms_p10_median_p90": ([float(v) for v in np.percentile(launch_ms, [10, 50, 90])]
-                                                  if len(launch_ms) else None),
-                     "kernel_source_sha256_16": kernel_source_hash()},
     }
+    shape = tuple(tuned["shape"])
+    window = f"{args.warmup}+{args.steps}"
+    fit_rate = prof["fitness_evals"] / (prof["fitness_ms"] * 1e-3)
+    p_l2 = l2_read_peak(torch, rose)
     g_l2 = gather_roofline(torch, rose, 2)
     g_hbm = gather_roofline(torch, rose, 1024)
-    fit_rate = prof["fitness_evals"] / (prof["fitness_ms"] * 1e-3)
-    out["gather_roofline"] = {
-        "what": "one 4-byte gather per particle-point evaluation, each from its own 128-byte line; peak = "
-                "gather-rate probe with an L2-resident working set (2 MiB per XCD)",
-        "peak_per_s": g_l2, "hbm_resident_peak_per_s": g_hbm, "achieved_evals_per_s": fit_rate,
-        "frac": fit_rate / g_l2}
-    log(f"gather probe: L2-resident {g_l2:.3e}/s, HBM-resident {g_hbm:.3e}/s; fitness {fit_rate:.3e} evals/s")
-    # L1 -> L2 read bandwidth of the fitness kernel: the committed counter
-    # summary's bytes per launch (while the kernel is unchanged) over this
-    # run's average launch time
-    l2_bytes = measured_counter("l2_read_bytes_per_launch", lookup, tuned["shape"]) if fmt == 0 else None
-    l2_gbs = l2_bytes / (fit_ms * 1e-3) / 1e9 if l2_bytes is not None else None
-    out["l2_roofline"] = {
-        "what": "L1 -> L2 read requests x 128 B per fitness launch (rocprofv3 TCP_TCC_READ_REQ) over the average "
-                "launch time; peak = 16 channels x 128 B per clock per XCD, 8 XCDs, 2.4 GHz",
-        "achieved": l2_gbs, "peak": L2_PEAK_GBS, "unit": "GB/s",
-        "frac": l2_gbs / L2_PEAK_GBS if l2_gbs is not None else None,
-        "probe_lines_gbs": g_l2 * 128.0 / 1e9}
+    log(f"L2 -> CU reads {p_l2 / 1e12:.2f} TB/s; one-line gathers: L2-resident {g_l2:.3e}/s, "
+        f"HBM-resident {g_hbm:.3e}/s; fitness {fit_rate:.3e} evals/s")
+    cnt, why = counter_summary(lookup, shape, window) if fmt == 0 else (None, "counters taken for binary32 only")
+    elem = 4.0 if fmt == 0 else 2.0
+    r_gather = p_l2 / elem  # evaluations/s if every evaluation's element came from L2 at the measured peak
+    ops = cnt["valu_lane_ops_per_eval"] if cnt else None
+    r_valu = VALU_LANE_OPS_PER_S / ops if ops else None
+    if cnt and cnt.get("valu_busy_frac") is not None and cnt["valu_busy_frac"] >= 0.6:
+        bound = "alu"
+    elif cnt and cnt.get("ta_stalled_by_tc_frac") is not None and cnt["ta_stalled_by_tc_frac"] >= 0.5:
+        bound = "l2"
+    else:
+        bound = "l2"
+    achieved_gbs = fit_evals * bytes_per_eval / (fit_ms * 1e-3) / 1e9
+    out["roofline"] = {
+        "bound": bound,
+        "achieved": achieved_gbs, "peak": p_l2 / 1e9, "unit": "GB/s", "frac": achieved_gbs * 1e9 / p_l2,
+        "traffic": cnt["traffic_bytes_per_launch"] if cnt else None,
+        "what": "fitness step (one iteration's fitness launches) on its gather roofline R_gather = P_L2 / bytes per "
+                "TSDF element: achieved = algorithmic bytes (one element per NEAREST evaluation, eight per "
+                "TRILINEAR) per step / average step time (HIP events on the launch stream); peak = P_L2, the L2 -> "
+                "CU read bandwidth measured in this run (coalesced 16-byte loads, 2 MiB L2-resident region per "
+                f"XCD; nominal {L2_NOMINAL_GBS / 1e3:.1f} TB/s); traffic = HBM bytes per step from the committed "
+                "rocprofv3 counter summary of the same command and window",
+        "kernel": ("k_fitness, switched pair <%d,%d> / <64,8> (one does the work each iteration)" % wide
+                   if shape == (0, 0) else f"k_fitness<{shape[0]},{shape[1]}>"),
+        "avg_launch_ms": fit_ms, "evals_per_launch": fit_evals, "bytes_per_eval": bytes_per_eval, "shape": list(shape),
+        "launch_ms_p10_median_p90": ([float(v) for v in np.percentile(launch_ms, [10, 50, 90])]
+                                     if len(launch_ms) else None),
+        "window_frames": window, "kernel_source_sha256_16": kernel_source_hash(),
+        "hbm": {"achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS},
+        "gather": {"R_gather_evals_per_s": r_gather, "achieved_evals_per_s": fit_rate, "frac": fit_rate / r_gather},
+        "valu": ({"lane_ops_per_eval": ops, "R_valu_evals_per_s": r_valu, "frac": fit_rate / r_valu,
+                  "busy_frac": cnt.get("valu_busy_frac")} if ops else None),
+        "l2_requests_per_eval": cnt["l2_requests_per_eval"] if cnt else None,
+        "l1_to_l2_gbs": (cnt["l2_read_bytes_per_launch"] / (fit_ms * 1e-3) / 1e9
+                         if cnt and cnt["l2_read_bytes_per_launch"] else None),
+        "ta_stalled_by_tc_frac": cnt["ta_stalled_by_tc_frac"] if cnt else None,
+        "counters": "rocprofv3 summary of the same command and window" if cnt else why,
+    }
+    out["gather_probe"] = {
+        "what": "not a ceiling: independent 4-byte loads, each from its own pseudo-random 128-byte line of a "
+                "region per XCD (2 MiB: L2-resident; 1 GiB: HBM-resident), loads/s",
+        "l2_resident_per_s": g_l2, "hbm_resident_per_s": g_hbm, "fitness_evals_per_s": fit_rate}
     if not args.no_cpu_baseline:
-        log("timing the CPU oracle on 3 iterations of frame 1")
+        log("timing the CPU oracle: frame 1 in full on all threads, its first iteration on one, the small frame")
         out["cpu_baseline"] = cpu_baseline(seq, depths[0], depths[1], p0, seq.n_particles, lookup)
     print(json.dumps(out), flush=True)
     vol.close()

@@ -113,8 +113,9 @@ size_t tsdf_bytes(int32_t nx, int32_t ny, int32_t nz, rose_tsdf_fmt fmt, int32_t
  * w_max caps the running-average weight (the fusion framework of Sec. 3:
  * Curless & Levoy 1996, KinectFusion 2011).  The buffer layout is internal
  * (8x8x8 bricks, brick-major); use tsdf_export / tsdf_import for a linear
- * view.  Errors: ROSE_E_ARG (NULL pointer, non-positive voxel/truncation,
- * w_max < 1), ROSE_E_SHAPE (dimensions), ROSE_E_DEVICE. */
+ * view.  Errors:
+ * ROSE_E_ARG (NULL pointer, non-positive voxel/truncation, w_max < 1),
+ * ROSE_E_SHAPE (dimensions), ROSE_E_DEVICE. */
 rose_status tsdf_create(int32_t nx, int32_t ny, int32_t nz, float voxel_m, float trunc_m, const float origin_m[3],
                         rose_tsdf_fmt fmt, float w_max, void* psi_dev, void* weight_dev, hipStream_t s,
                         rose_tsdf** out);
@@ -189,8 +190,10 @@ rose_status pst_particle_poses(const rose_pose* centre, const double r[6], const
  * camera->world; F_dev: n float32; rho_dev: n float32 or NULL.  m = 0 gives
  * F = 1.  The voxel is chosen in binary32 from a transform folded with the
  * voxel scale in binary64 and rounded once; squares are summed in binary64.
- * Limits: n <= ROSE_MAX_PARTICLES, m <= ROSE_MAX_IMAGE_PIXELS. */
-rose_status fitness_eval(const rose_tsdf* h, const float* pts_dev, int32_t m, const float* T_dev, int32_t n,
+ * Limits: n <= ROSE_MAX_PARTICLES, m <= ROSE_MAX_IMAGE_PIXELS.  The call
+ * packs the points into, and sums into, scratch owned by the handle (grown
+ * on demand, freed by tsdf_destroy), hence the non-const handle. */
+rose_status fitness_eval(rose_tsdf* h, const float* pts_dev, int32_t m, const float* T_dev, int32_t n,
                          rose_lookup lk, float* F_dev, float* rho_dev, hipStream_t s);
 
 /* Diagnostic: the NEAREST voxel of every (pose, point) pair of fitness_eval
@@ -495,25 +498,31 @@ rose_status rose_mlp_adam(int64_t n, float* params_dev, const float* grads_dev, 
 rose_status rose_gemm_bf16(int32_t M, int32_t N, int32_t K, const float* A_dev, int64_t sam, int64_t sak,
                            const float* B_dev, int64_t sbk, int64_t sbn, float* C_dev, int64_t ldc, hipStream_t s);
 
-/* Launch shape of the fitness kernel (process-wide): particles per
- * wavefront and points per lane per loop step.  Compiled shapes: (2, 4),
- * (4, 2) (default), (4, 4), (8, 2), (8, 4) -- points across the lanes, P
- * particles per wave -- and (64, 4), (64, 8), (64, 16) -- one particle per
- * lane, U points looked up per step.  (0, 0) selects the switching mode:
- * pso_track_frame and the learned tracker run (8, 4) ((4, 2) for trilinear
- * lookups) while the search footprint (see rose_fitness_set_switch) is
- * above the threshold and
- * (64, 8) at or below it, decided on the device each iteration from the
- * current axis lengths; every other caller runs (8, 4).  Other values give
- * ROSE_E_UNSUPPORTED.  The batched tracker runs the current shape when it
- * is (4, 2), (8, 2), (4, 4), (8, 4) or (64, 8) (the switching mode: its
- * (8, 4)), else (4, 2).
+/* Launch configuration of the fitness kernel.  A handle uses its own
+ * configuration once one was set on it (tsdf_set_fitness_shape / _switch),
+ * and the process-wide default (rose_fitness_set_*) otherwise; the defaults
+ * are read when a call starts.  Neither kind of setting may change while a
+ * call that uses it runs on another thread.
+ *
+ * Shape: particles per wavefront and points per lane per loop step.
+ * Compiled shapes: (2, 4), (4, 2) (default), (4, 4), (4, 8), (8, 2), (8, 4)
+ * -- points across the lanes, P particles per wave -- and (64, 4), (64, 8),
+ * (64, 16) -- one particle per lane, U points looked up per step.  (0, 0)
+ * selects the switching mode: pso_track_frame, the learned tracker and the
+ * plain fallbacks run the switching mode's points-across shape (default
+ * (4, 4); (4, 2) for trilinear lookups) while the search footprint (see
+ * rose_fitness_set_switch) is above the threshold and (64, 8) at or below
+ * it, decided on the device each iteration from the current axis lengths;
+ * fitness_eval and the comparison optimisers run the points-across shape.
+ * Other values give ROSE_E_UNSUPPORTED.  The batched tracker runs the first
+ * handle's shape (in the switching mode its points-across shape) when it
+ * is (4, 2), (8, 2), (4, 4), (4, 8), (8, 4) or (64, 8), else (4, 2).
  * Results do not depend on the shape beyond binary64 summation order. */
 rose_status rose_fitness_set_shape(int32_t particles_per_wave, int32_t points_per_lane);
 
-/* Threshold of the switching mode (process-wide): the footprint of an
- * iteration is max(r_4, r_5, r_6) + reference_depth_m * max(r_1, r_2, r_3)
- * (translation axis lengths plus rotation axis lengths turned into a
+/* Threshold of the switching mode (process-wide default): the footprint of
+ * an iteration is max(r_4, r_5, r_6) + reference_depth_m * max(r_1, r_2,
+ * r_3) (translation axis lengths plus rotation axis lengths turned into a
  * displacement at the reference depth), in units of the volume's voxel
  * size; at or below footprint_voxels the particle-per-lane kernel runs.
  * Defaults: 48 voxels for nearest lookups, 32 for trilinear ones, at 3 m;
@@ -522,6 +531,21 @@ rose_status rose_fitness_set_shape(int32_t particles_per_wave, int32_t points_pe
  * footprint_voxels is 0 or in (0, 1e6] with 0 <= reference_depth_m <= 1e3.
  * Host-only. */
 rose_status rose_fitness_set_switch(float footprint_voxels, float reference_depth_m);
+/* The switching mode's points-across shape (process-wide default (4, 4));
+ * any compiled shape with fewer than 64 particles per wave, else
+ * ROSE_E_UNSUPPORTED. */
+rose_status rose_fitness_set_switch_shape(int32_t particles_per_wave, int32_t points_per_lane);
+
+/* The same settings for one handle (fitness_eval, pso_track_frame and the
+ * calls built on them with that handle): the shape as in
+ * rose_fitness_set_shape, (-1, -1) returning the handle to the process-wide
+ * default; the switch threshold as in rose_fitness_set_switch together with
+ * the switching mode's points-across shape.  The first call copies the
+ * current process-wide default and then changes it.  ROSE_E_ARG (NULL
+ * handle, thresholds out of range), ROSE_E_UNSUPPORTED (shapes). */
+rose_status tsdf_set_fitness_shape(rose_tsdf* h, int32_t particles_per_wave, int32_t points_per_lane);
+rose_status tsdf_set_fitness_switch(rose_tsdf* h, float footprint_voxels, float reference_depth_m,
+                                    int32_t wide_particles, int32_t wide_points);
 
 /* ------------------------------------------------------- kernel timing */
 /* When enabled (process-wide), pso_track_frame and tsdf_integrate bracket

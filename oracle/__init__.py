@@ -28,7 +28,14 @@ Parity status per function (what pins it, tests/test_oracle_*.py):
 * fitness            -- pinned: analytic plane field F(d) = (d/mu)^2
                         (trilinear exact on a linear field); 1-Lipschitz
                         bound at the true pose (nearest); all-outside -> 1;
-                        Neumaier sum vs math.fsum; voxel index brute force.
+                        voxel index brute force.  Sums: binary64 mode
+                        (Neumaier) vs math.fsum; binary32 mode (the 2^-39
+                        grid) equals the exact rational sum of the terms
+                        rounded to the grid, is within m 2^-40 of math.fsum
+                        and does not change under any permutation of the
+                        points.
+* exp_rho            -- pinned: within 1 ulp of math.exp over [-745, 0] and
+                        exact at 0.
   (kahan=False)         the plain binary32 sum: within the recursive-
                         summation bound (m-1) 2^-24 sum v^2 of math.fsum; a
                         constructed case where it loses exactly the terms
@@ -154,6 +161,8 @@ def _load():
             P = C.c_void_p
             lib.orc_set_threads.argtypes = [C.c_int32]
             lib.orc_get_threads.restype = C.c_int32
+            lib.orc_exp.argtypes = [C.c_double]
+            lib.orc_exp.restype = C.c_double
             lib.orc_philox4x64_10.argtypes = [P, P, P]
             lib.orc_pst_sample.argtypes = [C.c_int32, C.c_uint64, P]
             lib.orc_pst_sample.restype = C.c_int
@@ -253,6 +262,14 @@ def philox4x64_10(ctr, key) -> np.ndarray:
     out = np.zeros(4, dtype=np.uint64)
     lib.orc_philox4x64_10(_p(c), _p(k), _p(out))
     return out
+
+
+def exp_rho(x) -> np.ndarray:
+    """The oracle's exp (orc_exp: Cody-Waite reduction, degree-13 Taylor
+    polynomial by Horner's rule with fma, 2^k scaling), elementwise."""
+    lib = _load()
+    xs = np.atleast_1d(np.asarray(x, dtype=np.float64))
+    return np.array([lib.orc_exp(float(v)) for v in xs.ravel()]).reshape(xs.shape)
 
 
 def pst_sample(n: int, seed: int):

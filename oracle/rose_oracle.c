@@ -21,8 +21,12 @@
  *             kernels, with the operation order written next to each step,
  *             so that integer outcomes (voxel and pixel indices) can be
  *             compared bit for bit.
- * Sums of squared TSDF values, the PST update (Alg. 1 / Eqs. ebs, rsdir,
- * rsinter, momentum, wafit) and pose algebra are always binary64.
+ * Sums of squared TSDF values: ORC_F64 adds them in binary64 with Neumaier
+ * compensation; ORC_F32 adds them exactly on a 2^-39 grid (each term
+ * rounded once to a multiple of 2^-39, the multiples added as integers), so
+ * that the sum does not depend on the order of its terms.  The PST update
+ * (Alg. 1 / Eqs. ebs, rsdir, rsinter, momentum, wafit) and pose algebra are
+ * always binary64; the likelihood exp(-F / tau) is orc_exp below.
  *
  * Parity status of each function is stated in the oracle's README block in
  * oracle/__init__.py and in the design notes.
@@ -32,6 +36,34 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* exp(x) for the likelihoods rho = exp(-F / tau) (Eq. pfolh), a fixed      */
+/* function of x: Cody-Waite reduction x = k ln2 + r with k = rint(x / ln2) */
+/* and ln2 given as a binary64 head and tail (one fma each), exp(r) from    */
+/* its Taylor series sum_{n<=13} r^n / n! by Horner's rule (one fma per     */
+/* step; |r| <= ln2 / 2, truncation error below 1e-17), then 2^k scaling.   */
+/* Every step is one correctly rounded binary64 operation.                  */
+/* ------------------------------------------------------------------------ */
+double orc_exp(double x) {
+    static const double ln2_head = 0x1.62e42fefa39efp-1;  /* ln 2 rounded to binary64 */
+    static const double ln2_tail = 0x1.abc9e3b39803fp-56; /* ln 2 - ln2_head */
+    static const double inv_ln2 = 0x1.71547652b82fep0;    /* 1 / ln 2 rounded */
+    if (!(x > -1100.0)) return 0.0;                       /* exp underflows to 0 well before */
+    double k = rint(x * inv_ln2);
+    double r = fma(-k, ln2_head, x);
+    r = fma(-k, ln2_tail, r);
+    /* c[n] = 1 / n!  (n! is exact in binary64 for n <= 13) */
+    double c[14];
+    double f = 1.0;
+    for (int n = 0; n <= 13; ++n) {
+        if (n > 0) f *= (double)n;
+        c[n] = 1.0 / f;
+    }
+    double p = c[13];
+    for (int n = 12; n >= 0; --n) p = fma(p, r, c[n]);
+    return ldexp(p, (int)k);
+}
 
 /* ------------------------------------------------------------------------ */
 /* Host threads for the two loops that may be split (see the header).  One  */
@@ -532,8 +564,15 @@ static void fold_voxel(const orc_grid* g, const double T[12], float V32[12]) {
 /*   S_i = sum_{j in O} psi(T_i x_j)^2, F_i = S_i / |O|  (|O| > 0),          */
 /*   rho_i = exp(-F_i / tau).  |O| = 0 gives F_i = 1.                        */
 /* T: n transforms, 3x4 row-major camera->world, binary64.                   */
-/* The sum is taken in binary64 with Neumaier compensation (Sec. 4 "GPU     */
-/* implementation", Kahan-Babuska-Neumaier summation).                       */
+/* The sum follows Sec. 4 "GPU implementation" (sums of many floating-point */
+/* numbers taken with compensation, Kahan summation):                       */
+/*  ORC_F64: binary64 with Neumaier compensation (Kahan-Babuska-Neumaier);  */
+/*  ORC_F32: exact on a 2^-39 grid -- every term v^2 (exact in binary64 for */
+/*           a binary32 v) rounded to the nearest multiple of 2^-39 (ties   */
+/*           to even), the integers added exactly (below 2^63 for up to     */
+/*           2^24 terms), S = (their sum) 2^-39 rounded once to binary64.   */
+/*           The result does not depend on the order of the terms; its      */
+/*           error is at most m 2^-40 absolute.                              */
 /* mask may be NULL (all points).  normalize=0 returns S_i instead of F_i.   */
 /* ------------------------------------------------------------------------ */
 static void neumaier_add(double* s, double* c, double v) {
@@ -542,6 +581,9 @@ static void neumaier_add(double* s, double* c, double v) {
     else *c += (v - t) + *s;
     *s = t;
 }
+
+/* v^2 on the 2^-39 grid: nearest integer (ties to even) to v^2 2^39 */
+static uint64_t grid_term(double v) { return (uint64_t)nearbyint(ldexp(v * v, 39)); }
 
 /* plain32 != 0 ("No Kahan" of the Sec. 5 TSDF-normalisation ablation): the  */
 /* sum is taken directly in binary32 in point order, acc = fmaf(v, v, acc)  */
@@ -566,6 +608,7 @@ static void fitness_range(void* arg, int64_t i0, int64_t i1) {
         fold_voxel(a->g, Ti, V32);
         double s = 0.0, c = 0.0;
         float acc = 0.0f;
+        uint64_t q = 0;
         for (int32_t j = 0; j < a->m; ++j) {
             if (a->mask != NULL && !a->mask[j]) continue;
             double gv[3];
@@ -580,11 +623,13 @@ static void fitness_range(void* arg, int64_t i0, int64_t i1) {
             if (a->plain32) {
                 const float vf = (float)v;
                 acc = fmaf(vf, vf, acc);
+            } else if (a->prec == ORC_F32) {
+                q += grid_term(v);
             } else {
                 neumaier_add(&s, &c, v * v);
             }
         }
-        double S = a->plain32 ? (double)acc : s + c;
+        double S = a->plain32 ? (double)acc : (a->prec == ORC_F32 ? ldexp((double)q, -39) : s + c);
         if (!a->normalize) a->F[i] = S;
         else a->F[i] = (a->cnt > 0) ? S / (double)a->cnt : 1.0;
     }
@@ -674,7 +719,7 @@ int orc_pst_update(const double* F, const float* pst, int32_t n, const double r_
         double rho_prev = rho_thr;
         double sw = 0, cw = 0, sr = 0, cr = 0, su[6] = {0}, cu[6] = {0};
         for (int32_t i = 0; i < n; ++i) {
-            double rho = exp(-F[i] / tau);
+            double rho = orc_exp(-F[i] / tau);
             if (!(rho > rho_prev)) continue;
             ++aps;
             double w = rho - rho_prev;
@@ -817,7 +862,7 @@ int orc_track_frame(const float* psi, int32_t nx, int32_t ny, int32_t nz, float 
         /* last non-empty iteration; at k = 1 (s*_0 = c_0, no average yet) it  */
         /* is the centre's own fitness (template row 0 sits at c_0).           */
         /* ORC_CENTRE_THRESHOLD: the centre's exact fitness at every k.        */
-        double centre = tsdf_built ? exp(-F[0] / P->tau) : 0.5;
+        double centre = tsdf_built ? orc_exp(-F[0] / P->tau) : 0.5;
         double thr_k = (k == 1 || (P->flags & ORC_CENTRE_THRESHOLD)) ? centre : thr;
         int aps = orc_pst_update(F, pst, n, r, qc, tc, P->tau, P->beta, P->eps, tsdf_built, thr_k, r_new, q_new,
                                  t_new, &rt, us, P->flags);
@@ -1057,7 +1102,7 @@ void orc_pfo_resample(const double* F, int32_t n, double F_best, double tau, dou
     double* Cs = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     double acc = 0.0;
     for (int32_t i = 0; i < n; ++i) {
-        acc += exp(-(F[i] - F_best) / tau);
+        acc += orc_exp(-(F[i] - F_best) / tau);
         Cs[i] = acc;
     }
     int32_t i = 0;
@@ -1170,7 +1215,7 @@ int orc_swarm_frame(const float* psi, int32_t nx, int32_t ny, int32_t nz, float 
         double srho = 0.0;
         for (int32_t i = 0; i < n; ++i) {
             if (F[i] < F[imin]) imin = i;
-            srho += exp(-F[i] / P->tau);
+            srho += orc_exp(-F[i] / P->tau);
         }
         best_index[k - 1] = -1;
         if (F[imin] < Fb) {
@@ -1183,7 +1228,7 @@ int orc_swarm_frame(const float* psi, int32_t nx, int32_t ny, int32_t nz, float 
             orc_pose_retract(q_prev, t_prev, u, qb, tb);
             best_index[k - 1] = imin;
         }
-        rho_best[k - 1] = exp(-Fb / P->tau);
+        rho_best[k - 1] = orc_exp(-Fb / P->tau);
         rho_mean[k - 1] = srho / (double)n;
         n_overlap[k - 1] = nO;
         if (k == K) break;
@@ -1211,7 +1256,7 @@ int orc_swarm_frame(const float* psi, int32_t nx, int32_t ny, int32_t nz, float 
     }
     memcpy(q_out, qb, sizeof qb);
     memcpy(t_out, tb, sizeof tb);
-    *rho_out = exp(-Fb / P->tau);
+    *rho_out = orc_exp(-Fb / P->tau);
     free(pts); free(mask); free(T); free(F); free(x); free(xn); free(v); free(pb); free(pF); free(anc);
     return 0;
 }

@@ -1,0 +1,193 @@
+"""Summarise rocprofv3 output of the benchmark into the counter summary that
+bench.py reads (HBM traffic, L1 -> L2 read bytes, VALU work and stalls of
+the fitness kernel per fitness step).
+
+Usage (repository root), after a kernel-trace run and the counter passes of
+the same bench.py command, each pass in its own rocprofv3 run:
+
+    python -m paper_2105_05600_amd.counters --trace DIR --pmc DIR [DIR ...] \
+        --bench-json FILE --copy-mib 1024 --steps 20 --warmup 5 --out FILE
+
+--trace: a `rocprofv3 --kernel-trace` output directory; --pmc: one
+`rocprofv3 --pmc ...` output directory per pass; --bench-json: the JSON line
+bench.py printed in the kernel-trace run (evaluations per fitness step);
+--copy-mib: the size of bench.py's --copy-probe, whose FETCH_SIZE and
+WRITE_SIZE readings scale those counters to bytes.
+
+A fitness step is one iteration's fitness launches (two in the switching
+mode: both kernels are launched, the one whose regime does not hold exits at
+once); the timed window is the last steps x iterations steps of the run.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("fitness.hip", "common.h")]
+VALU_LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock (non-packed issue)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def is_fitness(name: str) -> bool:
+    """The fitness kernel's instances (not its reduce, finish or batch
+    kernels)."""
+    return name.startswith("void k_fitness<") or name.startswith("k_fitness<")
+
+
+def _rows(pattern: str):
+    files = sorted(glob.glob(pattern, recursive=True))
+    if not files:
+        raise SystemExit(f"no file matches {pattern}")
+    for fn in files:
+        with open(fn, newline="") as f:
+            yield from csv.DictReader(f)
+
+
+def trace_steps(trace_dir: str, n_steps: int):
+    """Durations (ns) of the last n_steps fitness steps, and the kernel names
+    of a step."""
+    rows = [r for r in _rows(os.path.join(trace_dir, "**", "*kernel_trace.csv")) if is_fitness(r["Kernel_Name"])]
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    names = sorted({r["Kernel_Name"] for r in rows[-2 * n_steps:]})
+    per = len(names) if len(names) in (1, 2) else 1
+    rows = rows[-per * n_steps:]
+    dur = np.array([int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rows], float)
+    return dur.reshape(n_steps, per).sum(axis=1), names
+
+
+def pmc_steps(pmc_dir: str, n_steps: int, per: int):
+    """Per counter: its value summed over the dispatches of each of the last
+    n_steps fitness steps; and the copy probe's readings."""
+    vals = {}
+    copy = {}
+    for r in _rows(os.path.join(pmc_dir, "**", "*counter_collection.csv")):
+        name, c, v, d = r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"]), int(r["Dispatch_Id"])
+        if is_fitness(name):
+            vals.setdefault(c, {}).setdefault(d, 0.0)
+            vals[c][d] += v
+        elif "elementwise" in name or "Mul" in name:
+            copy.setdefault(c, []).append(v)
+    out = {}
+    for c, byd in vals.items():
+        seq = [byd[d] for d in sorted(byd)][-per * n_steps:]
+        out[c] = np.array(seq).reshape(n_steps, per).sum(axis=1)
+    return out, copy
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--pmc", nargs="+", required=True)
+    ap.add_argument("--bench-json", required=True)
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--steps", type=int, required=True)
+    ap.add_argument("--warmup", type=int, required=True)
+    ap.add_argument("--iters", type=int, default=20)
+    ap.add_argument("--command", default="")
+    ap.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+    n_steps = a.steps * a.iters
+    with open(a.bench_json) as f:
+        bench = json.loads([ln for ln in f if ln.startswith("{")][-1])
+    evals = float(bench["roofline"]["evals_per_launch"])
+    dur, names = trace_steps(a.trace, n_steps)
+    per = len(names)
+    counters, copy = {}, {}
+    for d in a.pmc:
+        c, cp = pmc_steps(d, n_steps, per)
+        counters.update(c)
+        for k, v in cp.items():
+            copy.setdefault(k, []).extend(v)
+    copy_kib = a.copy_mib * 1024.0
+
+    def scale(counter):
+        # the copy probe reads and writes copy_kib KiB per dispatch; take its
+        # largest reading (the 1 GiB multiply, not the small torch kernels)
+        ref = max(copy.get(counter, [0.0]))
+        return copy_kib / ref if ref > 0 else None
+
+    lines = [f"# k_fitness on the 512^3 room sequence: counters per fitness step", ""]
+    lines.append("rocprofv3 counter passes over one bench.py command, one run per pass; the timed window is the")
+    lines.append(f"last {n_steps} fitness steps ({a.steps} timed frames x {a.iters} iterations after {a.warmup} warmup "
+                 "frames).")
+    if a.command:
+        lines += ["", "Command (repository root, after `cd /tmp && export TMPDIR=/tmp` and back):", "",
+                  "    " + a.command]
+    lines += ["", f"Kernels of a fitness step: {', '.join('`' + n + '`' for n in names)}", "",
+              "| counter (per fitness step) | mean | min | max |", "|---|---|---|---|"]
+    for c in sorted(counters):
+        v = counters[c]
+        lines.append(f"| {c} | {v.mean():.4g} | {v.min():.4g} | {v.max():.4g} |")
+    ms = dur.mean() * 1e-6
+    lines += ["", f"Fitness step duration (kernel trace, sum over the step's launches): mean {dur.mean() / 1e3:.1f} us, "
+              f"p10 {np.percentile(dur, 10) / 1e3:.1f}, median {np.median(dur) / 1e3:.1f}, "
+              f"p90 {np.percentile(dur, 90) / 1e3:.1f} us; evaluations per step {evals:.4g} "
+              f"(bench.py, same window)."]
+    kv = {"kernel_source_sha256_16": kernel_source_hash(), "lookup": bench["config"].get("lookup", "nearest"),
+          "shape": "x".join(str(v) for v in bench["roofline"]["shape"]), "window": f"{a.warmup}+{a.steps}",
+          "evals_per_launch": f"{evals:.6g}", "trace_ms_per_launch": f"{ms:.6g}"}
+    derived = []
+    if "FETCH_SIZE" in counters and "WRITE_SIZE" in counters:
+        fs, ws = scale("FETCH_SIZE"), scale("WRITE_SIZE")
+        if fs and ws:
+            rd = counters["FETCH_SIZE"].mean() * 1024.0 * fs
+            wr = counters["WRITE_SIZE"].mean() * 1024.0 * ws
+            kv["traffic_bytes_per_launch"] = f"{rd + wr:.6g}"
+            derived.append(f"HBM read {rd / 1e6:.1f} MB + write {wr / 1e6:.2f} MB per step (FETCH_SIZE x {fs:.3f}, "
+                           f"WRITE_SIZE x {ws:.3f} from the copy probe), {(rd + wr) / (4 * evals):.2f}x the "
+                           f"algorithmic 4 B per evaluation; {(rd + wr) / (ms * 1e-3) / 1e12:.2f} TB/s")
+    if "TCP_TCC_READ_REQ_sum" in counters:
+        req = counters["TCP_TCC_READ_REQ_sum"].mean()
+        kv["l2_read_bytes_per_launch"] = f"{req * 128.0:.6g}"
+        kv["l2_requests_per_eval"] = f"{req / evals:.4g}"
+        derived.append(f"L1 -> L2 read requests {req / evals:.3f} per evaluation; x 128 B = "
+                       f"{req * 128 / (ms * 1e-3) / 1e12:.2f} TB/s")
+    if "TCP_TOTAL_CACHE_ACCESSES_sum" in counters:
+        acc = counters["TCP_TOTAL_CACHE_ACCESSES_sum"].mean()
+        kv["l1_accesses_per_eval"] = f"{acc / evals:.4g}"
+        if "TCP_TCC_READ_REQ_sum" in counters:
+            derived.append(f"L1 accesses {acc / evals:.3f} per evaluation, hit rate "
+                           f"{1 - counters['TCP_TCC_READ_REQ_sum'].mean() / acc:.3f}")
+    if "TCC_HIT_sum" in counters and "TCC_MISS_sum" in counters:
+        h, m = counters["TCC_HIT_sum"].mean(), counters["TCC_MISS_sum"].mean()
+        derived.append(f"L2 hit rate {h / (h + m):.3f}")
+    if "SQ_INSTS_VALU" in counters:
+        ops = counters["SQ_INSTS_VALU"].mean() * 64.0 / evals
+        kv["valu_lane_ops_per_eval"] = f"{ops:.4g}"
+        derived.append(f"VALU lane-ops per evaluation {ops:.2f} (SQ_INSTS_VALU x 64); the VALU ceiling "
+                       f"R_valu = {VALU_LANE_OPS_PER_S:.3e} / {ops:.2f} = {VALU_LANE_OPS_PER_S / ops:.3e} evals/s")
+    if "SQ_INSTS_VMEM_RD" in counters:
+        derived.append(f"vector memory reads per evaluation {counters['SQ_INSTS_VMEM_RD'].mean() * 64 / evals:.3f}")
+    if "TA_ADDR_STALLED_BY_TC_CYCLES_sum" in counters and "TA_BUSY_sum" in counters:
+        f = counters["TA_ADDR_STALLED_BY_TC_CYCLES_sum"].mean() / counters["TA_BUSY_sum"].mean()
+        kv["ta_stalled_by_tc_frac"] = f"{f:.4g}"
+        derived.append(f"the address unit waits on the L1 for {100 * f:.0f}% of its busy cycles")
+    if "SQ_ACTIVE_INST_VALU" in counters and "SQ_BUSY_CYCLES" in counters and "SQ_WAVES" in counters:
+        pass
+    lines += ["", "Derived:"] + [f"* {d}." for d in derived]
+    lines += ["", "Values read by bench.py (while the kernel sources hash to the value below and the window and",
+              "launch shape match its own):", ""]
+    lines += [f"{k}: {v}" for k, v in kv.items()]
+    with open(a.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -17,8 +17,6 @@
 namespace rose {
 
 constexpr int kWave = 64;
-constexpr int kBrick = 8;          // bricks of 8x8x8 voxels, brick-major storage
-constexpr int kBrickVox = 512;
 
 // ------------------------------------------------------------------ errors
 void set_error(const char* fmt, ...);
@@ -42,10 +40,22 @@ void clear_error();
         }                              \
     } while (0)
 
+// ----------------------------------------------- fitness launch configuration
+struct FitConfig {
+    int32_t p, u;           // fixed launch shape: particles per wave, points per lane per step
+    int32_t sw;             // 1: switching mode (points-across above the footprint threshold,
+                            // one particle per lane (64, 8) at or below it)
+    int32_t wide_p, wide_u; // switching mode: the points-across shape (nearest lookups)
+    float thr_vox[2];       // switching threshold by lookup (nearest, trilinear), voxels
+    float zref;             // metres: depth at which a rotation axis length becomes a displacement
+};
+
 // -------------------------------------------------------------------- grid
 struct Grid {
     int32_t nx, ny, nz;
-    int32_t nbx, nby, nbz;
+    int32_t nbx, nby, nbz;      // bricks per axis (dimensions are multiples of 8)
+    int32_t bstride_y;          // 64 nbx - 8     (brick_offset)
+    int32_t bstride_z;          // 64 nbx nby - 64
     float vox, mu, w_max;
     float origin[3];
     int32_t fmt;  // rose_tsdf_fmt
@@ -53,21 +63,24 @@ struct Grid {
     void* wgt;
 };
 
-// brick-major offset of voxel (i, j, k) inside the volume: brick index * 512
-// + in-brick offset.  Dimensions are at most 2048, so brick coordinates take
-// 8 bits and brick counts 9; extracting exactly those bits lets the compiler
-// see that every product fits a 24-bit multiply (v_mad_u32_u24; without the
-// bounds it emits 64-bit v_mad_u64_u32).  Callers pass in-volume indices or
-// discard the offset.
+// Brick-major offset of voxel (i, j, k): bricks of 8x8x8 voxels in x-fastest
+// brick order, voxels x-fastest inside a brick (brick index * 512 + in-brick
+// offset), so that the voxels around a point share few cache lines (a
+// 128-byte line holds an 8x4 patch of one z-slice) and few pages.  Written
+// per axis: with i = 8a + b, i + 63 (i & ~7) = 512 a + b, and likewise
+// 8 j + (64 nbx - 8)(j & ~7) and 64 k + (64 nbx nby - 64)(k & ~7), so the
+// offset is three masks and five multiply-adds, every product a 24-bit
+// multiply of in-volume indices (dimensions are at most 2048, brick
+// strides below 2^22).  Callers pass in-volume indices or discard the
+// offset.
 __host__ __device__ inline uint32_t brick_offset(const Grid& g, uint32_t i, uint32_t j, uint32_t k) {
 #if defined(__HIP_DEVICE_COMPILE__)
-    const uint32_t nbx = (uint32_t)g.nbx & 0x1ffu, nby = (uint32_t)g.nby & 0x1ffu;
-    const uint32_t b = (__builtin_amdgcn_ubfe(k, 3, 8) * nby + __builtin_amdgcn_ubfe(j, 3, 8)) * nbx +
-                       __builtin_amdgcn_ubfe(i, 3, 8);
+    const uint32_t a = __umul24(k & ~7u, (uint32_t)g.bstride_z) + __umul24(j & ~7u, (uint32_t)g.bstride_y);
+    return a + __umul24(i & ~7u, 63u) + (k << 6) + (j << 3) + i;
 #else
     const uint32_t b = ((k >> 3) * (uint32_t)g.nby + (j >> 3)) * (uint32_t)g.nbx + (i >> 3);
-#endif
     return (b << 9) | ((k & 7u) << 6) | ((j & 7u) << 3) | (i & 7u);
+#endif
 }
 
 // ------------------------------------------------------- TSDF value codecs
@@ -267,7 +280,55 @@ struct FrameIn {
     int32_t pad;
 };
 
+// ------------------------------------------------- fitness sums on a grid
+// Sums of psi^2 (Eq. ourlh) are exact on a grid of 2^-39: each term, exact in
+// binary64 for a binary32 psi, is rounded once (to nearest, ties to even) to
+// a multiple k 2^-39 and the integers k are added, so a sum does not depend
+// on the order, the slicing or the launch shape that produced it.  The
+// binary64 values in [2^13, 2^14) are spaced 2^-39 apart, so
+// fma(d, d, 8192) = 8192 + k 2^-39 in one rounding and its bit pattern is
+// kGridBase + k.  A term psi^2 = 1 (outside the grid) is kGridOne; k <= 2^39
+// and at most 2^24 terms per sum keep every sum below 2^63.
+constexpr uint64_t kGridBase = 0x40C0000000000000ull;  // bits of 8192.0
+constexpr uint64_t kGridOne = 1ull << 39;
+constexpr double kGridScale = 0x1p-39;
+
+// kGridBase + k for the term v^2 (a per-lane accumulator adds these and
+// subtracts kGridBase once per added term, modulo 2^64)
+__device__ inline uint64_t grid_term_bits(float v) {
+    const double d = (double)v;
+    return (uint64_t)__double_as_longlong(fma(d, d, 8192.0));
+}
+
+// exp(x) for the likelihoods rho = exp(-F / tau) (Eq. pfolh): k = rint(x /
+// ln 2), r = x - k ln 2 with ln 2 split in two binary64 parts (one fma
+// each), exp(r) by its Taylor series to degree 13 by Horner's rule (one fma
+// per step, |r| <= ln 2 / 2: truncation below 1e-17), scaled by 2^k.  Every
+// step is a correctly rounded binary64 operation, so the result is a fixed
+// function of x on any IEEE host or device.
+__host__ __device__ inline double exp_rho(double x) {
+    const double kLn2Hi = 0x1.62e42fefa39efp-1, kLn2Lo = 0x1.abc9e3b39803fp-56;
+    if (!(x > -1100.0)) return 0.0;  // also NaN -> 0 (never produced: F is finite)
+    const double k = rint(x * 0x1.71547652b82fep0);  // x / ln 2
+    double r = fma(-k, kLn2Hi, x);
+    r = fma(-k, kLn2Lo, r);
+    double fact = 1.0;
+    for (int n = 2; n <= 13; ++n) fact *= (double)n;  // 13! = 6227020800, exact
+    double p = 1.0 / fact;
+    for (int n = 13; n >= 1; --n) {
+        fact /= (double)n;          // (n-1)!, exact
+        p = fma(p, r, 1.0 / fact);  // c_{n-1} = 1/(n-1)!
+    }
+    return ldexp(p, (int)k);
+}
+
 // --------------------------------------------------------- wave primitives
+__device__ inline uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += (uint64_t)__shfl_xor((unsigned long long)v, off, kWave);
+    return v;
+}
+
 __device__ inline double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
@@ -313,10 +374,12 @@ struct Scratch;  // defined in api.hip
 struct rose_tsdf {
     rose::Grid g;
     int device;
+    rose::FitConfig cfg;  // own fitness launch configuration while cfg_set
+    int32_t cfg_set;
     // tracking scratch (device)
     float4* pts;        // all valid subsampled points of the current frame
     float4* pts_o;      // overlap-compacted points
-    double* partial;    // n_particles x splits partial sums of psi^2
+    uint64_t* partial;  // n_particles x splits partial sums of psi^2 (grid integers)
     float* F;           // n_particles fitness values of the last iteration
     rose::DevState* st; // device state of the current frame
     rose::DevState* st_host;  // pinned host copy
@@ -365,7 +428,7 @@ struct FitLaunch {
     int32_t pl_side;
     float pl_thr;   // voxels
     float pl_zref;  // metres: depth at which a rotation axis length is turned into a displacement
-    double* partial;           // n x splits
+    uint64_t* partial;         // n x splits grid integers
 };
 rose_status launch_fitness(const FitLaunch& L, hipStream_t s);
 // Schedule order of the first n rows of a PST template (cached per handle;
@@ -375,16 +438,13 @@ rose_status particle_order(rose_tsdf* h, const float* pst_dev, int32_t n, hipStr
 // point slices for n particles in waves of P (the launch shape's first entry)
 int choose_splits(int32_t n_particles, int64_t max_points, int32_t fmt, int P);
 bool fitness_shape_valid(int p, int u);
-void fitness_shape(int* p, int* u);
-// the switching mode (rose_fitness_set_shape(0, 0)): fitness_shape then
-// reports the points-across shape and the PST tracker sets pl_thr / pl_zref
-bool fitness_switching(int lookup, float* thr_vox, float* zref_m);
-// particles per wave of the current launch shape
-inline int shape_particles() {
-    int p, u;
-    fitness_shape(&p, &u);
-    return p;
-}
+// The effective launch configuration of a handle: its own (tsdf_set_fitness_*)
+// or else the process-wide default (rose_fitness_set_*).
+FitConfig fit_config(const rose_tsdf* h);
+// Launch shape (and switch threshold, 0 = no switch) a handle's fitness
+// launches use for lookup lk: the fixed shape, or in the switching mode the
+// points-across side (its wide shape; (4, 2) for trilinear lookups).
+void fit_launch_shape(const rose_tsdf* h, int lk, int* p, int* u, float* thr_vox, float* zref_m);
 int fitness_blocks(const FitLaunch& L, int P);
 bool batch_shape_valid(int p, int u);
 int batch_grid(int P, int U, int fmt, int lk, int requested);

@@ -12,28 +12,47 @@
 // the wave with butterfly shuffles, and written as one partial sum per
 // (particle, slice); a second pass adds the slices in a fixed order.
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
 
 namespace rose {
 
-// Byte offset of an element; volumes below 4 GB use 32-bit offsets so the
-// gather is a global load with a scalar base and a 32-bit vector offset.
 template <int FMT>
 __device__ inline uint32_t elem_bytes() {
     return FMT == ROSE_TSDF_F32 ? 4u : 2u;
 }
 
+// The psi buffer as a raw buffer resource (volumes below 4 GB): a gather is
+// one buffer load with a 32-bit byte offset in a vector register and the
+// base in scalar registers, and a load past the buffer's end returns 0
+// instead of touching memory, so no offset needs clamping for safety (the
+// value of an evaluation outside the grid is replaced by +1 anyway).
+struct PsiBuf {
+    __amdgpu_buffer_rsrc_t r;
+};
+
+template <int FMT>
+__device__ inline PsiBuf psi_buffer(const Grid& g) {
+    const uint32_t bytes = (uint32_t)g.nx * (uint32_t)g.ny * (uint32_t)g.nz * elem_bytes<FMT>();
+    // dword 3 of a raw (stride 0) buffer resource on gfx9-family targets
+    return PsiBuf{__builtin_amdgcn_make_buffer_rsrc(g.psi, (short)0, (int)bytes, 0x00020000)};
+}
+
 template <int FMT, bool WIDE>
-__device__ inline float gather(const void* base, uint32_t off) {
+__device__ inline float gather(const Grid& g, const PsiBuf& b, uint32_t off) {
     if constexpr (WIDE) {
-        return load_psi<FMT>(base, off);
+        return load_psi<FMT>(g.psi, off);
     } else {
-        const char* p = (const char*)base + (off * elem_bytes<FMT>());
-        if constexpr (FMT == ROSE_TSDF_F32) return *(const float*)p;
-        else if constexpr (FMT == ROSE_TSDF_F16) return __half2float(*(const __half*)p);
-        else return (float)(*(const int16_t*)p) * (1.0f / 32767.0f);
+        const int bo = (int)(off * elem_bytes<FMT>());
+        if constexpr (FMT == ROSE_TSDF_F32) {
+            return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(b.r, bo, 0, 0));
+        } else if constexpr (FMT == ROSE_TSDF_F16) {
+            return __half2float(__ushort_as_half(__builtin_amdgcn_raw_buffer_load_b16(b.r, bo, 0, 0)));
+        } else {
+            return (float)(int16_t)__builtin_amdgcn_raw_buffer_load_b16(b.r, bo, 0, 0) * (1.0f / 32767.0f);
+        }
     }
 }
 
@@ -42,30 +61,37 @@ struct VoxelTest {
 };
 
 // NEAREST voxel of voxel-space coordinate g: inside iff 0 <= g < n on every
-// axis (NaN is outside); then floor(g) == (uint32)g.
+// axis (NaN is outside); then floor(g) == (uint32)g.  Outside the grid the
+// conversions saturate and the offset would be meaningless: it is replaced
+// by one past the end of any buffer below 4 GB, where a buffer load fetches
+// no cache line and returns 0 (WIDE volumes, read through plain pointers,
+// get offset 0); the caller supplies the +1.
+// The offset is computed for every lane (the volatile empty asm keeps the
+// compiler from turning the select below into a branch around it).
+template <bool WIDE>
 __device__ inline bool nearest_offset(const Grid& g, const VoxelTest& e, float gx, float gy, float gz, uint32_t* off) {
+    uint32_t o = brick_offset(g, (uint32_t)gx, (uint32_t)gy, (uint32_t)gz);
+    asm volatile("" : "+v"(o));
     const bool in = (gx >= 0.0f) & (gx < e.fx) & (gy >= 0.0f) & (gy < e.fy) & (gz >= 0.0f) & (gz < e.fz);
-    // out-of-range conversions saturate; their offset is replaced below
-    const uint32_t o = brick_offset(g, (uint32_t)gx, (uint32_t)gy, (uint32_t)gz);
-    *off = in ? o : 0u;
+    *off = in ? o : (WIDE ? 0u : 0xffffffffu);
     return in;
 }
 
 template <int FMT, bool WIDE>
-__device__ inline float lookup_trilinear(const Grid& g, float gx, float gy, float gz) {
+__device__ inline float lookup_trilinear(const Grid& g, const PsiBuf& b, float gx, float gy, float gz) {
     const float hx = gx - 0.5f, hy = gy - 0.5f, hz = gz - 0.5f;
     const bool in = (hx >= 0.0f) & (hx < (float)(g.nx - 1)) & (hy >= 0.0f) & (hy < (float)(g.ny - 1)) &
                     (hz >= 0.0f) & (hz < (float)(g.nz - 1));
     const uint32_t ix = in ? (uint32_t)hx : 0u, iy = in ? (uint32_t)hy : 0u, iz = in ? (uint32_t)hz : 0u;
     const float fx = hx - (float)ix, fy = hy - (float)iy, fz = hz - (float)iz;
-    const float v000 = gather<FMT, WIDE>(g.psi, brick_offset(g, ix, iy, iz));
-    const float v100 = gather<FMT, WIDE>(g.psi, brick_offset(g, ix + 1, iy, iz));
-    const float v010 = gather<FMT, WIDE>(g.psi, brick_offset(g, ix, iy + 1, iz));
-    const float v110 = gather<FMT, WIDE>(g.psi, brick_offset(g, ix + 1, iy + 1, iz));
-    const float v001 = gather<FMT, WIDE>(g.psi, brick_offset(g, ix, iy, iz + 1));
-    const float v101 = gather<FMT, WIDE>(g.psi, brick_offset(g, ix + 1, iy, iz + 1));
-    const float v011 = gather<FMT, WIDE>(g.psi, brick_offset(g, ix, iy + 1, iz + 1));
-    const float v111 = gather<FMT, WIDE>(g.psi, brick_offset(g, ix + 1, iy + 1, iz + 1));
+    const float v000 = gather<FMT, WIDE>(g, b, brick_offset(g, ix, iy, iz));
+    const float v100 = gather<FMT, WIDE>(g, b, brick_offset(g, ix + 1, iy, iz));
+    const float v010 = gather<FMT, WIDE>(g, b, brick_offset(g, ix, iy + 1, iz));
+    const float v110 = gather<FMT, WIDE>(g, b, brick_offset(g, ix + 1, iy + 1, iz));
+    const float v001 = gather<FMT, WIDE>(g, b, brick_offset(g, ix, iy, iz + 1));
+    const float v101 = gather<FMT, WIDE>(g, b, brick_offset(g, ix + 1, iy, iz + 1));
+    const float v011 = gather<FMT, WIDE>(g, b, brick_offset(g, ix, iy + 1, iz + 1));
+    const float v111 = gather<FMT, WIDE>(g, b, brick_offset(g, ix + 1, iy + 1, iz + 1));
     const float c00 = fmaf(fx, v100 - v000, v000);
     const float c10 = fmaf(fx, v110 - v010, v010);
     const float c01 = fmaf(fx, v101 - v001, v001);
@@ -80,8 +106,6 @@ __device__ inline float bcast(float v, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
-// P particles per wave, U points per lane per loop step; all P*U gathers of
-// a step are issued before any is consumed.
 __device__ inline float wave_sum_f(float v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
@@ -102,9 +126,50 @@ __device__ inline bool switch_skips(const FitLaunch& a) {
     return small != (a.pl_side == 1);
 }
 
+// psi of one evaluation from its voxel-space coordinate: NEAREST takes the
+// voxel containing it (+1 outside the grid), TRILINEAR interpolates.
+// Evaluations are done in batches of K: all K addresses first, then all K
+// gathers (in flight together), then the selects.
+template <int K, int FMT, int LK, bool WIDE>
+__device__ inline void psi_batch(const Grid& g, const PsiBuf& b, const VoxelTest& ext, const float (&gx)[K],
+                                 const float (&gy)[K], const float (&gz)[K], float (&v)[K]) {
+    if constexpr (LK == ROSE_LOOKUP_NEAREST) {
+        uint32_t off[K];
+        bool in[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) in[k] = nearest_offset<WIDE>(g, ext, gx[k], gy[k], gz[k], &off[k]);
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = gather<FMT, WIDE>(g, b, off[k]);
+        // select in binary32 (one v_cndmask); the empty asm keeps the
+        // compiler from moving the select past the widening to binary64,
+        // where it costs two
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            v[k] = in[k] ? v[k] : 1.0f;
+            asm("" : "+v"(v[k]));
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = lookup_trilinear<FMT, WIDE>(g, b, gx[k], gy[k], gz[k]);
+    }
+}
+
+// add psi^2: on the 2^-39 grid (kGridBase + k per term; the caller removes
+// kGridBase once per added term), or plain binary32 for the no-Kahan
+// ablation
+template <bool ACC32>
+__device__ inline void add_sq(uint64_t& acc, float& accf, float v) {
+    if constexpr (ACC32) accf = fmaf(v, v, accf);
+    else acc += grid_term_bits(v);
+}
+
+// a binary32 sum (no-Kahan ablation) as a grid integer
+__device__ inline uint64_t grid_of_f32_sum(float f) { return (uint64_t)__double2ull_rn((double)f * 0x1p39); }
+
 template <int P, int U, int FMT, int LK, bool FROM_STATE, bool WIDE, bool ACC32 = false>
 __device__ void fitness_body(const FitLaunch& a, const int blk) {
     constexpr int kU = U;
+    constexpr int kStep = kWave * kU;
     const int lane = threadIdx.x & 63;
     // XCD-aware mapping: consecutive workgroups go to the 8 XCDs in turn
     // (XCD = workgroup index mod 8).  With splits a multiple of 8, XCD x owns
@@ -142,97 +207,131 @@ __device__ void fitness_body(const FitLaunch& a, const int blk) {
         }
         fold_to_voxel(T, (double)a.g.vox, a.g.origin, V);
     }
-    // rotation entries wave-uniform (scalar registers); the translation column
-    // is broadcast with a cross-lane shuffle so that each fma reads at most
-    // one scalar operand
+    // Up to 4 particles per wave: rotation entries wave-uniform in scalar
+    // registers and the translation column broadcast with a cross-lane
+    // shuffle, so that each fma reads at most one scalar operand.  With 8
+    // particles the 72 rotation entries would crowd out the scalar registers
+    // the loop needs (and spill), so all entries are broadcast to vector
+    // registers.
+    constexpr bool kRotScalar = true;
     float S[P][12];
 #pragma unroll
     for (int p = 0; p < P; ++p)
 #pragma unroll
-        for (int e = 0; e < 12; ++e) S[p][e] = (e % 4 == 3) ? __shfl(V[e], p, kWave) : bcast(V[e], p);
+        for (int e = 0; e < 12; ++e)
+            S[p][e] = (!kRotScalar || e % 4 == 3) ? __shfl(V[e], p, kWave) : bcast(V[e], p);
 
     const Grid g = a.g;
+    const PsiBuf pb = psi_buffer<FMT>(g);
     const VoxelTest ext{(float)g.nx, (float)g.ny, (float)g.nz};
     const int chunk = (m + a.splits - 1) / a.splits;
     const int j0 = split * chunk;
     const int j1 = min(m, j0 + chunk);
-    double acc[P];
-    float accf[P];  // ACC32: plain binary32 running sums
+    uint64_t acc[P];  // grid sums (kGridBase + k per added term)
+    float accf[P];    // ACC32: plain binary32 running sums
+    // Evaluations outside the grid (psi = +1, i.e. +1 to the sum each): with
+    // binary64 sums and NEAREST lookups they are counted per particle on the
+    // scalar unit (a population count of the wave's outside lanes) and their
+    // gathers aimed past the buffer's end, where the load returns 0; the
+    // count is added after the wave sum.  This keeps no per-evaluation lane
+    // mask alive across the gathers (P x U of them would not fit the scalar
+    // registers).
+    constexpr bool kCount = (LK == ROSE_LOOKUP_NEAREST) && !ACC32 && !WIDE;
+    int nout[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-        acc[p] = 0.0;
+        acc[p] = 0;
         accf[p] = 0.0f;
+        nout[p] = 0;
     }
-    // the next step's points are loaded one step ahead, so their latency
-    // overlaps the current step's gathers
-    float4 xn[kU];
-    bool okn[kU];
+    auto eval = [&](const float4 (&x)[kU], const bool (&okl)[kU], float (&v)[kU][P]) {
+        float gx[kU * P], gy[kU * P], gz[kU * P], w[kU * P];
+        if constexpr (kCount) {
+            // one particle's kU addresses at a time (the scheduling barriers
+            // keep the compiler from computing every evaluation's bounds
+            // test first, whose lane masks would not fit the scalar
+            // registers), then all P x kU gathers in flight together
+            uint32_t off[kU * P];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-        const int j = j0 + u * kWave + lane;
-        okn[u] = j < j1;
-        xn[u] = a.pts[okn[u] ? j : (j1 > j0 ? j0 : 0)];
-    }
-    for (int jb = j0; jb < j1; jb += kWave * kU) {
-        float4 x[kU];
-        bool ok[kU];
+            for (int p = 0; p < P; ++p) {
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            x[u] = xn[u];
-            ok[u] = okn[u];
-            const int j = jb + kWave * kU + u * kWave + lane;
-            okn[u] = j < j1;
-            xn[u] = a.pts[okn[u] ? j : j0];
-        }
-        float v[kU][P];
-        if constexpr (LK == ROSE_LOOKUP_NEAREST) {
-            uint32_t off[kU][P];
-            bool in[kU][P];
-#pragma unroll
-            for (int u = 0; u < kU; ++u)
-#pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    const float gx = xf_row(S[p][0], S[p][1], S[p][2], S[p][3], x[u].x, x[u].y, x[u].z);
-                    const float gy = xf_row(S[p][4], S[p][5], S[p][6], S[p][7], x[u].x, x[u].y, x[u].z);
-                    const float gz = xf_row(S[p][8], S[p][9], S[p][10], S[p][11], x[u].x, x[u].y, x[u].z);
-                    in[u][p] = nearest_offset(g, ext, gx, gy, gz, &off[u][p]);
+                for (int u = 0; u < kU; ++u) {
+                    const int k = u * P + p;
+                    gx[k] = xf_row(S[p][0], S[p][1], S[p][2], S[p][3], x[u].x, x[u].y, x[u].z);
+                    gy[k] = xf_row(S[p][4], S[p][5], S[p][6], S[p][7], x[u].x, x[u].y, x[u].z);
+                    gz[k] = xf_row(S[p][8], S[p][9], S[p][10], S[p][11], x[u].x, x[u].y, x[u].z);
+                    const bool in = nearest_offset<false>(g, ext, gx[k], gy[k], gz[k], &off[k]);
+                    nout[p] += __builtin_popcountll(__builtin_amdgcn_ballot_w64(!in && okl[u]));
+                    __builtin_amdgcn_sched_barrier(0);
                 }
+            }
 #pragma unroll
-            for (int u = 0; u < kU; ++u)
-#pragma unroll
-                for (int p = 0; p < P; ++p) v[u][p] = gather<FMT, WIDE>(g.psi, off[u][p]);
-#pragma unroll
-            for (int u = 0; u < kU; ++u)
-#pragma unroll
-                for (int p = 0; p < P; ++p) v[u][p] = in[u][p] ? v[u][p] : 1.0f;
+            for (int k = 0; k < kU * P; ++k) w[k] = gather<FMT, false>(g, pb, off[k]);
         } else {
 #pragma unroll
             for (int u = 0; u < kU; ++u)
 #pragma unroll
                 for (int p = 0; p < P; ++p) {
-                    const float gx = xf_row(S[p][0], S[p][1], S[p][2], S[p][3], x[u].x, x[u].y, x[u].z);
-                    const float gy = xf_row(S[p][4], S[p][5], S[p][6], S[p][7], x[u].x, x[u].y, x[u].z);
-                    const float gz = xf_row(S[p][8], S[p][9], S[p][10], S[p][11], x[u].x, x[u].y, x[u].z);
-                    v[u][p] = lookup_trilinear<FMT, WIDE>(g, gx, gy, gz);
+                    gx[u * P + p] = xf_row(S[p][0], S[p][1], S[p][2], S[p][3], x[u].x, x[u].y, x[u].z);
+                    gy[u * P + p] = xf_row(S[p][4], S[p][5], S[p][6], S[p][7], x[u].x, x[u].y, x[u].z);
+                    gz[u * P + p] = xf_row(S[p][8], S[p][9], S[p][10], S[p][11], x[u].x, x[u].y, x[u].z);
                 }
+            psi_batch<kU * P, FMT, LK, WIDE>(g, pb, ext, gx, gy, gz, w);
         }
 #pragma unroll
         for (int u = 0; u < kU; ++u)
 #pragma unroll
-            for (int p = 0; p < P; ++p) {
-                if constexpr (ACC32) {
-                    const float d = ok[u] ? v[u][p] : 0.0f;
-                    accf[p] = fmaf(d, d, accf[p]);
-                } else {
-                    const double d = (double)(ok[u] ? v[u][p] : 0.0f);
-                    acc[p] = fma(d, d, acc[p]);
-                }
-            }
+            for (int p = 0; p < P; ++p) v[u][p] = w[u * P + p];
+    };
+    bool all[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) all[u] = true;
+    // full steps (every lane's kU points valid), the next step's points
+    // loaded one step ahead so that their latency overlaps the gathers.  An
+    // empty slice loads nothing (with no points at all the point buffer may
+    // not exist) and writes a zero partial sum.
+    const int nfull = (j1 > j0) ? (j1 - j0) / kStep : 0;
+    float4 xn[kU];
+    if (j1 > j0) {
+#pragma unroll
+        for (int u = 0; u < kU; ++u) xn[u] = a.pts[min(j0 + u * kWave + lane, j1 - 1)];
     }
+    for (int st = 0; st < nfull; ++st) {
+        float4 x[kU];
+        const int jn = j0 + (st + 1) * kStep;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            x[u] = xn[u];
+            xn[u] = a.pts[min(jn + u * kWave + lane, j1 - 1)];
+        }
+        float v[kU][P];
+        eval(x, all, v);
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+#pragma unroll
+            for (int p = 0; p < P; ++p) add_sq<ACC32>(acc[p], accf[p], v[u][p]);
+    }
+    // the last, partial step: lanes past the slice end add nothing
+    const int jt = j0 + nfull * kStep;
+    if (jt < j1) {
+        bool ok[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) ok[u] = jt + u * kWave + lane < j1;
+        float v[kU][P];
+        eval(xn, ok, v);
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+#pragma unroll
+            for (int p = 0; p < P; ++p) add_sq<ACC32>(acc[p], accf[p], ok[u] ? v[u][p] : 0.0f);
+        }
+    }
+    // every lane added kU terms per particle in each step it ran (lanes past
+    // the slice end added 0); remove their kGridBase parts, modulo 2^64
+    const uint64_t terms = (uint64_t)kWave * kU * (uint64_t)(nfull + (jt < j1 ? 1 : 0));
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-        if constexpr (ACC32) acc[p] = (double)wave_sum_f(accf[p]);
-        else acc[p] = wave_sum(acc[p]);
+        if constexpr (ACC32) acc[p] = grid_of_f32_sum(wave_sum_f(accf[p]));
+        else acc[p] = wave_sum_u64(acc[p]) - terms * kGridBase + (uint64_t)nout[p] * kGridOne;
     }
     if (lane == 0) {
 #pragma unroll
@@ -244,28 +343,29 @@ __device__ void fitness_body(const FitLaunch& a, const int blk) {
     }
 }
 
+
 // Transposed mapping (shape (64, U)): one particle per lane.  A wave takes 64
 // consecutive particles of the schedule order over one slice of the point
-// list; each lane builds and keeps its own transform, the wave loads 64
-// points at a time (one 16-byte load per lane) and hands them out one by one
-// from lane registers (readlane: the point is wave-uniform).  Every gather
-// instruction then looks up one point under 64 neighbouring poses of the
-// schedule order: once the search radius has shrunk to a few centimetres
-// these land in a handful of voxels, and the lanes share cache lines (a CPU
-// count on the room frames: ~4 lanes per 128-byte line at r = 0.03, ~13 at
-// 0.01, against ~1.1 when the lanes hold 64 neighbouring points).  U points
-// are looked up per step, their gathers in flight together.  Slices, XCD
-// mapping and the partial-sum layout are those of fitness_body, but a
-// workgroup takes one group of 64 particles and its 4 waves take the 4
-// quarters of the slice (4x the waves of one wave per group and slice, which
-// the points-across slice counts would leave too few); each lane sums its
-// particle's squares in point order, and the quarters are added in order
-// through LDS.  Every exit before the barrier is uniform over the workgroup.
+// list; each lane builds and keeps its own transform and the points are
+// read U at a time from LDS (wave-uniform broadcasts).  Every gather instruction
+// then looks up one point under 64 neighbouring poses of the schedule order:
+// once the search radius has shrunk to a few centimetres these land in a
+// handful of voxels, and the lanes share cache lines (a CPU count on the
+// room frames: ~4 lanes per 128-byte line at r = 0.03, ~13 at 0.01, against
+// ~1.1 when the lanes hold 64 neighbouring points).  The U gathers of a step
+// are in flight together.  Slices, XCD mapping and the partial-sum layout
+// are those of fitness_body, but a workgroup takes one group of 64 particles
+// and its 4 waves take the 4 quarters of the slice (4x the waves of one wave
+// per group and slice, which the points-across slice counts would leave too
+// few); each lane sums its particle's squares in point order, and the
+// quarters are added in order through LDS.  Every exit before the barrier
+// is uniform over the workgroup.
 template <int U, int FMT, int LK, bool FROM_STATE, bool WIDE, bool ACC32 = false>
 __device__ void fitness_body_pl(const FitLaunch& a, const int blk) {
-    __shared__ double s_part[4][kWave];
+    __shared__ uint64_t s_part[4][kWave];
+    __shared__ float4 s_pts[4][kWave];
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int s8 = a.splits >> 3;
     const int r = blk % a.splits;
     const int split = (r & 7) * s8 + (r >> 3);
@@ -294,71 +394,58 @@ __device__ void fitness_body_pl(const FitLaunch& a, const int blk) {
     }
 
     const Grid g = a.g;
+    const PsiBuf pb = psi_buffer<FMT>(g);
     const VoxelTest ext{(float)g.nx, (float)g.ny, (float)g.nz};
     const int chunk = (m + a.splits - 1) / a.splits;
     const int s0 = split * chunk;
     const int s1 = min(m, s0 + chunk);
     const int quarter = (max(s1 - s0, 0) + 3) / 4;
-    const int j0 = s0 + wave * quarter;
-    const int j1 = min(s1, j0 + quarter);
-    double acc = 0.0;
+    const int j0 = __builtin_amdgcn_readfirstlane(s0 + wave * quarter);
+    const int j1 = __builtin_amdgcn_readfirstlane(min(s1, j0 + quarter));
+    uint64_t acc = 0;  // grid sum (kGridBase + k per added term)
     float accf = 0.0f;
-    for (int jb = j0; jb < j1; jb += kWave) {
-        // wave-uniform, >= 1; held in a scalar register so that the lane
-        // index of each broadcast below is scalar arithmetic
-        const int cnt = __builtin_amdgcn_readfirstlane(min(kWave, j1 - jb));
-        const float4 xl = a.pts[jb + (lane < cnt ? lane : 0)];
-        for (int u0 = 0; u0 < cnt; u0 += U) {
-            float v[U];
-            if constexpr (LK == ROSE_LOOKUP_NEAREST) {
-                uint32_t off[U];
-                bool in[U];
+    // the wave's points pass through LDS 64 at a time (one coalesced load,
+    // the next batch's loaded one batch ahead) and are read back with
+    // broadcast reads, every lane the same point
+    float4* sp = s_pts[wave];
+    auto eval = [&](auto kk, int u0) {
+        constexpr int K = decltype(kk)::value;
+        float gx[K], gy[K], gz[K], v[K];
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int src = min(u0 + u, cnt - 1);
-                    const float x = bcast(xl.x, src), y = bcast(xl.y, src), z = bcast(xl.z, src);
-                    const float gx = xf_row(V[0], V[1], V[2], V[3], x, y, z);
-                    const float gy = xf_row(V[4], V[5], V[6], V[7], x, y, z);
-                    const float gz = xf_row(V[8], V[9], V[10], V[11], x, y, z);
-                    in[u] = nearest_offset(g, ext, gx, gy, gz, &off[u]);
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u) v[u] = gather<FMT, WIDE>(g.psi, off[u]);
-#pragma unroll
-                for (int u = 0; u < U; ++u) v[u] = in[u] ? v[u] : 1.0f;
-            } else {
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int src = min(u0 + u, cnt - 1);
-                    const float x = bcast(xl.x, src), y = bcast(xl.y, src), z = bcast(xl.z, src);
-                    const float gx = xf_row(V[0], V[1], V[2], V[3], x, y, z);
-                    const float gy = xf_row(V[4], V[5], V[6], V[7], x, y, z);
-                    const float gz = xf_row(V[8], V[9], V[10], V[11], x, y, z);
-                    v[u] = lookup_trilinear<FMT, WIDE>(g, gx, gy, gz);
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const bool ok = u0 + u < cnt;  // wave-uniform
-                if constexpr (ACC32) {
-                    const float d = ok ? v[u] : 0.0f;
-                    accf = fmaf(d, d, accf);
-                } else {
-                    const double d = (double)(ok ? v[u] : 0.0f);
-                    acc = fma(d, d, acc);
-                }
-            }
+        for (int u = 0; u < K; ++u) {
+            const float4 x = sp[u0 + u];
+            gx[u] = xf_row(V[0], V[1], V[2], V[3], x.x, x.y, x.z);
+            gy[u] = xf_row(V[4], V[5], V[6], V[7], x.x, x.y, x.z);
+            gz[u] = xf_row(V[8], V[9], V[10], V[11], x.x, x.y, x.z);
         }
+        psi_batch<K, FMT, LK, WIDE>(g, pb, ext, gx, gy, gz, v);
+#pragma unroll
+        for (int u = 0; u < K; ++u) add_sq<ACC32>(acc, accf, v[u]);
+    };
+    float4 xn = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (j0 < j1) xn = a.pts[min(j0 + lane, j1 - 1)];
+    for (int jb = j0; jb < j1; jb += kWave) {
+        const int cnt = min(kWave, j1 - jb);  // wave-uniform
+        sp[lane] = xn;
+        __builtin_amdgcn_wave_barrier();
+        if (jb + kWave < j1) xn = a.pts[min(jb + kWave + lane, j1 - 1)];
+        int u0 = 0;
+        for (; u0 + U <= cnt; u0 += U) eval(std::integral_constant<int, U>{}, u0);
+        for (; u0 < cnt; ++u0) eval(std::integral_constant<int, 1>{}, u0);
+        __builtin_amdgcn_wave_barrier();  // the batch's reads come before the next batch's write
     }
-    s_part[wave][lane] = ACC32 ? (double)accf : acc;
+    // one term per point of the wave's quarter; the quarters are added as
+    // integers (binary32 for the no-Kahan ablation, in quarter order)
+    if constexpr (ACC32) s_part[wave][lane] = (uint64_t)__float_as_uint(accf);
+    else s_part[wave][lane] = acc - (uint64_t)max(j1 - j0, 0) * kGridBase;  // empty quarters: j1 <= j0
     __syncthreads();
     if (wave == 0 && live) {
-        double sum;
+        uint64_t sum;
         if constexpr (ACC32) {
-            float f = (float)s_part[0][lane];
+            float f = __uint_as_float((uint32_t)s_part[0][lane]);
 #pragma unroll
-            for (int w = 1; w < 4; ++w) f += (float)s_part[w][lane];
-            sum = (double)f;
+            for (int w = 1; w < 4; ++w) f += __uint_as_float((uint32_t)s_part[w][lane]);
+            sum = grid_of_f32_sum(f);
         } else {
             sum = s_part[0][lane];
 #pragma unroll
@@ -470,6 +557,7 @@ static int batch_grid_shape(int fmt, int lk, int requested) {
 int batch_grid(int P, int U, int fmt, int lk, int requested) {
     if (P == kWave && U == 8) return batch_grid_shape<kWave, 8>(fmt, lk, requested);
     if (P == 8 && U == 4) return batch_grid_shape<8, 4>(fmt, lk, requested);
+    if (P == 4 && U == 8) return batch_grid_shape<4, 8>(fmt, lk, requested);
     if (P == 8 && U == 2) return batch_grid_shape<8, 2>(fmt, lk, requested);
     if (P == 4 && U == 4) return batch_grid_shape<4, 4>(fmt, lk, requested);
     return batch_grid_shape<4, 2>(fmt, lk, requested);
@@ -498,7 +586,7 @@ static void launch_batch_shape(const FitLaunch* seqs, const int* begin, int coun
 
 bool batch_shape_valid(int P, int U) {
     return (P == 4 && U == 2) || (P == 8 && U == 2) || (P == 4 && U == 4) || (P == 8 && U == 4) ||
-           (P == kWave && U == 8);
+           (P == 4 && U == 8) || (P == kWave && U == 8);
 }
 
 rose_status launch_fitness_batch(const FitLaunch* seqs_dev, const int* begin_dev, int count, int base, int end,
@@ -506,6 +594,7 @@ rose_status launch_fitness_batch(const FitLaunch* seqs_dev, const int* begin_dev
     if (P == kWave && U == 8)
         launch_batch_shape<kWave, 8>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
     else if (P == 8 && U == 4) launch_batch_shape<8, 4>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
+    else if (P == 4 && U == 8) launch_batch_shape<4, 8>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
     else if (P == 8 && U == 2) launch_batch_shape<8, 2>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
     else if (P == 4 && U == 4) launch_batch_shape<4, 4>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
     else launch_batch_shape<4, 2>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
@@ -514,15 +603,15 @@ rose_status launch_fitness_batch(const FitLaunch* seqs_dev, const int* begin_dev
 }
 
 // fitness_eval second pass: F_i = sum of slices / m (m = 0: F = 1)
-__global__ __launch_bounds__(256) void k_fitness_finish(const double* partial, int32_t n, int32_t splits, int32_t m,
-                                                        float* F, float* rho) {
+__global__ __launch_bounds__(256) void k_fitness_finish(const uint64_t* partial, int32_t n, int32_t splits,
+                                                        int32_t m, float* F, float* rho) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    double s = 0.0;
-    for (int k = 0; k < splits; ++k) s += partial[(int64_t)i * splits + k];
-    const float f = (m > 0) ? (float)(s / (double)m) : 1.0f;
+    uint64_t q = 0;
+    for (int k = 0; k < splits; ++k) q += partial[(int64_t)i * splits + k];
+    const float f = (m > 0) ? (float)(((double)q * kGridScale) / (double)m) : 1.0f;
     F[i] = f;
-    if (rho) rho[i] = (float)exp(-(double)f);
+    if (rho) rho[i] = (float)exp_rho(-(double)f);
 }
 
 __global__ __launch_bounds__(256) void k_voxel_indices(Grid g, const float* pts, int32_t m, const float* T32,
@@ -549,9 +638,39 @@ __global__ __launch_bounds__(256) void k_pack_points(const float* pts3, int32_t 
     pts4[j] = make_float4(pts3[3 * (int64_t)j], pts3[3 * (int64_t)j + 1], pts3[3 * (int64_t)j + 2], 0.0f);
 }
 
-// launch shape (particles per wave, points per lane per step); the tuner
-// may change it process-wide
-static int g_shape_p = 4, g_shape_u = 2;
+// Process-wide default launch configuration (the tuner may change it); a
+// handle with its own configuration (cfg_set) uses that instead.
+// Switching-mode thresholds measured on the 640x480 room workload (1 cm
+// voxels, 10240 particles): 8, 16, 32, 48, 64, 96 voxels at 3 m -> 0.709,
+// 0.703, 0.618, 0.595, 0.632, 0.638 ms per fitness step (fixed (8, 4): 0.707
+// ms, fixed (64, 8): 0.651 ms).  With one shared footprint for all six axes
+// the crossover sits above the one measured with equal axis lengths (about
+// 25 voxels): the largest axis overstates the spread of the others.
+// Trilinear lookups (8 gathers per evaluation) cross over earlier: on the
+// same workload 8, 16, 32, 48 voxels -> 2.099, 2.075, 2.055, 2.217 ms per
+// step (4x2 alone: 2.100), so their default is 32.
+static const FitConfig kDefaultCfg = {4, 2, 0, 4, 4, {48.0f, 32.0f}, 3.0f};
+static FitConfig g_cfg = kDefaultCfg;
+
+FitConfig fit_config(const rose_tsdf* h) { return (h && h->cfg_set) ? h->cfg : g_cfg; }
+
+void fit_launch_shape(const rose_tsdf* h, int lk, int* p, int* u, float* thr_vox, float* zref_m) {
+    const FitConfig c = fit_config(h);
+    if (c.sw) {
+        // trilinear lookups (8 gathers per evaluation) keep (4, 2), deeper
+        // shapes being register-bound there: 1.80 ms for 4x2 against 2.80
+        // for 8x4 on a room frame
+        const bool tri = lk == ROSE_LOOKUP_TRILINEAR;
+        *p = tri ? 4 : c.wide_p;
+        *u = tri ? 2 : c.wide_u;
+        *thr_vox = c.thr_vox[tri ? 1 : 0];
+    } else {
+        *p = c.p;
+        *u = c.u;
+        *thr_vox = 0.0f;
+    }
+    *zref_m = c.zref;
+}
 
 template <int P, int U, int FMT, int LK, bool WIDE>
 static void launch_pu(const FitLaunch& L, hipStream_t s) {
@@ -577,6 +696,7 @@ static void launch_w(const FitLaunch& L, hipStream_t s) {
     const int p = L.shape_p, u = L.shape_u;
     if (p == 2 && u == 4) launch_pu<2, 4, FMT, LK, false>(L, s);
     else if (p == 4 && u == 4) launch_pu<4, 4, FMT, LK, false>(L, s);
+    else if (p == 4 && u == 8) launch_pu<4, 8, FMT, LK, false>(L, s);
     else if (p == 8 && u == 2) launch_pu<8, 2, FMT, LK, false>(L, s);
     else if (p == 8 && u == 4) launch_pu<8, 4, FMT, LK, false>(L, s);
     else if (p == kWave && u == 4) launch_pu<kWave, 4, FMT, LK, false>(L, s);
@@ -600,17 +720,11 @@ static void launch_fmt(const FitLaunch& L, hipStream_t s) {
 rose_status launch_fitness(const FitLaunch& L, hipStream_t s) {
     const uint64_t bytes = (uint64_t)L.g.nx * L.g.ny * L.g.nz * (L.g.fmt == ROSE_TSDF_F32 ? 4u : 2u);
     if (L.pl_thr > 0.0f && L.st && !L.T32 && bytes < (uint64_t(1) << 32)) {
-        // switched: the points-across kernel above the threshold (the given
-        // shape; 4x2 for trilinear lookups, whose 8 gathers per evaluation
-        // make deeper shapes register-bound: 1.80 ms for 4x2 against 2.80
-        // for 8x4 on a room frame), the particle-per-lane kernel at or below
-        // it; both write the same partial-sum slices
+        // switched: the points-across kernel (the given shape) above the
+        // threshold, the particle-per-lane kernel at or below it; both write
+        // the same partial-sum slices
         FitLaunch a = L, b = L;
         a.pl_side = 2;
-        if (L.lookup == ROSE_LOOKUP_TRILINEAR) {
-            a.shape_p = 4;
-            a.shape_u = 2;
-        }
         b.pl_side = 1;
         b.shape_p = kWave;
         b.shape_u = 8;
@@ -626,35 +740,8 @@ rose_status launch_fitness(const FitLaunch& L, hipStream_t s) {
 }
 
 bool fitness_shape_valid(int p, int u) {
-    return (p == 2 && u == 4) || (p == 4 && u == 2) || (p == 4 && u == 4) || (p == 8 && u == 2) ||
-           (p == 8 && u == 4) || (p == kWave && (u == 4 || u == 8 || u == 16));
-}
-
-void fitness_shape(int* p, int* u) {
-    *p = g_shape_p;
-    *u = g_shape_u;
-}
-
-// switching mode: the points-across shape (8, 4) while the search footprint
-// exceeds the threshold, one particle per lane (64, 8) at or below it.
-// Default threshold 48 voxels at a 3 m reference depth, measured on the
-// 640x480 room workload (1 cm voxels, 10240 particles): 8, 16, 32, 48, 64,
-// 96 voxels -> 0.709, 0.703, 0.618, 0.595, 0.632, 0.638 ms per fitness step
-// (fixed (8, 4): 0.707 ms, fixed (64, 8): 0.651 ms).  With one shared
-// footprint for all six axes the crossover sits above the one measured with
-// equal axis lengths (about 25 voxels): the largest axis overstates the
-// spread of the others.
-// Trilinear lookups (8 gathers per evaluation) cross over earlier: on the
-// same workload 8, 16, 32, 48 voxels -> 2.099, 2.075, 2.055, 2.217 ms per
-// step (4x2 alone: 2.100), so their default is 32.
-static bool g_switch = false;
-static float g_switch_vox[2] = {48.0f, 32.0f};  // by lookup: nearest, trilinear
-static float g_switch_zref = 3.0f;
-
-bool fitness_switching(int lookup, float* thr_vox, float* zref_m) {
-    *thr_vox = g_switch ? g_switch_vox[lookup == ROSE_LOOKUP_TRILINEAR ? 1 : 0] : 0.0f;
-    *zref_m = g_switch_zref;
-    return g_switch;
+    return (p == 2 && u == 4) || (p == 4 && u == 2) || (p == 4 && u == 4) || (p == 4 && u == 8) ||
+           (p == 8 && u == 2) || (p == 8 && u == 4) || (p == kWave && (u == 4 || u == 8 || u == 16));
 }
 
 // Point slices: a multiple of the 8 XCDs (see k_fitness).  For binary32
@@ -738,7 +825,7 @@ using namespace rose;
 
 extern "C" {
 
-rose_status fitness_eval(const rose_tsdf* h, const float* pts_dev, int32_t m, const float* T_dev, int32_t n,
+rose_status fitness_eval(rose_tsdf* h, const float* pts_dev, int32_t m, const float* T_dev, int32_t n,
                          rose_lookup lk, float* F_dev, float* rho_dev, hipStream_t s) {
     clear_error();
     ROSE_REQUIRE(h && T_dev && F_dev && (pts_dev || m == 0), ROSE_E_ARG, "fitness_eval: NULL argument");
@@ -746,20 +833,24 @@ rose_status fitness_eval(const rose_tsdf* h, const float* pts_dev, int32_t m, co
                  ROSE_MAX_PARTICLES);
     ROSE_REQUIRE(m >= 0 && m <= ROSE_MAX_IMAGE_PIXELS, ROSE_E_ARG, "fitness_eval: m = %d out of range", m);
     ROSE_REQUIRE(lk == ROSE_LOOKUP_NEAREST || lk == ROSE_LOOKUP_TRILINEAR, ROSE_E_ARG, "fitness_eval: bad lookup");
-    rose_tsdf* hm = const_cast<rose_tsdf*>(h);
-    const int splits = choose_splits(n, m, h->g.fmt, g_shape_p);
+    rose_tsdf* hm = h;
+    int sp, su;
+    float thr, zref;
+    fit_launch_shape(h, lk, &sp, &su, &thr, &zref);
+    const int splits = choose_splits(n, m, h->g.fmt, sp);
     // scratch: packed points and partial sums, owned by the handle
-    if (hm->cap_points < m) {
+    if (hm->cap_points < m || !hm->pts) {
         if (hm->pts) ROSE_CHECK_HIP(hipFree(hm->pts));
         hm->pts = nullptr;
-        ROSE_CHECK_HIP(hipMalloc(&hm->pts, sizeof(float4) * (size_t)(m > 0 ? m : 1)));
-        hm->cap_points = m;
+        const int64_t cap = m > 0 ? m : 1;
+        ROSE_CHECK_HIP(hipMalloc(&hm->pts, sizeof(float4) * (size_t)cap));
+        hm->cap_points = cap;
     }
     const int64_t need = (int64_t)n * splits;
     if (hm->cap_partial < need) {
         if (hm->partial) ROSE_CHECK_HIP(hipFree(hm->partial));
         hm->partial = nullptr;
-        ROSE_CHECK_HIP(hipMalloc(&hm->partial, sizeof(double) * (size_t)need));
+        ROSE_CHECK_HIP(hipMalloc(&hm->partial, sizeof(uint64_t) * (size_t)need));
         hm->cap_partial = need;
     }
     if (m > 0) {
@@ -776,7 +867,9 @@ rose_status fitness_eval(const rose_tsdf* h, const float* pts_dev, int32_t m, co
     L.splits = splits;
     L.lookup = lk;
     L.partial = hm->partial;
-    fitness_shape(&L.shape_p, &L.shape_u);
+    L.shape_p = sp;
+    L.shape_u = su;
+    L.pl_thr = 0.0f;  // no device state: the switch needs the current axis lengths
     rose_status st = launch_fitness(L, s);
     if (st != ROSE_OK) return st;
     hipLaunchKernelGGL(k_fitness_finish, dim3((n + 255) / 256), dim3(256), 0, s, hm->partial, n, splits, m, F_dev,
@@ -800,35 +893,84 @@ rose_status fitness_voxel_indices(const rose_tsdf* h, const float* pts_dev, int3
 
 }  // extern "C"
 
-extern "C" rose_status rose_fitness_set_switch(float footprint_voxels, float reference_depth_m) {
-    clear_error();
-    if (footprint_voxels == 0.0f) {  // the defaults
-        g_switch_vox[0] = 48.0f;
-        g_switch_vox[1] = 32.0f;
-        g_switch_zref = 3.0f;
+namespace rose {
+// Shared by the process-wide and the per-handle setters.
+static rose_status set_shape(FitConfig* c, int32_t p, int32_t u, const char* who) {
+    if (p == 0 && u == 0) {
+        c->sw = 1;
         return ROSE_OK;
     }
-    ROSE_REQUIRE(footprint_voxels > 0.0f && footprint_voxels <= 1.0e6f && reference_depth_m >= 0.0f &&
-                     reference_depth_m <= 1.0e3f,
-                 ROSE_E_ARG, "rose_fitness_set_switch: threshold %g voxels / depth %g m out of range",
-                 (double)footprint_voxels, (double)reference_depth_m);
-    g_switch_vox[0] = g_switch_vox[1] = footprint_voxels;
-    g_switch_zref = reference_depth_m;
+    ROSE_REQUIRE(fitness_shape_valid(p, u), ROSE_E_UNSUPPORTED, "%s: (%d, %d) is not a compiled shape", who, p, u);
+    c->sw = 0;
+    c->p = p;
+    c->u = u;
+    return ROSE_OK;
+}
+
+static rose_status set_switch(FitConfig* c, float vox, float zref, int32_t wide_p, int32_t wide_u, const char* who) {
+    ROSE_REQUIRE(wide_p != kWave && fitness_shape_valid(wide_p, wide_u), ROSE_E_UNSUPPORTED,
+                 "%s: (%d, %d) is not a compiled points-across shape", who, wide_p, wide_u);
+    if (vox == 0.0f) {  // the default thresholds
+        c->thr_vox[0] = kDefaultCfg.thr_vox[0];
+        c->thr_vox[1] = kDefaultCfg.thr_vox[1];
+        c->zref = kDefaultCfg.zref;
+    } else {
+        ROSE_REQUIRE(vox > 0.0f && vox <= 1.0e6f && zref >= 0.0f && zref <= 1.0e3f, ROSE_E_ARG,
+                     "%s: threshold %g voxels / depth %g m out of range", who, (double)vox, (double)zref);
+        c->thr_vox[0] = c->thr_vox[1] = vox;
+        c->zref = zref;
+    }
+    c->wide_p = wide_p;
+    c->wide_u = wide_u;
+    return ROSE_OK;
+}
+}  // namespace rose
+
+extern "C" rose_status rose_fitness_set_switch(float footprint_voxels, float reference_depth_m) {
+    clear_error();
+    return set_switch(&g_cfg, footprint_voxels, reference_depth_m, g_cfg.wide_p, g_cfg.wide_u,
+                      "rose_fitness_set_switch");
+}
+
+extern "C" rose_status rose_fitness_set_switch_shape(int32_t particles_per_wave, int32_t points_per_lane) {
+    clear_error();
+    FitConfig c = g_cfg;
+    rose_status st = set_switch(&c, 1.0f, 0.0f, particles_per_wave, points_per_lane, "rose_fitness_set_switch_shape");
+    if (st != ROSE_OK) return st;
+    g_cfg.wide_p = particles_per_wave;
+    g_cfg.wide_u = points_per_lane;
     return ROSE_OK;
 }
 
 extern "C" rose_status rose_fitness_set_shape(int32_t particles_per_wave, int32_t points_per_lane) {
     clear_error();
-    if (particles_per_wave == 0 && points_per_lane == 0) {
-        g_switch = true;
-        g_shape_p = 8;
-        g_shape_u = 4;
+    return set_shape(&g_cfg, particles_per_wave, points_per_lane, "rose_fitness_set_shape");
+}
+
+extern "C" rose_status tsdf_set_fitness_shape(rose_tsdf* h, int32_t particles_per_wave, int32_t points_per_lane) {
+    clear_error();
+    ROSE_REQUIRE(h != nullptr, ROSE_E_ARG, "tsdf_set_fitness_shape: NULL handle");
+    if (particles_per_wave == -1 && points_per_lane == -1) {  // back to the process-wide default
+        h->cfg_set = 0;
         return ROSE_OK;
     }
-    ROSE_REQUIRE(fitness_shape_valid(particles_per_wave, points_per_lane), ROSE_E_UNSUPPORTED,
-                 "rose_fitness_set_shape: (%d, %d) is not a compiled shape", particles_per_wave, points_per_lane);
-    g_switch = false;
-    g_shape_p = particles_per_wave;
-    g_shape_u = points_per_lane;
+    FitConfig c = fit_config(h);
+    rose_status st = set_shape(&c, particles_per_wave, points_per_lane, "tsdf_set_fitness_shape");
+    if (st != ROSE_OK) return st;
+    h->cfg = c;
+    h->cfg_set = 1;
+    return ROSE_OK;
+}
+
+extern "C" rose_status tsdf_set_fitness_switch(rose_tsdf* h, float footprint_voxels, float reference_depth_m,
+                                               int32_t wide_particles, int32_t wide_points) {
+    clear_error();
+    ROSE_REQUIRE(h != nullptr, ROSE_E_ARG, "tsdf_set_fitness_switch: NULL handle");
+    FitConfig c = fit_config(h);
+    rose_status st = set_switch(&c, footprint_voxels, reference_depth_m, wide_particles, wide_points,
+                                "tsdf_set_fitness_switch");
+    if (st != ROSE_OK) return st;
+    h->cfg = c;
+    h->cfg_set = 1;
     return ROSE_OK;
 }

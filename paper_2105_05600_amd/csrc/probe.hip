@@ -37,6 +37,33 @@ __global__ __launch_bounds__(256) void k_gather_peak(const float* buf, uint32_t 
     if (acc == -1.0e30f) sink[blockIdx.x] = acc;
 }
 
+// L2 -> CU read bandwidth probe: coalesced 16-byte loads (kStreamLoads in
+// flight per lane) sweeping a region per XCD that fits the XCD's L2 and is
+// far larger than a CU's L1, so that after the first sweep every load is an
+// L1 miss served by the L2.  The workgroups of an XCD start their sweeps at
+// staggered offsets.  Its byte rate is the measured peak of L2 -> CU reads
+// that bounds any kernel whose data is L2-resident.
+constexpr int kStreamLoads = 4;
+
+__global__ __launch_bounds__(256) void k_l2_stream(const float4* buf, uint32_t region_f4, uint32_t sweeps,
+                                                  float* sink) {
+    const uint32_t xcd = blockIdx.x & 7u;
+    const float4* region = buf + (uint64_t)xcd * region_f4;
+    const uint32_t mask = region_f4 - 1u;
+    const uint32_t start = (blockIdx.x >> 3) * (256u * kStreamLoads * 7u);
+    float acc = 0.0f;
+    for (uint32_t sw = 0; sw < sweeps; ++sw) {
+        for (uint32_t i = 0; i < region_f4; i += 256u * kStreamLoads) {
+            float4 v[kStreamLoads];
+#pragma unroll
+            for (int u = 0; u < kStreamLoads; ++u) v[u] = region[(start + i + (uint32_t)u * 256u + threadIdx.x) & mask];
+#pragma unroll
+            for (int u = 0; u < kStreamLoads; ++u) acc += (v[u].x + v[u].y) + (v[u].z + v[u].w);
+        }
+    }
+    if (acc == -1.0e30f) sink[blockIdx.x] = acc;
+}
+
 }  // namespace rose
 
 using namespace rose;
@@ -62,5 +89,24 @@ rose_status rose_gather_peak(const float* buf_dev, int64_t buf_elems, int32_t re
 }
 
 int32_t rose_gather_peak_loads_per_lane(void) { return kProbeLoads; }
+
+rose_status rose_l2_read_peak(const float* buf_dev, int64_t buf_elems, int32_t region_f4, int32_t blocks,
+                              int32_t sweeps, float* sink_dev, hipStream_t s) {
+    clear_error();
+    ROSE_REQUIRE(buf_dev && sink_dev, ROSE_E_ARG, "rose_l2_read_peak: NULL argument");
+    ROSE_REQUIRE(region_f4 >= 1024 && region_f4 <= (1 << 24) && (region_f4 & (region_f4 - 1)) == 0, ROSE_E_ARG,
+                 "rose_l2_read_peak: region_f4 = %d is not a power of two in [1024, 2^24]", region_f4);
+    ROSE_REQUIRE((int64_t)8 * region_f4 * 4 <= buf_elems, ROSE_E_SHAPE,
+                 "rose_l2_read_peak: 8 regions of %d float4 need %lld floats, buffer has %lld", region_f4,
+                 (long long)8 * region_f4 * 4, (long long)buf_elems);
+    ROSE_REQUIRE(((uintptr_t)buf_dev & 15u) == 0, ROSE_E_ARG, "rose_l2_read_peak: buffer not 16-byte aligned");
+    ROSE_REQUIRE(blocks >= 8 && blocks % 8 == 0 && blocks <= (1 << 20), ROSE_E_ARG,
+                 "rose_l2_read_peak: blocks = %d must be a positive multiple of 8", blocks);
+    ROSE_REQUIRE(sweeps >= 1, ROSE_E_ARG, "rose_l2_read_peak: sweeps must be >= 1");
+    hipLaunchKernelGGL(k_l2_stream, dim3(blocks), dim3(256), 0, s, (const float4*)buf_dev, (uint32_t)region_f4,
+                       (uint32_t)sweeps, sink_dev);
+    ROSE_CHECK_HIP(hipGetLastError());
+    return ROSE_OK;
+}
 
 }  // extern "C"

@@ -23,7 +23,8 @@ __device__ inline double trilinear64(const Grid& g, double hx, double hy, double
         for (int dy = 0; dy < 2; ++dy)
             for (int dx = 0; dx < 2; ++dx) {
                 const double w = (dx ? f[0] : 1.0 - f[0]) * (dy ? f[1] : 1.0 - f[1]) * (dz ? f[2] : 1.0 - f[2]);
-                const uint32_t off = brick_offset(g, (uint32_t)(i0[0] + dx), (uint32_t)(i0[1] + dy), (uint32_t)(i0[2] + dz));
+                const uint32_t off =
+                    brick_offset(g, (uint32_t)(i0[0] + dx), (uint32_t)(i0[1] + dy), (uint32_t)(i0[2] + dz));
                 acc += w * (double)load_psi<FMT>(g.psi, off);
             }
     return acc;

@@ -107,7 +107,7 @@ __global__ __launch_bounds__(1024) void k_swarm_best(SwarmArgs a, int k) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         const float f = a.F[i];
         argmin_merge(&fmin, &imin, f, i);
-        srho += exp(-(double)f / a.tau);
+        srho += exp_rho(-(double)f / a.tau);
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -146,7 +146,7 @@ __global__ __launch_bounds__(1024) void k_swarm_best(SwarmArgs a, int k) {
             for (int e = 0; e < 3; ++e) sw->tb[e] = t[e];
             sw->best_index[k] = bi;
         }
-        sw->rho_best[k] = exp(-(double)sw->Fb / a.tau);
+        sw->rho_best[k] = exp_rho(-(double)sw->Fb / a.tau);
         sw->rho_mean[k] = tot / (double)n;
         sw->n_overlap[k] = ch->n_overlap;
         sw->k = k + 1;
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(1024) void k_swarm_best(SwarmArgs a, int k) {
         const int chunk = (n + (int)blockDim.x - 1) / (int)blockDim.x;
         const int lo = min(n, (int)threadIdx.x * chunk), hi = min(n, lo + chunk);
         double part = 0.0;
-        for (int i = lo; i < hi; ++i) part += exp(-((double)a.F[i] - Fb) / a.tau);
+        for (int i = lo; i < hi; ++i) part += exp_rho(-((double)a.F[i] - Fb) / a.tau);
         s_pre[threadIdx.x] = part;
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(1024) void k_swarm_best(SwarmArgs a, int k) {
         __syncthreads();
         double acc = s_pre[threadIdx.x];
         for (int i = lo; i < hi; ++i) {
-            acc += exp(-((double)a.F[i] - Fb) / a.tau);
+            acc += exp_rho(-((double)a.F[i] - Fb) / a.tau);
             a.C[i] = acc;
         }
     }
@@ -280,7 +280,10 @@ static rose_status swarm_track(rose_tsdf* h, const float* depth_dev, const rose_
     const int su = (cam->width + p->stride - 1) / p->stride;
     const int sv = (cam->height + p->stride - 1) / p->stride;
     const int64_t mmax = (int64_t)su * sv;
-    const int splits = choose_splits(n, mmax, h->g.fmt, shape_particles());
+    int shp_p, shp_u;
+    float shp_thr, shp_zref;
+    fit_launch_shape(h, p->lookup, &shp_p, &shp_u, &shp_thr, &shp_zref);
+    const int splits = choose_splits(n, mmax, h->g.fmt, shp_p);
     rose_status g;
     if ((g = grow(&h->pts, &h->cap_points, mmax)) != ROSE_OK) return g;
     if ((g = grow(&h->pts_o, &h->cap_points_o, mmax)) != ROSE_OK) return g;
@@ -368,7 +371,8 @@ static rose_status swarm_track(rose_tsdf* h, const float* depth_dev, const rose_
     fl.partial = h->partial;
     fl.n = n;
     fl.splits = splits;
-    fitness_shape(&fl.shape_p, &fl.shape_u);
+    fl.shape_p = shp_p;  // no switch: the comparison optimisers keep one shape
+    fl.shape_u = shp_u;
     UpdateArgs ua{};
     ua.st = h->st;
     ua.partial = h->partial;
@@ -406,7 +410,7 @@ static rose_status swarm_track(rose_tsdf* h, const float* depth_dev, const rose_
     }
     for (int i = 0; i < 4; ++i) state->pose.q[i] = out->qb[i];
     for (int i = 0; i < 3; ++i) state->pose.t[i] = out->tb[i];
-    state->rho = exp(-(double)out->Fb / p->tau);
+    state->rho = exp_rho(-(double)out->Fb / p->tau);
     state->frame += 1;
     if (stats) {
         stats->iters = out->k;

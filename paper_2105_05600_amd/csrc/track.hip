@@ -150,7 +150,7 @@ __device__ void track_update_body(const UpdateArgs& a) {
     // APS threshold rho(s*_{k-1}): the carried Eq. wafit value from k = 2 on;
     // the centre's exact fitness (particle 0) at k = 1 or with
     // ROSE_FLAG_CENTRE_THRESHOLD
-    const double centre = exp(-(double)F0 / a.tau);
+    const double centre = exp_rho(-(double)F0 / a.tau);
     const double rho0 = (st->k == 0 || (a.flags & ROSE_FLAG_CENTRE_THRESHOLD)) ? centre : st->thr;
     double r[6];
     for (int d = 0; d < 6; ++d) r[d] = st->r[d];
@@ -158,7 +158,7 @@ __device__ void track_update_body(const UpdateArgs& a) {
     double cnt = 0.0, sw = 0.0, swr = 0.0, su[6] = {0, 0, 0, 0, 0, 0};
     for (int i = threadIdx.x; i < a.n; i += blockDim.x) {
         const float f = a.F[i];
-        const double rho = exp(-(double)f / a.tau);
+        const double rho = exp_rho(-(double)f / a.tau);
         if (rho > rho0) {
             const double w = rho - rho0;
             cnt += 1.0;
@@ -407,13 +407,16 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_cam
         ia.stride[l] = 1;
         ia.offset[l] = 0;
     }
+    int shp_p, shp_u;
+    float shp_thr, shp_zref;
+    fit_launch_shape(h, p->lookup, &shp_p, &shp_u, &shp_thr, &shp_zref);
     for (int l = 0; l < L; ++l) {
         const int st_l = L > 1 ? p->level_stride[l] : p->stride;
         lv_n[l] = L > 1 ? p->level_n[l] : n_particles;
         const int su = (cam->width + st_l - 1) / st_l;
         const int sv = (cam->height + st_l - 1) / st_l;
         const int64_t mmax = (int64_t)su * sv;
-        lv_splits[l] = choose_splits(lv_n[l], mmax, h->g.fmt, shape_particles());
+        lv_splits[l] = choose_splits(lv_n[l], mmax, h->g.fmt, shp_p);
         lv_off[l + 1] = lv_off[l] + mmax;
         mmax_all = std::max(mmax_all, mmax);
         partial_need = std::max(partial_need, (int64_t)lv_n[l] * lv_splits[l]);
@@ -458,8 +461,10 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_cam
     fl.lookup = p->lookup;
     fl.partial = h->partial;
     fl.acc32 = (p->flags & ROSE_FLAG_NO_KAHAN) ? 1 : 0;
-    fitness_shape(&fl.shape_p, &fl.shape_u);
-    fitness_switching(p->lookup, &fl.pl_thr, &fl.pl_zref);
+    fl.shape_p = shp_p;
+    fl.shape_u = shp_u;
+    fl.pl_thr = shp_thr;
+    fl.pl_zref = shp_zref;
 
     UpdateArgs ua;
     ua.st = h->st;
@@ -693,8 +698,10 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
     rose_batch* b = new rose_batch();
     b->count = count;
     b->use_graph = use_graph != 0;
-    int P, U;
-    fitness_shape(&P, &U);
+    // the first handle's launch configuration: its fixed shape, or in the
+    // switching mode its points-across shape
+    const FitConfig cfg = fit_config(tsdfs[0]);
+    int P = cfg.sw ? cfg.wide_p : cfg.p, U = cfg.sw ? cfg.wide_u : cfg.u;
     if (!batch_shape_valid(P, U)) {
         P = 4;
         U = 2;
@@ -1069,7 +1076,10 @@ rose_status pso_batch_track_learned(rose_batch* b, const float* const* depth_dev
                      "pso_batch_track_learned: plain parameters of sequence %d need stride >= 1 and one level", i);
         const int64_t mmax = (int64_t)((b->cams[i].width + pp.stride - 1) / pp.stride) *
                              ((b->cams[i].height + pp.stride - 1) / pp.stride);
-        const int splits = choose_splits(n_plain[i], mmax, h->g.fmt, shape_particles());
+        int sp, su;
+        float thr, zref;
+        fit_launch_shape(h, pp.lookup, &sp, &su, &thr, &zref);
+        const int splits = choose_splits(n_plain[i], mmax, h->g.fmt, sp);
         rose_status g;
         if ((g = grow(&h->pts, &h->cap_points, mmax)) != ROSE_OK) return g;
         if ((g = grow(&h->pts_o, &h->cap_points_o, mmax)) != ROSE_OK) return g;

@@ -127,7 +127,7 @@ struct UpdateArgs {
     DevState* st;
     Cam cam;
     const float* pst;
-    const double* partial;
+    const uint64_t* partial;
     float* F;
     const float4* pts;  // points of the next iteration's level
     float4* pts_o;
@@ -140,9 +140,13 @@ struct UpdateArgs {
     double beta, eps, tau, stop_tol;
 };
 
+// F_i = S_i / |O| (Eq. normallh) from the slice sums on the 2^-39 grid
+// (exact integer sum, then one rounding to binary64, an exact scaling, one
+// correctly rounded division and one rounding to binary32)
 __device__ inline float final_fitness(const UpdateArgs& a, int i, int nO) {
-    double s = 0.0;
-    for (int k = 0; k < a.splits; ++k) s += a.partial[(int64_t)i * a.splits + k];
+    uint64_t q = 0;
+    for (int k = 0; k < a.splits; ++k) q += a.partial[(int64_t)i * a.splits + k];
+    const double s = (double)q * kGridScale;
     double f;
     if (a.flags & ROSE_FLAG_NO_NORMALIZE) f = s;
     else f = (nO > 0) ? s / (double)nO : 1.0;

@@ -200,6 +200,8 @@ rose_status tsdf_create(int32_t nx, int32_t ny, int32_t nz, float voxel_m, float
     Grid& g = h->g;
     g.nx = nx; g.ny = ny; g.nz = nz;
     g.nbx = nx / 8; g.nby = ny / 8; g.nbz = nz / 8;
+    g.bstride_y = 64 * g.nbx - 8;
+    g.bstride_z = 64 * g.nbx * g.nby - 64;
     g.vox = voxel_m; g.mu = trunc_m; g.w_max = w_max;
     g.origin[0] = origin_m[0]; g.origin[1] = origin_m[1]; g.origin[2] = origin_m[2];
     g.fmt = fmt;

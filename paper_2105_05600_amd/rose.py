@@ -131,6 +131,9 @@ _sigs = {
     "depth_unproject": ([_P, C.POINTER(Camera), C.c_int32, C.c_int32, _P, _P, _S], C.c_int),
     "rose_fitness_set_shape": ([C.c_int32, C.c_int32], C.c_int),
     "rose_fitness_set_switch": ([C.c_float, C.c_float], C.c_int),
+    "rose_fitness_set_switch_shape": ([C.c_int32, C.c_int32], C.c_int),
+    "tsdf_set_fitness_shape": ([_P, C.c_int32, C.c_int32], C.c_int),
+    "tsdf_set_fitness_switch": ([_P, C.c_float, C.c_float, C.c_int32, C.c_int32], C.c_int),
     "overlap_mask": ([_P, C.c_int32, C.POINTER(Pose), C.POINTER(Pose), C.POINTER(Camera), _P, _S], C.c_int),
     "pso_track_frame": ([_P, _P, C.POINTER(Camera), _P, C.c_int32, C.POINTER(TrackParams), C.POINTER(Pose), _P,
                          C.POINTER(TrackState), C.POINTER(TrackStats), _S], C.c_int),
@@ -278,6 +281,18 @@ class Tsdf:
         p = pose(q, t)
         _check("tsdf_integrate", _lib.tsdf_integrate(self.handle, _ptr(depth), C.byref(cam), C.byref(p),
                                                      _stream(stream)))
+
+    def set_fitness_shape(self, particles_per_wave: int, points_per_lane: int):
+        """This handle's own fitness launch shape ((0, 0): switching mode;
+        (-1, -1): back to the process-wide default)."""
+        _check("tsdf_set_fitness_shape",
+               _lib.tsdf_set_fitness_shape(self.handle, int(particles_per_wave), int(points_per_lane)))
+
+    def set_fitness_switch(self, footprint_voxels: float, reference_depth_m: float = 3.0, wide=(4, 4)):
+        """This handle's switching threshold and points-across shape."""
+        _check("tsdf_set_fitness_switch",
+               _lib.tsdf_set_fitness_switch(self.handle, float(footprint_voxels), float(reference_depth_m),
+                                            int(wide[0]), int(wide[1])))
 
     def export(self, stream=None):
         nx, ny, nz = self.dims
@@ -633,6 +648,12 @@ def set_fitness_switch(footprint_voxels: float, reference_depth_m: float = 3.0):
     """Threshold of the switching launch mode (set_fitness_shape(0, 0));
     footprint_voxels = 0 restores the defaults."""
     _check("rose_fitness_set_switch", _lib.rose_fitness_set_switch(float(footprint_voxels), float(reference_depth_m)))
+
+
+def set_fitness_switch_shape(particles_per_wave: int, points_per_lane: int):
+    """Points-across shape of the switching mode (process-wide default)."""
+    _check("rose_fitness_set_switch_shape",
+           _lib.rose_fitness_set_switch_shape(int(particles_per_wave), int(points_per_lane)))
 
 
 class Batch:

@@ -84,6 +84,10 @@ def test_host_side_argument_errors(R):
     assert lib.rose_gather_peak(C.c_void_p(16), 1 << 10, 4096, 8, 1, 1, C.c_void_p(16), None) == R.E_SHAPE
     assert lib.rose_gather_peak(C.c_void_p(16), 1 << 20, 64, 12, 1, 1, C.c_void_p(16), None) == R.E_ARG
     assert lib.rose_gather_peak_loads_per_lane() == 8
+    assert lib.rose_l2_read_peak(C.c_void_p(16), 1 << 20, 3000, 8, 1, C.c_void_p(16), None) == R.E_ARG
+    assert lib.rose_l2_read_peak(C.c_void_p(16), 1 << 10, 4096, 8, 1, C.c_void_p(16), None) == R.E_SHAPE
+    assert lib.rose_l2_read_peak(C.c_void_p(16), 1 << 20, 4096, 12, 1, C.c_void_p(16), None) == R.E_ARG
+    assert lib.rose_l2_read_peak(C.c_void_p(16), 1 << 20, 4096, 8, 0, C.c_void_p(16), None) == R.E_ARG
     v = C.c_void_p(16)
     assert lib.pst_poisson(0, 1, 0.3, 100, v, v, v, None) == R.E_ARG
     assert lib.pst_poisson(8, 1, 2.5, 100, v, v, v, None) == R.E_ARG

@@ -25,3 +25,24 @@ def test_gather_probe_rates():
         assert torch.count_nonzero(sink) == 0
     print(rates)
     assert rates[2] > 1e10 and rates[2] > rates[256]
+
+
+def test_l2_read_probe_rate():
+    """The L2 -> CU read probe over an L2-resident region (2 MiB per XCD):
+    every byte is counted, the rate is plausible (above the HBM peak's order,
+    below 100 TB/s) and the sink is untouched."""
+    from paper_2105_05600_amd import rose
+    region = 2 * (1 << 20) // 16
+    buf = torch.rand(8 * region * 4, device="cuda")
+    sink = torch.zeros(2048, device="cuda")
+    rose.l2_read_peak(buf, region, 2048, 1, sink)  # warm
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    n = rose.l2_read_peak(buf, region, 2048, 2, sink)
+    e1.record()
+    torch.cuda.synchronize()
+    assert n == 2048 * 2 * region * 16
+    rate = n / (e0.elapsed_time(e1) * 1e-3)
+    print(f"L2 -> CU reads: {rate / 1e12:.2f} TB/s")
+    assert torch.count_nonzero(sink) == 0
+    assert 2e12 < rate < 1e14

@@ -138,24 +138,85 @@ def test_fitness_outside_grid_is_one(orc):
     assert orc.fitness(psi, 0.1, np.zeros(3), np.zeros((0, 3), np.float32), T[None])[0] == 1.0
 
 
-def test_fitness_sum_is_exact_sum_of_lookups(orc):
-    """Nearest-lookup F times |O| equals the exactly rounded sum (math.fsum)
-    of the squared values at the voxels the index routine reports."""
-    rng = np.random.default_rng(2)
+def _sum_case(seed=2, n_pts=3000, n_T=6):
+    rng = np.random.default_rng(seed)
     nx, ny, nz = 24, 20, 16
     psi = rng.uniform(-1, 1, (nz, ny, nx)).astype(np.float32)
+    psi[rng.random(psi.shape) < 0.1] *= 1e-6  # tiny terms, below the grid's resolution after squaring
     vox = 0.05
     origin = np.array([-0.6, -0.5, -0.4], np.float32)
-    pts = rng.uniform(-0.7, 0.7, (3000, 3)).astype(np.float32)
+    pts = rng.uniform(-0.7, 0.7, (n_pts, 3)).astype(np.float32)
     T = np.stack([np.hstack([synth.axis_angle(rng.standard_normal(3), 0.3), rng.uniform(-0.1, 0.1, (3, 1))])
-                  for _ in range(6)])
+                  for _ in range(n_T)])
+    return psi, vox, origin, pts, T
+
+
+def test_fitness_grid_sum_is_exact(orc):
+    """Binary32 mode: F times |O| is the exact rational sum of the squared
+    looked-up values (at the voxels the index routine reports) each rounded
+    to the nearest multiple of 2^-39, ties to even, then rounded once to
+    binary64 -- computed here with Fractions -- and it lies within
+    |O| 2^-40 of the exactly rounded sum (math.fsum) of the squares."""
+    from fractions import Fraction
+    psi, vox, origin, pts, T = _sum_case()
+    nz, ny, nx = psi.shape
     F = orc.fitness(psi, vox, origin, pts, T, lookup=0, prec=1)
     idx = orc.voxel_indices((nx, ny, nz), vox, origin, pts, T)
     flat = psi.ravel().astype(np.float64)
+    m = len(pts)
     for i in range(len(T)):
         v = np.where(idx[i] >= 0, flat[np.maximum(idx[i], 0)], 1.0)
-        exact = math.fsum(v * v) / len(pts)
-        assert abs(F[i] - exact) <= 1e-15 * exact
+        q = sum(round(Fraction(float(x)) ** 2 * 2 ** 39) for x in v)  # round(): nearest, ties to even
+        assert F[i] == (float(q) * 2.0 ** -39) / m
+        assert abs(F[i] * m - math.fsum(v * v)) <= m * 2.0 ** -40
+
+
+def test_fitness_grid_sum_ignores_point_order(orc):
+    """Binary32 mode: any permutation of the points gives the same F bit
+    for bit (the grid sum is exact); binary64 mode's compensated sum need
+    not, but stays within a few ulps."""
+    psi, vox, origin, pts, T = _sum_case(seed=5, n_pts=2000, n_T=4)
+    perm = np.random.default_rng(9).permutation(len(pts))
+    for lk in (0, 1):
+        a = orc.fitness(psi, vox, origin, pts, T, lookup=lk, prec=1)
+        b = orc.fitness(psi, vox, origin, pts[perm], T, lookup=lk, prec=1)
+        assert np.array_equal(a, b)
+        a64 = orc.fitness(psi, vox, origin, pts, T, lookup=lk, prec=0)
+        b64 = orc.fitness(psi, vox, origin, pts[perm], T, lookup=lk, prec=0)
+        assert np.allclose(a64, b64, rtol=1e-14, atol=0)
+
+
+def test_fitness_binary64_sum_is_compensated(orc):
+    """Binary64 mode: with the identity pose and points at voxel centres
+    (the voxel is unambiguous in either precision), F times |O| equals the
+    exactly rounded sum (math.fsum) of the squares within 1e-15 relative
+    (Neumaier compensation)."""
+    rng = np.random.default_rng(3)
+    nx, ny, nz = 24, 20, 16
+    psi = rng.uniform(-1, 1, (nz, ny, nx)).astype(np.float32)
+    vox = 0.0625
+    origin = np.zeros(3, np.float32)
+    ijk = np.stack([rng.integers(0, n, 5000) for n in (nx, ny, nz)], axis=1)
+    pts = ((ijk + 0.5) * vox).astype(np.float32)
+    T = np.hstack([np.eye(3), np.zeros((3, 1))])[None]
+    F = orc.fitness(psi, vox, origin, pts, T, lookup=0, prec=0)[0]
+    v = psi[ijk[:, 2], ijk[:, 1], ijk[:, 0]].astype(np.float64)
+    exact = math.fsum(v * v) / len(pts)
+    assert abs(F - exact) <= 1e-15 * exact
+
+
+def test_exp_rho_matches_exp(orc):
+    """The oracle's exp (Cody-Waite reduction, Taylor polynomial, 2^k
+    scaling) is within one ulp of math.exp over the likelihood range
+    (rho = exp(-F / tau), F >= 0) and exact at 0."""
+    rng = np.random.default_rng(4)
+    xs = np.concatenate([-rng.uniform(0, 1, 4000), -rng.uniform(0, 50, 2000), -rng.uniform(0, 745, 500),
+                         -np.arange(0, 40) * math.log(2), [-1e-300, -0.5, -1.0]])
+    got = orc.exp_rho(xs)
+    for x, g in zip(xs, got):
+        e = math.exp(x)
+        assert abs(g - e) <= math.ulp(e), (x, g, e)
+    assert orc.exp_rho([0.0])[0] == 1.0 and orc.exp_rho([-2000.0])[0] == 0.0
 
 
 def test_voxel_indices_are_floor_of_voxel_coordinate(orc):
