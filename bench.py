@@ -59,9 +59,9 @@ def parse():
                     help="poisson: 6D Poisson-disk template (dart throwing, packing fraction 0.03)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--render-workers", type=int, default=16)
-    ap.add_argument("--shape", default=None, metavar="P,U",
-                    help="fitness launch shape (particles per wave, points per lane; 0,0: switching mode); "
-                         "default: timed per run")
+    ap.add_argument("--shape", default="0,0", metavar="P,U",
+                    help="fitness launch shape (particles per wave, points per lane; 0,0: the switching mode, "
+                         "default); 'tune': time every candidate on one frame and keep the fastest")
     ap.add_argument("--switch", default=None, metavar="VOX,DEPTH",
                     help="switching-mode threshold: footprint in voxels, reference depth in metres")
     ap.add_argument("--switch-shape", default=None, metavar="P,U",
@@ -305,13 +305,13 @@ def main():
     if args.switch_shape:
         wide = tuple(int(v) for v in args.switch_shape.split(","))
         rose.set_fitness_switch_shape(*wide)
-    if args.shape:
+    if args.shape != "tune":
         shp = tuple(int(v) for v in args.shape.split(","))
         rose.set_fitness_shape(*shp)
         tuned = {"shape": shp, "ms": {}, "cached": False}
     else:
         tuned = autotune.tune_track(vol, dev_depths[nxt], seq.K, pst, params, st)
-    log(f"fitness shape {tuned['shape']} ({'given' if args.shape else 'timed'}: {tuned['ms']})")
+    log(f"fitness shape {tuned['shape']} ({'timed' if args.shape == 'tune' else 'given'}: {tuned['ms']})")
     rose.profile_enable(True)
     rose.profile_reset()
     evals = 0.0

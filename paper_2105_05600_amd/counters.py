@@ -177,8 +177,18 @@ def main(argv=None):
         f = counters["TA_ADDR_STALLED_BY_TC_CYCLES_sum"].mean() / counters["TA_BUSY_sum"].mean()
         kv["ta_stalled_by_tc_frac"] = f"{f:.4g}"
         derived.append(f"the address unit waits on the L1 for {100 * f:.0f}% of its busy cycles")
-    if "SQ_ACTIVE_INST_VALU" in counters and "SQ_BUSY_CYCLES" in counters and "SQ_WAVES" in counters:
-        pass
+    if "SQ_INSTS_VALU" in counters:
+        # a wave64 VALU instruction holds a 16-lane SIMD for 4 clocks; 1024
+        # SIMDs; the clock from GRBM_GUI_ACTIVE (summed over the 8 XCDs) when
+        # it was collected, else the nominal 2.4 GHz
+        cycles = ms * 1e-3 * 2.4e9
+        if "GRBM_GUI_ACTIVE" in counters:
+            cycles = counters["GRBM_GUI_ACTIVE"].mean() / 8.0
+            derived.append(f"effective clock {cycles / (ms * 1e-3) / 1e9:.2f} GHz (GRBM_GUI_ACTIVE / 8 over the "
+                           f"step time)")
+        busy = counters["SQ_INSTS_VALU"].mean() * 4.0 / (1024.0 * cycles)
+        kv["valu_busy_frac"] = f"{busy:.4g}"
+        derived.append(f"VALU busy {100 * busy:.0f}% of the SIMD cycles of a step")
     lines += ["", "Derived:"] + [f"* {d}." for d in derived]
     lines += ["", "Values read by bench.py (while the kernel sources hash to the value below and the window and",
               "launch shape match its own):", ""]
