@@ -144,6 +144,13 @@ rose_status tsdf_integrate(rose_tsdf* h, const float* depth_dev, const rose_came
  * clamped to [0, 65535] for u16).  weight_lin_dev may be NULL in
  * tsdf_import: weights then become 1 where psi < 1 and 0 elsewhere. */
 rose_status tsdf_export(const rose_tsdf* h, float* psi_lin_dev, float* weight_lin_dev, hipStream_t s);
+/* The handle keeps one bit per 8x8x8 brick, set while every voxel of the
+ * brick holds exactly +1; the fitness kernels skip the reads of such
+ * bricks (the value is known), fusion clears bits and tsdf_create /
+ * tsdf_import rebuild them.  After writing the psi buffer in any other way,
+ * call tsdf_rescan (asynchronous on s) before the next fitness call.
+ * ROSE_E_ARG for a NULL handle. */
+rose_status tsdf_rescan(rose_tsdf* h, hipStream_t s);
 rose_status tsdf_import(rose_tsdf* h, const float* psi_lin_dev, const float* weight_lin_dev, hipStream_t s);
 
 /* -------------------------------------------------------------- PST (a1) */
@@ -195,6 +202,7 @@ rose_status pst_particle_poses(const rose_pose* centre, const double r[6], const
  * on demand, freed by tsdf_destroy), hence the non-const handle. */
 rose_status fitness_eval(rose_tsdf* h, const float* pts_dev, int32_t m, const float* T_dev, int32_t n,
                          rose_lookup lk, float* F_dev, float* rho_dev, hipStream_t s);
+
 
 /* Diagnostic: the NEAREST voxel of every (pose, point) pair of fitness_eval
  * as a linear index (k*ny + j)*nx + i, or -1 outside the grid; idx_dev is

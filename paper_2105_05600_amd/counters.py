@@ -26,6 +26,7 @@ import glob
 import hashlib
 import json
 import os
+import re
 import sys
 
 import numpy as np
@@ -45,8 +46,8 @@ def kernel_source_hash() -> str:
 
 def is_fitness(name: str) -> bool:
     """The fitness kernel's instances (not its reduce, finish or batch
-    kernels)."""
-    return name.startswith("void k_fitness<") or name.startswith("k_fitness<")
+    kernels), with or without the namespace in the demangled name."""
+    return re.search(r"(^|[\s:])k_fitness<", name) is not None
 
 
 def _rows(pattern: str):
@@ -80,8 +81,8 @@ def pmc_steps(pmc_dir: str, n_steps: int, per: int):
         if is_fitness(name):
             vals.setdefault(c, {}).setdefault(d, 0.0)
             vals[c][d] += v
-        elif "elementwise" in name or "Mul" in name:
-            copy.setdefault(c, []).append(v)
+        elif "vectorized_elementwise_kernel" in name and ("AUnaryFunctor" in name or "MulFunctor" in name):
+            copy.setdefault(c, []).append(v)  # the copy probe's multiply by one
     out = {}
     for c, byd in vals.items():
         seq = [byd[d] for d in sorted(byd)][-per * n_steps:]
@@ -116,9 +117,9 @@ def main(argv=None):
     copy_kib = a.copy_mib * 1024.0
 
     def scale(counter):
-        # the copy probe reads and writes copy_kib KiB per dispatch; take its
-        # largest reading (the 1 GiB multiply, not the small torch kernels)
-        ref = max(copy.get(counter, [0.0]))
+        # the copy probe's multiply reads and writes copy_kib KiB per dispatch
+        vals = copy.get(counter, [])
+        ref = float(np.median(vals)) if vals else 0.0
         return copy_kib / ref if ref > 0 else None
 
     lines = [f"# k_fitness on the 512^3 room sequence: counters per fitness step", ""]

@@ -61,6 +61,11 @@ struct Grid {
     int32_t fmt;  // rose_tsdf_fmt
     void* psi;
     void* wgt;
+    // one bit per brick (brick-major order, 32 per word): set only while
+    // every voxel of the brick decodes to exactly +1 (unobserved or free
+    // space beyond the truncation band); cleared by fusion, rebuilt by
+    // tsdf_create / tsdf_import / tsdf_rescan
+    uint32_t* ones;
 };
 
 // Brick-major offset of voxel (i, j, k): bricks of 8x8x8 voxels in x-fastest

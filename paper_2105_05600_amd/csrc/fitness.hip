@@ -29,15 +29,27 @@ __device__ inline uint32_t elem_bytes() {
 // base in scalar registers, and a load past the buffer's end returns 0
 // instead of touching memory, so no offset needs clamping for safety (the
 // value of an evaluation outside the grid is replaced by +1 anyway).
+// The brick bits (Grid::ones) are read the same way.
 struct PsiBuf {
     __amdgpu_buffer_rsrc_t r;
+    __amdgpu_buffer_rsrc_t ones;
 };
 
 template <int FMT>
 __device__ inline PsiBuf psi_buffer(const Grid& g) {
     const uint32_t bytes = (uint32_t)g.nx * (uint32_t)g.ny * (uint32_t)g.nz * elem_bytes<FMT>();
+    const uint32_t words = ((uint32_t)g.nbx * (uint32_t)g.nby * (uint32_t)g.nbz + 31u) / 32u;
     // dword 3 of a raw (stride 0) buffer resource on gfx9-family targets
-    return PsiBuf{__builtin_amdgcn_make_buffer_rsrc(g.psi, (short)0, (int)bytes, 0x00020000)};
+    return PsiBuf{__builtin_amdgcn_make_buffer_rsrc(g.psi, (short)0, (int)bytes, 0x00020000),
+                  __builtin_amdgcn_make_buffer_rsrc(g.ones, (short)0, (int)(4u * words), 0x00020000)};
+}
+
+// whether the brick holding the voxel at element offset `off` is all +1
+// (offset / 512 = brick; bit brick mod 32 of word brick / 32, at byte
+// 4 (off >> 14))
+__device__ inline bool brick_all_ones(const PsiBuf& b, uint32_t off) {
+    const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(b.ones, (int)((off >> 12) & ~3u), 0, 0);
+    return __builtin_amdgcn_ubfe(w, off >> 9, 1) != 0u;
 }
 
 template <int FMT, bool WIDE>
@@ -229,13 +241,16 @@ __device__ void fitness_body(const FitLaunch& a, const int blk) {
     const int j1 = min(m, j0 + chunk);
     uint64_t acc[P];  // grid sums (kGridBase + k per added term)
     float accf[P];    // ACC32: plain binary32 running sums
-    // Evaluations outside the grid (psi = +1, i.e. +1 to the sum each): with
-    // binary64 sums and NEAREST lookups they are counted per particle on the
-    // scalar unit (a population count of the wave's outside lanes) and their
-    // gathers aimed past the buffer's end, where the load returns 0; the
-    // count is added after the wave sum.  This keeps no per-evaluation lane
-    // mask alive across the gathers (P x U of them would not fit the scalar
-    // registers).
+    // Evaluations outside the grid or in a brick that holds only +1 (psi =
+    // +1, i.e. +1 to the sum each): with grid sums and NEAREST lookups they
+    // are counted per particle on the scalar unit (a population count of the
+    // wave's lanes) and their gathers aimed past the buffer's end, where the
+    // load fetches no cache line and returns 0; the count is added after the
+    // wave sum.  This keeps no per-evaluation lane mask alive across the
+    // gathers (P x U of them would not fit the scalar registers), and when
+    // the search spreads the particles far from the surfaces it spares the
+    // gathers that land in free space (a fifth of all evaluations when the
+    // axis lengths are 0.2).
     constexpr bool kCount = (LK == ROSE_LOOKUP_NEAREST) && !ACC32 && !WIDE;
     int nout[P];
 #pragma unroll
@@ -260,7 +275,11 @@ __device__ void fitness_body(const FitLaunch& a, const int blk) {
                     gx[k] = xf_row(S[p][0], S[p][1], S[p][2], S[p][3], x[u].x, x[u].y, x[u].z);
                     gy[k] = xf_row(S[p][4], S[p][5], S[p][6], S[p][7], x[u].x, x[u].y, x[u].z);
                     gz[k] = xf_row(S[p][8], S[p][9], S[p][10], S[p][11], x[u].x, x[u].y, x[u].z);
-                    const bool in = nearest_offset<false>(g, ext, gx[k], gy[k], gz[k], &off[k]);
+                    bool in = nearest_offset<false>(g, ext, gx[k], gy[k], gz[k], &off[k]);
+                    if (in && brick_all_ones(pb, off[k])) {
+                        in = false;
+                        off[k] = 0xffffffffu;
+                    }
                     nout[p] += __builtin_popcountll(__builtin_amdgcn_ballot_w64(!in && okl[u]));
                     __builtin_amdgcn_sched_barrier(0);
                 }

@@ -52,20 +52,48 @@ __global__ __launch_bounds__(512) void k_integrate(IntegrateArgs a) {
     const float xc = xf_row(a.A[0], a.A[1], a.A[2], a.A[3], fi, fj, fk);
     const float yc = xf_row(a.A[4], a.A[5], a.A[6], a.A[7], fi, fj, fk);
     const float zc = xf_row(a.A[8], a.A[9], a.A[10], a.A[11], fi, fj, fk);
-    if (!(zc > 0.0f)) return;
-    const float pu = floorf(fmaf(a.fx, xc / zc, a.cx) + 0.5f);
-    const float pv = floorf(fmaf(a.fy, yc / zc, a.cy) + 0.5f);
-    if (!(pu >= 0.0f && pu < (float)a.W && pv >= 0.0f && pv < (float)a.H)) return;
-    const float D = a.depth[(uint32_t)pv * (uint32_t)a.W + (uint32_t)pu];
-    if (!(D > 0.0f)) return;
+    // every thread reaches the barrier below; `upd` marks the voxels that
+    // take this frame's measurement
+    bool upd = zc > 0.0f;
+    float pu = 0.0f, pv = 0.0f;
+    if (upd) {
+        pu = floorf(fmaf(a.fx, xc / zc, a.cx) + 0.5f);
+        pv = floorf(fmaf(a.fy, yc / zc, a.cy) + 0.5f);
+        upd = pu >= 0.0f && pu < (float)a.W && pv >= 0.0f && pv < (float)a.H;
+    }
+    float D = 0.0f;
+    if (upd) {
+        D = a.depth[(uint32_t)pv * (uint32_t)a.W + (uint32_t)pu];
+        upd = D > 0.0f;
+    }
     const float sdf = D - zc;
-    if (sdf < -g.mu) return;
-    const float d = fminf(1.0f, sdf / g.mu);
-    const uint32_t off = (b << 9) | t;
-    const float w0 = load_w<FMT>(g.wgt, off);
-    const float p0 = load_psi<FMT>(g.psi, off);
-    store_psi<FMT>(g.psi, off, fmaf(w0, p0, d) / (w0 + 1.0f));
-    store_w<FMT>(g.wgt, off, fminf(w0 + 1.0f, g.w_max));
+    upd = upd && !(sdf < -g.mu);
+    bool not_one = false;
+    if (upd) {
+        const float d = fminf(1.0f, sdf / g.mu);
+        const uint32_t off = (b << 9) | t;
+        const float w0 = load_w<FMT>(g.wgt, off);
+        const float p0 = load_psi<FMT>(g.psi, off);
+        store_psi<FMT>(g.psi, off, fmaf(w0, p0, d) / (w0 + 1.0f));
+        store_w<FMT>(g.wgt, off, fminf(w0 + 1.0f, g.w_max));
+        not_one = load_psi<FMT>(g.psi, off) != 1.0f;  // the stored value, decoded
+    }
+    // a brick with a value other than +1 leaves the all-ones set
+    if (__syncthreads_or(not_one) && t == 0) atomicAnd(&g.ones[b >> 5], ~(1u << (b & 31u)));
+}
+
+// the all-ones bit of every brick from the stored values (one block per
+// brick); words are cleared first by the caller
+template <int FMT>
+__global__ __launch_bounds__(512) void k_rescan(Grid g) {
+    const uint32_t b = blockIdx.x;
+    const bool one = load_psi<FMT>(g.psi, (b << 9) | threadIdx.x) == 1.0f;
+    if (__syncthreads_and(one) && threadIdx.x == 0) atomicOr(&g.ones[b >> 5], 1u << (b & 31u));
+}
+
+__global__ __launch_bounds__(256) void k_clear_words(uint32_t* w, uint32_t n) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) w[i] = 0u;
 }
 
 template <int FMT>
@@ -158,6 +186,19 @@ __global__ __launch_bounds__(256) void k_particle_poses(double qc0, double qc1, 
 
 // ------------------------------------------------------------ host helpers
 static uint64_t n_voxels(const Grid& g) { return (uint64_t)g.nx * g.ny * g.nz; }
+static uint32_t n_bricks(const Grid& g) { return (uint32_t)g.nbx * (uint32_t)g.nby * (uint32_t)g.nbz; }
+static uint32_t n_one_words(const Grid& g) { return (n_bricks(g) + 31u) / 32u; }
+
+// rebuild the all-ones bits of every brick from the stored values
+static rose_status rescan_ones(const Grid& g, hipStream_t s) {
+    const uint32_t w = n_one_words(g), nb = n_bricks(g);
+    hipLaunchKernelGGL(k_clear_words, dim3((w + 255) / 256), dim3(256), 0, s, g.ones, w);
+    if (g.fmt == ROSE_TSDF_F32) hipLaunchKernelGGL(k_rescan<ROSE_TSDF_F32>, dim3(nb), dim3(512), 0, s, g);
+    else if (g.fmt == ROSE_TSDF_F16) hipLaunchKernelGGL(k_rescan<ROSE_TSDF_F16>, dim3(nb), dim3(512), 0, s, g);
+    else hipLaunchKernelGGL(k_rescan<ROSE_TSDF_SN16>, dim3(nb), dim3(512), 0, s, g);
+    ROSE_CHECK_HIP(hipGetLastError());
+    return ROSE_OK;
+}
 
 }  // namespace rose
 
@@ -213,13 +254,20 @@ rose_status tsdf_create(int32_t nx, int32_t ny, int32_t nz, float voxel_m, float
         set_error("tsdf_create: hipGetDevice: %s", hipGetErrorString(e));
         return ROSE_E_DEVICE;
     }
+    e = hipMalloc((void**)&g.ones, sizeof(uint32_t) * (size_t)n_one_words(g));
+    if (e != hipSuccess) {
+        free(h);
+        set_error("tsdf_create: brick bits (%u words): %s", n_one_words(g), hipGetErrorString(e));
+        return ROSE_E_DEVICE;
+    }
     const uint64_t n = n_voxels(g);
     const unsigned blocks = (unsigned)((n + 255) / 256);
     if (fmt == ROSE_TSDF_F32) hipLaunchKernelGGL(k_fill<ROSE_TSDF_F32>, dim3(blocks), dim3(256), 0, s, g, n);
     else if (fmt == ROSE_TSDF_F16) hipLaunchKernelGGL(k_fill<ROSE_TSDF_F16>, dim3(blocks), dim3(256), 0, s, g, n);
     else hipLaunchKernelGGL(k_fill<ROSE_TSDF_SN16>, dim3(blocks), dim3(256), 0, s, g, n);
     e = hipGetLastError();
-    if (e != hipSuccess) {
+    if (e != hipSuccess || rescan_ones(g, s) != ROSE_OK) {
+        (void)hipFree(g.ones);
         free(h);
         set_error("tsdf_create: fill launch: %s", hipGetErrorString(e));
         return ROSE_E_DEVICE;
@@ -231,7 +279,8 @@ rose_status tsdf_create(int32_t nx, int32_t ny, int32_t nz, float voxel_m, float
 rose_status tsdf_destroy(rose_tsdf* h) {
     clear_error();
     if (h == nullptr) return ROSE_OK;
-    if (h->pts || h->partial || h->st || h->sw_x || h->n_orders) (void)hipDeviceSynchronize();
+    (void)hipDeviceSynchronize();  // kernels in flight may still read the handle's buffers
+    if (h->g.ones) (void)hipFree(h->g.ones);
     if (h->pts) (void)hipFree(h->pts);
     if (h->pts_o) (void)hipFree(h->pts_o);
     if (h->partial) (void)hipFree(h->partial);
@@ -314,7 +363,13 @@ rose_status tsdf_import(rose_tsdf* h, const float* psi_lin_dev, const float* wei
         hipLaunchKernelGGL(k_import<ROSE_TSDF_SN16>, dim3(blocks), dim3(256), 0, s, h->g, psi_lin_dev,
                            weight_lin_dev);
     ROSE_CHECK_HIP(hipGetLastError());
-    return ROSE_OK;
+    return rescan_ones(h->g, s);
+}
+
+rose_status tsdf_rescan(rose_tsdf* h, hipStream_t s) {
+    clear_error();
+    ROSE_REQUIRE(h, ROSE_E_ARG, "tsdf_rescan: NULL handle");
+    return rescan_ones(h->g, s);
 }
 
 }  // extern "C"

@@ -172,6 +172,7 @@ _sigs = {
     "rose_gather_peak": ([_P, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_uint32, _P, _S], C.c_int),
     "rose_gather_peak_loads_per_lane": ([], C.c_int32),
     "rose_l2_read_peak": ([_P, C.c_int64, C.c_int32, C.c_int32, C.c_int32, _P, _S], C.c_int),
+    "tsdf_rescan": ([_P, _S], C.c_int),
 }
 for _name, (_args, _res) in _sigs.items():
     _f = getattr(_lib, _name)
@@ -281,6 +282,10 @@ class Tsdf:
         p = pose(q, t)
         _check("tsdf_integrate", _lib.tsdf_integrate(self.handle, _ptr(depth), C.byref(cam), C.byref(p),
                                                      _stream(stream)))
+
+    def rescan(self, stream=None):
+        """Rebuild the handle's all-+1 brick bits after writing psi directly."""
+        _check("tsdf_rescan", _lib.tsdf_rescan(self.handle, _stream(stream)))
 
     def set_fitness_shape(self, particles_per_wave: int, points_per_lane: int):
         """This handle's own fitness launch shape ((0, 0): switching mode;

@@ -202,6 +202,41 @@ def test_fitness_shapes_parity(R, orc, shape):
     assert np.array_equal(F, Fo.astype(np.float32))
 
 
+@pytest.mark.parametrize("fmt", [0, 1])
+def test_fitness_all_ones_bricks(R, orc, fmt):
+    """Bricks holding only +1 are skipped by the points-across kernel (the
+    value is known): a volume with every other 8x8x8 brick set to +1 gives
+    the oracle's fitness bit for bit in every shape, and after the psi
+    buffer is overwritten directly, tsdf_rescan brings the bits up to date."""
+    rng = np.random.default_rng(41)
+    dims, vox, origin = (32, 24, 16), 0.04, (-0.64, -0.48, -0.32)
+    nx, ny, nz = dims
+    psi = rng.uniform(-1, 1, (nz, ny, nx)).astype(np.float32)
+    k, j, i = np.meshgrid(np.arange(nz) // 8, np.arange(ny) // 8, np.arange(nx) // 8, indexing="ij")
+    psi[(k + j + i) % 2 == 0] = 1.0
+    vol = R.Tsdf(dims, vox, 3 * vox, origin, fmt=fmt)
+    vol.load(dev(psi.ravel()))
+    ref = stored_values(psi, fmt)
+    pts = rng.uniform(-0.7, 0.7, (2999, 3)).astype(np.float32)
+    T = _random_poses(rng, 67)
+    Fo = orc.fitness(ref, vox, np.array(origin, np.float32), pts, T.astype(np.float64), lookup=0, prec=orc.F32)
+    try:
+        for shape in ((4, 4), (4, 8), (8, 4), (64, 8)):
+            vol.set_fitness_shape(*shape)
+            F, _ = R.fitness_eval(vol, dev(pts), dev(T), 0)
+            assert np.array_equal(host(F), Fo.astype(np.float32)), shape
+        # overwrite psi in place (all zeros: the same bytes in any layout), then rescan
+        vol.psi.zero_()
+        vol.rescan()
+        Fz = orc.fitness(np.zeros_like(ref), vox, np.array(origin, np.float32), pts, T.astype(np.float64),
+                         lookup=0, prec=orc.F32)
+        vol.set_fitness_shape(4, 4)
+        F, _ = R.fitness_eval(vol, dev(pts), dev(T), 0)
+        assert np.array_equal(host(F), Fz.astype(np.float32))
+    finally:
+        vol.close()
+
+
 @pytest.mark.parametrize("fmt", [0, 1, 2])
 @pytest.mark.parametrize("lookup", [0, 1])
 @pytest.mark.parametrize("n,m", [(1, 1), (5, 63), (67, 65), (130, 3001), (9, 0)])
