@@ -203,6 +203,21 @@ rose_status pst_particle_poses(const rose_pose* centre, const double r[6], const
 rose_status fitness_eval(rose_tsdf* h, const float* pts_dev, int32_t m, const float* T_dev, int32_t n,
                          rose_lookup lk, float* F_dev, float* rho_dev, hipStream_t s);
 
+/* fitness_eval for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same results (bit for bit) from the same kernels, but the packed
+ * points and the partial sums live in a fixed scratch array of the library
+ * (8 MiB per device, held from the first call on that device until the
+ * process ends) instead of the handle's scratch; the handle is not changed.
+ * No allocation, no free, no allocating library call.  Limits: m <=
+ * fitness_eval_noalloc_max_points() (131072), and n times the point slices
+ * the launch uses at most 786432 (ROSE_E_ARG otherwise, before anything is
+ * enqueued).  Calls that overlap on one device share the scratch and race:
+ * serialise them (one stream, or events).  Errors as fitness_eval, plus
+ * ROSE_E_DEVICE when the scratch address cannot be obtained. */
+rose_status fitness_eval_noalloc(const rose_tsdf* h, const float* pts_dev, int32_t m, const float* T_dev, int32_t n,
+                                 rose_lookup lk, float* F_dev, float* rho_dev, hipStream_t s);
+int32_t fitness_eval_noalloc_max_points(void);
 
 /* Diagnostic: the NEAREST voxel of every (pose, point) pair of fitness_eval
  * as a linear index (k*ny + j)*nx + i, or -1 outside the grid; idx_dev is

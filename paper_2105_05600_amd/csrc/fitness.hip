@@ -12,6 +12,7 @@
 // the wave with butterfly shuffles, and written as one partial sum per
 // (particle, slice); a second pass adds the slices in a fixed order.
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -896,6 +897,96 @@ rose_status fitness_eval(rose_tsdf* h, const float* pts_dev, int32_t m, const fl
     ROSE_CHECK_HIP(hipGetLastError());
     return ROSE_OK;
 }
+
+}  // extern "C"
+
+// ------------------------------------------------ allocation-free fitness
+// fitness_eval_noalloc keeps its scratch -- the packed points and the
+// (particle, slice) partial sums -- in one file-scope device array instead
+// of the handle's grown buffers.  Each device holds its own copy for the
+// life of the process; its address is looked up once per device, with that
+// device current, and kept.  Every slot the kernels read is written earlier
+// in the same call (the packing kernel writes the points, the fitness
+// kernels every (particle, slice) sum), so nothing needs clearing; calls
+// that overlap on one device share the array and race.
+namespace rose {
+constexpr int64_t kNoAllocPoints = 131072;    // 2 MiB of float4
+constexpr int64_t kNoAllocPartials = 786432;  // 6 MiB of grid sums
+struct NoAllocScratch {
+    float4 pts[kNoAllocPoints];
+    uint64_t partial[kNoAllocPartials];
+};
+static __device__ __align__(256) unsigned char scratch[sizeof(NoAllocScratch)];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static NoAllocScratch* g_scratch_ptr[kMaxDevices] = {};
+
+static rose_status noalloc_scratch(NoAllocScratch** out) {
+    int dev = 0;
+    ROSE_CHECK_HIP(hipGetDevice(&dev));
+    ROSE_REQUIRE(dev >= 0 && dev < kMaxDevices, ROSE_E_DEVICE, "fitness_eval_noalloc: device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        ROSE_REQUIRE(e == hipSuccess && p != nullptr, ROSE_E_DEVICE,
+                     "fitness_eval_noalloc: hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = (NoAllocScratch*)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return ROSE_OK;
+}
+}  // namespace rose
+
+extern "C" {
+
+rose_status fitness_eval_noalloc(const rose_tsdf* h, const float* pts_dev, int32_t m, const float* T_dev, int32_t n,
+                                 rose_lookup lk, float* F_dev, float* rho_dev, hipStream_t s) {
+    clear_error();
+    ROSE_REQUIRE(h && T_dev && F_dev && (pts_dev || m == 0), ROSE_E_ARG, "fitness_eval_noalloc: NULL argument");
+    ROSE_REQUIRE(n >= 1 && n <= ROSE_MAX_PARTICLES, ROSE_E_ARG, "fitness_eval_noalloc: n = %d out of [1, %d]", n,
+                 ROSE_MAX_PARTICLES);
+    ROSE_REQUIRE(m >= 0 && m <= kNoAllocPoints, ROSE_E_ARG, "fitness_eval_noalloc: m = %d out of [0, %lld]", m,
+                 (long long)kNoAllocPoints);
+    ROSE_REQUIRE(lk == ROSE_LOOKUP_NEAREST || lk == ROSE_LOOKUP_TRILINEAR, ROSE_E_ARG,
+                 "fitness_eval_noalloc: bad lookup");
+    int sp, su;
+    float thr, zref;
+    fit_launch_shape(h, lk, &sp, &su, &thr, &zref);
+    const int splits = choose_splits(n, m, h->g.fmt, sp);
+    ROSE_REQUIRE((int64_t)n * splits <= kNoAllocPartials, ROSE_E_ARG,
+                 "fitness_eval_noalloc: %d particles x %d point slices exceed the %lld partial sums of the scratch", n,
+                 splits, (long long)kNoAllocPartials);
+    NoAllocScratch* sc = nullptr;
+    rose_status st = noalloc_scratch(&sc);
+    if (st != ROSE_OK) return st;
+    if (m > 0) {
+        hipLaunchKernelGGL(k_pack_points, dim3((m + 255) / 256), dim3(256), 0, s, pts_dev, m, sc->pts);
+        ROSE_CHECK_HIP(hipGetLastError());
+    }
+    FitLaunch L{};
+    L.g = h->g;
+    L.pts = sc->pts;
+    L.count_dev = nullptr;
+    L.count = m;
+    L.T32 = T_dev;
+    L.n = n;
+    L.splits = splits;
+    L.lookup = lk;
+    L.partial = sc->partial;
+    L.shape_p = sp;
+    L.shape_u = su;
+    L.pl_thr = 0.0f;
+    st = launch_fitness(L, s);
+    if (st != ROSE_OK) return st;
+    hipLaunchKernelGGL(k_fitness_finish, dim3((n + 255) / 256), dim3(256), 0, s, sc->partial, n, splits, m, F_dev,
+                       rho_dev);
+    ROSE_CHECK_HIP(hipGetLastError());
+    return ROSE_OK;
+}
+
+int32_t fitness_eval_noalloc_max_points(void) { return (int32_t)kNoAllocPoints; }
 
 rose_status fitness_voxel_indices(const rose_tsdf* h, const float* pts_dev, int32_t m, const float* T_dev, int32_t n,
                                   int64_t* idx_dev, hipStream_t s) {

@@ -127,6 +127,8 @@ _sigs = {
     "pst_sample": ([C.c_int32, C.c_uint64, _P, _S], C.c_int),
     "pst_particle_poses": ([C.POINTER(Pose), _P, _P, C.c_int32, _P, _S], C.c_int),
     "fitness_eval": ([_P, _P, C.c_int32, _P, C.c_int32, C.c_int, _P, _P, _S], C.c_int),
+    "fitness_eval_noalloc": ([_P, _P, C.c_int32, _P, C.c_int32, C.c_int, _P, _P, _S], C.c_int),
+    "fitness_eval_noalloc_max_points": ([], C.c_int32),
     "fitness_voxel_indices": ([_P, _P, C.c_int32, _P, C.c_int32, _P, _S], C.c_int),
     "depth_unproject": ([_P, C.POINTER(Camera), C.c_int32, C.c_int32, _P, _P, _S], C.c_int),
     "rose_fitness_set_shape": ([C.c_int32, C.c_int32], C.c_int),
@@ -341,6 +343,22 @@ def fitness_eval(vol: Tsdf, pts: torch.Tensor, T: torch.Tensor, lookup: int = NE
     _check("fitness_eval", _lib.fitness_eval(vol.handle, _ptr(pts) if m else None, m, _ptr(T), n, lookup, _ptr(F),
                                              _ptr(rho), _stream(stream)))
     return F, rho
+
+
+def fitness_eval_noalloc(vol: Tsdf, pts: torch.Tensor, T: torch.Tensor, F: torch.Tensor, rho: torch.Tensor,
+                         lookup: int = NEAREST, stream=None):
+    """fitness_eval into caller-given F and rho (n float32 each) with the
+    library's fixed scratch: no device allocation by the library."""
+    _dev(pts, torch.float32, "pts")
+    _dev(T, torch.float32, "T")
+    _dev(F, torch.float32, "F")
+    _dev(rho, torch.float32, "rho")
+    m = pts.shape[0]
+    n = T.shape[0]
+    if F.numel() < n or rho.numel() < n:
+        raise ValueError("F and rho need n elements")
+    _check("fitness_eval_noalloc", _lib.fitness_eval_noalloc(vol.handle, _ptr(pts) if m else None, m, _ptr(T), n,
+                                                             lookup, _ptr(F), _ptr(rho), _stream(stream)))
 
 
 def voxel_indices(vol: Tsdf, pts: torch.Tensor, T: torch.Tensor, stream=None) -> torch.Tensor:

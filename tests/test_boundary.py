@@ -61,6 +61,14 @@ def test_host_side_argument_errors(R):
     assert lib.depth_unproject(C.c_void_p(16), C.byref(cam), 2, 5, C.c_void_p(16), C.c_void_p(16), None) == R.E_ARG
     assert lib.rose_fitness_set_shape(3, 3) == R.E_UNSUPPORTED
     assert lib.fitness_eval(None, None, 0, None, 1, 0, None, None, None) == R.E_ARG
+    v16 = C.c_void_p(16)
+    big = lib.fitness_eval_noalloc_max_points() + 1
+    assert lib.fitness_eval_noalloc_max_points() == 131072
+    assert lib.fitness_eval_noalloc(None, v16, 10, v16, 1, 0, v16, None, None) == R.E_ARG
+    assert lib.fitness_eval_noalloc(v16, v16, big, v16, 1, 0, v16, None, None) == R.E_ARG
+    assert b"out of [0, 131072]" in lib.rose_last_error()
+    assert lib.fitness_eval_noalloc(v16, v16, 10, v16, 0, 0, v16, None, None) == R.E_ARG
+    assert lib.fitness_eval_noalloc(v16, v16, 10, v16, 1, 7, v16, None, None) == R.E_ARG
     params = R.track_params(max_iters=0)
     st = R.track_state([1, 0, 0, 0], [0, 0, 0], [0.1] * 6)
     assert lib.pso_track_frame(C.c_void_p(16), C.c_void_p(16), C.byref(cam), C.c_void_p(16), 16, C.byref(params),
