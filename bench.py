@@ -291,14 +291,8 @@ def main():
         est.append(np.array(st.pose.t))
         return res
 
-    for i in range(1, 1 + args.warmup):
-        step(i)
-    torch.cuda.synchronize()
-    log(f"warmup {args.warmup} frames done")
-    # launch-shape tuning on the next frame: one tracked frame per compiled
-    # shape (from a copy of the state), fitness launches timed
-    from paper_2105_05600_amd import autotune
-    nxt = 1 + args.warmup
+    # the launch configuration is set before the warmup frames, so that they
+    # run the same kernels as the timed ones
     if args.switch:
         rose.set_fitness_switch(*(float(v) for v in args.switch.split(",")))
     wide = (4, 4)
@@ -309,8 +303,15 @@ def main():
         shp = tuple(int(v) for v in args.shape.split(","))
         rose.set_fitness_shape(*shp)
         tuned = {"shape": shp, "ms": {}, "cached": False}
-    else:
-        tuned = autotune.tune_track(vol, dev_depths[nxt], seq.K, pst, params, st)
+    for i in range(1, 1 + args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} frames done")
+    if args.shape == "tune":
+        # launch-shape tuning on the next frame: one tracked frame per
+        # compiled shape (from a copy of the state), fitness launches timed
+        from paper_2105_05600_amd import autotune
+        tuned = autotune.tune_track(vol, dev_depths[1 + args.warmup], seq.K, pst, params, st)
     log(f"fitness shape {tuned['shape']} ({'timed' if args.shape == 'tune' else 'given'}: {tuned['ms']})")
     rose.profile_enable(True)
     rose.profile_reset()

@@ -238,9 +238,15 @@ rose_status depth_unproject(const float* depth_dev, const rose_camera* cam, int3
 
 /* Overlap mask (Eq. validness): mask_dev[j] = 1 iff point j, moved to the
  * world by `centre` and into the previous camera by prev^-1, has z' > 0 and
- * projects inside [0, W-1] x [0, H-1].  m points, m x 3 float32. */
+ * projects inside [0, W-1] x [0, H-1] (binary32, continuous pixel
+ * coordinates).  m points, m x 3 float32.
+ * prev_depth_dev: NULL (the test is image bounds only), or the depth image
+ * of frame t-1 (H x W float32, device, caller-owned, read only) for the
+ * stricter reading of "inside the previous depth image": the pixel nearest to
+ * the projection, (floor(px + 1/2), floor(py + 1/2)) in binary32, must also
+ * hold a depth > 0. */
 rose_status overlap_mask(const float* pts_dev, int32_t m, const rose_pose* centre, const rose_pose* prev,
-                         const rose_camera* cam, uint8_t* mask_dev, hipStream_t s);
+                         const rose_camera* cam, const float* prev_depth_dev, uint8_t* mask_dev, hipStream_t s);
 
 /* --------------------------------------- learned-proposal inputs (a10) */
 /* Render the TSDF at camera pose T_wc through the given (low-resolution)
@@ -311,6 +317,9 @@ typedef struct {
 
 /* One frame of Alg. 1 (PFO with PST) on the device.
  * depth_dev: the current depth frame (cam->height x cam->width float32).
+ * prev_depth_dev: NULL, or the previous depth frame (same size, device,
+ * read only) for the stricter overlap test of overlap_mask (a point of O_k
+ * must also land on a valid pixel of frame t-1).
  * pst_dev: n_particles x 6 template from pst_sample (row 0 = origin).
  * init_centre: PST centre c_0 (NULL: state->pose, i.e. c_0 = s^{t-1}_*);
  * init_r: r_0 (NULL: state->r).  The overlap set always reprojects into the
@@ -331,9 +340,10 @@ typedef struct {
  * unchanged) when the frame has no valid point.
  * Limits: n_particles <= ROSE_MAX_PARTICLES; image <= ROSE_MAX_IMAGE_PIXELS.
  * A handle must not be used by two streams at once. */
-rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_camera* cam, const float* pst_dev,
-                            int32_t n_particles, const rose_track_params* p, const rose_pose* init_centre,
-                            const double* init_r, rose_track_state* state, rose_track_stats* stats, hipStream_t s);
+rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const float* prev_depth_dev,
+                            const rose_camera* cam, const float* pst_dev, int32_t n_particles,
+                            const rose_track_params* p, const rose_pose* init_centre, const double* init_r,
+                            rose_track_state* state, rose_track_stats* stats, hipStream_t s);
 
 /* ------------------------------------------- comparison optimisers */
 /* The two optimisers that Sec. 5 (ablation of the optimisation strategy)

@@ -173,7 +173,7 @@ def _load():
                                           C.c_int32, C.c_int, P]
             lib.orc_unproject.restype = C.c_int
             lib.orc_overlap.argtypes = [P, C.c_int32, P, P, C.c_float, C.c_float, C.c_float, C.c_float,
-                                        C.c_int32, C.c_int32, C.c_int, P]
+                                        C.c_int32, C.c_int32, P, C.c_int, P]
             lib.orc_overlap.restype = C.c_int
             lib.orc_fitness.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_float, P, P, C.c_int32, P, P,
                                         C.c_int32, C.c_int32, C.c_int, C.c_int, P]
@@ -186,7 +186,7 @@ def _load():
             lib.orc_pst_update.argtypes = [P, P, C.c_int32, P, P, P, C.c_double, C.c_double, C.c_double,
                                            C.c_int32, C.c_double, P, P, P, P, P, C.c_int32]
             lib.orc_pst_update.restype = C.c_int
-            lib.orc_track_frame.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_float, P, P, C.c_int32,
+            lib.orc_track_frame.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_float, P, P, P, C.c_int32,
                                             C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float, P, C.c_int32,
                                             P, P, P, P, P, C.c_int32, C.POINTER(_TrackParams), P, P, P, P, P,
                                             P, P, P, P, P, P, P]
@@ -320,14 +320,26 @@ def unproject(depth, K, stride: int, prec: int = F32) -> np.ndarray:
     return out[:m].copy()
 
 
-def overlap(pts, Tc, Tprev, K, prec: int = F32) -> np.ndarray:
+def _prev_depth(prev_depth, K):
+    if prev_depth is None:
+        return None
+    d = _f32(prev_depth)
+    if d.shape != (K.height, K.width):
+        raise ValueError(f"prev_depth must be {K.height} x {K.width}")
+    return d
+
+
+def overlap(pts, Tc, Tprev, K, prec: int = F32, prev_depth=None) -> np.ndarray:
+    """Overlap mask (Eq. validness); prev_depth: optional depth of frame
+    t-1, whose nearest pixel must then hold a valid depth as well."""
     lib = _load()
     pts = _f32(pts)
     Tc = _f64(np.asarray(Tc)[:3, :4])
     Tprev = _f64(np.asarray(Tprev)[:3, :4])
     mask = np.zeros(max(len(pts), 1), dtype=np.uint8)
-    lib.orc_overlap(_p(pts), len(pts), _p(Tc), _p(Tprev), K.fx, K.fy, K.cx, K.cy, K.width, K.height, prec,
-                    _p(mask))
+    pd = _prev_depth(prev_depth, K)
+    lib.orc_overlap(_p(pts), len(pts), _p(Tc), _p(Tprev), K.fx, K.fy, K.cx, K.cy, K.width, K.height,
+                    None if pd is None else _p(pd), prec, _p(mask))
     return mask[:len(pts)].astype(bool)
 
 
@@ -390,10 +402,12 @@ def pst_update(F, pst, r, qc, tc, tau=1.0, beta=0.1, eps=1e-3, tsdf_built=True, 
 
 def track_frame(psi, vox, origin, depth, K, pst, q_prev, t_prev, r_init, q_init=None, t_init=None,
                 tsdf_built=True, max_iters=20, early_stop=False, stride=4, lookup=NEAREST, flags=0, prec=F32,
-                beta=0.1, eps=1e-3, tau=1.0, stop_tol=1e-6, levels=None):
+                beta=0.1, eps=1e-3, tau=1.0, stop_tol=1e-6, levels=None, prev_depth=None):
     """One frame of Alg. 1.  levels: optional multi-resolution schedule
     [(n_particles, stride), ...] used in turn across the iterations (the
-    particles of a level are the first n rows of `pst`)."""
+    particles of a level are the first n rows of `pst`).  prev_depth:
+    optional depth of frame t-1 for the stricter overlap test (see
+    overlap)."""
     lib = _load()
     psi = _f32(psi)
     nz, ny, nx = psi.shape
@@ -417,7 +431,9 @@ def track_frame(psi, vox, origin, depth, K, pst, q_prev, t_prev, r_init, q_init=
     npts, nov = np.zeros(1, dtype=np.int32), np.zeros(1, dtype=np.int32)
     nov_it, rc_it, thr_it = np.zeros(32, dtype=np.int32), np.zeros(32), np.zeros(32)
     org = _f32(origin)
-    rc = lib.orc_track_frame(_p(psi), nx, ny, nz, float(vox), _p(org), _p(depth), W, H, K.fx, K.fy, K.cx, K.cy,
+    pd = _prev_depth(prev_depth, K)
+    rc = lib.orc_track_frame(_p(psi), nx, ny, nz, float(vox), _p(org), _p(depth),
+                             None if pd is None else _p(pd), W, H, K.fx, K.fy, K.cx, K.cy,
                              _p(pst), len(pst), _p(q_prev), _p(t_prev), _p(q_init), _p(t_init), _p(r_init),
                              int(tsdf_built), C.byref(P), _p(q_out), _p(t_out), _p(r1), _p(rho), _p(iters),
                              _p(aps), _p(rho_it), _p(npts), _p(nov), _p(nov_it), _p(rc_it), _p(thr_it))

@@ -425,10 +425,15 @@ void orc_pose_to_mat(const double q[4], const double t[3], double T[12]) {
 /* 0 <= fy y'/z' + cy <= H-1 (continuous pixel coordinates).                */
 /*   F32: A = T_prev^-1 T_c in binary64, rounded once; x' by xform_point;    */
 /*        px = fmaf(fx, x' / z', cx), py = fmaf(fy, y' / z', cy).           */
+/* Optional stricter reading of "in the previous depth image" (prev_depth  */
+/* non-NULL, the H x W depth frame t-1): the pixel nearest to (px, py),    */
+/* u = floor(px + 1/2), v = floor(py + 1/2) (in binary32 for F32), must     */
+/* also hold a valid depth (> 0).                                          */
 /* Writes mask[j] in {0,1}; returns |O_k|.                                   */
 /* ------------------------------------------------------------------------ */
 int orc_overlap(const float* pts, int32_t m, const double Tc[12], const double Tprev[12],
-                float fx, float fy, float cx, float cy, int32_t W, int32_t H, int prec, uint8_t* mask) {
+                float fx, float fy, float cx, float cy, int32_t W, int32_t H, const float* prev_depth, int prec,
+                uint8_t* mask) {
     double Ti[12], A[12];
     float A32[12];
     orc_rigid_inverse(Tprev, Ti);
@@ -446,6 +451,10 @@ int orc_overlap(const float* pts, int32_t m, const double Tc[12], const double T
                 float px = fmaf(fx, xp / zp, cx);
                 float py = fmaf(fy, yp / zp, cy);
                 keep = (px >= 0.0f && px <= (float)(W - 1) && py >= 0.0f && py <= (float)(H - 1));
+                if (keep && prev_depth) {
+                    const int32_t u = (int32_t)floorf(px + 0.5f), v = (int32_t)floorf(py + 0.5f);
+                    keep = prev_depth[(size_t)v * W + u] > 0.0f;
+                }
             }
         } else {
             if (!(o[2] > 0.0)) { keep = 0; }
@@ -453,6 +462,10 @@ int orc_overlap(const float* pts, int32_t m, const double Tc[12], const double T
                 double px = fx * (o[0] / o[2]) + cx;
                 double py = fy * (o[1] / o[2]) + cy;
                 keep = (px >= 0.0 && px <= (double)(W - 1) && py >= 0.0 && py <= (double)(H - 1));
+                if (keep && prev_depth) {
+                    const int32_t u = (int32_t)floor(px + 0.5), v = (int32_t)floor(py + 0.5);
+                    keep = prev_depth[(size_t)v * W + u] > 0.0f;
+                }
             }
         }
         mask[j] = (uint8_t)keep;
@@ -755,7 +768,9 @@ int orc_pst_update(const double* F, const float* pst, int32_t n, const double r_
 /* ------------------------------------------------------------------------ */
 /* One frame of Alg. 1 (PFO with PST), plain host loop.                      */
 /* Inputs: normalised TSDF psi (linear), depth of frame t (HxW, metres),    */
-/* intrinsics, stride, PST template (n x 6, row 0 = origin), previous final */
+/* optionally the depth of frame t-1 (prev_depth, NULL: the overlap test is */
+/* image bounds only; see orc_overlap), intrinsics, stride, PST template    */
+/* (n x 6, row 0 = origin), previous final                                  */
 /* pose s^{t-1}_* (q_prev, t_prev), PST initialisation c_0 (q_init, t_init) */
 /* and r_0 (r_init) (Sec. 4 "PST initialization": c_0 = s^{t-1}_*,          */
 /* r_0 = r_1^{t-1}).                                                         */
@@ -791,9 +806,10 @@ typedef struct {
 } orc_track_params;
 
 int orc_track_frame(const float* psi, int32_t nx, int32_t ny, int32_t nz, float vox, const float origin[3],
-                    const float* depth, int32_t W, int32_t H, float fx, float fy, float cx, float cy,
-                    const float* pst, int32_t n, const double q_prev[4], const double t_prev[3],
-                    const double q_init[4], const double t_init[3], const double r_init[6], int32_t tsdf_built,
+                    const float* depth, const float* prev_depth, int32_t W, int32_t H, float fx, float fy,
+                    float cx, float cy, const float* pst, int32_t n, const double q_prev[4],
+                    const double t_prev[3], const double q_init[4], const double t_init[3],
+                    const double r_init[6], int32_t tsdf_built,
                     const orc_track_params* P, double q_out[4], double t_out[3], double r1_out[6],
                     double* rho_out, int32_t* iters_out, int32_t* aps_sizes, double* rho_iter,
                     int32_t* n_points_out, int32_t* n_overlap_last, int32_t* n_overlap_iter,
@@ -848,7 +864,7 @@ int orc_track_frame(const float* psi, int32_t nx, int32_t ny, int32_t nz, float 
                 for (int32_t j = 0; j < m; ++j) mask[j] = 1;
                 nO = m;
             } else {
-                nO = orc_overlap(pts, m, Tc, Tprev, fx, fy, cx, cy, W, H, P->prec, mask);
+                nO = orc_overlap(pts, m, Tc, Tprev, fx, fy, cx, cy, W, H, prev_depth, P->prec, mask);
             }
             for (int32_t i = 0; i < n; ++i) orc_particle_pose(qc, tc, r, pst + 6 * (size_t)i, T + 12 * (size_t)i);
             orc_fitness_ex(psi, nx, ny, nz, vox, origin, pts, m, mask, T, n, P->lookup, P->prec,
@@ -1204,7 +1220,7 @@ int orc_swarm_frame(const float* psi, int32_t nx, int32_t ny, int32_t nz, float 
             for (int32_t j = 0; j < m; ++j) mask[j] = 1;
             nO = m;
         } else {
-            nO = orc_overlap(pts, m, Tb, Tprev, fx, fy, cx, cy, W, H, P->prec, mask);
+            nO = orc_overlap(pts, m, Tb, Tprev, fx, fy, cx, cy, W, H, NULL, P->prec, mask);
         }
         for (int32_t i = 0; i < n; ++i) orc_particle_pose(q_prev, t_prev, ones, x + 6 * (size_t)i, T + 12 * (size_t)i);
         orc_fitness(psi, nx, ny, nz, vox, origin, pts, m, mask, T, n, P->lookup, P->prec,

@@ -12,7 +12,9 @@ the same bench.py command, each pass in its own rocprofv3 run:
 `rocprofv3 --pmc ...` output directory per pass; --bench-json: the JSON line
 bench.py printed in the kernel-trace run (evaluations per fitness step);
 --copy-mib: the size of bench.py's --copy-probe, whose FETCH_SIZE and
-WRITE_SIZE readings scale those counters to bytes.
+WRITE_SIZE readings scale those counters to bytes.  --stats-out FILE also
+writes the kernel-trace statistics (per kernel: calls, average, min, max,
+share of GPU time) with bench.py's own timing of the same run beside them.
 
 A fitness step is one iteration's fitness launches (two in the switching
 mode: both kernels are launched, the one whose regime does not hold exits at
@@ -90,6 +92,34 @@ def pmc_steps(pmc_dir: str, n_steps: int, per: int):
     return out, copy
 
 
+def kernel_stats_md(trace_dir: str, bench: dict, dur_ns, names, command: str) -> str:
+    """Markdown summary of a `rocprofv3 --kernel-trace --stats` run."""
+    rows = list(_rows(os.path.join(trace_dir, "**", "*kernel_stats.csv")))
+    rf = bench["roofline"]
+    lines = ["# k_fitness on the 512^3 room sequence (640x480 stride 4, 10240 particles, 20 iterations)", "",
+             "rocprofv3 kernel-trace statistics of the default bench.py run (MI355X, gfx950, 256 CUs).", ""]
+    if command:
+        lines += ["Command (repository root, after `cd /tmp && export TMPDIR=/tmp` and back; `--no-cpu-baseline`",
+                  "only skips the host-side oracle timing):", "", "    " + command, ""]
+    lines += [f"Kernels of a fitness step: {', '.join('`' + n + '`' for n in names)}.", "",
+              "| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        name = r["Name"] if len(r["Name"]) <= 90 else r["Name"][:87] + "..."
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    ms = float(rf["avg_launch_ms"])
+    lines += ["", f"bench.py's HIP-event average per fitness step in the same run: {ms * 1e3:.1f} us; rocprofv3, "
+              f"the sum of the step's kernel durations over the same window: {dur_ns.mean() / 1e3:.1f} us.",
+              f"Algorithmic bytes per step: {rf['bytes_per_eval']:.0f} B x {rf['evals_per_launch']:.4g} "
+              f"particle-point evaluations = {rf['bytes_per_eval'] * rf['evals_per_launch'] / 1e6:.0f} MB -> "
+              f"{rf['achieved']:.0f} GB/s; measured L2 -> CU read peak {rf['peak']:.0f} GB/s (frac "
+              f"{rf['frac']:.3f}); vs the 8 TB/s HBM peak {rf['hbm']['frac']:.3f}.",
+              f"Bench line of this run: {bench['value']:.4g} {bench['unit']}, "
+              f"{bench['frames_per_s']:.1f} frames/s, fitness kernel "
+              f"{bench['fitness_kernel_evals_per_s']:.4g} evals/s."]
+    return "\n".join(lines) + "\n"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", required=True)
@@ -101,6 +131,8 @@ def main(argv=None):
     ap.add_argument("--iters", type=int, default=20)
     ap.add_argument("--command", default="")
     ap.add_argument("--out", required=True)
+    ap.add_argument("--stats-out", default=None)
+    ap.add_argument("--stats-command", default="")
     a = ap.parse_args(argv)
     n_steps = a.steps * a.iters
     with open(a.bench_json) as f:
@@ -197,6 +229,11 @@ def main(argv=None):
     with open(a.out, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
+    if a.stats_out:
+        md = kernel_stats_md(a.trace, bench, dur, names, a.stats_command)
+        with open(a.stats_out, "w") as f:
+            f.write(md)
+        print(md)
     return 0
 
 

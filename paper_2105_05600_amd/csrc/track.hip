@@ -321,7 +321,7 @@ rose_status depth_unproject(const float* depth_dev, const rose_camera* cam, int3
 }
 
 rose_status overlap_mask(const float* pts_dev, int32_t m, const rose_pose* centre, const rose_pose* prev,
-                         const rose_camera* cam, uint8_t* mask_dev, hipStream_t s) {
+                         const rose_camera* cam, const float* prev_depth_dev, uint8_t* mask_dev, hipStream_t s) {
     clear_error();
     ROSE_REQUIRE(pts_dev && centre && prev && mask_dev, ROSE_E_ARG, "overlap_mask: NULL argument");
     rose_status c = check_cam(cam, "overlap_mask");
@@ -329,7 +329,7 @@ rose_status overlap_mask(const float* pts_dev, int32_t m, const rose_pose* centr
     ROSE_REQUIRE(m >= 0 && m <= ROSE_MAX_IMAGE_PIXELS, ROSE_E_ARG, "overlap_mask: m out of range");
     if (m == 0) return ROSE_OK;
     OverlapArgs a;
-    a.cam = to_cam(cam);
+    a.cam = to_cam(cam, prev_depth_dev);
     double Tc[12], Tp[12], Ad[12];
     pose_matrix(centre->q, centre->t, Tc);
     pose_matrix(prev->q, prev->t, Tp);
@@ -343,10 +343,10 @@ rose_status overlap_mask(const float* pts_dev, int32_t m, const rose_pose* centr
     return ROSE_OK;
 }
 
-rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_camera* cam, const float* pst_dev,
-                            int32_t n_particles, const rose_track_params* p, const rose_pose* init_centre,
-                            const double* init_r, rose_track_state* state, rose_track_stats* stats,
-                            hipStream_t s) {
+rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const float* prev_depth_dev,
+                            const rose_camera* cam, const float* pst_dev, int32_t n_particles,
+                            const rose_track_params* p, const rose_pose* init_centre, const double* init_r,
+                            rose_track_state* state, rose_track_stats* stats, hipStream_t s) {
     clear_error();
     ROSE_REQUIRE(h && depth_dev && pst_dev && p && state, ROSE_E_ARG, "pso_track_frame: NULL argument");
     rose_status c = check_cam(cam, "pso_track_frame");
@@ -432,7 +432,7 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const rose_cam
     if (!h->st_host) ROSE_CHECK_HIP(hipHostMalloc(&h->st_host, sizeof(DevState), hipHostMallocDefault));
 
     ia.st = h->st;
-    ia.cam = to_cam(cam);
+    ia.cam = to_cam(cam, prev_depth_dev);
     ia.flags = p->flags;
     ia.pts = h->pts;
     ia.pts_o = h->pts_o;
@@ -996,7 +996,8 @@ rose_status pso_track_frame_learned(rose_tsdf* h, const float* depth_dev, const 
                  "pso_track_frame_learned: multi-resolution schedules are not supported here");
     if (fallback_out) *fallback_out = 0;
     if (!state->tsdf_built)
-        return pso_track_frame(h, depth_dev, cam, pst_plain_dev, n_plain, p, nullptr, nullptr, state, stats, s);
+        return pso_track_frame(h, depth_dev, nullptr, cam, pst_plain_dev, n_plain, p, nullptr, nullptr, state, stats,
+                               s);
     rose_camera low;
     low.fx = cam->fx / (float)lp->scale;
     low.fy = cam->fy / (float)lp->scale;
@@ -1029,7 +1030,7 @@ rose_status pso_track_frame_learned(rose_tsdf* h, const float* depth_dev, const 
         rose_track_state trial = *state;
         rose_track_params pl = *p;
         if (lp->iters > 0) pl.max_iters = lp->iters;
-        st = pso_track_frame(h, depth_dev, cam, pst_small_dev, n_small, &pl, &c0, r0, &trial, stats, s);
+        st = pso_track_frame(h, depth_dev, nullptr, cam, pst_small_dev, n_small, &pl, &c0, r0, &trial, stats, s);
         if (st == ROSE_OK && trial.rho >= state->rho - lp->delta) {
             *state = trial;
         } else if (st == ROSE_OK || st == ROSE_E_STATE) {
@@ -1040,7 +1041,8 @@ rose_status pso_track_frame_learned(rose_tsdf* h, const float* depth_dev, const 
     }
     if (fallback) {
         if (fallback_out) *fallback_out = 1;
-        return pso_track_frame(h, depth_dev, cam, pst_plain_dev, n_plain, p, nullptr, nullptr, state, stats, s);
+        return pso_track_frame(h, depth_dev, nullptr, cam, pst_plain_dev, n_plain, p, nullptr, nullptr, state, stats,
+                               s);
     }
     return ROSE_OK;
 }
@@ -1153,8 +1155,8 @@ rose_status pso_batch_track_learned(rose_batch* b, const float* const* depth_dev
         // fallback: plain PST from the unchanged state
         if (fallback_out) fallback_out[i] = 1;
         rose_track_stats fs;
-        st = pso_track_frame(b->h[i], depth_devs[i], &b->cams[i], pst_plain_devs[i], n_plain[i], &plain_params[i],
-                             nullptr, nullptr, &states[i], &fs, s);
+        st = pso_track_frame(b->h[i], depth_devs[i], nullptr, &b->cams[i], pst_plain_devs[i], n_plain[i],
+                             &plain_params[i], nullptr, nullptr, &states[i], &fs, s);
         if (st != ROSE_OK && st != ROSE_E_STATE) return st;
         fs.status = st;
         if (stats) stats[i] = fs;

@@ -10,6 +10,7 @@ namespace rose {
 struct Cam {
     float fx, fy, cx, cy;
     int32_t W, H;
+    const float* prev;  // depth of frame t-1 (H x W) for the stricter overlap test, or nullptr
 };
 
 // Eq. unproj in binary32: x = (((float)u - cx) z) / fx, y likewise.
@@ -19,7 +20,10 @@ __device__ inline float4 unproject_px(const Cam& c, int u, int v, float z) {
 
 // Eq. validness with A = T_prev^-1 T_c rounded to binary32:
 // x' = A x (fmaf chain); kept iff z' > 0 and the projection
-// (fmaf(fx, x'/z', cx), fmaf(fy, y'/z', cy)) lies in [0, W-1] x [0, H-1].
+// (fmaf(fx, x'/z', cx), fmaf(fy, y'/z', cy)) lies in [0, W-1] x [0, H-1];
+// with a previous depth image, also iff its pixel nearest to the projection,
+// (floor(px + 1/2), floor(py + 1/2)) in binary32, holds a depth > 0.  The
+// bounds test keeps that pixel inside the image.
 __device__ inline bool overlap_keep(const Cam& c, const float* A, float4 x) {
     const float xp = xf_row(A[0], A[1], A[2], A[3], x.x, x.y, x.z);
     const float yp = xf_row(A[4], A[5], A[6], A[7], x.x, x.y, x.z);
@@ -27,7 +31,10 @@ __device__ inline bool overlap_keep(const Cam& c, const float* A, float4 x) {
     if (!(zp > 0.0f)) return false;
     const float px = fmaf(c.fx, xp / zp, c.cx);
     const float py = fmaf(c.fy, yp / zp, c.cy);
-    return px >= 0.0f && px <= (float)(c.W - 1) && py >= 0.0f && py <= (float)(c.H - 1);
+    if (!(px >= 0.0f && px <= (float)(c.W - 1) && py >= 0.0f && py <= (float)(c.H - 1))) return false;
+    if (!c.prev) return true;
+    const int u = min((int)floorf(px + 0.5f), c.W - 1), v = min((int)floorf(py + 0.5f), c.H - 1);
+    return c.prev[(size_t)v * (size_t)c.W + (size_t)u] > 0.0f;
 }
 
 // Enumeration of the stride-s sample grid (su x sv samples).  Row-major
@@ -156,7 +163,9 @@ __device__ inline float final_fitness(const UpdateArgs& a, int i, int nO) {
 rose_status launch_track_init(const InitStatic& a, const FrameIn& in, hipStream_t s);
 rose_status launch_fitness_reduce(const UpdateArgs& a, hipStream_t s);
 
-inline Cam to_cam(const rose_camera* c) { return Cam{c->fx, c->fy, c->cx, c->cy, c->width, c->height}; }
+inline Cam to_cam(const rose_camera* c, const float* prev_depth = nullptr) {
+    return Cam{c->fx, c->fy, c->cx, c->cy, c->width, c->height, prev_depth};
+}
 
 inline rose_status check_cam(const rose_camera* c, const char* who) {
     ROSE_REQUIRE(c != nullptr, ROSE_E_ARG, "%s: NULL camera", who);

@@ -39,6 +39,19 @@ struct IntegrateArgs {
     const float* depth;
 };
 
+// The value store_psi<FMT> leaves in memory for v, decoded (computed here
+// rather than read back, which would cost a round trip to memory).
+template <int FMT>
+__device__ inline float stored_psi(float v) {
+    if constexpr (FMT == ROSE_TSDF_F32) {
+        return v;
+    } else if constexpr (FMT == ROSE_TSDF_F16) {
+        return __half2float(__float2half_rn(v));
+    } else {
+        return (float)(int16_t)rintf(fminf(fmaxf(v, -1.0f), 1.0f) * 32767.0f) * (1.0f / 32767.0f);
+    }
+}
+
 template <int FMT>
 __global__ __launch_bounds__(512) void k_integrate(IntegrateArgs a) {
     const Grid& g = a.g;
@@ -74,9 +87,10 @@ __global__ __launch_bounds__(512) void k_integrate(IntegrateArgs a) {
         const uint32_t off = (b << 9) | t;
         const float w0 = load_w<FMT>(g.wgt, off);
         const float p0 = load_psi<FMT>(g.psi, off);
-        store_psi<FMT>(g.psi, off, fmaf(w0, p0, d) / (w0 + 1.0f));
+        const float v = fmaf(w0, p0, d) / (w0 + 1.0f);
+        store_psi<FMT>(g.psi, off, v);
         store_w<FMT>(g.wgt, off, fminf(w0 + 1.0f, g.w_max));
-        not_one = load_psi<FMT>(g.psi, off) != 1.0f;  // the stored value, decoded
+        not_one = stored_psi<FMT>(v) != 1.0f;
     }
     // a brick with a value other than +1 leaves the all-ones set
     if (__syncthreads_or(not_one) && t == 0) atomicAnd(&g.ones[b >> 5], ~(1u << (b & 31u)));

@@ -136,8 +136,8 @@ _sigs = {
     "rose_fitness_set_switch_shape": ([C.c_int32, C.c_int32], C.c_int),
     "tsdf_set_fitness_shape": ([_P, C.c_int32, C.c_int32], C.c_int),
     "tsdf_set_fitness_switch": ([_P, C.c_float, C.c_float, C.c_int32, C.c_int32], C.c_int),
-    "overlap_mask": ([_P, C.c_int32, C.POINTER(Pose), C.POINTER(Pose), C.POINTER(Camera), _P, _S], C.c_int),
-    "pso_track_frame": ([_P, _P, C.POINTER(Camera), _P, C.c_int32, C.POINTER(TrackParams), C.POINTER(Pose), _P,
+    "overlap_mask": ([_P, C.c_int32, C.POINTER(Pose), C.POINTER(Pose), C.POINTER(Camera), _P, _P, _S], C.c_int),
+    "pso_track_frame": ([_P, _P, _P, C.POINTER(Camera), _P, C.c_int32, C.POINTER(TrackParams), C.POINTER(Pose), _P,
                          C.POINTER(TrackState), C.POINTER(TrackStats), _S], C.c_int),
     "tsdf_raycast": ([_P, C.POINTER(Pose), C.POINTER(Camera), C.c_double, C.c_double, C.c_double, _P, _S],
                      C.c_int),
@@ -382,15 +382,27 @@ def depth_unproject(depth: torch.Tensor, K, stride: int, tiled: bool = False, st
     return pts[: int(cnt.item())]
 
 
-def overlap_mask(pts: torch.Tensor, centre, prev, K, stream=None) -> torch.Tensor:
+def _prev_depth(prev_depth: Optional[torch.Tensor], cam):
+    """Device pointer of an optional previous depth frame (NULL when None)."""
+    if prev_depth is None:
+        return None
+    _dev(prev_depth, torch.float32, "prev_depth")
+    if prev_depth.numel() != cam.width * cam.height:
+        raise ValueError("prev_depth size does not match the camera")
+    return _ptr(prev_depth)
+
+
+def overlap_mask(pts: torch.Tensor, centre, prev, K, stream=None, prev_depth=None) -> torch.Tensor:
+    """Overlap mask (Eq. validness); prev_depth: optional depth of frame t-1
+    whose nearest pixel must then hold a valid depth as well."""
     _dev(pts, torch.float32, "pts")
     cam = camera(K)
     m = pts.shape[0]
     mask = torch.zeros(max(m, 1), dtype=torch.uint8, device=pts.device)
     c = pose(*centre)
     p = pose(*prev)
-    _check("overlap_mask", _lib.overlap_mask(_ptr(pts), m, C.byref(c), C.byref(p), C.byref(cam), _ptr(mask),
-                                             _stream(stream)))
+    _check("overlap_mask", _lib.overlap_mask(_ptr(pts), m, C.byref(c), C.byref(p), C.byref(cam),
+                                             _prev_depth(prev_depth, cam), _ptr(mask), _stream(stream)))
     return mask[:m].bool()
 
 
@@ -442,8 +454,9 @@ def track_state(q, t, r, tsdf_built=True, frame=0) -> TrackState:
 
 
 def track_frame(vol: Tsdf, depth: torch.Tensor, K, pst: torch.Tensor, params: TrackParams, state: TrackState,
-                init_centre=None, init_r=None, stream=None) -> dict:
-    """Run pso_track_frame; updates `state` in place and returns the stats."""
+                init_centre=None, init_r=None, stream=None, prev_depth=None) -> dict:
+    """Run pso_track_frame; updates `state` in place and returns the stats.
+    prev_depth: optional previous depth frame for the stricter overlap test."""
     _dev(depth, torch.float32, "depth")
     _dev(pst, torch.float32, "pst")
     cam = camera(K)
@@ -452,8 +465,9 @@ def track_frame(vol: Tsdf, depth: torch.Tensor, K, pst: torch.Tensor, params: Tr
     stats = TrackStats()
     c0 = C.byref(pose(*init_centre)) if init_centre is not None else None
     r0 = (C.c_double * 6)(*[float(v) for v in init_r]) if init_r is not None else None
-    st = _lib.pso_track_frame(vol.handle, _ptr(depth), C.byref(cam), _ptr(pst), pst.shape[0], C.byref(params), c0,
-                              r0, C.byref(state), C.byref(stats), _stream(stream))
+    st = _lib.pso_track_frame(vol.handle, _ptr(depth), _prev_depth(prev_depth, cam), C.byref(cam), _ptr(pst),
+                              pst.shape[0], C.byref(params), c0, r0, C.byref(state), C.byref(stats),
+                              _stream(stream))
     _check("pso_track_frame", st)
     it = stats.iters
     return dict(iters=it, n_points=stats.n_points, n_overlap_last=stats.n_overlap_last,

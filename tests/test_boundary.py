@@ -71,22 +71,22 @@ def test_host_side_argument_errors(R):
     assert lib.fitness_eval_noalloc(v16, v16, 10, v16, 1, 7, v16, None, None) == R.E_ARG
     params = R.track_params(max_iters=0)
     st = R.track_state([1, 0, 0, 0], [0, 0, 0], [0.1] * 6)
-    assert lib.pso_track_frame(C.c_void_p(16), C.c_void_p(16), C.byref(cam), C.c_void_p(16), 16, C.byref(params),
-                               None, None, C.byref(st), None, None) == R.E_ARG
+    assert lib.pso_track_frame(C.c_void_p(16), C.c_void_p(16), None, C.byref(cam), C.c_void_p(16), 16,
+                               C.byref(params), None, None, C.byref(st), None, None) == R.E_ARG
     params = R.track_params(max_iters=10)
-    assert lib.pso_track_frame(C.c_void_p(16), C.c_void_p(16), C.byref(cam), C.c_void_p(16), 0, C.byref(params),
-                               None, None, C.byref(st), None, None) == R.E_ARG
+    assert lib.pso_track_frame(C.c_void_p(16), C.c_void_p(16), None, C.byref(cam), C.c_void_p(16), 0,
+                               C.byref(params), None, None, C.byref(st), None, None) == R.E_ARG
     params = R.track_params(levels=[(8, 2), (16, 3)])
-    assert lib.pso_track_frame(C.c_void_p(16), C.c_void_p(16), C.byref(cam), C.c_void_p(16), 12, C.byref(params),
-                               None, None, C.byref(st), None, None) == R.E_ARG  # level larger than the template
+    assert lib.pso_track_frame(C.c_void_p(16), C.c_void_p(16), None, C.byref(cam), C.c_void_p(16), 12,
+                               C.byref(params), None, None, C.byref(st), None, None) == R.E_ARG  # level larger than the template
     assert b"level 1" in lib.rose_last_error()
     params = R.track_params(flags=R.FLAG_ISO_ONLY | R.FLAG_ANISO_ONLY)
-    assert lib.pso_track_frame(C.c_void_p(16), C.c_void_p(16), C.byref(cam), C.c_void_p(16), 16, C.byref(params),
-                               None, None, C.byref(st), None, None) == R.E_ARG
+    assert lib.pso_track_frame(C.c_void_p(16), C.c_void_p(16), None, C.byref(cam), C.c_void_p(16), 16,
+                               C.byref(params), None, None, C.byref(st), None, None) == R.E_ARG
     params = R.track_params(levels=[(8, 2), (16, 3)])
     params.levels = R.MAX_LEVELS + 1
-    assert lib.pso_track_frame(C.c_void_p(16), C.c_void_p(16), C.byref(cam), C.c_void_p(16), 16, C.byref(params),
-                               None, None, C.byref(st), None, None) == R.E_ARG
+    assert lib.pso_track_frame(C.c_void_p(16), C.c_void_p(16), None, C.byref(cam), C.c_void_p(16), 16,
+                               C.byref(params), None, None, C.byref(st), None, None) == R.E_ARG
     assert lib.rose_profile_read(None) == R.E_ARG
     assert lib.rose_gather_peak(C.c_void_p(16), 1 << 20, 3000, 8, 1, 1, C.c_void_p(16), None) == R.E_ARG
     assert lib.rose_gather_peak(C.c_void_p(16), 1 << 10, 4096, 8, 1, 1, C.c_void_p(16), None) == R.E_SHAPE

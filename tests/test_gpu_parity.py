@@ -137,6 +137,30 @@ def test_overlap_mask_bit_exact(R, orc):
         assert np.array_equal(g, o)
 
 
+def test_overlap_mask_prev_depth_bit_exact(R, orc):
+    """The stricter overlap test (valid depth at the nearest pixel of frame
+    t-1) on the GPU equals the oracle's mask bit for bit, with holes (zero,
+    negative, NaN) in the previous depth image."""
+    room = synth.unit_box_room(2105)
+    K = synth.Intrinsics.centred(160, 120, 140.0)
+    rng = np.random.default_rng(9)
+    prev = synth.Pose(synth.look_rotation([0.6, 0.5, 0.4]), np.array([0.01, -0.02, 0.0]))
+    prev_depth = synth.render_depth(room, K, prev)
+    prev_depth[rng.random(prev_depth.shape) < 0.25] = 0.0
+    prev_depth[30:50, 20:60] = np.nan
+    prev_depth[90:100, 100:140] = -2.0
+    for _ in range(4):
+        cur = synth.Pose(synth.axis_angle(rng.standard_normal(3), 0.15) @ prev.R, prev.t + rng.uniform(-0.1, 0.1, 3))
+        depth = synth.render_depth(room, K, cur)
+        pts = orc.unproject(depth, K, 1, orc.F32)
+        g = host(R.overlap_mask(dev(pts), (cur.q, cur.t), (prev.q, prev.t), K, prev_depth=dev(prev_depth)))
+        o = orc.overlap(pts, orc.pose_mat(cur.q, cur.t), orc.pose_mat(prev.q, prev.t), K, orc.F32,
+                        prev_depth=prev_depth)
+        b = orc.overlap(pts, orc.pose_mat(cur.q, cur.t), orc.pose_mat(prev.q, prev.t), K, orc.F32)
+        assert 0 < o.sum() < b.sum()
+        assert np.array_equal(g, o)
+
+
 # ------------------------------------------------- a5 voxel indices, fitness
 def stored_values(psi, fmt):
     """psi (binary32) as the storage format holds it, from the formats'
@@ -409,6 +433,31 @@ def test_track_frame_flags_parity(R, orc, small_gpu, flags, early):
     o = orc.track_frame(psi, w.vox, w.origin, w.depth, w.K, pst, prev.q, prev.t, np.full(6, 0.1), max_iters=12,
                         stride=w.stride, flags=flags, early_stop=early, prec=orc.F32)
     assert g["iters"] == o["iters"]
+    assert list(g["aps"]) == list(o["aps"])
+    assert np.linalg.norm(np.array(g["t"]) - o["t"]) <= 1e-4
+    assert _rot_err(g["q"], o["q"]) <= 1e-4
+
+
+def test_track_frame_prev_depth_parity(R, orc, small_gpu):
+    """pso_track_frame with the previous depth frame (holes punched into the
+    last fusion depth): every O_k size, APS size and the pose equal the
+    oracle's, and the option does change the overlap sets."""
+    w, vol, psi, pst = small_gpu
+    prev = w.fuse_poses[-1]
+    rng = np.random.default_rng(11)
+    prev_depth = w.fuse_depths[-1].copy()
+    prev_depth[rng.random(prev_depth.shape) < 0.2] = 0.0
+    prev_depth[20:70, 30:90] = 0.0
+    params = R.track_params(max_iters=w.iters, stride=w.stride)
+    st = R.track_state(prev.q, prev.t, [0.1] * 6)
+    g = R.track_frame(vol, dev(w.depth), w.K, dev(pst), params, st, prev_depth=dev(prev_depth))
+    o = orc.track_frame(psi, w.vox, w.origin, w.depth, w.K, pst, prev.q, prev.t, np.full(6, 0.1),
+                        max_iters=w.iters, stride=w.stride, prec=orc.F32, prev_depth=prev_depth)
+    b = orc.track_frame(psi, w.vox, w.origin, w.depth, w.K, pst, prev.q, prev.t, np.full(6, 0.1),
+                        max_iters=w.iters, stride=w.stride, prec=orc.F32)
+    assert o["n_overlap"][0] < b["n_overlap"][0]
+    assert g["iters"] == o["iters"]
+    assert list(g["n_overlap"]) == list(o["n_overlap"])
     assert list(g["aps"]) == list(o["aps"])
     assert np.linalg.norm(np.array(g["t"]) - o["t"]) <= 1e-4
     assert _rot_err(g["q"], o["q"]) <= 1e-4

@@ -85,6 +85,85 @@ def test_overlap_backward_motion_closed_form(orc, room):
     assert m_f.all()
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_overlap_prev_depth_identity_drops_exactly_the_holes(orc, room, prec):
+    """Identity motion: every point projects back onto the pixel it came
+    from, so the stricter test (a valid depth at the nearest pixel of frame
+    t-1) keeps exactly the bounds-only set minus the points whose own pixel
+    is a hole (zero, negative or NaN) of the previous depth image."""
+    K = synth.Intrinsics.centred(160, 120, 140.0)
+    pose = _look([0.6, 0.5, 0.4], [0.0, 0.0, 0.0])
+    depth = synth.render_depth(room, K, pose)
+    prev = depth.copy()
+    rng = np.random.default_rng(7)
+    prev[rng.random(prev.shape) < 0.3] = 0.0
+    prev[40:60, 70:100] = np.nan
+    prev[80:90, 10:30] = -1.0
+    pts = orc.unproject(depth, K, 1, prec)
+    v, u = np.nonzero(depth > 0)  # the unprojection's row-major order
+    base = orc.overlap(pts, pose.mat(), pose.mat(), K, prec)
+    mask = orc.overlap(pts, pose.mat(), pose.mat(), K, prec, prev_depth=prev)
+    valid = prev[v, u] > 0
+    assert 0 < valid.sum() < len(valid)
+    assert np.array_equal(mask, base & valid)
+    interior = (u > 0) & (u < K.width - 1) & (v > 0) & (v < K.height - 1)
+    assert base[interior].all()
+    # an all-valid previous image changes nothing
+    assert np.array_equal(orc.overlap(pts, pose.mat(), pose.mat(), K, prec, prev_depth=np.ones_like(prev)), base)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("shift", [3.4, 3.6])
+def test_overlap_prev_depth_nearest_pixel_of_a_lateral_shift(orc, prec, shift):
+    """A fronto-parallel plane at depth Z seen from frame t, whose camera
+    sits (s_x, s_y) = (shift Z / fx, 0.3 Z / fy) beside frame t-1's (same
+    rotation): pixel (u, v) lands at (u + shift, v + 0.3) of frame t-1, whose
+    nearest pixel is (u + round(shift), v).  With an invalid column band
+    [40, 50) in the previous depth image the stricter test drops exactly the
+    columns u with u + round(shift) in the band; the bounds test drops
+    u + shift > W - 1 and the last row (v + 0.3 > H - 1)."""
+    K = synth.Intrinsics.centred(96, 64, 80.0)
+    Z = 2.0
+    uu, vv = np.meshgrid(np.arange(K.width), np.arange(K.height))
+    u, v = uu.ravel(), vv.ravel()
+    pts = np.column_stack([(u - K.cx) * Z / K.fx, (v - K.cy) * Z / K.fy, np.full(u.size, Z)]).astype(np.float32)
+    prev_pose = _look([0.3, -0.8, 0.2], [0.1, 0.2, -0.05])
+    cur = synth.Pose(prev_pose.R, prev_pose.t + (shift * Z / K.fx) * prev_pose.R[:, 0]
+                     + (0.3 * Z / K.fy) * prev_pose.R[:, 1])
+    prev = np.ones((K.height, K.width), np.float32)
+    prev[:, 40:50] = 0.0
+    mask = orc.overlap(pts, cur.mat(), prev_pose.mat(), K, prec, prev_depth=prev)
+    base = orc.overlap(pts, cur.mat(), prev_pose.mat(), K, prec)
+    in_view = (u + shift <= K.width - 1) & (v < K.height - 1)
+    assert np.array_equal(base, in_view)
+    near = u + int(round(shift))
+    assert np.array_equal(mask, in_view & ~((near >= 40) & (near < 50)))
+
+
+def test_track_frame_prev_depth_special_cases(orc):
+    """Tracking with the stricter overlap test: an all-valid previous depth
+    image gives the bounds-only result exactly; an all-invalid one empties
+    every O_k, so every particle scores F = 1 (Eq. normallh over an empty
+    set), the APS stays empty and the pose does not move."""
+    w = synth.small_frame()
+    nx, ny, nz = w.dims
+    psi = np.ones((nz, ny, nx), np.float32)
+    wt = np.zeros_like(psi)
+    for p, d in zip(w.fuse_poses, w.fuse_depths):
+        orc.integrate(psi, wt, w.vox, w.origin, w.mu, d, w.K, p.q, p.t, prec=orc.F32)
+    pst, _ = orc.pst_sample(256, 5)
+    prev = w.fuse_poses[-1]
+    args = (psi, w.vox, w.origin, w.depth, w.K, pst, prev.q, prev.t, np.full(6, 0.1))
+    kw = dict(max_iters=6, stride=4, prec=orc.F32)
+    a = orc.track_frame(*args, **kw)
+    b = orc.track_frame(*args, prev_depth=np.ones_like(w.depth), **kw)
+    for key in ("q", "t", "r1", "aps", "n_overlap", "rho_iter"):
+        assert np.array_equal(a[key], b[key]), key
+    c = orc.track_frame(*args, prev_depth=np.zeros_like(w.depth), **kw)
+    assert c["status"] == 0 and (c["n_overlap"] == 0).all() and (c["aps"] == 0).all()
+    assert np.array_equal(c["t"], prev.t) and np.array_equal(c["q"], prev.q)
+
+
 # ---------------------------------------------------------------- fitness
 def test_fitness_plane_field_trilinear(orc):
     """psi(X) = (c - X_z)/mu is linear, so trilinear lookup is exact and a
