@@ -66,6 +66,8 @@ def parse():
                     help="switching-mode threshold: footprint in voxels, reference depth in metres")
     ap.add_argument("--switch-shape", default=None, metavar="P,U",
                     help="switching mode: the points-across shape used above the threshold (default 4,4)")
+    ap.add_argument("--dump-poses", default=None, metavar="FILE",
+                    help="write every frame's estimated and true pose (JSON) to FILE")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="before warmup, run a float32 copy of MIB MiB three times (counter calibration)")
     return ap.parse_args()
@@ -284,11 +286,13 @@ def main():
     vol.integrate(dev_depths[0], seq.K, p0.q, p0.t)
     st.tsdf_built = 1
     est = [np.array(p0.t)]
+    est_q = [np.array(p0.q)]
 
     def step(i):
         res = rose.track_frame(vol, dev_depths[i], seq.K, pst, params, st)
         vol.integrate(dev_depths[i], seq.K, st.pose.q, st.pose.t)
         est.append(np.array(st.pose.t))
+        est_q.append(np.array(st.pose.q))
         return res
 
     # the launch configuration is set before the warmup frames, so that they
@@ -331,6 +335,11 @@ def main():
     gt = np.array([p.t for p in seq.poses[:n_frames]])
     est_a = np.array(est)
     ate_mean, ate_rmse = synth.ate(est_a, gt)
+    if args.dump_poses:
+        with open(args.dump_poses, "w") as f:
+            json.dump({"t_est": est_a.tolist(), "q_est": np.array(est_q).tolist(), "t_true": gt.tolist(),
+                       "q_true": [list(map(float, p.q)) for p in seq.poses[:n_frames]],
+                       "ate_mean_m": ate_mean, "ate_rmse_m": ate_rmse}, f)
     fit_ms = prof["fitness_ms"] / max(prof["fitness_launches"], 1)
     fit_evals = prof["fitness_evals"] / max(prof["fitness_launches"], 1)
     bytes_per_eval = BYTES_PER_EVAL[lookup] * (1.0 if fmt == 0 else 0.5)

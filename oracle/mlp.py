@@ -11,6 +11,13 @@ Adam (Kingma & Ba 2015) on binary64 copies of the parameters.
 
 Parameter layout (shared with the GPU binding): W1 (1216, 256), b1 (256),
 W2 (256, 256), b2 (256), W3 (256, 12), b3 (12); y = x W + b (row vectors).
+
+bf16=True: every matrix product takes its two operands rounded to bfloat16
+first (binary32, then round to nearest even on the upper 16 bits: the
+rounding the matrix cores' inputs go through), then multiplies them in
+binary64; everything else is unchanged.  Pinned: the rounding's ties go to
+even and it is the identity on bfloat16 values; products of bfloat16-exact
+operands equal the plain ones.
 """
 from __future__ import annotations
 
@@ -30,14 +37,29 @@ def gelu_grad(z):
     return 0.5 * (1.0 + erf(z / math.sqrt(2.0))) + z * np.exp(-0.5 * z * z) / math.sqrt(2.0 * math.pi)
 
 
-def forward(p, X):
+def bf16_round(a) -> np.ndarray:
+    """a rounded to binary32, then to bfloat16 (nearest, ties to even), as
+    binary64 values."""
+    u = np.asarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + np.uint64(0x7FFF) + ((u >> np.uint64(16)) & np.uint64(1))) >> np.uint64(16)) << np.uint64(16)
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def mm(A, B, bf16: bool = False):
+    """A @ B in binary64; bf16: operands rounded to bfloat16 first."""
+    if bf16:
+        return bf16_round(A) @ bf16_round(B)
+    return A @ B
+
+
+def forward(p, X, bf16: bool = False):
     """Returns (out (B, 12), cache)."""
     X = np.asarray(X, np.float64)
-    Z1 = X @ p["W1"] + p["b1"]
+    Z1 = mm(X, p["W1"], bf16) + p["b1"]
     H1 = gelu(Z1)
-    Z2 = H1 @ p["W2"] + p["b2"]
+    Z2 = mm(H1, p["W2"], bf16) + p["b2"]
     H2 = gelu(Z2)
-    out = H2 @ p["W3"] + p["b3"]
+    out = mm(H2, p["W3"], bf16) + p["b3"]
     return out, (X, Z1, H1, Z2, H2)
 
 
@@ -54,24 +76,24 @@ def loss_and_dout(out, Y):
     return loss, np.concatenate([dmu, dls], axis=1)
 
 
-def backward(p, cache, dout):
+def backward(p, cache, dout, bf16: bool = False):
     X, Z1, H1, Z2, H2 = cache
     g = {}
-    g["W3"] = H2.T @ dout
+    g["W3"] = mm(H2.T, dout, bf16)
     g["b3"] = dout.sum(0)
-    dZ2 = (dout @ p["W3"].T) * gelu_grad(Z2)
-    g["W2"] = H1.T @ dZ2
+    dZ2 = mm(dout, p["W3"].T, bf16) * gelu_grad(Z2)
+    g["W2"] = mm(H1.T, dZ2, bf16)
     g["b2"] = dZ2.sum(0)
-    dZ1 = (dZ2 @ p["W2"].T) * gelu_grad(Z1)
-    g["W1"] = X.T @ dZ1
+    dZ1 = mm(dZ2, p["W2"].T, bf16) * gelu_grad(Z1)
+    g["W1"] = mm(X.T, dZ1, bf16)
     g["b1"] = dZ1.sum(0)
     return g
 
 
-def loss_and_grads(p, X, Y):
-    out, cache = forward(p, X)
+def loss_and_grads(p, X, Y, bf16: bool = False):
+    out, cache = forward(p, X, bf16)
     loss, dout = loss_and_dout(out, Y)
-    return loss, backward(p, cache, dout)
+    return loss, backward(p, cache, dout, bf16)
 
 
 def adam_step(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):

@@ -10,7 +10,7 @@
 
 namespace rose {
 
-typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
 // float -> bfloat16, round to nearest even (NaN kept quiet)
@@ -45,14 +45,16 @@ struct GemmArgs {
 
 constexpr int kGT = 64;  // block tile (M and N)
 constexpr int kKT = 32;  // K tile
+constexpr int kKP = kKT + 8;  // LDS row pitch (elements): 80-byte rows keep 16-byte reads aligned
 
 // 256 threads = 2x2 wavefronts, each owning a 32x32 sub-tile computed with
-// v_mfma_f32_32x32x8bf16_1k.  Operand layout of that instruction: lane l
-// holds A[l % 32][4 (l / 32) .. +3] and B[4 (l / 32) .. +3][l % 32]; the 16
-// accumulators of lane l are D[8 (i / 4) + 4 (l / 32) + i % 4][l % 32].
+// gfx950's double-K v_mfma_f32_32x32x16_bf16 (K = 16 per instruction).
+// Operand layout: lane l holds A[l % 32][8 (l / 32) .. +7] and
+// B[8 (l / 32) .. +7][l % 32]; the 16 accumulators of lane l are
+// D[8 (i / 4) + 4 (l / 32) + i % 4][l % 32].
 __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
-    __shared__ unsigned short As[kGT][kKT + 4];
-    __shared__ unsigned short Bs[kGT][kKT + 4];  // transposed: [n][k]
+    __shared__ __attribute__((aligned(16))) unsigned short As[kGT][kKP];
+    __shared__ __attribute__((aligned(16))) unsigned short Bs[kGT][kKP];  // transposed: [n][k]
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wm = wave >> 1, wn = wave & 1;
     const int m0 = blockIdx.y * kGT, n0 = blockIdx.x * kGT;
@@ -72,15 +74,15 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
         }
         __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < kKT; kk += 8) {
-            const int ml = wm * 32 + (lane & 31), nl = wn * 32 + (lane & 31), kb = kk + 4 * (lane >> 5);
-            bf16x4_t a, b;
+        for (int kk = 0; kk < kKT; kk += 16) {
+            const int ml = wm * 32 + (lane & 31), nl = wn * 32 + (lane & 31), kb = kk + 8 * (lane >> 5);
+            bf16x8_t a, b;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                a[q] = (short)As[ml][kb + q];
-                b[q] = (short)Bs[nl][kb + q];
+            for (int q = 0; q < 8; ++q) {
+                a[q] = __builtin_bit_cast(__bf16, As[ml][kb + q]);
+                b[q] = __builtin_bit_cast(__bf16, Bs[nl][kb + q]);
             }
-            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
         }
         __syncthreads();
     }

@@ -124,7 +124,10 @@ def render_depth(scene: Scene, K: Intrinsics, pose: Pose, zmin: float = 0.0, zma
     of standard deviation noise_k * z^2 is added (seeded).
     """
     dc = pixel_rays(K)
-    dw = dc @ pose.R.T
+    # elementwise in a fixed order (a BLAS product may round differently with
+    # its threading, which would make the frames differ between runs)
+    R = pose.R
+    dw = dc[:, 0:1] * R[:, 0] + dc[:, 1:2] * R[:, 1] + dc[:, 2:3] * R[:, 2]
     z = scene.raycast(pose.t, dw)
     if noise_k > 0:
         rng = np.random.default_rng(noise_seed)

@@ -93,11 +93,12 @@ class Scene:
                               np.where(da < 0, (self.room_lo[a] - o[a]) / da, np.inf))
                 ta = np.where(ta > 0, ta, np.inf)
                 t = np.minimum(t, ta)
-            dd = np.einsum("ij,ij->i", d, d)
+            # dot products written out (no BLAS: its rounding may depend on threading)
+            dd = d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1] + d[:, 2] * d[:, 2]
             for s in self.spheres:
                 oc = o - s.c
-                b = d @ oc
-                cc = oc @ oc - s.r * s.r
+                b = d[:, 0] * oc[0] + d[:, 1] * oc[1] + d[:, 2] * oc[2]
+                cc = oc[0] * oc[0] + oc[1] * oc[1] + oc[2] * oc[2] - s.r * s.r
                 disc = b * b - dd * cc
                 sq = np.sqrt(np.maximum(disc, 0.0))
                 t0 = (-b - sq) / dd

@@ -107,10 +107,19 @@ def net(R):
 
 
 def test_mlp_forward_vs_oracle(R, net):
+    """Against the oracle with the same BF16 operand rounding the matrix
+    cores apply (binary64 products): only the binary32 accumulation and
+    elementwise arithmetic differ, rel. L2 <= 1e-4; against the plain
+    binary64 network the BF16 operands cost ~1 %."""
     m, p, X, _ = net
     out = m.forward(m.pack(p), torch.from_numpy(X).cuda()).cpu().numpy()
-    ref, _ = omlp.forward({k: v.astype(np.float64) for k, v in p.items()}, X)
+    p64 = {k: v.astype(np.float64) for k, v in p.items()}
+    ref, _ = omlp.forward(p64, X, bf16=True)
     cos, rel = _cos_rel(out, ref)
+    print(f"forward vs the BF16-operand oracle: cos {cos:.9f}, rel {rel:.3e}")
+    assert cos >= 0.9999999 and rel <= 1e-4
+    ref64, _ = omlp.forward(p64, X)
+    cos, rel = _cos_rel(out, ref64)
     assert cos >= 0.999 and rel <= 1e-2
 
 
@@ -121,12 +130,17 @@ def test_mlp_gradients_vs_oracle(R, net):
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
     m.loss_grad(P, torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(), G, loss)
     gl = float(loss.item())
-    ol, og = omlp.loss_and_grads({k: v.astype(np.float64) for k, v in p.items()}, X, Y)
-    assert abs(gl - ol) <= 2e-2 * abs(ol)  # BF16 operands: ~1% output error
+    p64 = {k: v.astype(np.float64) for k, v in p.items()}
+    ol, og = omlp.loss_and_grads(p64, X, Y, bf16=True)
+    print(f"loss {gl:.9g} vs the BF16-operand oracle {ol:.9g}")
+    assert abs(gl - ol) <= 1e-4 * abs(ol)
     gg = m.unpack(G.cpu())
     for k in omlp.NAMES:
         cos, rel = _cos_rel(gg[k].numpy(), og[k])
-        assert cos >= 0.999 and rel <= 1e-2, (k, cos, rel)
+        print(f"grad {k}: cos {cos:.9f}, rel {rel:.3e}")
+        assert cos >= 0.9999999 and rel <= 1e-4, (k, cos, rel)
+    ol64, og64 = omlp.loss_and_grads(p64, X, Y)
+    assert abs(gl - ol64) <= 2e-2 * abs(ol64)  # the BF16 operands themselves: ~1 %
 
 
 def test_adam_vs_oracle(R):

@@ -65,3 +65,30 @@ def test_adam_first_step_is_signed_lr():
     mlp.adam_step(p, g, m, v, 1, lr=0.01, eps=0.0)
     for k in mlp.NAMES:
         assert np.allclose(p[k], [0.99, 1.01], atol=1e-15)
+
+
+def test_bf16_rounding_pins():
+    """Round to nearest, ties to even, on the upper 16 bits of binary32:
+    1 + 2^-8 (a tie) goes down to 1, 1 + 3 * 2^-8 (a tie) up to 1 + 2^-6,
+    1 + 2^-8 + 2^-20 up to 1 + 2^-7; bfloat16 values are kept; the relative
+    error is at most half a unit in the 8th bit, 2^-8."""
+    v = np.array([1 + 2.0**-8, 1 + 3 * 2.0**-8, 1 + 2.0**-8 + 2.0**-20, -(1 + 2.0**-8), 0.0, 3.5])
+    r = mlp.bf16_round(v)
+    assert list(r) == [1.0, 1 + 2.0**-6, 1 + 2.0**-7, -1.0, 0.0, 3.5]
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(10000) * 10.0 ** rng.uniform(-6, 6, 10000)
+    rx = mlp.bf16_round(x)
+    x32 = x.astype(np.float32).astype(np.float64)
+    assert np.all(np.abs(rx - x32) <= np.abs(x32) * 2.0**-8)
+    assert np.array_equal(mlp.bf16_round(rx), rx)
+
+
+def test_bf16_products_of_bf16_values_are_exact():
+    """Operands already in bfloat16 (small integers times powers of two)
+    give the same products in both modes; other operands do not."""
+    rng = np.random.default_rng(4)
+    A = rng.integers(-64, 64, (7, 33)) * 2.0**-5
+    B = rng.integers(-64, 64, (33, 5)) * 2.0**-3
+    assert np.array_equal(mlp.mm(A, B, bf16=True), A @ B)
+    C = rng.standard_normal((7, 33))
+    assert not np.array_equal(mlp.mm(C, B, bf16=True), C @ B)
