@@ -320,11 +320,14 @@ def main():
     rose.profile_enable(True)
     rose.profile_reset()
     evals = 0.0
+    step_evals, step_mode = [], []  # per timed fitness step: evaluations, kernel that worked
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for i in range(1 + args.warmup, n_frames):
         res = step(i)
         evals += float(sum(n * o for n, o in zip(res["n_particles"], res["n_overlap"])))
+        step_evals.extend(float(n * o) for n, o in zip(res["n_particles"], res["n_overlap"]))
+        step_mode.extend(res["fit_mode"])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     prof = rose.profile_read()
@@ -416,6 +419,19 @@ def main():
         "ta_stalled_by_tc_frac": cnt["ta_stalled_by_tc_frac"] if cnt else None,
         "counters": "rocprofv3 summary of the same command and window" if cnt else why,
     }
+    if shape == (0, 0) and len(launch_ms) == len(step_mode) and any(step_mode):
+        # the switching mode's two sides: steps, evaluations and time of each
+        split = {}
+        names = {1: "points_across", 2: "particle_per_lane"}
+        for mode, name in names.items():
+            idx = [j for j, m in enumerate(step_mode) if m == mode]
+            ev = sum(step_evals[j] for j in idx)
+            ms = float(sum(launch_ms[j] for j in idx))
+            wp = (4, 2) if lookup == 1 else wide  # the wide side of trilinear lookups is 4x2
+            split[name] = {"kernel": (f"k_fitness<{wp[0]},{wp[1]}>" if mode == 1 else "k_fitness<64,8>"),
+                           "steps": len(idx), "evals": ev, "ms": ms,
+                           "evals_per_s": ev / (ms * 1e-3) if ms > 0 else None}
+        out["roofline"]["switch_split"] = split
     out["gather_probe"] = {
         "what": "not a ceiling: independent 4-byte loads, each from its own pseudo-random 128-byte line of a "
                 "region per XCD (2 MiB: L2-resident; 1 GiB: HBM-resident), loads/s",

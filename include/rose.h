@@ -313,6 +313,9 @@ typedef struct {
     int32_t n_particles[ROSE_MAX_ITERS]; /* particles evaluated per iteration */
     double rho_centre[ROSE_MAX_ITERS];   /* exact rho of the centre c_{k-1} (particle 0) in iteration k */
     double r_iter[ROSE_MAX_ITERS][6];    /* axis lengths r_{k-1} that scale the template in iteration k */
+    int32_t fit_mode[ROSE_MAX_ITERS];    /* fitness kernel that did the work in iteration k: 0 one fixed launch
+                                          * shape; switching mode: 1 points across the lanes, 2 one particle
+                                          * per lane (pso_track_frame; 0 elsewhere) */
 } rose_track_stats;
 
 /* One frame of Alg. 1 (PFO with PST) on the device.

@@ -73,23 +73,35 @@ def trace_steps(trace_dir: str, n_steps: int):
     return dur.reshape(n_steps, per).sum(axis=1), names
 
 
+def _shape_of(name: str) -> str:
+    """'P,U' of a k_fitness instance name (its first two template arguments)."""
+    m = re.search(r"k_fitness<\s*(\d+),\s*(\d+)", name)
+    return f"{m.group(1)},{m.group(2)}" if m else name
+
+
 def pmc_steps(pmc_dir: str, n_steps: int, per: int):
     """Per counter: its value summed over the dispatches of each of the last
-    n_steps fitness steps; and the copy probe's readings."""
+    n_steps fitness steps; per counter and kernel shape ('P,U'), its total
+    over those dispatches; and the copy probe's readings."""
     vals = {}
+    names = {}
     copy = {}
     for r in _rows(os.path.join(pmc_dir, "**", "*counter_collection.csv")):
         name, c, v, d = r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"]), int(r["Dispatch_Id"])
         if is_fitness(name):
             vals.setdefault(c, {}).setdefault(d, 0.0)
             vals[c][d] += v
+            names[d] = _shape_of(name)
         elif "vectorized_elementwise_kernel" in name and ("AUnaryFunctor" in name or "MulFunctor" in name):
             copy.setdefault(c, []).append(v)  # the copy probe's multiply by one
-    out = {}
+    out, by_shape = {}, {}
     for c, byd in vals.items():
-        seq = [byd[d] for d in sorted(byd)][-per * n_steps:]
-        out[c] = np.array(seq).reshape(n_steps, per).sum(axis=1)
-    return out, copy
+        ds = sorted(byd)[-per * n_steps:]
+        out[c] = np.array([byd[d] for d in ds]).reshape(n_steps, per).sum(axis=1)
+        for d in ds:
+            by_shape.setdefault(c, {}).setdefault(names[d], 0.0)
+            by_shape[c][names[d]] += byd[d]
+    return out, by_shape, copy
 
 
 def kernel_stats_md(trace_dir: str, bench: dict, dur_ns, names, command: str) -> str:
@@ -140,10 +152,11 @@ def main(argv=None):
     evals = float(bench["roofline"]["evals_per_launch"])
     dur, names = trace_steps(a.trace, n_steps)
     per = len(names)
-    counters, copy = {}, {}
+    counters, by_shape, copy = {}, {}, {}
     for d in a.pmc:
-        c, cp = pmc_steps(d, n_steps, per)
+        c, bs, cp = pmc_steps(d, n_steps, per)
         counters.update(c)
+        by_shape.update(bs)
         for k, v in cp.items():
             copy.setdefault(k, []).extend(v)
     copy_kib = a.copy_mib * 1024.0
@@ -222,6 +235,33 @@ def main(argv=None):
         busy = counters["SQ_INSTS_VALU"].mean() * 4.0 / (1024.0 * cycles)
         kv["valu_busy_frac"] = f"{busy:.4g}"
         derived.append(f"VALU busy {100 * busy:.0f}% of the SIMD cycles of a step")
+    split = bench["roofline"].get("switch_split")
+    if split:
+        # per side of the switching mode: totals over the window's dispatches
+        # of that kernel (its idle launches included: they exit at once)
+        # divided by the evaluations it did (bench.py, same window)
+        for side, sd in split.items():
+            shp = re.search(r"<(\d+),(\d+)>", sd["kernel"])
+            key = f"{shp.group(1)},{shp.group(2)}"
+            ev = float(sd["evals"])
+            if ev <= 0:
+                continue
+            parts = [f"{side} ({sd['kernel']}): {sd['steps']} steps, {ev / max(sd['steps'], 1):.4g} evaluations and "
+                     f"{sd['ms'] / max(sd['steps'], 1):.3f} ms per step, {sd['evals_per_s']:.3e} evals/s"]
+            if key in by_shape.get("SQ_INSTS_VALU", {}):
+                ops = by_shape["SQ_INSTS_VALU"][key] * 64.0 / ev
+                parts.append(f"VALU lane-ops per evaluation {ops:.2f} (R_valu {VALU_LANE_OPS_PER_S / ops:.3e})")
+                kv[f"valu_lane_ops_per_eval_{side}"] = f"{ops:.4g}"
+            if key in by_shape.get("TCP_TCC_READ_REQ_sum", {}):
+                req = by_shape["TCP_TCC_READ_REQ_sum"][key] / ev
+                parts.append(f"L1 -> L2 read requests per evaluation {req:.3f}")
+                kv[f"l2_requests_per_eval_{side}"] = f"{req:.4g}"
+            if key in by_shape.get("TCP_TOTAL_CACHE_ACCESSES_sum", {}):
+                parts.append(f"L1 accesses per evaluation {by_shape['TCP_TOTAL_CACHE_ACCESSES_sum'][key] / ev:.3f}")
+            fs = scale("FETCH_SIZE")
+            if fs and key in by_shape.get("FETCH_SIZE", {}):
+                parts.append(f"HBM read bytes per evaluation {by_shape['FETCH_SIZE'][key] * 1024.0 * fs / ev:.2f}")
+            derived.append("; ".join(parts))
     lines += ["", "Derived:"] + [f"* {d}." for d in derived]
     lines += ["", "Values read by bench.py (while the kernel sources hash to the value below and the window and",
               "launch shape match its own):", ""]

@@ -304,6 +304,20 @@ __global__ __launch_bounds__(256) void k_overlap_only(OverlapArgs a) {
 
 using namespace rose;
 
+// Which kernel of a fitness launch did the work for axis lengths r: 0 when
+// the launch has one fixed shape; in the switching mode the footprint test
+// that both kernels evaluate on the device (largest translation axis length
+// plus the reference depth times the largest rotation axis length, against
+// the threshold in voxels): 1 points across the lanes, 2 one particle per
+// lane.  The same expression in the same precision as the kernels'.
+static int32_t switch_mode(const FitLaunch& L, const double r[6]) {
+    const uint64_t bytes = (uint64_t)L.g.nx * L.g.ny * L.g.nz * (L.g.fmt == ROSE_TSDF_F32 ? 4u : 2u);
+    if (!(L.pl_thr > 0.0f && L.st && !L.T32 && bytes < (uint64_t(1) << 32))) return 0;
+    const double rr = std::max(std::max(r[0], r[1]), r[2]);
+    const double rt = std::max(std::max(r[3], r[4]), r[5]);
+    return (rt + (double)L.pl_zref * rr) <= (double)L.pl_thr * (double)L.g.vox ? 2 : 1;
+}
+
 extern "C" {
 
 rose_status depth_unproject(const float* depth_dev, const rose_camera* cam, int32_t stride, int32_t order,
@@ -528,6 +542,7 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const float* p
             stats->rho_centre[k] = r.rho_centre[k];
             for (int d = 0; d < 6; ++d) stats->r_iter[k][d] = r.r_iter[k][d];
             stats->n_particles[k] = lv_n[k % L];
+            stats->fit_mode[k] = switch_mode(fl, r.r_iter[k]);
         }
     }
     return ROSE_OK;

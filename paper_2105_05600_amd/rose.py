@@ -63,7 +63,7 @@ class TrackStats(C.Structure):
                 ("status", C.c_int32), ("aps_size", C.c_int32 * MAX_ITERS),
                 ("n_overlap", C.c_int32 * MAX_ITERS), ("rho_iter", C.c_double * MAX_ITERS),
                 ("n_particles", C.c_int32 * MAX_ITERS), ("rho_centre", C.c_double * MAX_ITERS),
-                ("r_iter", (C.c_double * 6) * MAX_ITERS)]
+                ("r_iter", (C.c_double * 6) * MAX_ITERS), ("fit_mode", C.c_int32 * MAX_ITERS)]
 
 
 class LearnedParams(C.Structure):
@@ -474,6 +474,7 @@ def track_frame(vol: Tsdf, depth: torch.Tensor, K, pst: torch.Tensor, params: Tr
                 aps=list(stats.aps_size[:it]), n_overlap=list(stats.n_overlap[:it]),
                 rho_iter=list(stats.rho_iter[:it]), n_particles=list(stats.n_particles[:it]),
                 rho_centre=list(stats.rho_centre[:it]), r_iter=[list(stats.r_iter[k]) for k in range(it)],
+                fit_mode=list(stats.fit_mode[:it]),
                 q=list(state.pose.q), t=list(state.pose.t), r1=list(state.r), rho=state.rho)
 
 
