@@ -436,6 +436,21 @@ struct FitLaunch {
     uint64_t* partial;         // n x splits grid integers
 };
 rose_status launch_fitness(const FitLaunch& L, hipStream_t s);
+
+// The switching mode's footprint test: the largest translation axis length
+// plus zref times the largest rotation axis length, at most thr voxels of
+// size vox (axis lengths r: 3 rotation, then 3 translation).  Every kernel
+// that takes the decision evaluates this same expression on the same state.
+__host__ __device__ inline bool footprint_small(const double* r, float zref, float thr, float vox) {
+    const double rr = fmax(fmax(r[0], r[1]), r[2]);
+    const double rt = fmax(fmax(r[3], r[4]), r[5]);
+    return (rt + (double)zref * rr) <= (double)thr * (double)vox;
+}
+// Point slices of the particle-per-lane side in a switched batch: 4 times
+// the points-across side's, so that both sides have the same number of work
+// items per sequence (64 particles per item against 16).
+constexpr int kBatchPlSliceMul = 4;
+
 // Schedule order of the first n rows of a PST template (cached per handle;
 // the first request reads the template back, synchronising s).  nullptr
 // (index order) when the handle's cache is full.
@@ -452,10 +467,14 @@ FitConfig fit_config(const rose_tsdf* h);
 void fit_launch_shape(const rose_tsdf* h, int lk, int* p, int* u, float* thr_vox, float* zref_m);
 int fitness_blocks(const FitLaunch& L, int P);
 bool batch_shape_valid(int p, int u);
-int batch_grid(int P, int U, int fmt, int lk, int requested);
-// ctr_dev: the group's 8 per-XCD work counters, zero at launch
+// points-across shapes the switched batch kernel is built for
+bool batch_switch_shape_valid(int p, int u);
+int batch_grid(int P, int U, bool sw, int fmt, int lk, int requested);
+// ctr_dev: the group's 8 per-XCD work counters, zero at launch; sw: the
+// switching mode (P x U its points-across side, per-sequence thresholds in
+// the launch records)
 rose_status launch_fitness_batch(const FitLaunch* seqs_dev, const int* begin_dev, int count, int base, int end,
-                                 int grid, int P, int U, int fmt, int lk, int* ctr_dev, hipStream_t s);
+                                 int grid, int P, int U, bool sw, int fmt, int lk, int* ctr_dev, hipStream_t s);
 
 // PST template rows 0..n-1 (tsdf.hip)
 rose_status launch_pst_sample(int64_t n, uint64_t seed, float* out_dev, hipStream_t s);

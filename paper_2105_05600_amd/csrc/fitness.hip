@@ -132,10 +132,7 @@ __device__ inline float wave_sum_f(float v) {
 // same device state, so exactly one of them does the work.
 __device__ inline bool switch_skips(const FitLaunch& a) {
     if (a.pl_side == 0) return false;
-    const double* r = a.st->r;
-    const double rr = fmax(fmax(r[0], r[1]), r[2]);
-    const double rt = fmax(fmax(r[3], r[4]), r[5]);
-    const bool small = (rt + (double)a.pl_zref * rr) <= (double)a.pl_thr * (double)a.g.vox;
+    const bool small = footprint_small(a.st->r, a.pl_zref, a.pl_thr, a.g.vox);
     return small != (a.pl_side == 1);
 }
 
@@ -507,7 +504,15 @@ __device__ inline int fitness_blocks_dev(const FitLaunch& L, int P) {
 // counters (ctr[0..7]) are zero at launch: the kernel that runs before each
 // launch on the stream clears them, and every workgroup leaves once its
 // queue passes `end`.
-template <int P, int U, int FMT, int LK>
+//
+// SW (the switching mode; P x U the points-across side): each item asks the
+// footprint test of its sequence's state.  Above the threshold it is a
+// points-across item (16 particles x one of `splits` slices); at or below
+// it a particle-per-lane item (64 particles x one of kBatchPlSliceMul x
+// `splits` slices), so that both sides have the same item count and the
+// work list serves either.  The reduction adds the slices of the side that
+// ran (the same test on the same state).
+template <int P, int U, int FMT, int LK, bool SW>
 __global__ __launch_bounds__(256) void k_fitness_batch(const FitLaunch* __restrict__ seqs,
                                                        const int* __restrict__ begin, int count, int base, int end,
                                                        int* __restrict__ ctr) {
@@ -527,9 +532,18 @@ __global__ __launch_bounds__(256) void k_fitness_batch(const FitLaunch* __restri
         }
         const FitLaunch L = seqs[lo];  // wave-uniform: scalar loads of read-only memory
         const int blk = w - begin[lo];
-        if (blk >= fitness_blocks_dev(L, P)) continue;
         // the particle-per-lane body synchronises its workgroup once; every
-        // branch above is uniform over the workgroup (one item per workgroup)
+        // branch here is uniform over the workgroup (one item per workgroup,
+        // one state per sequence)
+        if constexpr (SW) {
+            if (footprint_small(L.st->r, L.pl_zref, L.pl_thr, L.g.vox)) {
+                FitLaunch Lp = L;
+                Lp.splits = L.splits * kBatchPlSliceMul;
+                if (blk < fitness_blocks_dev(Lp, kWave)) fitness_body_pl<8, FMT, LK, true, false>(Lp, blk);
+                continue;
+            }
+        }
+        if (blk >= fitness_blocks_dev(L, P)) continue;
         if constexpr (P == kWave) fitness_body_pl<U, FMT, LK, true, false>(L, blk);
         else fitness_body<P, U, FMT, LK, true, false>(L, blk);
     }
@@ -550,57 +564,69 @@ static int resident_grid(K kernel, int requested) {
     return std::max(8, std::min(requested, cus * per_cu) / 8 * 8);
 }
 
-template <int P, int U, int FMT, int LK>
+template <int P, int U, int FMT, int LK, bool SW>
 static void launch_batch_kernel(const FitLaunch* seqs, const int* begin, int count, int base, int end, int grid,
                                 int* ctr, hipStream_t s) {
-    hipLaunchKernelGGL((k_fitness_batch<P, U, FMT, LK>), dim3(grid), dim3(256), 0, s, seqs, begin, count, base, end,
-                       ctr);
+    hipLaunchKernelGGL((k_fitness_batch<P, U, FMT, LK, SW>), dim3(grid), dim3(256), 0, s, seqs, begin, count, base,
+                       end, ctr);
 }
 
-template <int P, int U>
+template <int P, int U, bool SW>
 static int batch_grid_shape(int fmt, int lk, int requested) {
     if (fmt == ROSE_TSDF_F32)
         return lk == ROSE_LOOKUP_TRILINEAR
-                   ? resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_TRILINEAR>, requested)
-                   : resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_NEAREST>, requested);
+                   ? resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_TRILINEAR, SW>, requested)
+                   : resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_NEAREST, SW>, requested);
     if (fmt == ROSE_TSDF_F16)
         return lk == ROSE_LOOKUP_TRILINEAR
-                   ? resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_TRILINEAR>, requested)
-                   : resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_NEAREST>, requested);
+                   ? resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_TRILINEAR, SW>, requested)
+                   : resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_NEAREST, SW>, requested);
     return lk == ROSE_LOOKUP_TRILINEAR
-               ? resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_TRILINEAR>, requested)
-               : resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_NEAREST>, requested);
+               ? resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_TRILINEAR, SW>, requested)
+               : resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_NEAREST, SW>, requested);
 }
 
 // grid of the persistent batch launch for a group (host query; call outside
 // stream capture)
-int batch_grid(int P, int U, int fmt, int lk, int requested) {
-    if (P == kWave && U == 8) return batch_grid_shape<kWave, 8>(fmt, lk, requested);
-    if (P == 8 && U == 4) return batch_grid_shape<8, 4>(fmt, lk, requested);
-    if (P == 4 && U == 8) return batch_grid_shape<4, 8>(fmt, lk, requested);
-    if (P == 8 && U == 2) return batch_grid_shape<8, 2>(fmt, lk, requested);
-    if (P == 4 && U == 4) return batch_grid_shape<4, 4>(fmt, lk, requested);
-    return batch_grid_shape<4, 2>(fmt, lk, requested);
+int batch_grid(int P, int U, bool sw, int fmt, int lk, int requested) {
+    if (sw) {
+        if (P == 4 && U == 4) return batch_grid_shape<4, 4, true>(fmt, lk, requested);
+        if (P == 8 && U == 4) return batch_grid_shape<8, 4, true>(fmt, lk, requested);
+        if (P == 8 && U == 2) return batch_grid_shape<8, 2, true>(fmt, lk, requested);
+        return batch_grid_shape<4, 2, true>(fmt, lk, requested);
+    }
+    if (P == kWave && U == 8) return batch_grid_shape<kWave, 8, false>(fmt, lk, requested);
+    if (P == 8 && U == 4) return batch_grid_shape<8, 4, false>(fmt, lk, requested);
+    if (P == 4 && U == 8) return batch_grid_shape<4, 8, false>(fmt, lk, requested);
+    if (P == 8 && U == 2) return batch_grid_shape<8, 2, false>(fmt, lk, requested);
+    if (P == 4 && U == 4) return batch_grid_shape<4, 4, false>(fmt, lk, requested);
+    return batch_grid_shape<4, 2, false>(fmt, lk, requested);
 }
 
-template <int P, int U>
+template <int P, int U, bool SW>
 static void launch_batch_shape(const FitLaunch* seqs, const int* begin, int count, int base, int end, int grid,
                                int fmt, int lk, int* ctr, hipStream_t s) {
     if (fmt == ROSE_TSDF_F32) {
         if (lk == ROSE_LOOKUP_TRILINEAR)
-            launch_batch_kernel<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_TRILINEAR>(seqs, begin, count, base, end, grid, ctr, s);
+            launch_batch_kernel<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_TRILINEAR, SW>(seqs, begin, count, base, end, grid,
+                                                                             ctr, s);
         else
-            launch_batch_kernel<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_NEAREST>(seqs, begin, count, base, end, grid, ctr, s);
+            launch_batch_kernel<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_NEAREST, SW>(seqs, begin, count, base, end, grid, ctr,
+                                                                            s);
     } else if (fmt == ROSE_TSDF_F16) {
         if (lk == ROSE_LOOKUP_TRILINEAR)
-            launch_batch_kernel<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_TRILINEAR>(seqs, begin, count, base, end, grid, ctr, s);
+            launch_batch_kernel<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_TRILINEAR, SW>(seqs, begin, count, base, end, grid,
+                                                                             ctr, s);
         else
-            launch_batch_kernel<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_NEAREST>(seqs, begin, count, base, end, grid, ctr, s);
+            launch_batch_kernel<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_NEAREST, SW>(seqs, begin, count, base, end, grid, ctr,
+                                                                            s);
     } else {
         if (lk == ROSE_LOOKUP_TRILINEAR)
-            launch_batch_kernel<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_TRILINEAR>(seqs, begin, count, base, end, grid, ctr, s);
+            launch_batch_kernel<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_TRILINEAR, SW>(seqs, begin, count, base, end, grid,
+                                                                              ctr, s);
         else
-            launch_batch_kernel<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_NEAREST>(seqs, begin, count, base, end, grid, ctr, s);
+            launch_batch_kernel<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_NEAREST, SW>(seqs, begin, count, base, end, grid,
+                                                                            ctr, s);
     }
 }
 
@@ -609,15 +635,26 @@ bool batch_shape_valid(int P, int U) {
            (P == 4 && U == 8) || (P == kWave && U == 8);
 }
 
+bool batch_switch_shape_valid(int P, int U) {
+    return (P == 4 && U == 2) || (P == 8 && U == 2) || (P == 4 && U == 4) || (P == 8 && U == 4);
+}
+
 rose_status launch_fitness_batch(const FitLaunch* seqs_dev, const int* begin_dev, int count, int base, int end,
-                                 int grid, int P, int U, int fmt, int lk, int* ctr_dev, hipStream_t s) {
-    if (P == kWave && U == 8)
-        launch_batch_shape<kWave, 8>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
-    else if (P == 8 && U == 4) launch_batch_shape<8, 4>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
-    else if (P == 4 && U == 8) launch_batch_shape<4, 8>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
-    else if (P == 8 && U == 2) launch_batch_shape<8, 2>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
-    else if (P == 4 && U == 4) launch_batch_shape<4, 4>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
-    else launch_batch_shape<4, 2>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
+                                 int grid, int P, int U, bool sw, int fmt, int lk, int* ctr_dev, hipStream_t s) {
+    if (sw) {
+        if (P == 4 && U == 4) launch_batch_shape<4, 4, true>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
+        else if (P == 8 && U == 4)
+            launch_batch_shape<8, 4, true>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
+        else if (P == 8 && U == 2)
+            launch_batch_shape<8, 2, true>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
+        else launch_batch_shape<4, 2, true>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
+    } else if (P == kWave && U == 8)
+        launch_batch_shape<kWave, 8, false>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
+    else if (P == 8 && U == 4) launch_batch_shape<8, 4, false>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
+    else if (P == 4 && U == 8) launch_batch_shape<4, 8, false>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
+    else if (P == 8 && U == 2) launch_batch_shape<8, 2, false>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
+    else if (P == 4 && U == 4) launch_batch_shape<4, 4, false>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
+    else launch_batch_shape<4, 2, false>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
     ROSE_CHECK_HIP(hipGetLastError());
     return ROSE_OK;
 }

@@ -480,7 +480,7 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const float* p
     fl.pl_thr = shp_thr;
     fl.pl_zref = shp_zref;
 
-    UpdateArgs ua;
+    UpdateArgs ua{};
     ua.st = h->st;
     ua.cam = ia.cam;
     ua.pst = pst_dev;
@@ -570,6 +570,7 @@ struct BatchGroup {
 
 struct rose_batch {
     int32_t count = 0, K = 0, P = 4, U = 2, total = 0, max_n = 1;
+    bool sw = false;  // the switching mode (P x U its points-across side)
     std::vector<BatchGroup> groups;
     bool use_graph = true;
     std::vector<rose_tsdf*> h;
@@ -662,7 +663,8 @@ static rose_status batch_enqueue(rose_batch* b, hipStream_t s) {
         for (size_t q = 0; q < b->groups.size(); ++q) {
             const BatchGroup& gr = b->groups[q];
             rose_status st = launch_fitness_batch(b->fit_dev + gr.first, b->begin_dev + gr.first, gr.count, gr.base,
-                                                  gr.end, gr.grid, b->P, b->U, gr.fmt, gr.lk, b->ctr_dev + 8 * q, s);
+                                                  gr.end, gr.grid, b->P, b->U, b->sw, gr.fmt, gr.lk,
+                                                  b->ctr_dev + 8 * q, s);
             if (st != ROSE_OK) return st;
         }
         hipLaunchKernelGGL(k_fitness_reduce_batch, dim3((b->max_n + 255) / 256, b->count), dim3(256), 0, s,
@@ -714,15 +716,18 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
     b->count = count;
     b->use_graph = use_graph != 0;
     // the first handle's launch configuration: its fixed shape, or in the
-    // switching mode its points-across shape
+    // switching mode its points-across shape (each sequence keeps its own
+    // switch threshold)
     const FitConfig cfg = fit_config(tsdfs[0]);
-    int P = cfg.sw ? cfg.wide_p : cfg.p, U = cfg.sw ? cfg.wide_u : cfg.u;
-    if (!batch_shape_valid(P, U)) {
+    const bool sw = cfg.sw != 0;
+    int P = sw ? cfg.wide_p : cfg.p, U = sw ? cfg.wide_u : cfg.u;
+    if (sw ? !batch_switch_shape_valid(P, U) : !batch_shape_valid(P, U)) {
         P = 4;
         U = 2;
     }
     b->P = P;
     b->U = U;
+    b->sw = sw;
     // the fitness work arrays list the sequences grouped by (format, lookup)
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
@@ -745,9 +750,10 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
         const int sv = (cams[i].height + p.stride - 1) / p.stride;
         const int64_t mmax = (int64_t)su * sv;
         const int splits = choose_splits(n_particles[i], mmax, h->g.fmt, P);
+        const int slots = sw ? splits * kBatchPlSliceMul : splits;
         if ((g = grow(&h->pts, &h->cap_points, mmax)) != ROSE_OK) break;
         if ((g = grow(&h->pts_o, &h->cap_points_o, mmax)) != ROSE_OK) break;
-        if ((g = grow(&h->partial, &h->cap_partial, (int64_t)n_particles[i] * splits)) != ROSE_OK) break;
+        if ((g = grow(&h->partial, &h->cap_partial, (int64_t)n_particles[i] * slots)) != ROSE_OK) break;
         if ((g = grow(&h->F, &h->cap_particles, (int64_t)n_particles[i])) != ROSE_OK) break;
         if (!h->st && hipMalloc(&h->st, sizeof(DevState)) != hipSuccess) {
             set_error("pso_batch_create: hipMalloc failed");
@@ -770,6 +776,17 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
         L.shape_u = U;
         L.partial = h->partial;
         nblk[pos[i]] = fitness_blocks(L, P);
+        int sp_p, sp_u;
+        float thr = 0.0f, zref = 0.0f;
+        fit_launch_shape(h, p.lookup, &sp_p, &sp_u, &thr, &zref);
+        if (sw) {
+            // the sequence's own threshold; the particle-per-lane side's items
+            FitLaunch Lp = L;
+            Lp.splits = splits * kBatchPlSliceMul;
+            nblk[pos[i]] = std::max(nblk[pos[i]], fitness_blocks(Lp, kWave));
+            L.pl_thr = thr;
+            L.pl_zref = zref;
+        }
         InitStatic& ia = init[i];
         ia = InitStatic{};
         ia.st = h->st;
@@ -797,6 +814,12 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
         ua.eps = p.eps;
         ua.tau = p.tau;
         ua.stop_tol = p.stop_tol;
+        if (sw) {
+            ua.pl_splits = splits * kBatchPlSliceMul;
+            ua.pl_zref = zref;
+            ua.pl_thr = thr;
+            ua.vox = h->g.vox;
+        }
         stp[i] = h->st;
         b->h.push_back(h);
         b->cams.push_back(cams[i]);
@@ -823,7 +846,7 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
         gr.count = e - k;
         gr.base = begin[k];
         gr.end = begin[e];
-        gr.grid = batch_grid(P, U, gr.fmt, gr.lk, gr.end - gr.base);
+        gr.grid = batch_grid(P, U, sw, gr.fmt, gr.lk, gr.end - gr.base);
         b->groups.push_back(gr);
         k = e;
     }

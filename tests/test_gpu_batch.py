@@ -51,9 +51,11 @@ def _single(R, w, fmt, n, stride, steps, lookup=0):
     return out
 
 
-@pytest.mark.parametrize("shape", [(4, 2), (64, 8)])
+@pytest.mark.parametrize("shape", [(4, 2), (64, 8), (0, 0)])
 @pytest.mark.parametrize("use_graph", [False, True])
 def test_batch_equals_single_path(R, scenes, use_graph, shape):
+    """shape (0, 0): the switching mode on both paths (the batch decides per
+    sequence and iteration inside its persistent kernel)."""
     R.set_fitness_shape(*shape)
     try:
         _batch_equals_single(R, scenes, use_graph)

@@ -159,11 +159,12 @@ def batch_case(R, orc, nthreads):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("shape", [(8, 4), (64, 8)])
+@pytest.mark.parametrize("shape", [(8, 4), (64, 8), (0, 0)])
 def test_batch_step_against_oracle(R, batch_case, shape):
     """One batched frame step (persistent fitness launch, graph replay) of
     the uneven sequences, every sequence against the oracle's frame, in a
-    points-across and the particle-per-lane launch shape."""
+    points-across and the particle-per-lane launch shape and in the
+    switching mode (each sequence's own side per iteration)."""
     setups, refs = batch_case
     params = [R.track_params(max_iters=20, stride=4) for _ in setups]
     stream = torch.cuda.Stream()
