@@ -446,10 +446,6 @@ __host__ __device__ inline bool footprint_small(const double* r, float zref, flo
     const double rt = fmax(fmax(r[3], r[4]), r[5]);
     return (rt + (double)zref * rr) <= (double)thr * (double)vox;
 }
-// Point slices of the particle-per-lane side in a switched batch: 4 times
-// the points-across side's, so that both sides have the same number of work
-// items per sequence (64 particles per item against 16).
-constexpr int kBatchPlSliceMul = 4;
 
 // Schedule order of the first n rows of a PST template (cached per handle;
 // the first request reads the template back, synchronising s).  nullptr
@@ -469,12 +465,15 @@ int fitness_blocks(const FitLaunch& L, int P);
 bool batch_shape_valid(int p, int u);
 // points-across shapes the switched batch kernel is built for
 bool batch_switch_shape_valid(int p, int u);
-int batch_grid(int P, int U, bool sw, int fmt, int lk, int requested);
-// ctr_dev: the group's 8 per-XCD work counters, zero at launch; sw: the
-// switching mode (P x U its points-across side, per-sequence thresholds in
-// the launch records)
+int batch_grid(int P, int U, int side, int fmt, int lk, int requested);
+// ctr_dev: the group's 8 per-XCD work counters, zero at launch.  side: 0
+// every item runs; in the switching mode the points-across launch (P x U,
+// side 2) runs the items of sequences whose footprint test fails and the
+// particle-per-lane launch (64 x 8, side 1) those whose test holds, each
+// skipping the rest of a sequence's items at once (per-sequence thresholds
+// in the launch records)
 rose_status launch_fitness_batch(const FitLaunch* seqs_dev, const int* begin_dev, int count, int base, int end,
-                                 int grid, int P, int U, bool sw, int fmt, int lk, int* ctr_dev, hipStream_t s);
+                                 int grid, int P, int U, int side, int fmt, int lk, int* ctr_dev, hipStream_t s);
 
 // PST template rows 0..n-1 (tsdf.hip)
 rose_status launch_pst_sample(int64_t n, uint64_t seed, float* out_dev, hipStream_t s);

@@ -505,14 +505,16 @@ __device__ inline int fitness_blocks_dev(const FitLaunch& L, int P) {
 // launch on the stream clears them, and every workgroup leaves once its
 // queue passes `end`.
 //
-// SW (the switching mode; P x U the points-across side): each item asks the
-// footprint test of its sequence's state.  Above the threshold it is a
-// points-across item (16 particles x one of `splits` slices); at or below
-// it a particle-per-lane item (64 particles x one of kBatchPlSliceMul x
-// `splits` slices), so that both sides have the same item count and the
-// work list serves either.  The reduction adds the slices of the side that
-// ran (the same test on the same state).
-template <int P, int U, int FMT, int LK, bool SW>
+// SIDE (the switching mode): the points-across launch (SIDE 2) and the
+// particle-per-lane launch (SIDE 1) each walk their own work list over all
+// sequences; an item runs only when its sequence's footprint test (the one
+// the single-sequence kernels take, on the same state) selects the
+// launch's side.  Otherwise the workgroup moves its XCD's counter past the
+// rest of that sequence's items (atomicMax: counters only move forward, and
+// every skipped item belongs to the same sequence), so a sequence on the
+// other side costs a few fetches, not one per item.  SIDE 0: every item
+// runs (one fixed shape).
+template <int P, int U, int FMT, int LK, int SIDE>
 __global__ __launch_bounds__(256) void k_fitness_batch(const FitLaunch* __restrict__ seqs,
                                                        const int* __restrict__ begin, int count, int base, int end,
                                                        int* __restrict__ ctr) {
@@ -531,19 +533,19 @@ __global__ __launch_bounds__(256) void k_fitness_batch(const FitLaunch* __restri
             else hi = mid;
         }
         const FitLaunch L = seqs[lo];  // wave-uniform: scalar loads of read-only memory
-        const int blk = w - begin[lo];
-        // the particle-per-lane body synchronises its workgroup once; every
-        // branch here is uniform over the workgroup (one item per workgroup,
-        // one state per sequence)
-        if constexpr (SW) {
-            if (footprint_small(L.st->r, L.pl_zref, L.pl_thr, L.g.vox)) {
-                FitLaunch Lp = L;
-                Lp.splits = L.splits * kBatchPlSliceMul;
-                if (blk < fitness_blocks_dev(Lp, kWave)) fitness_body_pl<8, FMT, LK, true, false>(Lp, blk);
+        if constexpr (SIDE != 0) {
+            const bool small = footprint_small(L.st->r, L.pl_zref, L.pl_thr, L.g.vox);
+            if (small != (SIDE == 1)) {
+                // begin[] entries and base are multiples of 8: the next item of
+                // this XCD's queue past the sequence is k = (begin[lo+1] - base) / 8
+                if (threadIdx.x == 0) atomicMax(&ctr[xcd], (begin[lo + 1] - base) >> 3);
                 continue;
             }
         }
+        const int blk = w - begin[lo];
         if (blk >= fitness_blocks_dev(L, P)) continue;
+        // the particle-per-lane body synchronises its workgroup once; every
+        // branch above is uniform over the workgroup (one item per workgroup)
         if constexpr (P == kWave) fitness_body_pl<U, FMT, LK, true, false>(L, blk);
         else fitness_body<P, U, FMT, LK, true, false>(L, blk);
     }
@@ -564,70 +566,88 @@ static int resident_grid(K kernel, int requested) {
     return std::max(8, std::min(requested, cus * per_cu) / 8 * 8);
 }
 
-template <int P, int U, int FMT, int LK, bool SW>
+template <int P, int U, int FMT, int LK, int SIDE>
 static void launch_batch_kernel(const FitLaunch* seqs, const int* begin, int count, int base, int end, int grid,
                                 int* ctr, hipStream_t s) {
-    hipLaunchKernelGGL((k_fitness_batch<P, U, FMT, LK, SW>), dim3(grid), dim3(256), 0, s, seqs, begin, count, base,
+    hipLaunchKernelGGL((k_fitness_batch<P, U, FMT, LK, SIDE>), dim3(grid), dim3(256), 0, s, seqs, begin, count, base,
                        end, ctr);
 }
 
-template <int P, int U, bool SW>
+template <int P, int U, int SIDE>
 static int batch_grid_shape(int fmt, int lk, int requested) {
     if (fmt == ROSE_TSDF_F32)
         return lk == ROSE_LOOKUP_TRILINEAR
-                   ? resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_TRILINEAR, SW>, requested)
-                   : resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_NEAREST, SW>, requested);
+                   ? resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_TRILINEAR, SIDE>, requested)
+                   : resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_NEAREST, SIDE>, requested);
     if (fmt == ROSE_TSDF_F16)
         return lk == ROSE_LOOKUP_TRILINEAR
-                   ? resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_TRILINEAR, SW>, requested)
-                   : resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_NEAREST, SW>, requested);
+                   ? resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_TRILINEAR, SIDE>, requested)
+                   : resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_NEAREST, SIDE>, requested);
     return lk == ROSE_LOOKUP_TRILINEAR
-               ? resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_TRILINEAR, SW>, requested)
-               : resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_NEAREST, SW>, requested);
+               ? resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_TRILINEAR, SIDE>, requested)
+               : resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_NEAREST, SIDE>, requested);
+}
+
+template <int SIDE>
+static int batch_grid_side(int P, int U, int fmt, int lk, int requested) {
+    if constexpr (SIDE == 0)
+        if (P == kWave && U == 8) return batch_grid_shape<kWave, 8, SIDE>(fmt, lk, requested);
+    if (P == 8 && U == 4) return batch_grid_shape<8, 4, SIDE>(fmt, lk, requested);
+    if (P == 4 && U == 8) return batch_grid_shape<4, 8, SIDE>(fmt, lk, requested);
+    if (P == 8 && U == 2) return batch_grid_shape<8, 2, SIDE>(fmt, lk, requested);
+    if (P == 4 && U == 4) return batch_grid_shape<4, 4, SIDE>(fmt, lk, requested);
+    return batch_grid_shape<4, 2, SIDE>(fmt, lk, requested);
 }
 
 // grid of the persistent batch launch for a group (host query; call outside
 // stream capture)
-int batch_grid(int P, int U, bool sw, int fmt, int lk, int requested) {
-    if (sw) {
-        if (P == 4 && U == 4) return batch_grid_shape<4, 4, true>(fmt, lk, requested);
-        if (P == 8 && U == 4) return batch_grid_shape<8, 4, true>(fmt, lk, requested);
-        if (P == 8 && U == 2) return batch_grid_shape<8, 2, true>(fmt, lk, requested);
-        return batch_grid_shape<4, 2, true>(fmt, lk, requested);
-    }
-    if (P == kWave && U == 8) return batch_grid_shape<kWave, 8, false>(fmt, lk, requested);
-    if (P == 8 && U == 4) return batch_grid_shape<8, 4, false>(fmt, lk, requested);
-    if (P == 4 && U == 8) return batch_grid_shape<4, 8, false>(fmt, lk, requested);
-    if (P == 8 && U == 2) return batch_grid_shape<8, 2, false>(fmt, lk, requested);
-    if (P == 4 && U == 4) return batch_grid_shape<4, 4, false>(fmt, lk, requested);
-    return batch_grid_shape<4, 2, false>(fmt, lk, requested);
+int batch_grid(int P, int U, int side, int fmt, int lk, int requested) {
+    if (side == 1) return batch_grid_shape<kWave, 8, 1>(fmt, lk, requested);
+    if (side == 2) return batch_grid_side<2>(P, U, fmt, lk, requested);
+    return batch_grid_side<0>(P, U, fmt, lk, requested);
 }
 
-template <int P, int U, bool SW>
+template <int P, int U, int SIDE>
 static void launch_batch_shape(const FitLaunch* seqs, const int* begin, int count, int base, int end, int grid,
                                int fmt, int lk, int* ctr, hipStream_t s) {
     if (fmt == ROSE_TSDF_F32) {
         if (lk == ROSE_LOOKUP_TRILINEAR)
-            launch_batch_kernel<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_TRILINEAR, SW>(seqs, begin, count, base, end, grid,
-                                                                             ctr, s);
+            launch_batch_kernel<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_TRILINEAR, SIDE>(seqs, begin, count, base, end, grid,
+                                                                               ctr, s);
         else
-            launch_batch_kernel<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_NEAREST, SW>(seqs, begin, count, base, end, grid, ctr,
-                                                                            s);
+            launch_batch_kernel<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_NEAREST, SIDE>(seqs, begin, count, base, end, grid,
+                                                                             ctr, s);
     } else if (fmt == ROSE_TSDF_F16) {
         if (lk == ROSE_LOOKUP_TRILINEAR)
-            launch_batch_kernel<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_TRILINEAR, SW>(seqs, begin, count, base, end, grid,
-                                                                             ctr, s);
+            launch_batch_kernel<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_TRILINEAR, SIDE>(seqs, begin, count, base, end, grid,
+                                                                               ctr, s);
         else
-            launch_batch_kernel<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_NEAREST, SW>(seqs, begin, count, base, end, grid, ctr,
-                                                                            s);
+            launch_batch_kernel<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_NEAREST, SIDE>(seqs, begin, count, base, end, grid,
+                                                                             ctr, s);
     } else {
         if (lk == ROSE_LOOKUP_TRILINEAR)
-            launch_batch_kernel<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_TRILINEAR, SW>(seqs, begin, count, base, end, grid,
-                                                                              ctr, s);
+            launch_batch_kernel<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_TRILINEAR, SIDE>(seqs, begin, count, base, end,
+                                                                                grid, ctr, s);
         else
-            launch_batch_kernel<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_NEAREST, SW>(seqs, begin, count, base, end, grid,
-                                                                            ctr, s);
+            launch_batch_kernel<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_NEAREST, SIDE>(seqs, begin, count, base, end, grid,
+                                                                              ctr, s);
     }
+}
+
+template <int SIDE>
+static void launch_batch_side(const FitLaunch* seqs, const int* begin, int count, int base, int end, int grid, int P,
+                              int U, int fmt, int lk, int* ctr, hipStream_t s) {
+    if constexpr (SIDE == 0) {
+        if (P == kWave && U == 8) {
+            launch_batch_shape<kWave, 8, SIDE>(seqs, begin, count, base, end, grid, fmt, lk, ctr, s);
+            return;
+        }
+    }
+    if (P == 8 && U == 4) launch_batch_shape<8, 4, SIDE>(seqs, begin, count, base, end, grid, fmt, lk, ctr, s);
+    else if (P == 4 && U == 8) launch_batch_shape<4, 8, SIDE>(seqs, begin, count, base, end, grid, fmt, lk, ctr, s);
+    else if (P == 8 && U == 2) launch_batch_shape<8, 2, SIDE>(seqs, begin, count, base, end, grid, fmt, lk, ctr, s);
+    else if (P == 4 && U == 4) launch_batch_shape<4, 4, SIDE>(seqs, begin, count, base, end, grid, fmt, lk, ctr, s);
+    else launch_batch_shape<4, 2, SIDE>(seqs, begin, count, base, end, grid, fmt, lk, ctr, s);
 }
 
 bool batch_shape_valid(int P, int U) {
@@ -635,26 +655,16 @@ bool batch_shape_valid(int P, int U) {
            (P == 4 && U == 8) || (P == kWave && U == 8);
 }
 
-bool batch_switch_shape_valid(int P, int U) {
-    return (P == 4 && U == 2) || (P == 8 && U == 2) || (P == 4 && U == 4) || (P == 8 && U == 4);
-}
+bool batch_switch_shape_valid(int P, int U) { return batch_shape_valid(P, U) && P != kWave; }
 
 rose_status launch_fitness_batch(const FitLaunch* seqs_dev, const int* begin_dev, int count, int base, int end,
-                                 int grid, int P, int U, bool sw, int fmt, int lk, int* ctr_dev, hipStream_t s) {
-    if (sw) {
-        if (P == 4 && U == 4) launch_batch_shape<4, 4, true>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
-        else if (P == 8 && U == 4)
-            launch_batch_shape<8, 4, true>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
-        else if (P == 8 && U == 2)
-            launch_batch_shape<8, 2, true>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
-        else launch_batch_shape<4, 2, true>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
-    } else if (P == kWave && U == 8)
-        launch_batch_shape<kWave, 8, false>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
-    else if (P == 8 && U == 4) launch_batch_shape<8, 4, false>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
-    else if (P == 4 && U == 8) launch_batch_shape<4, 8, false>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
-    else if (P == 8 && U == 2) launch_batch_shape<8, 2, false>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
-    else if (P == 4 && U == 4) launch_batch_shape<4, 4, false>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
-    else launch_batch_shape<4, 2, false>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
+                                 int grid, int P, int U, int side, int fmt, int lk, int* ctr_dev, hipStream_t s) {
+    if (side == 1)
+        launch_batch_shape<kWave, 8, 1>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
+    else if (side == 2)
+        launch_batch_side<2>(seqs_dev, begin_dev, count, base, end, grid, P, U, fmt, lk, ctr_dev, s);
+    else
+        launch_batch_side<0>(seqs_dev, begin_dev, count, base, end, grid, P, U, fmt, lk, ctr_dev, s);
     ROSE_CHECK_HIP(hipGetLastError());
     return ROSE_OK;
 }

@@ -564,8 +564,9 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const float* p
 struct BatchGroup {
     int fmt, lk;
     int first, count;  // positions in the group-ordered work arrays
-    int base, end;     // work items [base, end)
+    int base, end;     // work items [base, end) of the points-across (or fixed-shape) list
     int grid;
+    int base_pl, end_pl, grid_pl;  // the switching mode's particle-per-lane list
 };
 
 struct rose_batch {
@@ -579,7 +580,8 @@ struct rose_batch {
     std::vector<int32_t> n;
     FitLaunch* fit_dev = nullptr;
     int* begin_dev = nullptr;
-    int* ctr_dev = nullptr;  // 8 work counters per group
+    int* begin_pl_dev = nullptr;  // the switching mode's particle-per-lane work list
+    int* ctr_dev = nullptr;  // 8 work counters per group and launch
     InitStatic* init_dev = nullptr;
     UpdateArgs* upd_dev = nullptr;
     DevState** stp_dev = nullptr;
@@ -642,6 +644,7 @@ static void batch_free(rose_batch* b) {
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->fit_dev) (void)hipFree(b->fit_dev);
     if (b->begin_dev) (void)hipFree(b->begin_dev);
+    if (b->begin_pl_dev) (void)hipFree(b->begin_pl_dev);
     if (b->ctr_dev) (void)hipFree(b->ctr_dev);
     if (b->init_dev) (void)hipFree(b->init_dev);
     if (b->upd_dev) (void)hipFree(b->upd_dev);
@@ -653,9 +656,10 @@ static void batch_free(rose_batch* b) {
 
 static rose_status batch_enqueue(rose_batch* b, hipStream_t s) {
     // every group's counters are cleared before each round of fitness launches
-    // (by the init kernel, then by each update kernel); each group has its own
-    // 8 counters, so the launches of one round do not disturb each other
-    const int n_ctr = 8 * (int)b->groups.size();
+    // (by the init kernel, then by each update kernel); each group and launch
+    // has its own 8 counters, so the launches of one round do not disturb
+    // each other
+    const int n_ctr = 8 * (int)b->groups.size() * (b->sw ? 2 : 1);
     hipLaunchKernelGGL(k_track_init_batch, dim3(b->count), dim3(1024), 0, s, b->init_dev, b->in_host, b->ctr_dev,
                        n_ctr);
     ROSE_CHECK_HIP(hipGetLastError());
@@ -663,9 +667,16 @@ static rose_status batch_enqueue(rose_batch* b, hipStream_t s) {
         for (size_t q = 0; q < b->groups.size(); ++q) {
             const BatchGroup& gr = b->groups[q];
             rose_status st = launch_fitness_batch(b->fit_dev + gr.first, b->begin_dev + gr.first, gr.count, gr.base,
-                                                  gr.end, gr.grid, b->P, b->U, b->sw, gr.fmt, gr.lk,
+                                                  gr.end, gr.grid, b->P, b->U, b->sw ? 2 : 0, gr.fmt, gr.lk,
                                                   b->ctr_dev + 8 * q, s);
             if (st != ROSE_OK) return st;
+            if (b->sw) {
+                // the particle-per-lane side over its own list and counters
+                st = launch_fitness_batch(b->fit_dev + gr.first, b->begin_pl_dev + gr.first, gr.count, gr.base_pl,
+                                          gr.end_pl, gr.grid_pl, kWave, 8, 1, gr.fmt, gr.lk,
+                                          b->ctr_dev + 8 * ((int)b->groups.size() + q), s);
+                if (st != ROSE_OK) return st;
+            }
         }
         hipLaunchKernelGGL(k_fitness_reduce_batch, dim3((b->max_n + 255) / 256, b->count), dim3(256), 0, s,
                            b->upd_dev);
@@ -738,7 +749,7 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
     std::vector<int> pos(count);
     for (int k = 0; k < count; ++k) pos[order[k]] = k;
     std::vector<FitLaunch> fit(count);
-    std::vector<int> nblk(count, 0);
+    std::vector<int> nblk(count, 0), nblk_pl(count, 0);
     std::vector<InitStatic> init(count);
     std::vector<UpdateArgs> upd(count);
     std::vector<DevState*> stp(count);
@@ -750,10 +761,9 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
         const int sv = (cams[i].height + p.stride - 1) / p.stride;
         const int64_t mmax = (int64_t)su * sv;
         const int splits = choose_splits(n_particles[i], mmax, h->g.fmt, P);
-        const int slots = sw ? splits * kBatchPlSliceMul : splits;
         if ((g = grow(&h->pts, &h->cap_points, mmax)) != ROSE_OK) break;
         if ((g = grow(&h->pts_o, &h->cap_points_o, mmax)) != ROSE_OK) break;
-        if ((g = grow(&h->partial, &h->cap_partial, (int64_t)n_particles[i] * slots)) != ROSE_OK) break;
+        if ((g = grow(&h->partial, &h->cap_partial, (int64_t)n_particles[i] * splits)) != ROSE_OK) break;
         if ((g = grow(&h->F, &h->cap_particles, (int64_t)n_particles[i])) != ROSE_OK) break;
         if (!h->st && hipMalloc(&h->st, sizeof(DevState)) != hipSuccess) {
             set_error("pso_batch_create: hipMalloc failed");
@@ -781,9 +791,7 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
         fit_launch_shape(h, p.lookup, &sp_p, &sp_u, &thr, &zref);
         if (sw) {
             // the sequence's own threshold; the particle-per-lane side's items
-            FitLaunch Lp = L;
-            Lp.splits = splits * kBatchPlSliceMul;
-            nblk[pos[i]] = std::max(nblk[pos[i]], fitness_blocks(Lp, kWave));
+            nblk_pl[pos[i]] = fitness_blocks(L, kWave);
             L.pl_thr = thr;
             L.pl_zref = zref;
         }
@@ -814,12 +822,6 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
         ua.eps = p.eps;
         ua.tau = p.tau;
         ua.stop_tol = p.stop_tol;
-        if (sw) {
-            ua.pl_splits = splits * kBatchPlSliceMul;
-            ua.pl_zref = zref;
-            ua.pl_thr = thr;
-            ua.vox = h->g.vox;
-        }
         stp[i] = h->st;
         b->h.push_back(h);
         b->cams.push_back(cams[i]);
@@ -832,8 +834,11 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
         batch_free(b);
         return g;
     }
-    std::vector<int> begin(count + 1, 0);
-    for (int k = 0; k < count; ++k) begin[k + 1] = begin[k] + (nblk[k] + 7) / 8 * 8;
+    std::vector<int> begin(count + 1, 0), begin_pl(count + 1, 0);
+    for (int k = 0; k < count; ++k) {
+        begin[k + 1] = begin[k] + (nblk[k] + 7) / 8 * 8;
+        begin_pl[k + 1] = begin_pl[k] + (nblk_pl[k] + 7) / 8 * 8;
+    }
     b->total = begin[count];
     for (int k = 0; k < count;) {
         const int key = tsdfs[order[k]]->g.fmt * 2 + params[order[k]].lookup;
@@ -846,14 +851,19 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
         gr.count = e - k;
         gr.base = begin[k];
         gr.end = begin[e];
-        gr.grid = batch_grid(P, U, sw, gr.fmt, gr.lk, gr.end - gr.base);
+        gr.grid = batch_grid(P, U, sw ? 2 : 0, gr.fmt, gr.lk, gr.end - gr.base);
+        gr.base_pl = begin_pl[k];
+        gr.end_pl = begin_pl[e];
+        gr.grid_pl = sw ? batch_grid(kWave, 8, 1, gr.fmt, gr.lk, gr.end_pl - gr.base_pl) : 0;
         b->groups.push_back(gr);
         k = e;
     }
+    const size_t n_ctr = 8 * b->groups.size() * (sw ? 2 : 1);
     bool ok = hipMalloc(&b->fit_dev, sizeof(FitLaunch) * count) == hipSuccess &&
               hipMalloc(&b->begin_dev, sizeof(int) * (count + 1)) == hipSuccess &&
-              hipMalloc(&b->ctr_dev, sizeof(int) * 8 * b->groups.size()) == hipSuccess &&
-              hipMemset(b->ctr_dev, 0, sizeof(int) * 8 * b->groups.size()) == hipSuccess &&
+              hipMalloc(&b->begin_pl_dev, sizeof(int) * (count + 1)) == hipSuccess &&
+              hipMalloc(&b->ctr_dev, sizeof(int) * n_ctr) == hipSuccess &&
+              hipMemset(b->ctr_dev, 0, sizeof(int) * n_ctr) == hipSuccess &&
               hipMalloc(&b->init_dev, sizeof(InitStatic) * count) == hipSuccess &&
               hipMalloc(&b->upd_dev, sizeof(UpdateArgs) * count) == hipSuccess &&
               hipMalloc(&b->stp_dev, sizeof(DevState*) * count) == hipSuccess &&
@@ -861,6 +871,8 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
               hipHostMalloc(&b->out_host, sizeof(DevState) * count, hipHostMallocDefault) == hipSuccess;
     ok = ok && hipMemcpy(b->fit_dev, fit.data(), sizeof(FitLaunch) * count, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(b->begin_dev, begin.data(), sizeof(int) * (count + 1), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(b->begin_pl_dev, begin_pl.data(), sizeof(int) * (count + 1), hipMemcpyHostToDevice) ==
+             hipSuccess &&
          hipMemcpy(b->init_dev, init.data(), sizeof(InitStatic) * count, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(b->upd_dev, upd.data(), sizeof(UpdateArgs) * count, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(b->stp_dev, stp.data(), sizeof(DevState*) * count, hipMemcpyHostToDevice) == hipSuccess;

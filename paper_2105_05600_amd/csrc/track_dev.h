@@ -145,20 +145,14 @@ struct UpdateArgs {
     int32_t early_stop;
     int32_t flags;
     double beta, eps, tau, stop_tol;
-    // a switched batch: the particle-per-lane side wrote pl_splits slices
-    // per particle when the footprint test (pl_zref, pl_thr, vox) holds;
-    // pl_splits = 0 otherwise (always `splits`)
-    int32_t pl_splits;
-    float pl_zref, pl_thr, vox;
 };
 
 // F_i = S_i / |O| (Eq. normallh) from the slice sums on the 2^-39 grid
 // (exact integer sum, then one rounding to binary64, an exact scaling, one
 // correctly rounded division and one rounding to binary32)
 __device__ inline float final_fitness(const UpdateArgs& a, int i, int nO) {
-    const int S = (a.pl_splits > 0 && footprint_small(a.st->r, a.pl_zref, a.pl_thr, a.vox)) ? a.pl_splits : a.splits;
     uint64_t q = 0;
-    for (int k = 0; k < S; ++k) q += a.partial[(int64_t)i * S + k];
+    for (int k = 0; k < a.splits; ++k) q += a.partial[(int64_t)i * a.splits + k];
     const double s = (double)q * kGridScale;
     double f;
     if (a.flags & ROSE_FLAG_NO_NORMALIZE) f = s;
