@@ -77,30 +77,47 @@ def fresh(seqs, depths):
     return vols, states
 
 
-def learned_main(args):
-    """Plain PST (10240 particles, 20 iterations) one sequence after another
-    vs the learned proposal batched over all sequences (settings and weights
-    of paper_2105_05600_amd/weights), on 320x240 sequences at 1-4 m/s."""
+def learned_comparison(n, frames, seed_base, modes=("plain_single", "plain_batched", "learned", "untrained",
+                                                      "small_carried"), log=lambda s: None, single_shape=(0, 0),
+                       batch_shape=(4, 2)):
+    """The same n held-out 320x240 sequences (seeds seed_base + 10 i, 1-4
+    m/s) tracked for `frames` frames, fused at the tracked pose, in each of
+    the modes:
+    * plain_single: plain PST (10240 particles, 20 iterations), one sequence
+      after another through pso_track_frame;
+    * plain_batched: the same budget, batched (pso_batch_track);
+    * learned: the learned proposal batched (pso_batch_track_learned with the
+      committed weights and settings: small template and iteration count,
+      per-sequence plain fallback);
+    * untrained: the same path with an untrained network of the same shape;
+    * small_carried: the learned run's budget batched, centre and axis
+      lengths carried from the previous frame (no network).
+    The single-sequence path runs in single_shape (the switching mode by
+    default), the batched modes in batch_shape.  Returns {mode:
+    {"frames_per_s", "ate_rmse_m" (per sequence), "ate_rmse_mean_m",
+    "ate_rmse_median_m", "fallbacks"}}."""
     from paper_2105_05600_amd import train_proposal as tp
+    import synth.mlp_init as mlp_init
     weights = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "proposal.npz")
     with open(os.path.splitext(weights)[0] + ".json") as f:
         meta = json.load(f)
-    n = args.sequences
-    seqs = [tp.make_sequence(args.seed_base + 10 * i, args.frames, 320, 240) for i in range(n)]
+    seqs = [tp.make_sequence(seed_base + 10 * i, frames, 320, 240) for i in range(n)]
     t0 = time.perf_counter()
-    depths = [[torch.from_numpy(d).cuda() for d in sq.depths(range(args.frames), workers=16)] for sq in seqs]
-    log(f"rendered {n} x {args.frames} frames in {time.perf_counter() - t0:.1f} s")
+    depths = [[torch.from_numpy(d).cuda() for d in sq.depths(range(frames), workers=16)] for sq in seqs]
+    log(f"rendered {n} x {frames} frames in {time.perf_counter() - t0:.1f} s")
     net = rose.Mlp(tp.FEATURE_DIM, 256, 12, max_batch=max(64, n))
-    P = net.pack(tp.load(weights))
+    trained = net.pack(tp.load(weights))
+    untrained = net.pack(mlp_init.init_params(1))
     iters = meta.get("iters", 0) or 20
     pst_small = rose.pst_sample(meta.get("particles", 4096), 5600)
     pst_plain = rose.pst_sample(10240, 5600)
     plain = rose.track_params(max_iters=20, stride=4)
     small = rose.track_params(max_iters=iters, stride=4)
     lp = rose.learned_params(scale=8, kappa=meta["kappa"], delta=meta["delta"], iters=iters)
-    rose.set_fitness_shape(8, 2)
-
-    def start():
+    steps = n * (frames - 1)
+    out = {}
+    for mode in modes:
+        rose.set_fitness_shape(*(single_shape if mode == "plain_single" else batch_shape))
         vols, states = [], (rose.TrackState * n)()
         for i, sq in enumerate(seqs):
             vol = rose.Tsdf(sq.dims, sq.vox, sq.mu, sq.origin)
@@ -108,79 +125,64 @@ def learned_main(args):
             vol.integrate(depths[i][0], sq.K, p0.q, p0.t)
             vols.append(vol)
             states[i] = rose.track_state(p0.q, p0.t, [0.55] * 6)
-        return vols, states
+        est = [[np.array(sq.poses[0].t)] for sq in seqs]
+        b = None
+        if mode == "plain_batched":
+            b = rose.Batch(vols, [sq.K for sq in seqs], [pst_plain] * n, [plain] * n, use_graph=True)
+        elif mode != "plain_single":
+            b = rose.Batch(vols, [sq.K for sq in seqs], [pst_small] * n, [small] * n,
+                           use_graph=(mode == "small_carried"))
+        work = torch.zeros(n * (tp.LOW_W * tp.LOW_H + tp.FEATURE_DIM + 12), device="cuda")
+        vel = [[0.0] * 6 for _ in range(n)]
+        fallbacks = 0
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for f in range(1, frames):
+            if mode == "plain_single":
+                for i, sq in enumerate(seqs):
+                    r = rose.track_frame(vols[i], depths[i][f], sq.K, pst_plain, plain, states[i])
+                    est[i].append(np.array(r["t"]))
+                    vols[i].integrate(depths[i][f], sq.K, r["q"], r["t"])
+                continue
+            prev = [(list(states[i].pose.q), list(states[i].pose.t)) for i in range(n)]
+            if mode in ("learned", "untrained"):
+                res = rose.batch_track_learned(b, [d[f] for d in depths], net,
+                                               trained if mode == "learned" else untrained, work, vel, lp,
+                                               [pst_plain] * n, [plain] * n, states)
+                fallbacks += sum(int(r["fallback"]) for r in res)
+            else:
+                b.track([d[f] for d in depths], states)
+            for i, sq in enumerate(seqs):
+                q, t = list(states[i].pose.q), list(states[i].pose.t)
+                vel[i] = rose.chart_log(prev[i][0], prev[i][1], q, t)
+                est[i].append(np.array(t))
+                vols[i].integrate(depths[i][f], sq.K, q, t)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t1
+        if b is not None:
+            b.close()
+        for v in vols:
+            v.close()
+        ates = [synth.ate(np.array(e), np.array([p.t for p in sq.poses[:frames]]))[1] for e, sq in zip(est, seqs)]
+        out[mode] = {"frames_per_s": steps / wall, "ate_rmse_m": ates, "ate_rmse_mean_m": float(np.mean(ates)),
+                     "ate_rmse_median_m": float(np.median(ates)), "fallbacks": fallbacks}
+        log(f"{mode}: {steps / wall:.1f} frames/s, ATE mean {np.mean(ates):.4f} m, median {np.median(ates):.4f} m, "
+            f"fallbacks {fallbacks}")
+    rose.set_fitness_shape(4, 2)
+    return out
 
-    def ate(est):
-        return [synth.ate(np.array(e), np.array([p.t for p in sq.poses[:args.frames]]))[1]
-                for e, sq in zip(est, seqs)]
 
-    # plain, one sequence after another
-    vols, states = start()
-    est = [[np.array(sq.poses[0].t)] for sq in seqs]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for f in range(1, args.frames):
-        for i, sq in enumerate(seqs):
-            r = rose.track_frame(vols[i], depths[i][f], sq.K, pst_plain, plain, states[i])
-            est[i].append(np.array(r["t"]))
-            vols[i].integrate(depths[i][f], sq.K, r["q"], r["t"])
-    torch.cuda.synchronize()
-    wall_p = time.perf_counter() - t1
-    ate_p = ate(est)
-    for v in vols:
-        v.close()
-    # control: plain PST with the learned run's budget (small template and
-    # iteration count, carried state), batched like the learned form
-    vols, states = start()
-    est = [[np.array(sq.poses[0].t)] for sq in seqs]
-    bc = rose.Batch(vols, [sq.K for sq in seqs], [pst_small] * n, [small] * n, use_graph=False)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for f in range(1, args.frames):
-        res = bc.track([d[f] for d in depths], states)
-        for i, sq in enumerate(seqs):
-            est[i].append(np.array(res[i]["t"]))
-            vols[i].integrate(depths[i][f], sq.K, res[i]["q"], res[i]["t"])
-    torch.cuda.synchronize()
-    wall_c = time.perf_counter() - t1
-    ate_c = ate(est)
-    bc.close()
-    for v in vols:
-        v.close()
-    # learned, batched
-    vols, states = start()
-    est = [[np.array(sq.poses[0].t)] for sq in seqs]
-    b = rose.Batch(vols, [sq.K for sq in seqs], [pst_small] * n, [small] * n, use_graph=False)
-    work = torch.zeros(n * (tp.LOW_W * tp.LOW_H + tp.FEATURE_DIM + 12), device="cuda")
-    vel = [[0.0] * 6 for _ in range(n)]
-    fallbacks = 0
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for f in range(1, args.frames):
-        prev = [(list(states[i].pose.q), list(states[i].pose.t)) for i in range(n)]
-        res = rose.batch_track_learned(b, [d[f] for d in depths], net, P, work, vel, lp, [pst_plain] * n,
-                                       [plain] * n, states)
-        for i, sq in enumerate(seqs):
-            fallbacks += int(res[i]["fallback"])
-            q, t = list(states[i].pose.q), list(states[i].pose.t)
-            vel[i] = rose.chart_log(prev[i][0], prev[i][1], q, t)
-            est[i].append(np.array(t))
-            vols[i].integrate(depths[i][f], sq.K, q, t)
-    torch.cuda.synchronize()
-    wall_l = time.perf_counter() - t1
-    ate_l = ate(est)
-    b.close()
-    steps = n * (args.frames - 1)
+def learned_main(args):
+    """Plain PST one sequence after another and batched, the learned proposal
+    batched with the trained and with an untrained network, and the learned
+    run's budget without a network, on the same held-out 320x240 sequences
+    (see learned_comparison)."""
+    res = learned_comparison(args.sequences, args.frames, args.seed_base, log=log)
     out = {"metric": "learned proposal batched vs plain PST: frames/s over all sequences and ATE",
-           "sequences": n, "frames": args.frames, "image": [320, 240], "seed_base": args.seed_base,
-           "learned": {"particles": pst_small.shape[0], "iters": iters, "kappa": meta["kappa"], "delta": meta["delta"]},
-           "plain_single": {"frames_per_s": steps / wall_p, "ate_rmse_mean_m": float(np.mean(ate_p)),
-                            "ate_rmse_median_m": float(np.median(ate_p))},
-           "learned_batched": {"frames_per_s": steps / wall_l, "ate_rmse_mean_m": float(np.mean(ate_l)),
-                               "ate_rmse_median_m": float(np.median(ate_l)), "fallbacks": fallbacks},
-           "plain_small_batched": {"frames_per_s": steps / wall_c, "ate_rmse_mean_m": float(np.mean(ate_c)),
-                                   "ate_rmse_median_m": float(np.median(ate_c))},
-           "speedup": wall_p / wall_l, "ate_plain": ate_p, "ate_learned": ate_l, "ate_plain_small": ate_c}
+           "sequences": args.sequences, "frames": args.frames, "image": [320, 240], "seed_base": args.seed_base}
+    for mode, r in res.items():
+        out[mode] = {k: v for k, v in r.items()}
+    out["speedup_learned_vs_plain_single"] = res["learned"]["frames_per_s"] / res["plain_single"]["frames_per_s"]
     print(json.dumps(out), flush=True)
 
 

@@ -388,6 +388,8 @@ struct rose_tsdf {
     float* F;           // n_particles fitness values of the last iteration
     rose::DevState* st; // device state of the current frame
     rose::DevState* st_host;  // pinned host copy
+    rose::FrameIn* learn_in;  // pinned: the learned frame's proposal (c_0, r_0) and its finite flag
+    int32_t* learn_ok;
     int64_t cap_points;
     int64_t cap_points_o;
     int64_t cap_partial;

@@ -536,9 +536,16 @@ __global__ __launch_bounds__(256) void k_fitness_batch(const FitLaunch* __restri
         if constexpr (SIDE != 0) {
             const bool small = footprint_small(L.st->r, L.pl_zref, L.pl_thr, L.g.vox);
             if (small != (SIDE == 1)) {
-                // begin[] entries and base are multiples of 8: the next item of
-                // this XCD's queue past the sequence is k = (begin[lo+1] - base) / 8
-                if (threadIdx.x == 0) atomicMax(&ctr[xcd], (begin[lo + 1] - base) >> 3);
+                // skip this sequence and the following ones on the other side
+                // (at most 64 looked at per skip): begin[] entries and base are
+                // multiples of 8, so the next item of this XCD's queue at the
+                // start of sequence j is k = (begin[j] - base) / 8
+                int j = lo + 1;
+                for (int look = 0; look < 64 && j < count; ++look, ++j) {
+                    const FitLaunch& Lj = seqs[j];
+                    if (footprint_small(Lj.st->r, Lj.pl_zref, Lj.pl_thr, Lj.g.vox) == (SIDE == 1)) break;
+                }
+                if (threadIdx.x == 0) atomicMax(&ctr[xcd], (begin[j] - base) >> 3);
                 continue;
             }
         }

@@ -561,6 +561,32 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const float* p
 #include <vector>
 
 // sequences of one storage format and lookup: one fitness launch each
+// The learned PST proposal from the network outputs o (12 per sequence: the
+// chart offset mu, then the log axis lengths l): c_0 = s * Delta(mu) (the
+// chart retraction of the pose s held in in[i].qc, in[i].tc on entry) and
+// r_0 = clamp(kappa exp(l), r_min, r_max), written over in[i] (pinned host
+// memory read by the tracker's init kernel or by the host).  A sequence
+// whose outputs are not all finite keeps its pose and axis lengths and is
+// flagged ok[i] = 0.  One thread per sequence.
+__global__ __launch_bounds__(64) void k_learned_proposal(const float* o, int32_t n, FrameIn* in, int32_t* ok,
+                                                         double kappa, double r_min, double r_max) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float* oi = o + 12 * (int64_t)i;
+    bool fin = true;
+    for (int e = 0; e < 12; ++e) fin = fin && isfinite(oi[e]);
+    ok[i] = fin ? 1 : 0;
+    if (!fin || !in[i].active) return;
+    double mu[6], q[4], t[3];
+    for (int d = 0; d < 6; ++d) mu[d] = (double)oi[d];
+    for (int e = 0; e < 4; ++e) q[e] = in[i].qc[e];
+    for (int e = 0; e < 3; ++e) t[e] = in[i].tc[e];
+    retract(q, t, mu);
+    for (int e = 0; e < 4; ++e) in[i].qc[e] = q[e];
+    for (int e = 0; e < 3; ++e) in[i].tc[e] = t[e];
+    for (int d = 0; d < 6; ++d) in[i].r[d] = fmin(r_max, fmax(r_min, kappa * exp_rho((double)oi[6 + d])));
+}
+
 struct BatchGroup {
     int fmt, lk;
     int first, count;  // positions in the group-ordered work arrays
@@ -587,6 +613,7 @@ struct rose_batch {
     DevState** stp_dev = nullptr;
     FrameIn* in_host = nullptr;
     DevState* out_host = nullptr;
+    int32_t* prop_ok = nullptr;  // pinned: the learned proposal's finite flag per sequence
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t graph_stream = nullptr;
@@ -651,6 +678,7 @@ static void batch_free(rose_batch* b) {
     if (b->stp_dev) (void)hipFree(b->stp_dev);
     if (b->in_host) (void)hipHostFree(b->in_host);
     if (b->out_host) (void)hipHostFree(b->out_host);
+    if (b->prop_ok) (void)hipHostFree(b->prop_ok);
     delete b;
 }
 
@@ -687,6 +715,10 @@ static rose_status batch_enqueue(rose_batch* b, hipStream_t s) {
     ROSE_CHECK_HIP(hipGetLastError());
     return ROSE_OK;
 }
+
+static rose_status batch_track_impl(rose_batch* b, const float* const* depth_devs, const rose_pose* init_centres,
+                                    const double* init_rs, const float* prop_dev, const rose_learned_params* lp,
+                                    rose_track_state* states, rose_track_stats* stats, hipStream_t s);
 
 extern "C" {
 
@@ -868,7 +900,8 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
               hipMalloc(&b->upd_dev, sizeof(UpdateArgs) * count) == hipSuccess &&
               hipMalloc(&b->stp_dev, sizeof(DevState*) * count) == hipSuccess &&
               hipHostMalloc(&b->in_host, sizeof(FrameIn) * count, hipHostMallocDefault) == hipSuccess &&
-              hipHostMalloc(&b->out_host, sizeof(DevState) * count, hipHostMallocDefault) == hipSuccess;
+              hipHostMalloc(&b->out_host, sizeof(DevState) * count, hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&b->prop_ok, sizeof(int32_t) * count, hipHostMallocDefault) == hipSuccess;
     ok = ok && hipMemcpy(b->fit_dev, fit.data(), sizeof(FitLaunch) * count, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(b->begin_dev, begin.data(), sizeof(int) * (count + 1), hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(b->begin_pl_dev, begin_pl.data(), sizeof(int) * (count + 1), hipMemcpyHostToDevice) ==
@@ -901,6 +934,19 @@ rose_status pso_batch_destroy(rose_batch* b) {
 rose_status pso_batch_track(rose_batch* b, const float* const* depth_devs, const rose_pose* init_centres,
                             const double* init_rs, rose_track_state* states, rose_track_stats* stats,
                             hipStream_t s) {
+    return batch_track_impl(b, depth_devs, init_centres, init_rs, nullptr, nullptr, states, stats, s);
+}
+
+}  // extern "C"
+
+// One batched frame step.  prop_dev (nullable): network outputs (12 per
+// sequence, device) from which k_learned_proposal sets every active
+// sequence's c_0 and r_0 on the device, after the host has written the
+// carried pose and axis lengths and before the step's launches, so the
+// outputs never travel to the host; its finite flags land in b->prop_ok.
+static rose_status batch_track_impl(rose_batch* b, const float* const* depth_devs, const rose_pose* init_centres,
+                                    const double* init_rs, const float* prop_dev, const rose_learned_params* lp,
+                                    rose_track_state* states, rose_track_stats* stats, hipStream_t s) {
     clear_error();
     ROSE_REQUIRE(b && depth_devs && states, ROSE_E_ARG, "pso_batch_track: NULL argument");
     for (int i = 0; i < b->count; ++i) ROSE_REQUIRE(depth_devs[i], ROSE_E_ARG, "pso_batch_track: NULL depth %d", i);
@@ -934,6 +980,11 @@ rose_status pso_batch_track(rose_batch* b, const float* const* depth_devs, const
                 stats[i].rho_iter[0] = 0.5;
             }
         }
+    }
+    if (prop_dev) {
+        hipLaunchKernelGGL(k_learned_proposal, dim3((b->count + 63) / 64), dim3(64), 0, s, prop_dev, b->count,
+                           b->in_host, b->prop_ok, lp->kappa, lp->r_min, lp->r_max);
+        ROSE_CHECK_HIP(hipGetLastError());
     }
     const bool graph = b->use_graph && s != nullptr;
     if (graph) {
@@ -991,8 +1042,6 @@ rose_status pso_batch_track(rose_batch* b, const float* const* depth_devs, const
     }
     return ROSE_OK;
 }
-
-}  // extern "C"
 
 // ------------------------------------------------------- learned proposal
 extern "C" {
@@ -1063,20 +1112,26 @@ rose_status pso_track_frame_learned(rose_tsdf* h, const float* depth_dev, const 
     if ((st = proposal_features(depth_dev, cam, render, &low, lp->scale, velocity, lp->feature_dim, X, s)) != ROSE_OK)
         return st;
     if ((st = rose_mlp_forward(mlp, mlp_params_dev, X, 1, out, s)) != ROSE_OK) return st;
-    float o[12];
-    ROSE_CHECK_HIP(hipMemcpyAsync(o, out, sizeof o, hipMemcpyDeviceToHost, s));
+    // the proposal on the device, by the same kernel as the batched step's
+    if (!h->learn_in) ROSE_CHECK_HIP(hipHostMalloc(&h->learn_in, sizeof(FrameIn), hipHostMallocDefault));
+    if (!h->learn_ok) ROSE_CHECK_HIP(hipHostMalloc(&h->learn_ok, sizeof(int32_t), hipHostMallocDefault));
+    FrameIn& lin = *h->learn_in;
+    for (int i = 0; i < 4; ++i) lin.qc[i] = state->pose.q[i];
+    for (int i = 0; i < 3; ++i) lin.tc[i] = state->pose.t[i];
+    for (int d = 0; d < 6; ++d) lin.r[d] = state->r[d];
+    lin.active = 1;
+    hipLaunchKernelGGL(k_learned_proposal, dim3(1), dim3(64), 0, s, out, 1, h->learn_in, h->learn_ok, lp->kappa,
+                       lp->r_min, lp->r_max);
+    ROSE_CHECK_HIP(hipGetLastError());
     ROSE_CHECK_HIP(hipStreamSynchronize(s));
-    bool finite = true;
-    for (int i = 0; i < 12; ++i) finite = finite && std::isfinite(o[i]);
+    const bool finite = *h->learn_ok != 0;
     bool fallback = !finite;
     if (finite) {
-        double mu[6], r0[6];
-        for (int d = 0; d < 6; ++d) {
-            mu[d] = o[d];
-            r0[d] = std::min(lp->r_max, std::max(lp->r_min, lp->kappa * std::exp((double)o[6 + d])));
-        }
+        double r0[6];
         rose_pose c0;
-        if ((st = rose_chart_exp(&state->pose, mu, &c0)) != ROSE_OK) return st;
+        for (int i = 0; i < 4; ++i) c0.q[i] = lin.qc[i];
+        for (int i = 0; i < 3; ++i) c0.t[i] = lin.tc[i];
+        for (int d = 0; d < 6; ++d) r0[d] = lin.r[d];
         rose_track_state trial = *state;
         rose_track_params pl = *p;
         if (lp->iters > 0) pl.max_iters = lp->iters;
@@ -1168,32 +1223,16 @@ rose_status pso_batch_track_learned(rose_batch* b, const float* const* depth_dev
             return st;
     }
     if ((st = rose_mlp_forward(mlp, mlp_params_dev, X, n, out, s)) != ROSE_OK) return st;
-    std::vector<float> o((size_t)n * 12);
-    ROSE_CHECK_HIP(hipMemcpyAsync(o.data(), out, sizeof(float) * o.size(), hipMemcpyDeviceToHost, s));
-    ROSE_CHECK_HIP(hipStreamSynchronize(s));
-    // proposals: c_0 = s^{t-1} * Delta(mu), r_0 = kappa exp(l) clamped; sequences
-    // without a finite proposal run from their own state and fall back below
-    std::vector<rose_pose> c0(n);
-    std::vector<double> r0((size_t)n * 6);
-    std::vector<char> finite(n, 1);
-    for (int i = 0; i < n; ++i) {
-        c0[i] = states[i].pose;
-        for (int d = 0; d < 6; ++d) r0[6 * i + d] = states[i].r[d];
-        if (!states[i].tsdf_built) continue;
-        const float* oi = &o[(size_t)i * 12];
-        for (int e = 0; e < 12; ++e) finite[i] = finite[i] && std::isfinite(oi[e]);
-        if (!finite[i]) continue;
-        double mu[6];
-        for (int d = 0; d < 6; ++d) {
-            mu[d] = oi[d];
-            r0[6 * i + d] = std::min(lp->r_max, std::max(lp->r_min, lp->kappa * std::exp((double)oi[6 + d])));
-        }
-        if ((st = rose_chart_exp(&states[i].pose, mu, &c0[i])) != ROSE_OK) return st;
-    }
+    // proposals c_0 = s^{t-1} * Delta(mu), r_0 = kappa exp(l) clamped, set on
+    // the device inside the step (the network outputs stay on the device);
+    // sequences without a finite proposal run from their own state and fall
+    // back below
     std::vector<rose_track_state> trial(states, states + n);
     std::vector<rose_track_stats> tstats(n);
-    if ((st = pso_batch_track(b, depth_devs, c0.data(), r0.data(), trial.data(), tstats.data(), s)) != ROSE_OK)
+    if ((st = batch_track_impl(b, depth_devs, nullptr, nullptr, out, lp, trial.data(), tstats.data(), s)) != ROSE_OK)
         return st;
+    std::vector<char> finite(n, 1);
+    for (int i = 0; i < n; ++i) finite[i] = !states[i].tsdf_built || b->prop_ok[i] != 0;
     for (int i = 0; i < n; ++i) {
         const bool keep = !states[i].tsdf_built ||
                           (finite[i] && tstats[i].status == ROSE_OK && trial[i].rho >= states[i].rho - lp->delta);

@@ -301,6 +301,8 @@ rose_status tsdf_destroy(rose_tsdf* h) {
     if (h->F) (void)hipFree(h->F);
     if (h->st) (void)hipFree(h->st);
     if (h->st_host) (void)hipHostFree(h->st_host);
+    if (h->learn_in) (void)hipHostFree(h->learn_in);
+    if (h->learn_ok) (void)hipHostFree(h->learn_ok);
     if (h->sw_x) (void)hipFree(h->sw_x);
     if (h->sw_v) (void)hipFree(h->sw_v);
     if (h->sw_p) (void)hipFree(h->sw_p);
