@@ -10,8 +10,8 @@ iterations, fusion at the tracked pose after every frame.  Depth frames are
 rendered on the host before timing and are resident in HBM.
 
 The batch's fitness launch shape is chosen by timing the supported shapes
-and the switching mode on the first frame steps (a small autotuner); the
-single-sequence path runs in the switching mode.  Both paths give
+on the first frame steps (a small autotuner); the single-sequence path runs
+in the switching mode.  Both paths give
 bit-identical poses (tested); the JSON line reports frames/s and
 evaluations/s of both and the ATE of every sequence.
 

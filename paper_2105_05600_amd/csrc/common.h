@@ -465,17 +465,10 @@ FitConfig fit_config(const rose_tsdf* h);
 void fit_launch_shape(const rose_tsdf* h, int lk, int* p, int* u, float* thr_vox, float* zref_m);
 int fitness_blocks(const FitLaunch& L, int P);
 bool batch_shape_valid(int p, int u);
-// points-across shapes the switched batch kernel is built for
-bool batch_switch_shape_valid(int p, int u);
-int batch_grid(int P, int U, int side, int fmt, int lk, int requested);
-// ctr_dev: the group's 8 per-XCD work counters, zero at launch.  side: 0
-// every item runs; in the switching mode the points-across launch (P x U,
-// side 2) runs the items of sequences whose footprint test fails and the
-// particle-per-lane launch (64 x 8, side 1) those whose test holds, each
-// skipping the rest of a sequence's items at once (per-sequence thresholds
-// in the launch records)
+int batch_grid(int P, int U, int fmt, int lk, int requested);
+// ctr_dev: the group's 8 per-XCD work counters, zero at launch
 rose_status launch_fitness_batch(const FitLaunch* seqs_dev, const int* begin_dev, int count, int base, int end,
-                                 int grid, int P, int U, int side, int fmt, int lk, int* ctr_dev, hipStream_t s);
+                                 int grid, int P, int U, int fmt, int lk, int* ctr_dev, hipStream_t s);
 
 // PST template rows 0..n-1 (tsdf.hip)
 rose_status launch_pst_sample(int64_t n, uint64_t seed, float* out_dev, hipStream_t s);

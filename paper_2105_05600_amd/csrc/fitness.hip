@@ -132,7 +132,10 @@ __device__ inline float wave_sum_f(float v) {
 // same device state, so exactly one of them does the work.
 __device__ inline bool switch_skips(const FitLaunch& a) {
     if (a.pl_side == 0) return false;
-    const bool small = footprint_small(a.st->r, a.pl_zref, a.pl_thr, a.g.vox);
+    const double* r = a.st->r;
+    const double rr = fmax(fmax(r[0], r[1]), r[2]);
+    const double rt = fmax(fmax(r[3], r[4]), r[5]);
+    const bool small = (rt + (double)a.pl_zref * rr) <= (double)a.pl_thr * (double)a.g.vox;
     return small != (a.pl_side == 1);
 }
 
@@ -504,17 +507,7 @@ __device__ inline int fitness_blocks_dev(const FitLaunch& L, int P) {
 // counters (ctr[0..7]) are zero at launch: the kernel that runs before each
 // launch on the stream clears them, and every workgroup leaves once its
 // queue passes `end`.
-//
-// SIDE (the switching mode): the points-across launch (SIDE 2) and the
-// particle-per-lane launch (SIDE 1) each walk their own work list over all
-// sequences; an item runs only when its sequence's footprint test (the one
-// the single-sequence kernels take, on the same state) selects the
-// launch's side.  Otherwise the workgroup moves its XCD's counter past the
-// rest of that sequence's items (atomicMax: counters only move forward, and
-// every skipped item belongs to the same sequence), so a sequence on the
-// other side costs a few fetches, not one per item.  SIDE 0: every item
-// runs (one fixed shape).
-template <int P, int U, int FMT, int LK, int SIDE>
+template <int P, int U, int FMT, int LK>
 __global__ __launch_bounds__(256) void k_fitness_batch(const FitLaunch* __restrict__ seqs,
                                                        const int* __restrict__ begin, int count, int base, int end,
                                                        int* __restrict__ ctr) {
@@ -533,22 +526,6 @@ __global__ __launch_bounds__(256) void k_fitness_batch(const FitLaunch* __restri
             else hi = mid;
         }
         const FitLaunch L = seqs[lo];  // wave-uniform: scalar loads of read-only memory
-        if constexpr (SIDE != 0) {
-            const bool small = footprint_small(L.st->r, L.pl_zref, L.pl_thr, L.g.vox);
-            if (small != (SIDE == 1)) {
-                // skip this sequence and the following ones on the other side
-                // (at most 64 looked at per skip): begin[] entries and base are
-                // multiples of 8, so the next item of this XCD's queue at the
-                // start of sequence j is k = (begin[j] - base) / 8
-                int j = lo + 1;
-                for (int look = 0; look < 64 && j < count; ++look, ++j) {
-                    const FitLaunch& Lj = seqs[j];
-                    if (footprint_small(Lj.st->r, Lj.pl_zref, Lj.pl_thr, Lj.g.vox) == (SIDE == 1)) break;
-                }
-                if (threadIdx.x == 0) atomicMax(&ctr[xcd], (begin[j] - base) >> 3);
-                continue;
-            }
-        }
         const int blk = w - begin[lo];
         if (blk >= fitness_blocks_dev(L, P)) continue;
         // the particle-per-lane body synchronises its workgroup once; every
@@ -573,88 +550,58 @@ static int resident_grid(K kernel, int requested) {
     return std::max(8, std::min(requested, cus * per_cu) / 8 * 8);
 }
 
-template <int P, int U, int FMT, int LK, int SIDE>
+template <int P, int U, int FMT, int LK>
 static void launch_batch_kernel(const FitLaunch* seqs, const int* begin, int count, int base, int end, int grid,
                                 int* ctr, hipStream_t s) {
-    hipLaunchKernelGGL((k_fitness_batch<P, U, FMT, LK, SIDE>), dim3(grid), dim3(256), 0, s, seqs, begin, count, base,
-                       end, ctr);
+    hipLaunchKernelGGL((k_fitness_batch<P, U, FMT, LK>), dim3(grid), dim3(256), 0, s, seqs, begin, count, base, end,
+                       ctr);
 }
 
-template <int P, int U, int SIDE>
+template <int P, int U>
 static int batch_grid_shape(int fmt, int lk, int requested) {
     if (fmt == ROSE_TSDF_F32)
         return lk == ROSE_LOOKUP_TRILINEAR
-                   ? resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_TRILINEAR, SIDE>, requested)
-                   : resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_NEAREST, SIDE>, requested);
+                   ? resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_TRILINEAR>, requested)
+                   : resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_NEAREST>, requested);
     if (fmt == ROSE_TSDF_F16)
         return lk == ROSE_LOOKUP_TRILINEAR
-                   ? resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_TRILINEAR, SIDE>, requested)
-                   : resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_NEAREST, SIDE>, requested);
+                   ? resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_TRILINEAR>, requested)
+                   : resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_NEAREST>, requested);
     return lk == ROSE_LOOKUP_TRILINEAR
-               ? resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_TRILINEAR, SIDE>, requested)
-               : resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_NEAREST, SIDE>, requested);
-}
-
-template <int SIDE>
-static int batch_grid_side(int P, int U, int fmt, int lk, int requested) {
-    if constexpr (SIDE == 0)
-        if (P == kWave && U == 8) return batch_grid_shape<kWave, 8, SIDE>(fmt, lk, requested);
-    if (P == 8 && U == 4) return batch_grid_shape<8, 4, SIDE>(fmt, lk, requested);
-    if (P == 4 && U == 8) return batch_grid_shape<4, 8, SIDE>(fmt, lk, requested);
-    if (P == 8 && U == 2) return batch_grid_shape<8, 2, SIDE>(fmt, lk, requested);
-    if (P == 4 && U == 4) return batch_grid_shape<4, 4, SIDE>(fmt, lk, requested);
-    return batch_grid_shape<4, 2, SIDE>(fmt, lk, requested);
+               ? resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_TRILINEAR>, requested)
+               : resident_grid(&k_fitness_batch<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_NEAREST>, requested);
 }
 
 // grid of the persistent batch launch for a group (host query; call outside
 // stream capture)
-int batch_grid(int P, int U, int side, int fmt, int lk, int requested) {
-    if (side == 1) return batch_grid_shape<kWave, 8, 1>(fmt, lk, requested);
-    if (side == 2) return batch_grid_side<2>(P, U, fmt, lk, requested);
-    return batch_grid_side<0>(P, U, fmt, lk, requested);
+int batch_grid(int P, int U, int fmt, int lk, int requested) {
+    if (P == kWave && U == 8) return batch_grid_shape<kWave, 8>(fmt, lk, requested);
+    if (P == 8 && U == 4) return batch_grid_shape<8, 4>(fmt, lk, requested);
+    if (P == 4 && U == 8) return batch_grid_shape<4, 8>(fmt, lk, requested);
+    if (P == 8 && U == 2) return batch_grid_shape<8, 2>(fmt, lk, requested);
+    if (P == 4 && U == 4) return batch_grid_shape<4, 4>(fmt, lk, requested);
+    return batch_grid_shape<4, 2>(fmt, lk, requested);
 }
 
-template <int P, int U, int SIDE>
+template <int P, int U>
 static void launch_batch_shape(const FitLaunch* seqs, const int* begin, int count, int base, int end, int grid,
                                int fmt, int lk, int* ctr, hipStream_t s) {
     if (fmt == ROSE_TSDF_F32) {
         if (lk == ROSE_LOOKUP_TRILINEAR)
-            launch_batch_kernel<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_TRILINEAR, SIDE>(seqs, begin, count, base, end, grid,
-                                                                               ctr, s);
+            launch_batch_kernel<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_TRILINEAR>(seqs, begin, count, base, end, grid, ctr, s);
         else
-            launch_batch_kernel<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_NEAREST, SIDE>(seqs, begin, count, base, end, grid,
-                                                                             ctr, s);
+            launch_batch_kernel<P, U, ROSE_TSDF_F32, ROSE_LOOKUP_NEAREST>(seqs, begin, count, base, end, grid, ctr, s);
     } else if (fmt == ROSE_TSDF_F16) {
         if (lk == ROSE_LOOKUP_TRILINEAR)
-            launch_batch_kernel<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_TRILINEAR, SIDE>(seqs, begin, count, base, end, grid,
-                                                                               ctr, s);
+            launch_batch_kernel<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_TRILINEAR>(seqs, begin, count, base, end, grid, ctr, s);
         else
-            launch_batch_kernel<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_NEAREST, SIDE>(seqs, begin, count, base, end, grid,
-                                                                             ctr, s);
+            launch_batch_kernel<P, U, ROSE_TSDF_F16, ROSE_LOOKUP_NEAREST>(seqs, begin, count, base, end, grid, ctr, s);
     } else {
         if (lk == ROSE_LOOKUP_TRILINEAR)
-            launch_batch_kernel<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_TRILINEAR, SIDE>(seqs, begin, count, base, end,
-                                                                                grid, ctr, s);
+            launch_batch_kernel<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_TRILINEAR>(seqs, begin, count, base, end, grid, ctr, s);
         else
-            launch_batch_kernel<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_NEAREST, SIDE>(seqs, begin, count, base, end, grid,
-                                                                              ctr, s);
+            launch_batch_kernel<P, U, ROSE_TSDF_SN16, ROSE_LOOKUP_NEAREST>(seqs, begin, count, base, end, grid, ctr, s);
     }
-}
-
-template <int SIDE>
-static void launch_batch_side(const FitLaunch* seqs, const int* begin, int count, int base, int end, int grid, int P,
-                              int U, int fmt, int lk, int* ctr, hipStream_t s) {
-    if constexpr (SIDE == 0) {
-        if (P == kWave && U == 8) {
-            launch_batch_shape<kWave, 8, SIDE>(seqs, begin, count, base, end, grid, fmt, lk, ctr, s);
-            return;
-        }
-    }
-    if (P == 8 && U == 4) launch_batch_shape<8, 4, SIDE>(seqs, begin, count, base, end, grid, fmt, lk, ctr, s);
-    else if (P == 4 && U == 8) launch_batch_shape<4, 8, SIDE>(seqs, begin, count, base, end, grid, fmt, lk, ctr, s);
-    else if (P == 8 && U == 2) launch_batch_shape<8, 2, SIDE>(seqs, begin, count, base, end, grid, fmt, lk, ctr, s);
-    else if (P == 4 && U == 4) launch_batch_shape<4, 4, SIDE>(seqs, begin, count, base, end, grid, fmt, lk, ctr, s);
-    else launch_batch_shape<4, 2, SIDE>(seqs, begin, count, base, end, grid, fmt, lk, ctr, s);
 }
 
 bool batch_shape_valid(int P, int U) {
@@ -662,16 +609,15 @@ bool batch_shape_valid(int P, int U) {
            (P == 4 && U == 8) || (P == kWave && U == 8);
 }
 
-bool batch_switch_shape_valid(int P, int U) { return batch_shape_valid(P, U) && P != kWave; }
-
 rose_status launch_fitness_batch(const FitLaunch* seqs_dev, const int* begin_dev, int count, int base, int end,
-                                 int grid, int P, int U, int side, int fmt, int lk, int* ctr_dev, hipStream_t s) {
-    if (side == 1)
-        launch_batch_shape<kWave, 8, 1>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
-    else if (side == 2)
-        launch_batch_side<2>(seqs_dev, begin_dev, count, base, end, grid, P, U, fmt, lk, ctr_dev, s);
-    else
-        launch_batch_side<0>(seqs_dev, begin_dev, count, base, end, grid, P, U, fmt, lk, ctr_dev, s);
+                                 int grid, int P, int U, int fmt, int lk, int* ctr_dev, hipStream_t s) {
+    if (P == kWave && U == 8)
+        launch_batch_shape<kWave, 8>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
+    else if (P == 8 && U == 4) launch_batch_shape<8, 4>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
+    else if (P == 4 && U == 8) launch_batch_shape<4, 8>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
+    else if (P == 8 && U == 2) launch_batch_shape<8, 2>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
+    else if (P == 4 && U == 4) launch_batch_shape<4, 4>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
+    else launch_batch_shape<4, 2>(seqs_dev, begin_dev, count, base, end, grid, fmt, lk, ctr_dev, s);
     ROSE_CHECK_HIP(hipGetLastError());
     return ROSE_OK;
 }

@@ -590,14 +590,12 @@ __global__ __launch_bounds__(64) void k_learned_proposal(const float* o, int32_t
 struct BatchGroup {
     int fmt, lk;
     int first, count;  // positions in the group-ordered work arrays
-    int base, end;     // work items [base, end) of the points-across (or fixed-shape) list
+    int base, end;     // work items [base, end)
     int grid;
-    int base_pl, end_pl, grid_pl;  // the switching mode's particle-per-lane list
 };
 
 struct rose_batch {
     int32_t count = 0, K = 0, P = 4, U = 2, total = 0, max_n = 1;
-    bool sw = false;  // the switching mode (P x U its points-across side)
     std::vector<BatchGroup> groups;
     bool use_graph = true;
     std::vector<rose_tsdf*> h;
@@ -606,8 +604,7 @@ struct rose_batch {
     std::vector<int32_t> n;
     FitLaunch* fit_dev = nullptr;
     int* begin_dev = nullptr;
-    int* begin_pl_dev = nullptr;  // the switching mode's particle-per-lane work list
-    int* ctr_dev = nullptr;  // 8 work counters per group and launch
+    int* ctr_dev = nullptr;  // 8 work counters per group
     InitStatic* init_dev = nullptr;
     UpdateArgs* upd_dev = nullptr;
     DevState** stp_dev = nullptr;
@@ -671,7 +668,6 @@ static void batch_free(rose_batch* b) {
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->fit_dev) (void)hipFree(b->fit_dev);
     if (b->begin_dev) (void)hipFree(b->begin_dev);
-    if (b->begin_pl_dev) (void)hipFree(b->begin_pl_dev);
     if (b->ctr_dev) (void)hipFree(b->ctr_dev);
     if (b->init_dev) (void)hipFree(b->init_dev);
     if (b->upd_dev) (void)hipFree(b->upd_dev);
@@ -684,10 +680,9 @@ static void batch_free(rose_batch* b) {
 
 static rose_status batch_enqueue(rose_batch* b, hipStream_t s) {
     // every group's counters are cleared before each round of fitness launches
-    // (by the init kernel, then by each update kernel); each group and launch
-    // has its own 8 counters, so the launches of one round do not disturb
-    // each other
-    const int n_ctr = 8 * (int)b->groups.size() * (b->sw ? 2 : 1);
+    // (by the init kernel, then by each update kernel); each group has its own
+    // 8 counters, so the launches of one round do not disturb each other
+    const int n_ctr = 8 * (int)b->groups.size();
     hipLaunchKernelGGL(k_track_init_batch, dim3(b->count), dim3(1024), 0, s, b->init_dev, b->in_host, b->ctr_dev,
                        n_ctr);
     ROSE_CHECK_HIP(hipGetLastError());
@@ -695,16 +690,8 @@ static rose_status batch_enqueue(rose_batch* b, hipStream_t s) {
         for (size_t q = 0; q < b->groups.size(); ++q) {
             const BatchGroup& gr = b->groups[q];
             rose_status st = launch_fitness_batch(b->fit_dev + gr.first, b->begin_dev + gr.first, gr.count, gr.base,
-                                                  gr.end, gr.grid, b->P, b->U, b->sw ? 2 : 0, gr.fmt, gr.lk,
-                                                  b->ctr_dev + 8 * q, s);
+                                                  gr.end, gr.grid, b->P, b->U, gr.fmt, gr.lk, b->ctr_dev + 8 * q, s);
             if (st != ROSE_OK) return st;
-            if (b->sw) {
-                // the particle-per-lane side over its own list and counters
-                st = launch_fitness_batch(b->fit_dev + gr.first, b->begin_pl_dev + gr.first, gr.count, gr.base_pl,
-                                          gr.end_pl, gr.grid_pl, kWave, 8, 1, gr.fmt, gr.lk,
-                                          b->ctr_dev + 8 * ((int)b->groups.size() + q), s);
-                if (st != ROSE_OK) return st;
-            }
         }
         hipLaunchKernelGGL(k_fitness_reduce_batch, dim3((b->max_n + 255) / 256, b->count), dim3(256), 0, s,
                            b->upd_dev);
@@ -759,18 +746,15 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
     b->count = count;
     b->use_graph = use_graph != 0;
     // the first handle's launch configuration: its fixed shape, or in the
-    // switching mode its points-across shape (each sequence keeps its own
-    // switch threshold)
+    // switching mode its points-across shape (the batch does not switch)
     const FitConfig cfg = fit_config(tsdfs[0]);
-    const bool sw = cfg.sw != 0;
-    int P = sw ? cfg.wide_p : cfg.p, U = sw ? cfg.wide_u : cfg.u;
-    if (sw ? !batch_switch_shape_valid(P, U) : !batch_shape_valid(P, U)) {
+    int P = cfg.sw ? cfg.wide_p : cfg.p, U = cfg.sw ? cfg.wide_u : cfg.u;
+    if (!batch_shape_valid(P, U)) {
         P = 4;
         U = 2;
     }
     b->P = P;
     b->U = U;
-    b->sw = sw;
     // the fitness work arrays list the sequences grouped by (format, lookup)
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
@@ -781,7 +765,7 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
     std::vector<int> pos(count);
     for (int k = 0; k < count; ++k) pos[order[k]] = k;
     std::vector<FitLaunch> fit(count);
-    std::vector<int> nblk(count, 0), nblk_pl(count, 0);
+    std::vector<int> nblk(count, 0);
     std::vector<InitStatic> init(count);
     std::vector<UpdateArgs> upd(count);
     std::vector<DevState*> stp(count);
@@ -818,15 +802,6 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
         L.shape_u = U;
         L.partial = h->partial;
         nblk[pos[i]] = fitness_blocks(L, P);
-        int sp_p, sp_u;
-        float thr = 0.0f, zref = 0.0f;
-        fit_launch_shape(h, p.lookup, &sp_p, &sp_u, &thr, &zref);
-        if (sw) {
-            // the sequence's own threshold; the particle-per-lane side's items
-            nblk_pl[pos[i]] = fitness_blocks(L, kWave);
-            L.pl_thr = thr;
-            L.pl_zref = zref;
-        }
         InitStatic& ia = init[i];
         ia = InitStatic{};
         ia.st = h->st;
@@ -866,11 +841,8 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
         batch_free(b);
         return g;
     }
-    std::vector<int> begin(count + 1, 0), begin_pl(count + 1, 0);
-    for (int k = 0; k < count; ++k) {
-        begin[k + 1] = begin[k] + (nblk[k] + 7) / 8 * 8;
-        begin_pl[k + 1] = begin_pl[k] + (nblk_pl[k] + 7) / 8 * 8;
-    }
+    std::vector<int> begin(count + 1, 0);
+    for (int k = 0; k < count; ++k) begin[k + 1] = begin[k] + (nblk[k] + 7) / 8 * 8;
     b->total = begin[count];
     for (int k = 0; k < count;) {
         const int key = tsdfs[order[k]]->g.fmt * 2 + params[order[k]].lookup;
@@ -883,17 +855,13 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
         gr.count = e - k;
         gr.base = begin[k];
         gr.end = begin[e];
-        gr.grid = batch_grid(P, U, sw ? 2 : 0, gr.fmt, gr.lk, gr.end - gr.base);
-        gr.base_pl = begin_pl[k];
-        gr.end_pl = begin_pl[e];
-        gr.grid_pl = sw ? batch_grid(kWave, 8, 1, gr.fmt, gr.lk, gr.end_pl - gr.base_pl) : 0;
+        gr.grid = batch_grid(P, U, gr.fmt, gr.lk, gr.end - gr.base);
         b->groups.push_back(gr);
         k = e;
     }
-    const size_t n_ctr = 8 * b->groups.size() * (sw ? 2 : 1);
+    const size_t n_ctr = 8 * b->groups.size();
     bool ok = hipMalloc(&b->fit_dev, sizeof(FitLaunch) * count) == hipSuccess &&
               hipMalloc(&b->begin_dev, sizeof(int) * (count + 1)) == hipSuccess &&
-              hipMalloc(&b->begin_pl_dev, sizeof(int) * (count + 1)) == hipSuccess &&
               hipMalloc(&b->ctr_dev, sizeof(int) * n_ctr) == hipSuccess &&
               hipMemset(b->ctr_dev, 0, sizeof(int) * n_ctr) == hipSuccess &&
               hipMalloc(&b->init_dev, sizeof(InitStatic) * count) == hipSuccess &&
@@ -904,8 +872,6 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
               hipHostMalloc(&b->prop_ok, sizeof(int32_t) * count, hipHostMallocDefault) == hipSuccess;
     ok = ok && hipMemcpy(b->fit_dev, fit.data(), sizeof(FitLaunch) * count, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(b->begin_dev, begin.data(), sizeof(int) * (count + 1), hipMemcpyHostToDevice) == hipSuccess &&
-         hipMemcpy(b->begin_pl_dev, begin_pl.data(), sizeof(int) * (count + 1), hipMemcpyHostToDevice) ==
-             hipSuccess &&
          hipMemcpy(b->init_dev, init.data(), sizeof(InitStatic) * count, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(b->upd_dev, upd.data(), sizeof(UpdateArgs) * count, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(b->stp_dev, stp.data(), sizeof(DevState*) * count, hipMemcpyHostToDevice) == hipSuccess;
