@@ -132,20 +132,53 @@ def kernel_stats_md(trace_dir: str, bench: dict, dur_ns, names, command: str) ->
     return "\n".join(lines) + "\n"
 
 
+def batch_stats_md(trace_dir: str, bench_json: str, command: str) -> str:
+    """Markdown summary of a kernel-trace run of bench_batch.py: per kernel
+    calls, average, min, max and share of GPU time, with the run's own
+    frames/s of both paths."""
+    rows = list(_rows(os.path.join(trace_dir, "**", "*kernel_stats.csv")))
+    with open(bench_json) as f:
+        b = json.loads([ln for ln in f if ln.startswith("{")][-1])
+    lines = [f"# Batched tracking of {b['sequences']} uneven sequences ({b['frames']} frames each)", "",
+             "rocprofv3 kernel-trace statistics of one bench_batch.py run (MI355X, gfx950): the launch-shape",
+             "tuning, the batched run and the same sequences one after another through the single path.", ""]
+    if command:
+        lines += ["Command (repository root, after `cd /tmp && export TMPDIR=/tmp` and back):", "",
+                  "    " + command, ""]
+    lines += ["| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
+    for r in rows[:24]:
+        name = r["Name"] if len(r["Name"]) <= 90 else r["Name"][:87] + "..."
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    lines += ["", f"Run: batch shape {b['shape']} (tuning, ms per frame step: {b['tune_ms_per_step']}); "
+              f"batched {b['batch']['frames_per_s']:.1f} frames/s ({b['batch']['evals_per_s']:.3e} evals/s), "
+              f"one after another {b['single']['frames_per_s']:.1f} frames/s; speed-up {b['speedup']:.3f}; "
+              f"poses identical: {b['poses_identical']}; mean ATE {b['ate_rmse_m']['mean']:.4f} m."]
+    return "\n".join(lines) + "\n"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", required=True)
-    ap.add_argument("--pmc", nargs="+", required=True)
+    ap.add_argument("--pmc", nargs="*", default=[])
     ap.add_argument("--bench-json", required=True)
+    ap.add_argument("--batch", action="store_true",
+                    help="the trace is of bench_batch.py: write only its kernel statistics to --out")
     ap.add_argument("--copy-mib", type=int, default=1024)
-    ap.add_argument("--steps", type=int, required=True)
-    ap.add_argument("--warmup", type=int, required=True)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--iters", type=int, default=20)
     ap.add_argument("--command", default="")
     ap.add_argument("--out", required=True)
     ap.add_argument("--stats-out", default=None)
     ap.add_argument("--stats-command", default="")
     a = ap.parse_args(argv)
+    if a.batch:
+        md = batch_stats_md(a.trace, a.bench_json, a.command)
+        with open(a.out, "w") as f:
+            f.write(md)
+        print(md)
+        return 0
     n_steps = a.steps * a.iters
     with open(a.bench_json) as f:
         bench = json.loads([ln for ln in f if ln.startswith("{")][-1])
