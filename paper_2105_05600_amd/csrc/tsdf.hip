@@ -92,8 +92,11 @@ __global__ __launch_bounds__(512) void k_integrate(IntegrateArgs a) {
         store_w<FMT>(g.wgt, off, fminf(w0 + 1.0f, g.w_max));
         not_one = stored_psi<FMT>(v) != 1.0f;
     }
-    // a brick with a value other than +1 leaves the all-ones set
-    if (__syncthreads_or(not_one) && t == 0) atomicAnd(&g.ones[b >> 5], ~(1u << (b & 31u)));
+    // a brick with a value other than +1 leaves the all-ones set; bits only
+    // ever clear during fusion, so a bit already seen clear needs no atomic
+    // (most bricks of the truncation band were cleared by earlier frames)
+    if (__syncthreads_or(not_one) && t == 0 && ((g.ones[b >> 5] >> (b & 31u)) & 1u))
+        atomicAnd(&g.ones[b >> 5], ~(1u << (b & 31u)));
 }
 
 // the all-ones bit of every brick from the stored values (one block per
