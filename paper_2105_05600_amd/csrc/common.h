@@ -435,8 +435,19 @@ struct FitLaunch {
     int32_t pl_side;
     float pl_thr;   // voxels
     float pl_zref;  // metres: depth at which a rotation axis length is turned into a displacement
-    uint64_t* partial;         // n x splits grid integers
+    uint64_t* partial;         // n x splits x kPartSub grid integers (partial_index)
 };
+
+// Partial sums: every (particle, slice) owns kPartSub consecutive slots.  The
+// particle-per-lane kernel's workgroups take a quarter of a slice for 256
+// particles and each writes its quarter's sum to its own slot; the
+// points-across kernel writes its slice's sum to the first slot and zeros to
+// the others.  A particle's fitness is the sum of its splits x kPartSub
+// consecutive slots (integers on the 2^-39 grid, so the order is free).
+constexpr int kPartSub = 4;
+__host__ __device__ inline int64_t partial_index(int64_t pi, int splits, int split, int sub) {
+    return (pi * splits + split) * kPartSub + sub;
+}
 rose_status launch_fitness(const FitLaunch& L, hipStream_t s);
 
 // The switching mode's footprint test: the largest translation axis length

@@ -358,44 +358,50 @@ __device__ void fitness_body(const FitLaunch& a, const int blk) {
         for (int p = 0; p < P; ++p)
             if (p0 + p < a.n) {
                 const int pi = (FROM_STATE && a.order) ? a.order[p0 + p] : p0 + p;
-                a.partial[(int64_t)pi * a.splits + split] = acc[p];
+                uint64_t* dst = a.partial + partial_index(pi, a.splits, split, 0);
+                dst[0] = acc[p];
+#pragma unroll
+                for (int q = 1; q < kPartSub; ++q) dst[q] = 0;
             }
     }
 }
 
 
 // Transposed mapping (shape (64, U)): one particle per lane.  A wave takes 64
-// consecutive particles of the schedule order over one slice of the point
-// list; each lane builds and keeps its own transform and the points are
-// read U at a time from LDS (wave-uniform broadcasts).  Every gather instruction
-// then looks up one point under 64 neighbouring poses of the schedule order:
-// once the search radius has shrunk to a few centimetres these land in a
-// handful of voxels, and the lanes share cache lines (a CPU count on the
-// room frames: ~4 lanes per 128-byte line at r = 0.03, ~13 at 0.01, against
-// ~1.1 when the lanes hold 64 neighbouring points).  The U gathers of a step
-// are in flight together.  Slices, XCD mapping and the partial-sum layout
-// are those of fitness_body, but a workgroup takes one group of 64 particles
-// and its 4 waves take the 4 quarters of the slice (4x the waves of one wave
-// per group and slice, which the points-across slice counts would leave too
-// few); each lane sums its particle's squares in point order, and the
-// quarters are added in order through LDS.  Every exit before the barrier
-// is uniform over the workgroup.
+// consecutive particles of the schedule order; each lane builds and keeps
+// its own transform and the points are read U at a time from LDS
+// (wave-uniform broadcasts).  Every gather instruction then looks up one
+// point under 64 neighbouring poses of the schedule order: once the search
+// radius has shrunk to a few centimetres these land in a handful of voxels,
+// and the lanes share cache lines (a CPU count on the room frames: ~4 lanes
+// per 128-byte line at r = 0.03, ~13 at 0.01, against ~1.1 when the lanes
+// hold 64 neighbouring points).  The U gathers of a step are in flight
+// together.  A workgroup takes 256 particles (its 4 waves, 64 consecutive
+// particles each) and one quarter of a slice: the 4 waves evaluate the same
+// points in step -- the workgroup stages them in LDS 64 at a time (one
+// coalesced load by wave 0, the next batch loaded one batch ahead) -- so
+// the neighbouring poses of its 256 particles gather from the same lines at
+// about the same time and share them in the CU's L1.  Each lane sums its
+// particle's squares over the quarter into the quarter's own partial slot.
+// Slices and their XCD mapping are those of fitness_body counted in
+// quarters (XCD x owns the contiguous quarter-slices x 4S/8 ...).  Every
+// exit before a barrier is uniform over the workgroup.
 template <int U, int FMT, int LK, bool FROM_STATE, bool WIDE, bool ACC32 = false>
 __device__ void fitness_body_pl(const FitLaunch& a, const int blk) {
-    __shared__ uint64_t s_part[4][kWave];
-    __shared__ float4 s_pts[4][kWave];
+    __shared__ float4 s_pts[kWave];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int s8 = a.splits >> 3;
-    const int r = blk % a.splits;
-    const int split = (r & 7) * s8 + (r >> 3);
-    const int group = blk / a.splits;
-    const int p0 = group * kWave;
-    if (p0 >= a.n) return;
+    const int R = a.splits * kPartSub;  // quarter-slices, a multiple of 8
+    const int r = blk % R;
+    const int qs = (r & 7) * (R >> 3) + (r >> 3);
+    const int split = qs / kPartSub, sub = qs % kPartSub;
+    const int g4 = blk / R;
+    if (g4 * 4 * kWave >= a.n) return;
     if (FROM_STATE && (a.st->stopped || switch_skips(a))) return;
     const int m = a.count_dev ? *a.count_dev : a.count;
 
-    const bool live = p0 + lane < a.n;
+    const int p0 = (g4 * 4 + wave) * kWave;
+    const bool live = p0 + lane < a.n;  // a wave past the last particle still keeps the barriers
     int pi = live ? p0 + lane : a.n - 1;
     if (FROM_STATE && a.order) pi = a.order[pi];
     float V[12];
@@ -419,21 +425,17 @@ __device__ void fitness_body_pl(const FitLaunch& a, const int blk) {
     const int chunk = (m + a.splits - 1) / a.splits;
     const int s0 = split * chunk;
     const int s1 = min(m, s0 + chunk);
-    const int quarter = (max(s1 - s0, 0) + 3) / 4;
-    const int j0 = __builtin_amdgcn_readfirstlane(s0 + wave * quarter);
+    const int quarter = (max(s1 - s0, 0) + kPartSub - 1) / kPartSub;
+    const int j0 = __builtin_amdgcn_readfirstlane(s0 + sub * quarter);
     const int j1 = __builtin_amdgcn_readfirstlane(min(s1, j0 + quarter));
     uint64_t acc = 0;  // grid sum (kGridBase + k per added term)
     float accf = 0.0f;
-    // the wave's points pass through LDS 64 at a time (one coalesced load,
-    // the next batch's loaded one batch ahead) and are read back with
-    // broadcast reads, every lane the same point
-    float4* sp = s_pts[wave];
     auto eval = [&](auto kk, int u0) {
         constexpr int K = decltype(kk)::value;
         float gx[K], gy[K], gz[K], v[K];
 #pragma unroll
         for (int u = 0; u < K; ++u) {
-            const float4 x = sp[u0 + u];
+            const float4 x = s_pts[u0 + u];
             gx[u] = xf_row(V[0], V[1], V[2], V[3], x.x, x.y, x.z);
             gy[u] = xf_row(V[4], V[5], V[6], V[7], x.x, x.y, x.z);
             gz[u] = xf_row(V[8], V[9], V[10], V[11], x.x, x.y, x.z);
@@ -443,35 +445,24 @@ __device__ void fitness_body_pl(const FitLaunch& a, const int blk) {
         for (int u = 0; u < K; ++u) add_sq<ACC32>(acc, accf, v[u]);
     };
     float4 xn = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    if (j0 < j1) xn = a.pts[min(j0 + lane, j1 - 1)];
+    if (wave == 0 && j0 < j1) xn = a.pts[min(j0 + lane, j1 - 1)];
     for (int jb = j0; jb < j1; jb += kWave) {
-        const int cnt = min(kWave, j1 - jb);  // wave-uniform
-        sp[lane] = xn;
-        __builtin_amdgcn_wave_barrier();
-        if (jb + kWave < j1) xn = a.pts[min(jb + kWave + lane, j1 - 1)];
+        const int cnt = min(kWave, j1 - jb);  // workgroup-uniform
+        if (wave == 0) s_pts[lane] = xn;
+        __syncthreads();
+        if (wave == 0 && jb + kWave < j1) xn = a.pts[min(jb + kWave + lane, j1 - 1)];
         int u0 = 0;
         for (; u0 + U <= cnt; u0 += U) eval(std::integral_constant<int, U>{}, u0);
         for (; u0 < cnt; ++u0) eval(std::integral_constant<int, 1>{}, u0);
-        __builtin_amdgcn_wave_barrier();  // the batch's reads come before the next batch's write
+        __syncthreads();  // every wave's reads of the batch come before the next batch's write
     }
-    // one term per point of the wave's quarter; the quarters are added as
-    // integers (binary32 for the no-Kahan ablation, in quarter order)
-    if constexpr (ACC32) s_part[wave][lane] = (uint64_t)__float_as_uint(accf);
-    else s_part[wave][lane] = acc - (uint64_t)max(j1 - j0, 0) * kGridBase;  // empty quarters: j1 <= j0
-    __syncthreads();
-    if (wave == 0 && live) {
+    // one term per point of the quarter (none for an empty quarter); the
+    // no-Kahan ablation's binary32 sum is put on the grid per quarter
+    if (live) {
         uint64_t sum;
-        if constexpr (ACC32) {
-            float f = __uint_as_float((uint32_t)s_part[0][lane]);
-#pragma unroll
-            for (int w = 1; w < 4; ++w) f += __uint_as_float((uint32_t)s_part[w][lane]);
-            sum = grid_of_f32_sum(f);
-        } else {
-            sum = s_part[0][lane];
-#pragma unroll
-            for (int w = 1; w < 4; ++w) sum += s_part[w][lane];
-        }
-        a.partial[(int64_t)pi * a.splits + split] = sum;
+        if constexpr (ACC32) sum = grid_of_f32_sum(accf);
+        else sum = acc - (uint64_t)max(j1 - j0, 0) * kGridBase;
+        a.partial[partial_index(pi, a.splits, split, sub)] = sum;
     }
 }
 
@@ -481,16 +472,17 @@ __global__ __launch_bounds__(256) void k_fitness(FitLaunch a) {
     else fitness_body<P, U, FMT, LK, FROM_STATE, WIDE, ACC32>(a, blockIdx.x);
 }
 
-// workgroups of a launch: 4 particle groups per workgroup (points across the
-// lanes) or one (one particle per lane, its 4 waves splitting the slice)
+// workgroups of a launch: 4 particle groups per workgroup and one slice
+// (points across the lanes), or 4 groups of 64 and one quarter of a slice
+// (one particle per lane)
 int fitness_blocks(const FitLaunch& L, int P) {
     const int groups = (L.n + P - 1) / P;
-    return (P == kWave ? groups : (groups + 3) / 4) * L.splits;
+    return (P == kWave ? (groups + 3) / 4 * kPartSub : (groups + 3) / 4) * L.splits;
 }
 
 __device__ inline int fitness_blocks_dev(const FitLaunch& L, int P) {
     const int groups = (L.n + P - 1) / P;
-    return (P == kWave ? groups : (groups + 3) / 4) * L.splits;
+    return (P == kWave ? (groups + 3) / 4 * kPartSub : (groups + 3) / 4) * L.splits;
 }
 
 // Persistent fitness over many tracked sequences of one storage format and
@@ -628,7 +620,8 @@ __global__ __launch_bounds__(256) void k_fitness_finish(const uint64_t* partial,
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     uint64_t q = 0;
-    for (int k = 0; k < splits; ++k) q += partial[(int64_t)i * splits + k];
+    const int S = splits * kPartSub;
+    for (int k = 0; k < S; ++k) q += partial[(int64_t)i * S + k];
     const float f = (m > 0) ? (float)(((double)q * kGridScale) / (double)m) : 1.0f;
     F[i] = f;
     if (rho) rho[i] = (float)exp_rho(-(double)f);
@@ -866,7 +859,7 @@ rose_status fitness_eval(rose_tsdf* h, const float* pts_dev, int32_t m, const fl
         ROSE_CHECK_HIP(hipMalloc(&hm->pts, sizeof(float4) * (size_t)cap));
         hm->cap_points = cap;
     }
-    const int64_t need = (int64_t)n * splits;
+    const int64_t need = (int64_t)n * splits * kPartSub;
     if (hm->cap_partial < need) {
         if (hm->partial) ROSE_CHECK_HIP(hipFree(hm->partial));
         hm->partial = nullptr;
@@ -955,9 +948,10 @@ rose_status fitness_eval_noalloc(const rose_tsdf* h, const float* pts_dev, int32
     float thr, zref;
     fit_launch_shape(h, lk, &sp, &su, &thr, &zref);
     const int splits = choose_splits(n, m, h->g.fmt, sp);
-    ROSE_REQUIRE((int64_t)n * splits <= kNoAllocPartials, ROSE_E_ARG,
-                 "fitness_eval_noalloc: %d particles x %d point slices exceed the %lld partial sums of the scratch", n,
-                 splits, (long long)kNoAllocPartials);
+    ROSE_REQUIRE((int64_t)n * splits * kPartSub <= kNoAllocPartials, ROSE_E_ARG,
+                 "fitness_eval_noalloc: %d particles x %d point slices x %d need more than the %lld partial sums of "
+                 "the scratch",
+                 n, splits, kPartSub, (long long)kNoAllocPartials);
     NoAllocScratch* sc = nullptr;
     rose_status st = noalloc_scratch(&sc);
     if (st != ROSE_OK) return st;

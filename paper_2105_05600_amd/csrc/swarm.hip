@@ -287,7 +287,7 @@ static rose_status swarm_track(rose_tsdf* h, const float* depth_dev, const rose_
     rose_status g;
     if ((g = grow(&h->pts, &h->cap_points, mmax)) != ROSE_OK) return g;
     if ((g = grow(&h->pts_o, &h->cap_points_o, mmax)) != ROSE_OK) return g;
-    if ((g = grow(&h->partial, &h->cap_partial, (int64_t)n * splits)) != ROSE_OK) return g;
+    if ((g = grow(&h->partial, &h->cap_partial, (int64_t)n * splits * kPartSub)) != ROSE_OK) return g;
     if ((g = grow(&h->F, &h->cap_particles, (int64_t)n)) != ROSE_OK) return g;
     if (!h->st) ROSE_CHECK_HIP(hipMalloc(&h->st, sizeof(DevState)));
     if (!h->st_host) ROSE_CHECK_HIP(hipHostMalloc(&h->st_host, sizeof(DevState), hipHostMallocDefault));

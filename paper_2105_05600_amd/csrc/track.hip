@@ -433,7 +433,7 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const float* p
         lv_splits[l] = choose_splits(lv_n[l], mmax, h->g.fmt, shp_p);
         lv_off[l + 1] = lv_off[l] + mmax;
         mmax_all = std::max(mmax_all, mmax);
-        partial_need = std::max(partial_need, (int64_t)lv_n[l] * lv_splits[l]);
+        partial_need = std::max(partial_need, (int64_t)lv_n[l] * lv_splits[l] * kPartSub);
         ia.stride[l] = st_l;
         ia.offset[l] = (int32_t)lv_off[l];
     }
@@ -779,7 +779,7 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
         const int splits = choose_splits(n_particles[i], mmax, h->g.fmt, P);
         if ((g = grow(&h->pts, &h->cap_points, mmax)) != ROSE_OK) break;
         if ((g = grow(&h->pts_o, &h->cap_points_o, mmax)) != ROSE_OK) break;
-        if ((g = grow(&h->partial, &h->cap_partial, (int64_t)n_particles[i] * splits)) != ROSE_OK) break;
+        if ((g = grow(&h->partial, &h->cap_partial, (int64_t)n_particles[i] * splits * kPartSub)) != ROSE_OK) break;
         if ((g = grow(&h->F, &h->cap_particles, (int64_t)n_particles[i])) != ROSE_OK) break;
         if (!h->st && hipMalloc(&h->st, sizeof(DevState)) != hipSuccess) {
             set_error("pso_batch_create: hipMalloc failed");
@@ -1156,7 +1156,7 @@ rose_status pso_batch_track_learned(rose_batch* b, const float* const* depth_dev
         rose_status g;
         if ((g = grow(&h->pts, &h->cap_points, mmax)) != ROSE_OK) return g;
         if ((g = grow(&h->pts_o, &h->cap_points_o, mmax)) != ROSE_OK) return g;
-        if ((g = grow(&h->partial, &h->cap_partial, (int64_t)n_plain[i] * splits)) != ROSE_OK) return g;
+        if ((g = grow(&h->partial, &h->cap_partial, (int64_t)n_plain[i] * splits * kPartSub)) != ROSE_OK) return g;
         if ((g = grow(&h->F, &h->cap_particles, (int64_t)n_plain[i])) != ROSE_OK) return g;
     }
     const int64_t npx = (int64_t)lp->low_w * lp->low_h, fd = lp->feature_dim;

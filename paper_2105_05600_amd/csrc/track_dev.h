@@ -152,7 +152,8 @@ struct UpdateArgs {
 // correctly rounded division and one rounding to binary32)
 __device__ inline float final_fitness(const UpdateArgs& a, int i, int nO) {
     uint64_t q = 0;
-    for (int k = 0; k < a.splits; ++k) q += a.partial[(int64_t)i * a.splits + k];
+    const int S = a.splits * kPartSub;
+    for (int k = 0; k < S; ++k) q += a.partial[(int64_t)i * S + k];
     const double s = (double)q * kGridScale;
     double f;
     if (a.flags & ROSE_FLAG_NO_NORMALIZE) f = s;
