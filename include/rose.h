@@ -211,7 +211,7 @@ rose_status fitness_eval(rose_tsdf* h, const float* pts_dev, int32_t m, const fl
  * process ends) instead of the handle's scratch; the handle is not changed.
  * No allocation, no free, no allocating library call.  Limits: m <=
  * fitness_eval_noalloc_max_points() (131072), and n times the point slices
- * the launch uses at most 786432 (ROSE_E_ARG otherwise, before anything is
+ * the launch uses at most 196608 (ROSE_E_ARG otherwise, before anything is
  * enqueued).  Calls that overlap on one device share the scratch and race:
  * serialise them (one stream, or events).  Errors as fitness_eval, plus
  * ROSE_E_DEVICE when the scratch address cannot be obtained. */
