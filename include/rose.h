@@ -151,6 +151,20 @@ rose_status tsdf_export(const rose_tsdf* h, float* psi_lin_dev, float* weight_li
  * call tsdf_rescan (asynchronous on s) before the next fitness call.
  * ROSE_E_ARG for a NULL handle. */
 rose_status tsdf_rescan(rose_tsdf* h, hipStream_t s);
+
+/* Particle schedule orders.  The first track call with a PST template on a
+ * handle reads the template back once and caches the order in which the
+ * fitness kernels take its rows (similar rotations together, for cache
+ * reuse), keyed by the template's device pointer and row count, up to 8
+ * templates per handle; further templates run in index order.  Results do
+ * not depend on the order, only speed does: a template rewritten in place,
+ * or new template data at the address of a freed one (as a caching
+ * allocator hands out), keeps the old order.  tsdf_forget_templates drops
+ * the cache (it waits for the device to be idle and frees the orders;
+ * batches created on the handle hold the old orders and must be created
+ * again); tsdf_template_orders returns the number cached. */
+rose_status tsdf_forget_templates(rose_tsdf* h);
+int32_t tsdf_template_orders(const rose_tsdf* h);
 rose_status tsdf_import(rose_tsdf* h, const float* psi_lin_dev, const float* weight_lin_dev, hipStream_t s);
 
 /* -------------------------------------------------------------- PST (a1) */

@@ -118,24 +118,29 @@ __global__ __launch_bounds__(1024) void k_track_init_batch(const InitStatic* a, 
 // F_i of every particle from its slice partials (fixed slice order), before
 // the update: many workgroups, so the update kernel's single workgroup reads
 // n floats instead of n x splits doubles.
+// one wavefront per particle i (wave-uniform exits)
 __device__ inline void reduce_fitness_body(const UpdateArgs& a, int i) {
     if (i >= a.n || a.st->stopped) return;
-    a.F[i] = final_fitness(a, i, a.st->n_overlap);
+    const float f = final_fitness(a, i, a.st->n_overlap);
+    if ((threadIdx.x & 63) == 0) a.F[i] = f;
 }
 
+// 4 particles per workgroup of 256 threads
+constexpr int kReducePerBlock = 256 / kWave;
+
 __global__ __launch_bounds__(256) void k_fitness_reduce(UpdateArgs a) {
-    reduce_fitness_body(a, blockIdx.x * blockDim.x + threadIdx.x);
+    reduce_fitness_body(a, blockIdx.x * kReducePerBlock + (int)(threadIdx.x >> 6));
 }
 
 rose_status launch_fitness_reduce(const UpdateArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_fitness_reduce, dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_fitness_reduce, dim3((a.n + kReducePerBlock - 1) / kReducePerBlock), dim3(256), 0, s, a);
     ROSE_CHECK_HIP(hipGetLastError());
     return ROSE_OK;
 }
 
 // one column of workgroups per sequence
 __global__ __launch_bounds__(256) void k_fitness_reduce_batch(const UpdateArgs* a) {
-    reduce_fitness_body(a[blockIdx.y], blockIdx.x * blockDim.x + threadIdx.x);
+    reduce_fitness_body(a[blockIdx.y], blockIdx.x * kReducePerBlock + (int)(threadIdx.x >> 6));
 }
 
 __device__ void track_update_body(const UpdateArgs& a) {
@@ -509,7 +514,8 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const float* p
         if ((g = launch_fitness(fl, s)) != ROSE_OK) return g;
         prof_end(tok_fit[k], s, 0.0);
         const int tu = prof_begin(PROF_UPDATE, s);
-        hipLaunchKernelGGL(k_fitness_reduce, dim3((ua.n + 255) / 256), dim3(256), 0, s, ua);
+        hipLaunchKernelGGL(k_fitness_reduce, dim3((ua.n + kReducePerBlock - 1) / kReducePerBlock), dim3(256), 0, s,
+                           ua);
         hipLaunchKernelGGL(k_track_update, dim3(1), dim3(1024), 0, s, ua);
         prof_end(tu, s, 0.0);
         ROSE_CHECK_HIP(hipGetLastError());
@@ -693,7 +699,8 @@ static rose_status batch_enqueue(rose_batch* b, hipStream_t s) {
                                                   gr.end, gr.grid, b->P, b->U, gr.fmt, gr.lk, b->ctr_dev + 8 * q, s);
             if (st != ROSE_OK) return st;
         }
-        hipLaunchKernelGGL(k_fitness_reduce_batch, dim3((b->max_n + 255) / 256, b->count), dim3(256), 0, s,
+        hipLaunchKernelGGL(k_fitness_reduce_batch, dim3((b->max_n + kReducePerBlock - 1) / kReducePerBlock, b->count),
+                           dim3(256), 0, s,
                            b->upd_dev);
         hipLaunchKernelGGL(k_track_update_batch, dim3(b->count), dim3(1024), 0, s, b->upd_dev, b->ctr_dev, n_ctr);
         ROSE_CHECK_HIP(hipGetLastError());

@@ -149,11 +149,17 @@ struct UpdateArgs {
 
 // F_i = S_i / |O| (Eq. normallh) from the slice sums on the 2^-39 grid
 // (exact integer sum, then one rounding to binary64, an exact scaling, one
-// correctly rounded division and one rounding to binary32)
+// correctly rounded division and one rounding to binary32).  One wavefront
+// per particle: lane l adds the particle's slots l, l + 64, ... (coalesced
+// 8-byte reads of its splits x kPartSub consecutive slots), then the wave
+// adds the lanes' integers; every lane returns F_i.
 __device__ inline float final_fitness(const UpdateArgs& a, int i, int nO) {
-    uint64_t q = 0;
+    const int lane = threadIdx.x & 63;
     const int S = a.splits * kPartSub;
-    for (int k = 0; k < S; ++k) q += a.partial[(int64_t)i * S + k];
+    const uint64_t* row = a.partial + (int64_t)i * S;
+    uint64_t q = 0;
+    for (int k = lane; k < S; k += kWave) q += row[k];
+    q = wave_sum_u64(q);
     const double s = (double)q * kGridScale;
     double f;
     if (a.flags & ROSE_FLAG_NO_NORMALIZE) f = s;

@@ -391,6 +391,22 @@ rose_status tsdf_rescan(rose_tsdf* h, hipStream_t s) {
     return rescan_ones(h->g, s);
 }
 
+rose_status tsdf_forget_templates(rose_tsdf* h) {
+    clear_error();
+    ROSE_REQUIRE(h, ROSE_E_ARG, "tsdf_forget_templates: NULL handle");
+    ROSE_CHECK_HIP(hipDeviceSynchronize());  // no launch may still read an order
+    for (int i = 0; i < h->n_orders; ++i) {
+        if (h->orders[i].order) ROSE_CHECK_HIP(hipFree(h->orders[i].order));
+        h->orders[i].order = nullptr;
+        h->orders[i].pst = nullptr;
+        h->orders[i].n = 0;
+    }
+    h->n_orders = 0;
+    return ROSE_OK;
+}
+
+int32_t tsdf_template_orders(const rose_tsdf* h) { return h ? h->n_orders : 0; }
+
 }  // extern "C"
 
 namespace rose {

@@ -136,6 +136,8 @@ _sigs = {
     "rose_fitness_set_switch_shape": ([C.c_int32, C.c_int32], C.c_int),
     "tsdf_set_fitness_shape": ([_P, C.c_int32, C.c_int32], C.c_int),
     "tsdf_set_fitness_switch": ([_P, C.c_float, C.c_float, C.c_int32, C.c_int32], C.c_int),
+    "tsdf_forget_templates": ([_P], C.c_int),
+    "tsdf_template_orders": ([_P], C.c_int32),
     "overlap_mask": ([_P, C.c_int32, C.POINTER(Pose), C.POINTER(Pose), C.POINTER(Camera), _P, _P, _S], C.c_int),
     "pso_track_frame": ([_P, _P, _P, C.POINTER(Camera), _P, C.c_int32, C.POINTER(TrackParams), C.POINTER(Pose), _P,
                          C.POINTER(TrackState), C.POINTER(TrackStats), _S], C.c_int),
@@ -288,6 +290,14 @@ class Tsdf:
     def rescan(self, stream=None):
         """Rebuild the handle's all-+1 brick bits after writing psi directly."""
         _check("tsdf_rescan", _lib.tsdf_rescan(self.handle, _stream(stream)))
+
+    def forget_templates(self):
+        """Drop the cached particle schedule orders (waits for the device)."""
+        _check("tsdf_forget_templates", _lib.tsdf_forget_templates(self.handle))
+
+    def template_orders(self) -> int:
+        """Number of PST templates whose schedule order is cached."""
+        return int(_lib.tsdf_template_orders(self.handle))
 
     def set_fitness_shape(self, particles_per_wave: int, points_per_lane: int):
         """This handle's own fitness launch shape ((0, 0): switching mode;

@@ -88,6 +88,8 @@ def test_host_side_argument_errors(R):
     assert lib.pso_track_frame(C.c_void_p(16), C.c_void_p(16), None, C.byref(cam), C.c_void_p(16), 16,
                                C.byref(params), None, None, C.byref(st), None, None) == R.E_ARG
     assert lib.rose_profile_read(None) == R.E_ARG
+    assert lib.tsdf_forget_templates(None) == R.E_ARG
+    assert lib.tsdf_template_orders(None) == 0
     assert lib.rose_gather_peak(C.c_void_p(16), 1 << 20, 3000, 8, 1, 1, C.c_void_p(16), None) == R.E_ARG
     assert lib.rose_gather_peak(C.c_void_p(16), 1 << 10, 4096, 8, 1, 1, C.c_void_p(16), None) == R.E_SHAPE
     assert lib.rose_gather_peak(C.c_void_p(16), 1 << 20, 64, 12, 1, 1, C.c_void_p(16), None) == R.E_ARG

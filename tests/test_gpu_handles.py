@@ -147,3 +147,32 @@ def test_track_frame_on_non_default_stream(R):
     assert got["t"] == ref["t"] and got["q"] == ref["q"]
     vol_a.close()
     vol_b.close()
+
+
+def test_template_order_cache_forget(R):
+    """The schedule-order cache (speed only): a template tracked on a handle
+    is cached once; a template rewritten in place keeps the cached order and
+    still gives the results of a fresh handle (the order changes no result);
+    tsdf_forget_templates empties the cache and the next frame caches again."""
+    w = synth.small_frame()
+    vol = _volume(R, w)
+    fresh = _volume(R, w)
+    try:
+        pst = R.pst_sample(w.n_particles, w.pst_seed)
+        a = _track(R, vol, w, pst)
+        assert vol.template_orders() == 1
+        # new rows written into the same buffer: the cached order is stale
+        pst.copy_(R.pst_sample(w.n_particles, w.pst_seed + 1))
+        b = _track(R, vol, w, pst)
+        assert vol.template_orders() == 1
+        c = _track(R, fresh, w, pst)
+        assert b["aps"] == c["aps"] and b["t"] == c["t"] and b["q"] == c["q"]
+        assert a["aps"] != b["aps"] or a["t"] != b["t"]  # a different template tracks differently
+        vol.forget_templates()
+        assert vol.template_orders() == 0
+        d = _track(R, vol, w, pst)
+        assert vol.template_orders() == 1
+        assert d["aps"] == c["aps"] and d["t"] == c["t"] and d["q"] == c["q"]
+    finally:
+        vol.close()
+        fresh.close()
