@@ -138,6 +138,10 @@ rose_status launch_fitness_reduce(const UpdateArgs& a, hipStream_t s) {
     return ROSE_OK;
 }
 
+// one column of workgroups per sequence
+__global__ __launch_bounds__(256) void k_fitness_reduce_batch(const UpdateArgs* a) {
+    reduce_fitness_body(a[blockIdx.y], blockIdx.x * kReducePerBlock + (int)(threadIdx.x >> 6));
+}
 
 __device__ void track_update_body(const UpdateArgs& a) {
     __shared__ int lds[17];
@@ -241,15 +245,9 @@ __device__ void track_update_body(const UpdateArgs& a) {
 
 __global__ __launch_bounds__(1024) void k_track_update(UpdateArgs a) { track_update_body(a); }
 
-// one workgroup per sequence: the sequence's slice reduction (one wavefront
-// per particle) and then its update, in one launch per iteration
 __global__ __launch_bounds__(1024) void k_track_update_batch(const UpdateArgs* a, int* ctr, int n_ctr) {
     clear_counters(ctr, n_ctr);
-    const UpdateArgs& u = a[blockIdx.x];
-    const int waves = (int)(blockDim.x >> 6);
-    for (int i = (int)(threadIdx.x >> 6); i < u.n; i += waves) reduce_fitness_body(u, i);
-    __syncthreads();  // every F_i of the sequence written before the update reads them
-    track_update_body(u);
+    track_update_body(a[blockIdx.x]);
 }
 
 // copy every sequence's device state to pinned host memory
@@ -701,6 +699,9 @@ static rose_status batch_enqueue(rose_batch* b, hipStream_t s) {
                                                   gr.end, gr.grid, b->P, b->U, gr.fmt, gr.lk, b->ctr_dev + 8 * q, s);
             if (st != ROSE_OK) return st;
         }
+        hipLaunchKernelGGL(k_fitness_reduce_batch, dim3((b->max_n + kReducePerBlock - 1) / kReducePerBlock, b->count),
+                           dim3(256), 0, s,
+                           b->upd_dev);
         hipLaunchKernelGGL(k_track_update_batch, dim3(b->count), dim3(1024), 0, s, b->upd_dev, b->ctr_dev, n_ctr);
         ROSE_CHECK_HIP(hipGetLastError());
     }
