@@ -468,8 +468,11 @@ rose_status pso_track_frame_learned(rose_tsdf* h, const float* depth_dev, const 
  * pso_batch_track call, with the same per-sequence semantics as
  * pso_track_frame.  Per frame step the device work is: one unprojection /
  * overlap launch (one workgroup per sequence), then per iteration one
- * persistent fitness launch over all sequences and one update launch, then
- * one launch copying the states to pinned host memory; with use_graph != 0
+ * persistent fitness launch per group over the sequences that share it, the
+ * fitness launches of pso_track_frame for each sequence that has its own
+ * (see rose_batch_set_own_launch), one slice-reduction launch and one update
+ * launch, then one launch copying the states to pinned host memory; with
+ * use_graph != 0
  * and a non-null stream it is captured into a HIP graph on the first call
  * and replayed afterwards (new inputs are read from pinned host memory).
  * The fitness launch shape is the one set by rose_fitness_set_shape when the
@@ -494,6 +497,18 @@ rose_status pso_batch_track(rose_batch* b, const float* const* depth_devs, const
                             const double* init_rs, rose_track_state* states, rose_track_stats* stats,
                             hipStream_t s);
 rose_status pso_batch_destroy(rose_batch* b);
+/* Which sequences of a batch created afterwards take launches of their own:
+ * those whose handle runs the switching mode (rose_fitness_set_shape(0, 0)
+ * or tsdf_set_fitness_switch) and whose iteration holds at least min_evals
+ * particle x point evaluations (n_particles x ceil(width / stride) x
+ * ceil(height / stride)).  They run pso_track_frame's fitness launches
+ * (both kernels, the one for the current search footprint chosen on the
+ * device; stats fit_mode reports it) inside the batch's stream or graph, in
+ * sequence order; the persistent launches have no particle-per-lane side
+ * and serve the others.  Process-wide, host-only; default 8388608 (2^23);
+ * 0: every switching-mode sequence; ROSE_E_ARG if min_evals < 0.  Results
+ * do not depend on it. */
+rose_status rose_batch_set_own_launch(int64_t min_evals);
 
 /* Batched learned frame step: for every sequence of batch b whose model
  * exists, the learned proposal of pso_track_frame_learned (raycast at the

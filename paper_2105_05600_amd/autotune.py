@@ -18,7 +18,11 @@ import torch
 from paper_2105_05600_amd import rose
 
 SHAPES = [(4, 2), (8, 2), (4, 4), (4, 8), (2, 4), (8, 4), (64, 4), (64, 8), (64, 16)]  # (64, U): one particle per lane
-BATCH_SHAPES = [(4, 2), (8, 2), (4, 4), (4, 8), (8, 4), (64, 8)]  # shapes the batched tracker supports
+# the batched tracker's candidates: the fixed shapes of its persistent launch,
+# and the switching mode (0, 0), in which each sequence with enough work per
+# iteration takes the single path's launches of its own and the rest share
+# the persistent launch at the switching mode's points-across shape
+BATCH_SHAPES = [(4, 2), (8, 2), (4, 4), (4, 8), (8, 4), (64, 8), (0, 0)]
 # the tracker's candidates: the points-across shapes and the switching mode
 # (0, 0).  The fixed particle-per-lane shapes are left out: they win only on
 # iterations with a small search footprint and lose on wide ones, and one

@@ -559,8 +559,10 @@ rose_status pso_track_frame(rose_tsdf* h, const float* depth_dev, const float* p
 // ------------------------------------------------------------------ batching
 // Many sequences tracked in lockstep: per frame step one init launch (one
 // workgroup per sequence), then per iteration one persistent fitness launch
-// over every sequence's work and one update launch (one workgroup per
-// sequence), then one launch copying the states to pinned host memory.  The
+// per group over the small sequences' work, the fitness launches of each
+// large switching-mode sequence (the single path's), one slice-reduction
+// launch and one update launch (one workgroup per sequence), then one
+// launch copying the states to pinned host memory.  The
 // sequence of launches is captured once into a HIP graph and replayed every
 // frame step; per-frame inputs are read by the init kernel from pinned host
 // memory, so the graph itself never changes.
@@ -600,9 +602,19 @@ struct BatchGroup {
     int grid;
 };
 
+// Sequences in the switching mode whose iteration holds at least this many
+// particle x point evaluations (n_particles x the points at the stride) take
+// launches of their own in a batch; read when a batch is created.
+static int64_t g_batch_own_min = int64_t(1) << 23;
+
 struct rose_batch {
     int32_t count = 0, K = 0, P = 4, U = 2, total = 0, max_n = 1;
     std::vector<BatchGroup> groups;
+    // sequences with launches of their own (the single path's fitness
+    // launches, switching included), and those launch records
+    std::vector<int> own;
+    std::vector<FitLaunch> own_fl;
+    std::vector<int> own_of;  // per sequence: its index in own, or -1
     bool use_graph = true;
     std::vector<rose_tsdf*> h;
     std::vector<rose_camera> cams;
@@ -640,6 +652,19 @@ static rose_status batch_refresh(rose_batch* b, bool force) {
         stale = u.partial != h->partial || u.F != h->F || u.pts != h->pts || u.pts_o != h->pts_o || u.st != h->st;
     }
     if (!stale) return ROSE_OK;
+    for (size_t j = 0; j < b->own.size(); ++j) {
+        const rose_tsdf* h = b->h[b->own[j]];
+        FitLaunch& L = b->own_fl[j];
+        L.pts = h->pts_o;
+        L.count_dev = &h->st->n_overlap;
+        L.st = h->st;
+        L.partial = h->partial;
+    }
+    // a captured graph holds the own launches' records by value: capture again
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
     for (int i = 0; i < b->count; ++i) {
         rose_tsdf* h = b->h[i];
         FitLaunch& L = b->fit_host[b->pos[i]];
@@ -697,6 +722,10 @@ static rose_status batch_enqueue(rose_batch* b, hipStream_t s) {
             const BatchGroup& gr = b->groups[q];
             rose_status st = launch_fitness_batch(b->fit_dev + gr.first, b->begin_dev + gr.first, gr.count, gr.base,
                                                   gr.end, gr.grid, b->P, b->U, gr.fmt, gr.lk, b->ctr_dev + 8 * q, s);
+            if (st != ROSE_OK) return st;
+        }
+        for (const FitLaunch& L : b->own_fl) {
+            rose_status st = launch_fitness(L, s);
             if (st != ROSE_OK) return st;
         }
         hipLaunchKernelGGL(k_fitness_reduce_batch, dim3((b->max_n + kReducePerBlock - 1) / kReducePerBlock, b->count),
@@ -762,13 +791,26 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
     }
     b->P = P;
     b->U = U;
-    // the fitness work arrays list the sequences grouped by (format, lookup)
+    // sequences in the switching mode with enough work per iteration to fill
+    // the GPU alone take the single path's fitness launches (both kernels,
+    // chosen on the device); the rest share the persistent launches
+    const int64_t own_min = g_batch_own_min;
+    std::vector<char> own(count, 0);
+    for (int i = 0; i < count; ++i) {
+        int sp, su;
+        float thr, zref;
+        fit_launch_shape(tsdfs[i], params[i].lookup, &sp, &su, &thr, &zref);
+        const int64_t mm = (int64_t)((cams[i].width + params[i].stride - 1) / params[i].stride) *
+                           ((cams[i].height + params[i].stride - 1) / params[i].stride);
+        own[i] = thr > 0.0f && (int64_t)n_particles[i] * mm >= own_min;
+    }
+    // the fitness work arrays list the sequences grouped by (format, lookup),
+    // the sequences with launches of their own last (in no group)
+    auto group_key = [&](int x) { return own[x] ? 1 << 20 : tsdfs[x]->g.fmt * 2 + params[x].lookup; };
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-        const int kx = tsdfs[x]->g.fmt * 2 + params[x].lookup, ky = tsdfs[y]->g.fmt * 2 + params[y].lookup;
-        return kx < ky;
-    });
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return group_key(x) < group_key(y); });
+    b->own_of.assign(count, -1);
     std::vector<int> pos(count);
     for (int k = 0; k < count; ++k) pos[order[k]] = k;
     std::vector<FitLaunch> fit(count);
@@ -783,7 +825,10 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
         const int su = (cams[i].width + p.stride - 1) / p.stride;
         const int sv = (cams[i].height + p.stride - 1) / p.stride;
         const int64_t mmax = (int64_t)su * sv;
-        const int splits = choose_splits(n_particles[i], mmax, h->g.fmt, P);
+        int shp_p = P, shp_u = U;
+        float shp_thr = 0.0f, shp_zref = 0.0f;
+        if (own[i]) fit_launch_shape(h, p.lookup, &shp_p, &shp_u, &shp_thr, &shp_zref);
+        const int splits = choose_splits(n_particles[i], mmax, h->g.fmt, shp_p);
         if ((g = grow(&h->pts, &h->cap_points, mmax)) != ROSE_OK) break;
         if ((g = grow(&h->pts_o, &h->cap_points_o, mmax)) != ROSE_OK) break;
         if ((g = grow(&h->partial, &h->cap_partial, (int64_t)n_particles[i] * splits * kPartSub)) != ROSE_OK) break;
@@ -805,10 +850,17 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
         if ((g = particle_order(h, pst_devs[i], n_particles[i], nullptr, &L.order)) != ROSE_OK) break;
         L.splits = splits;
         L.lookup = p.lookup;
-        L.shape_p = P;
-        L.shape_u = U;
+        L.shape_p = shp_p;
+        L.shape_u = shp_u;
+        L.pl_thr = shp_thr;
+        L.pl_zref = shp_zref;
         L.partial = h->partial;
-        nblk[pos[i]] = fitness_blocks(L, P);
+        nblk[pos[i]] = own[i] ? 0 : fitness_blocks(L, P);
+        if (own[i]) {
+            b->own_of[i] = (int)b->own.size();
+            b->own.push_back(i);
+            b->own_fl.push_back(L);
+        }
         InitStatic& ia = init[i];
         ia = InitStatic{};
         ia.st = h->st;
@@ -851,10 +903,10 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
     std::vector<int> begin(count + 1, 0);
     for (int k = 0; k < count; ++k) begin[k + 1] = begin[k] + (nblk[k] + 7) / 8 * 8;
     b->total = begin[count];
-    for (int k = 0; k < count;) {
-        const int key = tsdfs[order[k]]->g.fmt * 2 + params[order[k]].lookup;
+    for (int k = 0; k < count && !own[order[k]];) {
+        const int key = group_key(order[k]);
         int e = k;
-        while (e < count && tsdfs[order[e]]->g.fmt * 2 + params[order[e]].lookup == key) ++e;
+        while (e < count && group_key(order[e]) == key) ++e;
         BatchGroup gr;
         gr.fmt = tsdfs[order[k]]->g.fmt;
         gr.lk = params[order[k]].lookup;
@@ -866,7 +918,7 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
         b->groups.push_back(gr);
         k = e;
     }
-    const size_t n_ctr = 8 * b->groups.size();
+    const size_t n_ctr = std::max<size_t>(8, 8 * b->groups.size());
     bool ok = hipMalloc(&b->fit_dev, sizeof(FitLaunch) * count) == hipSuccess &&
               hipMalloc(&b->begin_dev, sizeof(int) * (count + 1)) == hipSuccess &&
               hipMalloc(&b->ctr_dev, sizeof(int) * n_ctr) == hipSuccess &&
@@ -893,6 +945,14 @@ rose_status pso_batch_create(int32_t count, rose_tsdf* const* tsdfs, const rose_
     b->upd_host = upd;
     b->pos = pos;
     *out = b;
+    return ROSE_OK;
+}
+
+rose_status rose_batch_set_own_launch(int64_t min_evals) {
+    clear_error();
+    ROSE_REQUIRE(min_evals >= 0, ROSE_E_ARG, "rose_batch_set_own_launch: min_evals = %lld is negative",
+                 (long long)min_evals);
+    g_batch_own_min = min_evals;
     return ROSE_OK;
 }
 
@@ -1010,6 +1070,7 @@ static rose_status batch_track_impl(rose_batch* b, const float* const* depth_dev
                 stats[i].rho_centre[k] = r.rho_centre[k];
                 for (int d = 0; d < 6; ++d) stats[i].r_iter[k][d] = r.r_iter[k][d];
                 stats[i].n_particles[k] = b->n[i];
+                if (b->own_of[i] >= 0) stats[i].fit_mode[k] = switch_mode(b->own_fl[b->own_of[i]], r.r_iter[k]);
             }
         }
     }

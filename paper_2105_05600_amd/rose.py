@@ -157,6 +157,7 @@ _sigs = {
     "pso_batch_create": ([C.c_int32, _P, _P, _P, _P, _P, C.c_int32, C.POINTER(C.c_void_p)], C.c_int),
     "pso_batch_track": ([_P, _P, _P, _P, _P, _P, _S], C.c_int),
     "pso_batch_destroy": ([_P], C.c_int),
+    "rose_batch_set_own_launch": ([C.c_int64], C.c_int),
     "pso_batch_track_learned": ([_P, _P, _P, _P, _P, _P, C.POINTER(LearnedParams), _P, _P, C.POINTER(TrackParams),
                                  _P, _P, _P, _S], C.c_int),
     "rose_chart_log": ([C.POINTER(Pose), C.POINTER(Pose), _P], C.c_int),
@@ -698,6 +699,15 @@ def set_fitness_switch(footprint_voxels: float, reference_depth_m: float = 3.0):
     _check("rose_fitness_set_switch", _lib.rose_fitness_set_switch(float(footprint_voxels), float(reference_depth_m)))
 
 
+BATCH_OWN_LAUNCH_DEFAULT = 1 << 23
+
+
+def set_batch_own_launch(min_evals: int):
+    """Batches created afterwards give a switching-mode sequence launches of
+    its own when n_particles x points per iteration >= min_evals (0: all)."""
+    _check("rose_batch_set_own_launch", _lib.rose_batch_set_own_launch(int(min_evals)))
+
+
 def set_fitness_switch_shape(particles_per_wave: int, points_per_lane: int):
     """Points-across shape of the switching mode (process-wide default)."""
     _check("rose_fitness_set_switch_shape",
@@ -753,8 +763,9 @@ class Batch:
             s = ST[i]
             it = s.iters
             out.append(dict(status=s.status, iters=it, n_points=s.n_points, aps=list(s.aps_size[:it]),
-                            n_overlap=list(s.n_overlap[:it]), q=list(states[i].pose.q), t=list(states[i].pose.t),
-                            r1=list(states[i].r), rho=states[i].rho))
+                            n_overlap=list(s.n_overlap[:it]), fit_mode=list(s.fit_mode[:it]),
+                            q=list(states[i].pose.q), t=list(states[i].pose.t), r1=list(states[i].r),
+                            rho=states[i].rho))
         return out
 
 

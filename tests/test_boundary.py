@@ -176,3 +176,16 @@ def test_fitness_shapes_host_side(R):
         assert lib.rose_fitness_set_switch(0.0, 0.0) == R.OK  # the defaults
     finally:
         assert lib.rose_fitness_set_shape(4, 2) == R.OK
+
+
+def test_batch_own_launch_setting_host_side(R):
+    """rose_batch_set_own_launch takes any min_evals >= 0 and refuses a
+    negative one; no device call is made."""
+    lib = R._lib
+    try:
+        assert lib.rose_batch_set_own_launch(-1) == R.E_ARG
+        assert b"negative" in lib.rose_last_error()
+        for v in (0, 1, 1 << 40):
+            assert lib.rose_batch_set_own_launch(v) == R.OK
+    finally:
+        R.set_batch_own_launch(R.BATCH_OWN_LAUNCH_DEFAULT)
