@@ -79,7 +79,7 @@ def fresh(seqs, depths):
 
 def learned_comparison(n, frames, seed_base, modes=("plain_single", "plain_batched", "learned", "untrained",
                                                       "small_carried"), log=lambda s: None, single_shape=(0, 0),
-                       batch_shape=(4, 2)):
+                       batch_shape=(0, 0)):
     """The same n held-out 320x240 sequences (seeds seed_base + 10 i, 1-4
     m/s) tracked for `frames` frames, fused at the tracked pose, in each of
     the modes:
@@ -92,8 +92,10 @@ def learned_comparison(n, frames, seed_base, modes=("plain_single", "plain_batch
     * untrained: the same path with an untrained network of the same shape;
     * small_carried: the learned run's budget batched, centre and axis
       lengths carried from the previous frame (no network).
-    The single-sequence path runs in single_shape (the switching mode by
-    default), the batched modes in batch_shape.  Returns {mode:
+    The single-sequence path runs in single_shape, the batched modes in
+    batch_shape (both the switching mode by default: a batched sequence with
+    2^23 or more evaluations per iteration, as every one here, then takes
+    the single path's own launches inside the batch).  Returns {mode:
     {"frames_per_s", "ate_rmse_m" (per sequence), "ate_rmse_mean_m",
     "ate_rmse_median_m", "fallbacks"}}."""
     from paper_2105_05600_amd import train_proposal as tp
@@ -177,7 +179,8 @@ def learned_main(args):
     batched with the trained and with an untrained network, and the learned
     run's budget without a network, on the same held-out 320x240 sequences
     (see learned_comparison)."""
-    res = learned_comparison(args.sequences, args.frames, args.seed_base, log=log)
+    res = learned_comparison(args.sequences, args.frames, args.seed_base, log=log,
+                             batch_shape=tuple(args.batch_shape))
     out = {"metric": "learned proposal batched vs plain PST: frames/s over all sequences and ATE",
            "sequences": args.sequences, "frames": args.frames, "image": [320, 240], "seed_base": args.seed_base}
     for mode, r in res.items():
@@ -193,6 +196,8 @@ def main():
     ap.add_argument("--tune-steps", type=int, default=3)
     ap.add_argument("--small", action="store_true", help="small sequences (128^3 at 4 cm, 160x120, 1024 particles)")
     ap.add_argument("--seed-base", type=int, default=52000, help="--learned: first sequence seed")
+    ap.add_argument("--batch-shape", type=int, nargs=2, default=[0, 0],
+                    help="--learned: fitness launch shape of the batched modes ((0, 0): switching mode)")
     ap.add_argument("--learned", action="store_true",
                     help="learned proposal, batched, against plain PST one sequence after another (320x240)")
     args = ap.parse_args()

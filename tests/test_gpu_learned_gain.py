@@ -6,8 +6,8 @@ its own tracked poses:
 
 * plain PST (10240 particles, 20 iterations) one sequence after another
   (the single-sequence path in the switching mode), and the same budget
-  batched (a control for the batching alone: its poses equal the single
-  path's bit for bit, so only its speed differs);
+  batched in the switching mode (a control for the batching alone: its
+  poses equal the single path's bit for bit, so only its speed differs);
 * the learned proposal batched (pso_batch_track_learned: the network's
   centre and axis lengths, the small template and iteration count, plain
   PST as per-sequence fallback), with the trained network and with an

@@ -159,7 +159,7 @@ def batch_case(R, orc, nthreads):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("shape", [(8, 4), (64, 8), pytest.param((0, 0), marks=pytest.mark.skip(reason="the batch does not switch: its switching-mode launches were removed after a run of this case hung with no cause found"))])
+@pytest.mark.parametrize("shape", [(8, 4), (64, 8), pytest.param((0, 0), marks=pytest.mark.skip(reason="a run of the batch equality test hung with the persistent kernel's switching launches (since removed, no cause found); the switching mode is covered by test_batch_step_own_launches_against_oracle"))])
 def test_batch_step_against_oracle(R, batch_case, shape):
     """One batched frame step (persistent fitness launch, graph replay) of
     the uneven sequences, every sequence against the oracle's frame, in a
@@ -181,3 +181,33 @@ def test_batch_step_against_oracle(R, batch_case, shape):
     for i, (g, o) in enumerate(zip(got, refs)):
         assert g["status"] == 0
         _compare(f"batch {shape} sequence {i}", g, o)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("own_min", ["default", 60_000_000])
+def test_batch_step_own_launches_against_oracle(R, batch_case, own_min):
+    """The batch in the switching mode: sequences with 2^23 or more
+    evaluations per iteration (here all four) take the single path's own
+    switched fitness launches inside the batch's graph; with the threshold
+    at 6e7 evaluations the 4800-point x 4096-particle and 4800 x 10240
+    sequences share the persistent launch instead (mixed batch).  One
+    batched frame step, every sequence against the oracle's frame."""
+    setups, refs = batch_case
+    params = [R.track_params(max_iters=20, stride=4) for _ in setups]
+    stream = torch.cuda.Stream()
+    try:
+        R.set_fitness_shape(0, 0)
+        R.set_batch_own_launch(R.BATCH_OWN_LAUNCH_DEFAULT if own_min == "default" else own_min)
+        with torch.cuda.stream(stream):
+            b = R.Batch([s[1] for s in setups], [s[0].K for s in setups], [s[2] for s in setups], params,
+                        use_graph=True)
+            states = (R.TrackState * len(setups))(*[R.track_state(s[0].poses[0].q, s[0].poses[0].t, [0.55] * 6)
+                                                      for s in setups])
+            got = b.track([s[3] for s in setups], states, stream=stream)
+            b.close()
+    finally:
+        R.set_fitness_shape(4, 2)
+        R.set_batch_own_launch(R.BATCH_OWN_LAUNCH_DEFAULT)
+    for i, (g, o) in enumerate(zip(got, refs)):
+        assert g["status"] == 0
+        _compare(f"batch switching (own launches from {own_min}) sequence {i}", g, o)
