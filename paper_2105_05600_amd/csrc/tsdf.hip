@@ -28,8 +28,6 @@ __global__ __launch_bounds__(256) void k_fill(Grid g, uint64_t n) {
     store_w<FMT>(g.wgt, (uint32_t)i, 0.0f);
 }
 
-// One block per 8x8x8 brick, one thread per voxel (threadIdx.x is the
-// in-brick offset, so loads and stores of a brick are contiguous).
 // A: voxel index -> camera coordinates, binary32 3x4 (see tsdf_integrate).
 struct IntegrateArgs {
     Grid g;
@@ -52,50 +50,83 @@ __device__ inline float stored_psi(float v) {
     }
 }
 
+// One wavefront per 8x8x8 brick (4 per workgroup): lane l takes the voxels
+// at in-brick offsets l + 64 m, m = 0..7 (z layer m of the brick), so each
+// of its 8 loads and stores covers 64 contiguous voxels.
 template <int FMT>
-__global__ __launch_bounds__(512) void k_integrate(IntegrateArgs a) {
+__global__ __launch_bounds__(256) void k_integrate(IntegrateArgs a, uint32_t n_bricks) {
     const Grid& g = a.g;
-    const uint32_t b = blockIdx.x;
+    const uint32_t b = blockIdx.x * 4u + (threadIdx.x >> 6);
+    if (b >= n_bricks) return;  // wave-uniform
     const uint32_t bx = b % (uint32_t)g.nbx;
     const uint32_t by = (b / (uint32_t)g.nbx) % (uint32_t)g.nby;
     const uint32_t bz = b / ((uint32_t)g.nbx * (uint32_t)g.nby);
-    const uint32_t t = threadIdx.x;
-    const uint32_t i = bx * 8 + (t & 7u), j = by * 8 + ((t >> 3) & 7u), k = bz * 8 + (t >> 6);
-    const float fi = (float)i, fj = (float)j, fk = (float)k;
-    const float xc = xf_row(a.A[0], a.A[1], a.A[2], a.A[3], fi, fj, fk);
-    const float yc = xf_row(a.A[4], a.A[5], a.A[6], a.A[7], fi, fj, fk);
-    const float zc = xf_row(a.A[8], a.A[9], a.A[10], a.A[11], fi, fj, fk);
-    // every thread reaches the barrier below; `upd` marks the voxels that
-    // take this frame's measurement
-    bool upd = zc > 0.0f;
-    float pu = 0.0f, pv = 0.0f;
-    if (upd) {
-        pu = floorf(fmaf(a.fx, xc / zc, a.cx) + 0.5f);
-        pv = floorf(fmaf(a.fy, yc / zc, a.cy) + 0.5f);
-        upd = pu >= 0.0f && pu < (float)a.W && pv >= 0.0f && pv < (float)a.H;
+    const uint32_t lane = threadIdx.x & 63u;
+    // A brick that takes no measurement is left at once: its 8 corner voxels
+    // all lie behind the camera, or all in front of it and beyond one edge of
+    // the image.  Camera coordinates are affine in the voxel index and each
+    // condition is a half-space, so every voxel of such a brick (inside the
+    // corners' convex hull) fails the per-voxel test below.  The conditions
+    // are evaluated in binary64 with margins (1 cm, 2 pixels) far above the
+    // rounding of the per-voxel binary32 arithmetic (below 0.1 pixel in
+    // front of the 1 cm plane).
+    {
+        bool behind = false, front = false, left = false, right = false, top = false, bottom = false;
+        if (lane < 8) {
+            const double ci = (double)(bx * 8 + 7 * (lane & 1u)), cj = (double)(by * 8 + 7 * ((lane >> 1) & 1u)),
+                         ck = (double)(bz * 8 + 7 * (lane >> 2));
+            const double x = (double)a.A[0] * ci + (double)a.A[1] * cj + (double)a.A[2] * ck + (double)a.A[3];
+            const double y = (double)a.A[4] * ci + (double)a.A[5] * cj + (double)a.A[6] * ck + (double)a.A[7];
+            const double z = (double)a.A[8] * ci + (double)a.A[9] * cj + (double)a.A[10] * ck + (double)a.A[11];
+            behind = z < -0.01;
+            front = z > 0.01;
+            left = (double)a.fx * x + ((double)a.cx + 2.5) * z < 0.0;
+            right = (double)a.fx * x + ((double)a.cx + 0.5 - (double)a.W - 2.0) * z > 0.0;
+            top = (double)a.fy * y + ((double)a.cy + 2.5) * z < 0.0;
+            bottom = (double)a.fy * y + ((double)a.cy + 0.5 - (double)a.H - 2.0) * z > 0.0;
+        }
+        auto all8 = [](bool c) { return (__builtin_amdgcn_ballot_w64(c) & 0xffull) == 0xffull; };
+        if (all8(behind) || (all8(front) && (all8(left) || all8(right) || all8(top) || all8(bottom)))) return;
     }
-    float D = 0.0f;
-    if (upd) {
-        D = a.depth[(uint32_t)pv * (uint32_t)a.W + (uint32_t)pu];
-        upd = D > 0.0f;
-    }
-    const float sdf = D - zc;
-    upd = upd && !(sdf < -g.mu);
     bool not_one = false;
-    if (upd) {
-        const float d = fminf(1.0f, sdf / g.mu);
-        const uint32_t off = (b << 9) | t;
-        const float w0 = load_w<FMT>(g.wgt, off);
-        const float p0 = load_psi<FMT>(g.psi, off);
-        const float v = fmaf(w0, p0, d) / (w0 + 1.0f);
-        store_psi<FMT>(g.psi, off, v);
-        store_w<FMT>(g.wgt, off, fminf(w0 + 1.0f, g.w_max));
-        not_one = stored_psi<FMT>(v) != 1.0f;
+#pragma unroll
+    for (uint32_t m = 0; m < 8; ++m) {
+        const uint32_t t = lane + 64u * m;
+        const uint32_t i = bx * 8 + (t & 7u), j = by * 8 + ((t >> 3) & 7u), k = bz * 8 + m;
+        const float fi = (float)i, fj = (float)j, fk = (float)k;
+        const float xc = xf_row(a.A[0], a.A[1], a.A[2], a.A[3], fi, fj, fk);
+        const float yc = xf_row(a.A[4], a.A[5], a.A[6], a.A[7], fi, fj, fk);
+        const float zc = xf_row(a.A[8], a.A[9], a.A[10], a.A[11], fi, fj, fk);
+        // `upd` marks the voxels that take this frame's measurement
+        bool upd = zc > 0.0f;
+        float pu = 0.0f, pv = 0.0f;
+        if (upd) {
+            pu = floorf(fmaf(a.fx, xc / zc, a.cx) + 0.5f);
+            pv = floorf(fmaf(a.fy, yc / zc, a.cy) + 0.5f);
+            upd = pu >= 0.0f && pu < (float)a.W && pv >= 0.0f && pv < (float)a.H;
+        }
+        float D = 0.0f;
+        if (upd) {
+            D = a.depth[(uint32_t)pv * (uint32_t)a.W + (uint32_t)pu];
+            upd = D > 0.0f;
+        }
+        const float sdf = D - zc;
+        upd = upd && !(sdf < -g.mu);
+        if (upd) {
+            const float d = fminf(1.0f, sdf / g.mu);
+            const uint32_t off = (b << 9) | t;
+            const float w0 = load_w<FMT>(g.wgt, off);
+            const float p0 = load_psi<FMT>(g.psi, off);
+            const float v = fmaf(w0, p0, d) / (w0 + 1.0f);
+            store_psi<FMT>(g.psi, off, v);
+            store_w<FMT>(g.wgt, off, fminf(w0 + 1.0f, g.w_max));
+            not_one = not_one || stored_psi<FMT>(v) != 1.0f;
+        }
     }
     // a brick with a value other than +1 leaves the all-ones set; bits only
     // ever clear during fusion, so a bit already seen clear needs no atomic
     // (most bricks of the truncation band were cleared by earlier frames)
-    if (__syncthreads_or(not_one) && t == 0 && ((g.ones[b >> 5] >> (b & 31u)) & 1u))
+    if (__builtin_amdgcn_ballot_w64(not_one) != 0ull && lane == 0 && ((g.ones[b >> 5] >> (b & 31u)) & 1u))
         atomicAnd(&g.ones[b >> 5], ~(1u << (b & 31u)));
 }
 
@@ -343,11 +374,12 @@ rose_status tsdf_integrate(rose_tsdf* h, const float* depth_dev, const rose_came
     a.fx = cam->fx; a.fy = cam->fy; a.cx = cam->cx; a.cy = cam->cy;
     a.W = cam->width; a.H = cam->height;
     a.depth = depth_dev;
-    const unsigned blocks = (unsigned)(g.nbx * g.nby * g.nbz);
+    const uint32_t nb = n_bricks(g);
+    const unsigned blocks = (nb + 3u) / 4u;
     const int tok = prof_begin(PROF_INTEGRATE, s);
-    if (g.fmt == ROSE_TSDF_F32) hipLaunchKernelGGL(k_integrate<ROSE_TSDF_F32>, dim3(blocks), dim3(512), 0, s, a);
-    else if (g.fmt == ROSE_TSDF_F16) hipLaunchKernelGGL(k_integrate<ROSE_TSDF_F16>, dim3(blocks), dim3(512), 0, s, a);
-    else hipLaunchKernelGGL(k_integrate<ROSE_TSDF_SN16>, dim3(blocks), dim3(512), 0, s, a);
+    if (g.fmt == ROSE_TSDF_F32) hipLaunchKernelGGL(k_integrate<ROSE_TSDF_F32>, dim3(blocks), dim3(256), 0, s, a, nb);
+    else if (g.fmt == ROSE_TSDF_F16) hipLaunchKernelGGL(k_integrate<ROSE_TSDF_F16>, dim3(blocks), dim3(256), 0, s, a, nb);
+    else hipLaunchKernelGGL(k_integrate<ROSE_TSDF_SN16>, dim3(blocks), dim3(256), 0, s, a, nb);
     prof_end(tok, s, 0.0);
     ROSE_CHECK_HIP(hipGetLastError());
     return ROSE_OK;
