@@ -159,18 +159,33 @@ __device__ void track_update_body(const UpdateArgs& a) {
     const double rho0 = (st->k == 0 || (a.flags & ROSE_FLAG_CENTRE_THRESHOLD)) ? centre : st->thr;
     double r[6];
     for (int d = 0; d < 6; ++d) r[d] = st->r[d];
-    // per-thread APS sums: count, sum w, sum w rho, sum w u_d
+    // per-thread APS sums: count, sum w, sum w rho, sum w u_d, over the
+    // thread's particles i = threadIdx.x + j blockDim.x in increasing j; the
+    // loads of 8 of them are issued before their arithmetic (latency)
     double cnt = 0.0, sw = 0.0, swr = 0.0, su[6] = {0, 0, 0, 0, 0, 0};
-    for (int i = threadIdx.x; i < a.n; i += blockDim.x) {
-        const float f = a.F[i];
-        const double rho = exp_rho(-(double)f / a.tau);
-        if (rho > rho0) {
-            const double w = rho - rho0;
-            cnt += 1.0;
-            sw += w;
-            swr += w * rho;
+    constexpr int kAhead = 8;
+    const int bd = (int)blockDim.x;
+    for (int i0 = threadIdx.x; i0 < a.n; i0 += kAhead * bd) {
+        float f[kAhead], pr[kAhead][6];
 #pragma unroll
-            for (int d = 0; d < 6; ++d) su[d] += w * (r[d] * (double)a.pst[6 * (int64_t)i + d]);
+        for (int q = 0; q < kAhead; ++q) {
+            const int i = min(i0 + q * bd, a.n - 1);
+            f[q] = a.F[i];
+#pragma unroll
+            for (int d = 0; d < 6; ++d) pr[q][d] = a.pst[6 * (int64_t)i + d];
+        }
+#pragma unroll
+        for (int q = 0; q < kAhead; ++q) {
+            if (i0 + q * bd >= a.n) break;
+            const double rho = exp_rho(-(double)f[q] / a.tau);
+            if (rho > rho0) {
+                const double w = rho - rho0;
+                cnt += 1.0;
+                sw += w;
+                swr += w * rho;
+#pragma unroll
+                for (int d = 0; d < 6; ++d) su[d] += w * (r[d] * (double)pr[q][d]);
+            }
         }
     }
     double v9[9] = {cnt, sw, swr, su[0], su[1], su[2], su[3], su[4], su[5]};
