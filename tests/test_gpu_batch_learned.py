@@ -2,7 +2,10 @@
 features per sequence, one network forward over all sequences, one batched
 small-template step, per-sequence plain fallback) equals the single learned
 frame (pso_track_frame_learned) sequence by sequence, frame after frame:
-poses, axis lengths, fitness and fallback decisions bit for bit."""
+poses, axis lengths, fitness and fallback decisions bit for bit; with the
+fixed launch shape (4, 2) and in the switching mode, where every sequence
+here (over 2^23 evaluations per iteration) takes the single path's own
+fitness launches inside the batch."""
 import json
 import os
 
@@ -16,9 +19,19 @@ WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
                        "weights", "proposal.npz")
 
 
+@pytest.mark.parametrize("shape", [(4, 2), (0, 0)])
 @pytest.mark.parametrize("always_fall_back", [False, True])
-def test_batch_learned_equals_single(always_fall_back):
-    from paper_2105_05600_amd import rose, train_proposal as tp
+def test_batch_learned_equals_single(always_fall_back, shape):
+    from paper_2105_05600_amd import rose
+    rose.set_fitness_shape(*shape)
+    try:
+        _batch_learned_equals_single(rose, always_fall_back)
+    finally:
+        rose.set_fitness_shape(4, 2)
+
+
+def _batch_learned_equals_single(rose, always_fall_back):
+    from paper_2105_05600_amd import train_proposal as tp
     with open(os.path.splitext(WEIGHTS)[0] + ".json") as f:
         meta = json.load(f)
     n_seq, n_frames = 4, 8
