@@ -472,14 +472,17 @@ rose_status pso_track_frame_learned(rose_tsdf* h, const float* depth_dev, const 
  * fitness launches of pso_track_frame for each sequence that has its own
  * (see rose_batch_set_own_launch), one slice-reduction launch and one update
  * launch, then one launch copying the states to pinned host memory; with
- * use_graph != 0
- * and a non-null stream it is captured into a HIP graph on the first call
- * and replayed afterwards (new inputs are read from pinned host memory).
- * The fitness launch shape is the one set by rose_fitness_set_shape when the
- * batch is created ((4,2), (8,2), (4,4) or (8,4); otherwise (4,2)); one
- * persistent fitness launch per iteration and per group of sequences that
- * share a storage format and lookup; its workgroups take work items from one
- * counter per XCD, cleared by the kernel before each fitness round.
+ * use_graph != 0 and a non-null stream it is captured into a HIP graph on
+ * the first call and replayed afterwards (new inputs are read from pinned
+ * host memory; a change of a handle's scratch pointers makes the next call
+ * capture again).  The persistent launches run the first handle's launch
+ * shape when the batch is created -- the fixed shape set by
+ * rose_fitness_set_shape or tsdf_set_fitness_shape if it is (4,2), (8,2),
+ * (4,4), (8,4), (4,8) or (64,8), in the switching mode its points-across
+ * shape, otherwise (4,2) -- one per iteration and per group of sequences
+ * that share a storage format and lookup; their workgroups take work items
+ * from one counter per XCD, cleared by the kernel before each fitness
+ * round.
  * Creation reads each template back once to derive the particle schedule
  * order (as pso_track_frame does).  Volumes must be below 4 GB.  The handles
  * must stay alive while the batch exists; tracking one through another path
