@@ -135,3 +135,48 @@ def test_batch_first_frame_corner_case(R, scenes):
     assert np.allclose(list(states[1].r), 0.55) and got[1]["iters"] == 1
     assert got[0]["iters"] == 5 and got[2]["iters"] == 5
     b.close()
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_mixed_handle_modes_equal_single_path(R, scenes, use_graph):
+    """Launch configurations set per handle: the second sequence's handle in
+    the switching mode (its own launches at min_evals 0), the others on the
+    process-wide fixed shape (4, 2) in the persistent launch.  Every
+    sequence equals the single path run on a handle configured the same
+    way, and reports the kernel of each iteration as that path does."""
+    ws, fmts, ns, strides = scenes
+    R.set_batch_own_launch(0)
+    try:
+        ref, vols = [], []
+        for i, (w, f, n, s) in enumerate(zip(ws, fmts, ns, strides)):
+            v = _volume(R, w, f)
+            if i == 1:
+                v.set_fitness_shape(0, 0)
+            st = R.track_state(w.fuse_poses[-1].q, w.fuse_poses[-1].t, [0.1] * 6)
+            ref.append(R.track_frame(v, torch.from_numpy(w.depth).cuda(), w.K, R.pst_sample(n, 5600 + n),
+                                     R.track_params(max_iters=w.iters, stride=s), st))
+            v.close()
+            v = _volume(R, w, f)
+            if i == 1:
+                v.set_fitness_shape(0, 0)
+            vols.append(v)
+        psts = [R.pst_sample(n, 5600 + n) for n in ns]
+        params = [R.track_params(max_iters=w.iters, stride=s) for w, s in zip(ws, strides)]
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            b = R.Batch(vols, [w.K for w in ws], psts, params, use_graph=use_graph)
+            states = (R.TrackState * len(ws))(*[R.track_state(w.fuse_poses[-1].q, w.fuse_poses[-1].t, [0.1] * 6)
+                                                  for w in ws])
+            got = b.track([torch.from_numpy(w.depth).cuda() for w in ws], states, stream=stream)
+            b.close()
+        for i, r in enumerate(ref):
+            assert got[i]["status"] == 0
+            assert got[i]["aps"] == r["aps"] and got[i]["n_overlap"] == r["n_overlap"], i
+            assert np.array_equal(got[i]["t"], r["t"]) and np.array_equal(got[i]["q"], r["q"]), i
+            assert np.array_equal(got[i]["r1"], r["r1"]), i
+            assert got[i]["fit_mode"] == (r["fit_mode"] if i == 1 else [0] * len(got[i]["fit_mode"])), i
+        assert all(m in (1, 2) for m in ref[1]["fit_mode"])
+        for v in vols:
+            v.close()
+    finally:
+        R.set_batch_own_launch(R.BATCH_OWN_LAUNCH_DEFAULT)
