@@ -70,22 +70,51 @@ __device__ inline float gather(const Grid& g, const PsiBuf& b, uint32_t off) {
 }
 
 struct VoxelTest {
-    float fx, fy, fz;  // grid extent as float
+    uint32_t bx, by, bz;  // bit patterns of the grid extent as binary32
 };
 
+__device__ inline VoxelTest voxel_test(const Grid& g) {
+    return VoxelTest{__float_as_uint((float)g.nx), __float_as_uint((float)g.ny), __float_as_uint((float)g.nz)};
+}
+
+// The voxel-space particle transform as the bounds test below needs it.  A
+// transform with a non-finite entry makes every coordinate it produces NaN
+// or infinite (an infinity never cancels to a finite value), i.e. every
+// evaluation outside the grid: it is replaced by one that puts every point
+// at -1 on each axis, also outside.  The translation entries get + 0, which
+// turns -0 into +0 and leaves every other value as it is; then no
+// coordinate of the fmaf chain is ever -0 (its innermost addend is not, and
+// an exact zero sum rounds to +0).  No evaluation changes.
+__device__ inline void sanitize_voxel_transform(float V[12]) {
+    bool fin = true;
+#pragma unroll
+    for (int e = 0; e < 12; ++e) fin = fin && isfinite(V[e]);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) V[4 * r + c] = fin ? V[4 * r + c] : 0.0f;
+        V[4 * r + 3] = fin ? V[4 * r + 3] + 0.0f : -1.0f;
+    }
+}
+
 // NEAREST voxel of voxel-space coordinate g: inside iff 0 <= g < n on every
-// axis (NaN is outside); then floor(g) == (uint32)g.  Outside the grid the
-// conversions saturate and the offset would be meaningless: it is replaced
-// by one past the end of any buffer below 4 GB, where a buffer load fetches
-// no cache line and returns 0 (WIDE volumes, read through plain pointers,
-// get offset 0); the caller supplies the +1.
+// axis (NaN is outside); then floor(g) == (uint32)g.  The test compares the
+// binary32 bit patterns as unsigned integers, one comparison per axis: for
+// values >= +0 their order is the order of the values, and a negative
+// value, -0 or NaN of either sign lies above every extent's pattern.  It
+// equals the float test except at g = -0, which the sanitized transforms
+// never produce.  Outside the grid the conversions saturate and the offset
+// would be meaningless: it is replaced by one past the end of any buffer
+// below 4 GB, where a buffer load fetches no cache line and returns 0 (WIDE
+// volumes, read through plain pointers, get offset 0); the caller supplies
+// the +1.
 // The offset is computed for every lane (the volatile empty asm keeps the
 // compiler from turning the select below into a branch around it).
 template <bool WIDE>
 __device__ inline bool nearest_offset(const Grid& g, const VoxelTest& e, float gx, float gy, float gz, uint32_t* off) {
     uint32_t o = brick_offset(g, (uint32_t)gx, (uint32_t)gy, (uint32_t)gz);
     asm volatile("" : "+v"(o));
-    const bool in = (gx >= 0.0f) & (gx < e.fx) & (gy >= 0.0f) & (gy < e.fy) & (gz >= 0.0f) & (gz < e.fz);
+    const bool in = (__float_as_uint(gx) < e.bx) & (__float_as_uint(gy) < e.by) & (__float_as_uint(gz) < e.bz);
     *off = in ? o : (WIDE ? 0u : 0xffffffffu);
     return in;
 }
@@ -219,6 +248,7 @@ __device__ void fitness_body(const FitLaunch& a, const int blk) {
             for (int e = 0; e < 12; ++e) T[e] = (double)a.T32[12 * (int64_t)pi + e];
         }
         fold_to_voxel(T, (double)a.g.vox, a.g.origin, V);
+        sanitize_voxel_transform(V);
     }
     // Up to 4 particles per wave: rotation entries wave-uniform in scalar
     // registers and the translation column broadcast with a cross-lane
@@ -236,7 +266,7 @@ __device__ void fitness_body(const FitLaunch& a, const int blk) {
 
     const Grid g = a.g;
     const PsiBuf pb = psi_buffer<FMT>(g);
-    const VoxelTest ext{(float)g.nx, (float)g.ny, (float)g.nz};
+    const VoxelTest ext = voxel_test(g);
     const int chunk = (m + a.splits - 1) / a.splits;
     const int j0 = split * chunk;
     const int j1 = min(m, j0 + chunk);
@@ -417,11 +447,12 @@ __device__ void fitness_body_pl(const FitLaunch& a, const int blk) {
             for (int e = 0; e < 12; ++e) T[e] = (double)a.T32[12 * (int64_t)pi + e];
         }
         fold_to_voxel(T, (double)a.g.vox, a.g.origin, V);
+        sanitize_voxel_transform(V);
     }
 
     const Grid g = a.g;
     const PsiBuf pb = psi_buffer<FMT>(g);
-    const VoxelTest ext{(float)g.nx, (float)g.ny, (float)g.nz};
+    const VoxelTest ext = voxel_test(g);
     const int chunk = (m + a.splits - 1) / a.splits;
     const int s0 = split * chunk;
     const int s1 = min(m, s0 + chunk);

@@ -592,3 +592,35 @@ def test_track_switching_small_footprint(R, orc, room_frame, r0):
     assert np.linalg.norm(np.array(g["t"]) - o["t"]) <= 1e-4
     assert _rot_err(g["q"], o["q"]) <= 1e-4
     assert np.allclose(g["r1"], o["r1"], rtol=1e-6)
+
+
+@pytest.mark.parametrize("shape", [(4, 4), (64, 8), (0, 0)])
+def test_fitness_nonfinite_and_negative_zero_transforms(R, orc, shape):
+    """Particle transforms with a NaN, +inf or -inf entry put every
+    evaluation outside the grid (F = 1), and a transform whose voxel x
+    coordinate is exactly -0 for points at x = +0 (rotation row (-1, -0, -0),
+    translation -0, origin 0) keeps those points in voxel 0 (-0 >= 0): the
+    kernels' bounds test on binary32 bit patterns, after they sanitize the
+    transforms, equals the oracle's float test bit for bit."""
+    rng = np.random.default_rng(7)
+    dims, vox, origin = (32, 24, 16), 0.04, (0.0, 0.0, 0.0)
+    vol, psi = _random_volume(R, rng, dims, vox, origin, 0)
+    m = 200
+    pts = np.stack([np.zeros(m), rng.uniform(0.01, 0.9, m), rng.uniform(0.01, 0.6, m)], 1).astype(np.float32)
+    pts[m // 2:, 0] = rng.uniform(0.0, 1.2, m - m // 2)
+    T = np.zeros((5, 3, 4), np.float32)
+    for i in range(5):
+        T[i, :, :3] = np.eye(3)
+    T[1, 0, 1] = np.nan
+    T[2, 1, 3] = np.inf
+    T[3, 2, 0] = -np.inf
+    T[4, 0, :] = [-1.0, -0.0, -0.0, -0.0]
+    T = T.reshape(5, 12)
+    Fo = orc.fitness(psi, vox, np.array(origin, np.float32), pts, T.astype(np.float64), lookup=0, prec=orc.F32)
+    assert Fo[1] == Fo[2] == Fo[3] == 1.0 and Fo[4] < 1.0
+    try:
+        vol.set_fitness_shape(*shape)
+        F, _ = R.fitness_eval(vol, dev(pts), dev(T), 0)
+    finally:
+        vol.close()
+    assert np.array_equal(host(F), Fo.astype(np.float32))
