@@ -416,6 +416,9 @@ def main():
         "l2_requests_per_eval": cnt["l2_requests_per_eval"] if cnt else None,
         "l1_to_l2_gbs": (cnt["l2_read_bytes_per_launch"] / (fit_ms * 1e-3) / 1e9
                          if cnt and cnt["l2_read_bytes_per_launch"] else None),
+        # algorithmic gather bytes over the L1 -> L2 line bytes of the same step
+        "coalescing_efficiency": (fit_evals * bytes_per_eval / cnt["l2_read_bytes_per_launch"]
+                                  if cnt and cnt["l2_read_bytes_per_launch"] else None),
         "ta_stalled_by_tc_frac": cnt["ta_stalled_by_tc_frac"] if cnt else None,
         "counters": "rocprofv3 summary of the same command and window" if cnt else why,
     }
