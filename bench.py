@@ -65,7 +65,7 @@ def parse():
     ap.add_argument("--switch", default=None, metavar="VOX,DEPTH",
                     help="switching-mode threshold: footprint in voxels, reference depth in metres")
     ap.add_argument("--switch-shape", default=None, metavar="P,U",
-                    help="switching mode: the points-across shape used above the threshold (default 4,4)")
+                    help="switching mode: the points-across shape used above the threshold (default 4,2)")
     ap.add_argument("--dump-poses", default=None, metavar="FILE",
                     help="write every frame's estimated and true pose (JSON) to FILE")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -299,7 +299,7 @@ def main():
     # run the same kernels as the timed ones
     if args.switch:
         rose.set_fitness_switch(*(float(v) for v in args.switch.split(",")))
-    wide = (4, 4)
+    wide = (4, 2)
     if args.switch_shape:
         wide = tuple(int(v) for v in args.switch_shape.split(","))
         rose.set_fitness_switch_shape(*wide)

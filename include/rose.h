@@ -578,14 +578,14 @@ rose_status rose_gemm_bf16(int32_t M, int32_t N, int32_t K, const float* A_dev, 
  * (64, 16) -- one particle per lane, U points looked up per step.  (0, 0)
  * selects the switching mode: pso_track_frame, the learned tracker and the
  * plain fallbacks run the switching mode's points-across shape (default
- * (4, 4); (4, 2) for trilinear lookups) while the search footprint (see
+ * (4, 2), for both lookups) while the search footprint (see
  * rose_fitness_set_switch) is above the threshold and (64, 8) at or below
  * it, decided on the device each iteration from the current axis lengths;
  * fitness_eval and the comparison optimisers run the points-across shape.
  * Other values give ROSE_E_UNSUPPORTED.  The batched tracker runs the first
  * handle's shape (in the switching mode its points-across shape) when it
  * is (4, 2), (8, 2), (4, 4), (4, 8), (8, 4) or (64, 8), else (4, 2).
- * Results do not depend on the shape beyond binary64 summation order. */
+ * Results do not depend on the shape (the fitness sums are exact). */
 rose_status rose_fitness_set_shape(int32_t particles_per_wave, int32_t points_per_lane);
 
 /* Threshold of the switching mode (process-wide default): the footprint of
@@ -599,7 +599,7 @@ rose_status rose_fitness_set_shape(int32_t particles_per_wave, int32_t points_pe
  * footprint_voxels is 0 or in (0, 1e6] with 0 <= reference_depth_m <= 1e3.
  * Host-only. */
 rose_status rose_fitness_set_switch(float footprint_voxels, float reference_depth_m);
-/* The switching mode's points-across shape (process-wide default (4, 4));
+/* The switching mode's points-across shape (process-wide default (4, 2));
  * any compiled shape with fewer than 64 particles per wave, else
  * ROSE_E_UNSUPPORTED. */
 rose_status rose_fitness_set_switch_shape(int32_t particles_per_wave, int32_t points_per_lane);

@@ -692,8 +692,11 @@ __global__ __launch_bounds__(256) void k_pack_points(const float* pts3, int32_t 
 // 25 voxels): the largest axis overstates the spread of the others.
 // Trilinear lookups (8 gathers per evaluation) cross over earlier: on the
 // same workload 8, 16, 32, 48 voxels -> 2.099, 2.075, 2.055, 2.217 ms per
-// step (4x2 alone: 2.100), so their default is 32.
-static const FitConfig kDefaultCfg = {4, 2, 0, 4, 4, {48.0f, 32.0f}, 3.0f};
+// step (4x2 alone: 2.100), so their default is 32.  The points-across
+// shape of the switching mode: 4x2 (bench, 20 frames, three runs each:
+// 3.698-3.706e11 evaluations/s against 3.632-3.634e11 for 4x4; 8x2 3.67e11,
+// 2x4 3.63e11, 8x4 3.52e11, 4x8 3.46e11).
+static const FitConfig kDefaultCfg = {4, 2, 0, 4, 2, {48.0f, 32.0f}, 3.0f};
 static FitConfig g_cfg = kDefaultCfg;
 
 FitConfig fit_config(const rose_tsdf* h) { return (h && h->cfg_set) ? h->cfg : g_cfg; }

@@ -306,7 +306,7 @@ class Tsdf:
         _check("tsdf_set_fitness_shape",
                _lib.tsdf_set_fitness_shape(self.handle, int(particles_per_wave), int(points_per_lane)))
 
-    def set_fitness_switch(self, footprint_voxels: float, reference_depth_m: float = 3.0, wide=(4, 4)):
+    def set_fitness_switch(self, footprint_voxels: float, reference_depth_m: float = 3.0, wide=(4, 2)):
         """This handle's switching threshold and points-across shape."""
         _check("tsdf_set_fitness_switch",
                _lib.tsdf_set_fitness_switch(self.handle, float(footprint_voxels), float(reference_depth_m),
