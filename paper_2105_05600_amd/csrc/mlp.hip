@@ -134,13 +134,25 @@ __global__ __launch_bounds__(256) void k_nll(const float* out, const float* Y, i
     }
 }
 
-// column sums (bias gradients): one thread per column, rows in order
-__global__ __launch_bounds__(256) void k_colsum(const float* X, int32_t rows, int32_t cols, float* out) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= cols) return;
+// column sums (bias gradients): a workgroup per 64 columns; wave w of its
+// 16 sums rows w, w + 16, ... of its lane's column (each row read as one
+// coalesced 64-column segment), then one lane per column adds the 16
+// partial sums in wave order (a fixed order: deterministic)
+constexpr int kColsumWaves = 16;
+__global__ __launch_bounds__(1024) void k_colsum(const float* X, int32_t rows, int32_t cols, float* out) {
+    __shared__ float part[kColsumWaves][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + lane;
     float s = 0.0f;
-    for (int r = 0; r < rows; ++r) s += X[(int64_t)r * cols + c];
-    out[c] = s;
+    if (c < cols)
+        for (int r = w; r < rows; r += kColsumWaves) s += X[(int64_t)r * cols + c];
+    part[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && c < cols) {
+        float t = 0.0f;
+        for (int k = 0; k < kColsumWaves; ++k) t += part[k][lane];
+        out[c] = t;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_adam(int64_t n, float* p, const float* gr, float* m, float* v, float lr,
@@ -279,7 +291,7 @@ rose_status rose_mlp_loss_grad(rose_mlp* m, const float* params_dev, const float
     if ((st = gemm(hid, out, B, m->H2, 1, hid, m->dY, out, 1, G + o.W3, out, EPI_STORE, nullptr, nullptr, nullptr,
                    s)) != ROSE_OK)
         return st;
-    hipLaunchKernelGGL(k_colsum, dim3((out + 255) / 256), dim3(256), 0, s, m->dY, B, out, G + o.b3);
+    hipLaunchKernelGGL(k_colsum, dim3((out + 63) / 64), dim3(64 * kColsumWaves), 0, s, m->dY, B, out, G + o.b3);
     // dZ2 = (dY W3^T) * gelu'(Z2)
     if ((st = gemm(B, hid, out, m->dY, out, 1, P + o.W3, 1, out, m->dZ2, hid, EPI_GELU_GRAD, nullptr, nullptr, m->Z2,
                    s)) != ROSE_OK)
@@ -288,7 +300,7 @@ rose_status rose_mlp_loss_grad(rose_mlp* m, const float* params_dev, const float
     if ((st = gemm(hid, hid, B, m->H1, 1, hid, m->dZ2, hid, 1, G + o.W2, hid, EPI_STORE, nullptr, nullptr, nullptr,
                    s)) != ROSE_OK)
         return st;
-    hipLaunchKernelGGL(k_colsum, dim3((hid + 255) / 256), dim3(256), 0, s, m->dZ2, B, hid, G + o.b2);
+    hipLaunchKernelGGL(k_colsum, dim3((hid + 63) / 64), dim3(64 * kColsumWaves), 0, s, m->dZ2, B, hid, G + o.b2);
     // dZ1 = (dZ2 W2^T) * gelu'(Z1)
     if ((st = gemm(B, hid, hid, m->dZ2, hid, 1, P + o.W2, 1, hid, m->dZ1, hid, EPI_GELU_GRAD, nullptr, nullptr, m->Z1,
                    s)) != ROSE_OK)
@@ -297,7 +309,7 @@ rose_status rose_mlp_loss_grad(rose_mlp* m, const float* params_dev, const float
     if ((st = gemm(in, hid, B, X_dev, 1, in, m->dZ1, hid, 1, G + o.W1, hid, EPI_STORE, nullptr, nullptr, nullptr,
                    s)) != ROSE_OK)
         return st;
-    hipLaunchKernelGGL(k_colsum, dim3((hid + 255) / 256), dim3(256), 0, s, m->dZ1, B, hid, G + o.b1);
+    hipLaunchKernelGGL(k_colsum, dim3((hid + 63) / 64), dim3(64 * kColsumWaves), 0, s, m->dZ1, B, hid, G + o.b1);
     ROSE_CHECK_HIP(hipGetLastError());
     return ROSE_OK;
 }
