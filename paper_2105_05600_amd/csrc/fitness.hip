@@ -416,7 +416,7 @@ __device__ void fitness_body(const FitLaunch& a, const int blk) {
 // Slices and their XCD mapping are those of fitness_body counted in
 // quarters (XCD x owns the contiguous quarter-slices x 4S/8 ...).  Every
 // exit before a barrier is uniform over the workgroup.
-template <int U, int FMT, int LK, bool FROM_STATE, bool WIDE, bool ACC32 = false>
+template <int U, int FMT, int LK, bool FROM_STATE, bool WIDE, bool ACC32 = false, int WG = 4>
 __device__ void fitness_body_pl(const FitLaunch& a, const int blk) {
     __shared__ float4 s_pts[kWave];
     const int lane = threadIdx.x & 63;
@@ -426,11 +426,11 @@ __device__ void fitness_body_pl(const FitLaunch& a, const int blk) {
     const int qs = (r & 7) * (R >> 3) + (r >> 3);
     const int split = qs / kPartSub, sub = qs % kPartSub;
     const int g4 = blk / R;
-    if (g4 * 4 * kWave >= a.n) return;
+    if (g4 * WG * kWave >= a.n) return;
     if (FROM_STATE && (a.st->stopped || switch_skips(a))) return;
     const int m = a.count_dev ? *a.count_dev : a.count;
 
-    const int p0 = (g4 * 4 + wave) * kWave;
+    const int p0 = (g4 * WG + wave) * kWave;
     const bool live = p0 + lane < a.n;  // a wave past the last particle still keeps the barriers
     int pi = live ? p0 + lane : a.n - 1;
     if (FROM_STATE && a.order) pi = a.order[pi];
@@ -497,15 +497,21 @@ __device__ void fitness_body_pl(const FitLaunch& a, const int blk) {
     }
 }
 
+// Wavefronts per workgroup of the particle-per-lane launches (their
+// kPlWaves x 64 particles share the staged points of one quarter-slice);
+// the persistent batch kernel runs the same body with 4.
+constexpr int kPlWaves = 8;
+
 template <int P, int U, int FMT, int LK, bool FROM_STATE, bool WIDE, bool ACC32 = false>
-__global__ __launch_bounds__(256) void k_fitness(FitLaunch a) {
-    if constexpr (P == kWave) fitness_body_pl<U, FMT, LK, FROM_STATE, WIDE, ACC32>(a, blockIdx.x);
+__global__ __launch_bounds__(P == kWave ? kWave * kPlWaves : 256) void k_fitness(FitLaunch a) {
+    if constexpr (P == kWave) fitness_body_pl<U, FMT, LK, FROM_STATE, WIDE, ACC32, kPlWaves>(a, blockIdx.x);
     else fitness_body<P, U, FMT, LK, FROM_STATE, WIDE, ACC32>(a, blockIdx.x);
 }
 
-// workgroups of a launch: 4 particle groups per workgroup and one slice
-// (points across the lanes), or 4 groups of 64 and one quarter of a slice
-// (one particle per lane)
+// work items of the persistent batch kernel (its workgroups: 4 particle
+// groups and one slice (points across the lanes), or 4 groups of 64 and one
+// quarter of a slice (one particle per lane)); also the workgroups of a
+// points-across launch
 int fitness_blocks(const FitLaunch& L, int P) {
     const int groups = (L.n + P - 1) / P;
     return (P == kWave ? (groups + 3) / 4 * kPartSub : (groups + 3) / 4) * L.splits;
@@ -721,16 +727,21 @@ void fit_launch_shape(const rose_tsdf* h, int lk, int* p, int* u, float* thr_vox
 
 template <int P, int U, int FMT, int LK, bool WIDE>
 static void launch_pu(const FitLaunch& L, hipStream_t s) {
-    const unsigned blocks = (unsigned)fitness_blocks(L, P);
+    // particle-per-lane: kPlWaves groups of 64 per workgroup and one
+    // quarter-slice; points across: 4 groups per workgroup and one slice
+    const int groups = (L.n + P - 1) / P;
+    const unsigned blocks =
+        (unsigned)(P == kWave ? (groups + kPlWaves - 1) / kPlWaves * kPartSub * L.splits : fitness_blocks(L, P));
+    const dim3 threads(P == kWave ? kWave * kPlWaves : 256);
     if (L.T32)
-        hipLaunchKernelGGL((k_fitness<P, U, FMT, LK, false, WIDE>), dim3(blocks), dim3(256), 0, s, L);
+        hipLaunchKernelGGL((k_fitness<P, U, FMT, LK, false, WIDE>), dim3(blocks), threads, 0, s, L);
     else if constexpr (FMT == ROSE_TSDF_F32 && !WIDE) {
         if (L.acc32)
-            hipLaunchKernelGGL((k_fitness<P, U, FMT, LK, true, WIDE, true>), dim3(blocks), dim3(256), 0, s, L);
+            hipLaunchKernelGGL((k_fitness<P, U, FMT, LK, true, WIDE, true>), dim3(blocks), threads, 0, s, L);
         else
-            hipLaunchKernelGGL((k_fitness<P, U, FMT, LK, true, WIDE>), dim3(blocks), dim3(256), 0, s, L);
+            hipLaunchKernelGGL((k_fitness<P, U, FMT, LK, true, WIDE>), dim3(blocks), threads, 0, s, L);
     } else
-        hipLaunchKernelGGL((k_fitness<P, U, FMT, LK, true, WIDE>), dim3(blocks), dim3(256), 0, s, L);
+        hipLaunchKernelGGL((k_fitness<P, U, FMT, LK, true, WIDE>), dim3(blocks), threads, 0, s, L);
 }
 
 template <int FMT, int LK>
