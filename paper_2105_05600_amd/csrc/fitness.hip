@@ -497,14 +497,20 @@ __device__ void fitness_body_pl(const FitLaunch& a, const int blk) {
     }
 }
 
-// Wavefronts per workgroup of the particle-per-lane launches (their
-// kPlWaves x 64 particles share the staged points of one quarter-slice);
-// the persistent batch kernel runs the same body with 4.
+// Wavefronts per workgroup of a particle-per-lane launch (its WG x 64
+// particles share the staged points of one quarter-slice): 8 while that
+// still leaves kPlWideMinBlocks workgroups or more (4 per CU), else 4 (the
+// persistent batch kernel always runs 4).  On the 640x480 / 10240-particle
+// room workload (1280 workgroups of 8) 8 waves took 92.8-93.0 ms over the
+// bench's 275 particle-per-lane steps against 97.0-97.3 ms with 4 (16: 104.2
+// ms); on 320x240 frames (640 workgroups of 8) and on 160x120 frames with
+// 1024 particles (64) 8 waves were 7-10 % slower over whole sequences.
 constexpr int kPlWaves = 8;
+constexpr int kPlWideMinBlocks = 1024;
 
-template <int P, int U, int FMT, int LK, bool FROM_STATE, bool WIDE, bool ACC32 = false>
-__global__ __launch_bounds__(P == kWave ? kWave * kPlWaves : 256) void k_fitness(FitLaunch a) {
-    if constexpr (P == kWave) fitness_body_pl<U, FMT, LK, FROM_STATE, WIDE, ACC32, kPlWaves>(a, blockIdx.x);
+template <int P, int U, int FMT, int LK, bool FROM_STATE, bool WIDE, bool ACC32 = false, int WG = 4>
+__global__ __launch_bounds__(P == kWave ? kWave * WG : 256) void k_fitness(FitLaunch a) {
+    if constexpr (P == kWave) fitness_body_pl<U, FMT, LK, FROM_STATE, WIDE, ACC32, WG>(a, blockIdx.x);
     else fitness_body<P, U, FMT, LK, FROM_STATE, WIDE, ACC32>(a, blockIdx.x);
 }
 
@@ -725,23 +731,33 @@ void fit_launch_shape(const rose_tsdf* h, int lk, int* p, int* u, float* thr_vox
     *zref_m = c.zref;
 }
 
-template <int P, int U, int FMT, int LK, bool WIDE>
-static void launch_pu(const FitLaunch& L, hipStream_t s) {
-    // particle-per-lane: kPlWaves groups of 64 per workgroup and one
-    // quarter-slice; points across: 4 groups per workgroup and one slice
-    const int groups = (L.n + P - 1) / P;
-    const unsigned blocks =
-        (unsigned)(P == kWave ? (groups + kPlWaves - 1) / kPlWaves * kPartSub * L.splits : fitness_blocks(L, P));
-    const dim3 threads(P == kWave ? kWave * kPlWaves : 256);
+template <int P, int U, int FMT, int LK, bool WIDE, int WG>
+static void launch_pu_wg(const FitLaunch& L, unsigned blocks, hipStream_t s) {
+    const dim3 threads(P == kWave ? kWave * WG : 256);
     if (L.T32)
-        hipLaunchKernelGGL((k_fitness<P, U, FMT, LK, false, WIDE>), dim3(blocks), threads, 0, s, L);
+        hipLaunchKernelGGL((k_fitness<P, U, FMT, LK, false, WIDE, false, WG>), dim3(blocks), threads, 0, s, L);
     else if constexpr (FMT == ROSE_TSDF_F32 && !WIDE) {
         if (L.acc32)
-            hipLaunchKernelGGL((k_fitness<P, U, FMT, LK, true, WIDE, true>), dim3(blocks), threads, 0, s, L);
+            hipLaunchKernelGGL((k_fitness<P, U, FMT, LK, true, WIDE, true, WG>), dim3(blocks), threads, 0, s, L);
         else
-            hipLaunchKernelGGL((k_fitness<P, U, FMT, LK, true, WIDE>), dim3(blocks), threads, 0, s, L);
+            hipLaunchKernelGGL((k_fitness<P, U, FMT, LK, true, WIDE, false, WG>), dim3(blocks), threads, 0, s, L);
     } else
-        hipLaunchKernelGGL((k_fitness<P, U, FMT, LK, true, WIDE>), dim3(blocks), threads, 0, s, L);
+        hipLaunchKernelGGL((k_fitness<P, U, FMT, LK, true, WIDE, false, WG>), dim3(blocks), threads, 0, s, L);
+}
+
+template <int P, int U, int FMT, int LK, bool WIDE>
+static void launch_pu(const FitLaunch& L, hipStream_t s) {
+    // points across: 4 groups per workgroup and one slice; particle per
+    // lane: WG groups of 64 per workgroup and one quarter-slice
+    if constexpr (P == kWave) {
+        const int groups = (L.n + kWave - 1) / kWave;
+        const int wide = (groups + kPlWaves - 1) / kPlWaves * kPartSub * L.splits;
+        if (wide >= kPlWideMinBlocks) {
+            launch_pu_wg<P, U, FMT, LK, WIDE, kPlWaves>(L, (unsigned)wide, s);
+            return;
+        }
+    }
+    launch_pu_wg<P, U, FMT, LK, WIDE, 4>(L, (unsigned)fitness_blocks(L, P), s);
 }
 
 template <int FMT, int LK>
